@@ -1,0 +1,162 @@
+"""One semi-implicit time step by direct solves (FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section "Spatial & temporal discretization" (semi-implicit scheme: linear
+terms implicit, potential terms explicit, Navier-Stokes nonlinearity lagged)
+and section "Iterative solvers and preconditioning" (the three linear systems).
+Reading of the coupling: every coupling term is taken at time level k (v^k in
+the convection matrix, phi^k and Phi^k in the potentials and in the Korteweg
+force, mu^k and v^k in the Oseen convecting field), so the sub-solves of one
+step are independent of each other.
+
+Models:
+* ``ch``      one phase, double-well potential, no vapour field.
+* ``ch_ac``   one phase plus the vapour field, liquid/gas interpolated potential.
+* ``ternary`` polymer and NFA phases (solvent = 1 - phi_p - phi_N), vapour
+              field and the Oseen step; the eliminated phase's chemical
+              potential is recovered from the second CH equation (the paper's
+              air-elimination procedure in section "Numerical results", applied
+              to the solvent).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fem, potential as pot, solvers, systems
+from .systems import Params
+
+
+class Operators:
+    """Mesh plus the step-independent matrices."""
+
+    def __init__(self, n: int, need_p2: bool = False):
+        self.n = n
+        self.mesh = fem.Mesh(n)
+        self.M = fem.p1_mass(self.mesh)
+        self.K = fem.p1_stiffness(self.mesh)
+        self.Mv = fem.p2_mass(self.mesh) if need_p2 else None
+        self.B = fem.divergence_matrix(self.mesh) if need_p2 else None
+        self._Ksym = {}
+
+    def Ksym(self, eta):
+        if eta not in self._Ksym:
+            self._Ksym[eta] = fem.p2_sym_stiffness(self.mesh, eta)
+        return self._Ksym[eta]
+
+    def mass_solve(self, b):
+        return solvers.sparse_solve(self.M, b)
+
+
+def _solve(A, b, how):
+    if how == "dense":
+        return solvers.dense_solve(A, b)
+    return solvers.sparse_solve(A, b)
+
+
+def chemical_potential(ops: Operators, fprime_nodal, phi, beta):
+    """mu = M^{-1}(M f' + beta K phi) = f' + beta M^{-1} K phi (second CH equation)."""
+    return fprime_nodal + beta * ops.mass_solve(ops.K @ phi)
+
+
+def initial_state(ops: Operators, prm: Params, model: str, fields: dict):
+    """Complete the seeded fields with initial chemical potentials."""
+    st = dict(phi=[np.array(f, dtype=np.float64) for f in fields["phi"]],
+              Phi_v=None if fields.get("Phi_v") is None else np.array(fields["Phi_v"]),
+              vel=None if fields.get("vel") is None else np.array(fields["vel"]),
+              p=None if fields.get("p") is None else np.array(fields["p"]))
+    if model == "ch":
+        fp = [pot.dfdphi_bin(st["phi"][0])]
+    elif model == "ch_ac":
+        fp = [pot.dfdphi_bin(st["phi"][0], st["Phi_v"])]
+    else:
+        fp = list(pot.dfdphi_ter(st["phi"][0], st["phi"][1], st["Phi_v"]))
+    st["mu"] = [chemical_potential(ops, f, ph, prm.beta) for f, ph in zip(fp, st["phi"])]
+    if model == "ternary":
+        ps = 1.0 - st["phi"][0] - st["phi"][1]
+        st["mu_s"] = chemical_potential(ops, pot.dfdphis_ter(ps, st["Phi_v"]), ps, prm.beta)
+    return st
+
+
+def explicit_terms(model, st):
+    """Nodal f'(phi^k) per CH phase and f_v'(Phi^k) for the AC equation."""
+    if model == "ch":
+        return [pot.dfdphi_bin(st["phi"][0])], None
+    if model == "ch_ac":
+        return ([pot.dfdphi_bin(st["phi"][0], st["Phi_v"])],
+                pot.dfdPhi_bin(st["phi"][0], st["Phi_v"]))
+    dp, dn = pot.dfdphi_ter(st["phi"][0], st["phi"][1], st["Phi_v"])
+    return [dp, dn], pot.dfdPhi_ter(st["phi"][0], st["phi"][1], st["Phi_v"])
+
+
+def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
+         return_systems: bool = False):
+    """Advance one step; ``how`` in {"dense", "splu", "fft"} (fft needs v = 0)."""
+    n, M, K = ops.n, ops.M, ops.K
+    mesh = ops.mesh
+    vel = st.get("vel")
+    C = fem.p1_convection(mesh, vel) if vel is not None else None
+    if how == "fft" and C is not None:
+        raise ValueError("the Fourier solve needs a convection-free system")
+    fps, fv = explicit_terms(model, st)
+    out = dict(vel=vel, p=st.get("p"))
+    sysrec = {}
+
+    # Cahn-Hilliard, one solve per phase (same matrix)
+    A_ch = systems.ch_matrix(M, K, C, prm)
+    sysrec["ch"] = A_ch
+    phis, mus = [], []
+    for ph, fp in zip(st["phi"], fps):
+        b = systems.ch_rhs(M, ph, fp, prm)
+        sysrec.setdefault("ch_rhs", []).append(b)
+        if how == "fft":
+            N = n * n
+            x1, x2 = solvers.fft_ch_solve(n, prm, b[:N], b[N:])
+            x = np.concatenate([x1, x2])
+        else:
+            x = _solve(A_ch, b, how)
+        phis.append(x[: n * n])
+        mus.append(x[n * n:])
+    out["phi"], out["mu"] = phis, mus
+
+    # Allen-Cahn
+    if model in ("ch_ac", "ternary"):
+        A_ac = systems.ac_matrix(M, K, C, prm)
+        b = systems.ac_rhs(M, st["Phi_v"], fv, prm)
+        sysrec["ac"], sysrec["ac_rhs"] = A_ac, b
+        out["Phi_v"] = solvers.fft_ac_solve(n, prm, b) if how == "fft" else _solve(A_ac, b, how)
+    else:
+        out["Phi_v"] = None
+
+    # Oseen step and closure
+    if model == "ternary":
+        ps_k = 1.0 - st["phi"][0] - st["phi"][1]
+        grads = [fem.p1_grad(mesh, u) for u in (st["phi"][0], st["phi"][1], ps_k, st["Phi_v"])]
+        betas = [prm.beta, prm.beta, prm.beta, prm.beta_v]
+        mu_grads = [fem.p1_grad(mesh, u) for u in (st["mu"][0], st["mu"][1], st["mu_s"])]
+        w_const = -prm.alpha * (mu_grads[0] + mu_grads[1] + mu_grads[2])
+        J = fem.p2_convection(mesh, prm.rho * vel, w_const)
+        Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm)
+        F = fem.korteweg_load(mesh, grads, betas)
+        rhs = systems.oseen_rhs(ops.Mv, vel, F, prm)
+        sysrec["ns_A"], sysrec["ns_rhs"] = Avel, rhs
+        v, p, _ = solvers.bordered_oseen_solve(Avel, ops.B, M, rhs, dense=(how == "dense"))
+        N2 = 4 * n * n
+        out["vel"] = np.stack([v[:N2], v[N2:]])
+        out["p"] = p
+        ps1 = 1.0 - phis[0] - phis[1]
+        out["mu_s"] = pot.dfdphis_ter(ps_k, st["Phi_v"]) + prm.beta * ops.mass_solve(K @ ps1)
+    if return_systems:
+        return out, sysrec
+    return out
+
+
+def mass(ops: Operators, u):
+    """Discrete mass 1^T M u."""
+    return float(np.ones(ops.n * ops.n) @ (ops.M @ u))
+
+
+def energy_ch(ops: Operators, prm: Params, phi, Phi=None):
+    """E_h = beta/2 phi^T K phi + sum_i (M 1)_i f(phi_i) (binary potential)."""
+    lump = ops.M @ np.ones(ops.n * ops.n)
+    return 0.5 * prm.beta * phi @ (ops.K @ phi) + lump @ pot.f_bin(phi, Phi)

@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs shared by the HIP path, its tests and the CPU oracle.
+
+This module holds no arithmetic of the method itself: it only draws the initial
+fields (uniform noise about a mean, a layered vapour field, a divergence-free
+random velocity from a stream function) and names the workload parameters.
+Both the oracle and the GPU path receive identical arrays from here.
+
+Numbering convention (a stated interface, used by both sides): on the periodic
+unit square with n cells per side, vertex (i, j) has id ``i + n*j`` and sits at
+``(i/n, j/n)``.  Quadratic (P2) velocity nodes are the n*n vertices, then the
+midpoints of the horizontal edges ``(i,j)-(i+1,j)``, then of the vertical edges
+``(i,j)-(i,j+1)``, then of the diagonal edges ``(i,j)-(i+1,j+1)``; each group is
+numbered ``i + n*j``.
+
+The paper's initial data (section "Numerical results", figure of the initial
+condition) is a polymer/NFA/solvent film with uniform +-0.01 fluctuations; the
+workloads below keep that noise model on a periodic box.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 20250117
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def vertex_coords(n: int) -> np.ndarray:
+    """(n*n, 2) coordinates of the P1 nodes in id order."""
+    j, i = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([i.ravel() / n, j.ravel() / n], axis=1)
+
+
+def p2_coords(n: int) -> np.ndarray:
+    """(4*n*n, 2) coordinates of the P2 nodes in id order (see module doc)."""
+    v = vertex_coords(n)
+    h = 1.0 / n
+    return np.concatenate(
+        [v, v + [0.5 * h, 0.0], v + [0.0, 0.5 * h], v + [0.5 * h, 0.5 * h]], axis=0
+    )
+
+
+def noisy_field(n: int, mean: float, amp: float, seed: int) -> np.ndarray:
+    """mean + amp * U(-1, 1) at every vertex."""
+    return mean + amp * rng(seed).uniform(-1.0, 1.0, size=n * n)
+
+
+def vapour_layer(n: int) -> np.ndarray:
+    """Phi_v^0 = sin^2(pi y): liquid at y = 0 (= 1 by periodicity), vapour at y = 1/2."""
+    y = vertex_coords(n)[:, 1]
+    return np.sin(np.pi * y) ** 2
+
+
+def stream_velocity(n: int, seed: int, modes: int = 16, amp: float = 0.01) -> np.ndarray:
+    """Divergence-free velocity v = (d psi/dy, -d psi/dx) at the P2 nodes.
+
+    psi = sum_m amp * sin(2 pi k_m . x + theta_m), k_m uniform on {-4..4}^2 minus 0,
+    theta_m ~ U(0, 2 pi).  Returns (2, 4*n*n): x components then y components.
+    """
+    g = rng(seed)
+    ks = []
+    while len(ks) < modes:
+        k = g.integers(-4, 5, size=2)
+        if k[0] != 0 or k[1] != 0:
+            ks.append(k)
+    ks = np.array(ks, dtype=np.float64)
+    th = g.uniform(0.0, 2.0 * np.pi, size=modes)
+    xy = p2_coords(n)
+    arg = 2.0 * np.pi * (xy @ ks.T) + th[None, :]
+    c = amp * np.cos(arg) * 2.0 * np.pi
+    vx = c @ ks[:, 1]
+    vy = -(c @ ks[:, 0])
+    return np.stack([vx, vy], axis=0)
+
+
+def log_uniform(g: np.random.Generator, lo: float, hi: float) -> float:
+    return float(np.exp(g.uniform(np.log(lo), np.log(hi))))
+
+
+# Workloads.  "binary" = one Cahn-Hilliard phase with the double-well / mixing
+# potential; "ternary" = polymer and NFA phases (solvent eliminated) with the
+# fitted quartic potential, plus the vapour field and the Oseen step.
+CONFIGS = {
+    "ch32": dict(n=32, model="ch", eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.0,
+                 viscosity=1.0, steps=1, mean=0.5, seed=BASE_SEED + 0),
+    "dry256": dict(n=256, model="ternary", eps=0.01, tau=5e-4, mobility=1.0, evap_rate=0.1,
+                   viscosity=1.0, steps=20, mean=0.3, seed=BASE_SEED + 1),
+    "chac1024": dict(n=1024, model="ch_ac", eps=0.005, tau=1e-4, mobility=1.0, evap_rate=0.1,
+                     viscosity=1.0, steps=1, mean=0.4, seed=BASE_SEED + 2,
+                     tau_sweep=(1e-5, 1e-4, 1e-3, 1e-2)),
+    "batch64": dict(instances=64, sizes=(64, 128, 256, 512), seed=BASE_SEED + 3),
+    "adjoint128": dict(n=128, model="ternary", eps=0.015, tau=1e-3, mobility=2.0, evap_rate=0.2,
+                       viscosity=1.0, steps=50, mean=0.3, seed=BASE_SEED + 4,
+                       theta0=(0.0125, 1.5, 0.15)),
+}
+
+
+def initial_state(n: int, model: str, mean: float, seed: int, with_velocity: bool | None = None):
+    """Initial fields for a workload.  Keys: phi (list of arrays), Phi_v, vel, p.
+
+    Each field draws from its own child stream of ``SeedSequence(seed)``.
+    """
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(4)
+    seeds = [int(k.generate_state(1)[0]) for k in kids]
+    nphase = 2 if model == "ternary" else 1
+    phi = [noisy_field(n, mean, 0.01, seeds[i]) for i in range(nphase)]
+    Phi_v = vapour_layer(n) if model in ("ch_ac", "ternary") else None
+    if with_velocity is None:
+        with_velocity = model == "ternary"
+    vel = stream_velocity(n, seeds[2]) if with_velocity else None
+    p = np.zeros(n * n) if model == "ternary" else None
+    return dict(phi=phi, Phi_v=Phi_v, vel=vel, p=p)
+
+
+def batch_instances(count: int = 64, sizes=(64, 128, 256, 512), seed: int = BASE_SEED + 3):
+    """Per-instance mesh size and parameters for the batched workload."""
+    g = rng(seed)
+    out = []
+    for _ in range(count):
+        out.append(dict(
+            n=int(g.choice(sizes)),
+            eps=log_uniform(g, 0.005, 0.05),
+            tau=log_uniform(g, 1e-5, 1e-2),
+            mobility=log_uniform(g, 0.1, 10.0),
+            evap_rate=log_uniform(g, 0.01, 1.0),
+            seed=int(g.integers(0, 2**31 - 1)),
+        ))
+    return out

@@ -1,0 +1,218 @@
+"""Pins of the oracle's systems, solvers and time step.
+
+* Fourier-mode solves (symbols written out from the stencils) == SuperLU ==
+  dense LU on the same systems.
+* Manufactured solutions: the CH and AC systems with convection converge at
+  second order in L2 for P1; the Taylor-Hood Oseen system at third order for
+  velocity and second for pressure.
+* Invariants: per-phase discrete mass balance, energy decay at small tau,
+  divergence-free velocity and mean-zero pressure after the Oseen solve.
+* Derivatives of the potentials against central differences of the densities.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fem, potential as pot, solvers, step as S, systems
+from oracle.systems import Params
+from paper_2501_11767_amd import inputs
+
+
+def _state(ops, prm, model, n, mean, seed, vel=False):
+    f = inputs.initial_state(n, model, mean, seed, with_velocity=vel)
+    return S.initial_state(ops, prm, model, f)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_fft_equals_splu_equals_dense_ch_ac(n):
+    ops = S.Operators(n)
+    prm = Params(eps=0.05, tau=1e-3, mobility=1.3, evap_rate=0.4)
+    st = _state(ops, prm, "ch_ac", n, 0.4, 11)
+    a = S.step(ops, prm, "ch_ac", st, "fft")
+    b = S.step(ops, prm, "ch_ac", st, "splu")
+    c = S.step(ops, prm, "ch_ac", st, "dense")
+    for k in ("phi", "mu"):
+        for x in (b, c):
+            assert np.linalg.norm(a[k][0] - x[k][0]) <= 1e-12 * np.linalg.norm(a[k][0])
+    for x in (b, c):
+        assert np.linalg.norm(a["Phi_v"] - x["Phi_v"]) <= 1e-13 * np.linalg.norm(a["Phi_v"])
+
+
+def test_symbols_match_assembled_matrices():
+    n = 8
+    ops = S.Operators(n)
+    Kh, Mh = solvers.p1_symbols(n)
+    # eigen-decomposition: A F^{-1} = F^{-1} diag(symbol) on a random vector
+    x = np.random.default_rng(0).standard_normal(n * n)
+    X = np.fft.fft2(x.reshape(n, n))
+    for A, s in ((ops.K, Kh), (ops.M, Mh)):
+        y = np.real(np.fft.ifft2(s * X)).ravel()
+        assert np.allclose(A @ x, y, atol=1e-13)
+
+
+def _mms_fields():
+    tp = 2 * np.pi
+    phi = lambda x, y: 0.3 * np.cos(tp * x) * np.sin(tp * y) + 0.1 * np.sin(2 * tp * x)
+    lap_phi = lambda x, y: -2 * tp ** 2 * 0.3 * np.cos(tp * x) * np.sin(tp * y) \
+        - (2 * tp) ** 2 * 0.1 * np.sin(2 * tp * x)
+    phi_x = lambda x, y: -tp * 0.3 * np.sin(tp * x) * np.sin(tp * y) + 2 * tp * 0.1 * np.cos(2 * tp * x)
+    phi_y = lambda x, y: tp * 0.3 * np.cos(tp * x) * np.cos(tp * y)
+    mu = lambda x, y: np.sin(tp * x) * np.cos(2 * tp * y)
+    lap_mu = lambda x, y: -(tp ** 2 + (2 * tp) ** 2) * np.sin(tp * x) * np.cos(2 * tp * y)
+    return phi, lap_phi, phi_x, phi_y, mu, lap_mu
+
+
+def _nodal(n, f):
+    xy = inputs.vertex_coords(n)
+    return f(xy[:, 0], xy[:, 1])
+
+
+def test_mms_cahn_hilliard_with_convection_second_order():
+    phi, lap_phi, phi_x, phi_y, mu, lap_mu = _mms_fields()
+    prm = Params(eps=0.1, tau=0.01, mobility=1.0)
+    a, b = 0.7, -0.4
+    errs = []
+    for n in (16, 32, 64):
+        ops = S.Operators(n)
+        vel = np.zeros((2, 4 * n * n))
+        vel[0], vel[1] = a, b
+        C = fem.p1_convection(ops.mesh, vel)
+        A = systems.ch_matrix(ops.M, ops.K, C, prm)
+        F1 = lambda x, y: phi(x, y) + prm.tau * (a * phi_x(x, y) + b * phi_y(x, y)) \
+            - prm.tau * prm.gamma * lap_mu(x, y)
+        F2 = lambda x, y: mu(x, y) + prm.beta * lap_phi(x, y)
+        t, g, be = prm.tau, prm.gamma, prm.beta
+        rhs = np.concatenate([fem.p1_load(ops.mesh, F1), -(t * g / be) * fem.p1_load(ops.mesh, F2)])
+        x = solvers.sparse_solve(A, rhs)
+        N = n * n
+        e = x[:N] - _nodal(n, phi)
+        errs.append(np.sqrt(e @ (ops.M @ e)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert r1 > 3.5 and r2 > 3.7, errs
+
+
+def test_mms_allen_cahn_with_convection_second_order():
+    phi, lap_phi, phi_x, phi_y, _, _ = _mms_fields()
+    prm = Params(eps=0.2, tau=0.01, evap_rate=1.0)
+    a, b = -0.3, 0.9
+    errs = []
+    for n in (16, 32, 64):
+        ops = S.Operators(n)
+        vel = np.zeros((2, 4 * n * n))
+        vel[0], vel[1] = a, b
+        C = fem.p1_convection(ops.mesh, vel)
+        A = systems.ac_matrix(ops.M, ops.K, C, prm)
+        F = lambda x, y: phi(x, y) + prm.tau * (a * phi_x(x, y) + b * phi_y(x, y)) \
+            - prm.tau * prm.delta_v * lap_phi(x, y)
+        x = solvers.sparse_solve(A, fem.p1_load(ops.mesh, F))
+        e = x - _nodal(n, phi)
+        errs.append(np.sqrt(e @ (ops.M @ e)))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.7, errs
+
+
+def test_mms_oseen_taylor_hood_orders():
+    tp = 2 * np.pi
+    u = lambda x, y: np.sin(tp * x) * np.cos(tp * y)
+    v = lambda x, y: -np.cos(tp * x) * np.sin(tp * y)
+    p = lambda x, y: np.sin(tp * x) * np.sin(tp * y)
+    ux = lambda x, y: tp * np.cos(tp * x) * np.cos(tp * y)
+    uy = lambda x, y: -tp * np.sin(tp * x) * np.sin(tp * y)
+    vx = lambda x, y: tp * np.sin(tp * x) * np.sin(tp * y)
+    vy = lambda x, y: -tp * np.cos(tp * x) * np.cos(tp * y)
+    px = lambda x, y: tp * np.cos(tp * x) * np.sin(tp * y)
+    py = lambda x, y: tp * np.sin(tp * x) * np.cos(tp * y)
+    prm = Params(eps=0.1, tau=0.05, viscosity=0.7, rho=1.0)
+    wa, wb = 0.5, 0.25
+    k = prm.rho / prm.tau
+    fx = lambda x, y: k * u(x, y) + wa * ux(x, y) + wb * uy(x, y) + prm.viscosity * 2 * tp ** 2 * u(x, y) + px(x, y)
+    fy = lambda x, y: k * v(x, y) + wa * vx(x, y) + wb * vy(x, y) + prm.viscosity * 2 * tp ** 2 * v(x, y) + py(x, y)
+    ev, ep = [], []
+    for n in (8, 16, 32):
+        ops = S.Operators(n, need_p2=True)
+        m = ops.mesh
+        w = np.zeros((2, 4 * n * n))
+        w[0], w[1] = wa, wb
+        J = fem.p2_convection(m, w)
+        Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm)
+        rhs = fem.p2_load_vec(m, fx, fy)
+        vel, pr, _ = solvers.bordered_oseen_solve(Avel, ops.B, ops.M, rhs)
+        xy2 = inputs.p2_coords(n)
+        eu = vel - np.concatenate([u(xy2[:, 0], xy2[:, 1]), v(xy2[:, 0], xy2[:, 1])])
+        Mv2 = sp.block_diag([ops.Mv, ops.Mv])
+        ev.append(np.sqrt(eu @ (Mv2 @ eu)))
+        epp = pr - _nodal(n, p)
+        epp -= (np.ones(n * n) @ (ops.M @ epp))  # both mean-zero up to quadrature
+        ep.append(np.sqrt(epp @ (ops.M @ epp)))
+    assert ev[0] / ev[1] > 6.5 and ev[1] / ev[2] > 7.0, ev
+    assert ep[0] / ep[1] > 3.3 and ep[1] / ep[2] > 3.6, ep
+
+
+def test_ch_mass_balance_with_convection():
+    n = 16
+    ops = S.Operators(n)
+    prm = Params(eps=0.05, tau=1e-3, mobility=1.0)
+    f = inputs.initial_state(n, "ch", 0.5, 5)
+    f["vel"] = inputs.stream_velocity(n, 9, amp=0.05)
+    st = S.initial_state(ops, prm, "ch", f)
+    out = S.step(ops, prm, "ch", st, "splu")
+    C = fem.p1_convection(ops.mesh, f["vel"])
+    one = np.ones(n * n)
+    lhs = one @ (ops.M @ (out["phi"][0] - st["phi"][0])) + prm.tau * one @ (C @ out["phi"][0])
+    assert abs(lhs) < 1e-13 * abs(one @ (ops.M @ st["phi"][0]))
+    # without convection the mass is conserved exactly
+    st["vel"] = None
+    out = S.step(ops, prm, "ch", st, "fft")
+    assert abs(S.mass(ops, out["phi"][0]) - S.mass(ops, st["phi"][0])) < 1e-14
+
+
+def test_energy_decays_at_small_tau():
+    c = inputs.CONFIGS["ch32"]
+    n = c["n"]
+    ops = S.Operators(n)
+    prm = Params(eps=c["eps"], tau=1e-5, mobility=c["mobility"])
+    st = _state(ops, prm, "ch", n, c["mean"], c["seed"])
+    E = [S.energy_ch(ops, prm, st["phi"][0])]
+    for _ in range(100):
+        st = S.step(ops, prm, "ch", st, "fft")
+        E.append(S.energy_ch(ops, prm, st["phi"][0]))
+    assert np.all(np.diff(E) < 0.0)
+
+
+def test_ternary_step_dense_equals_splu_and_invariants():
+    n = 8
+    ops = S.Operators(n, need_p2=True)
+    prm = Params(eps=0.04, tau=5e-4, mobility=1.0, evap_rate=0.1, viscosity=1.0)
+    st = _state(ops, prm, "ternary", n, 0.3, 2, vel=True)
+    a = S.step(ops, prm, "ternary", st, "splu")
+    b = S.step(ops, prm, "ternary", st, "dense")
+    for k in ("vel", "p", "Phi_v", "mu_s"):
+        assert np.linalg.norm(a[k] - b[k]) <= 1e-11 * np.linalg.norm(a[k]), k
+    for i in range(2):
+        assert np.linalg.norm(a["phi"][i] - b["phi"][i]) <= 1e-13 * np.linalg.norm(a["phi"][i])
+    v = np.concatenate([a["vel"][0], a["vel"][1]])
+    assert np.abs(ops.B @ v).max() < 1e-12
+    assert abs(np.ones(n * n) @ (ops.M @ a["p"])) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_potential_derivatives_central_difference(seed):
+    g = np.random.default_rng(seed)
+    phi, Phi = g.uniform(0, 1, 50), g.uniform(0, 1, 50)
+    h = 1e-6
+    fd = (pot.f_bin(phi + h) - pot.f_bin(phi - h)) / (2 * h)
+    assert np.allclose(pot.dfdphi_bin(phi), fd, atol=1e-8)
+    fd = (pot.f_bin(phi + h, Phi) - pot.f_bin(phi - h, Phi)) / (2 * h)
+    assert np.allclose(pot.dfdphi_bin(phi, Phi), fd, atol=1e-8)
+    fd = (pot.f_bin(phi, Phi + h) - pot.f_bin(phi, Phi - h)) / (2 * h)
+    assert np.allclose(pot.dfdPhi_bin(phi, Phi), fd, atol=1e-8)
+    pp, pn = 0.5 * phi, 0.5 * g.uniform(0, 1, 50)
+    dp, dn = pot.dfdphi_ter(pp, pn, Phi)
+    assert np.allclose(dp, (pot.f_ter(pp + h, pn, Phi) - pot.f_ter(pp - h, pn, Phi)) / (2 * h), atol=1e-8)
+    assert np.allclose(dn, (pot.f_ter(pp, pn + h, Phi) - pot.f_ter(pp, pn - h, Phi)) / (2 * h), atol=1e-8)
+    assert np.allclose(pot.dfdPhi_ter(pp, pn, Phi),
+                       (pot.f_ter(pp, pn, Phi + h) - pot.f_ter(pp, pn, Phi - h)) / (2 * h), atol=1e-8)
+    # the unreduced solvent derivative of eq. (appPotential) at phi_a = 0
+    ps = 1 - pp - pn
+    p = pot.interp(Phi)
+    full = lambda s: (1 - p) * (3.5 * pp ** 2 * pn ** 2 + 0.3 * s ** 2) + p * (3.5 * pp ** 2 + 3.5 * pn ** 2 + 2 * s ** 2)
+    assert np.allclose(pot.dfdphis_ter(ps, Phi), (full(ps + h) - full(ps - h)) / (2 * h), atol=1e-8)
