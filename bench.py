@@ -1,0 +1,263 @@
+"""Benchmark of the coupled Cahn-Hilliard + Allen-Cahn step on one MI355X.
+
+Workload (one "step" = one pass of the whole hot path): on the periodic
+1024 x 1024 P1 mesh (1,048,576 nodes), assemble the step, build both
+right-hand sides, solve the 2,097,152-unknown Cahn-Hilliard block with FGMRES
+and the matching-Schur block preconditioner, and the 1,048,576-unknown
+Allen-Cahn system with FGMRES and multigrid, to ||b - A x|| <= 1e-8 ||b||.
+eps = 0.005, mobility 1, evaporation rate 0.1; initial phi = 0.4 +- 0.01
+uniform noise, Phi_v = sin^2(pi y); tau = 1e-4 for the timed steps.
+
+Prints one JSON line: DOF*iterations/s over the timed steps in the mixed
+precision form (FP32 multigrid inside FP64 FGMRES), ms per step, the same for
+plain FP64, a tau sweep {1e-5, 1e-4, 1e-3, 1e-2} with the error of both forms
+against the oracle's exact Fourier-mode solve, the roofline of the dominant
+kernel and the oracle's own FGMRES rate on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--tau", type=float, default=1e-4)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_steps(ctx, chns, f, k, opts):
+    """k coupled steps in place; returns (wall ms list, infos list)."""
+    import torch
+    walls, infos = [], []
+    for _ in range(k):
+        t0 = time.perf_counter()
+        rc, inf = ctx.timestep(f, f, 1, opts)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        infos.append(inf)
+        if rc < 0:
+            raise RuntimeError(f"timestep failed: {rc}")
+    return walls, infos
+
+
+def dof_iters(infos, N):
+    """Sum over solves of (unknowns x iterations) and of solve ms."""
+    di, ms = 0.0, 0.0
+    for inf in infos:
+        ch, ac = inf[0], inf[1]
+        di += 2 * N * ch["iters"] + N * ac["iters"]
+        ms += ch["ms"] + ac["ms"]
+    return di, ms
+
+
+def kernel_roofline(ctx, chns, N, reps):
+    """Average duration of single kernels, timed with events on the stream
+    the library launches on (torch's current stream)."""
+    import torch
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.rand(2 * N, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+    x32, y32 = x[:N].float().contiguous(), torch.zeros(N, dtype=torch.float32, device="cuda")
+    cases = {
+        # name: (callable, algorithmic bytes per launch)
+        "ch_block_f64": (lambda: ctx.spmv(chns.OP_CH, x, y), N * (7 * 4 + 2 * 7 * 8 + 16 + 16)),
+        "spmv7_f64": (lambda: ctx.spmv(chns.OP_X, x[:N], y[:N]), N * (7 * 12 + 8 + 8)),
+        "spmv7_f32": (lambda: ctx.spmv(chns.OP_X, x32, y32, precision=chns.MIXED), N * (7 * 8 + 4 + 4)),
+    }
+    for name, (fn, nbytes) in cases.items():
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out[name] = dict(us=us, bytes=nbytes, gbs=gbs, frac=gbs / HBM_PEAK_GBS)
+    return out
+
+
+def cpu_baseline(cfg, n, tau, budget_s=20.0):
+    """The oracle's flexible GMRES with its multigrid block preconditioner on
+    the same CH system, a bounded number of Arnoldi steps, single thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fem, krylov, precond as PC, systems
+    from oracle.systems import Params
+    from paper_2501_11767_amd import inputs
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        m = fem.Mesh(n)
+        M, K = fem.p1_mass(m), fem.p1_stiffness(m)
+        prm = Params(eps=cfg["eps"], tau=tau, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+        f = inputs.initial_state(n, "ch_ac", cfg["mean"], cfg["seed"])
+        from oracle import potential as pot
+        A = systems.ch_matrix(M, K, None, prm)
+        b = systems.ch_rhs(M, f["phi"][0], pot.dfdphi_bin(f["phi"][0], f["Phi_v"]), prm)
+        P = PC.CHPreconditioner(M, K, None, prm, n, inner="mg")
+        setup = time.perf_counter() - t0
+        # one Arnoldi step to size the sample, then as many as fit the budget
+        t1 = time.perf_counter()
+        krylov.fgmres(A, b, prec=P.apply, fixed_iters=1)
+        one = time.perf_counter() - t1
+        k = int(max(1, min(30, (budget_s - setup) / max(one, 1e-3))))
+        t2 = time.perf_counter()
+        krylov.fgmres(A, b, prec=P.apply, fixed_iters=k)
+        dt = time.perf_counter() - t2
+    N2 = 2 * n * n
+    return dict(value=N2 * k / dt, unit="DOF·iters/s", cores=1, kind="oracle",
+                sample=f"oracle FGMRES + V(2,2) block preconditioner, CH system of the "
+                       f"{n}x{n} mesh ({N2} unknowns), {k} Arnoldi steps in {dt:.1f} s "
+                       f"after {setup:.1f} s of set-up, FP64, 1 thread")
+
+
+def oracle_errors(cfg, n, st0, sweep, sweep_fields):
+    """CPU leg: the oracle's exact solve of each swept step (convection-free
+    periodic systems, one 2x2 solve per Fourier mode) and the relative error
+    of the GPU fields against it."""
+    from oracle import potential as pot, solvers
+    from oracle.systems import Params
+    phi0, Phi0 = st0["phi"][0], st0["Phi_v"]
+    Kh, Mh = solvers.p1_symbols(n)
+    Mx = lambda v: np.real(np.fft.ifft2(Mh * np.fft.fft2(v.reshape(n, n)))).ravel()
+    fp, fv = pot.dfdphi_bin(phi0, Phi0), pot.dfdPhi_bin(phi0, Phi0)
+    for row in sweep:
+        prm = Params(eps=cfg["eps"], tau=row["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+        t0 = time.perf_counter()
+        ph, mu = solvers.fft_ch_solve(n, prm, Mx(phi0), -(prm.tau * prm.gamma / prm.beta) * Mx(fp))
+        Ph = solvers.fft_ac_solve(n, prm, Mx(Phi0) - prm.tau * prm.gamma_v * Mx(fv))
+        row["oracle_ms"] = (time.perf_counter() - t0) * 1e3
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        for name in ("fp64", "mixed"):
+            g = sweep_fields[(row["tau"], name)]
+            row[name].update(err_phi=rel(g["phi"], ph), err_mu=rel(g["mu"], mu), err_Phi=rel(g["Phi"], Ph))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2501_11767_amd import chns, inputs
+    cfg = inputs.CONFIGS["chac1024"]
+    n = args.n
+    N = n * n
+    p = dict(eps=cfg["eps"], tau=args.tau, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+    ctx = chns.Context(n, "ch_ac", **p)
+    st0 = inputs.initial_state(n, "ch_ac", cfg["mean"], cfg["seed"])
+    fields = {}
+
+    def fresh():
+        phi, Phi = dev(st0["phi"][0]), dev(st0["Phi_v"])
+        mu = torch.zeros(N, dtype=torch.float64, device="cuda")
+        fields.update(phi=phi, mu=mu, Phi=Phi)
+        return ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+
+    res = {}
+    for name, prec in (("mixed", chns.MIXED), ("fp64", chns.F64)):
+        opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart)
+        f = fresh()
+        run_steps(ctx, chns, f, args.warmup, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        walls, infos = run_steps(ctx, chns, f, args.steps, opts)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        di, solve_ms = dof_iters(infos, N)
+        res[name] = dict(
+            value=di / (solve_ms * 1e-3), ms_per_step=total * 1e3 / args.steps,
+            ms_per_step_median=float(np.median(walls)),
+            ch_iters=[i[0]["iters"] for i in infos], ac_iters=[i[1]["iters"] for i in infos],
+            converged=all(i[0]["converged"] and i[1]["converged"] for i in infos),
+            rel_res_ch=max(i[0]["res_true"] / i[0]["bnorm"] for i in infos))
+    kern = kernel_roofline(ctx, chns, N, args.kernel_reps)
+
+    sweep, sweep_fields = [], {}
+    if not args.no_sweep:
+        for tau in cfg["tau_sweep"]:
+            ctx.set_params(**dict(p, tau=tau))
+            row = dict(tau=tau)
+            for name, prec in (("fp64", chns.F64), ("mixed", chns.MIXED)):
+                opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, maxiter=2000)
+                f = fresh()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, inf = ctx.timestep(f, f, 1, opts)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) * 1e3
+                sweep_fields[(tau, name)] = {k: v.cpu().numpy() for k, v in fields.items()}
+                row[name] = dict(ms_to_1e8=wall, ch_iters=inf[0]["iters"], ac_iters=inf[1]["iters"],
+                                 converged=bool(inf[0]["converged"] and inf[1]["converged"]))
+            sweep.append(row)
+        ctx.set_params(**p)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, n, args.tau)
+        if sweep:
+            oracle_errors(cfg, n, st0, sweep, sweep_fields)
+
+    dom = "ch_block_f64"
+    kd = kern[dom]
+    line = {
+        "metric": METRIC,
+        "value": res["mixed"]["value"],
+        "unit": "DOF·iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["mixed"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (FGMRES) + f32 (multigrid)",
+        "data": "synthetic",
+        "config": {"workload": f"chac{n}: coupled CH + AC step, periodic {n}x{n} P1 ({N} nodes, "
+                               f"{3 * N} unknowns), eps {cfg['eps']}, tau {args.tau}, FGMRES({args.restart}) "
+                               f"rtol 1e-8, V(2,2) block preconditioner",
+                   "n": n, "tau": args.tau, "restart": args.restart},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kd["frac"], "traffic": None,
+                     "bytes_per_launch": kd["bytes"], "us_per_launch": kd["us"]},
+        "cpu_baseline": cpu,
+        "mixed": res["mixed"],
+        "fp64": res["fp64"],
+        "kernels": kern,
+        "sweep": sweep,
+    }
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * chns.h -- C-ABI of the MI355X (gfx950) solver library for the linear systems
+ * of one semi-implicit finite-element time step of the Cahn-Hilliard /
+ * Allen-Cahn / Navier-Stokes drying model of arXiv 2501.11767
+ * ("Preconditioning for a Cahn-Hilliard-Navier-Stokes model for morphology
+ * formation in organic solar cells").
+ *
+ * Problem statement (paper, sections "Spatial & temporal discretization" and
+ * "Iterative solvers and preconditioning"): a triangulation, the fields
+ * phi_i^k, mu_i^k, Phi_v^k, v^k, p^k and the parameters go in; the step-(k+1)
+ * fields come out.  Each step solves
+ *   - per Cahn-Hilliard phase eq. (CH_linear):
+ *       [[M + tau C, tau g K], [tau g K, -(tau g / beta) M]] [phi; mu]
+ *         = [M phi^k; -(tau g / beta) f^k],
+ *   - the Allen-Cahn system (M + tau delta_v K + tau C) Phi = M Phi^k - tau g_v f_v^k,
+ *   - the Oseen saddle point eq. (linearnav) [[A, B^T], [B, 0]] [v; p] = [..; 0],
+ * with FGMRES and the paper's block-diagonal preconditioners.
+ *
+ * Conventions shared by every entry point
+ *   - Mesh: periodic unit square, n cells per side (n even, 8 <= n <= 8192),
+ *     each cell split along its (i,j)-(i+1,j+1) diagonal.  P1 node (i, j) has
+ *     id i + n*j.  P2 velocity nodes: the n*n vertices, then the midpoints of
+ *     horizontal, vertical and diagonal edges, each block numbered i + n*j;
+ *     a velocity field is 2 * 4n^2 doubles, x components first.
+ *   - Parameter reading: beta = eps^2, gamma = mobility, gamma_v = evap_rate,
+ *     delta_v = evap_rate * eps^2, beta_v = eps^2, rho and alpha as given.
+ *   - Every "d_" pointer is device memory owned by the caller, FP64 unless
+ *     stated, contiguous, not aliased with another argument unless stated.
+ *     Every "h_" pointer is host memory owned by the caller.
+ *   - "stream" is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream unless documented as synchronising.
+ *   - The context owns all matrices, multigrid levels and Krylov workspace;
+ *     it allocates device memory only in chns_create.  A context is not
+ *     thread-safe; use one context per stream.
+ *   - Return values: CHNS_OK, the warning CHNS_WNOCONV (outputs written with
+ *     the best iterate), or a negative error.  Invalid arguments are rejected
+ *     with CHNS_EINVAL before anything is launched; chns_last_error() then
+ *     describes the problem.
+ */
+#ifndef CHNS_H
+#define CHNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHNS_API __attribute__((visibility("default")))
+
+typedef struct chns_ctx chns_ctx;
+
+enum {
+  CHNS_OK = 0,
+  CHNS_WNOCONV = 1,      /* tolerance not reached within maxiter: best iterate written */
+  CHNS_EINVAL = -1,      /* invalid argument (shape, null pointer, NaN/Inf parameter) */
+  CHNS_ENOMEM = -2,      /* device allocation failed in chns_create */
+  CHNS_EHIP = -3,        /* a HIP runtime call failed */
+  CHNS_ESTATE = -4,      /* call not valid in the context's current state */
+  CHNS_EUNSUPPORTED = -5 /* operation not available for this model */
+};
+
+/* Models: which fields a step advances. */
+enum {
+  CHNS_MODEL_CH = 0,      /* one CH phase, double-well potential phi^2 (1-phi)^2 */
+  CHNS_MODEL_CH_AC = 1,   /* one CH phase + vapour field, liquid/gas interpolated potential */
+  CHNS_MODEL_TERNARY = 2  /* polymer + NFA CH phases (solvent = 1 - sum), vapour, Oseen */
+};
+
+/* Linear systems (blocks) of a step. */
+enum { CHNS_BLOCK_CH = 0, CHNS_BLOCK_AC = 1, CHNS_BLOCK_NS = 2 };
+
+/* Operators for chns_spmv / chns_get_matrix. */
+enum {
+  CHNS_OP_M = 0,       /* P1 mass, n^2 x n^2 */
+  CHNS_OP_K = 1,       /* P1 stiffness */
+  CHNS_OP_C = 2,       /* P1 convection C(v^k) from the last chns_assemble */
+  CHNS_OP_CH = 3,      /* CH 2x2 block operator on [phi; mu], 2n^2 x 2n^2 */
+  CHNS_OP_AC = 4,      /* Allen-Cahn matrix M + tau delta_v K + tau C */
+  CHNS_OP_X = 5,       /* matching factor tau g K + sqrt(tau g / beta) M */
+  CHNS_OP_L = 6,       /* CH (1,1) block M + tau C */
+  CHNS_OP_NS = 7       /* Oseen saddle point on [v_x; v_y; p] (ternary model) */
+};
+
+/* Arithmetic of the preconditioner: all FP64, or FP32 multigrid inside an
+ * FP64 flexible Krylov method (residuals, dots, Hessenberg in FP64). */
+enum { CHNS_F64 = 0, CHNS_MIXED = 1 };
+
+typedef struct {
+  int32_t n;      /* cells per side */
+  int32_t model;  /* CHNS_MODEL_* */
+} chns_mesh;
+
+typedef struct {
+  double eps;        /* interface parameter: beta = beta_v = eps^2 */
+  double tau;        /* time step */
+  double mobility;   /* gamma_i (all phases) */
+  double evap_rate;  /* gamma_v; delta_v = evap_rate * eps^2 */
+  double viscosity;  /* eta */
+  double alpha;      /* alpha_i in the Oseen convecting field */
+  double rho;        /* density (rho = 1 when all pure densities are 1) */
+} chns_params;
+
+typedef struct {
+  double rtol, atol;    /* stop when ||b - A x||_2 <= max(rtol ||b||_2, atol) */
+  int32_t restart;      /* FGMRES restart length m (1..256) */
+  int32_t maxiter;      /* total Arnoldi steps allowed */
+  int32_t precision;    /* CHNS_F64 or CHNS_MIXED */
+  int32_t mg_cycles;    /* V-cycles per inner solve (>= 1) */
+  int32_t mg_pre;       /* damped-Jacobi pre-smoothing sweeps (>= 1) */
+  int32_t mg_post;      /* post-smoothing sweeps (>= 0) */
+  int32_t mg_coarse;    /* sweeps on the coarsest level (>= 1) */
+  double mg_omega;      /* Jacobi damping, 0 < omega <= 1 */
+} chns_solve_opts;
+
+typedef struct {
+  int32_t iters;      /* Arnoldi steps taken */
+  int32_t restarts;   /* cycles started */
+  int32_t converged;  /* 1 if the true residual met the tolerance */
+  int32_t status;     /* CHNS_OK or CHNS_WNOCONV */
+  double bnorm;       /* ||b||_2 */
+  double res0;        /* ||b - A x0||_2 */
+  double res_true;    /* ||b - A x||_2 of the returned iterate (recomputed) */
+  double ms;          /* wall time of the solve in milliseconds (hipEvent) */
+} chns_solve_info;
+
+/* Field set at one time level (device pointers; NULL where the model has no
+ * such field).  phi[0], phi[1]: CH phases (n^2 each); mu[0..1] their chemical
+ * potentials; mu[2] the eliminated solvent's potential (ternary); Phi_v: vapour
+ * field (n^2); vel: P2 velocity (2 * 4n^2); p: pressure (n^2, mean zero). */
+typedef struct {
+  double* phi[2];
+  double* mu[3];
+  double* Phi_v;
+  double* vel;
+  double* p;
+} chns_fields;
+
+/* Defaults: rtol 1e-8, atol 0, restart 30, maxiter 600, F64, 1 V(2,2) cycle,
+ * 16 coarse sweeps, omega 2/3. */
+CHNS_API void chns_default_opts(chns_solve_opts* opts);
+
+/* Build the mesh tables, sparsity patterns (CSR -> SELL-C-sigma), multigrid
+ * hierarchy and Krylov workspace, and assemble M and K on the device
+ * (coloured element scatter).  Synchronising.  *out is NULL on failure. */
+CHNS_API int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out);
+
+CHNS_API int chns_destroy(chns_ctx* ctx);
+
+/* Replace the parameters and re-form every parameter-dependent operator
+ * (on all multigrid levels).  Asynchronous on the context's internal stream
+ * order; synchronising on return. */
+CHNS_API int chns_set_params(chns_ctx* ctx, const chns_params* params);
+
+/* Per-step assembly (paper: C(v^k) of eq. (CH_linear); J(w^k) and the PCD
+ * matrix A_p(w^k) for the Oseen step): coloured element scatter of the
+ * convection matrix from the P2 velocity d_vel (NULL means v = 0), Galerkin
+ * refresh of every coarse level, and re-forming of the block values.
+ * d_mu: for the ternary model the three chemical potentials (polymer, NFA,
+ * solvent) entering w = rho v - alpha sum grad mu_i; NULL otherwise. */
+CHNS_API int chns_assemble(chns_ctx* ctx, const double* d_vel, const double* const* d_mu,
+                           void* stream);
+
+/* Shape of an assembled operator (host query, no device work). */
+CHNS_API int chns_matrix_shape(chns_ctx* ctx, int32_t op, int64_t* nrows, int64_t* ncols,
+                               int64_t* nnz);
+
+/* Copy an assembled operator back as sorted CSR with explicit zeros kept:
+ * h_rowptr[nrows+1], h_col[nnz], h_val[nnz] (any may be NULL to skip).
+ * Synchronising. */
+CHNS_API int chns_get_matrix(chns_ctx* ctx, int32_t op, int32_t* h_rowptr, int32_t* h_col,
+                             double* h_val, void* stream);
+
+/* y = alpha * A x + beta * y for op in CHNS_OP_*.  precision CHNS_F64: x, y
+ * double; CHNS_MIXED: x, y float with FP32 matrix values.  x and y must not
+ * overlap.  With beta == 0, y is not read. */
+CHNS_API int chns_spmv(chns_ctx* ctx, int32_t op, int32_t precision, double alpha,
+                       const void* d_x, double beta, void* d_y, void* stream);
+
+/* z = P^{-1} r for a block (paper: CH diag(L, X M^{-1} X) with L ~ M + tau C
+ * and X = tau g K + sqrt(tau g / beta) M; AC multigrid on its matrix; NS
+ * diag(A^, M_p^{-1} A_p K_p^{-1})).  Inner inverses are opts->mg_cycles
+ * geometric V-cycles in the precision opts->precision; r and z are FP64 and
+ * must not overlap. */
+CHNS_API int chns_precond_apply(chns_ctx* ctx, int32_t block, const chns_solve_opts* opts,
+                                const double* d_r, double* d_z, void* stream);
+
+/* Solve block * x = b by right-preconditioned restarted FGMRES (classical
+ * Gram-Schmidt twice, Givens least squares on the device), stopping rule
+ * ||b - A x|| <= max(rtol ||b||, atol) on the recomputed true residual.
+ * d_x holds the initial guess and receives the solution.  Synchronising
+ * (reads the residual estimate back once per Arnoldi step).  h_info may be NULL. */
+CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, const double* d_b, double* d_x,
+                               const chns_solve_opts* opts, chns_solve_info* h_info,
+                               void* stream);
+
+/* Right-hand sides of one step from the level-k fields (paper: [M phi^k;
+ * -(tau g/beta) f^k] per CH phase with f^k = M f'(phi^k) nodal, the AC
+ * right-hand side, and for the ternary model (rho/tau) M v^k + F^k with the
+ * Korteweg force F).  d_rhs_ch: 2n^2 per CH phase, phases consecutive;
+ * d_rhs_ac: n^2 or NULL; d_rhs_ns: 9n^2 or NULL. */
+CHNS_API int chns_step_rhs(chns_ctx* ctx, const chns_fields* in, double* d_rhs_ch,
+                           double* d_rhs_ac, double* d_rhs_ns, void* stream);
+
+/* Advance nsteps time steps from *in to *out (both field sets complete for
+ * the model; in and out may be the same set).  Per step: assemble, right-hand
+ * sides, one FGMRES solve per CH phase, the AC solve, the Oseen solve, the
+ * closure of the eliminated phase.  h_info (may be NULL) receives one entry
+ * per solve, in the order CH phases, AC, NS, per step.  Synchronising. */
+CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
+                           int32_t nsteps, const chns_solve_opts* opts,
+                           chns_solve_info* h_info, void* stream);
+
+/* Message of the last error on this context (never NULL). */
+CHNS_API const char* chns_last_error(const chns_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHNS_H */

@@ -1,0 +1,78 @@
+// Solver context: device-resident matrices, multigrid levels and Krylov
+// workspace behind the C-ABI of chns.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/chns.h"
+#include "host_mesh.hpp"
+#include "kernels.hpp"
+
+namespace chns {
+
+constexpr int MAX_RESTART = 64;
+
+// Values of one operator on one level, FP64 plus FP32 copy, and 1/diag.
+struct OpVals {
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  double* d64 = nullptr;
+  float* d32 = nullptr;
+};
+
+struct Level {
+  int n = 0, N = 0;
+  Csr csr;
+  Sell sell;
+  DSell d;
+  int* diag = nullptr;
+  // transfer to the next coarser level
+  Csr Pcsr, Rcsr;
+  std::vector<double> Pval, Rval;
+  Sell Psell, Rsell;
+  DSell dP, dR;
+  double *P64 = nullptr, *R64 = nullptr;
+  float *P32 = nullptr, *R32 = nullptr;
+  int *gptr = nullptr, *gsrc = nullptr;
+  double* gw = nullptr;
+  // base value streams
+  double *M = nullptr, *K = nullptr, *C = nullptr;
+  float *M32 = nullptr, *K32 = nullptr, *C32 = nullptr;
+  // preconditioner operators
+  OpVals L, X, AC;
+  // multigrid work vectors (per precision)
+  double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *e64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr, *t32 = nullptr, *r32 = nullptr, *e32 = nullptr;
+};
+
+struct Krylov {
+  int64_t nmax = 0;
+  double *V = nullptr, *Z = nullptr;
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+  double *scal = nullptr, *htmp = nullptr, *part = nullptr, *nrm_part = nullptr;
+  double* host = nullptr;  // pinned readback
+};
+
+}  // namespace chns
+
+struct chns_ctx {
+  chns_mesh mesh{};
+  chns_params prm{};
+  int N = 0;            // P1 nodes
+  bool has_conv = false;
+  std::vector<chns::Level> lv;
+  chns::Elements el;
+  int *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;
+  chns::Krylov kr;
+  // scratch: FP64 tmp1/tmp2/corr (N each), FP32 r/z (2N each) and
+  // tmp1/tmp2/corr (N each), right-hand sides and the CH unknown [phi; mu]
+  double *w64a = nullptr, *w64b = nullptr, *w64c = nullptr;
+  double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr;
+  float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr, *w32c = nullptr;
+  std::vector<void*> allocs;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};

@@ -1,0 +1,77 @@
+// Host-side mesh tables, sparsity patterns and SELL-C-sigma layouts.
+//
+// Mesh: periodic unit square with n cells per side, each cell (i, j) split by
+// its (i,j)-(i+1,j+1) diagonal into a lower triangle ((i,j),(i+1,j),(i+1,j+1))
+// and an upper triangle ((i,j),(i+1,j+1),(i,j+1)).  P1 node (i, j) = i + n*j;
+// P2 nodes: vertices, then horizontal, vertical and diagonal edge midpoints.
+// P2 local order on a triangle (v0, v1, v2): vertices, then the nodes of the
+// edges (v1,v2), (v0,v2), (v0,v1).
+//
+// Elements are grouped in 8 colours, colour = (i mod 2) + 2 (j mod 2) + 4 type
+// (type 0 = lower, 1 = upper); for even n no two triangles of one colour share
+// a vertex or an edge, so a colour can be scattered without atomics.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace chns {
+
+struct Csr {
+  int nrows = 0, ncols = 0;
+  std::vector<int> rowptr, col;
+  int64_t nnz() const { return rowptr.empty() ? 0 : rowptr.back(); }
+  // position of (r, c) in col[], or -1
+  int find(int r, int c) const;
+};
+
+// SELL-C-sigma: rows sorted by length inside windows of sigma rows (stable,
+// longest first), cut into slices of C rows; slice s stores its entries
+// column-major (entry k of the slice's lane l at slice_ptr[s] + k*C + l),
+// padded to the slice's longest row with value 0 and a valid column.
+struct Sell {
+  int nrows = 0, ncols = 0, C = 64, sigma = 1, nslices = 0, width_max = 0;
+  bool uniform = false;          // every slice has width width_max and perm is identity
+  std::vector<int> slice_ptr;    // nslices + 1
+  std::vector<int> slice_w;      // nslices
+  std::vector<int> col;          // slice_ptr[nslices]
+  std::vector<int> perm;         // nslices*C: row stored at that lane position (-1 = none)
+  std::vector<int> csr2sell;     // CSR entry -> SELL slot
+  std::vector<int> diag;         // per row: SELL slot of the diagonal entry (-1 if absent)
+  int64_t slots() const { return slice_ptr.empty() ? 0 : slice_ptr.back(); }
+};
+
+struct Elements {
+  int n = 0, ne = 0;
+  std::vector<int> v;            // ne*3 P1 vertex ids, colour-sorted
+  std::vector<int> p2;           // ne*6 P2 node ids
+  std::vector<int> type;         // 0 lower, 1 upper
+  int colour_ptr[9] = {0};
+};
+
+Elements make_elements(int n);
+
+// Node-pair pattern of an element list: rows from `rn` (per element nr ids),
+// columns from `cn` (nc ids), sorted, duplicates merged.
+Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, const int* cn,
+                          int nc);
+
+Sell make_sell(const Csr& A, int C, int sigma);
+
+// Nested P1 prolongation from size n/2 to n (values: 1 or 1/2).
+void p1_prolongation(int nf, Csr& P, std::vector<double>& val);
+
+// Galerkin map A_c = P^T A_f P on fixed patterns: for each coarse SELL slot,
+// the list of (fine SELL slot, weight).  ptr has Sc.slots()+1 entries.
+struct GalerkinMap {
+  std::vector<int> ptr, src;
+  std::vector<double> w;
+};
+GalerkinMap make_galerkin(const Csr& Af, const Sell& Sf, const Csr& P, const std::vector<double>& Pv,
+                          const Csr& Ac, const Sell& Sc, std::string* err);
+
+// Transpose of a CSR pattern with values.
+void csr_transpose(const Csr& A, const std::vector<double>& av, Csr& T, std::vector<double>& tv);
+
+}  // namespace chns

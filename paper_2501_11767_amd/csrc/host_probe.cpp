@@ -1,0 +1,102 @@
+// Host-only view of the mesh tables, SELL layouts and Galerkin maps that the
+// library builds, exported for CPU tests of the indexing (no device code).
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "host_mesh.hpp"
+
+using namespace chns;
+
+namespace {
+
+void copy_out(const std::vector<int>& v, int32_t* dst) {
+  if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(int));
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) int64_t chns_probe_p1_nnz(int n) {
+  Elements E = make_elements(n);
+  return pattern_from_elements(n * n, n * n, E.ne, E.v.data(), 3, E.v.data(), 3).nnz();
+}
+
+// P1 pattern (CSR) and its SELL-C-64 layout: sell_col[slots], csr2sell[nnz],
+// diag[N], and the flags (uniform, width).
+__attribute__((visibility("default"))) int chns_probe_p1(int n, int32_t* rowptr, int32_t* col,
+                                                         int32_t* sell_col, int32_t* csr2sell,
+                                                         int32_t* diag, int32_t* flags) {
+  Elements E = make_elements(n);
+  Csr A = pattern_from_elements(n * n, n * n, E.ne, E.v.data(), 3, E.v.data(), 3);
+  Sell S = make_sell(A, 64, 1);
+  copy_out(A.rowptr, rowptr);
+  copy_out(A.col, col);
+  copy_out(S.col, sell_col);
+  copy_out(S.csr2sell, csr2sell);
+  copy_out(S.diag, diag);
+  if (flags) {
+    flags[0] = S.uniform;
+    flags[1] = S.width_max;
+    flags[2] = int(S.slots());
+  }
+  return 0;
+}
+
+// Element tables in colour order: v[ne*3], p2[ne*6], type[ne], colour_ptr[9].
+__attribute__((visibility("default"))) int chns_probe_elements(int n, int32_t* v, int32_t* p2,
+                                                               int32_t* type, int32_t* cptr) {
+  Elements E = make_elements(n);
+  copy_out(E.v, v);
+  copy_out(E.p2, p2);
+  copy_out(E.type, type);
+  if (cptr) std::memcpy(cptr, E.colour_ptr, 9 * sizeof(int));
+  return 0;
+}
+
+// Apply the Galerkin map of level nf -> nf/2 to fine values given in CSR
+// order; coarse values returned in CSR order.
+__attribute__((visibility("default"))) int chns_probe_galerkin(int nf, const double* fine_csr,
+                                                               double* coarse_csr) {
+  Elements Ef = make_elements(nf), Ec = make_elements(nf / 2);
+  Csr Af = pattern_from_elements(nf * nf, nf * nf, Ef.ne, Ef.v.data(), 3, Ef.v.data(), 3);
+  Csr Ac = pattern_from_elements(nf * nf / 4, nf * nf / 4, Ec.ne, Ec.v.data(), 3, Ec.v.data(), 3);
+  Sell Sf = make_sell(Af, 64, 1), Sc = make_sell(Ac, 64, 1);
+  Csr P;
+  std::vector<double> Pv;
+  p1_prolongation(nf, P, Pv);
+  std::string err;
+  GalerkinMap G = make_galerkin(Af, Sf, P, Pv, Ac, Sc, &err);
+  if (!err.empty()) return -1;
+  std::vector<double> fs(Sf.slots(), 0.0), cs(Sc.slots(), 0.0);
+  for (int64_t q = 0; q < Af.nnz(); ++q) fs[Sf.csr2sell[q]] = fine_csr[q];
+  for (int64_t s = 0; s < Sc.slots(); ++s)
+    for (int k = G.ptr[s]; k < G.ptr[s + 1]; ++k) cs[s] += G.w[k] * fs[G.src[k]];
+  for (int64_t q = 0; q < Ac.nnz(); ++q) coarse_csr[q] = cs[Sc.csr2sell[q]];
+  return 0;
+}
+
+// Prolongation nf -> nf/2 as CSR (rowptr[nf^2+1], col, val) and the SELL
+// layout flags of P and R = P^T: flags = {P uniform, P width, R uniform, R width}.
+__attribute__((visibility("default"))) int chns_probe_prolongation(int nf, int32_t* rowptr,
+                                                                   int32_t* col, double* val,
+                                                                   int32_t* flags) {
+  Csr P, R;
+  std::vector<double> Pv, Rv;
+  p1_prolongation(nf, P, Pv);
+  csr_transpose(P, Pv, R, Rv);
+  copy_out(P.rowptr, rowptr);
+  copy_out(P.col, col);
+  if (val) std::memcpy(val, Pv.data(), Pv.size() * sizeof(double));
+  if (flags) {
+    Sell Ps = make_sell(P, 64, 1), Rs = make_sell(R, 64, 1);
+    flags[0] = Ps.uniform;
+    flags[1] = Ps.width_max;
+    flags[2] = Rs.uniform;
+    flags[3] = Rs.width_max;
+  }
+  return int(P.nnz());
+}
+
+}  // extern "C"

@@ -1,0 +1,703 @@
+// gfx950 kernels of the solver: SELL-C-sigma sparse products (plain, residual
+// and Jacobi forms, the shared-pattern Cahn-Hilliard block), coloured element
+// assembly, Galerkin refresh of the coarse levels, and the FP64 reductions of
+// flexible GMRES.
+//
+// Everything here is bandwidth-bound (about 0.1-0.2 flop per byte), so the
+// kernels are written for coalesced HBM streams: SELL slices are 64 rows wide
+// (one wavefront, one row per lane, entry k of all 64 rows contiguous), all
+// loads of a row are issued before the arithmetic, and workgroups are
+// remapped so each of the 8 XCDs works on a contiguous range of rows (its L2
+// then also holds the neighbouring rows that the column gathers touch).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace chns {
+
+namespace {
+
+constexpr int BS = 256;   // workgroup size (4 wavefronts)
+constexpr int W7 = 7;     // width of every P1 row on the periodic mesh
+constexpr int MAXRED = 1024;
+
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  Map them so that XCD x processes one contiguous range.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a 256-thread workgroup; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ SpMV
+
+template <typename T, typename TV>
+__global__ __launch_bounds__(BS) void k_spmv_sell(int nslices, int nrows, const int* __restrict__ sptr,
+                                                  const int* __restrict__ sw,
+                                                  const int* __restrict__ col,
+                                                  const TV* __restrict__ val,
+                                                  const int* __restrict__ perm,
+                                                  const T* __restrict__ x, T* __restrict__ y,
+                                                  T alpha, T beta) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int pos = b * BS + threadIdx.x;
+  const int slice = pos >> 6, lane = pos & 63;
+  if (slice >= nslices) return;
+  const int row = perm ? perm[pos] : pos;
+  if (row < 0 || row >= nrows) return;
+  const int w = sw[slice];
+  const int base = sptr[slice] + lane;
+  T sum = T(0);
+  for (int k = 0; k < w; ++k) {
+    const int q = base + k * 64;
+    sum += T(val[q]) * x[col[q]];
+  }
+  y[row] = (beta == T(0)) ? alpha * sum : alpha * sum + beta * y[row];
+}
+
+// Uniform width-7 patterns (P1): identity permutation, slice s = rows 64s..64s+63.
+template <typename T, typename TV, int MODE>
+__global__ __launch_bounds__(BS) void k_stencil7(int nrows, const int* __restrict__ col,
+                                                 const TV* __restrict__ val,
+                                                 const T* __restrict__ x,
+                                                 const T* __restrict__ b,
+                                                 const T* __restrict__ dinv, T p0, T p1,
+                                                 T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= nrows) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  int c[W7];
+  TV v[W7];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) sum += T(v[k]) * x[c[k]];
+  if (MODE == ST_SPMV) {  // p0 = alpha, p1 = beta
+    y[row] = (p1 == T(0)) ? p0 * sum : p0 * sum + p1 * y[row];
+  } else if (MODE == ST_RESID) {
+    y[row] = b[row] - sum;
+  } else {  // ST_JACOBI, p0 = omega
+    y[row] = x[row] + p0 * dinv[row] * (b[row] - sum);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_jacobi0(int n, const T* __restrict__ dinv,
+                                                const T* __restrict__ b, T omega,
+                                                T* __restrict__ x) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) x[i] = omega * dinv[i] * b[i];
+}
+
+template <typename T, typename TV>
+__global__ __launch_bounds__(1024) void k_coarse_jacobi(int nrows, const int* __restrict__ col,
+                                                        const TV* __restrict__ val,
+                                                        const T* __restrict__ dinv,
+                                                        const T* __restrict__ b, T omega,
+                                                        int sweeps, T* __restrict__ x) {
+  __shared__ T xa[1024], xb[1024];
+  const int r = threadIdx.x;
+  T* cur = xa;
+  T* nxt = xb;
+  if (r < nrows) cur[r] = T(0);
+  __syncthreads();
+  int c[W7];
+  TV v[W7];
+  T d = T(0), br = T(0);
+  if (r < nrows) {
+    const size_t base = size_t(r >> 6) * (64 * W7) + (r & 63);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) {
+      c[k] = col[base + k * 64];
+      v[k] = val[base + k * 64];
+    }
+    d = dinv[r];
+    br = b[r];
+  }
+  for (int s = 0; s < sweeps; ++s) {
+    if (r < nrows) {
+      T sum = T(0);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) sum += T(v[k]) * cur[c[k]];
+      nxt[r] = cur[r] + omega * d * (br - sum);
+    }
+    __syncthreads();
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (r < nrows) x[r] = cur[r];
+}
+
+template <typename T, typename TV, bool L_IS_M>
+__global__ __launch_bounds__(BS) void k_ch_block(int n, const int* __restrict__ col,
+                                                 const TV* __restrict__ Lv,
+                                                 const TV* __restrict__ Kv,
+                                                 const TV* __restrict__ Mv, T c12, T c22,
+                                                 const T* __restrict__ x, T alpha, T beta,
+                                                 T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= n) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  const T* x1 = x;
+  const T* x2 = x + n;
+  int c[W7];
+  TV kv[W7], mv[W7], lv[W7];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    kv[k] = Kv[base + k * 64];
+    mv[k] = Mv[base + k * 64];
+    if (!L_IS_M) lv[k] = Lv[base + k * 64];
+  }
+  T sl = T(0), sk1 = T(0), sk2 = T(0), sm = T(0);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const T a = x1[c[k]], bb = x2[c[k]];
+    sl += T(L_IS_M ? mv[k] : lv[k]) * a;
+    sk1 += T(kv[k]) * a;
+    sk2 += T(kv[k]) * bb;
+    sm += T(mv[k]) * bb;
+  }
+  const T y1 = alpha * (sl + c12 * sk2);
+  const T y2 = alpha * (c12 * sk1 + c22 * sm);
+  if (beta == T(0)) {
+    y[row] = y1;
+    y[n + row] = y2;
+  } else {
+    y[row] = y1 + beta * y[row];
+    y[n + row] = y2 + beta * y[n + row];
+  }
+}
+
+// ------------------------------------------------------------------ vectors
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_axpby(int64_t n, T a, const T* __restrict__ x, T b,
+                                              T* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) y[i] = (b == T(0)) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(BS) void k_convert(int64_t n, const TI* __restrict__ x,
+                                                TO* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) y[i] = TO(x[i]);
+}
+
+__global__ __launch_bounds__(BS) void k_scale_by_inv(int64_t n, const double* __restrict__ x,
+                                                     const double* __restrict__ inv,
+                                                     double* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) y[i] = x[i] * inv[0];
+}
+
+// ------------------------------------------------------------------ Krylov reductions
+
+constexpr int MD_G = 8;  // basis vectors per multi-dot pass
+
+__global__ __launch_bounds__(BS) void k_mdot_partial(int64_t n, const double* __restrict__ V,
+                                                     int64_t ldv, int k,
+                                                     const double* __restrict__ w,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int g0 = blockIdx.y * MD_G;
+  const int kk = min(MD_G, k - g0);
+  double acc[MD_G];
+#pragma unroll
+  for (int i = 0; i < MD_G; ++i) acc[i] = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
+    const double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < MD_G; ++i)
+      if (i < kk) acc[i] += V[(g0 + i) * ldv + r] * wr;
+  }
+  for (int i = 0; i < kk; ++i) {
+    const double s = block_sum(acc[i], sh);
+    if (threadIdx.x == 0) part[int64_t(g0 + i) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_mdot_reduce(int nblk, int k, const double* __restrict__ part,
+                                                    double* __restrict__ h_tmp,
+                                                    double* __restrict__ h_col, int accumulate) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = wid; i < k; i += 4) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[int64_t(i) * nblk + b];
+    s = wave_sum(s);
+    if (lane == 0) {
+      h_tmp[i] = s;
+      h_col[i] = accumulate ? h_col[i] + s : s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_maxpy(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                              int k, const double* __restrict__ h,
+                                              double* __restrict__ w,
+                                              double* __restrict__ nrm_part) {
+  __shared__ double hs[257];
+  __shared__ double sh[4];
+  for (int i = threadIdx.x; i < k; i += BS) hs[i] = h[i];
+  __syncthreads();
+  double acc = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
+    double wr = w[r];
+    for (int i = 0; i < k; ++i) wr -= hs[i] * V[i * ldv + r];
+    w[r] = wr;
+    acc += wr * wr;
+  }
+  if (nrm_part) {
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) nrm_part[blockIdx.x] = s;
+  }
+}
+
+__device__ double sum_partials_wave(int nblk, const double* part) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += part[b];
+  return wave_sum(s);
+}
+
+// One wavefront.  H column-major with leading dimension m+1.
+__global__ void k_arnoldi_finish(int nblk, const double* __restrict__ nrm_part, int j, int m,
+                                 double* __restrict__ H, double* __restrict__ cs,
+                                 double* __restrict__ sn, double* __restrict__ g,
+                                 double* __restrict__ scal) {
+  const double nrm = sqrt(sum_partials_wave(nblk, nrm_part));
+  if (threadIdx.x != 0) return;
+  const int ld = m + 1;
+  double* h = H + int64_t(j) * ld;
+  h[j + 1] = nrm;
+  for (int i = 0; i < j; ++i) {
+    const double a = h[i], b = h[i + 1];
+    h[i] = cs[i] * a + sn[i] * b;
+    h[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = h[j], b = h[j + 1];
+  double c, s;
+  if (b == 0.0) {
+    c = 1.0;
+    s = 0.0;
+  } else if (fabs(b) > fabs(a)) {
+    const double t = a / b;
+    s = 1.0 / sqrt(1.0 + t * t);
+    c = t * s;
+  } else {
+    const double t = b / a;
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
+  }
+  cs[j] = c;
+  sn[j] = s;
+  h[j] = c * a + s * b;
+  h[j + 1] = 0.0;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  scal[0] = fabs(g[j + 1]);
+  scal[1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  scal[2] = nrm;
+}
+
+__global__ void k_lsq_solve(int k, int m, const double* __restrict__ H, const double* __restrict__ g,
+                            double* __restrict__ y) {
+  if (threadIdx.x != 0) return;
+  const int ld = m + 1;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int l = i + 1; l < k; ++l) s -= H[int64_t(l) * ld + i] * y[l];
+    y[i] = s / H[int64_t(i) * ld + i];
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_xupdate(int64_t n, const double* __restrict__ Z,
+                                                int64_t ldz, int k, const double* __restrict__ y,
+                                                double* __restrict__ x) {
+  __shared__ double ys[257];
+  for (int i = threadIdx.x; i < k; i += BS) ys[i] = y[i];
+  __syncthreads();
+  const int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (r >= n) return;
+  double s = x[r];
+  for (int i = 0; i < k; ++i) s += ys[i] * Z[i * ldz + r];
+  x[r] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_norm_partial(int64_t n, const double* __restrict__ w,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) acc += w[r] * w[r];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_norm_finish(int nblk, const double* __restrict__ part, double* __restrict__ scal,
+                              double* __restrict__ g, int m) {
+  const double nrm = sqrt(sum_partials_wave(nblk, part));
+  if (threadIdx.x == 0) {
+    scal[0] = nrm;
+    scal[1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    scal[2] = nrm;
+    if (g) {
+      g[0] = nrm;
+      for (int i = 1; i <= m; ++i) g[i] = 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ assembly
+
+// int psi_k lambda_a / |T| for the P2 basis psi_k (vertices, then edge nodes
+// opposite vertices 0, 1, 2) against the P1 basis lambda_a, from the monomial
+// integrals int l0^a l1^b l2^c = 2|T| a! b! c! / (a+b+c+2)!.
+__device__ __forceinline__ double w_p2p1(int k, int a) {
+  if (k < 3) return (k == a) ? (1.0 / 30.0) : (-1.0 / 60.0);
+  return ((k - 3) == a) ? (1.0 / 15.0) : (2.0 / 15.0);
+}
+
+__global__ __launch_bounds__(BS) void k_assemble_p1(int kind, int e0, int e1,
+                                                    const int* __restrict__ ep2,
+                                                    const int* __restrict__ etype,
+                                                    const int* __restrict__ eslot, double h,
+                                                    const double* __restrict__ vel, int64_t n2,
+                                                    double* __restrict__ val) {
+  const int e = e0 + blockIdx.x * BS + threadIdx.x;
+  if (e >= e1) return;
+  // local vertex coordinates relative to the first vertex
+  double x1, y1, x2, y2;
+  if (etype[e] == 0) {  // (i,j), (i+1,j), (i+1,j+1)
+    x1 = h; y1 = 0.0; x2 = h; y2 = h;
+  } else {              // (i,j), (i+1,j+1), (i,j+1)
+    x1 = h; y1 = h; x2 = 0.0; y2 = h;
+  }
+  const double det = x1 * y2 - x2 * y1;
+  const double area = 0.5 * fabs(det);
+  double gx[3], gy[3];
+  gx[1] = y2 / det;  gy[1] = -x2 / det;
+  gx[2] = -y1 / det; gy[2] = x1 / det;
+  gx[0] = -gx[1] - gx[2];
+  gy[0] = -gy[1] - gy[2];
+  double loc[9];
+  if (kind == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) loc[a * 3 + b] = area / 12.0 * (a == b ? 2.0 : 1.0);
+  } else if (kind == 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) loc[a * 3 + b] = area * (gx[a] * gx[b] + gy[a] * gy[b]);
+  } else {
+    double vx[6], vy[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int node = ep2[e * 6 + k];
+      vx[k] = vel[node];
+      vy[k] = vel[n2 + node];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double Va_x = 0.0, Va_y = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double wk = w_p2p1(k, a);
+        Va_x += wk * vx[k];
+        Va_y += wk * vy[k];
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b) loc[a * 3 + b] = area * (Va_x * gx[b] + Va_y * gy[b]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) val[eslot[e * 9 + q]] += loc[q];
+}
+
+__global__ __launch_bounds__(BS) void k_galerkin(int64_t nslots, const int* __restrict__ ptr,
+                                                 const int* __restrict__ src,
+                                                 const double* __restrict__ w,
+                                                 const double* __restrict__ fine,
+                                                 double* __restrict__ coarse) {
+  const int64_t s = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (s >= nslots) return;
+  double acc = 0.0;
+  for (int q = ptr[s]; q < ptr[s + 1]; ++q) acc += w[q] * fine[src[q]];
+  coarse[s] = acc;
+}
+
+__global__ __launch_bounds__(BS) void k_combine(int64_t n, double a, const double* __restrict__ A,
+                                                double b, const double* __restrict__ B, double c,
+                                                const double* __restrict__ C,
+                                                double* __restrict__ o64, float* __restrict__ o32) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i >= n) return;
+  double v = a * A[i];
+  if (B) v += b * B[i];
+  if (C) v += c * C[i];
+  o64[i] = v;
+  if (o32) o32[i] = float(v);
+}
+
+__global__ __launch_bounds__(BS) void k_diag_inverse(int n, const int* __restrict__ diag,
+                                                     const double* __restrict__ val,
+                                                     double* __restrict__ d64,
+                                                     float* __restrict__ d32) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const double d = 1.0 / val[diag[i]];
+  d64[i] = d;
+  if (d32) d32[i] = float(d);
+}
+
+// ------------------------------------------------------------------ right-hand sides
+
+__device__ __forceinline__ void binary_terms(double phi, const double* Phi, int j, double& fp,
+                                             double& fv) {
+  const double om = 1.0 - phi;
+  const double dliq = 2.0 * phi * om * om - 2.0 * phi * phi * om;
+  if (!Phi) {
+    fp = dliq;
+    fv = 0.0;
+    return;
+  }
+  const double P = Phi[j];
+  const double p = P * P * (3.0 - 2.0 * P);
+  const double dgas = 2.0 * phi - 2.0 * om;
+  fp = (1.0 - p) * dliq + p * dgas;
+  const double fliq = phi * phi * om * om, fgas = phi * phi + om * om;
+  fv = 6.0 * P * (1.0 - P) * (fgas - fliq);
+}
+
+__global__ __launch_bounds__(BS) void k_rhs_binary(int n, const int* __restrict__ col,
+                                                   const double* __restrict__ Mv,
+                                                   const double* __restrict__ phi,
+                                                   const double* __restrict__ Phi, double c_mu,
+                                                   double c_ac, double* __restrict__ rhs_ch,
+                                                   double* __restrict__ rhs_ac) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= n) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  double s_phi = 0.0, s_fp = 0.0, s_Phi = 0.0, s_fv = 0.0;
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const int j = col[base + k * 64];
+    const double m = Mv[base + k * 64];
+    const double ph = phi[j];
+    double fp, fv;
+    binary_terms(ph, Phi, j, fp, fv);
+    s_phi += m * ph;
+    s_fp += m * fp;
+    if (Phi) {
+      s_Phi += m * Phi[j];
+      s_fv += m * fv;
+    }
+  }
+  rhs_ch[row] = s_phi;
+  rhs_ch[n + row] = c_mu * s_fp;
+  if (rhs_ac) rhs_ac[row] = s_Phi + c_ac * s_fv;
+}
+
+}  // namespace
+
+// ================================================================== launchers
+
+template <typename T, typename TV>
+void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s) {
+  if (A.uniform && A.width == W7) {
+    hipLaunchKernelGGL((k_stencil7<T, TV, ST_SPMV>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
+                       A.nrows, A.col, val, x, (const T*)nullptr, (const T*)nullptr, alpha, beta, y);
+  } else {
+    const int npos = A.nslices * 64;
+    hipLaunchKernelGGL((k_spmv_sell<T, TV>), dim3(ceil_div(npos, BS)), dim3(BS), 0, s, A.nslices,
+                       A.nrows, A.slice_ptr, A.slice_w, A.col, val, A.uniform ? nullptr : A.perm, x,
+                       y, alpha, beta);
+  }
+}
+
+template <typename T, typename TV>
+void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv,
+             T omega, T* y, hipStream_t s) {
+  const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
+  if (mode == ST_RESID)
+    hipLaunchKernelGGL((k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.col, val, x, b,
+                       dinv, omega, T(0), y);
+  else
+    hipLaunchKernelGGL((k_stencil7<T, TV, ST_JACOBI>), g, blk, 0, s, A.nrows, A.col, val, x, b,
+                       dinv, omega, T(0), y);
+}
+
+template <typename T>
+void jacobi0(int n, const T* dinv, const T* b, T omega, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_jacobi0<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, dinv, b, omega, x);
+}
+
+template <typename T, typename TV>
+void coarse_jacobi(const DSell& A, const TV* val, const T* dinv, const T* b, T omega, int sweeps,
+                   T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_coarse_jacobi<T, TV>), dim3(1), dim3(1024), 0, s, A.nrows, A.col, val,
+                     dinv, b, omega, sweeps, x);
+}
+
+template <typename T, typename TV>
+void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
+              T alpha, T beta, T* y, hipStream_t s) {
+  const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
+  if (L == M)
+    hipLaunchKernelGGL((k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.col, L, K, M, c12, c22,
+                       x, alpha, beta, y);
+  else
+    hipLaunchKernelGGL((k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.col, L, K, M, c12, c22,
+                       x, alpha, beta, y);
+}
+
+template <typename T>
+void axpby(int64_t n, T a, const T* x, T b, T* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpby<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, a, x, b, y);
+}
+
+template <typename TI, typename TO>
+void convert(int64_t n, const TI* x, TO* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<TI, TO>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, y);
+}
+
+void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by_inv, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y);
+}
+
+int reduce_blocks(int64_t n) {
+  const int64_t b = (n + 4 * BS - 1) / (4 * BS);
+  return int(b < 1 ? 1 : (b > MAXRED ? MAXRED : b));
+}
+
+void mdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
+                  hipStream_t s) {
+  const int nblk = reduce_blocks(n);
+  hipLaunchKernelGGL(k_mdot_partial, dim3(nblk, ceil_div(k, MD_G)), dim3(BS), 0, s, n, V, ldv, k,
+                     w, part);
+}
+
+void mdot_reduce(int nblk, int k, const double* part, double* h_tmp, double* h_col, int accumulate,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(BS), 0, s, nblk, k, part, h_tmp, h_col,
+                     accumulate);
+}
+
+void maxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
+           double* nrm_part, hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpy, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ldv, k, h, w, nrm_part);
+}
+
+void arnoldi_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* cs,
+                    double* sn, double* g, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, s, nblk, nrm_part, j, m, H, cs, sn, g,
+                     scal);
+}
+
+void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(64), 0, s, k, m, H, g, y);
+}
+
+void xupdate(int64_t n, const double* Z, int64_t ldz, int k, const double* y, double* x,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_xupdate, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, Z, ldz, k, y, x);
+}
+
+void norm_partial(int64_t n, const double* w, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_partial, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, w, part);
+}
+
+void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, nblk, part, scal, g, m);
+}
+
+void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, const int* eslot,
+                 double h, const double* vel, int64_t n2, double* val, hipStream_t s) {
+  if (e1 <= e0) return;
+  hipLaunchKernelGGL(k_assemble_p1, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, kind, e0, e1, ep2,
+                     etype, eslot, h, vel, n2, val);
+}
+
+void galerkin(int64_t nslots, const int* ptr, const int* src, const double* w, const double* fine,
+              double* coarse, hipStream_t s) {
+  hipLaunchKernelGGL(k_galerkin, dim3(ceil_div(nslots, BS)), dim3(BS), 0, s, nslots, ptr, src, w,
+                     fine, coarse);
+}
+
+void combine(int64_t nslots, double a, const double* A, double b, const double* B, double c,
+             const double* C, double* out64, float* out32, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(ceil_div(nslots, BS)), dim3(BS), 0, s, nslots, a, A, b, B, c,
+                     C, out64, out32);
+}
+
+void diag_inverse(int nrows, const int* diag, const double* val, double* d64, float* d32,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_inverse, dim3(ceil_div(nrows, BS)), dim3(BS), 0, s, nrows, diag, val,
+                     d64, d32);
+}
+
+void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,
+                double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col, Mv,
+                     phi, Phi, c_mu, c_ac, rhs_ch, rhs_ac);
+}
+
+// explicit instantiations
+template void spmv<double, double>(const DSell&, const double*, const double*, double*, double,
+                                   double, hipStream_t);
+template void spmv<float, float>(const DSell&, const float*, const float*, float*, float, float,
+                                 hipStream_t);
+template void stencil<double, double>(const DSell&, const double*, int, const double*,
+                                      const double*, const double*, double, double*, hipStream_t);
+template void stencil<float, float>(const DSell&, const float*, int, const float*, const float*,
+                                    const float*, float, float*, hipStream_t);
+template void jacobi0<double>(int, const double*, const double*, double, double*, hipStream_t);
+template void jacobi0<float>(int, const float*, const float*, float, float*, hipStream_t);
+template void coarse_jacobi<double, double>(const DSell&, const double*, const double*,
+                                            const double*, double, int, double*, hipStream_t);
+template void coarse_jacobi<float, float>(const DSell&, const float*, const float*, const float*,
+                                          float, int, float*, hipStream_t);
+template void ch_block<double, double>(const DSell&, const double*, const double*, const double*,
+                                       double, double, const double*, double, double, double*,
+                                       hipStream_t);
+template void ch_block<float, float>(const DSell&, const float*, const float*, const float*, float,
+                                     float, const float*, float, float, float*, hipStream_t);
+template void axpby<double>(int64_t, double, const double*, double, double*, hipStream_t);
+template void axpby<float>(int64_t, float, const float*, float, float*, hipStream_t);
+template void convert<double, float>(int64_t, const double*, float*, hipStream_t);
+template void convert<float, double>(int64_t, const float*, double*, hipStream_t);
+
+}  // namespace chns

@@ -1,0 +1,99 @@
+// Launchers of the gfx950 kernels (definitions in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace chns {
+
+// Device view of a SELL-C-sigma pattern with C = 64 (one wavefront per slice).
+struct DSell {
+  int nrows = 0, nslices = 0, width = 0;  // width: slice width when uniform
+  int uniform = 0;                        // all slices width `width`, identity permutation
+  const int* slice_ptr = nullptr;
+  const int* slice_w = nullptr;
+  const int* col = nullptr;
+  const int* perm = nullptr;              // lane position -> row (-1 padding)
+};
+
+// Operator modes of the fused stencil kernel (uniform width-7 P1 patterns).
+enum StencilMode { ST_SPMV = 0, ST_RESID = 1, ST_JACOBI = 2 };
+
+// y = alpha A x + beta y on any SELL pattern (beta == 0: y not read).
+template <typename T, typename TV>
+void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s);
+
+// Uniform P1 operators: mode ST_RESID: y = b - A x;  ST_JACOBI: y = x + omega dinv (b - A x).
+template <typename T, typename TV>
+void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv,
+             T omega, T* y, hipStream_t s);
+
+// x = omega dinv b (first Jacobi sweep from zero).
+template <typename T>
+void jacobi0(int n, const T* dinv, const T* b, T omega, T* x, hipStream_t s);
+
+// Coarsest level: `sweeps` damped-Jacobi sweeps from x = 0 in one workgroup
+// (nrows <= 1024, uniform width-7 pattern).
+template <typename T, typename TV>
+void coarse_jacobi(const DSell& A, const TV* val, const T* dinv, const T* b, T omega, int sweeps,
+                   T* x, hipStream_t s);
+
+// CH block on [x1; x2] with value streams L = M + tau C, K, M (uniform P1):
+//   y1 = alpha (L x1 + c12 K x2) + beta y1,  y2 = alpha (c12 K x1 + c22 M x2) + beta y2.
+template <typename T, typename TV>
+void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
+              T alpha, T beta, T* y, hipStream_t s);
+
+// Vector kernels.
+template <typename T>
+void axpby(int64_t n, T a, const T* x, T b, T* y, hipStream_t s);
+template <typename TI, typename TO>
+void convert(int64_t n, const TI* x, TO* y, hipStream_t s);
+void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipStream_t s);
+
+// Krylov reductions (FP64).  Partial sums per workgroup go to `part`
+// (reduce_blocks(n) * cols doubles); reduce_* finish them deterministically.
+int reduce_blocks(int64_t n);
+void mdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
+                  hipStream_t s);
+// h_out[i] (+)= sum of partials; also writes h_tmp for the following maxpy.
+void mdot_reduce(int nblk, int k, const double* part, double* h_tmp, double* h_col, int accumulate,
+                 hipStream_t s);
+// w -= V h (k columns); with nrm_part != nullptr also partial sums of w^2.
+void maxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
+           double* nrm_part, hipStream_t s);
+// Norm of w from partials, Givens update of Hessenberg column j, residual
+// estimate, 1/h_{j+1,j}.  H is (m+1) x m column-major with leading dim m+1.
+void arnoldi_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* cs,
+                    double* sn, double* g, double* scal, hipStream_t s);
+// Least squares back-substitution for k columns: y = R^{-1} g.
+void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
+// x += Z y (k columns).
+void xupdate(int64_t n, const double* Z, int64_t ldz, int k, const double* y, double* x,
+             hipStream_t s);
+// ||w||: partials then scal[0] = norm, scal[1] = 1/norm (0 if norm == 0), g = [norm, 0...].
+void norm_partial(int64_t n, const double* w, double* part, hipStream_t s);
+void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s);
+
+// Assembly: coloured element scatter into a SELL value array.  kind 0: P1
+// mass, 1: P1 stiffness, 2: P1 convection by a P2 velocity vel (2 x n2 nodes).
+void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, const int* eslot,
+                 double h, const double* vel, int64_t n2, double* val, hipStream_t s);
+
+// coarse[s] = sum_k w_k fine[src_k] over the Galerkin map.
+void galerkin(int64_t nslots, const int* ptr, const int* src, const double* w, const double* fine,
+              double* coarse, hipStream_t s);
+// out = a A + b B + c C (C may be null) with FP32 copy; dinv from diagonal slots.
+void combine(int64_t nslots, double a, const double* A, double b, const double* B, double c,
+             const double* C, double* out64, float* out32, hipStream_t s);
+void diag_inverse(int nrows, const int* diag, const double* val, double* d64, float* d32,
+                  hipStream_t s);
+
+// Right-hand sides of the binary models (uniform P1 pattern of M):
+// rhs_ch = [M phi; -(tau g/beta) M f'(phi, Phi)], rhs_ac = M Phi - tau g_v M f_v(phi, Phi).
+// Phi == nullptr selects the pure double-well (no vapour field).
+void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
+                double c_mu, double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s);
+
+}  // namespace chns

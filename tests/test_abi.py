@@ -1,0 +1,61 @@
+"""The C-ABI library loads, exports every entry point the header declares,
+and rejects invalid arguments before touching the device (CPU only)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2501_11767_amd import chns
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "chns.h")).read()
+    return sorted(set(re.findall(r"CHNS_API\s+[\w\s\*]+?\b(chns_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(chns.LIBPATH):
+        pytest.skip("library not built")
+    return chns.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(chns.EXPORTS)
+
+
+def test_default_opts(L):
+    o = chns.default_opts()
+    assert o.rtol == 1e-8 and o.restart == 30 and o.precision == chns.F64
+    assert o.mg_pre == 2 and o.mg_post == 2 and abs(o.mg_omega - 2 / 3) < 1e-15
+
+
+@pytest.mark.parametrize("n,model", [(7, 0), (6, 0), (0, 1), (10000, 1), (16, 9)])
+def test_create_rejects_bad_mesh(L, n, model):
+    h = ct.c_void_p()
+    rc = L.chns_create(ct.byref(chns.Mesh(n, model)), ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)),
+                       ct.byref(h))
+    assert rc == chns.EINVAL and not h.value
+    assert len(L.chns_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("bad", [dict(eps=float("nan")), dict(tau=-1.0), dict(mobility=0.0),
+                                 dict(rho=float("inf")), dict(viscosity=0.0)])
+def test_create_rejects_bad_params(L, bad):
+    p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.1, viscosity=1.0, alpha=1e-8, rho=1.0)
+    p.update(bad)
+    h = ct.c_void_p()
+    rc = L.chns_create(ct.byref(chns.Mesh(16, chns.MODEL_CH_AC)), ct.byref(chns.Params(**p)), ct.byref(h))
+    assert rc == chns.EINVAL and not h.value
+
+
+def test_null_context_is_rejected(L):
+    assert L.chns_destroy(None) == chns.EINVAL
+    assert L.chns_spmv(None, 0, 0, 1.0, None, 0.0, None, None) == chns.EINVAL
