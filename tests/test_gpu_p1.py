@@ -139,7 +139,7 @@ def test_precond_matches_oracle_vcycle(chns, n, conv):
     M, K = fem.p1_mass(m), fem.p1_stiffness(m)
     C = None
     if conv:
-        vel = inputs.stream_velocity(n, 3, amp=0.3)
+        vel = inputs.stream_velocity(n, 3, amp=0.05)
         ctx.assemble(_t(vel.ravel()))
         C = fem.p1_convection(m, vel)
     g = np.random.default_rng(1)
@@ -175,7 +175,7 @@ def test_krylov_solve_reaches_direct_solution(chns, precision):
     ctx = chns.Context(n, "ch_ac", **PRM)
     ops = S.Operators(n)
     prm = _oracle_prm(PRM)
-    vel = inputs.stream_velocity(n, 8, amp=0.2)
+    vel = inputs.stream_velocity(n, 8, amp=0.02)
     f = inputs.initial_state(n, "ch_ac", 0.4, 12)
     f["vel"] = vel
     st = S.initial_state(ops, prm, "ch_ac", f)
