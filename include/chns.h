@@ -103,14 +103,15 @@ typedef struct {
 
 typedef struct {
   double rtol, atol;    /* stop when ||b - A x||_2 <= max(rtol ||b||_2, atol) */
-  int32_t restart;      /* FGMRES restart length m (1..256) */
+  int32_t restart;      /* FGMRES restart length m (1..64) */
   int32_t maxiter;      /* total Arnoldi steps allowed */
   int32_t precision;    /* CHNS_F64 or CHNS_MIXED */
   int32_t mg_cycles;    /* V-cycles per inner solve (>= 1) */
-  int32_t mg_pre;       /* damped-Jacobi pre-smoothing sweeps (>= 1) */
-  int32_t mg_post;      /* post-smoothing sweeps (>= 0) */
-  int32_t mg_coarse;    /* sweeps on the coarsest level (>= 1) */
-  double mg_omega;      /* Jacobi damping, 0 < omega <= 1 */
+  int32_t mg_pre;       /* Chebyshev pre-smoothing steps (>= 1) */
+  int32_t mg_post;      /* Chebyshev post-smoothing steps (>= 0) */
+  int32_t mg_coarse;    /* Chebyshev steps on a coarse cut level (>= 1) */
+  double mg_lmax;       /* upper bound of the spectrum of D^{-1}A (smoothing on [lmax/4, lmax]) */
+  double mg_rho_cut;    /* cut the hierarchy at the first level with 8 b n_l^2 / a <= rho_cut */
 } chns_solve_opts;
 
 typedef struct {
@@ -136,8 +137,15 @@ typedef struct {
   double* p;
 } chns_fields;
 
-/* Defaults: rtol 1e-8, atol 0, restart 30, maxiter 600, F64, 1 V(2,2) cycle,
- * 16 coarse sweeps, omega 2/3. */
+/* Defaults: rtol 1e-8, atol 0, restart 40, maxiter 600, F64, 1 V(2,2) cycle,
+ * 8 coarse steps, lmax 2.1, rho_cut 0.25.
+ *
+ * The inner cycle for an operator A = a M + b K (+ c C): Galerkin levels
+ * n, n/2, ... (nested P1 interpolation) down to the first level where
+ * 8 b n_l^2 / a <= rho_cut or the last level (size >= 4); Chebyshev smoothing
+ * of D^{-1}A on [lmax/4, lmax]; on the cut level Chebyshev steps on
+ * [0.45 / (1 + 8 b n_l^2 / a), lmax] (mg_coarse of them on a coarse level,
+ * mg_pre + mg_post when the operator is cut on the finest level). */
 CHNS_API void chns_default_opts(chns_solve_opts* opts);
 
 /* Build the mesh tables, sparsity patterns (CSR -> SELL-C-sigma), multigrid
@@ -186,7 +194,8 @@ CHNS_API int chns_precond_apply(chns_ctx* ctx, int32_t block, const chns_solve_o
                                 const double* d_r, double* d_z, void* stream);
 
 /* Solve block * x = b by right-preconditioned restarted FGMRES (classical
- * Gram-Schmidt twice, Givens least squares on the device), stopping rule
+ * Gram-Schmidt with a second pass only when the first loses more than half
+ * of the vector's norm squared, Givens least squares on the device), stopping rule
  * ||b - A x|| <= max(rtol ||b||, atol) on the recomputed true residual.
  * d_x holds the initial guess and receives the solution.  Synchronising
  * (reads the residual estimate back once per Arnoldi step).  h_info may be NULL. */

@@ -1,29 +1,47 @@
-"""Geometric multigrid V-cycle on the nested periodic P1 meshes (FP64).
+"""Geometric multigrid on the nested periodic P1 meshes (FP64).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper approximates the inverse of each diagonal block (M + tau C, the
-matching factor tau g K + sqrt(tau g / beta) M, the Allen-Cahn matrix, the
-velocity block, the pressure stiffness) by a multigrid cycle (section
-"Iterative solvers and preconditioning"; the numerical-results section names
-algebraic variants).  The GPU path uses one geometric family on the nested
-right-diagonal meshes; this module writes that cycle out plainly so the GPU
-cycle can be checked operation by operation:
+matching factor tau g K + sqrt(tau g / beta) M, the Allen-Cahn matrix, ...)
+by a multigrid cycle (section "Iterative solvers and preconditioning"; the
+numerical-results section names algebraic variants).  The GPU path uses one
+geometric family on the nested right-diagonal meshes; this module writes that
+cycle out plainly so the GPU cycle can be checked operation by operation.
+
+Definition of the cycle for an operator A = a M + b K (+ c C):
 
 * levels n, n/2, ... while the size is even and the next size is >= 4;
-* prolongation P = P1 interpolation from the mesh of size n/2 to size n
-  (coarse vertex (I, J) sits at fine vertex (2I, 2J); fine edge midpoints take
-  the mean of the two coarse edge ends; the diagonal edge joins (I, J) and
-  (I+1, J+1));
-* restriction R = P^T, Galerkin coarse operators A_c = P^T A P;
-* smoother: damped Jacobi x <- x + omega D^{-1} (b - A x);
-* V(pre, post) cycle from a zero initial guess; the coarsest level applies
-  ``coarse`` damped-Jacobi sweeps.
+* prolongation P = P1 interpolation from size n/2 to n (coarse vertex (I, J)
+  sits at fine vertex (2I, 2J); fine edge midpoints take the mean of the two
+  coarse edge ends; the diagonal edge joins (I, J) and (I+1, J+1));
+  restriction R = P^T; Galerkin coarse operators A_c = P^T A P;
+* level cut: with rho_l = 8 b n_l^2 / a (the ratio of the K and M parts of
+  the diagonal, 8 b / (a h^2)), the cycle stops at the first level with
+  rho_l <= rho_cut (that operator is mass-dominated and well conditioned) or
+  at the last level; a mass-dominated operator (L = M + tau C) is therefore
+  handled on the fine level alone;
+* smoother: Chebyshev iteration for D^{-1} A on [lmax/4, lmax] (pre and post);
+  on the cut level, Chebyshev steps on [0.9 * 0.5 / (1 + rho), lmax], since the
+  eigenvalues of D^{-1}(a M + b K) lie in [0.5 / (1 + rho), 2]: ``coarse``
+  steps when the cut level is a coarse level, pre + post steps when the
+  operator is cut on the fine level (no coarse levels at all);
+* V(pre, post) cycle from a zero initial guess.
+
+Chebyshev iteration (first kind) on [lo, hi] with theta = (hi + lo) / 2,
+delta = (hi - lo) / 2, sigma = theta / delta:
+  r_0 = D^{-1}(b - A x_0), d_0 = r_0 / theta, x_1 = x_0 + d_0, rho_0 = 1 / sigma;
+  for i >= 1: rho_i = 1 / (2 sigma - rho_{i-1}),
+              d_i = rho_i rho_{i-1} d_{i-1} + (2 rho_i / delta) D^{-1}(b - A x_i),
+              x_{i+1} = x_i + d_i.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+
+LMAX = 2.1
+RHO_CUT = 0.25
 
 
 def prolongation(nf: int):
@@ -50,9 +68,26 @@ def level_sizes(n: int, nmin: int = 4):
     return out
 
 
+def rho(a, b, nl):
+    return 8.0 * b * nl * nl / a
+
+
+def cut_level(sizes, a, b, rho_cut=RHO_CUT):
+    for l, nl in enumerate(sizes):
+        if rho(a, b, nl) <= rho_cut:
+            return l
+    return len(sizes) - 1
+
+
 class Hierarchy:
-    def __init__(self, A, n: int, nmin: int = 4):
-        self.sizes = level_sizes(n, nmin)
+    """Galerkin hierarchy of A = a M + b K (+ c C) down to its cut level."""
+
+    def __init__(self, A, n: int, a: float = 1.0, b: float = 0.0, nmin: int = 4,
+                 rho_cut: float = RHO_CUT):
+        sizes = level_sizes(n, nmin)
+        self.cut = cut_level(sizes, a, b, rho_cut)
+        self.sizes = sizes[: self.cut + 1]
+        self.rho_last = rho(a, b, self.sizes[-1])
         self.A = [sp.csr_matrix(A)]
         self.P = []
         for nf in self.sizes[:-1]:
@@ -62,20 +97,33 @@ class Hierarchy:
         self.Dinv = [1.0 / Al.diagonal() for Al in self.A]
 
 
-def vcycle(H: Hierarchy, b, pre=2, post=2, coarse=16, omega=2.0 / 3.0, level=0):
+def chebyshev(A, Dinv, b, x, lo, hi, steps):
+    """``steps`` Chebyshev steps for D^{-1} A on [lo, hi] starting from x."""
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho_prev = 1.0 / sigma
+    d = Dinv * (b - A @ x) / theta
+    x = x + d
+    for _ in range(1, steps):
+        rho_i = 1.0 / (2.0 * sigma - rho_prev)
+        d = rho_i * rho_prev * d + (2.0 * rho_i / delta) * (Dinv * (b - A @ x))
+        x = x + d
+        rho_prev = rho_i
+    return x
+
+
+def vcycle(H: Hierarchy, b, pre=2, post=2, coarse=8, lmax=LMAX, level=0):
     A, Dinv = H.A[level], H.Dinv[level]
     x = np.zeros_like(b)
     if level == len(H.A) - 1:
-        for _ in range(coarse):
-            x = x + omega * Dinv * (b - A @ x)
-        return x
-    for _ in range(pre):
-        x = x + omega * Dinv * (b - A @ x)
+        lo = 0.9 * 0.5 / (1.0 + H.rho_last)
+        return chebyshev(A, Dinv, b, x, lo, lmax, coarse if level > 0 else pre + post)
+    x = chebyshev(A, Dinv, b, x, lmax / 4.0, lmax, pre)
     r = b - A @ x
     P = H.P[level]
-    x = x + P @ vcycle(H, P.T @ r, pre, post, coarse, omega, level + 1)
-    for _ in range(post):
-        x = x + omega * Dinv * (b - A @ x)
+    x = x + P @ vcycle(H, P.T @ r, pre, post, coarse, lmax, level + 1)
+    if post > 0:
+        x = chebyshev(A, Dinv, b, x, lmax / 4.0, lmax, post)
     return x
 
 

@@ -17,7 +17,9 @@ Navier-Stokes: diag(A^, S^) with the pressure convection-diffusion
   approximation S^{-1} = M_p^{-1} A_p K_p^{-1} (section "Iterative solvers and
   preconditioning", last display).
 
-Inner solves are ``exact`` (SuperLU) or ``mg`` (the V-cycle of ``multigrid``).
+Inner solves are ``exact`` (SuperLU) or ``mg`` (the cycle of ``multigrid``;
+each operator a M + b K (+ c C) passes its coefficients so that the cycle is
+cut at the level where it is mass-dominated).
 """
 from __future__ import annotations
 
@@ -52,8 +54,9 @@ class CHPreconditioner:
         self.X = matching_factor(M, K, prm)
         self.inner, self.mgkw, self.N = inner, mgkw, M.shape[0]
         if inner == "mg":
-            self.HL = mg.Hierarchy(self.L, n)
-            self.HX = mg.Hierarchy(self.X, n)
+            t, g, b = prm.tau, prm.gamma, prm.beta
+            self.HL = mg.Hierarchy(self.L, n, a=1.0, b=0.0)
+            self.HX = mg.Hierarchy(self.X, n, a=np.sqrt(t * g / b), b=t * g)
 
     def _inv(self, which, r):
         if self.inner == "exact":
@@ -69,10 +72,10 @@ class CHPreconditioner:
 
 
 class ACPreconditioner:
-    def __init__(self, A, n, inner="exact", **mgkw):
+    def __init__(self, A, n, prm, inner="exact", **mgkw):
         self.A, self.inner, self.mgkw = A.tocsr(), inner, mgkw
         if inner == "mg":
-            self.H = mg.Hierarchy(self.A, n)
+            self.H = mg.Hierarchy(self.A, n, a=1.0, b=prm.tau * prm.delta_v)
 
     def apply(self, r):
         if self.inner == "exact":

@@ -40,7 +40,7 @@ class SolveOpts(ct.Structure):
     _fields_ = [("rtol", ct.c_double), ("atol", ct.c_double), ("restart", ct.c_int32),
                 ("maxiter", ct.c_int32), ("precision", ct.c_int32), ("mg_cycles", ct.c_int32),
                 ("mg_pre", ct.c_int32), ("mg_post", ct.c_int32), ("mg_coarse", ct.c_int32),
-                ("mg_omega", ct.c_double)]
+                ("mg_lmax", ct.c_double), ("mg_rho_cut", ct.c_double)]
 
 
 class SolveInfo(ct.Structure):

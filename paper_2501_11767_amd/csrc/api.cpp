@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -99,9 +100,10 @@ int check_opts(chns_ctx* c, const chns_solve_opts* o) {
   if (o->precision != CHNS_F64 && o->precision != CHNS_MIXED)
     return fail(c, CHNS_EINVAL, "unknown precision");
   if (o->mg_cycles < 1 || o->mg_pre < 1 || o->mg_post < 0 || o->mg_coarse < 1 || o->mg_cycles > 64 ||
-      o->mg_pre > 64 || o->mg_post > 64 || o->mg_coarse > 4096)
-    return fail(c, CHNS_EINVAL, "multigrid sweep counts out of range");
-  if (!(o->mg_omega > 0.0 && o->mg_omega <= 1.0)) return fail(c, CHNS_EINVAL, "mg_omega must be in (0, 1]");
+      o->mg_pre > 32 || o->mg_post > 32 || o->mg_coarse > MAXCHEB)
+    return fail(c, CHNS_EINVAL, "multigrid step counts out of range (pre 1..32, post 0..32, coarse 1..64)");
+  if (!(o->mg_lmax > 0.0 && o->mg_lmax < 100.0)) return fail(c, CHNS_EINVAL, "mg_lmax must be in (0, 100)");
+  if (!(o->mg_rho_cut >= 0.0 && is_finite(o->mg_rho_cut))) return fail(c, CHNS_EINVAL, "mg_rho_cut must be >= 0");
   return CHNS_OK;
 }
 
@@ -114,6 +116,12 @@ int form_operators(chns_ctx* c, hipStream_t s) {
   const double beta = p.eps * p.eps, tg = p.tau * p.mobility;
   const double smatch = std::sqrt(tg / beta);
   const double delta_v = p.evap_rate * p.eps * p.eps;
+  c->coefL[0] = 1.0;
+  c->coefL[1] = 0.0;
+  c->coefX[0] = smatch;
+  c->coefX[1] = tg;
+  c->coefAC[0] = 1.0;
+  c->coefAC[1] = p.tau * delta_v;
   for (auto& L : c->lv) {
     const int64_t ns = L.sell.slots();
     const double* C = c->has_conv ? L.C : nullptr;
@@ -160,6 +168,7 @@ template <> struct Sel<double> {
   static double* t(Level& L) { return L.t64; }
   static double* r(Level& L) { return L.r64; }
   static double* e(Level& L) { return L.e64; }
+  static double* dd(Level& L) { return L.d64; }
   static const double* P(Level& L) { return L.P64; }
   static const double* R(Level& L) { return L.R64; }
   static const double* M(Level& L) { return L.M; }
@@ -172,51 +181,106 @@ template <> struct Sel<float> {
   static float* t(Level& L) { return L.t32; }
   static float* r(Level& L) { return L.r32; }
   static float* e(Level& L) { return L.e32; }
+  static float* dd(Level& L) { return L.d32; }
   static const float* P(Level& L) { return L.P32; }
   static const float* R(Level& L) { return L.R32; }
   static const float* M(Level& L) { return L.M32; }
 };
 
-// One V(pre, post) cycle from x = 0 on level l: x = V b.  `x` and `b` may be
-// external buffers on level 0; the level's t and r vectors are scratch.
+// Chebyshev coefficients for `steps` steps on [lo, hi] (first kind):
+// d_0 = r_0 / theta; d_i = rho_i rho_{i-1} d_{i-1} + (2 rho_i / delta) r_i.
 template <typename T>
-void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, const T* b, T* x, const chns_solve_opts& o,
-            hipStream_t s) {
-  Level& L = c->lv[l];
-  const OpVals& A = L.*op;
-  const T w = T(o.mg_omega);
-  const bool last = (l + 1 == c->lv.size());
-  if (last) {
-    if (L.N <= 1024) {
-      coarse_jacobi<T, T>(L.d, Sel<T>::v(A), Sel<T>::d(A), b, w, o.mg_coarse, x, s);
-    } else {
-      T* cur = (o.mg_coarse % 2 == 1) ? x : Sel<T>::t(L);
-      T* oth = (cur == x) ? Sel<T>::t(L) : x;
-      jacobi0<T>(L.N, Sel<T>::d(A), b, w, cur, s);
-      for (int k = 1; k < o.mg_coarse; ++k) {
-        stencil<T, T>(L.d, Sel<T>::v(A), ST_JACOBI, cur, b, Sel<T>::d(A), w, oth, s);
-        std::swap(cur, oth);
-      }
-    }
+ChebCoef<T> cheb_coef(double lo, double hi, int steps) {
+  ChebCoef<T> cc{};
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho_prev = 1.0 / sigma;
+  cc.steps = steps;
+  cc.c1[0] = T(0);
+  cc.c2[0] = T(1.0 / theta);
+  for (int i = 1; i < steps; ++i) {
+    const double rho_i = 1.0 / (2.0 * sigma - rho_prev);
+    cc.c1[i] = T(rho_i * rho_prev);
+    cc.c2[i] = T(2.0 * rho_i / delta);
+    rho_prev = rho_i;
+  }
+  return cc;
+}
+
+// Level where the cycle of a M + b K stops: first l with 8 b n_l^2 / a <= rho_cut.
+size_t cut_level(chns_ctx* c, const double* coef, double rho_cut) {
+  for (size_t l = 0; l < c->lv.size(); ++l) {
+    const double nl = c->lv[l].n;
+    if (8.0 * coef[1] * nl * nl / coef[0] <= rho_cut) return l;
+  }
+  return c->lv.size() - 1;
+}
+
+const double* coef_of(chns_ctx* c, OpVals Level::*op) {
+  if (op == &Level::L) return c->coefL;
+  if (op == &Level::X) return c->coefX;
+  return c->coefAC;
+}
+
+// Chebyshev steps from x = 0 (cur/oth ping-pong so that the result lands in x).
+template <typename T>
+void cheb_from_zero(Level& L, const OpVals& A, const T* b, T* x, const ChebCoef<T>& cc,
+                    hipStream_t s) {
+  if (L.N <= 1024) {
+    coarse_cheb<T, T>(L.d, Sel<T>::v(A), Sel<T>::d(A), b, cc, x, s);
     return;
   }
-  const int swaps = (o.mg_pre - 1) + o.mg_post;
-  T* cur = (swaps % 2 == 0) ? x : Sel<T>::t(L);
+  T* cur = ((cc.steps - 1) % 2 == 0) ? x : Sel<T>::t(L);
   T* oth = (cur == x) ? Sel<T>::t(L) : x;
-  jacobi0<T>(L.N, Sel<T>::d(A), b, w, cur, s);
+  T* d = Sel<T>::dd(L);
+  cheb0<T>(L.N, Sel<T>::d(A), b, cc.c2[0], d, cur, s);
+  for (int k = 1; k < cc.steps; ++k) {
+    stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, cur, b, Sel<T>::d(A), d, cc.c1[k], cc.c2[k], oth, s);
+    std::swap(cur, oth);
+  }
+}
+
+// One V(pre, post) cycle from x = 0 on level l (down to the cut level):
+// x = V b.  `x` and `b` may be external buffers on level 0; the level's t, r
+// and d vectors are scratch.
+template <typename T>
+void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T* x,
+            const chns_solve_opts& o, hipStream_t s) {
+  Level& L = c->lv[l];
+  const OpVals& A = L.*op;
+  const double lmax = o.mg_lmax;
+  if (l == cut) {
+    const double* cf = coef_of(c, op);
+    const double nl = L.n;
+    const double rho = 8.0 * cf[1] * nl * nl / cf[0];
+    const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
+    cheb_from_zero<T>(L, A, b, x, cheb_coef<T>(0.45 / (1.0 + rho), lmax, std::min(steps, MAXCHEB)), s);
+    return;
+  }
+  const ChebCoef<T> pre = cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre);
+  const int swaps_post = o.mg_post;
+  // pre-smoothing from zero: result must end in `cur`, then the post steps
+  // alternate; choose the start buffer so that the final iterate is `x`.
+  T* cur = ((o.mg_pre - 1 + swaps_post) % 2 == 0) ? x : Sel<T>::t(L);
+  T* oth = (cur == x) ? Sel<T>::t(L) : x;
+  T* d = Sel<T>::dd(L);
+  cheb0<T>(L.N, Sel<T>::d(A), b, pre.c2[0], d, cur, s);
   for (int k = 1; k < o.mg_pre; ++k) {
-    stencil<T, T>(L.d, Sel<T>::v(A), ST_JACOBI, cur, b, Sel<T>::d(A), w, oth, s);
+    stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, cur, b, Sel<T>::d(A), d, pre.c1[k], pre.c2[k], oth, s);
     std::swap(cur, oth);
   }
   T* r = Sel<T>::r(L);
-  stencil<T, T>(L.d, Sel<T>::v(A), ST_RESID, cur, b, nullptr, T(0), r, s);
+  stencil<T, T>(L.d, Sel<T>::v(A), ST_RESID, cur, b, nullptr, nullptr, T(0), T(0), r, s);
   Level& G = c->lv[l + 1];
   spmv<T, T>(L.dR, Sel<T>::R(L), r, Sel<T>::b(G), T(1), T(0), s);
-  vcycle<T>(c, op, l + 1, Sel<T>::b(G), Sel<T>::x(G), o, s);
+  vcycle<T>(c, op, l + 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
   spmv<T, T>(L.dP, Sel<T>::P(L), Sel<T>::x(G), cur, T(1), T(1), s);
-  for (int k = 0; k < o.mg_post; ++k) {
-    stencil<T, T>(L.d, Sel<T>::v(A), ST_JACOBI, cur, b, Sel<T>::d(A), w, oth, s);
-    std::swap(cur, oth);
+  if (o.mg_post > 0) {
+    const ChebCoef<T> post = cheb_coef<T>(lmax / 4.0, lmax, o.mg_post);
+    for (int k = 0; k < o.mg_post; ++k) {
+      stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, cur, b, Sel<T>::d(A), d, post.c1[k], post.c2[k],
+                    oth, s);
+      std::swap(cur, oth);
+    }
   }
 }
 
@@ -224,15 +288,14 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, const T* b, T* x, const ch
 template <typename T>
 void mg_solve(chns_ctx* c, OpVals Level::*op, const T* b, T* x, const chns_solve_opts& o,
               hipStream_t s) {
-  vcycle<T>(c, op, 0, b, x, o, s);
+  const size_t cut = cut_level(c, coef_of(c, op), o.mg_rho_cut);
+  vcycle<T>(c, op, 0, cut, b, x, o, s);
   Level& L = c->lv[0];
   for (int k = 1; k < o.mg_cycles; ++k) {
-    // e64/e32 hold the residual, the level's r/t are used inside the cycle,
-    // so the correction goes through the FP32/FP64 scratch of the context.
     T* res = Sel<T>::e(L);
-    stencil<T, T>(L.d, Sel<T>::v(L.*op), ST_RESID, x, b, nullptr, T(0), res, s);
+    stencil<T, T>(L.d, Sel<T>::v(L.*op), ST_RESID, x, b, nullptr, nullptr, T(0), T(0), res, s);
     T* corr = std::is_same<T, double>::value ? (T*)c->w64c : (T*)c->w32c;
-    vcycle<T>(c, op, 0, res, corr, o, s);
+    vcycle<T>(c, op, 0, cut, res, corr, o, s);
     axpby<T>(L.N, T(1), corr, T(1), x, s);
   }
 }
@@ -349,14 +412,17 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       double* hcol = K.H + int64_t(j) * (m + 1);
       TRY(precond(c, block, o, vj, zj, s));
       TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
-      // classical Gram-Schmidt, twice; the second update also yields ||w||^2
-      mdot_partial(n, K.V, ld, j + 1, vn, K.part, s);
-      mdot_reduce(nblk, j + 1, K.part, K.htmp, hcol, 0, s);
-      maxpy(n, K.V, ld, j + 1, K.htmp, vn, nullptr, s);
-      mdot_partial(n, K.V, ld, j + 1, vn, K.part, s);
-      mdot_reduce(nblk, j + 1, K.part, K.htmp, hcol, 1, s);
-      maxpy(n, K.V, ld, j + 1, K.htmp, vn, K.nrm_part, s);
-      arnoldi_finish(nblk, K.nrm_part, j, m, K.H, K.cs, K.sn, K.g, K.scal, s);
+      // classical Gram-Schmidt; the first multi-dot also gives ||w||^2 (w is
+      // basis slot j+1), the update gives ||w'||^2, and a second pass runs
+      // only when ||w'||^2 < ||w||^2 / 2 (decided on the device).
+      mdot_partial(n, K.V, ld, j + 2, vn, K.part, nullptr, s);
+      mdot_reduce(nblk, j + 2, K.part, K.htmp, hcol, 0, nullptr, s);
+      maxpy(n, K.V, ld, j + 1, K.htmp, vn, K.nrm_part, nullptr, s);
+      reorth_decide(nblk, K.nrm_part, K.htmp + j + 1, K.flag, K.scal, s);
+      mdot_partial(n, K.V, ld, j + 1, vn, K.part, K.flag, s);
+      mdot_reduce(nblk, j + 1, K.part, K.htmp, hcol, 1, K.flag, s);
+      maxpy(n, K.V, ld, j + 1, K.htmp, vn, K.nrm_part2, K.flag, s);
+      arnoldi_finish(nblk, K.nrm_part2, K.flag, j, m, K.H, K.cs, K.sn, K.g, K.scal, s);
       scale_by_inv(n, vn, K.scal + 1, vn, s);
       HIPCHK(c, hipGetLastError());
       k = j + 1;
@@ -456,8 +522,8 @@ int build(chns_ctx* c) {
       TRY(dalloc(c, &o->d64, N));
       TRY(dalloc(c, &o->d32, N));
     }
-    for (double** v : {&L.b64, &L.x64, &L.t64, &L.r64, &L.e64}) TRY(dalloc(c, v, N));
-    for (float** v : {&L.b32, &L.x32, &L.t32, &L.r32, &L.e32}) TRY(dalloc(c, v, N));
+    for (double** v : {&L.b64, &L.x64, &L.t64, &L.r64, &L.e64, &L.d64}) TRY(dalloc(c, v, N));
+    for (float** v : {&L.b32, &L.x32, &L.t32, &L.r32, &L.e32, &L.d32}) TRY(dalloc(c, v, N));
     HIPCHK(c, hipMemset(L.C, 0, ns * sizeof(double)));
     HIPCHK(c, hipMemset(L.C32, 0, ns * sizeof(float)));
   }
@@ -480,6 +546,8 @@ int build(chns_ctx* c) {
   TRY(dalloc(c, &K.htmp, MAX_RESTART + 2));
   TRY(dalloc(c, &K.part, size_t(1024) * (MAX_RESTART + 2)));
   TRY(dalloc(c, &K.nrm_part, 1024));
+  TRY(dalloc(c, &K.nrm_part2, 1024));
+  TRY(dalloc(c, &K.flag, 4));
   HIPCHK(c, hipHostMalloc((void**)&K.host, 8 * sizeof(double), hipHostMallocDefault));
   HIPCHK(c, hipEventCreate(&c->ev0));
   HIPCHK(c, hipEventCreate(&c->ev1));
@@ -519,14 +587,15 @@ void chns_default_opts(chns_solve_opts* o) {
   if (!o) return;
   o->rtol = 1e-8;
   o->atol = 0.0;
-  o->restart = 30;
+  o->restart = 40;
   o->maxiter = 600;
   o->precision = CHNS_F64;
   o->mg_cycles = 1;
   o->mg_pre = 2;
   o->mg_post = 2;
-  o->mg_coarse = 16;
-  o->mg_omega = 2.0 / 3.0;
+  o->mg_coarse = 8;
+  o->mg_lmax = 2.1;
+  o->mg_rho_cut = 0.25;
 }
 
 int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out) {

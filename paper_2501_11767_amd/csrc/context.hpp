@@ -46,6 +46,8 @@ struct Level {
   // multigrid work vectors (per precision)
   double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *e64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *t32 = nullptr, *r32 = nullptr, *e32 = nullptr;
+  double* d64 = nullptr;  // Chebyshev direction
+  float* d32 = nullptr;
 };
 
 struct Krylov {
@@ -53,6 +55,8 @@ struct Krylov {
   double *V = nullptr, *Z = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *scal = nullptr, *htmp = nullptr, *part = nullptr, *nrm_part = nullptr;
+  double* nrm_part2 = nullptr;
+  int* flag = nullptr;  // second Gram-Schmidt pass wanted
   double* host = nullptr;  // pinned readback
 };
 
@@ -63,6 +67,8 @@ struct chns_ctx {
   chns_params prm{};
   int N = 0;            // P1 nodes
   bool has_conv = false;
+  // multigrid: operator coefficients a M + b K for the level cut
+  double coefL[2] = {1, 0}, coefX[2] = {1, 0}, coefAC[2] = {1, 0};
   std::vector<chns::Level> lv;
   chns::Elements el;
   int *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;

@@ -81,7 +81,8 @@ __global__ __launch_bounds__(BS) void k_stencil7(int nrows, const int* __restric
                                                  const TV* __restrict__ val,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ b,
-                                                 const T* __restrict__ dinv, T p0, T p1,
+                                                 const T* __restrict__ dinv,
+                                                 T* __restrict__ d, T p0, T p1,
                                                  T* __restrict__ y) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * BS + threadIdx.x;
@@ -100,34 +101,41 @@ __global__ __launch_bounds__(BS) void k_stencil7(int nrows, const int* __restric
     y[row] = (p1 == T(0)) ? p0 * sum : p0 * sum + p1 * y[row];
   } else if (MODE == ST_RESID) {
     y[row] = b[row] - sum;
-  } else {  // ST_JACOBI, p0 = omega
-    y[row] = x[row] + p0 * dinv[row] * (b[row] - sum);
+  } else {  // ST_CHEB, p0 = c1, p1 = c2
+    const T r = dinv[row] * (b[row] - sum);
+    const T dn = (p0 == T(0)) ? p1 * r : p0 * d[row] + p1 * r;
+    d[row] = dn;
+    y[row] = x[row] + dn;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_jacobi0(int n, const T* __restrict__ dinv,
-                                                const T* __restrict__ b, T omega,
-                                                T* __restrict__ x) {
+__global__ __launch_bounds__(BS) void k_cheb0(int n, const T* __restrict__ dinv,
+                                              const T* __restrict__ b, T c2, T* __restrict__ d,
+                                              T* __restrict__ x) {
   const int i = blockIdx.x * BS + threadIdx.x;
-  if (i < n) x[i] = omega * dinv[i] * b[i];
+  if (i < n) {
+    const T v = c2 * (dinv[i] * b[i]);
+    d[i] = v;
+    x[i] = v;
+  }
 }
 
+// Chebyshev steps from x = 0 on a level of at most 1024 rows: one workgroup,
+// one row per thread, the row kept in registers, x in LDS.
 template <typename T, typename TV>
-__global__ __launch_bounds__(1024) void k_coarse_jacobi(int nrows, const int* __restrict__ col,
-                                                        const TV* __restrict__ val,
-                                                        const T* __restrict__ dinv,
-                                                        const T* __restrict__ b, T omega,
-                                                        int sweeps, T* __restrict__ x) {
+__global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, const int* __restrict__ col,
+                                                      const TV* __restrict__ val,
+                                                      const T* __restrict__ dinv,
+                                                      const T* __restrict__ b, ChebCoef<T> cc,
+                                                      T* __restrict__ x) {
   __shared__ T xa[1024], xb[1024];
   const int r = threadIdx.x;
   T* cur = xa;
   T* nxt = xb;
-  if (r < nrows) cur[r] = T(0);
-  __syncthreads();
   int c[W7];
   TV v[W7];
-  T d = T(0), br = T(0);
+  T di = T(0), br = T(0), dd = T(0);
   if (r < nrows) {
     const size_t base = size_t(r >> 6) * (64 * W7) + (r & 63);
 #pragma unroll
@@ -135,15 +143,19 @@ __global__ __launch_bounds__(1024) void k_coarse_jacobi(int nrows, const int* __
       c[k] = col[base + k * 64];
       v[k] = val[base + k * 64];
     }
-    d = dinv[r];
+    di = dinv[r];
     br = b[r];
+    dd = cc.c2[0] * (di * br);
+    cur[r] = dd;
   }
-  for (int s = 0; s < sweeps; ++s) {
+  __syncthreads();
+  for (int s = 1; s < cc.steps; ++s) {
     if (r < nrows) {
       T sum = T(0);
 #pragma unroll
       for (int k = 0; k < W7; ++k) sum += T(v[k]) * cur[c[k]];
-      nxt[r] = cur[r] + omega * d * (br - sum);
+      dd = cc.c1[s] * dd + cc.c2[s] * (di * (br - sum));
+      nxt[r] = cur[r] + dd;
     }
     __syncthreads();
     T* t = cur;
@@ -226,7 +238,9 @@ constexpr int MD_G = 8;  // basis vectors per multi-dot pass
 __global__ __launch_bounds__(BS) void k_mdot_partial(int64_t n, const double* __restrict__ V,
                                                      int64_t ldv, int k,
                                                      const double* __restrict__ w,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part,
+                                                     const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   __shared__ double sh[4];
   const int g0 = blockIdx.y * MD_G;
   const int kk = min(MD_G, k - g0);
@@ -246,25 +260,29 @@ __global__ __launch_bounds__(BS) void k_mdot_partial(int64_t n, const double* __
   }
 }
 
+// One workgroup per basis vector.
 __global__ __launch_bounds__(BS) void k_mdot_reduce(int nblk, int k, const double* __restrict__ part,
                                                     double* __restrict__ h_tmp,
-                                                    double* __restrict__ h_col, int accumulate) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = wid; i < k; i += 4) {
-    double s = 0.0;
-    for (int b = lane; b < nblk; b += 64) s += part[int64_t(i) * nblk + b];
-    s = wave_sum(s);
-    if (lane == 0) {
-      h_tmp[i] = s;
-      h_col[i] = accumulate ? h_col[i] + s : s;
-    }
+                                                    double* __restrict__ h_col, int accumulate,
+                                                    const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += BS) s += part[int64_t(i) * nblk + b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    h_tmp[i] = s;
+    h_col[i] = accumulate ? h_col[i] + s : s;
   }
 }
 
 __global__ __launch_bounds__(BS) void k_maxpy(int64_t n, const double* __restrict__ V, int64_t ldv,
                                               int k, const double* __restrict__ h,
                                               double* __restrict__ w,
-                                              double* __restrict__ nrm_part) {
+                                              double* __restrict__ nrm_part,
+                                              const int* __restrict__ flag) {
+  if (flag && *flag == 0) return;
   __shared__ double hs[257];
   __shared__ double sh[4];
   for (int i = threadIdx.x; i < k; i += BS) hs[i] = h[i];
@@ -290,12 +308,24 @@ __device__ double sum_partials_wave(int nblk, const double* part) {
   return wave_sum(s);
 }
 
+__global__ void k_reorth_decide(int nblk, const double* __restrict__ nrm_part,
+                                const double* __restrict__ ww, int* __restrict__ flag,
+                                double* __restrict__ scal) {
+  const double w2 = sum_partials_wave(nblk, nrm_part);
+  if (threadIdx.x == 0) {
+    scal[3] = w2;
+    flag[0] = (w2 < 0.5 * ww[0]) ? 1 : 0;
+  }
+}
+
 // One wavefront.  H column-major with leading dimension m+1.
-__global__ void k_arnoldi_finish(int nblk, const double* __restrict__ nrm_part, int j, int m,
+__global__ void k_arnoldi_finish(int nblk, const double* __restrict__ nrm_part,
+                                 const int* __restrict__ flag, int j, int m,
                                  double* __restrict__ H, double* __restrict__ cs,
                                  double* __restrict__ sn, double* __restrict__ g,
                                  double* __restrict__ scal) {
-  const double nrm = sqrt(sum_partials_wave(nblk, nrm_part));
+  const bool second = (flag == nullptr) || (*flag != 0);
+  const double nrm = second ? sqrt(sum_partials_wave(nblk, nrm_part)) : sqrt(scal[3]);
   if (threadIdx.x != 0) return;
   const int ld = m + 1;
   double* h = H + int64_t(j) * ld;
@@ -539,7 +569,8 @@ template <typename T, typename TV>
 void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s) {
   if (A.uniform && A.width == W7) {
     hipLaunchKernelGGL((k_stencil7<T, TV, ST_SPMV>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
-                       A.nrows, A.col, val, x, (const T*)nullptr, (const T*)nullptr, alpha, beta, y);
+                       A.nrows, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       alpha, beta, y);
   } else {
     const int npos = A.nslices * 64;
     hipLaunchKernelGGL((k_spmv_sell<T, TV>), dim3(ceil_div(npos, BS)), dim3(BS), 0, s, A.nslices,
@@ -549,27 +580,27 @@ void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipS
 }
 
 template <typename T, typename TV>
-void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv,
-             T omega, T* y, hipStream_t s) {
+void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv, T* d,
+             T c1, T c2, T* y, hipStream_t s) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (mode == ST_RESID)
     hipLaunchKernelGGL((k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.col, val, x, b,
-                       dinv, omega, T(0), y);
+                       dinv, d, c1, c2, y);
   else
-    hipLaunchKernelGGL((k_stencil7<T, TV, ST_JACOBI>), g, blk, 0, s, A.nrows, A.col, val, x, b,
-                       dinv, omega, T(0), y);
+    hipLaunchKernelGGL((k_stencil7<T, TV, ST_CHEB>), g, blk, 0, s, A.nrows, A.col, val, x, b,
+                       dinv, d, c1, c2, y);
 }
 
 template <typename T>
-void jacobi0(int n, const T* dinv, const T* b, T omega, T* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_jacobi0<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, dinv, b, omega, x);
+void cheb0(int n, const T* dinv, const T* b, T c2, T* d, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb0<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, dinv, b, c2, d, x);
 }
 
 template <typename T, typename TV>
-void coarse_jacobi(const DSell& A, const TV* val, const T* dinv, const T* b, T omega, int sweeps,
-                   T* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_jacobi<T, TV>), dim3(1), dim3(1024), 0, s, A.nrows, A.col, val,
-                     dinv, b, omega, sweeps, x);
+void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const ChebCoef<T>& cc,
+                 T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_coarse_cheb<T, TV>), dim3(1), dim3(1024), 0, s, A.nrows, A.col, val, dinv,
+                     b, cc, x);
 }
 
 template <typename T, typename TV>
@@ -604,27 +635,33 @@ int reduce_blocks(int64_t n) {
 }
 
 void mdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                  hipStream_t s) {
+                  const int* flag, hipStream_t s) {
   const int nblk = reduce_blocks(n);
   hipLaunchKernelGGL(k_mdot_partial, dim3(nblk, ceil_div(k, MD_G)), dim3(BS), 0, s, n, V, ldv, k,
-                     w, part);
+                     w, part, flag);
 }
 
 void mdot_reduce(int nblk, int k, const double* part, double* h_tmp, double* h_col, int accumulate,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(BS), 0, s, nblk, k, part, h_tmp, h_col,
-                     accumulate);
+                 const int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(k), dim3(BS), 0, s, nblk, k, part, h_tmp, h_col,
+                     accumulate, flag);
 }
 
 void maxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
-           double* nrm_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_maxpy, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ldv, k, h, w, nrm_part);
+           double* nrm_part, const int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_maxpy, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ldv, k, h, w, nrm_part,
+                     flag);
 }
 
-void arnoldi_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* cs,
-                    double* sn, double* g, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, s, nblk, nrm_part, j, m, H, cs, sn, g,
-                     scal);
+void reorth_decide(int nblk, const double* nrm_part, const double* ww, int* flag, double* scal,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_reorth_decide, dim3(1), dim3(64), 0, s, nblk, nrm_part, ww, flag, scal);
+}
+
+void arnoldi_finish(int nblk, const double* nrm_part, const int* flag, int j, int m, double* H,
+                    double* cs, double* sn, double* g, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, s, nblk, nrm_part, flag, j, m, H, cs,
+                     sn, g, scal);
 }
 
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {
@@ -681,15 +718,18 @@ template void spmv<double, double>(const DSell&, const double*, const double*, d
 template void spmv<float, float>(const DSell&, const float*, const float*, float*, float, float,
                                  hipStream_t);
 template void stencil<double, double>(const DSell&, const double*, int, const double*,
-                                      const double*, const double*, double, double*, hipStream_t);
+                                      const double*, const double*, double*, double, double,
+                                      double*, hipStream_t);
 template void stencil<float, float>(const DSell&, const float*, int, const float*, const float*,
-                                    const float*, float, float*, hipStream_t);
-template void jacobi0<double>(int, const double*, const double*, double, double*, hipStream_t);
-template void jacobi0<float>(int, const float*, const float*, float, float*, hipStream_t);
-template void coarse_jacobi<double, double>(const DSell&, const double*, const double*,
-                                            const double*, double, int, double*, hipStream_t);
-template void coarse_jacobi<float, float>(const DSell&, const float*, const float*, const float*,
-                                          float, int, float*, hipStream_t);
+                                    const float*, float*, float, float, float*, hipStream_t);
+template void cheb0<double>(int, const double*, const double*, double, double*, double*,
+                            hipStream_t);
+template void cheb0<float>(int, const float*, const float*, float, float*, float*, hipStream_t);
+template void coarse_cheb<double, double>(const DSell&, const double*, const double*,
+                                          const double*, const ChebCoef<double>&, double*,
+                                          hipStream_t);
+template void coarse_cheb<float, float>(const DSell&, const float*, const float*, const float*,
+                                        const ChebCoef<float>&, float*, hipStream_t);
 template void ch_block<double, double>(const DSell&, const double*, const double*, const double*,
                                        double, double, const double*, double, double, double*,
                                        hipStream_t);

@@ -18,26 +18,37 @@ struct DSell {
 };
 
 // Operator modes of the fused stencil kernel (uniform width-7 P1 patterns).
-enum StencilMode { ST_SPMV = 0, ST_RESID = 1, ST_JACOBI = 2 };
+enum StencilMode { ST_SPMV = 0, ST_RESID = 1, ST_CHEB = 2 };
+
+// Chebyshev step coefficients: step i updates d <- c1[i] d + c2[i] D^{-1}(b - A x),
+// x <- x + d (c1[0] = 0).
+constexpr int MAXCHEB = 64;
+template <typename T>
+struct ChebCoef {
+  T c1[MAXCHEB];
+  T c2[MAXCHEB];
+  int steps;
+};
 
 // y = alpha A x + beta y on any SELL pattern (beta == 0: y not read).
 template <typename T, typename TV>
 void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s);
 
-// Uniform P1 operators: mode ST_RESID: y = b - A x;  ST_JACOBI: y = x + omega dinv (b - A x).
+// Uniform P1 operators: mode ST_RESID: y = b - A x;
+// ST_CHEB: d <- c1 d + c2 dinv (b - A x) (d not read when c1 == 0), y = x + d.
 template <typename T, typename TV>
 void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv,
-             T omega, T* y, hipStream_t s);
+             T* d, T c1, T c2, T* y, hipStream_t s);
 
-// x = omega dinv b (first Jacobi sweep from zero).
+// First Chebyshev step from x = 0: x = d = c2 dinv b.
 template <typename T>
-void jacobi0(int n, const T* dinv, const T* b, T omega, T* x, hipStream_t s);
+void cheb0(int n, const T* dinv, const T* b, T c2, T* d, T* x, hipStream_t s);
 
-// Coarsest level: `sweeps` damped-Jacobi sweeps from x = 0 in one workgroup
-// (nrows <= 1024, uniform width-7 pattern).
+// Chebyshev steps from x = 0 in one workgroup (nrows <= 1024, uniform
+// width-7 pattern), for the cut level of a cycle.
 template <typename T, typename TV>
-void coarse_jacobi(const DSell& A, const TV* val, const T* dinv, const T* b, T omega, int sweeps,
-                   T* x, hipStream_t s);
+void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const ChebCoef<T>& cc,
+                 T* x, hipStream_t s);
 
 // CH block on [x1; x2] with value streams L = M + tau C, K, M (uniform P1):
 //   y1 = alpha (L x1 + c12 K x2) + beta y1,  y2 = alpha (c12 K x1 + c22 M x2) + beta y2.
@@ -55,18 +66,24 @@ void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipS
 // Krylov reductions (FP64).  Partial sums per workgroup go to `part`
 // (reduce_blocks(n) * cols doubles); reduce_* finish them deterministically.
 int reduce_blocks(int64_t n);
+// Kernels taking `flag` (may be null) return at once when *flag == 0.
 void mdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                  hipStream_t s);
-// h_out[i] (+)= sum of partials; also writes h_tmp for the following maxpy.
+                  const int* flag, hipStream_t s);
+// h_col[i] (+)= sum of partials of vector i; also h_tmp[i] for the following maxpy.
 void mdot_reduce(int nblk, int k, const double* part, double* h_tmp, double* h_col, int accumulate,
-                 hipStream_t s);
+                 const int* flag, hipStream_t s);
 // w -= V h (k columns); with nrm_part != nullptr also partial sums of w^2.
 void maxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
-           double* nrm_part, hipStream_t s);
-// Norm of w from partials, Givens update of Hessenberg column j, residual
-// estimate, 1/h_{j+1,j}.  H is (m+1) x m column-major with leading dim m+1.
-void arnoldi_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* cs,
-                    double* sn, double* g, double* scal, hipStream_t s);
+           double* nrm_part, const int* flag, hipStream_t s);
+// Second Gram-Schmidt pass wanted?  flag = (||w'||^2 < ||w||^2 / 2) with
+// ||w'||^2 from nrm_part and ||w||^2 = *ww; scal[3] = ||w'||^2.
+void reorth_decide(int nblk, const double* nrm_part, const double* ww, int* flag, double* scal,
+                   hipStream_t s);
+// Norm of w (from nrm_part when *flag, else sqrt(scal[3])), Givens update of
+// Hessenberg column j, residual estimate, 1/h_{j+1,j}.  H is (m+1) x m
+// column-major with leading dim m+1.
+void arnoldi_finish(int nblk, const double* nrm_part, const int* flag, int j, int m, double* H,
+                    double* cs, double* sn, double* g, double* scal, hipStream_t s);
 // Least squares back-substitution for k columns: y = R^{-1} g.
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // x += Z y (k columns).

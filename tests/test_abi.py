@@ -33,8 +33,9 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_default_opts(L):
     o = chns.default_opts()
-    assert o.rtol == 1e-8 and o.restart == 30 and o.precision == chns.F64
-    assert o.mg_pre == 2 and o.mg_post == 2 and abs(o.mg_omega - 2 / 3) < 1e-15
+    assert o.rtol == 1e-8 and o.restart == 40 and o.precision == chns.F64
+    assert o.mg_pre == 2 and o.mg_post == 2 and o.mg_coarse == 8
+    assert o.mg_lmax == 2.1 and o.mg_rho_cut == 0.25
 
 
 @pytest.mark.parametrize("n,model", [(7, 0), (6, 0), (0, 1), (10000, 1), (16, 9)])

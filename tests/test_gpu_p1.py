@@ -127,12 +127,16 @@ def test_step_rhs(chns):
     assert _rel(_np(rch), sys2["ch_rhs"][0]) < 1e-13
 
 
-@pytest.mark.parametrize("n,conv", [(16, False), (32, True), (40, False), (66, False)])
-def test_precond_matches_oracle_vcycle(chns, n, conv):
+@pytest.mark.parametrize("n,conv,prm", [(16, False, PRM), (32, True, PRM), (40, False, PRM),
+                                          (66, False, PRM),
+                                          (128, False, dict(PRM, eps=0.005, tau=1e-2, evap_rate=50.0))])
+def test_precond_matches_oracle_vcycle(chns, n, conv, prm):
     """The preconditioner is a fixed linear operator: compare with the oracle's
     cycle on the same hierarchy (n = 40 and 66 exercise odd coarsest sizes,
-    66 the multi-workgroup coarsest level)."""
+    66 a cut level too large for one workgroup; the last case cuts the X and
+    AC cycles on coarse levels)."""
     import torch
+    PRM = prm
     ctx = chns.Context(n, "ch_ac", **PRM)
     m = fem.Mesh(n)
     prm = _oracle_prm(PRM)
@@ -144,8 +148,8 @@ def test_precond_matches_oracle_vcycle(chns, n, conv):
         C = fem.p1_convection(m, vel)
     g = np.random.default_rng(1)
     for cycles in (1, 2):
-        kw = dict(pre=2, post=1, coarse=12, omega=0.7)
-        opts = chns.default_opts(mg_pre=2, mg_post=1, mg_coarse=12, mg_omega=0.7, mg_cycles=cycles)
+        kw = dict(pre=2, post=1, coarse=12)
+        opts = chns.default_opts(mg_pre=2, mg_post=1, mg_coarse=12, mg_cycles=cycles)
         P = PC.CHPreconditioner(M, K, C, prm, n, inner="mg", cycles=cycles, **kw)
         r = g.standard_normal(2 * n * n)
         z = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
@@ -153,7 +157,7 @@ def test_precond_matches_oracle_vcycle(chns, n, conv):
         torch.cuda.synchronize()
         assert _rel(_np(z), P.apply(r)) < 1e-12
         Aac = systems.ac_matrix(M, K, C, prm)
-        Pa = PC.ACPreconditioner(Aac, n, inner="mg", cycles=cycles, **kw)
+        Pa = PC.ACPreconditioner(Aac, n, prm, inner="mg", cycles=cycles, **kw)
         ra = g.standard_normal(n * n)
         za = torch.zeros(n * n, dtype=torch.float64, device="cuda")
         ctx.precond(chns.BLOCK_AC, _t(ra), za, opts)

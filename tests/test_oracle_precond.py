@@ -12,6 +12,7 @@
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from oracle import krylov, multigrid as mg, precond as PC, solvers, step as S, systems
 from oracle.systems import Params
@@ -72,7 +73,8 @@ def test_vcycle_converges_and_is_symmetric(tau):
     ops = S.Operators(n)
     prm = Params(eps=0.01, tau=tau, mobility=1.0)
     X = PC.matching_factor(ops.M, ops.K, prm)
-    H = mg.Hierarchy(X, n)
+    a, b = np.sqrt(prm.tau * prm.gamma / prm.beta), prm.tau * prm.gamma
+    H = mg.Hierarchy(X, n, a=a, b=b, rho_cut=0.0)
     assert H.sizes == [32, 16, 8, 4]
     N = n * n
     # symmetric: <x, B y> = <y, B x> for the cycle operator B
@@ -84,6 +86,29 @@ def test_vcycle_converges_and_is_symmetric(tau):
     for _ in range(5):
         e = e - mg.vcycle(H, X @ e)
     assert (np.linalg.norm(e) / e0) ** (1 / 5) < 0.3
+
+
+def test_chebyshev_matches_the_chebyshev_polynomial():
+    # For A = diag(lam), D = I, x0 = 0: the error after k steps is
+    # T_k((theta - lam)/delta) / T_k(theta/delta) times the initial error.
+    lo, hi, k = 0.3, 2.0, 5
+    lam = np.linspace(0.05, 2.0, 40)
+    A = sp.diags(lam).tocsr()
+    x = mg.chebyshev(A, np.ones(40), np.ones(40), np.zeros(40), lo, hi, k)
+    e = x - 1.0 / lam
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    T = lambda t: np.cosh(k * np.arccosh(t)) if t >= 1 else np.cos(k * np.arccos(np.clip(t, -1, 1)))
+    ref = np.array([T((theta - l) / delta) for l in lam]) / T(theta / delta) * (-1.0 / lam)
+    assert np.allclose(e, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_level_cut_rule():
+    sizes = mg.level_sizes(1024)
+    assert sizes == [1024, 512, 256, 128, 64, 32, 16, 8, 4]
+    assert mg.cut_level(sizes, 1.0, 0.0) == 0          # pure mass: fine level only
+    # rho_l = 8 b n_l^2 / a <= 0.25 first at n_l = 16 for b/a = 1e-4 / 2
+    assert mg.cut_level(sizes, 2.0, 1e-4) == 6
+    assert mg.cut_level(sizes, 1.0, 1.0) == len(sizes) - 1
 
 
 def test_fgmres_reaches_direct_solution_with_block_preconditioner():
