@@ -79,7 +79,9 @@ enum {
   CHNS_OP_AC = 4,      /* Allen-Cahn matrix M + tau delta_v K + tau C */
   CHNS_OP_X = 5,       /* matching factor tau g K + sqrt(tau g / beta) M */
   CHNS_OP_L = 6,       /* CH (1,1) block M + tau C */
-  CHNS_OP_NS = 7       /* Oseen saddle point on [v_x; v_y; p] (ternary model) */
+  CHNS_OP_NS = 7,      /* Oseen saddle point on [v_x; v_y; p], 9n^2 x 9n^2 (ternary model) */
+  CHNS_OP_VX = 8,      /* velocity block A_xx = (rho/tau) M + J(w) + K_sym,xx on P2, 4n^2 x 4n^2 */
+  CHNS_OP_AP = 9       /* pressure convection-diffusion matrix (rho/tau) M + eta K + N(w), P1 */
 };
 
 /* Arithmetic of the preconditioner: all FP64, or FP32 multigrid inside an
@@ -162,10 +164,12 @@ CHNS_API int chns_set_params(chns_ctx* ctx, const chns_params* params);
 
 /* Per-step assembly (paper: C(v^k) of eq. (CH_linear); J(w^k) and the PCD
  * matrix A_p(w^k) for the Oseen step): coloured element scatter of the
- * convection matrix from the P2 velocity d_vel (NULL means v = 0), Galerkin
- * refresh of every coarse level, and re-forming of the block values.
- * d_mu: for the ternary model the three chemical potentials (polymer, NFA,
- * solvent) entering w = rho v - alpha sum grad mu_i; NULL otherwise. */
+ * convection matrix from the P2 velocity d_vel (NULL means v = 0; required
+ * for the ternary model), Galerkin refresh of every coarse level, and
+ * re-forming of the block values.  d_mu: for the ternary model the three
+ * chemical potentials (polymer, NFA, solvent) entering the convecting field
+ * w = rho v - alpha sum_i grad mu_i (an entry or the array may be NULL for
+ * mu = 0); ignored otherwise. */
 CHNS_API int chns_assemble(chns_ctx* ctx, const double* d_vel, const double* const* d_mu,
                            void* stream);
 
@@ -180,16 +184,18 @@ CHNS_API int chns_get_matrix(chns_ctx* ctx, int32_t op, int32_t* h_rowptr, int32
                              double* h_val, void* stream);
 
 /* y = alpha * A x + beta * y for op in CHNS_OP_*.  precision CHNS_F64: x, y
- * double; CHNS_MIXED: x, y float with FP32 matrix values.  x and y must not
- * overlap.  With beta == 0, y is not read. */
+ * double; CHNS_MIXED: x, y float with FP32 matrix values (not for CHNS_OP_NS).
+ * x and y must not overlap.  With beta == 0, y is not read. */
 CHNS_API int chns_spmv(chns_ctx* ctx, int32_t op, int32_t precision, double alpha,
                        const void* d_x, double beta, void* d_y, void* stream);
 
 /* z = P^{-1} r for a block (paper: CH diag(L, X M^{-1} X) with L ~ M + tau C
  * and X = tau g K + sqrt(tau g / beta) M; AC multigrid on its matrix; NS
- * diag(A^, M_p^{-1} A_p K_p^{-1})).  Inner inverses are opts->mg_cycles
- * geometric V-cycles in the precision opts->precision; r and z are FP64 and
- * must not overlap. */
+ * diag(A^, M_p^{-1} A_p K_p^{-1}) with A^ = diag of the two velocity component
+ * blocks and K_p^{-1} applied to mean-zero pressures).  Inner inverses are
+ * opts->mg_cycles geometric V-cycles in the precision opts->precision (the
+ * velocity blocks start on their P2 level and continue on the P1 levels); r
+ * and z are FP64 and must not overlap. */
 CHNS_API int chns_precond_apply(chns_ctx* ctx, int32_t block, const chns_solve_opts* opts,
                                 const double* d_r, double* d_z, void* stream);
 
@@ -198,7 +204,8 @@ CHNS_API int chns_precond_apply(chns_ctx* ctx, int32_t block, const chns_solve_o
  * of the vector's norm squared, Givens least squares on the device), stopping rule
  * ||b - A x|| <= max(rtol ||b||, atol) on the recomputed true residual.
  * d_x holds the initial guess and receives the solution.  Synchronising
- * (reads the residual estimate back once per Arnoldi step).  h_info may be NULL. */
+ * (reads the residual estimate back once per Arnoldi step).  h_info may be NULL.
+ * For CHNS_BLOCK_NS the returned pressure is projected to mean zero. */
 CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, const double* d_b, double* d_x,
                                const chns_solve_opts* opts, chns_solve_info* h_info,
                                void* stream);
@@ -206,8 +213,11 @@ CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, const double* d_b, 
 /* Right-hand sides of one step from the level-k fields (paper: [M phi^k;
  * -(tau g/beta) f^k] per CH phase with f^k = M f'(phi^k) nodal, the AC
  * right-hand side, and for the ternary model (rho/tau) M v^k + F^k with the
- * Korteweg force F).  d_rhs_ch: 2n^2 per CH phase, phases consecutive;
- * d_rhs_ac: n^2 or NULL; d_rhs_ns: 9n^2 or NULL. */
+ * Korteweg force F = int G : grad, G = beta sum_i grad phi_i (x) grad phi_i
+ * + beta_v grad Phi (x) grad Phi over polymer, NFA and solvent, and zero
+ * pressure rows).  d_rhs_ch: 2n^2 per CH phase, phases consecutive; d_rhs_ac:
+ * n^2 (required for models with a vapour field); d_rhs_ns: 9n^2 (required for
+ * the ternary model). */
 CHNS_API int chns_step_rhs(chns_ctx* ctx, const chns_fields* in, double* d_rhs_ch,
                            double* d_rhs_ac, double* d_rhs_ns, void* stream);
 

@@ -28,6 +28,21 @@ Definition of the cycle for an operator A = a M + b K (+ c C):
   operator is cut on the fine level (no coarse levels at all);
 * V(pre, post) cycle from a zero initial guess.
 
+Velocity blocks (P2): the hierarchy starts with the P2 operator on mesh n and
+coarsens first to P1 on the same mesh (the P1 space is a subspace of the P2
+space; P interpolates P1 linearly to the edge midpoints), then follows the P1
+levels above.  The P2 level smooths on [LMAX_P2/4, LMAX_P2]: for every P2
+element matrix of a nonnegative combination of mass and stiffness forms the
+largest eigenvalue of D_e^{-1} A_e is below 2.21, which bounds D^{-1} A.
+The cut rule applies to the P1 levels; the xx/yy velocity forms have a P1
+diagonal of 6 eta, so they enter with b = 1.5 eta.
+
+Singular operators (the pressure Laplacian on the torus, constant null space):
+the right-hand side is projected to mean zero, the cycle runs to the last
+level, whose Chebyshev interval starts at 0.9 (1 - cos(2 pi / n_L)) / 2 (the
+smallest nonzero eigenvalue of D^{-1} K there), and the result is projected to
+mean zero.
+
 Chebyshev iteration (first kind) on [lo, hi] with theta = (hi + lo) / 2,
 delta = (hi - lo) / 2, sigma = theta / delta:
   r_0 = D^{-1}(b - A x_0), d_0 = r_0 / theta, x_1 = x_0 + d_0, rho_0 = 1 / sigma;
@@ -41,6 +56,7 @@ import numpy as np
 import scipy.sparse as sp
 
 LMAX = 2.1
+LMAX_P2 = 2.3
 RHO_CUT = 0.25
 
 
@@ -59,6 +75,24 @@ def prolongation(nf: int):
                 cols += [cid(I, J), cid(I + dI, J + dJ)]
                 vals += [0.5, 0.5]
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf * nf, nc * nc))
+
+
+def p2_to_p1(n: int):
+    """P1 on mesh n into P2 on mesh n: vertex nodes copy, edge midpoints average."""
+    N = n * n
+    idx = lambda i, j: (i % n) + n * (j % n)
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    i, j = ii.ravel(), jj.ravel()
+    rows = [np.arange(N)]
+    cols = [idx(i, j)]
+    vals = [np.ones(N)]
+    for blk, (di, dj) in enumerate(((1, 0), (0, 1), (1, 1)), start=1):
+        r = blk * N + idx(i, j)
+        rows += [r, r]
+        cols += [idx(i, j), idx(i + di, j + dj)]
+        vals += [0.5 * np.ones(N), 0.5 * np.ones(N)]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(4 * N, N))
 
 
 def level_sizes(n: int, nmin: int = 4):
@@ -80,20 +114,35 @@ def cut_level(sizes, a, b, rho_cut=RHO_CUT):
 
 
 class Hierarchy:
-    """Galerkin hierarchy of A = a M + b K (+ c C) down to its cut level."""
+    """Galerkin hierarchy of A = a M + b K (+ c C) down to its cut level.
+
+    ``p2``: A is a P2 operator; ``singular``: pressure Laplacian (a = 0)."""
 
     def __init__(self, A, n: int, a: float = 1.0, b: float = 0.0, nmin: int = 4,
-                 rho_cut: float = RHO_CUT):
+                 rho_cut: float = RHO_CUT, p2: bool = False, singular: bool = False):
         sizes = level_sizes(n, nmin)
-        self.cut = cut_level(sizes, a, b, rho_cut)
+        self.singular = singular
+        self.cut = len(sizes) - 1 if singular else cut_level(sizes, a, b, rho_cut)
         self.sizes = sizes[: self.cut + 1]
-        self.rho_last = rho(a, b, self.sizes[-1])
         self.A = [sp.csr_matrix(A)]
         self.P = []
+        self.lmax = []
+        if p2:
+            P = p2_to_p1(n)
+            self.P.append(P)
+            self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
+            self.lmax.append(LMAX_P2)
         for nf in self.sizes[:-1]:
             P = prolongation(nf)
             self.P.append(P)
             self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
+            self.lmax.append(LMAX)
+        self.lmax.append(LMAX)
+        nl = self.sizes[-1]
+        if singular:
+            self.lo_last = 0.9 * (1.0 - np.cos(2.0 * np.pi / nl)) / 2.0
+        else:
+            self.lo_last = 0.9 * 0.5 / (1.0 + rho(a, b, nl))
         self.Dinv = [1.0 / Al.diagonal() for Al in self.A]
 
 
@@ -112,24 +161,28 @@ def chebyshev(A, Dinv, b, x, lo, hi, steps):
     return x
 
 
-def vcycle(H: Hierarchy, b, pre=2, post=2, coarse=8, lmax=LMAX, level=0):
-    A, Dinv = H.A[level], H.Dinv[level]
+def vcycle(H: Hierarchy, b, pre=2, post=2, coarse=8, level=0):
+    A, Dinv, lmax = H.A[level], H.Dinv[level], H.lmax[level]
     x = np.zeros_like(b)
     if level == len(H.A) - 1:
-        lo = 0.9 * 0.5 / (1.0 + H.rho_last)
-        return chebyshev(A, Dinv, b, x, lo, lmax, coarse if level > 0 else pre + post)
+        return chebyshev(A, Dinv, b, x, H.lo_last, lmax, coarse if level > 0 else pre + post)
     x = chebyshev(A, Dinv, b, x, lmax / 4.0, lmax, pre)
     r = b - A @ x
     P = H.P[level]
-    x = x + P @ vcycle(H, P.T @ r, pre, post, coarse, lmax, level + 1)
+    x = x + P @ vcycle(H, P.T @ r, pre, post, coarse, level + 1)
     if post > 0:
         x = chebyshev(A, Dinv, b, x, lmax / 4.0, lmax, post)
     return x
 
 
 def mg_solve(H: Hierarchy, b, cycles=1, **kw):
-    """``cycles`` V-cycles as a stationary iteration from x = 0."""
+    """``cycles`` V-cycles as a stationary iteration from x = 0 (with mean-zero
+    projections of the right-hand side and the result when singular)."""
+    if H.singular:
+        b = b - b.mean()
     x = vcycle(H, b, **kw)
     for _ in range(cycles - 1):
         x = x + vcycle(H, b - H.A[0] @ x, **kw)
+    if H.singular:
+        x = x - x.mean()
     return x

@@ -81,3 +81,53 @@ class ACPreconditioner:
         if self.inner == "exact":
             return sparse_solve(self.A, r)
         return mg.mg_solve(self.H, r, **self.mgkw)
+
+
+def pcd_matrix(M, K, Cw, prm):
+    """A_p = (rho/tau) M_p + eta K_p + N_p(w): the convection-diffusion operator
+    of the velocity block discretised on the pressure space."""
+    A = (prm.rho / prm.tau) * M + prm.viscosity * K
+    if Cw is not None:
+        A = A + Cw
+    return A.tocsr()
+
+
+class NSPreconditioner:
+    """diag(A^, S^) for eq. (linearnav): A^ = diag(A_xx^{-1}, A_yy^{-1}) (the
+    component blocks of the velocity operator), S^{-1} = M_p^{-1} A_p K_p^{-1}
+    with K_p^{-1} on mean-zero pressures."""
+
+    def __init__(self, Avel, M, K, Ap, prm, n, inner="exact", **mgkw):
+        N2 = 4 * n * n
+        self.Axx = Avel[:N2, :N2].tocsr()
+        self.Ayy = Avel[N2:, N2:].tocsr()
+        self.M, self.K, self.Ap = M.tocsr(), K.tocsr(), Ap.tocsr()
+        self.inner, self.mgkw, self.N2, self.N = inner, mgkw, N2, n * n
+        if inner == "mg":
+            a, b = prm.rho / prm.tau, 1.5 * prm.viscosity
+            self.Hx = mg.Hierarchy(self.Axx, n, a=a, b=b, p2=True)
+            self.Hy = mg.Hierarchy(self.Ayy, n, a=a, b=b, p2=True)
+            self.HK = mg.Hierarchy(self.K, n, a=0.0, b=1.0, singular=True)
+            self.HM = mg.Hierarchy(self.M, n, a=1.0, b=0.0)
+
+    def _kp_inv(self, r):
+        r = r - r.mean()
+        if self.inner == "mg":
+            return mg.mg_solve(self.HK, r, **self.mgkw)
+        N = self.N
+        one = sp.csr_matrix(np.ones((N, 1)))
+        B = sp.bmat([[self.K, one], [one.T, None]], format="csc")
+        y = sparse_solve(B, np.concatenate([r, [0.0]]))[:N]
+        return y - y.mean()
+
+    def apply(self, r):
+        N2, N = self.N2, self.N
+        if self.inner == "mg":
+            zx = mg.mg_solve(self.Hx, r[:N2], **self.mgkw)
+            zy = mg.mg_solve(self.Hy, r[N2:2 * N2], **self.mgkw)
+            zp = mg.mg_solve(self.HM, self.Ap @ self._kp_inv(r[2 * N2:]), **self.mgkw)
+        else:
+            zx = sparse_solve(self.Axx, r[:N2])
+            zy = sparse_solve(self.Ayy, r[N2:2 * N2])
+            zp = sparse_solve(self.M, self.Ap @ self._kp_inv(r[2 * N2:]))
+        return np.concatenate([zx, zy, zp])

@@ -16,7 +16,7 @@ LIBPATH = os.path.join(HERE, "libchns.so")
 OK, WNOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 MODEL_CH, MODEL_CH_AC, MODEL_TERNARY = 0, 1, 2
 BLOCK_CH, BLOCK_AC, BLOCK_NS = 0, 1, 2
-OP_M, OP_K, OP_C, OP_CH, OP_AC, OP_X, OP_L, OP_NS = range(8)
+OP_M, OP_K, OP_C, OP_CH, OP_AC, OP_X, OP_L, OP_NS, OP_VX, OP_AP = range(10)
 F64, MIXED = 0, 1
 MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}
 

@@ -24,6 +24,8 @@ namespace {
     }                                                                          \
   } while (0)
 
+#define HIPCHK_VOID(expr) (void)(expr)
+
 #define TRY(expr)              \
   do {                         \
     int rc_ = (expr);          \
@@ -109,6 +111,8 @@ int check_opts(chns_ctx* c, const chns_solve_opts* o) {
 
 // ------------------------------------------------------------------ operators
 
+int form_ternary(chns_ctx* c, hipStream_t s);
+
 // Re-form L = M + tau C, X = tau g K + sqrt(tau g / beta) M and the AC matrix
 // M + tau delta_v K + tau C on every level, with FP32 copies and 1/diag.
 int form_operators(chns_ctx* c, hipStream_t s) {
@@ -132,6 +136,58 @@ int form_operators(chns_ctx* c, hipStream_t s) {
     diag_inverse(L.N, L.diag, L.X.v64, L.X.d64, L.X.d32, s);
     diag_inverse(L.N, L.diag, L.AC.v64, L.AC.d64, L.AC.d32, s);
   }
+  HIPCHK(c, hipGetLastError());
+  if (c->ternary) TRY(form_ternary(c, s));
+  return CHNS_OK;
+}
+
+// Ternary model: velocity blocks A_xx = (rho/tau) M + J + K_xx (and yy) on the
+// P2 level and Galerkin down the P1 levels, the Oseen operator values, and the
+// PCD matrix A_p = (rho/tau) M + eta K + N_p(w) on the finest P1 level.
+int form_ternary(chns_ctx* c, hipStream_t s) {
+  const auto& p = c->prm;
+  const double cm = p.rho / p.tau;
+  c->coefV[0] = cm;
+  c->coefV[1] = 1.5 * p.viscosity;  // the xx/yy forms have a P1 diagonal of 6 eta
+  P2Level& P = c->p2;
+  const int64_t ns2 = P.sell.slots();
+  combine(ns2, cm, P.Mv, 1.0, P.J, 1.0, P.Kxx, P.Vx.v64, P.Vx.v32, s);
+  combine(ns2, cm, P.Mv, 1.0, P.J, 1.0, P.Kyy, P.Vy.v64, P.Vy.v32, s);
+  diag_inverse(P.N4, P.diag, P.Vx.v64, P.Vx.d64, P.Vx.d32, s);
+  diag_inverse(P.N4, P.diag, P.Vy.v64, P.Vy.d64, P.Vy.d32, s);
+  Level& L0 = c->lv[0];
+  galerkin(L0.sell.slots(), P.gptr, P.gsrc, P.gw, P.Vx.v64, L0.Vx.v64, s);
+  galerkin(L0.sell.slots(), P.gptr, P.gsrc, P.gw, P.Vy.v64, L0.Vy.v64, s);
+  for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
+    Level& F = c->lv[l];
+    Level& G = c->lv[l + 1];
+    galerkin(G.sell.slots(), F.gptr, F.gsrc, F.gw, F.Vx.v64, G.Vx.v64, s);
+    galerkin(G.sell.slots(), F.gptr, F.gsrc, F.gw, F.Vy.v64, G.Vy.v64, s);
+  }
+  for (auto& L : c->lv) {
+    const int64_t ns = L.sell.slots();
+    convert<double, float>(ns, L.Vx.v64, L.Vx.v32, s);
+    convert<double, float>(ns, L.Vy.v64, L.Vy.v32, s);
+    diag_inverse(L.N, L.diag, L.Vx.v64, L.Vx.d64, L.Vx.d32, s);
+    diag_inverse(L.N, L.diag, L.Vy.v64, L.Vy.d64, L.Vy.d32, s);
+  }
+  form_ns(c->ns.sell.slots(), c->ns.kind, c->ns.src, cm, P.Mv, P.J, P.Kxx, P.Kxy, P.Kyx, P.Kyy,
+          c->ns.B, c->ns.val, s);
+  combine(L0.sell.slots(), cm, L0.M, p.viscosity, L0.K, 1.0, L0.Cw, L0.Ap.v64, L0.Ap.v32, s);
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
+int assemble_sym_stiffness(chns_ctx* c, hipStream_t s) {
+  P2Level& P = c->p2;
+  const int64_t ns2 = P.sell.slots();
+  double* outs[4] = {P.Kxx, P.Kxy, P.Kyx, P.Kyy};
+  for (double* o : outs) HIPCHK(c, hipMemsetAsync(o, 0, ns2 * sizeof(double), s));
+  MuGrad none{{nullptr, nullptr, nullptr}, 0.0};
+  for (int col = 0; col < 8; ++col)
+    assemble_p2(1, c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
+                c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb, c->prm.viscosity, nullptr, 0.0,
+                4 * int64_t(c->N), none, outs, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -215,11 +271,19 @@ size_t cut_level(chns_ctx* c, const double* coef, double rho_cut) {
   return c->lv.size() - 1;
 }
 
+const double kCoefKp[2] = {0.0, 1.0};
+const double kCoefMp[2] = {1.0, 0.0};
+
 const double* coef_of(chns_ctx* c, OpVals Level::*op) {
   if (op == &Level::L) return c->coefL;
   if (op == &Level::X) return c->coefX;
+  if (op == &Level::Vx || op == &Level::Vy) return c->coefV;
+  if (op == &Level::Kp) return kCoefKp;
+  if (op == &Level::Mp) return kCoefMp;
   return c->coefAC;
 }
+
+bool singular_of(OpVals Level::*op) { return op == &Level::Kp; }
 
 // Chebyshev steps from x = 0 (cur/oth ping-pong so that the result lands in x).
 template <typename T>
@@ -251,9 +315,14 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
   if (l == cut) {
     const double* cf = coef_of(c, op);
     const double nl = L.n;
-    const double rho = 8.0 * cf[1] * nl * nl / cf[0];
+    double lo;
+    if (singular_of(op)) {
+      lo = 0.9 * (1.0 - std::cos(2.0 * M_PI / nl)) / 2.0;  // smallest nonzero eigenvalue of D^-1 K
+    } else {
+      lo = 0.45 / (1.0 + 8.0 * cf[1] * nl * nl / cf[0]);
+    }
     const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
-    cheb_from_zero<T>(L, A, b, x, cheb_coef<T>(0.45 / (1.0 + rho), lmax, std::min(steps, MAXCHEB)), s);
+    cheb_from_zero<T>(L, A, b, x, cheb_coef<T>(lo, lmax, std::min(steps, MAXCHEB)), s);
     return;
   }
   const ChebCoef<T> pre = cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre);
@@ -300,6 +369,110 @@ void mg_solve(chns_ctx* c, OpVals Level::*op, const T* b, T* x, const chns_solve
   }
 }
 
+template <typename T> struct SelP2;
+template <> struct SelP2<double> {
+  static const double* v(const OpVals& o) { return o.v64; }
+  static const double* d(const OpVals& o) { return o.d64; }
+  static double* t(P2Level& L) { return L.t64; }
+  static double* r(P2Level& L) { return L.r64; }
+  static double* dd(P2Level& L) { return L.d64; }
+  static double* e(P2Level& L) { return L.e64; }
+  static double* corr(P2Level& L) { return L.c64; }
+  static const double* P(P2Level& L) { return L.P64; }
+  static const double* R(P2Level& L) { return L.R64; }
+};
+template <> struct SelP2<float> {
+  static const float* v(const OpVals& o) { return o.v32; }
+  static const float* d(const OpVals& o) { return o.d32; }
+  static float* t(P2Level& L) { return L.t32; }
+  static float* r(P2Level& L) { return L.r32; }
+  static float* dd(P2Level& L) { return L.d32; }
+  static float* e(P2Level& L) { return L.e32; }
+  static float* corr(P2Level& L) { return L.c32; }
+  static const float* P(P2Level& L) { return L.P32; }
+  static const float* R(P2Level& L) { return L.R32; }
+};
+
+constexpr double LMAX_P2 = 2.3;  // bound of D^-1 A for P2 mass/stiffness combinations
+
+// V-cycle of a velocity block: P2 level on the finest mesh, then the P1
+// hierarchy of the same block (Galerkin through P1 -> P2 interpolation).
+template <typename T>
+void vcycle_p2(chns_ctx* c, OpVals P2Level::*op2, OpVals Level::*op1, const T* b, T* x,
+               const chns_solve_opts& o, hipStream_t s) {
+  P2Level& P = c->p2;
+  Level& L0 = c->lv[0];
+  const OpVals& A = P.*op2;
+  const double lmax = LMAX_P2;
+  const ChebCoef<T> pre = cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre);
+  T* cur = ((o.mg_pre - 1 + o.mg_post) % 2 == 0) ? x : SelP2<T>::t(P);
+  T* oth = (cur == x) ? SelP2<T>::t(P) : x;
+  T* d = SelP2<T>::dd(P);
+  cheb0<T>(P.N4, SelP2<T>::d(A), b, pre.c2[0], d, cur, s);
+  for (int k = 1; k < o.mg_pre; ++k) {
+    sell_op<T, T>(P.d, SelP2<T>::v(A), ST_CHEB, cur, b, SelP2<T>::d(A), d, pre.c1[k], pre.c2[k], oth, s);
+    std::swap(cur, oth);
+  }
+  T* r = SelP2<T>::r(P);
+  sell_op<T, T>(P.d, SelP2<T>::v(A), ST_RESID, cur, b, nullptr, nullptr, T(0), T(0), r, s);
+  spmv<T, T>(P.dR, SelP2<T>::R(P), r, Sel<T>::b(L0), T(1), T(0), s);
+  const size_t cut = cut_level(c, coef_of(c, op1), o.mg_rho_cut);
+  vcycle<T>(c, op1, 0, cut, Sel<T>::b(L0), Sel<T>::x(L0), o, s);
+  spmv<T, T>(P.dP, SelP2<T>::P(P), Sel<T>::x(L0), cur, T(1), T(1), s);
+  if (o.mg_post > 0) {
+    const ChebCoef<T> post = cheb_coef<T>(lmax / 4.0, lmax, o.mg_post);
+    for (int k = 0; k < o.mg_post; ++k) {
+      sell_op<T, T>(P.d, SelP2<T>::v(A), ST_CHEB, cur, b, SelP2<T>::d(A), d, post.c1[k], post.c2[k],
+                    oth, s);
+      std::swap(cur, oth);
+    }
+  }
+}
+
+template <typename T>
+void mg_solve_p2(chns_ctx* c, OpVals P2Level::*op2, OpVals Level::*op1, const T* b, T* x,
+                 const chns_solve_opts& o, hipStream_t s) {
+  P2Level& P = c->p2;
+  vcycle_p2<T>(c, op2, op1, b, x, o, s);
+  for (int k = 1; k < o.mg_cycles; ++k) {
+    T* res = SelP2<T>::e(P);
+    sell_op<T, T>(P.d, SelP2<T>::v(P.*op2), ST_RESID, x, b, nullptr, nullptr, T(0), T(0), res, s);
+    T* corr = SelP2<T>::corr(P);
+    vcycle_p2<T>(c, op2, op1, res, corr, o, s);
+    axpby<T>(P.N4, T(1), corr, T(1), x, s);
+  }
+}
+
+template <typename T>
+void mean_zero(chns_ctx* c, int64_t n, T* x, hipStream_t s) {
+  sum_partial<T>(n, x, c->red, s);
+  sub_mean<T>(n, reduce_blocks(n), c->red, x, s);
+}
+
+// Pressure convection-diffusion Schur approximation: z = M_p^{-1} A_p K_p^{-1} r
+// with K_p^{-1} on mean-zero pressures.
+template <typename T>
+void pcd_apply(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_solve_opts& o,
+               hipStream_t s) {
+  Level& L0 = c->lv[0];
+  const int N = c->N;
+  HIPCHK_VOID(hipMemcpyAsync(tmp1, r, N * sizeof(T), hipMemcpyDeviceToDevice, s));
+  mean_zero<T>(c, N, tmp1, s);
+  mg_solve<T>(c, &Level::Kp, tmp1, tmp2, o, s);
+  mean_zero<T>(c, N, tmp2, s);
+  spmv<T, T>(L0.d, Sel<T>::v(L0.Ap), tmp2, tmp1, T(1), T(0), s);
+  mg_solve<T>(c, &Level::Mp, tmp1, z, o, s);
+}
+
+template <typename T>
+void ns_precond_t(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_solve_opts& o,
+                  hipStream_t s) {
+  const int64_t N4 = 4 * int64_t(c->N);
+  mg_solve_p2<T>(c, &P2Level::Vx, &Level::Vx, r, z, o, s);
+  mg_solve_p2<T>(c, &P2Level::Vy, &Level::Vy, r + N4, z + N4, o, s);
+  pcd_apply<T>(c, r + 2 * N4, z + 2 * N4, tmp1, tmp2, o, s);
+}
+
 template <typename T>
 void ch_precond_t(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_solve_opts& o,
                   hipStream_t s) {
@@ -331,6 +504,14 @@ int precond(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, d
       mg_solve<float>(c, &Level::AC, c->r32, c->z32, o, s);
       convert<float, double>(N, c->z32, z, s);
     }
+  } else if (block == CHNS_BLOCK_NS && c->ternary) {
+    if (o.precision == CHNS_F64) {
+      ns_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
+    } else {
+      convert<double, float>(9 * int64_t(N), r, c->r32, s);
+      ns_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
+      convert<float, double>(9 * int64_t(N), c->z32, z, s);
+    }
   } else {
     return fail(c, CHNS_EUNSUPPORTED, "block not available");
   }
@@ -341,6 +522,7 @@ int precond(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, d
 int64_t block_size(chns_ctx* c, int block) {
   if (block == CHNS_BLOCK_CH) return 2 * int64_t(c->N);
   if (block == CHNS_BLOCK_AC) return c->N;
+  if (block == CHNS_BLOCK_NS) return 9 * int64_t(c->N);
   return 0;
 }
 
@@ -355,6 +537,8 @@ int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha
     ch_block<double, double>(L0.d, Lv, L0.K, L0.M, tg, -tg / beta_, x, alpha, beta, y, s);
   } else if (block == CHNS_BLOCK_AC) {
     spmv<double, double>(L0.d, L0.AC.v64, x, y, alpha, beta, s);
+  } else if (block == CHNS_BLOCK_NS && c->ternary) {
+    spmv<double, double>(c->ns.d, c->ns.val, x, y, alpha, beta, s);
   } else {
     return fail(c, CHNS_EUNSUPPORTED, "block not available");
   }
@@ -435,6 +619,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
     xupdate(n, K.Z, ld, k, K.y, x, s);
     HIPCHK(c, hipGetLastError());
   }
+  if (block == CHNS_BLOCK_NS) mean_zero<double>(c, c->N, x + 8 * int64_t(c->N), s);
   HIPCHK(c, hipEventRecord(c->ev1, s));
   HIPCHK(c, hipEventSynchronize(c->ev1));
   float ms = 0.f;
@@ -447,6 +632,111 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
 }
 
 // ------------------------------------------------------------------ set-up
+
+// Taylor-Hood patterns, slot tables, P2 -> P1 transfer and reference tables.
+int build_ternary_tables(chns_ctx* c) {
+  const int N = c->N;
+  const Elements& E = c->el;
+  P2Level& P = c->p2;
+  NSData& S = c->ns;
+  Level& L0 = c->lv[0];
+  P.N4 = 4 * N;
+  P.csr = p2_pattern(E);
+  P.sell = make_sell(P.csr, 64, 1);
+  TRY(upload_sell(c, P.sell, P.d));
+  TRY(upload(c, &P.diag, P.sell.diag));
+  S.bcsr = b_pattern(E);
+  S.bsell = make_sell(S.bcsr, 64, 1);
+  TRY(upload_sell(c, S.bsell, S.db));
+  S.csr = ns_pattern(E);
+  S.sell = make_sell(S.csr, 64, 1);
+  TRY(upload_sell(c, S.sell, S.d));
+  // element slot tables
+  std::vector<int> s36(size_t(E.ne) * 36), sb(size_t(E.ne) * 36);
+  for (int e = 0; e < E.ne; ++e) {
+    const int* q = &E.p2[e * 6];
+    const int* v = &E.v[e * 3];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) s36[size_t(e) * 36 + i * 6 + j] = P.sell.csr2sell[P.csr.find(q[i], q[j])];
+    for (int a = 0; a < 3; ++a)
+      for (int cc = 0; cc < 2; ++cc)
+        for (int k = 0; k < 6; ++k)
+          sb[size_t(e) * 36 + a * 12 + cc * 6 + k] = S.bsell.csr2sell[S.bcsr.find(v[a], cc * 4 * N + q[k])];
+  }
+  TRY(upload(c, &S.eslot36, s36));
+  TRY(upload(c, &S.eslotb, sb));
+  // Oseen operator slots: source stream and slot
+  std::vector<int8_t> kind(S.sell.slots(), int8_t(-1));
+  std::vector<int> src(S.sell.slots(), 0);
+  for (int r = 0; r < S.csr.nrows; ++r)
+    for (int q = S.csr.rowptr[r]; q < S.csr.rowptr[r + 1]; ++q) {
+      const int col = S.csr.col[q];
+      const int slot = S.sell.csr2sell[q];
+      if (r < 8 * N && col < 8 * N) {
+        const int cr = r / (4 * N), cc = col / (4 * N);
+        kind[slot] = int8_t(2 * cr + cc);
+        src[slot] = P.sell.csr2sell[P.csr.find(r % (4 * N), col % (4 * N))];
+      } else if (r < 8 * N) {  // B^T: velocity row r, pressure column
+        kind[slot] = 4;
+        src[slot] = S.bsell.csr2sell[S.bcsr.find(col - 8 * N, r)];
+      } else {
+        kind[slot] = 4;
+        src[slot] = S.bsell.csr2sell[S.bcsr.find(r - 8 * N, col)];
+      }
+    }
+  TRY(upload(c, &S.kind, kind));
+  TRY(upload(c, &S.src, src));
+  // P1 -> P2 on the finest mesh and the Galerkin map P2 -> P1
+  p2_from_p1_prolongation(c->mesh.n, P.Pcsr, P.Pval);
+  csr_transpose(P.Pcsr, P.Pval, P.Rcsr, P.Rval);
+  P.Psell = make_sell(P.Pcsr, 64, 1);
+  P.Rsell = make_sell(P.Rcsr, 64, 1);
+  TRY(upload_sell(c, P.Psell, P.dP));
+  TRY(upload_sell(c, P.Rsell, P.dR));
+  auto sell_vals = [](const Sell& Sl, const Csr& A, const std::vector<double>& v) {
+    std::vector<double> out(Sl.slots(), 0.0);
+    for (int64_t q = 0; q < A.nnz(); ++q) out[Sl.csr2sell[q]] = v[q];
+    return out;
+  };
+  auto pv = sell_vals(P.Psell, P.Pcsr, P.Pval), rv = sell_vals(P.Rsell, P.Rcsr, P.Rval);
+  std::vector<float> pv32(pv.begin(), pv.end()), rv32(rv.begin(), rv.end());
+  TRY(upload(c, &P.P64, pv));
+  TRY(upload(c, &P.R64, rv));
+  TRY(upload(c, &P.P32, pv32));
+  TRY(upload(c, &P.R32, rv32));
+  std::string gerr;
+  GalerkinMap gm = make_galerkin(P.csr, P.sell, P.Pcsr, P.Pval, L0.csr, L0.sell, &gerr);
+  if (!gerr.empty()) return fail(c, CHNS_EINVAL, gerr);
+  TRY(upload(c, &P.gptr, gm.ptr));
+  TRY(upload(c, &P.gsrc, gm.src));
+  TRY(upload(c, &P.gw, gm.w));
+  // reference tables
+  const P2Tables T = p2_tables();
+  std::vector<double> flat(sizeof(P2Tables) / sizeof(double));
+  std::memcpy(flat.data(), &T, sizeof(P2Tables));
+  TRY(upload(c, &S.tables, flat));
+  const double* b = S.tables;
+  S.tb.MM = b;
+  S.tb.S = b + 36;
+  S.tb.T3 = S.tb.S + 324;
+  S.tb.T2 = S.tb.T3 + 648;
+  S.tb.TB = S.tb.T2 + 108;
+  S.tb.TI = S.tb.TB + 54;
+  // values and vectors
+  const size_t ns2 = P.sell.slots(), n4 = P.N4;
+  for (double** v : {&P.Mv, &P.J, &P.Kxx, &P.Kxy, &P.Kyx, &P.Kyy}) TRY(dalloc(c, v, ns2));
+  for (OpVals* o : {&P.Vx, &P.Vy}) {
+    TRY(dalloc(c, &o->v64, ns2));
+    TRY(dalloc(c, &o->v32, ns2));
+    TRY(dalloc(c, &o->d64, n4));
+    TRY(dalloc(c, &o->d32, n4));
+  }
+  for (double** v : {&P.b64, &P.x64, &P.t64, &P.r64, &P.d64, &P.e64, &P.c64}) TRY(dalloc(c, v, n4));
+  for (float** v : {&P.b32, &P.x32, &P.t32, &P.r32, &P.d32, &P.e32, &P.c32}) TRY(dalloc(c, v, n4));
+  TRY(dalloc(c, &S.B, S.bsell.slots()));
+  TRY(dalloc(c, &S.val, S.sell.slots()));
+  return CHNS_OK;
+}
 
 int build(chns_ctx* c) {
   const int n = c->mesh.n;
@@ -475,6 +765,7 @@ int build(chns_ctx* c) {
             const int q = L.csr.find(c->el.v[e * 3 + a], c->el.v[e * 3 + b]);
             slot[size_t(e) * 9 + a * 3 + b] = L.sell.csr2sell[q];
           }
+      TRY(upload(c, &c->ep1, c->el.v));
       TRY(upload(c, &c->ep2, c->el.p2));
       TRY(upload(c, &c->etype, c->el.type));
       TRY(upload(c, &c->eslot, slot));
@@ -507,6 +798,7 @@ int build(chns_ctx* c) {
     TRY(upload(c, &F.gsrc, gm.src));
     TRY(upload(c, &F.gw, gm.w));
   }
+  if (c->ternary) TRY(build_ternary_tables(c));
   // values and work vectors
   for (auto& L : c->lv) {
     const size_t ns = L.sell.slots(), N = L.N;
@@ -522,19 +814,46 @@ int build(chns_ctx* c) {
       TRY(dalloc(c, &o->d64, N));
       TRY(dalloc(c, &o->d32, N));
     }
+    if (c->ternary) {
+      for (OpVals* o : {&L.Vx, &L.Vy}) {
+        TRY(dalloc(c, &o->v64, ns));
+        TRY(dalloc(c, &o->v32, ns));
+        TRY(dalloc(c, &o->d64, N));
+        TRY(dalloc(c, &o->d32, N));
+      }
+      for (OpVals* o : {&L.Kp, &L.Mp}) {
+        TRY(dalloc(c, &o->d64, N));
+        TRY(dalloc(c, &o->d32, N));
+      }
+      L.Kp.v64 = L.K;
+      L.Kp.v32 = L.K32;
+      L.Mp.v64 = L.M;
+      L.Mp.v32 = L.M32;
+      if (&L == &c->lv[0]) {
+        TRY(dalloc(c, &L.Ap.v64, ns));
+        TRY(dalloc(c, &L.Ap.v32, ns));
+        TRY(dalloc(c, &L.Cw, ns));
+        HIPCHK(c, hipMemset(L.Cw, 0, ns * sizeof(double)));
+      }
+    }
     for (double** v : {&L.b64, &L.x64, &L.t64, &L.r64, &L.e64, &L.d64}) TRY(dalloc(c, v, N));
     for (float** v : {&L.b32, &L.x32, &L.t32, &L.r32, &L.e32, &L.d32}) TRY(dalloc(c, v, N));
     HIPCHK(c, hipMemset(L.C, 0, ns * sizeof(double)));
     HIPCHK(c, hipMemset(L.C32, 0, ns * sizeof(float)));
   }
   const size_t N1 = size_t(c->N), N2 = 2 * N1;
-  for (double** v : {&c->w64a, &c->w64b, &c->w64c, &c->rhs_ac}) TRY(dalloc(c, v, N1));
-  for (double** v : {&c->rhs_ch, &c->xch}) TRY(dalloc(c, v, N2));
-  for (float** v : {&c->r32, &c->z32}) TRY(dalloc(c, v, N2));
+  const size_t NB = c->ternary ? 9 * N1 : N2;  // largest block
+  for (double** v : {&c->w64a, &c->w64b, &c->w64c, &c->w64d, &c->rhs_ac, &c->xac, &c->fs})
+    TRY(dalloc(c, v, N1));
+  for (double** v : {&c->rhs_ch, &c->xch}) TRY(dalloc(c, v, 2 * N2));
+  if (c->ternary)
+    for (double** v : {&c->rhs_ns, &c->xns}) TRY(dalloc(c, v, 9 * N1));
+  for (float** v : {&c->r32, &c->z32}) TRY(dalloc(c, v, NB));
   for (float** v : {&c->w32a, &c->w32b, &c->w32c}) TRY(dalloc(c, v, N1));
+  TRY(dalloc(c, &c->red, 1024));
   // Krylov workspace, sized for the largest block
   Krylov& K = c->kr;
-  K.nmax = int64_t(N2);
+  K.nmax = int64_t(NB);
   TRY(dalloc(c, &K.V, size_t(MAX_RESTART + 1) * K.nmax));
   TRY(dalloc(c, &K.Z, size_t(MAX_RESTART) * K.nmax));
   TRY(dalloc(c, &K.H, size_t(MAX_RESTART + 1) * MAX_RESTART));
@@ -558,6 +877,26 @@ int build(chns_ctx* c) {
   TRY(assemble_base(c, 1, L0.K, nullptr, s));
   galerkin_down(c, &Level::M, &Level::M32, s);
   galerkin_down(c, &Level::K, &Level::K32, s);
+  if (c->ternary) {
+    for (auto& L : c->lv) {
+      diag_inverse(L.N, L.diag, L.K, L.Kp.d64, L.Kp.d32, s);
+      diag_inverse(L.N, L.diag, L.M, L.Mp.d64, L.Mp.d32, s);
+    }
+    P2Level& P = c->p2;
+    const int64_t ns2 = P.sell.slots();
+    HIPCHK(c, hipMemsetAsync(P.Mv, 0, ns2 * sizeof(double), s));
+    HIPCHK(c, hipMemsetAsync(P.J, 0, ns2 * sizeof(double), s));
+    HIPCHK(c, hipMemsetAsync(c->ns.B, 0, c->ns.bsell.slots() * sizeof(double), s));
+    MuGrad none{{nullptr, nullptr, nullptr}, 0.0};
+    double* mo[1] = {P.Mv};
+    for (int col = 0; col < 8; ++col) {
+      const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
+      assemble_p2(0, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb, 0.0,
+                  nullptr, 0.0, 4 * int64_t(c->N), none, mo, s);
+      assemble_b(e0, e1, c->etype, c->ns.eslotb, 1.0 / c->mesh.n, c->ns.tb, c->ns.B, s);
+    }
+    TRY(assemble_sym_stiffness(c, s));
+  }
   TRY(form_operators(c, s));
   HIPCHK(c, hipDeviceSynchronize());
   return CHNS_OK;
@@ -575,6 +914,81 @@ void release(chns_ctx* c) {
 const DSell* op_pattern(chns_ctx* c, int op) {
   if (op >= CHNS_OP_M && op <= CHNS_OP_L) return &c->lv[0].d;
   return nullptr;
+}
+
+// Ternary right-hand sides: two CH phases, AC, and the Oseen momentum rows
+// (rho/tau) M v^k + F^k (pressure rows zero); fs = d f / d phi_s at level k.
+int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_ac, double* rhs_ns,
+                double* fs, hipStream_t s) {
+  const auto& p = c->prm;
+  const int N = c->N;
+  const double beta = p.eps * p.eps;
+  Level& L0 = c->lv[0];
+  rhs_ternary(L0.d, L0.M, in->phi[0], in->phi[1], in->Phi_v, -(p.tau * p.mobility / beta),
+              -p.tau * p.evap_rate, rhs_ch, rhs_ch + 2 * int64_t(N), rhs_ac, fs, s);
+  P2Level& P = c->p2;
+  const int64_t N4 = 4 * int64_t(N);
+  const double cm = p.rho / p.tau;
+  spmv<double, double>(P.d, P.Mv, in->vel, rhs_ns, cm, 0.0, s);
+  spmv<double, double>(P.d, P.Mv, in->vel + N4, rhs_ns + N4, cm, 0.0, s);
+  HIPCHK(c, hipMemsetAsync(rhs_ns + 2 * N4, 0, N * sizeof(double), s));
+  for (int col = 0; col < 8; ++col)
+    korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
+             1.0 / c->mesh.n, c->ns.tb, in->phi[0], in->phi[1], in->Phi_v, beta, beta, N4, rhs_ns, s);
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
+int chns_solve_block(chns_ctx* c, int block, const double* b, double* x, const chns_solve_opts& o,
+                     chns_solve_info** info, int& worst, hipStream_t s);
+
+// One ternary step from `cur` into `out` (all outputs written at the end, so
+// the two field sets may coincide).
+int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
+                 const chns_solve_opts& o, chns_solve_info** info, int& worst, hipStream_t s) {
+  const int N = c->N;
+  const size_t bytes = size_t(N) * sizeof(double);
+  const double beta = c->prm.eps * c->prm.eps;
+  const double* mu3[3] = {cur.mu[0], cur.mu[1], cur.mu[2]};
+  TRY(chns_assemble(c, cur.vel, mu3, s));
+  TRY(ternary_rhs(c, &cur, c->rhs_ch, c->rhs_ac, c->rhs_ns, c->fs, s));
+  double* xch = c->xch;
+  for (int ph = 0; ph < 2; ++ph) {
+    HIPCHK(c, hipMemcpyAsync(xch + 2 * ph * size_t(N), cur.phi[ph], bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(xch + (2 * ph + 1) * size_t(N), cur.mu[ph], bytes, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->xac, cur.Phi_v, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->xns, cur.vel, 8 * bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->xns + 8 * size_t(N), cur.p, bytes, hipMemcpyDeviceToDevice, s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_CH, c->rhs_ch, xch, o, info, worst, s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_CH, c->rhs_ch + 2 * size_t(N), xch + 2 * size_t(N), o, info, worst, s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_AC, c->rhs_ac, c->xac, o, info, worst, s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_NS, c->rhs_ns, c->xns, o, info, worst, s));
+  for (int ph = 0; ph < 2; ++ph) {
+    HIPCHK(c, hipMemcpyAsync(out->phi[ph], xch + 2 * ph * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(out->mu[ph], xch + (2 * ph + 1) * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(out->Phi_v, c->xac, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(out->vel, c->xns, 8 * bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(out->p, c->xns + 8 * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
+  // closure: phi_s = 1 - phi_p - phi_N; mu_s = f_s'(level k) + beta M^{-1} K phi_s
+  Level& L0 = c->lv[0];
+  one_minus_sum(N, out->phi[0], out->phi[1], c->w64d, s);
+  spmv<double, double>(L0.d, L0.K, c->w64d, c->w64a, 1.0, 0.0, s);
+  cheb_from_zero<double>(L0, L0.Mp, c->w64a, c->w64b, cheb_coef<double>(0.49, 2.01, 40), s);
+  axpy_into(N, beta, c->w64b, c->fs, out->mu[2], s);
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
+int chns_solve_block(chns_ctx* c, int block, const double* b, double* x, const chns_solve_opts& o,
+                     chns_solve_info** info, int& worst, hipStream_t s) {
+  chns_solve_info inf{};
+  const int rc = fgmres(c, block, b, x, o, &inf, s);
+  if (rc < 0) return rc;
+  if (rc > worst) worst = rc;
+  if (info && *info) *(*info)++ = inf;
+  return CHNS_OK;
 }
 
 }  // namespace
@@ -613,10 +1027,6 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out
     g_create_err = "unknown model";
     return CHNS_EINVAL;
   }
-  if (mesh->model == CHNS_MODEL_TERNARY) {
-    g_create_err = "the ternary model (Oseen block) is not available in this build";
-    return CHNS_EUNSUPPORTED;
-  }
   chns_ctx tmp;
   if (check_params(&tmp, params) != CHNS_OK) {
     g_create_err = tmp.err;
@@ -625,6 +1035,7 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out
   chns_ctx* c = new chns_ctx();
   c->mesh = *mesh;
   c->prm = *params;
+  c->ternary = (mesh->model == CHNS_MODEL_TERNARY);
   const int rc = build(c);
   if (rc < 0) {
     g_create_err = c->err;
@@ -648,6 +1059,7 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
   if (!c) return CHNS_EINVAL;
   TRY(check_params(c, p));
   c->prm = *p;
+  if (c->ternary) TRY(assemble_sym_stiffness(c, nullptr));
   TRY(form_operators(c, nullptr));
   HIPCHK(c, hipDeviceSynchronize());
   return CHNS_OK;
@@ -655,9 +1067,26 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
 
 int chns_assemble(chns_ctx* c, const double* d_vel, const double* const* d_mu, void* stream) {
   if (!c) return CHNS_EINVAL;
-  (void)d_mu;
+  if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Level& L0 = c->lv[0];
+  if (c->ternary) {
+    P2Level& P = c->p2;
+    MuGrad mg{{nullptr, nullptr, nullptr}, c->prm.alpha};
+    if (d_mu)
+      for (int i = 0; i < 3; ++i) mg.mu[i] = d_mu[i];
+    HIPCHK(c, hipMemsetAsync(P.J, 0, P.sell.slots() * sizeof(double), s));
+    HIPCHK(c, hipMemsetAsync(L0.Cw, 0, L0.sell.slots() * sizeof(double), s));
+    double* jo[1] = {P.J};
+    for (int col = 0; col < 8; ++col) {
+      const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
+      assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb,
+                  0.0, d_vel, c->prm.rho, 4 * int64_t(c->N), mg, jo, s);
+      assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, 1.0 / c->mesh.n, d_vel,
+                       c->prm.rho, 4 * int64_t(c->N), mg, L0.Cw, s);
+    }
+    HIPCHK(c, hipGetLastError());
+  }
   if (d_vel) {
     TRY(assemble_base(c, 2, L0.C, d_vel, s));
     galerkin_down(c, &Level::C, &Level::C32, s);
@@ -682,6 +1111,15 @@ int chns_matrix_shape(chns_ctx* c, int32_t op, int64_t* nrows, int64_t* ncols, i
   } else if (op == CHNS_OP_CH) {
     r = k = 2 * int64_t(L0.N);
     z = 4 * L0.csr.nnz();
+  } else if (op == CHNS_OP_NS && c->ternary) {
+    r = k = 9 * int64_t(L0.N);
+    z = c->ns.csr.nnz();
+  } else if (op == CHNS_OP_VX && c->ternary) {
+    r = k = 4 * int64_t(L0.N);
+    z = c->p2.csr.nnz();
+  } else if (op == CHNS_OP_AP && c->ternary) {
+    r = k = L0.N;
+    z = L0.csr.nnz();
   } else {
     return fail(c, CHNS_EINVAL, "unknown operator");
   }
@@ -705,8 +1143,26 @@ int chns_get_matrix(chns_ctx* c, int32_t op, int32_t* h_rowptr, int32_t* h_col, 
     for (int64_t q = 0; q < nnz; ++q) csrv[q] = sv[L0.sell.csr2sell[q]];
     return CHNS_OK;
   };
+  if ((op == CHNS_OP_NS || op == CHNS_OP_VX) && c->ternary) {
+    const Csr& A = op == CHNS_OP_NS ? c->ns.csr : c->p2.csr;
+    const Sell& Sl = op == CHNS_OP_NS ? c->ns.sell : c->p2.sell;
+    const double* d = op == CHNS_OP_NS ? c->ns.val : c->p2.Vx.v64;
+    if (h_val) {
+      std::vector<double> sv(Sl.slots());
+      HIPCHK(c, hipMemcpyAsync(sv.data(), d, sv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      for (int64_t q = 0; q < A.nnz(); ++q) h_val[q] = sv[Sl.csr2sell[q]];
+    }
+    if (h_rowptr) std::memcpy(h_rowptr, A.rowptr.data(), (A.nrows + 1) * sizeof(int));
+    if (h_col) std::memcpy(h_col, A.col.data(), A.nnz() * sizeof(int));
+    return CHNS_OK;
+  }
   const double* src = nullptr;
   switch (op) {
+    case CHNS_OP_AP:
+      if (!c->ternary) return fail(c, CHNS_EINVAL, "unknown operator");
+      src = L0.Ap.v64;
+      break;
     case CHNS_OP_M: src = L0.M; break;
     case CHNS_OP_K: src = L0.K; break;
     case CHNS_OP_C: src = L0.C; break;
@@ -778,9 +1234,27 @@ int chns_spmv(chns_ctx* c, int32_t op, int32_t precision, double alpha, const vo
     HIPCHK(c, hipGetLastError());
     return CHNS_OK;
   }
+  if ((op == CHNS_OP_NS || op == CHNS_OP_VX) && c->ternary) {
+    if (precision != CHNS_F64 && op == CHNS_OP_NS)
+      return fail(c, CHNS_EUNSUPPORTED, "the Oseen operator is applied in FP64 only");
+    if (op == CHNS_OP_NS)
+      spmv<double, double>(c->ns.d, c->ns.val, (const double*)d_x, (double*)d_y, alpha, beta, s);
+    else if (precision == CHNS_F64)
+      spmv<double, double>(c->p2.d, c->p2.Vx.v64, (const double*)d_x, (double*)d_y, alpha, beta, s);
+    else
+      spmv<float, float>(c->p2.d, c->p2.Vx.v32, (const float*)d_x, (float*)d_y, float(alpha),
+                         float(beta), s);
+    HIPCHK(c, hipGetLastError());
+    return CHNS_OK;
+  }
   const double* v64 = nullptr;
   const float* v32 = nullptr;
   switch (op) {
+    case CHNS_OP_AP:
+      if (!c->ternary) return fail(c, CHNS_EINVAL, "unknown operator");
+      v64 = L0.Ap.v64;
+      v32 = L0.Ap.v32;
+      break;
     case CHNS_OP_M: v64 = L0.M; v32 = L0.M32; break;
     case CHNS_OP_K: v64 = L0.K; v32 = L0.K32; break;
     case CHNS_OP_C: v64 = L0.C; v32 = L0.C32; break;
@@ -803,7 +1277,8 @@ int chns_precond_apply(chns_ctx* c, int32_t block, const chns_solve_opts* opts, 
   TRY(check_opts(c, opts));
   if (!d_r || !d_z) return fail(c, CHNS_EINVAL, "r or z is NULL");
   if (d_r == d_z) return fail(c, CHNS_EINVAL, "r and z must not overlap");
-  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_AC) return fail(c, CHNS_EUNSUPPORTED, "block not available");
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_AC && !(block == CHNS_BLOCK_NS && c->ternary))
+    return fail(c, CHNS_EUNSUPPORTED, "block not available");
   return precond(c, block, *opts, d_r, d_z, static_cast<hipStream_t>(stream));
 }
 
@@ -812,7 +1287,8 @@ int chns_krylov_solve(chns_ctx* c, int32_t block, const double* d_b, double* d_x
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
   if (!d_b || !d_x) return fail(c, CHNS_EINVAL, "b or x is NULL");
-  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_AC) return fail(c, CHNS_EUNSUPPORTED, "block not available");
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_AC && !(block == CHNS_BLOCK_NS && c->ternary))
+    return fail(c, CHNS_EUNSUPPORTED, "block not available");
   if (block == CHNS_BLOCK_AC && c->mesh.model == CHNS_MODEL_CH)
     return fail(c, CHNS_EUNSUPPORTED, "model has no AC block");
   return fgmres(c, block, d_b, d_x, *opts, h_info, static_cast<hipStream_t>(stream));
@@ -822,7 +1298,11 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
                   void* stream) {
   if (!c) return CHNS_EINVAL;
   if (!in || !in->phi[0] || !d_rhs_ch) return fail(c, CHNS_EINVAL, "missing field or output");
-  (void)d_rhs_ns;
+  if (c->ternary) {
+    if (!in->phi[1] || !in->Phi_v || !in->vel || !d_rhs_ac || !d_rhs_ns)
+      return fail(c, CHNS_EINVAL, "the ternary model needs phi[0..1], Phi_v, vel and all outputs");
+    return ternary_rhs(c, in, d_rhs_ch, d_rhs_ac, d_rhs_ns, c->fs, static_cast<hipStream_t>(stream));
+  }
   const bool ac = c->mesh.model == CHNS_MODEL_CH_AC;
   if (ac && !in->Phi_v) return fail(c, CHNS_EINVAL, "model needs Phi_v");
   const auto& p = c->prm;
@@ -842,6 +1322,22 @@ int chns_timestep(chns_ctx* c, const chns_fields* in, const chns_fields* out, in
   const bool ac = c->mesh.model == CHNS_MODEL_CH_AC;
   if (!in->phi[0] || !in->mu[0] || !out->phi[0] || !out->mu[0])
     return fail(c, CHNS_EINVAL, "phi[0] and mu[0] are required");
+  if (c->ternary) {
+    const chns_fields* fs[2] = {in, out};
+    for (const chns_fields* f : fs)
+      if (!f->phi[1] || !f->mu[1] || !f->mu[2] || !f->Phi_v || !f->vel || !f->p)
+        return fail(c, CHNS_EINVAL, "the ternary model needs every field");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int worst = CHNS_OK;
+    chns_fields cur = *in;
+    chns_solve_info* info = h_info;
+    for (int k = 0; k < nsteps; ++k) {
+      TRY(ternary_step(c, cur, out, *opts, &info, worst, s));
+      cur = *out;
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return worst;
+  }
   if (ac && (!in->Phi_v || !out->Phi_v)) return fail(c, CHNS_EINVAL, "model needs Phi_v");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int N = c->N;

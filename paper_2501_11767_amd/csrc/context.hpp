@@ -43,11 +43,52 @@ struct Level {
   float *M32 = nullptr, *K32 = nullptr, *C32 = nullptr;
   // preconditioner operators
   OpVals L, X, AC;
+  // ternary model: velocity blocks (Galerkin from P2), pressure Laplacian and
+  // mass (values = K, M), and on the finest level the PCD matrix A_p and the
+  // P1 convection by the Oseen convecting field
+  OpVals Vx, Vy, Kp, Mp, Ap;
+  double* Cw = nullptr;
   // multigrid work vectors (per precision)
   double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *e64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *t32 = nullptr, *r32 = nullptr, *e32 = nullptr;
   double* d64 = nullptr;  // Chebyshev direction
   float* d32 = nullptr;
+};
+
+// The P2 velocity level on the finest mesh (ternary model).
+struct P2Level {
+  int N4 = 0;
+  Csr csr;
+  Sell sell;
+  DSell d;
+  Csr Pcsr, Rcsr;  // P1 -> P2 on the same mesh, and its transpose
+  std::vector<double> Pval, Rval;
+  Sell Psell, Rsell;
+  DSell dP, dR;
+  double *P64 = nullptr, *R64 = nullptr;
+  float *P32 = nullptr, *R32 = nullptr;
+  int *gptr = nullptr, *gsrc = nullptr;  // Galerkin map P2 -> P1 finest level
+  double* gw = nullptr;
+  int* diag = nullptr;
+  double *Mv = nullptr, *J = nullptr, *Kxx = nullptr, *Kxy = nullptr, *Kyx = nullptr, *Kyy = nullptr;
+  OpVals Vx, Vy;
+  double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *d64 = nullptr,
+         *e64 = nullptr, *c64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr, *t32 = nullptr, *r32 = nullptr, *d32 = nullptr,
+        *e32 = nullptr, *c32 = nullptr;
+};
+
+// Divergence matrix, the Oseen operator and the element slot tables.
+struct NSData {
+  Csr bcsr, csr;
+  Sell bsell, sell;
+  DSell db, d;
+  double *B = nullptr, *val = nullptr;
+  int8_t* kind = nullptr;
+  int* src = nullptr;
+  int *eslot36 = nullptr, *eslotb = nullptr;
+  double* tables = nullptr;
+  DP2Tables tb{};
 };
 
 struct Krylov {
@@ -67,16 +108,22 @@ struct chns_ctx {
   chns_params prm{};
   int N = 0;            // P1 nodes
   bool has_conv = false;
+  bool ternary = false;
+  chns::P2Level p2;
+  chns::NSData ns;
+  double coefV[2] = {1, 0};
   // multigrid: operator coefficients a M + b K for the level cut
   double coefL[2] = {1, 0}, coefX[2] = {1, 0}, coefAC[2] = {1, 0};
   std::vector<chns::Level> lv;
   chns::Elements el;
-  int *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;
+  int *ep1 = nullptr, *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;
   chns::Krylov kr;
   // scratch: FP64 tmp1/tmp2/corr (N each), FP32 r/z (2N each) and
   // tmp1/tmp2/corr (N each), right-hand sides and the CH unknown [phi; mu]
   double *w64a = nullptr, *w64b = nullptr, *w64c = nullptr;
   double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr;
+  double *rhs_ns = nullptr, *xns = nullptr, *xac = nullptr, *fs = nullptr, *w64d = nullptr;
+  double* red = nullptr;  // reduction partials for mean projections
   float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr, *w32c = nullptr;
   std::vector<void*> allocs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -1,6 +1,8 @@
 #include "host_mesh.hpp"
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <numeric>
 
 namespace chns {
@@ -210,6 +212,176 @@ void csr_transpose(const Csr& A, const std::vector<double>& av, Csr& T, std::vec
       T.col[p] = r;
       tv[p] = av[q];
     }
+}
+
+void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val) {
+  const int N = n * n;
+  auto id = [n](int i, int j) { return ((i % n + n) % n) + n * ((j % n + n) % n); };
+  P.nrows = 4 * N;
+  P.ncols = N;
+  P.rowptr.assign(P.nrows + 1, 0);
+  P.col.clear();
+  val.clear();
+  std::vector<std::vector<std::pair<int, double>>> rows(P.nrows);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      rows[id(i, j)].push_back({id(i, j), 1.0});
+      const int d[3][2] = {{1, 0}, {0, 1}, {1, 1}};
+      for (int blk = 0; blk < 3; ++blk) {
+        auto& r = rows[(blk + 1) * N + id(i, j)];
+        r.push_back({id(i, j), 0.5});
+        r.push_back({id(i + d[blk][0], j + d[blk][1]), 0.5});
+      }
+    }
+  for (int r = 0; r < P.nrows; ++r) {
+    auto& row = rows[r];
+    std::sort(row.begin(), row.end());
+    for (auto& e : row) {
+      P.col.push_back(e.first);
+      val.push_back(e.second);
+    }
+    P.rowptr[r + 1] = int(P.col.size());
+  }
+}
+
+Csr p2_pattern(const Elements& E) {
+  const int N = E.n * E.n;
+  return pattern_from_elements(4 * N, 4 * N, E.ne, E.p2.data(), 6, E.p2.data(), 6);
+}
+
+Csr b_pattern(const Elements& E) {
+  const int N = E.n * E.n;
+  std::vector<int> vel(size_t(E.ne) * 12);
+  for (int e = 0; e < E.ne; ++e)
+    for (int k = 0; k < 6; ++k) {
+      vel[size_t(e) * 12 + k] = E.p2[e * 6 + k];
+      vel[size_t(e) * 12 + 6 + k] = 4 * N + E.p2[e * 6 + k];
+    }
+  return pattern_from_elements(N, 8 * N, E.ne, E.v.data(), 3, vel.data(), 12);
+}
+
+Csr ns_pattern(const Elements& E) {
+  // velocity rows couple to both velocity components and to pressure;
+  // pressure rows couple to both velocity components only.
+  const int N = E.n * E.n;
+  std::vector<std::vector<int>> rows(9 * N);
+  for (int e = 0; e < E.ne; ++e) {
+    const int* q = &E.p2[e * 6];
+    const int* v = &E.v[e * 3];
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < 6; ++a) {
+        auto& r = rows[c * 4 * N + q[a]];
+        for (int d = 0; d < 2; ++d)
+          for (int b = 0; b < 6; ++b) r.push_back(d * 4 * N + q[b]);
+        for (int b = 0; b < 3; ++b) r.push_back(8 * N + v[b]);
+      }
+    for (int a = 0; a < 3; ++a) {
+      auto& r = rows[8 * N + v[a]];
+      for (int d = 0; d < 2; ++d)
+        for (int b = 0; b < 6; ++b) r.push_back(d * 4 * N + q[b]);
+    }
+  }
+  Csr A;
+  A.nrows = A.ncols = 9 * N;
+  A.rowptr.assign(A.nrows + 1, 0);
+  for (int r = 0; r < A.nrows; ++r) {
+    auto& v = rows[r];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    A.rowptr[r + 1] = A.rowptr[r] + int(v.size());
+  }
+  for (auto& v : rows) A.col.insert(A.col.end(), v.begin(), v.end());
+  return A;
+}
+
+namespace {
+
+// Polynomials in the barycentrics (l0, l1, l2), integrated over a triangle by
+// int l0^a l1^b l2^c = 2|T| a! b! c! / (a+b+c+2)!.
+using Mono = std::array<int, 3>;
+using Poly = std::map<Mono, double>;
+
+Poly mul(const Poly& p, const Poly& q) {
+  Poly r;
+  for (auto& [mp, cp] : p)
+    for (auto& [mq, cq] : q) r[{mp[0] + mq[0], mp[1] + mq[1], mp[2] + mq[2]}] += cp * cq;
+  return r;
+}
+
+double fact(int k) {
+  double f = 1;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+double integrate(const Poly& p) {  // divided by |T|
+  double s = 0;
+  for (auto& [m, c] : p) s += c * 2.0 * fact(m[0]) * fact(m[1]) * fact(m[2]) / fact(m[0] + m[1] + m[2] + 2);
+  return s;
+}
+
+Poly lam(int a) {
+  Mono m{0, 0, 0};
+  m[a] = 1;
+  return Poly{{m, 1.0}};
+}
+
+}  // namespace
+
+P2Tables p2_tables() {
+  // psi_k and d psi_k / d lambda_a as polynomials
+  Poly psi[6], dpsi[6][3];
+  const int edge[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+  for (int k = 0; k < 3; ++k) {
+    Poly p = mul(lam(k), lam(k));
+    for (auto& t : p) t.second *= 2.0;
+    p[{k == 0, k == 1, k == 2}] -= 1.0;  // 2 l_k^2 - l_k
+    psi[k] = p;
+    for (int a = 0; a < 3; ++a) {
+      Poly d;
+      if (a == k) {
+        d = lam(k);
+        for (auto& t : d) t.second *= 4.0;
+        d[{0, 0, 0}] = -1.0;  // 4 l_k - 1
+      }
+      dpsi[k][a] = d;
+    }
+  }
+  for (int e = 0; e < 3; ++e) {
+    const int k = edge[e][0], l = edge[e][1];
+    Poly p = mul(lam(k), lam(l));
+    for (auto& t : p) t.second *= 4.0;
+    psi[3 + e] = p;
+    for (int a = 0; a < 3; ++a) {
+      Poly d;
+      if (a == k) d = lam(l);
+      if (a == l) d = lam(k);
+      for (auto& t : d) t.second *= 4.0;
+      dpsi[3 + e][a] = d;
+    }
+  }
+  P2Tables T{};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) T.MM[i][j] = integrate(mul(psi[i], psi[j]));
+  for (int i = 0; i < 6; ++i)
+    for (int a = 0; a < 3; ++a)
+      for (int j = 0; j < 6; ++j)
+        for (int b = 0; b < 3; ++b) T.S[i][a][j][b] = integrate(mul(dpsi[i][a], dpsi[j][b]));
+  for (int m = 0; m < 6; ++m)
+    for (int k = 0; k < 6; ++k) {
+      const Poly pk = mul(psi[m], psi[k]);
+      for (int n = 0; n < 6; ++n)
+        for (int a = 0; a < 3; ++a) T.T3[m][k][n][a] = integrate(mul(pk, dpsi[n][a]));
+    }
+  for (int m = 0; m < 6; ++m)
+    for (int n = 0; n < 6; ++n)
+      for (int a = 0; a < 3; ++a) T.T2[m][n][a] = integrate(mul(psi[m], dpsi[n][a]));
+  for (int q = 0; q < 3; ++q)
+    for (int k = 0; k < 6; ++k)
+      for (int a = 0; a < 3; ++a) T.TB[q][k][a] = integrate(mul(lam(q), dpsi[k][a]));
+  for (int k = 0; k < 6; ++k)
+    for (int a = 0; a < 3; ++a) T.TI[k][a] = integrate(dpsi[k][a]);
+  return T;
 }
 
 }  // namespace chns

@@ -74,4 +74,28 @@ GalerkinMap make_galerkin(const Csr& Af, const Sell& Sf, const Csr& P, const std
 // Transpose of a CSR pattern with values.
 void csr_transpose(const Csr& A, const std::vector<double>& av, Csr& T, std::vector<double>& tv);
 
+// P1 on mesh n into P2 on mesh n (vertex nodes copy, edge midpoints average).
+void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val);
+
+// Taylor-Hood patterns on mesh n (N = n^2 vertices, 4N P2 nodes):
+//   scalar P2 (4N x 4N), B (N x 8N: pressure rows, [x; y] velocity columns),
+//   the Oseen operator (9N x 9N: rows/cols [v_x; v_y; p], no p-p block).
+Csr p2_pattern(const Elements& E);
+Csr b_pattern(const Elements& E);
+Csr ns_pattern(const Elements& E);
+
+// Exact integrals over a triangle T divided by |T|, in barycentric form, for
+// the P2 basis psi_k (vertices, then the nodes of edges (1,2), (0,2), (0,1))
+// and the P1 basis lambda_a; dpsi[k][a] = d psi_k / d lambda_a (psi written
+// as a polynomial in the three barycentrics).
+struct P2Tables {
+  double MM[6][6];           // int psi_i psi_j
+  double S[6][3][6][3];      // int dpsi[i][a] dpsi[j][b]
+  double T3[6][6][6][3];     // int psi_m psi_k dpsi[n][a]
+  double T2[6][6][3];        // int psi_m dpsi[n][a]
+  double TB[3][6][3];        // int lambda_q dpsi[k][a]
+  double TI[6][3];           // int dpsi[k][a]
+};
+P2Tables p2_tables();
+
 }  // namespace chns

@@ -99,4 +99,22 @@ __attribute__((visibility("default"))) int chns_probe_prolongation(int nf, int32
   return int(P.nnz());
 }
 
+// P2 reference tables, flattened in declaration order (MM, S, T3, T2, TB, TI).
+__attribute__((visibility("default"))) int chns_probe_p2_tables(double* out) {
+  P2Tables T = p2_tables();
+  std::memcpy(out, &T, sizeof(P2Tables));
+  return int(sizeof(P2Tables) / sizeof(double));
+}
+
+// Taylor-Hood patterns: which = 0 scalar P2, 1 B, 2 Oseen.  Returns nnz; fills
+// rowptr/col when non-null.
+__attribute__((visibility("default"))) int64_t chns_probe_th_pattern(int n, int which, int32_t* rowptr,
+                                                                     int32_t* col) {
+  Elements E = make_elements(n);
+  Csr A = which == 0 ? p2_pattern(E) : which == 1 ? b_pattern(E) : ns_pattern(E);
+  copy_out(A.rowptr, rowptr);
+  copy_out(A.col, col);
+  return A.nnz();
+}
+
 }  // extern "C"

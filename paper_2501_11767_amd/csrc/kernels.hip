@@ -561,6 +561,343 @@ __global__ __launch_bounds__(BS) void k_rhs_binary(int n, const int* __restrict_
   if (rhs_ac) rhs_ac[row] = s_Phi + c_ac * s_fv;
 }
 
+// ------------------------------------------------------------------ Taylor-Hood
+
+template <typename T, typename TV, int MODE>
+__global__ __launch_bounds__(BS) void k_sell_op(int nslices, int nrows, const int* __restrict__ sptr,
+                                                const int* __restrict__ sw,
+                                                const int* __restrict__ col,
+                                                const TV* __restrict__ val,
+                                                const int* __restrict__ perm,
+                                                const T* __restrict__ x, const T* __restrict__ b,
+                                                const T* __restrict__ dinv, T* __restrict__ d,
+                                                T c1, T c2, T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int pos = blk * BS + threadIdx.x;
+  const int slice = pos >> 6, lane = pos & 63;
+  if (slice >= nslices) return;
+  const int row = perm ? perm[pos] : pos;
+  if (row < 0 || row >= nrows) return;
+  const int w = sw[slice];
+  const int base = sptr[slice] + lane;
+  T sum = T(0);
+  for (int k = 0; k < w; ++k) {
+    const int q = base + k * 64;
+    sum += T(val[q]) * x[col[q]];
+  }
+  if (MODE == ST_RESID) {
+    y[row] = b[row] - sum;
+  } else {
+    const T r = dinv[row] * (b[row] - sum);
+    const T dn = (c1 == T(0)) ? c2 * r : c1 * d[row] + c2 * r;
+    d[row] = dn;
+    y[row] = x[row] + dn;
+  }
+}
+
+struct ElemGeo {
+  double area;
+  double gx[3], gy[3];
+};
+
+__device__ __forceinline__ ElemGeo elem_geo(int type, double h) {
+  double x1, y1, x2, y2;
+  if (type == 0) {
+    x1 = h; y1 = 0.0; x2 = h; y2 = h;
+  } else {
+    x1 = h; y1 = h; x2 = 0.0; y2 = h;
+  }
+  const double det = x1 * y2 - x2 * y1;
+  ElemGeo g;
+  g.area = 0.5 * fabs(det);
+  g.gx[1] = y2 / det;  g.gy[1] = -x2 / det;
+  g.gx[2] = -y1 / det; g.gy[2] = x1 / det;
+  g.gx[0] = -g.gx[1] - g.gx[2];
+  g.gy[0] = -g.gy[1] - g.gy[2];
+  return g;
+}
+
+// w_const = -alpha sum_i grad mu_i on the element (P1 gradients are constant).
+__device__ __forceinline__ void mu_const(const MuGrad& mg, const int* vtx, const ElemGeo& g,
+                                         double& wx, double& wy) {
+  wx = 0.0;
+  wy = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    if (!mg.mu[i]) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double m = mg.mu[i][vtx[a]];
+      wx += m * g.gx[a];
+      wy += m * g.gy[a];
+    }
+  }
+  wx *= -mg.alpha;
+  wy *= -mg.alpha;
+}
+
+__global__ __launch_bounds__(BS) void k_assemble_p2(int kind, int e0, int e1,
+                                                    const int* __restrict__ ep1,
+                                                    const int* __restrict__ ep2,
+                                                    const int* __restrict__ etype,
+                                                    const int* __restrict__ eslot, double h,
+                                                    DP2Tables tb, double eta,
+                                                    const double* __restrict__ vel, double wscale,
+                                                    int64_t n2, MuGrad mg, double* o0, double* o1,
+                                                    double* o2, double* o3) {
+  const int e = e0 + blockIdx.x * BS + threadIdx.x;
+  if (e >= e1) return;
+  const ElemGeo g = elem_geo(etype[e], h);
+  const int* slot = eslot + size_t(e) * 36;
+  if (kind == 0) {
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) o0[slot[i * 6 + j]] += g.area * tb.MM[i * 6 + j];
+    return;
+  }
+  if (kind == 1) {
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double gxx = 0, gxy = 0, gyx = 0, gyy = 0;  // G^{cd}[i][j] = int d_c psi_i d_d psi_j
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            const double sv = tb.S[((i * 3 + a) * 6 + j) * 3 + b];
+            gxx += g.gx[a] * g.gx[b] * sv;
+            gxy += g.gx[a] * g.gy[b] * sv;
+            gyx += g.gy[a] * g.gx[b] * sv;
+            gyy += g.gy[a] * g.gy[b] * sv;
+          }
+        const int q = slot[i * 6 + j];
+        o0[q] += eta * g.area * (2.0 * gxx + gyy);
+        o1[q] += eta * g.area * gyx;
+        o2[q] += eta * g.area * gxy;
+        o3[q] += eta * g.area * (gxx + 2.0 * gyy);
+      }
+    return;
+  }
+  // convection J_e[m][n] = |T| sum_a (sum_k (w_k . g_a) T3[m][k][n][a] + (w_c . g_a) T2[m][n][a])
+  double wg[6][3];
+  for (int k = 0; k < 6; ++k) {
+    const int node = ep2[e * 6 + k];
+    const double wx = wscale * vel[node], wy = wscale * vel[n2 + node];
+    for (int a = 0; a < 3; ++a) wg[k][a] = wx * g.gx[a] + wy * g.gy[a];
+  }
+  double cx, cy;
+  mu_const(mg, ep1 + size_t(e) * 3, g, cx, cy);
+  double cg[3];
+  for (int a = 0; a < 3; ++a) cg[a] = cx * g.gx[a] + cy * g.gy[a];
+  for (int m = 0; m < 6; ++m)
+    for (int n = 0; n < 6; ++n) {
+      double acc = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        double t = cg[a] * tb.T2[(m * 6 + n) * 3 + a];
+        for (int k = 0; k < 6; ++k) t += wg[k][a] * tb.T3[((m * 6 + k) * 6 + n) * 3 + a];
+        acc += t;
+      }
+      o0[slot[m * 6 + n]] += g.area * acc;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_assemble_b(int e0, int e1, const int* __restrict__ etype,
+                                                   const int* __restrict__ eslot, double h,
+                                                   DP2Tables tb, double* __restrict__ out) {
+  const int e = e0 + blockIdx.x * BS + threadIdx.x;
+  if (e >= e1) return;
+  const ElemGeo g = elem_geo(etype[e], h);
+  const int* slot = eslot + size_t(e) * 36;  // [q][c*6 + k]
+  for (int q = 0; q < 3; ++q)
+    for (int k = 0; k < 6; ++k) {
+      double bx = 0.0, by = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const double t = tb.TB[(q * 6 + k) * 3 + a];
+        bx += g.gx[a] * t;
+        by += g.gy[a] * t;
+      }
+      out[slot[q * 12 + k]] += -g.area * bx;
+      out[slot[q * 12 + 6 + k]] += -g.area * by;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_assemble_p1_conv(int e0, int e1, const int* __restrict__ ep1,
+                                                         const int* __restrict__ ep2,
+                                                         const int* __restrict__ etype,
+                                                         const int* __restrict__ eslot, double h,
+                                                         const double* __restrict__ vel,
+                                                         double wscale, int64_t n2, MuGrad mg,
+                                                         double* __restrict__ val) {
+  const int e = e0 + blockIdx.x * BS + threadIdx.x;
+  if (e >= e1) return;
+  const ElemGeo g = elem_geo(etype[e], h);
+  double vx[6], vy[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int node = ep2[e * 6 + k];
+    vx[k] = wscale * vel[node];
+    vy[k] = wscale * vel[n2 + node];
+  }
+  double cx, cy;
+  mu_const(mg, ep1 + size_t(e) * 3, g, cx, cy);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // int w lambda_a / |T| = sum_k W[k][a] w_k + w_c / 3
+    double Vx = cx / 3.0, Vy = cy / 3.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double wk = w_p2p1(k, a);
+      Vx += wk * vx[k];
+      Vy += wk * vy[k];
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) val[eslot[e * 9 + a * 3 + b]] += g.area * (Vx * g.gx[b] + Vy * g.gy[b]);
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_korteweg(int e0, int e1, const int* __restrict__ ep1,
+                                                 const int* __restrict__ ep2,
+                                                 const int* __restrict__ etype, double h,
+                                                 DP2Tables tb, const double* __restrict__ php,
+                                                 const double* __restrict__ phn,
+                                                 const double* __restrict__ Phi, double beta,
+                                                 double beta_v, int64_t n2,
+                                                 double* __restrict__ out) {
+  const int e = e0 + blockIdx.x * BS + threadIdx.x;
+  if (e >= e1) return;
+  const ElemGeo g = elem_geo(etype[e], h);
+  const int* v = ep1 + size_t(e) * 3;
+  double gp[2] = {0, 0}, gn[2] = {0, 0}, gv[2] = {0, 0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gp[0] += php[v[a]] * g.gx[a];
+    gp[1] += php[v[a]] * g.gy[a];
+    gn[0] += phn[v[a]] * g.gx[a];
+    gn[1] += phn[v[a]] * g.gy[a];
+    gv[0] += Phi[v[a]] * g.gx[a];
+    gv[1] += Phi[v[a]] * g.gy[a];
+  }
+  const double gs[2] = {-gp[0] - gn[0], -gp[1] - gn[1]};  // solvent = 1 - phi_p - phi_N
+  double G[2][2];
+  for (int c = 0; c < 2; ++c)
+    for (int d = 0; d < 2; ++d)
+      G[c][d] = beta * (gp[c] * gp[d] + gn[c] * gn[d] + gs[c] * gs[d]) + beta_v * gv[c] * gv[d];
+  for (int k = 0; k < 6; ++k) {
+    const int node = ep2[e * 6 + k];
+    for (int c = 0; c < 2; ++c) {
+      double acc = 0.0;
+      for (int a = 0; a < 3; ++a) acc += tb.TI[k * 3 + a] * (g.gx[a] * G[c][0] + g.gy[a] * G[c][1]);
+      out[c * n2 + node] += g.area * acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_form_ns(int64_t n, const int8_t* __restrict__ kind,
+                                                const int* __restrict__ src, double cm,
+                                                const double* __restrict__ Mv,
+                                                const double* __restrict__ J,
+                                                const double* __restrict__ Kxx,
+                                                const double* __restrict__ Kxy,
+                                                const double* __restrict__ Kyx,
+                                                const double* __restrict__ Kyy,
+                                                const double* __restrict__ B,
+                                                double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i >= n) return;
+  const int k = kind[i], s = src[i];
+  double v = 0.0;
+  if (k == 0) v = cm * Mv[s] + J[s] + Kxx[s];
+  else if (k == 1) v = Kxy[s];
+  else if (k == 2) v = Kyx[s];
+  else if (k == 3) v = cm * Mv[s] + J[s] + Kyy[s];
+  else if (k == 4) v = B[s];
+  out[i] = v;
+}
+
+__device__ __forceinline__ void ternary_terms(double pp, double pn, double P, double& dp, double& dn,
+                                              double& fv, double& fs) {
+  const double ps = 1.0 - pp - pn;
+  const double p = P * P * (3.0 - 2.0 * P);
+  dp = (1.0 - p) * (7.0 * pp * pn * pn - 0.6 * ps) + p * (7.0 * pp - 4.0 * ps);
+  dn = (1.0 - p) * (7.0 * pp * pp * pn - 0.6 * ps) + p * (7.0 * pn - 4.0 * ps);
+  const double liq = 3.5 * pp * pp * pn * pn + 0.3 * ps * ps;
+  const double gas = 3.5 * pp * pp + 3.5 * pn * pn + 2.0 * ps * ps;
+  fv = 6.0 * P * (1.0 - P) * (gas - liq);
+  fs = (1.0 - p) * 0.6 * ps + p * 4.0 * ps;
+}
+
+__global__ __launch_bounds__(BS) void k_rhs_ternary(int n, const int* __restrict__ col,
+                                                    const double* __restrict__ Mv,
+                                                    const double* __restrict__ php,
+                                                    const double* __restrict__ phn,
+                                                    const double* __restrict__ Phi, double c_mu,
+                                                    double c_ac, double* __restrict__ rhs_p,
+                                                    double* __restrict__ rhs_n,
+                                                    double* __restrict__ rhs_ac,
+                                                    double* __restrict__ fs_out) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= n) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  double s_p = 0, s_n = 0, s_dp = 0, s_dn = 0, s_P = 0, s_fv = 0;
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const int j = col[base + k * 64];
+    const double m = Mv[base + k * 64];
+    const double a = php[j], b = phn[j], P = Phi[j];
+    double dp, dn, fv, fs;
+    ternary_terms(a, b, P, dp, dn, fv, fs);
+    s_p += m * a;
+    s_n += m * b;
+    s_dp += m * dp;
+    s_dn += m * dn;
+    s_P += m * P;
+    s_fv += m * fv;
+  }
+  rhs_p[row] = s_p;
+  rhs_p[n + row] = c_mu * s_dp;
+  rhs_n[row] = s_n;
+  rhs_n[n + row] = c_mu * s_dn;
+  rhs_ac[row] = s_P + c_ac * s_fv;
+  double dp, dn, fv, fs;
+  ternary_terms(php[row], phn[row], Phi[row], dp, dn, fv, fs);
+  fs_out[row] = fs;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_sum_partial(int64_t n, const T* __restrict__ x,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) acc += double(x[r]);
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_sub_mean(int64_t n, int nblk, const double* __restrict__ part,
+                                                 T* __restrict__ x) {
+  __shared__ double sh[4];
+  __shared__ double mean;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += BS) s += part[b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) mean = s / double(n);
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) x[i] = T(double(x[i]) - mean);
+}
+
+__global__ __launch_bounds__(BS) void k_one_minus_sum(int64_t n, const double* __restrict__ a,
+                                                      const double* __restrict__ b,
+                                                      double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) out[i] = 1.0 - a[i] - b[i];
+}
+
+__global__ __launch_bounds__(BS) void k_axpy_into(int64_t n, double a, const double* __restrict__ x,
+                                                  const double* __restrict__ y,
+                                                  double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + y[i];
+}
+
 }  // namespace
 
 // ================================================================== launchers
@@ -712,6 +1049,86 @@ void rhs_binary(const DSell& A, const double* Mv, const double* phi, const doubl
                      phi, Phi, c_mu, c_ac, rhs_ch, rhs_ac);
 }
 
+template <typename T, typename TV>
+void sell_op(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv, T* d,
+             T c1, T c2, T* y, hipStream_t s) {
+  const int npos = A.nslices * 64;
+  const int* perm = A.uniform ? nullptr : A.perm;
+  if (mode == ST_RESID)
+    hipLaunchKernelGGL((k_sell_op<T, TV, ST_RESID>), dim3(ceil_div(npos, BS)), dim3(BS), 0, s,
+                       A.nslices, A.nrows, A.slice_ptr, A.slice_w, A.col, val, perm, x, b, dinv, d,
+                       c1, c2, y);
+  else
+    hipLaunchKernelGGL((k_sell_op<T, TV, ST_CHEB>), dim3(ceil_div(npos, BS)), dim3(BS), 0, s,
+                       A.nslices, A.nrows, A.slice_ptr, A.slice_w, A.col, val, perm, x, b, dinv, d,
+                       c1, c2, y);
+}
+
+void assemble_p2(int kind, int e0, int e1, const int* ep1, const int* ep2, const int* etype,
+                 const int* eslot36, double h, DP2Tables tb, double eta, const double* vel,
+                 double wscale, int64_t n2, MuGrad mg, double* const* out, hipStream_t s) {
+  if (e1 <= e0) return;
+  hipLaunchKernelGGL(k_assemble_p2, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, kind, e0, e1, ep1,
+                     ep2, etype, eslot36, h, tb, eta, vel, wscale, n2, mg, out[0],
+                     kind == 1 ? out[1] : nullptr, kind == 1 ? out[2] : nullptr,
+                     kind == 1 ? out[3] : nullptr);
+}
+
+void assemble_b(int e0, int e1, const int* etype, const int* eslotb, double h, DP2Tables tb,
+                double* out, hipStream_t s) {
+  if (e1 <= e0) return;
+  hipLaunchKernelGGL(k_assemble_b, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, e0, e1, etype,
+                     eslotb, h, tb, out);
+}
+
+void assemble_p1_conv(int e0, int e1, const int* ep1, const int* ep2, const int* etype,
+                      const int* eslot, double h, const double* vel, double wscale, int64_t n2,
+                      MuGrad mg, double* val, hipStream_t s) {
+  if (e1 <= e0) return;
+  hipLaunchKernelGGL(k_assemble_p1_conv, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, e0, e1, ep1,
+                     ep2, etype, eslot, h, vel, wscale, n2, mg, val);
+}
+
+void korteweg(int e0, int e1, const int* ep1, const int* ep2, const int* etype, double h,
+              DP2Tables tb, const double* php, const double* phn, const double* Phi, double beta,
+              double beta_v, int64_t n2, double* out, hipStream_t s) {
+  if (e1 <= e0) return;
+  hipLaunchKernelGGL(k_korteweg, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, e0, e1, ep1, ep2,
+                     etype, h, tb, php, phn, Phi, beta, beta_v, n2, out);
+}
+
+void form_ns(int64_t nslots, const int8_t* kind, const int* src, double cm, const double* Mv,
+             const double* J, const double* Kxx, const double* Kxy, const double* Kyx,
+             const double* Kyy, const double* B, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_form_ns, dim3(ceil_div(nslots, BS)), dim3(BS), 0, s, nslots, kind, src, cm,
+                     Mv, J, Kxx, Kxy, Kyx, Kyy, B, out);
+}
+
+void rhs_ternary(const DSell& A, const double* Mv, const double* php, const double* phn,
+                 const double* Phi, double c_mu, double c_ac, double* rhs_p, double* rhs_n,
+                 double* rhs_ac, double* fs, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_ternary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col, Mv,
+                     php, phn, Phi, c_mu, c_ac, rhs_p, rhs_n, rhs_ac, fs);
+}
+
+template <typename T>
+void sum_partial(int64_t n, const T* x, double* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_sum_partial<T>), dim3(reduce_blocks(n)), dim3(BS), 0, s, n, x, part);
+}
+
+template <typename T>
+void sub_mean(int64_t n, int nblk, const double* part, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_sub_mean<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, nblk, part, x);
+}
+
+void one_minus_sum(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_one_minus_sum, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, a, b, out);
+}
+
+void axpy_into(int64_t n, double a, const double* x, const double* y, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_into, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, a, x, y, out);
+}
+
 // explicit instantiations
 template void spmv<double, double>(const DSell&, const double*, const double*, double*, double,
                                    double, hipStream_t);
@@ -739,5 +1156,13 @@ template void axpby<double>(int64_t, double, const double*, double, double*, hip
 template void axpby<float>(int64_t, float, const float*, float, float*, hipStream_t);
 template void convert<double, float>(int64_t, const double*, float*, hipStream_t);
 template void convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template void sell_op<double, double>(const DSell&, const double*, int, const double*, const double*,
+                                      const double*, double*, double, double, double*, hipStream_t);
+template void sell_op<float, float>(const DSell&, const float*, int, const float*, const float*,
+                                    const float*, float*, float, float, float*, hipStream_t);
+template void sum_partial<double>(int64_t, const double*, double*, hipStream_t);
+template void sum_partial<float>(int64_t, const float*, double*, hipStream_t);
+template void sub_mean<double>(int64_t, int, const double*, double*, hipStream_t);
+template void sub_mean<float>(int64_t, int, const double*, float*, hipStream_t);
 
 }  // namespace chns

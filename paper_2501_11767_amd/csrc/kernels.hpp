@@ -113,4 +113,73 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
                 double c_mu, double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s);
 
+// ------------------------------------------------------------ Taylor-Hood / ternary
+
+// General SELL operator forms (any pattern): ST_RESID and ST_CHEB as in stencil().
+template <typename T, typename TV>
+void sell_op(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv, T* d,
+             T c1, T c2, T* y, hipStream_t s);
+
+// Device copy of the exact P2 reference tables (see host_mesh.hpp).
+struct DP2Tables {
+  const double* MM;   // [6][6]
+  const double* S;    // [6][3][6][3]
+  const double* T3;   // [6][6][6][3]
+  const double* T2;   // [6][6][3]
+  const double* TB;   // [3][6][3]
+  const double* TI;   // [6][3]
+};
+
+// Per-element gradient sources for the constant part of the convecting field
+// w = rho v - alpha sum_i grad mu_i (mu: up to 3 P1 fields, may be null).
+struct MuGrad {
+  const double* mu[3];
+  double alpha;
+};
+
+// P2 element scatter (one colour [e0, e1)).  kind 0: mass into out[0];
+// kind 1: symmetric-gradient blocks eta (2G^xx + G^yy), eta G^yx, eta G^xy,
+// eta (G^xx + 2G^yy) into out[0..3]; kind 2: convection by w = wscale * vel +
+// w_const(mu) into out[0].  eslot36: 36 P2 SELL slots per element.
+void assemble_p2(int kind, int e0, int e1, const int* ep1, const int* ep2, const int* etype,
+                 const int* eslot36, double h, DP2Tables tb, double eta, const double* vel,
+                 double wscale, int64_t n2, MuGrad mg, double* const* out, hipStream_t s);
+// B_e[q][c,k] = -int d_c psi_k lambda_q into the B SELL (36 slots per element).
+void assemble_b(int e0, int e1, const int* etype, const int* eslotb, double h, DP2Tables tb,
+                double* out, hipStream_t s);
+// P1 convection by w = wscale * vel + w_const(mu) (kind-2 P1 assembly with a
+// constant part), into a P1 SELL value array.
+void assemble_p1_conv(int e0, int e1, const int* ep1, const int* ep2, const int* etype,
+                      const int* eslot, double h, const double* vel, double wscale, int64_t n2,
+                      MuGrad mg, double* val, hipStream_t s);
+// Korteweg load F_(c,k) += int G : grad(psi_k e_c), G = beta sum over
+// phi_p, phi_N, phi_s = 1 - phi_p - phi_N of grad phi (x) grad phi, plus
+// beta_v grad Phi (x) grad Phi; out has 2 x n2 entries.
+void korteweg(int e0, int e1, const int* ep1, const int* ep2, const int* etype, double h,
+              DP2Tables tb, const double* php, const double* phn, const double* Phi, double beta,
+              double beta_v, int64_t n2, double* out, hipStream_t s);
+
+// Oseen operator values from the streams: kind 0 cm Mv + J + Kxx, 1 Kxy,
+// 2 Kyx, 3 cm Mv + J + Kyy (src: P2 slot), 4 B (src: B slot), -1 zero.
+void form_ns(int64_t nslots, const int8_t* kind, const int* src, double cm, const double* Mv,
+             const double* J, const double* Kxx, const double* Kxy, const double* Kyx,
+             const double* Kyy, const double* B, double* out, hipStream_t s);
+
+// Right-hand sides of the ternary model (fitted quartic, air = 0, solvent
+// eliminated), P1 pattern of M: rhs_p = [M phi_p; c_mu M f'_p], rhs_n likewise,
+// rhs_ac = M Phi + c_ac M f_v; fs = d f / d phi_s at the nodes (for the closure).
+void rhs_ternary(const DSell& A, const double* Mv, const double* php, const double* phn,
+                 const double* Phi, double c_mu, double c_ac, double* rhs_p, double* rhs_n,
+                 double* rhs_ac, double* fs, hipStream_t s);
+
+// Mean-zero projection: partial sums (double) then x -= sum / n.
+template <typename T>
+void sum_partial(int64_t n, const T* x, double* part, hipStream_t s);
+template <typename T>
+void sub_mean(int64_t n, int nblk, const double* part, T* x, hipStream_t s);
+
+// Elementwise helpers of the ternary closure.
+void one_minus_sum(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
+void axpy_into(int64_t n, double a, const double* x, const double* y, double* out, hipStream_t s);
+
 }  // namespace chns

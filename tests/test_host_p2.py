@@ -1,0 +1,152 @@
+"""CPU checks of the Taylor-Hood host tables (no GPU needed).
+
+The assembly kernels for the velocity/pressure matrices evaluate element
+matrices from exact barycentric integral tables built on the host with the
+monomial formula.  Here the tables are checked against the oracle's
+quadrature, and a numpy re-enactment of the kernels' element formulas is
+scattered and compared with the oracle's assembled P2 mass, symmetric
+stiffness, convection, divergence and Korteweg load; the Taylor-Hood sparsity
+patterns are compared with the element connectivity.
+"""
+import ctypes as ct
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fem
+
+PROBE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                     "paper_2501_11767_amd", "libchns_hostprobe.so")
+
+
+@pytest.fixture(scope="module")
+def probe():
+    if not os.path.exists(PROBE):
+        pytest.skip("host probe library not built")
+    L = ct.CDLL(PROBE)
+    L.chns_probe_th_pattern.restype = ct.c_int64
+    return L
+
+
+def tables(probe):
+    out = np.zeros(36 + 324 + 648 + 108 + 54 + 18)
+    k = probe.chns_probe_p2_tables(out.ctypes.data_as(ct.c_void_p))
+    assert k == len(out)
+    o = 0
+    res = {}
+    for name, shape in (("MM", (6, 6)), ("S", (6, 3, 6, 3)), ("T3", (6, 6, 6, 3)), ("T2", (6, 6, 3)),
+                        ("TB", (3, 6, 3)), ("TI", (6, 3))):
+        sz = int(np.prod(shape))
+        res[name] = out[o:o + sz].reshape(shape)
+        o += sz
+    return res
+
+
+def test_tables_match_quadrature(probe):
+    T = tables(probe)
+    lam = fem.QP
+    psi = fem.p2_basis(lam)
+    dps = fem.p2_basis_dlam(lam)  # (q, k, a)
+    w = fem.QW
+    assert np.allclose(T["MM"], np.einsum("q,qi,qj->ij", w, psi, psi), atol=1e-15)
+    assert np.allclose(T["S"], np.einsum("q,qia,qjb->iajb", w, dps, dps), atol=1e-14)
+    assert np.allclose(T["T3"], np.einsum("q,qm,qk,qna->mkna", w, psi, psi, dps), atol=1e-15)
+    assert np.allclose(T["T2"], np.einsum("q,qm,qna->mna", w, psi, dps), atol=1e-15)
+    assert np.allclose(T["TB"], np.einsum("q,qs,qka->ska", w, lam, dps), atol=1e-15)
+    assert np.allclose(T["TI"], np.einsum("q,qka->ka", w, dps), atol=1e-15)
+    # textbook P2 mass matrix times 180/|T| (edge node e opposite vertex e)
+    ref = np.array([[6, -1, -1, -4, 0, 0], [-1, 6, -1, 0, -4, 0], [-1, -1, 6, 0, 0, -4],
+                    [-4, 0, 0, 32, 16, 16], [0, -4, 0, 16, 32, 16], [0, 0, -4, 16, 16, 32]], float)
+    assert np.allclose(T["MM"] * 180, ref, atol=1e-12)
+
+
+def _geom(n, ty):
+    h = 1.0 / n
+    x1, y1, x2, y2 = (h, 0.0, h, h) if ty == 0 else (h, h, 0.0, h)
+    det = x1 * y2 - x2 * y1
+    g = np.zeros((3, 2))
+    g[1] = (y2 / det, -x2 / det)
+    g[2] = (-y1 / det, x1 / det)
+    g[0] = -g[1] - g[2]
+    return 0.5 * abs(det), g
+
+
+def test_element_formulas_reassemble_oracle(probe):
+    """Kernel formulas: M_e = |T| MM; G^{cd}_e = |T| sum_ab g_a^c g_b^d S;
+    J_e[m][n] = |T| sum_a (sum_k (w_k . g_a) T3[m][k][n][a] + (w_c . g_a) T2[m][n][a]);
+    B_e[q][c,k] = -|T| sum_a g_a^c TB[q][k][a]; F_e[c][k] = |T| sum_a (G g_a)_c TI[k][a]."""
+    T = tables(probe)
+    n = 8
+    N = n * n
+    m = fem.Mesh(n)
+    from paper_2501_11767_amd import inputs
+    w = inputs.stream_velocity(n, 4, amp=0.3)
+    wc = np.random.default_rng(0).standard_normal((m.ne, 2))
+    grads = [np.random.default_rng(s).standard_normal((m.ne, 2)) for s in (1, 2)]
+    eta = 0.7
+    blocks = {k: np.zeros((4 * N, 4 * N)) for k in ("M", "J", "xx", "xy", "yx", "yy")}
+    B = np.zeros((N, 8 * N))
+    F = np.zeros(8 * N)
+    for e in range(m.ne):
+        ty = 0 if np.allclose(m.xy[e, 1] - m.xy[e, 0], [m.h, 0]) else 1
+        area, g = _geom(n, ty)
+        q = m.tri2[e]
+        G = {(c, d): area * np.einsum("a,b,iajb->ij", g[:, c], g[:, d], T["S"]) for c in range(2) for d in range(2)}
+        Me = area * T["MM"]
+        wk = np.stack([w[0][q], w[1][q]], 1)  # (6, 2)
+        wg = wk @ g.T  # (k, a): w_k . g_a
+        Je = area * (np.einsum("ka,mkna->mn", wg, T["T3"]) + np.einsum("a,mna->mn", g @ wc[e], T["T2"]))
+        Ke = {"xx": eta * (2 * G[0, 0] + G[1, 1]), "xy": eta * G[1, 0], "yx": eta * G[0, 1],
+              "yy": eta * (G[0, 0] + 2 * G[1, 1])}
+        ix = np.ix_(q, q)
+        blocks["M"][ix] += Me
+        blocks["J"][ix] += Je
+        for k, v in Ke.items():
+            blocks[k][ix] += v
+        for c in range(2):
+            Be = -area * np.einsum("a,ska->sk", g[:, c], T["TB"])
+            B[np.ix_(m.tri[e], c * 4 * N + q)] += Be
+        Gt = sum(np.outer(gr[e], gr[e]) for gr in grads)
+        for c in range(2):
+            F[c * 4 * N + q] += area * np.einsum("ka,a->k", T["TI"], g @ Gt[c])
+    assert np.allclose(blocks["M"], fem.p2_mass(m).toarray(), atol=1e-15)
+    assert np.allclose(blocks["J"], fem.p2_convection(m, w, wc).toarray(), atol=1e-13)
+    Ks = fem.p2_sym_stiffness(m, eta).toarray()
+    assert np.allclose(blocks["xx"], Ks[:4 * N, :4 * N], atol=1e-12)
+    assert np.allclose(blocks["xy"], Ks[:4 * N, 4 * N:], atol=1e-12)
+    assert np.allclose(blocks["yx"], Ks[4 * N:, :4 * N], atol=1e-12)
+    assert np.allclose(blocks["yy"], Ks[4 * N:, 4 * N:], atol=1e-12)
+    assert np.allclose(B, fem.divergence_matrix(m).toarray(), atol=1e-13)
+    assert np.allclose(F, fem.korteweg_load(m, grads, [1.0, 1.0]), atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_th_patterns(probe, n):
+    N = n * n
+    m = fem.Mesh(n)
+    for which, shape in ((0, (4 * N, 4 * N)), (1, (N, 8 * N)), (2, (9 * N, 9 * N))):
+        nnz = probe.chns_probe_th_pattern(n, which, None, None)
+        rp = np.zeros(shape[0] + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        probe.chns_probe_th_pattern(n, which, rp.ctypes.data_as(ct.c_void_p), col.ctypes.data_as(ct.c_void_p))
+        got = sp.csr_matrix((np.ones(nnz), col, rp), shape=shape)
+        # expected: node pairs sharing a triangle
+        Mv = fem.p2_mass(m)
+        if which == 0:
+            ref = Mv
+        else:
+            Bm = fem.divergence_matrix(m)
+            if which == 1:
+                ref = Bm
+            else:
+                vv = sp.bmat([[Mv, Mv], [Mv, Mv]])
+                ref = sp.bmat([[vv, Bm.T], [Bm, None]]).tocsr()
+        ref = sp.csr_matrix((np.ones(ref.nnz), ref.indices, ref.indptr), shape=shape)
+        ref.sum_duplicates()
+        assert (got != ref).nnz == 0
+        if which == 0:
+            assert nnz == 46 * N
+        if which == 1:
+            assert nnz == 38 * N
