@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--dry-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -140,6 +141,40 @@ def cpu_baseline(cfg, n, tau, budget_s=20.0):
                        f"after {setup:.1f} s of set-up, FP64, 1 thread")
 
 
+def dry_section(chns, steps):
+    """The full coupled drying step (two CH phases, AC, Taylor-Hood Oseen) on the
+    periodic 256 x 256 mesh in plain FP64: ms per coupled step and FGMRES
+    iterations per solve.  mu^0 = 0 (only an initial guess and the alpha-scaled
+    convecting term; alpha = 1e-8)."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    cfg = inputs.CONFIGS["dry256"]
+    n = cfg["n"]
+    N = n * n
+    ctx = chns.Context(n, "ternary", eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"],
+                       evap_rate=cfg["evap_rate"], viscosity=cfg["viscosity"], alpha=1e-8, rho=1.0)
+    st = inputs.initial_state(n, "ternary", cfg["mean"], cfg["seed"])
+    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
+    fld = dict(phi=[dev(st["phi"][0]), dev(st["phi"][1])], mu=[z(), z(), z()],
+               Phi_v=dev(st["Phi_v"]), vel=dev(st["vel"].ravel()), p=dev(st["p"]))
+    f = ctx.fields(**fld)
+    opts = chns.default_opts(rtol=1e-8, precision=chns.F64, maxiter=1000)
+    ctx.timestep(f, f, 1, opts)  # warm-up step
+    torch.cuda.synchronize()
+    walls, its = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rc, inf = ctx.timestep(f, f, 1, opts)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        its.append([i["iters"] for i in inf])
+    ctx.close()
+    return dict(workload=f"dry256: ternary CH + AC + Taylor-Hood Oseen step, periodic {n}x{n} "
+                         f"({2 * 2 * N} CH + {N} AC + {9 * N} NS unknowns), FP64, rtol 1e-8",
+                ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
+                iters_ch_p_ch_n_ac_ns=its, steps=steps)
+
+
 def oracle_errors(cfg, n, st0, sweep, sweep_fields):
     """CPU leg: the oracle's exact solve of each swept step (convection-free
     periodic systems, one 2x2 solve per Fourier mode) and the relative error
@@ -221,6 +256,7 @@ def main():
                                  converged=bool(inf[0]["converged"] and inf[1]["converged"]))
             sweep.append(row)
         ctx.set_params(**p)
+    dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, n, args.tau)
@@ -254,6 +290,7 @@ def main():
         "fp64": res["fp64"],
         "kernels": kern,
         "sweep": sweep,
+        "dry256": dry,
     }
     ctx.close()
     print(json.dumps(line))

@@ -201,7 +201,10 @@ class Context:
 
     @staticmethod
     def fields(phi=(), mu=(), Phi_v=None, vel=None, p=None) -> Fields:
+        """Field set of device pointers; the tensors stay referenced by the
+        returned structure so they outlive the calls that use it."""
         f = Fields()
+        f._keep = (tuple(phi), tuple(mu), Phi_v, vel, p)
         for i, t in enumerate(phi):
             f.phi[i] = t.data_ptr()
         for i, t in enumerate(mu):
