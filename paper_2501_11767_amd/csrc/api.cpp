@@ -567,6 +567,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   norm_finish(nblk, K.nrm_part, K.scal, nullptr, m, s);
   TRY(read_scal(c, s, 3));
   inf.bnorm = K.host[0];
+  if (!std::isfinite(inf.bnorm)) return fail(c, CHNS_EINVAL, "right-hand side is not finite");
   const double tol = std::fmax(o.rtol * inf.bnorm, o.atol);
   int iters = 0;
   bool first = true;

@@ -218,6 +218,11 @@ def test_krylov_maxiter_reports_no_convergence(chns):
     assert info["converged"] == 1 and info["iters"] == 0
     with pytest.raises(chns.ChnsError):
         ctx.solve(chns.BLOCK_AC, b, x)  # the CH-only model has no AC block
+    # a non-finite right-hand side is an error, not a vacuous convergence
+    bad = b.clone()
+    bad[5] = float("inf")
+    with pytest.raises(chns.ChnsError):
+        ctx.solve(chns.BLOCK_CH, bad, x.zero_())
     ctx.close()
 
 
