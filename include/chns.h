@@ -233,6 +233,45 @@ CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fiel
 /* Message of the last error on this context (never NULL). */
 CHNS_API const char* chns_last_error(const chns_ctx* ctx);
 
+/* ---------------------------------------------------------------- batched form
+ * Many independent instances of the CH + AC model (CHNS_MODEL_CH_AC, v = 0),
+ * each with its own mesh size and parameters, advanced together: every stage
+ * of a step (right-hand sides, operator products, multigrid sweeps, Krylov
+ * reductions) is one launch covering all instances.  Fields are packed: the
+ * nodes of instance i occupy [off[i], off[i+1]) of each field array
+ * (off from chns_batch_offsets, off[i+1] - off[i] = n_i^2). */
+typedef struct chns_batch chns_batch;
+
+/* count instances with sizes h_n[i] (multiples of 32 in 32..2048) and
+ * parameters h_params[i].  Synchronising.  *out is NULL on failure. */
+CHNS_API int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_params,
+                               chns_batch** out);
+CHNS_API int chns_batch_destroy(chns_batch* b);
+/* h_offsets[count + 1]: node offsets of the instances in the packed fields. */
+CHNS_API int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets);
+/* Advance all instances nsteps steps in place (d_phi, d_mu, d_Phi packed,
+ * FP64).  Each block (the stacked CH blocks, then the stacked AC matrices) is
+ * solved by FGMRES with per-instance Krylov scalars on the device and a fixed
+ * budget of ceil(maxiter / restart) restart cycles; an instance stops updating
+ * once its true or estimated residual meets its own tolerance.  opts->mg_cycles
+ * must be 1.  use_graph != 0: the nsteps steps are captured into a hipGraph on
+ * a (non-default) stream the first time these arguments are seen and replayed
+ * afterwards; otherwise the steps run eagerly and stop the restart loop early
+ * once every instance has converged.  h_iters (2*count, may be NULL): Arnoldi
+ * steps of the last step, CH then AC; h_conv (2*count, may be NULL): 1 where
+ * the recomputed true residual met the tolerance; h_ms: wall time.
+ * Returns CHNS_WNOCONV if any instance did not converge.  Synchronising. */
+CHNS_API int chns_batch_timestep(chns_batch* b, double* d_phi, double* d_mu, double* d_Phi,
+                                 int32_t nsteps, const chns_solve_opts* opts, int32_t use_graph,
+                                 int32_t* h_iters, int32_t* h_conv, double* h_ms, void* stream);
+/* Autotuner: time the batched smoothing kernel on every level in launch shapes
+ * rows-per-thread {1, 2, 4} x workgroup {128, 256, 512, 1024} and keep the
+ * fastest per level.  cache_path (may be NULL): a text file "gfx950" followed
+ * by "rows rpt block" lines, read when present (cached levels are not timed)
+ * and rewritten with the chosen shapes.  Synchronising. */
+CHNS_API int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream);
+CHNS_API const char* chns_batch_last_error(const chns_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

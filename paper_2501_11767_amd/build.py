@@ -26,12 +26,13 @@ FLAGS = [
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]
-SOURCES = ["kernels.hip", "api.cpp", "host_mesh.cpp"]
+SOURCES = ["kernels.hip", "kernels_batch.hip", "api.cpp", "batch.cpp", "host_mesh.cpp"]
+HIP_LANG = {"kernels.hip", "kernels_batch.hip", "api.cpp", "batch.cpp"}
 
 
 def _compile(src: str) -> str:
     out = os.path.join(BUILD, os.path.basename(src) + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") or src == "api.cpp" else []
+    lang = ["-x", "hip"] if src in HIP_LANG else []
     cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

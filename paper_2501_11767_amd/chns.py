@@ -24,6 +24,8 @@ EXPORTS = [
     "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble",
     "chns_matrix_shape", "chns_get_matrix", "chns_spmv", "chns_precond_apply",
     "chns_krylov_solve", "chns_step_rhs", "chns_timestep", "chns_last_error",
+    "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
+    "chns_batch_tune", "chns_batch_last_error",
 ]
 
 
@@ -91,8 +93,16 @@ def lib():
                                 ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
     L.chns_last_error.argtypes = [vp]
     L.chns_last_error.restype = ct.c_char_p
+    L.chns_batch_create.argtypes = [i32, vp, vp, ct.POINTER(vp)]
+    L.chns_batch_destroy.argtypes = [vp]
+    L.chns_batch_offsets.argtypes = [vp, vp]
+    L.chns_batch_timestep.argtypes = [vp, vp, vp, vp, i32, ct.POINTER(SolveOpts), i32, vp, vp,
+                                      ct.POINTER(ct.c_double), vp]
+    L.chns_batch_tune.argtypes = [vp, ct.c_char_p, vp]
+    L.chns_batch_last_error.argtypes = [vp]
+    L.chns_batch_last_error.restype = ct.c_char_p
     for name in EXPORTS:
-        if name not in ("chns_default_opts", "chns_last_error"):
+        if name not in ("chns_default_opts", "chns_last_error", "chns_batch_last_error"):
             getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -226,3 +236,62 @@ class Context:
         rc = self._check(self.L.chns_timestep(self.h, ct.byref(fin), ct.byref(fout), nsteps,
                                               ct.byref(o), infos, _stream()))
         return rc, [i.as_dict() for i in infos]
+
+
+class Batch:
+    """Owns a chns_batch: independent CH + AC instances advanced together."""
+
+    def __init__(self, sizes, params):
+        import numpy as np
+        self.L = lib()
+        self.count = len(sizes)
+        self.sizes = [int(n) for n in sizes]
+        n = (ct.c_int32 * self.count)(*self.sizes)
+        full = []
+        for p in params:
+            q = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.0, viscosity=1.0, alpha=0.0, rho=1.0)
+            q.update(p)
+            full.append(Params(**q))
+        arr = (Params * self.count)(*full)
+        h = ct.c_void_p()
+        rc = self.L.chns_batch_create(self.count, ct.cast(n, ct.c_void_p), ct.cast(arr, ct.c_void_p),
+                                      ct.byref(h))
+        if rc != OK:
+            raise ChnsError(rc, self.L.chns_batch_last_error(None).decode())
+        self.h = h
+        off = np.zeros(self.count + 1, dtype=np.int64)
+        self.L.chns_batch_offsets(self.h, off.ctypes.data_as(ct.c_void_p))
+        self.offsets = off
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.chns_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise ChnsError(rc, self.L.chns_batch_last_error(self.h).decode())
+        return rc
+
+    def tune(self, cache_path=None, stream=None):
+        s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+        self._check(self.L.chns_batch_tune(self.h, cache_path.encode() if cache_path else None, s))
+
+    def timestep(self, phi, mu, Phi, nsteps=1, opts=None, use_graph=False, stream=None):
+        import numpy as np
+        o = opts or default_opts()
+        it = np.zeros(2 * self.count, dtype=np.int32)
+        cv = np.zeros(2 * self.count, dtype=np.int32)
+        ms = ct.c_double()
+        s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+        rc = self._check(self.L.chns_batch_timestep(
+            self.h, _ptr(phi), _ptr(mu), _ptr(Phi), nsteps, ct.byref(o), int(use_graph),
+            it.ctypes.data_as(ct.c_void_p), cv.ctypes.data_as(ct.c_void_p), ct.byref(ms), s))
+        return rc, dict(iters_ch=it[:self.count], iters_ac=it[self.count:], conv_ch=cv[:self.count],
+                        conv_ac=cv[self.count:], ms=ms.value)

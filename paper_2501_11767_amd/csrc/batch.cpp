@@ -1,0 +1,910 @@
+// Batched form: many independent CH + AC instances (uneven mesh sizes and
+// parameters) advanced together.  Every stage is one launch over all
+// instances: stacked per-level operators, stacked Krylov vectors, per-instance
+// Krylov scalars on the device, a fixed restart budget with per-instance
+// freezing (no host synchronisation inside a step, so the steps can be
+// captured in a hipGraph), and an autotuned launch shape per level.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/chns.h"
+#include "host_mesh.hpp"
+#include "kernels.hpp"
+#include "kernels_batch.hpp"
+
+using namespace chns;
+
+namespace {
+
+constexpr int NOPS = 3;  // 0: L = M, 1: X = s M + tau g K, 2: AC = M + tau delta_v K
+constexpr int BMAX_RESTART = 64;
+
+struct SizeTables {  // host tables of one mesh size, all its levels
+  std::vector<int> n;
+  std::vector<Csr> csr;
+  std::vector<Sell> sell;
+  std::vector<Csr> P, R;
+  std::vector<std::vector<double>> Pv, Rv;
+  std::vector<Sell> Psell, Rsell;
+  std::vector<GalerkinMap> gm;
+  Elements el;
+  std::vector<int> eslot;
+  int *d_ep2 = nullptr, *d_etype = nullptr, *d_eslot = nullptr;
+};
+
+template <typename T>
+struct Vec2 {
+  T* p[2] = {nullptr, nullptr};
+};
+
+struct BLevel {
+  int nrows = 0, nslices = 0;
+  std::vector<int> roff;  // per instance, -1 when absent
+  BStencil st;
+  int *col = nullptr, *sinst = nullptr, *diag = nullptr;
+  int *Pcol = nullptr, *Rcol = nullptr;  // transfer to the next level
+  double *P64 = nullptr, *R64 = nullptr;
+  float *P32 = nullptr, *R32 = nullptr;
+  int *gptr = nullptr, *gsrc = nullptr;
+  double* gw = nullptr;
+  int64_t slots = 0;
+  double *M = nullptr, *K = nullptr;
+  float* M32 = nullptr;
+  double* v64[NOPS] = {};
+  float* v32[NOPS] = {};
+  double* d64[NOPS] = {};
+  float* d32[NOPS] = {};
+  double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *dd64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr, *t32 = nullptr, *r32 = nullptr, *dd32 = nullptr;
+  // per op: masks (per slice) and counts, coarse Chebyshev coefficients [step][inst]
+  uint8_t *smooth[NOPS] = {}, *coarse[NOPS] = {}, *present[NOPS] = {};
+  int nsmooth[NOPS] = {}, ncoarse[NOPS] = {}, npresent[NOPS] = {};
+  double* cc64[NOPS][2] = {};
+  float* cc32[NOPS][2] = {};
+  double* aco[NOPS][2] = {};  // per-instance a, b of each op
+};
+
+}  // namespace
+
+struct chns_batch {
+  int count = 0;
+  std::vector<int> n;
+  std::vector<chns_params> prm;
+  std::vector<int64_t> off;  // node offsets (level 0)
+  int64_t Ntot = 0;
+  std::vector<BLevel> lv;
+  std::map<int, std::unique_ptr<SizeTables>> sizes;
+  // per-instance scalars
+  double *c12 = nullptr, *c22 = nullptr, *cmu = nullptr, *cac = nullptr;
+  float *c12f = nullptr, *c22f = nullptr;
+  int* cinst = nullptr;      // chunk -> instance over [phi_all; mu_all]
+  int *cr = nullptr;         // chunk ranges per instance (first half)
+  int nchunk1 = 0;
+  // Krylov
+  double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  double *y = nullptr, *h = nullptr, *inv = nullptr, *nrm = nullptr, *nrm2 = nullptr, *tol = nullptr;
+  double *part = nullptr, *part2 = nullptr;
+  int *flag = nullptr, *active = nullptr, *kcols = nullptr;
+  int *iters[2] = {}, *conv[2] = {};
+  // step buffers
+  double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr, *xac = nullptr;
+  double *w64a = nullptr, *w64b = nullptr;
+  float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string graph_key;
+  // current coarse-coefficient opts
+  std::string opts_key;
+  std::vector<void*> allocs;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_err;
+
+#define BCHK(b, expr)                                                  \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess) {                                            \
+      (b)->err = std::string(#expr) + ": " + hipGetErrorString(e_);    \
+      return CHNS_EHIP;                                                \
+    }                                                                  \
+  } while (0)
+#define BTRY(expr)            \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ < 0) return rc_;  \
+  } while (0)
+
+template <typename T>
+int balloc(chns_batch* b, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return CHNS_OK;
+  void* q = nullptr;
+  if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) {
+    b->err = "hipMalloc failed";
+    return CHNS_ENOMEM;
+  }
+  b->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return CHNS_OK;
+}
+
+template <typename T>
+int bupload(chns_batch* b, T** p, const std::vector<T>& h) {
+  BTRY(balloc(b, p, h.size()));
+  if (!h.empty()) BCHK(b, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CHNS_OK;
+}
+
+int fail(chns_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+SizeTables* tables_for(chns_batch* b, int n) {
+  auto it = b->sizes.find(n);
+  if (it != b->sizes.end()) return it->second.get();
+  auto T = std::make_unique<SizeTables>();
+  std::vector<int> sz{n};
+  while (sz.back() % 2 == 0 && sz.back() / 2 >= 4) sz.push_back(sz.back() / 2);
+  T->n = sz;
+  for (int nl : sz) {
+    Elements E = make_elements(nl);
+    T->csr.push_back(pattern_from_elements(nl * nl, nl * nl, E.ne, E.v.data(), 3, E.v.data(), 3));
+    T->sell.push_back(make_sell(T->csr.back(), 64, 1));
+    if (nl == n) T->el = std::move(E);
+  }
+  for (size_t l = 0; l + 1 < sz.size(); ++l) {
+    Csr P, R;
+    std::vector<double> Pv, Rv;
+    p1_prolongation(sz[l], P, Pv);
+    csr_transpose(P, Pv, R, Rv);
+    T->Psell.push_back(make_sell(P, 64, 1));
+    T->Rsell.push_back(make_sell(R, 64, 1));
+    T->gm.push_back(make_galerkin(T->csr[l], T->sell[l], P, Pv, T->csr[l + 1], T->sell[l + 1], nullptr));
+    T->P.push_back(std::move(P));
+    T->R.push_back(std::move(R));
+    T->Pv.push_back(std::move(Pv));
+    T->Rv.push_back(std::move(Rv));
+  }
+  const Csr& A = T->csr[0];
+  T->eslot.resize(size_t(T->el.ne) * 9);
+  for (int e = 0; e < T->el.ne; ++e)
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c)
+        T->eslot[size_t(e) * 9 + a * 3 + c] = T->sell[0].csr2sell[A.find(T->el.v[e * 3 + a], T->el.v[e * 3 + c])];
+  SizeTables* raw = T.get();
+  b->sizes[n] = std::move(T);
+  return raw;
+}
+
+// Stack the per-instance level structures.
+int build_levels(chns_batch* b) {
+  int Lmax = 0;
+  std::vector<SizeTables*> tab(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    tab[i] = tables_for(b, b->n[i]);
+    Lmax = std::max(Lmax, int(tab[i]->n.size()));
+  }
+  b->lv.resize(Lmax);
+  for (int l = 0; l < Lmax; ++l) {
+    BLevel& L = b->lv[l];
+    L.roff.assign(b->count, -1);
+    int rows = 0;
+    for (int i = 0; i < b->count; ++i)
+      if (l < int(tab[i]->n.size())) {
+        L.roff[i] = rows;
+        const int nl = tab[i]->n[l];
+        rows += ((nl * nl + 63) / 64) * 64;  // slice-aligned
+      }
+    L.nrows = rows;
+    L.nslices = rows / 64;
+    L.slots = int64_t(rows) * 7;
+    std::vector<int> col(L.slots, 0), sinst(L.nslices, 0), diag(rows, 0);
+    for (int i = 0; i < b->count; ++i) {
+      if (L.roff[i] < 0) continue;
+      const Sell& S = tab[i]->sell[l];
+      const int r0 = L.roff[i];
+      for (int64_t q = 0; q < S.slots(); ++q) col[int64_t(r0) * 7 + q] = S.col[q] + r0;
+      for (int r = 0; r < S.nrows; ++r) diag[r0 + r] = int(int64_t(r0) * 7 + S.diag[r]);
+      // padding rows of a partial last slice keep diag at their own slot 0
+      for (int r = S.nrows; r < S.nslices * 64; ++r) diag[r0 + r] = int(int64_t(r0) * 7 + (r / 64) * 448 + (r % 64));
+      for (int s = 0; s < S.nslices; ++s) sinst[r0 / 64 + s] = i;
+    }
+    BTRY(bupload(b, &L.col, col));
+    BTRY(bupload(b, &L.sinst, sinst));
+    BTRY(bupload(b, &L.diag, diag));
+    L.st.nrows = L.nrows;
+    L.st.col = L.col;
+    L.st.sinst = L.sinst;
+  }
+  // transfers and Galerkin maps between l and l+1
+  for (int l = 0; l + 1 < Lmax; ++l) {
+    BLevel& F = b->lv[l];
+    BLevel& G = b->lv[l + 1];
+    std::vector<int> Pcol(int64_t(F.nrows) * 2, 0), Rcol(int64_t(G.nrows) * 7, 0);
+    std::vector<double> Pval(int64_t(F.nrows) * 2, 0.0), Rval(int64_t(G.nrows) * 7, 0.0);
+    std::vector<int> gptr(G.slots + 1, 0), gsrc;
+    std::vector<double> gw;
+    std::vector<std::vector<std::pair<int, double>>> lists(G.slots);
+    for (int i = 0; i < b->count; ++i) {
+      if (G.roff[i] < 0) continue;
+      SizeTables* T = tab[i];
+      const int rf = F.roff[i], rc = G.roff[i];
+      const Sell& Ps = T->Psell[l];
+      const Sell& Rs = T->Rsell[l];
+      std::vector<double> pv(Ps.slots(), 0.0), rv(Rs.slots(), 0.0);
+      for (int64_t q = 0; q < T->P[l].nnz(); ++q) pv[Ps.csr2sell[q]] = T->Pv[l][q];
+      for (int64_t q = 0; q < T->R[l].nnz(); ++q) rv[Rs.csr2sell[q]] = T->Rv[l][q];
+      if (Ps.width_max != 2 || !Ps.uniform || Rs.width_max != 7 || !Rs.uniform)
+        return fail(b, CHNS_EINVAL, "unexpected transfer layout");
+      for (int64_t q = 0; q < Ps.slots(); ++q) {
+        Pcol[int64_t(rf) * 2 + q] = Ps.col[q] + rc;
+        Pval[int64_t(rf) * 2 + q] = pv[q];
+      }
+      for (int64_t q = 0; q < Rs.slots(); ++q) {
+        Rcol[int64_t(rc) * 7 + q] = Rs.col[q] + rf;
+        Rval[int64_t(rc) * 7 + q] = rv[q];
+      }
+      const GalerkinMap& gm = T->gm[l];
+      for (int64_t s = 0; s + 1 < int64_t(gm.ptr.size()); ++s)
+        for (int k = gm.ptr[s]; k < gm.ptr[s + 1]; ++k)
+          lists[int64_t(rc) * 7 + s].push_back({int(int64_t(rf) * 7 + gm.src[k]), gm.w[k]});
+    }
+    for (int64_t s = 0; s < G.slots; ++s) {
+      gptr[s + 1] = gptr[s] + int(lists[s].size());
+      for (auto& e : lists[s]) {
+        gsrc.push_back(e.first);
+        gw.push_back(e.second);
+      }
+    }
+    std::vector<float> P32(Pval.begin(), Pval.end()), R32(Rval.begin(), Rval.end());
+    BTRY(bupload(b, &F.Pcol, Pcol));
+    BTRY(bupload(b, &F.Rcol, Rcol));
+    BTRY(bupload(b, &F.P64, Pval));
+    BTRY(bupload(b, &F.R64, Rval));
+    BTRY(bupload(b, &F.P32, P32));
+    BTRY(bupload(b, &F.R32, R32));
+    BTRY(bupload(b, &F.gptr, gptr));
+    BTRY(bupload(b, &F.gsrc, gsrc));
+    BTRY(bupload(b, &F.gw, gw));
+  }
+  return CHNS_OK;
+}
+
+double op_a(const chns_params& p, int op) {
+  if (op == 1) return std::sqrt(p.tau * p.mobility / (p.eps * p.eps));
+  return 1.0;
+}
+double op_b(const chns_params& p, int op) {
+  if (op == 1) return p.tau * p.mobility;
+  if (op == 2) return p.tau * p.evap_rate * p.eps * p.eps;
+  return 0.0;
+}
+
+int ninst_levels(chns_batch* b, int i) {
+  int c = 0;
+  for (auto& L : b->lv)
+    if (L.roff[i] >= 0) ++c;
+  return c;
+}
+
+template <typename T>
+std::vector<T> cheb_seq(double lo, double hi, int steps, bool first) {
+  // first ? c2 sequence : c1 sequence
+  std::vector<T> out(steps);
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho_prev = 1.0 / sigma;
+  out[0] = first ? T(1.0 / theta) : T(0);
+  for (int i = 1; i < steps; ++i) {
+    const double rho_i = 1.0 / (2.0 * sigma - rho_prev);
+    out[i] = first ? T(2.0 * rho_i / delta) : T(rho_i * rho_prev);
+    rho_prev = rho_i;
+  }
+  return out;
+}
+
+// Masks and coarse Chebyshev coefficients for the given options.
+int prepare_cycles(chns_batch* b, const chns_solve_opts& o) {
+  char key[256];
+  std::snprintf(key, sizeof key, "%d/%d/%d/%.17g/%.17g", o.mg_pre, o.mg_post, o.mg_coarse, o.mg_lmax,
+                o.mg_rho_cut);
+  if (b->opts_key == key) return CHNS_OK;
+  const int Lmax = int(b->lv.size());
+  for (int op = 0; op < NOPS; ++op) {
+    std::vector<int> cut(b->count);
+    for (int i = 0; i < b->count; ++i) {
+      const double a = op_a(b->prm[i], op), bb = op_b(b->prm[i], op);
+      const int Li = ninst_levels(b, i);
+      cut[i] = Li - 1;
+      int nl = b->n[i];
+      for (int l = 0; l < Li; ++l, nl /= 2)
+        if (8.0 * bb * double(nl) * nl / a <= o.mg_rho_cut) {
+          cut[i] = l;
+          break;
+        }
+    }
+    for (int l = 0; l < Lmax; ++l) {
+      BLevel& L = b->lv[l];
+      std::vector<uint8_t> sm(L.nslices, 0), co(L.nslices, 0), pr(L.nslices, 0);
+      L.nsmooth[op] = L.ncoarse[op] = L.npresent[op] = 0;
+      const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
+      std::vector<double> c1(size_t(steps) * b->count, 0.0), c2(size_t(steps) * b->count, 1.0);
+      for (int i = 0; i < b->count; ++i) {
+        if (L.roff[i] < 0 || l > cut[i]) continue;
+        const int nl = b->n[i] >> l;
+        const int s0 = L.roff[i] / 64, s1 = s0 + (nl * nl + 63) / 64;
+        const uint8_t role = (l < cut[i]) ? 1 : 2;
+        for (int s = s0; s < s1; ++s) {
+          pr[s] = 1;
+          (role == 1 ? sm : co)[s] = 1;
+        }
+        L.npresent[op]++;
+        if (role == 1) {
+          L.nsmooth[op]++;
+        } else {
+          L.ncoarse[op]++;
+          const double a = op_a(b->prm[i], op), bb = op_b(b->prm[i], op);
+          const double lo = 0.45 / (1.0 + 8.0 * bb * double(nl) * nl / a);
+          auto s1v = cheb_seq<double>(lo, o.mg_lmax, steps, false);
+          auto s2v = cheb_seq<double>(lo, o.mg_lmax, steps, true);
+          for (int s = 0; s < steps; ++s) {
+            c1[size_t(s) * b->count + i] = s1v[s];
+            c2[size_t(s) * b->count + i] = s2v[s];
+          }
+        }
+      }
+      std::vector<float> c1f(c1.begin(), c1.end()), c2f(c2.begin(), c2.end());
+      BTRY(bupload(b, &L.smooth[op], sm));
+      BTRY(bupload(b, &L.coarse[op], co));
+      BTRY(bupload(b, &L.present[op], pr));
+      BTRY(bupload(b, &L.cc64[op][0], c1));
+      BTRY(bupload(b, &L.cc64[op][1], c2));
+      BTRY(bupload(b, &L.cc32[op][0], c1f));
+      BTRY(bupload(b, &L.cc32[op][1], c2f));
+    }
+  }
+  b->opts_key = key;
+  return CHNS_OK;
+}
+
+template <typename T> struct BSel;
+template <> struct BSel<double> {
+  static double* v(BLevel& L, int op) { return L.v64[op]; }
+  static double* d(BLevel& L, int op) { return L.d64[op]; }
+  static double* cc(BLevel& L, int op, int w) { return L.cc64[op][w]; }
+  static double* b(BLevel& L) { return L.b64; }
+  static double* x(BLevel& L) { return L.x64; }
+  static double* t(BLevel& L) { return L.t64; }
+  static double* r(BLevel& L) { return L.r64; }
+  static double* dd(BLevel& L) { return L.dd64; }
+  static double* P(BLevel& L) { return L.P64; }
+  static double* R(BLevel& L) { return L.R64; }
+  static double* M(BLevel& L) { return L.M; }
+};
+template <> struct BSel<float> {
+  static float* v(BLevel& L, int op) { return L.v32[op]; }
+  static float* d(BLevel& L, int op) { return L.d32[op]; }
+  static float* cc(BLevel& L, int op, int w) { return L.cc32[op][w]; }
+  static float* b(BLevel& L) { return L.b32; }
+  static float* x(BLevel& L) { return L.x32; }
+  static float* t(BLevel& L) { return L.t32; }
+  static float* r(BLevel& L) { return L.r32; }
+  static float* dd(BLevel& L) { return L.dd32; }
+  static float* P(BLevel& L) { return L.P32; }
+  static float* R(BLevel& L) { return L.R32; }
+  static float* M(BLevel& L) { return L.M32; }
+};
+
+// Batched V-cycle of operator `op` on level l: instances with their cut
+// below l smooth and recurse, instances cut at l take Chebyshev steps.
+template <typename T>
+void bvcycle(chns_batch* b, int op, int l, const T* rhs, T* x, const chns_solve_opts& o,
+             hipStream_t s) {
+  BLevel& L = b->lv[l];
+  const T* v = BSel<T>::v(L, op);
+  const T* di = BSel<T>::d(L, op);
+  T* d = BSel<T>::dd(L);
+  T* t = BSel<T>::t(L);
+  const double lmax = o.mg_lmax;
+  if (L.nsmooth[op] > 0) {
+    auto pc1 = cheb_seq<T>(lmax / 4.0, lmax, o.mg_pre, false);
+    auto pc2 = cheb_seq<T>(lmax / 4.0, lmax, o.mg_pre, true);
+    const uint8_t* m = L.smooth[op];
+    T* cur = ((o.mg_pre - 1 + o.mg_post) % 2 == 0) ? x : t;
+    T* oth = (cur == x) ? t : x;
+    bstencil<T>(L.st, v, 3, nullptr, rhs, di, d, T(0), pc2[0], nullptr, nullptr, m, cur, s);
+    for (int k = 1; k < o.mg_pre; ++k) {
+      bstencil<T>(L.st, v, 2, cur, rhs, di, d, pc1[k], pc2[k], nullptr, nullptr, m, oth, s);
+      std::swap(cur, oth);
+    }
+    T* r = BSel<T>::r(L);
+    bstencil<T>(L.st, v, 1, cur, rhs, nullptr, nullptr, T(0), T(0), nullptr, nullptr, m, r, s);
+    BLevel& G = b->lv[l + 1];
+    bspmv_uniform<T>(G.nrows, 7, L.Rcol, BSel<T>::R(L), G.present[op], r, BSel<T>::b(G), T(1), T(0), s);
+    bvcycle<T>(b, op, l + 1, BSel<T>::b(G), BSel<T>::x(G), o, s);
+    bspmv_uniform<T>(L.nrows, 2, L.Pcol, BSel<T>::P(L), m, BSel<T>::x(G), cur, T(1), T(1), s);
+    if (o.mg_post > 0) {
+      auto qc1 = cheb_seq<T>(lmax / 4.0, lmax, o.mg_post, false);
+      auto qc2 = cheb_seq<T>(lmax / 4.0, lmax, o.mg_post, true);
+      for (int k = 0; k < o.mg_post; ++k) {
+        bstencil<T>(L.st, v, 2, cur, rhs, di, d, qc1[k], qc2[k], nullptr, nullptr, m, oth, s);
+        std::swap(cur, oth);
+      }
+    }
+  }
+  if (L.ncoarse[op] > 0) {
+    const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
+    const uint8_t* m = L.coarse[op];
+    const T* c1 = BSel<T>::cc(L, op, 0);
+    const T* c2 = BSel<T>::cc(L, op, 1);
+    T* cur = ((steps - 1) % 2 == 0) ? x : t;
+    T* oth = (cur == x) ? t : x;
+    bstencil<T>(L.st, v, 3, nullptr, rhs, di, d, T(0), T(0), c1, c2, m, cur, s);
+    for (int k = 1; k < steps; ++k) {
+      bstencil<T>(L.st, v, 2, cur, rhs, di, d, T(0), T(0), c1 + size_t(k) * b->count,
+                  c2 + size_t(k) * b->count, m, oth, s);
+      std::swap(cur, oth);
+    }
+  }
+}
+
+template <typename T>
+void bprecond_t(chns_batch* b, int block, const T* r, T* z, T* tmp1, T* tmp2,
+                const chns_solve_opts& o, hipStream_t s) {
+  const int64_t N = b->Ntot;
+  BLevel& L0 = b->lv[0];
+  if (block == CHNS_BLOCK_CH) {
+    bvcycle<T>(b, 0, 0, r, z, o, s);
+    bvcycle<T>(b, 1, 0, r + N, tmp1, o, s);
+    bstencil<T>(L0.st, BSel<T>::M(L0), 0, tmp1, nullptr, nullptr, nullptr, T(1), T(0), nullptr,
+                nullptr, nullptr, tmp2, s);
+    bvcycle<T>(b, 1, 0, tmp2, z + N, o, s);
+  } else {
+    bvcycle<T>(b, 2, 0, r, z, o, s);
+  }
+}
+
+void bprecond(chns_batch* b, int block, const double* r, double* z, const chns_solve_opts& o,
+              hipStream_t s) {
+  const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
+  if (o.precision == CHNS_F64) {
+    bprecond_t<double>(b, block, r, z, b->w64a, b->w64b, o, s);
+  } else {
+    convert<double, float>(n, r, b->r32, s);
+    bprecond_t<float>(b, block, b->r32, b->z32, b->w32a, b->w32b, o, s);
+    convert<float, double>(n, b->z32, z, s);
+  }
+}
+
+void bapply(chns_batch* b, int block, const double* x, double* y, double alpha, double beta,
+            hipStream_t s) {
+  BLevel& L0 = b->lv[0];
+  if (block == CHNS_BLOCK_CH)
+    bch_block<double>(L0.st, L0.M, L0.K, L0.M, b->c12, b->c22, x, alpha, beta, y, s);
+  else
+    bstencil<double>(L0.st, L0.v64[2], 0, x, nullptr, nullptr, nullptr, alpha, beta, nullptr,
+                     nullptr, nullptr, y, s);
+}
+
+__global__ void k_not_into(int n, const int* __restrict__ a, int* __restrict__ o) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] ? 0 : 1;
+}
+
+// Batched FGMRES with a fixed budget of restart cycles; instances freeze on
+// convergence.  sync_check: read the number of active instances back after
+// each cycle and stop early (not allowed under graph capture).
+int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_solve_opts& o,
+            bool sync_check, hipStream_t s) {
+  const int m = o.restart;
+  const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
+  const int nchunk = int(n / BCHUNK);
+  const int half = (block == CHNS_BLOCK_CH) ? b->nchunk1 : 0;
+  const int cycles = (o.maxiter + m - 1) / m;
+  const int hs = m + 2, Hs = (m + 1) * m, ldH = m + 1;
+  const int bi = block == CHNS_BLOCK_CH ? 0 : 1;
+  double* V = b->V;
+  dfill_int(b->count, 0, b->iters[bi], s);
+  bnorm_partial(n, rhs, b->part, s);
+  bnorm_finish(b->count, nchunk, b->part, b->cr, half, m, 1, o.rtol, o.atol, b->nrm, b->inv, b->g,
+               b->tol, b->active, b->kcols, s);
+  for (int cyc = 0; cyc <= cycles; ++cyc) {
+    dcopy(n, rhs, V, s);
+    bapply(b, block, x, V, -1.0, 1.0, s);
+    bnorm_partial(n, V, b->part, s);
+    bnorm_finish(b->count, nchunk, b->part, b->cr, half, m, 0, o.rtol, o.atol, b->nrm, b->inv,
+                 b->g, b->tol, b->active, b->kcols, s);
+    if (cyc == cycles) break;  // final true residual only
+    if (sync_check) {
+      std::vector<int> act(b->count);
+      BCHK(b, hipMemcpyAsync(act.data(), b->active, b->count * sizeof(int), hipMemcpyDeviceToHost, s));
+      BCHK(b, hipStreamSynchronize(s));
+      bool any = false;
+      for (int a : act) any = any || a;
+      if (!any) break;
+    }
+    bscale(n, V, b->inv, b->cinst, V, s);
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + int64_t(j) * n;
+      double* vn = V + int64_t(j + 1) * n;
+      double* zj = b->Z + int64_t(j) * n;
+      bprecond(b, block, vj, zj, o, s);
+      bapply(b, block, zj, vn, 1.0, 0.0, s);
+      bmdot_partial(n, V, n, j + 2, vn, b->part, nullptr, b->cinst, s);
+      bmdot_reduce(b->count, nchunk, j + 2, b->part, b->cr, half, b->h, hs, b->H, Hs, j, ldH, 0,
+                   nullptr, s);
+      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, nullptr, b->cinst, s);
+      breorth_decide(b->count, nchunk, b->part2, b->cr, half, b->h, hs, j + 1, b->flag, b->nrm2, s);
+      bmdot_partial(n, V, n, j + 1, vn, b->part, b->flag, b->cinst, s);
+      bmdot_reduce(b->count, nchunk, j + 1, b->part, b->cr, half, b->h, hs, b->H, Hs, j, ldH, 1,
+                   b->flag, s);
+      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, b->flag, b->cinst, s);
+      barnoldi_finish(b->count, nchunk, b->part2, b->cr, half, b->flag, b->nrm2, j, m, b->H, b->cs,
+                      b->sn, b->g, b->inv, b->tol, b->active, b->kcols, b->iters[bi], s);
+      bscale(n, vn, b->inv, b->cinst, vn, s);
+    }
+    blsq(b->count, m, b->H, b->g, b->kcols, b->y, s);
+    bxupdate(n, b->Z, n, m, b->y, x, b->cinst, s);
+  }
+  hipLaunchKernelGGL(k_not_into, dim3((b->count + 63) / 64), dim3(64), 0, s, b->count, b->active,
+                     b->conv[bi]);
+  BCHK(b, hipGetLastError());
+  return CHNS_OK;
+}
+
+int bstep(chns_batch* b, double* phi, double* mu, double* Phi, const chns_solve_opts& o, bool sync_check,
+          hipStream_t s) {
+  const int64_t N = b->Ntot;
+  BLevel& L0 = b->lv[0];
+  brhs_binary(L0.st, L0.M, phi, Phi, b->cmu, b->cac, b->rhs_ch, b->rhs_ac, s);
+  dcopy(N, phi, b->xch, s);
+  dcopy(N, mu, b->xch + N, s);
+  dcopy(N, Phi, b->xac, s);
+  BTRY(bfgmres(b, CHNS_BLOCK_CH, b->rhs_ch, b->xch, o, sync_check, s));
+  BTRY(bfgmres(b, CHNS_BLOCK_AC, b->rhs_ac, b->xac, o, sync_check, s));
+  dcopy(N, b->xch, phi, s);
+  dcopy(N, b->xch + N, mu, s);
+  dcopy(N, b->xac, Phi, s);
+  BCHK(b, hipGetLastError());
+  return CHNS_OK;
+}
+
+int bbuild(chns_batch* b) {
+  BTRY(build_levels(b));
+  const int64_t N = b->lv[0].nrows;
+  b->Ntot = N;
+  b->off.assign(b->count + 1, 0);
+  for (int i = 0; i < b->count; ++i) b->off[i + 1] = b->off[i] + int64_t(b->n[i]) * b->n[i];
+  for (int i = 0; i < b->count; ++i)
+    if (b->lv[0].roff[i] != b->off[i]) return fail(b, CHNS_EINVAL, "instance offsets not packed");
+  // per-instance scalars
+  std::vector<double> c12(b->count), c22(b->count), cmu(b->count), cac(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    const auto& p = b->prm[i];
+    const double tg = p.tau * p.mobility, be = p.eps * p.eps;
+    c12[i] = tg;
+    c22[i] = -tg / be;
+    cmu[i] = -tg / be;
+    cac[i] = -p.tau * p.evap_rate;
+  }
+  BTRY(bupload(b, &b->c12, c12));
+  BTRY(bupload(b, &b->c22, c22));
+  BTRY(bupload(b, &b->cmu, cmu));
+  BTRY(bupload(b, &b->cac, cac));
+  // chunks
+  b->nchunk1 = int(N / BCHUNK);
+  std::vector<int> cinst(2 * b->nchunk1), cr(2 * b->count);
+  for (int i = 0; i < b->count; ++i) {
+    cr[2 * i] = int(b->off[i] / BCHUNK);
+    cr[2 * i + 1] = int(b->off[i + 1] / BCHUNK);
+    for (int c = cr[2 * i]; c < cr[2 * i + 1]; ++c) cinst[c] = cinst[c + b->nchunk1] = i;
+  }
+  BTRY(bupload(b, &b->cinst, cinst));
+  BTRY(bupload(b, &b->cr, cr));
+  // values and vectors per level
+  for (size_t l = 0; l < b->lv.size(); ++l) {
+    BLevel& L = b->lv[l];
+    const size_t ns = L.slots, nr = L.nrows;
+    BTRY(balloc(b, &L.M, ns));
+    BTRY(balloc(b, &L.K, ns));
+    BTRY(balloc(b, &L.M32, ns));
+    for (int op = 0; op < NOPS; ++op) {
+      BTRY(balloc(b, &L.v64[op], ns));
+      BTRY(balloc(b, &L.v32[op], ns));
+      BTRY(balloc(b, &L.d64[op], nr));
+      BTRY(balloc(b, &L.d32[op], nr));
+      std::vector<double> a(b->count), bb(b->count);
+      for (int i = 0; i < b->count; ++i) {
+        a[i] = op_a(b->prm[i], op);
+        bb[i] = op_b(b->prm[i], op);
+      }
+      BTRY(bupload(b, &L.aco[op][0], a));
+      BTRY(bupload(b, &L.aco[op][1], bb));
+    }
+    for (double** v : {&L.b64, &L.x64, &L.t64, &L.r64, &L.dd64}) BTRY(balloc(b, v, nr));
+    for (float** v : {&L.b32, &L.x32, &L.t32, &L.r32, &L.dd32}) BTRY(balloc(b, v, nr));
+    BCHK(b, hipMemset(L.M, 0, ns * sizeof(double)));
+    BCHK(b, hipMemset(L.K, 0, ns * sizeof(double)));
+    // padding rows (partial slices of tiny levels): unit diagonal keeps 1/diag finite
+    BCHK(b, hipMemset(L.b64, 0, nr * sizeof(double)));
+  }
+  // assembly of M and K on the finest level, instance by instance
+  BLevel& L0 = b->lv[0];
+  for (int i = 0; i < b->count; ++i) {
+    SizeTables* T = tables_for(b, b->n[i]);
+    if (!T->d_eslot) {
+      BTRY(bupload(b, &T->d_ep2, T->el.p2));
+      BTRY(bupload(b, &T->d_etype, T->el.type));
+      BTRY(bupload(b, &T->d_eslot, T->eslot));
+    }
+    const int64_t so = int64_t(L0.roff[i]) * 7;
+    for (int col = 0; col < 8; ++col) {
+      assemble_p1(0, T->el.colour_ptr[col], T->el.colour_ptr[col + 1], T->d_ep2, T->d_etype,
+                  T->d_eslot, 1.0 / b->n[i], nullptr, 0, L0.M + so, nullptr);
+      assemble_p1(1, T->el.colour_ptr[col], T->el.colour_ptr[col + 1], T->d_ep2, T->d_etype,
+                  T->d_eslot, 1.0 / b->n[i], nullptr, 0, L0.K + so, nullptr);
+    }
+  }
+  for (size_t l = 0; l + 1 < b->lv.size(); ++l) {
+    BLevel& F = b->lv[l];
+    BLevel& G = b->lv[l + 1];
+    galerkin(G.slots, F.gptr, F.gsrc, F.gw, F.M, G.M, nullptr);
+    galerkin(G.slots, F.gptr, F.gsrc, F.gw, F.K, G.K, nullptr);
+  }
+  for (auto& L : b->lv) {
+    convert<double, float>(L.slots, L.M, L.M32, nullptr);
+    for (int op = 0; op < NOPS; ++op) {
+      bcombine(L.slots, L.sinst, L.aco[op][0], L.M, L.aco[op][1], L.K, L.v64[op], L.v32[op], nullptr);
+      diag_inverse(L.nrows, L.diag, L.v64[op], L.d64[op], L.d32[op], nullptr);
+    }
+  }
+  BCHK(b, hipGetLastError());
+  // Krylov workspace for the CH block (2N) with restart <= BMAX_RESTART
+  const size_t n2 = 2 * size_t(N), cnt = size_t(b->count), m = BMAX_RESTART;
+  BTRY(balloc(b, &b->V, (m + 1) * n2));
+  BTRY(balloc(b, &b->Z, m * n2));
+  BTRY(balloc(b, &b->H, cnt * (m + 1) * m));
+  BTRY(balloc(b, &b->cs, cnt * (m + 1)));
+  BTRY(balloc(b, &b->sn, cnt * (m + 1)));
+  BTRY(balloc(b, &b->g, cnt * (m + 2)));
+  BTRY(balloc(b, &b->y, cnt * (m + 1)));
+  BTRY(balloc(b, &b->h, cnt * (m + 2)));
+  for (double** v : {&b->inv, &b->nrm, &b->nrm2, &b->tol}) BTRY(balloc(b, v, cnt));
+  for (int** v : {&b->flag, &b->active, &b->kcols, &b->iters[0], &b->iters[1], &b->conv[0], &b->conv[1]})
+    BTRY(balloc(b, v, cnt));
+  BTRY(balloc(b, &b->part, (m + 2) * n2 / BCHUNK));
+  BTRY(balloc(b, &b->part2, n2 / BCHUNK));
+  for (double** v : {&b->rhs_ch, &b->xch}) BTRY(balloc(b, v, n2));
+  for (double** v : {&b->rhs_ac, &b->xac, &b->w64a, &b->w64b}) BTRY(balloc(b, v, size_t(N)));
+  for (float** v : {&b->r32, &b->z32}) BTRY(balloc(b, v, n2));
+  for (float** v : {&b->w32a, &b->w32b}) BTRY(balloc(b, v, size_t(N)));
+  BCHK(b, hipEventCreate(&b->ev0));
+  BCHK(b, hipEventCreate(&b->ev1));
+  BCHK(b, hipDeviceSynchronize());
+  return CHNS_OK;
+}
+
+void brelease(chns_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+}
+
+int check_bopts(chns_batch* b, const chns_solve_opts* o) {
+  if (!o) return fail(b, CHNS_EINVAL, "opts is NULL");
+  if (!(o->rtol >= 0) || !(o->atol >= 0) || !std::isfinite(o->rtol) || !std::isfinite(o->atol))
+    return fail(b, CHNS_EINVAL, "rtol/atol must be finite and >= 0");
+  if (o->restart < 1 || o->restart > BMAX_RESTART) return fail(b, CHNS_EINVAL, "restart must be in 1..64");
+  if (o->maxiter < 1 || o->maxiter > 4096) return fail(b, CHNS_EINVAL, "maxiter must be in 1..4096");
+  if (o->precision != CHNS_F64 && o->precision != CHNS_MIXED) return fail(b, CHNS_EINVAL, "unknown precision");
+  if (o->mg_cycles != 1) return fail(b, CHNS_EUNSUPPORTED, "the batched form runs one cycle per inner solve");
+  if (o->mg_pre < 1 || o->mg_pre > 32 || o->mg_post < 0 || o->mg_post > 32 || o->mg_coarse < 1 ||
+      o->mg_coarse > MAXCHEB || o->mg_pre + o->mg_post > MAXCHEB)
+    return fail(b, CHNS_EINVAL, "multigrid step counts out of range");
+  if (!(o->mg_lmax > 0.0 && o->mg_lmax < 100.0) || !(o->mg_rho_cut >= 0.0))
+    return fail(b, CHNS_EINVAL, "bad mg_lmax / mg_rho_cut");
+  return CHNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_params, chns_batch** out) {
+  if (!out) return CHNS_EINVAL;
+  *out = nullptr;
+  if (count < 1 || count > 4096 || !h_n || !h_params) {
+    g_batch_err = "count must be in 1..4096 with sizes and parameters";
+    return CHNS_EINVAL;
+  }
+  for (int i = 0; i < count; ++i) {
+    if (h_n[i] < 32 || h_n[i] > 2048 || h_n[i] % 32 != 0) {
+      g_batch_err = "each n must be a multiple of 32 in 32..2048";
+      return CHNS_EINVAL;
+    }
+    const chns_params& p = h_params[i];
+    const double v[] = {p.eps, p.tau, p.mobility, p.evap_rate};
+    for (double x : v)
+      if (!std::isfinite(x)) {
+        g_batch_err = "parameter is NaN or Inf";
+        return CHNS_EINVAL;
+      }
+    if (p.eps <= 0 || p.tau <= 0 || p.mobility <= 0 || p.evap_rate < 0) {
+      g_batch_err = "eps, tau, mobility must be positive and evap_rate >= 0";
+      return CHNS_EINVAL;
+    }
+  }
+  chns_batch* b = new chns_batch();
+  b->count = count;
+  b->n.assign(h_n, h_n + count);
+  b->prm.assign(h_params, h_params + count);
+  const int rc = bbuild(b);
+  if (rc < 0) {
+    g_batch_err = b->err;
+    brelease(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return CHNS_OK;
+}
+
+int chns_batch_destroy(chns_batch* b) {
+  if (!b) return CHNS_EINVAL;
+  (void)hipDeviceSynchronize();
+  brelease(b);
+  delete b;
+  return CHNS_OK;
+}
+
+int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets) {
+  if (!b || !h_offsets) return CHNS_EINVAL;
+  std::memcpy(h_offsets, b->off.data(), (b->count + 1) * sizeof(int64_t));
+  return CHNS_OK;
+}
+
+int chns_batch_timestep(chns_batch* b, double* d_phi, double* d_mu, double* d_Phi, int32_t nsteps,
+                        const chns_solve_opts* opts, int32_t use_graph, int32_t* h_iters,
+                        int32_t* h_conv, double* h_ms, void* stream) {
+  if (!b) return CHNS_EINVAL;
+  BTRY(check_bopts(b, opts));
+  if (!d_phi || !d_mu || !d_Phi || nsteps < 1 || nsteps > 1000)
+    return fail(b, CHNS_EINVAL, "fields must be non-NULL and nsteps in 1..1000");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (use_graph && !s) return fail(b, CHNS_EINVAL, "graph capture needs a non-default stream");
+  BTRY(prepare_cycles(b, *opts));
+  BCHK(b, hipEventRecord(b->ev0, s));
+  if (use_graph) {
+    char key[512];
+    std::snprintf(key, sizeof key, "%p/%p/%p/%d/%p/%s/%d/%d/%d/%.17g/%.17g", (void*)d_phi, (void*)d_mu,
+                  (void*)d_Phi, nsteps, (void*)s, b->opts_key.c_str(), opts->restart, opts->maxiter,
+                  opts->precision, opts->rtol, opts->atol);
+    if (b->graph_key != key) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+      BCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      int rc = CHNS_OK;
+      for (int k = 0; k < nsteps && rc == CHNS_OK; ++k) rc = bstep(b, d_phi, d_mu, d_Phi, *opts, false, s);
+      hipGraph_t gr = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &gr);
+      if (rc < 0) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(b, CHNS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      b->graph = gr;
+      BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_key = key;
+    }
+    BCHK(b, hipGraphLaunch(b->exec, s));
+  } else {
+    for (int k = 0; k < nsteps; ++k) BTRY(bstep(b, d_phi, d_mu, d_Phi, *opts, true, s));
+  }
+  BCHK(b, hipEventRecord(b->ev1, s));
+  BCHK(b, hipEventSynchronize(b->ev1));
+  float ms = 0.f;
+  BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  if (h_ms) *h_ms = ms;
+  if (h_iters) {
+    BCHK(b, hipMemcpy(h_iters, b->iters[0], b->count * sizeof(int), hipMemcpyDeviceToHost));
+    BCHK(b, hipMemcpy(h_iters + b->count, b->iters[1], b->count * sizeof(int), hipMemcpyDeviceToHost));
+  }
+  int worst = CHNS_OK;
+  std::vector<int> c0(b->count), c1(b->count);
+  BCHK(b, hipMemcpy(c0.data(), b->conv[0], b->count * sizeof(int), hipMemcpyDeviceToHost));
+  BCHK(b, hipMemcpy(c1.data(), b->conv[1], b->count * sizeof(int), hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->count; ++i) {
+    if (!c0[i] || !c1[i]) worst = CHNS_WNOCONV;
+    if (h_conv) {
+      h_conv[i] = c0[i];
+      h_conv[b->count + i] = c1[i];
+    }
+  }
+  return worst;
+}
+
+int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream) {
+  if (!b) return CHNS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // cache: one line per level "rows rpt block"
+  std::map<int, std::pair<int, int>> cache;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      int rows, rpt, blk;
+      char arch[64];
+      if (std::fscanf(f, "%63s", arch) == 1 && std::string(arch) == "gfx950")
+        while (std::fscanf(f, "%d %d %d", &rows, &rpt, &blk) == 3) cache[rows] = {rpt, blk};
+      std::fclose(f);
+    }
+  }
+  const int rpts[3] = {1, 2, 4};
+  const int blocks[4] = {128, 256, 512, 1024};
+  for (auto& L : b->lv) {
+    auto it = cache.find(L.nrows);
+    if (it != cache.end()) {
+      L.st.rpt = it->second.first;
+      L.st.block = it->second.second;
+      continue;
+    }
+    float best = 1e30f;
+    int br = 1, bb = 256;
+    for (int rpt : rpts)
+      for (int blk : blocks) {
+        BStencil st = L.st;
+        st.rpt = rpt;
+        st.block = blk;
+        for (int w = 0; w < 2; ++w)
+          bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
+                          nullptr, L.t32, s);
+        BCHK(b, hipEventRecord(b->ev0, s));
+        for (int w = 0; w < 10; ++w)
+          bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
+                          nullptr, L.t32, s);
+        BCHK(b, hipEventRecord(b->ev1, s));
+        BCHK(b, hipEventSynchronize(b->ev1));
+        float ms = 0.f;
+        BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        if (ms < best) {
+          best = ms;
+          br = rpt;
+          bb = blk;
+        }
+      }
+    L.st.rpt = br;
+    L.st.block = bb;
+    cache[L.nrows] = {br, bb};
+  }
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "w")) {
+      std::fprintf(f, "gfx950\n");
+      for (auto& e : cache) std::fprintf(f, "%d %d %d\n", e.first, e.second.first, e.second.second);
+      std::fclose(f);
+    }
+  }
+  b->graph_key.clear();  // launch shapes changed
+  return CHNS_OK;
+}
+
+const char* chns_batch_last_error(const chns_batch* b) {
+  if (!b) return g_batch_err.c_str();
+  return b->err.c_str();
+}
+
+}  // extern "C"

@@ -507,7 +507,8 @@ __global__ __launch_bounds__(BS) void k_diag_inverse(int n, const int* __restric
                                                      float* __restrict__ d32) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i >= n) return;
-  const double d = 1.0 / val[diag[i]];
+  const double v = val[diag[i]];
+  const double d = (v != 0.0) ? 1.0 / v : 0.0;  // padding rows of stacked levels hold zeros
   d64[i] = d;
   if (d32) d32[i] = float(d);
 }

@@ -1,0 +1,610 @@
+// Batched kernels: every launch covers all instances of the batch (stacked
+// per-level P1 operators, stacked Krylov vectors with per-instance scalars).
+#include <hip/hip_runtime.h>
+
+#include "kernels_batch.hpp"
+
+namespace chns {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int W7 = 7;
+
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup (any multiple of 64 up to 1024); valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+template <typename T, int MODE, int RPT>
+__global__ void k_bstencil(int nrows, const int* __restrict__ col, const T* __restrict__ val,
+                           const T* __restrict__ x, const T* __restrict__ b,
+                           const T* __restrict__ dinv, T* __restrict__ d, T p0, T p1,
+                           const T* __restrict__ cc1, const T* __restrict__ cc2,
+                           const uint8_t* __restrict__ mask, const int* __restrict__ sinst,
+                           T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row0 = blk * blockDim.x * RPT + threadIdx.x;
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int row = row0 + rr * blockDim.x;
+    if (row >= nrows) continue;
+    const int slice = row >> 6;
+    if (mask && !mask[slice]) continue;
+    T c1 = p0, c2 = p1;
+    if (cc1) {
+      const int inst = sinst[slice];
+      c1 = cc1[inst];
+      c2 = cc2[inst];
+    }
+    if (MODE == 3) {
+      const T v = c2 * (dinv[row] * b[row]);
+      d[row] = v;
+      y[row] = v;
+      continue;
+    }
+    const size_t base = size_t(slice) * (64 * W7) + (row & 63);
+    int c[W7];
+    T v[W7];
+#pragma unroll
+    for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+#pragma unroll
+    for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
+    T sum = T(0);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) sum += v[k] * x[c[k]];
+    if (MODE == 0) {
+      y[row] = (c2 == T(0)) ? c1 * sum : c1 * sum + c2 * y[row];
+    } else if (MODE == 1) {
+      y[row] = b[row] - sum;
+    } else {
+      const T r = dinv[row] * (b[row] - sum);
+      const T dn = (c1 == T(0)) ? c2 * r : c1 * d[row] + c2 * r;
+      d[row] = dn;
+      y[row] = x[row] + dn;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_bspmv_uniform(int nrows, int width, const int* __restrict__ col,
+                                                      const T* __restrict__ val,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const T* __restrict__ x, T* __restrict__ y,
+                                                      T alpha, T beta) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= nrows) return;
+  const int slice = row >> 6;
+  if (mask && !mask[slice]) return;
+  const size_t base = size_t(slice) * 64 * width + (row & 63);
+  T sum = T(0);
+  for (int k = 0; k < width; ++k) sum += val[base + k * 64] * x[col[base + k * 64]];
+  y[row] = (beta == T(0)) ? alpha * sum : alpha * sum + beta * y[row];
+}
+
+template <typename T, bool L_IS_M>
+__global__ __launch_bounds__(BS) void k_bch_block(int n, const int* __restrict__ col,
+                                                  const int* __restrict__ sinst,
+                                                  const T* __restrict__ Lv, const T* __restrict__ Kv,
+                                                  const T* __restrict__ Mv,
+                                                  const T* __restrict__ c12a,
+                                                  const T* __restrict__ c22a,
+                                                  const T* __restrict__ x, T alpha, T beta,
+                                                  T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= n) return;
+  const int inst = sinst[row >> 6];
+  const T c12 = c12a[inst], c22 = c22a[inst];
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  const T* x1 = x;
+  const T* x2 = x + n;
+  int c[W7];
+  T kv[W7], mv[W7], lv[W7];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    kv[k] = Kv[base + k * 64];
+    mv[k] = Mv[base + k * 64];
+    if (!L_IS_M) lv[k] = Lv[base + k * 64];
+  }
+  T sl = T(0), sk1 = T(0), sk2 = T(0), sm = T(0);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const T a = x1[c[k]], bb = x2[c[k]];
+    sl += (L_IS_M ? mv[k] : lv[k]) * a;
+    sk1 += kv[k] * a;
+    sk2 += kv[k] * bb;
+    sm += mv[k] * bb;
+  }
+  const T y1 = alpha * (sl + c12 * sk2);
+  const T y2 = alpha * (c12 * sk1 + c22 * sm);
+  if (beta == T(0)) {
+    y[row] = y1;
+    y[n + row] = y2;
+  } else {
+    y[row] = y1 + beta * y[row];
+    y[n + row] = y2 + beta * y[n + row];
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_brhs_binary(int n, const int* __restrict__ col,
+                                                    const int* __restrict__ sinst,
+                                                    const double* __restrict__ Mv,
+                                                    const double* __restrict__ phi,
+                                                    const double* __restrict__ Phi,
+                                                    const double* __restrict__ c_mu,
+                                                    const double* __restrict__ c_ac,
+                                                    double* __restrict__ rhs_ch,
+                                                    double* __restrict__ rhs_ac) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= n) return;
+  const int inst = sinst[row >> 6];
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  double s_phi = 0.0, s_fp = 0.0, s_Phi = 0.0, s_fv = 0.0;
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const int j = col[base + k * 64];
+    const double m = Mv[base + k * 64];
+    const double ph = phi[j], P = Phi[j];
+    const double om = 1.0 - ph;
+    const double dliq = 2.0 * ph * om * om - 2.0 * ph * ph * om;
+    const double p = P * P * (3.0 - 2.0 * P);
+    const double dgas = 2.0 * ph - 2.0 * om;
+    const double fp = (1.0 - p) * dliq + p * dgas;
+    const double fv = 6.0 * P * (1.0 - P) * ((ph * ph + om * om) - ph * ph * om * om);
+    s_phi += m * ph;
+    s_fp += m * fp;
+    s_Phi += m * P;
+    s_fv += m * fv;
+  }
+  rhs_ch[row] = s_phi;
+  rhs_ch[n + row] = c_mu[inst] * s_fp;
+  rhs_ac[row] = s_Phi + c_ac[inst] * s_fv;
+}
+
+__global__ __launch_bounds__(BS) void k_bcombine(int64_t n, const int* __restrict__ sinst,
+                                                 const double* __restrict__ a,
+                                                 const double* __restrict__ A,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ B,
+                                                 double* __restrict__ o64, float* __restrict__ o32) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i >= n) return;
+  const int inst = sinst[i / (64 * W7)];
+  const double v = a[inst] * A[i] + b[inst] * B[i];
+  o64[i] = v;
+  if (o32) o32[i] = float(v);
+}
+
+// ---------------------------------------------------------------- Krylov
+
+constexpr int MD_G = 8;
+constexpr int RPC = BCHUNK / BS;  // rows per thread in a chunk
+
+__global__ __launch_bounds__(BS) void k_bmdot_partial(int64_t n, const double* __restrict__ V,
+                                                      int64_t ldv, int k,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ part,
+                                                      const int* __restrict__ flag,
+                                                      const int* __restrict__ cinst) {
+  const int c = blockIdx.x;
+  if (flag && flag[cinst[c]] == 0) return;
+  __shared__ double sh[16];
+  const int g0 = blockIdx.y * MD_G;
+  const int kk = min(MD_G, k - g0);
+  double acc[MD_G];
+#pragma unroll
+  for (int i = 0; i < MD_G; ++i) acc[i] = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RPC; ++rr) {
+    const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
+    const double wr = w[r];
+#pragma unroll
+    for (int i = 0; i < MD_G; ++i)
+      if (i < kk) acc[i] += V[(g0 + i) * ldv + r] * wr;
+  }
+  for (int i = 0; i < kk; ++i) {
+    const double s = block_sum(acc[i], sh);
+    if (threadIdx.x == 0) part[int64_t(g0 + i) * gridDim.x + c] = s;
+  }
+}
+
+__device__ double chunk_sum(const double* part, const int* cr, int half, int i) {
+  double s = 0.0;
+  for (int c = cr[2 * i] + int(threadIdx.x); c < cr[2 * i + 1]; c += blockDim.x) {
+    s += part[c];
+    if (half) s += part[c + half];
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(BS) void k_bmdot_reduce(int nchunk, int k, const double* __restrict__ part,
+                                                     const int* __restrict__ cr, int half,
+                                                     double* __restrict__ h, int hs,
+                                                     double* __restrict__ H, int Hs, int j, int ldH,
+                                                     int accumulate, const int* __restrict__ flag) {
+  const int i = blockIdx.x, v = blockIdx.y;
+  if (flag && flag[i] == 0) return;
+  __shared__ double sh[16];
+  const double s = block_sum(chunk_sum(part + int64_t(v) * nchunk, cr, half, i), sh);
+  if (threadIdx.x == 0) {
+    h[i * hs + v] = s;
+    double* hc = H + int64_t(i) * Hs + int64_t(j) * ldH;
+    hc[v] = accumulate ? hc[v] + s : s;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_bmaxpy(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                               int k, const double* __restrict__ h, int hs,
+                                               double* __restrict__ w,
+                                               double* __restrict__ nrm_part,
+                                               const int* __restrict__ flag,
+                                               const int* __restrict__ cinst) {
+  const int c = blockIdx.x;
+  const int inst = cinst[c];
+  if (flag && flag[inst] == 0) return;
+  __shared__ double hsh[80];
+  __shared__ double sh[16];
+  for (int i = threadIdx.x; i < k; i += BS) hsh[i] = h[inst * hs + i];
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RPC; ++rr) {
+    const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
+    double wr = w[r];
+    for (int i = 0; i < k; ++i) wr -= hsh[i] * V[i * ldv + r];
+    w[r] = wr;
+    acc += wr * wr;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) nrm_part[c] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_breorth_decide(int nchunk, const double* __restrict__ part,
+                                                       const int* __restrict__ cr, int half,
+                                                       const double* __restrict__ h, int hs,
+                                                       int wwpos, int* __restrict__ flag,
+                                                       double* __restrict__ nrm2) {
+  const int i = blockIdx.x;
+  __shared__ double sh[16];
+  const double s = block_sum(chunk_sum(part, cr, half, i), sh);
+  if (threadIdx.x == 0) {
+    nrm2[i] = s;
+    flag[i] = (s < 0.5 * h[i * hs + wwpos]) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_barnoldi_finish(int nchunk, const double* __restrict__ part2,
+                                                        const int* __restrict__ cr, int half,
+                                                        const int* __restrict__ flag,
+                                                        const double* __restrict__ nrm2, int j,
+                                                        int m, double* __restrict__ H,
+                                                        double* __restrict__ cs,
+                                                        double* __restrict__ sn,
+                                                        double* __restrict__ g,
+                                                        double* __restrict__ inv,
+                                                        const double* __restrict__ tol,
+                                                        int* __restrict__ active,
+                                                        int* __restrict__ kcols,
+                                                        int* __restrict__ iters) {
+  const int i = blockIdx.x;
+  __shared__ double sh[16];
+  const double s2 = block_sum(chunk_sum(part2, cr, half, i), sh);
+  if (threadIdx.x != 0) return;
+  if (!active[i]) {
+    inv[i] = 0.0;
+    return;
+  }
+  const double nrm = flag[i] ? sqrt(s2) : sqrt(nrm2[i]);
+  const int ld = m + 1;
+  double* Hi = H + int64_t(i) * (m + 1) * m;
+  double* h = Hi + int64_t(j) * ld;
+  double* csi = cs + i * (m + 1);
+  double* sni = sn + i * (m + 1);
+  double* gi = g + i * (m + 2);
+  h[j + 1] = nrm;
+  for (int l = 0; l < j; ++l) {
+    const double a = h[l], b = h[l + 1];
+    h[l] = csi[l] * a + sni[l] * b;
+    h[l + 1] = -sni[l] * a + csi[l] * b;
+  }
+  const double a = h[j], b = h[j + 1];
+  double cc, ss;
+  if (b == 0.0) {
+    cc = 1.0;
+    ss = 0.0;
+  } else if (fabs(b) > fabs(a)) {
+    const double t = a / b;
+    ss = 1.0 / sqrt(1.0 + t * t);
+    cc = t * ss;
+  } else {
+    const double t = b / a;
+    cc = 1.0 / sqrt(1.0 + t * t);
+    ss = t * cc;
+  }
+  csi[j] = cc;
+  sni[j] = ss;
+  h[j] = cc * a + ss * b;
+  h[j + 1] = 0.0;
+  gi[j + 1] = -ss * gi[j];
+  gi[j] = cc * gi[j];
+  iters[i] += 1;
+  const double est = fabs(gi[j + 1]);
+  if (!(est > tol[i]) || nrm == 0.0 || !isfinite(est)) {
+    active[i] = 0;
+    kcols[i] = j + 1;
+  }
+  inv[i] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+}
+
+__global__ __launch_bounds__(BS) void k_bscale(int64_t n, const double* __restrict__ w,
+                                               const double* __restrict__ inv,
+                                               const int* __restrict__ cinst,
+                                               double* __restrict__ v) {
+  const int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (r >= n) return;
+  v[r] = w[r] * inv[cinst[r / BCHUNK]];
+}
+
+__global__ void k_blsq(int count, int m, const double* __restrict__ H, const double* __restrict__ g,
+                       const int* __restrict__ kcols, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int k = kcols[i];
+  const int ld = m + 1;
+  const double* Hi = H + int64_t(i) * (m + 1) * m;
+  const double* gi = g + i * (m + 2);
+  double* yi = y + i * (m + 1);
+  for (int l = k; l < m; ++l) yi[l] = 0.0;
+  for (int l = k - 1; l >= 0; --l) {
+    double s = gi[l];
+    for (int q = l + 1; q < k; ++q) s -= Hi[int64_t(q) * ld + l] * yi[q];
+    yi[l] = s / Hi[int64_t(l) * ld + l];
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_bxupdate(int64_t n, const double* __restrict__ Z,
+                                                 int64_t ldz, int m, const double* __restrict__ y,
+                                                 double* __restrict__ x,
+                                                 const int* __restrict__ cinst) {
+  const int c = blockIdx.x;
+  const int inst = cinst[c];
+  __shared__ double ys[80];
+  for (int i = threadIdx.x; i < m; i += BS) ys[i] = y[inst * (m + 1) + i];
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < RPC; ++rr) {
+    const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
+    double s = x[r];
+    for (int i = 0; i < m; ++i) s += ys[i] * Z[i * ldz + r];
+    x[r] = s;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_bnorm_partial(int64_t n, const double* __restrict__ w,
+                                                      double* __restrict__ part) {
+  const int c = blockIdx.x;
+  __shared__ double sh[16];
+  double acc = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RPC; ++rr) {
+    const double v = w[int64_t(c) * BCHUNK + rr * BS + threadIdx.x];
+    acc += v * v;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[c] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_bnorm_finish(int nchunk, const double* __restrict__ part,
+                                                     const int* __restrict__ cr, int half, int m,
+                                                     int first, double rtol, double atol,
+                                                     double* __restrict__ nrm,
+                                                     double* __restrict__ inv,
+                                                     double* __restrict__ g,
+                                                     double* __restrict__ tol,
+                                                     int* __restrict__ active,
+                                                     int* __restrict__ kcols) {
+  const int i = blockIdx.x;
+  __shared__ double sh[16];
+  const double s = block_sum(chunk_sum(part, cr, half, i), sh);
+  if (threadIdx.x != 0) return;
+  const double v = sqrt(s);
+  nrm[i] = v;
+  if (first) {
+    tol[i] = fmax(rtol * v, atol);
+    return;
+  }
+  const int act = (v > tol[i]) && isfinite(v);
+  active[i] = act;
+  kcols[i] = act ? m : 0;
+  inv[i] = (act && v > 0.0) ? 1.0 / v : 0.0;
+  double* gi = g + i * (m + 2);
+  gi[0] = v;
+  for (int l = 1; l < m + 2; ++l) gi[l] = 0.0;
+}
+
+__global__ __launch_bounds__(BS) void k_dcopy(int64_t n, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+__global__ __launch_bounds__(BS) void k_dfill_int(int64_t n, int v, int* __restrict__ x) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+}  // namespace
+
+// ================================================================== launchers
+
+template <typename T, int MODE>
+static void launch_bstencil(const BStencil& A, const T* val, const T* x, const T* b, const T* dinv,
+                            T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, T* y,
+                            hipStream_t s) {
+  const int rows_per_block = A.block * A.rpt;
+  const dim3 g(ceil_div(A.nrows, rows_per_block)), blk(A.block);
+  if (A.rpt == 4)
+    hipLaunchKernelGGL((k_bstencil<T, MODE, 4>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
+                       p0, p1, cc1, cc2, mask, A.sinst, y);
+  else if (A.rpt == 2)
+    hipLaunchKernelGGL((k_bstencil<T, MODE, 2>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
+                       p0, p1, cc1, cc2, mask, A.sinst, y);
+  else
+    hipLaunchKernelGGL((k_bstencil<T, MODE, 1>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
+                       p0, p1, cc1, cc2, mask, A.sinst, y);
+}
+
+template <typename T>
+void bstencil(const BStencil& A, const T* val, int mode, const T* x, const T* b, const T* dinv,
+              T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, T* y,
+              hipStream_t s) {
+  switch (mode) {
+    case 0: launch_bstencil<T, 0>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
+    case 1: launch_bstencil<T, 1>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
+    case 2: launch_bstencil<T, 2>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
+    default: launch_bstencil<T, 3>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
+  }
+}
+
+template <typename T>
+void bspmv_uniform(int nrows, int width, const int* col, const T* val, const uint8_t* mask,
+                   const T* x, T* y, T alpha, T beta, hipStream_t s) {
+  hipLaunchKernelGGL((k_bspmv_uniform<T>), dim3(ceil_div(nrows, BS)), dim3(BS), 0, s, nrows, width,
+                     col, val, mask, x, y, alpha, beta);
+}
+
+template <typename T>
+void bch_block(const BStencil& A, const T* L, const T* K, const T* M, const T* c12, const T* c22,
+               const T* x, T alpha, T beta, T* y, hipStream_t s) {
+  const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
+  if (L == M)
+    hipLaunchKernelGGL((k_bch_block<T, true>), g, blk, 0, s, A.nrows, A.col, A.sinst, L, K, M, c12,
+                       c22, x, alpha, beta, y);
+  else
+    hipLaunchKernelGGL((k_bch_block<T, false>), g, blk, 0, s, A.nrows, A.col, A.sinst, L, K, M, c12,
+                       c22, x, alpha, beta, y);
+}
+
+void brhs_binary(const BStencil& A, const double* Mv, const double* phi, const double* Phi,
+                 const double* c_mu, const double* c_ac, double* rhs_ch, double* rhs_ac,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_brhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col,
+                     A.sinst, Mv, phi, Phi, c_mu, c_ac, rhs_ch, rhs_ac);
+}
+
+void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A, const double* b,
+              const double* B, double* out64, float* out32, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcombine, dim3(ceil_div(nslots, BS)), dim3(BS), 0, s, nslots, sinst, a, A,
+                     b, B, out64, out32);
+}
+
+void bmdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
+                   const int* flag, const int* cinst, hipStream_t s) {
+  const int nchunk = int(n / BCHUNK);
+  hipLaunchKernelGGL(k_bmdot_partial, dim3(nchunk, ceil_div(k, MD_G)), dim3(BS), 0, s, n, V, ldv, k,
+                     w, part, flag, cinst);
+}
+
+void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* cr, int half,
+                  double* h, int hs, double* H, int Hs, int j, int ldH, int accumulate,
+                  const int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmdot_reduce, dim3(count, k), dim3(BS), 0, s, nchunk, k, part, cr, half, h,
+                     hs, H, Hs, j, ldH, accumulate, flag);
+}
+
+void bmaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, int hs, double* w,
+            double* nrm_part, const int* flag, const int* cinst, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmaxpy, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, V, ldv, k, h, hs, w,
+                     nrm_part, flag, cinst);
+}
+
+void breorth_decide(int count, int nchunk, const double* part, const int* cr, int half,
+                    const double* h, int hs, int wwpos, int* flag, double* nrm2, hipStream_t s) {
+  hipLaunchKernelGGL(k_breorth_decide, dim3(count), dim3(BS), 0, s, nchunk, part, cr, half, h, hs,
+                     wwpos, flag, nrm2);
+}
+
+void barnoldi_finish(int count, int nchunk, const double* part2, const int* cr, int half,
+                     const int* flag, const double* nrm2, int j, int m, double* H, double* cs,
+                     double* sn, double* g, double* inv, const double* tol, int* active,
+                     int* kcols, int* iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_barnoldi_finish, dim3(count), dim3(BS), 0, s, nchunk, part2, cr, half, flag,
+                     nrm2, j, m, H, cs, sn, g, inv, tol, active, kcols, iters);
+}
+
+void bscale(int64_t n, const double* w, const double* inv, const int* cinst, double* v,
+            hipStream_t s) {
+  hipLaunchKernelGGL(k_bscale, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, w, inv, cinst, v);
+}
+
+void blsq(int count, int m, const double* H, const double* g, const int* kcols, double* y,
+          hipStream_t s) {
+  hipLaunchKernelGGL(k_blsq, dim3(ceil_div(count, 64)), dim3(64), 0, s, count, m, H, g, kcols, y);
+}
+
+void bxupdate(int64_t n, const double* Z, int64_t ldz, int m, const double* y, double* x,
+              const int* cinst, hipStream_t s) {
+  hipLaunchKernelGGL(k_bxupdate, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, Z, ldz, m, y, x, cinst);
+}
+
+void bnorm_partial(int64_t n, const double* w, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_bnorm_partial, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, w, part);
+}
+
+void bnorm_finish(int count, int nchunk, const double* part, const int* cr, int half, int m,
+                  int first, double rtol, double atol, double* nrm, double* inv, double* g,
+                  double* tol, int* active, int* kcols, hipStream_t s) {
+  hipLaunchKernelGGL(k_bnorm_finish, dim3(count), dim3(BS), 0, s, nchunk, part, cr, half, m, first,
+                     rtol, atol, nrm, inv, g, tol, active, kcols);
+}
+
+void dcopy(int64_t n, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcopy, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, y);
+}
+
+void dfill_int(int64_t n, int v, int* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_dfill_int, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, v, x);
+}
+
+template void bstencil<double>(const BStencil&, const double*, int, const double*, const double*,
+                               const double*, double*, double, double, const double*,
+                               const double*, const uint8_t*, double*, hipStream_t);
+template void bstencil<float>(const BStencil&, const float*, int, const float*, const float*,
+                              const float*, float*, float, float, const float*, const float*,
+                              const uint8_t*, float*, hipStream_t);
+template void bspmv_uniform<double>(int, int, const int*, const double*, const uint8_t*,
+                                    const double*, double*, double, double, hipStream_t);
+template void bspmv_uniform<float>(int, int, const int*, const float*, const uint8_t*,
+                                   const float*, float*, float, float, hipStream_t);
+template void bch_block<double>(const BStencil&, const double*, const double*, const double*,
+                                const double*, const double*, const double*, double, double,
+                                double*, hipStream_t);
+
+}  // namespace chns

@@ -1,0 +1,102 @@
+// Launchers of the batched kernels (definitions in kernels_batch.hip).
+//
+// Batched layout: every instance's level-l P1 matrix is a uniform width-7
+// SELL-C-64 block; the blocks of all instances present on level l are
+// stacked (columns offset by the instance's row offset), so one launch covers
+// every instance.  Instance row counts are multiples of 1024, so a 1024-row
+// chunk (and a 64-row slice) never straddles two instances.  Per-slice masks
+// select the instances an operation applies to on a level; per-slice
+// instance ids look up per-instance scalars.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace chns {
+
+constexpr int BCHUNK = 1024;  // rows per reduction chunk
+
+struct BStencil {
+  int nrows = 0;
+  const int* col = nullptr;
+  const int* sinst = nullptr;     // slice -> instance
+  int rpt = 1;                    // rows per thread (1, 2, 4)
+  int block = 256;                // workgroup size
+};
+
+// Modes: 0 SPMV (y = p0 A x + p1 y), 1 RESID (y = b - A x),
+// 2 CHEB (d <- c1 d + c2 dinv (b - A x), y = x + d; per-instance c1/c2 when
+// cc1/cc2 are given, else p0/p1), 3 CHEB0 (x = d = c2 dinv b).
+// mask (per slice, may be null): rows of slices with mask 0 are skipped.
+template <typename T>
+void bstencil(const BStencil& A, const T* val, int mode, const T* x, const T* b, const T* dinv,
+              T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, T* y,
+              hipStream_t s);
+
+// General uniform-width SELL product with a per-slice mask of output rows.
+template <typename T>
+void bspmv_uniform(int nrows, int width, const int* col, const T* val, const uint8_t* mask,
+                   const T* x, T* y, T alpha, T beta, hipStream_t s);
+
+// Stacked CH block on [phi_all; mu_all]: per-instance c12, c22.
+template <typename T>
+void bch_block(const BStencil& A, const T* L, const T* K, const T* M, const T* c12, const T* c22,
+               const T* x, T alpha, T beta, T* y, hipStream_t s);
+
+// Right-hand sides with per-instance c_mu, c_ac.
+void brhs_binary(const BStencil& A, const double* Mv, const double* phi, const double* Phi,
+                 const double* c_mu, const double* c_ac, double* rhs_ch, double* rhs_ac,
+                 hipStream_t s);
+
+// Per-instance combine: out = a_i A + b_i B (coefficients per slice instance).
+void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A, const double* b,
+              const double* B, double* out64, float* out32, hipStream_t s);
+
+// ---------------------------------------------------------------- batched Krylov
+// Block vectors of length n (multiple of BCHUNK); chunk c belongs to
+// instance cinst[c].  Per-instance arrays are indexed [inst * stride + j].
+
+// part[v * nchunk + c] = sum over chunk c of V_v . w (v < k); V_v = V + v*ldv.
+void bmdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
+                   const int* flag, const int* cinst, hipStream_t s);
+// For each instance: h[i*hs + v] = sum of its chunks; hcol (H column j of each
+// instance, stride Hs) set or accumulated.  Instance chunk list: ranges
+// [cr[2i], cr[2i+1]) and, when two_ranges, [cr[2i] + half, cr[2i+1] + half).
+void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* cr, int half,
+                  double* h, int hs, double* H, int Hs, int j, int ldH, int accumulate,
+                  const int* flag, hipStream_t s);
+// w -= V h_inst (k columns) with per-chunk w^2 partials.
+void bmaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, int hs, double* w,
+            double* nrm_part, const int* flag, const int* cinst, hipStream_t s);
+// Per instance: ||w'||^2 from partials; flag_i = (||w'||^2 < ||w||^2 / 2), ww = h[i*hs + wwpos].
+void breorth_decide(int count, int nchunk, const double* part, const int* cr, int half,
+                    const double* h, int hs, int wwpos, int* flag, double* nrm2, hipStream_t s);
+// Per instance: norm, Givens update of column j, residual estimate, activity.
+void barnoldi_finish(int count, int nchunk, const double* part2, const int* cr, int half,
+                     const int* flag, const double* nrm2, int j, int m, double* H, double* cs,
+                     double* sn, double* g, double* inv, const double* tol, int* active,
+                     int* kcols, int* iters, hipStream_t s);
+// x = x * inv[inst] on chunks (v may alias w).
+void bscale(int64_t n, const double* w, const double* inv, const int* cinst, double* v,
+            hipStream_t s);
+// Per instance: y = R^{-1} g on its kcols columns (rest 0).
+void blsq(int count, int m, const double* H, const double* g, const int* kcols, double* y,
+          hipStream_t s);
+// x += Z y_inst (m columns).
+void bxupdate(int64_t n, const double* Z, int64_t ldz, int m, const double* y, double* x,
+              const int* cinst, hipStream_t s);
+// Per-instance norms: part[c] = sum w^2 over chunk c; then norm_i, inv_i,
+// g_i = [norm, 0..]; first: tol_i = max(rtol norm_i, atol), active_i = 1;
+// else active_i = (norm_i > tol_i) and kcols_i = m.
+void bnorm_partial(int64_t n, const double* w, double* part, hipStream_t s);
+void bnorm_finish(int count, int nchunk, const double* part, const int* cr, int half, int m,
+                  int first, double rtol, double atol, double* nrm, double* inv, double* g,
+                  double* tol, int* active, int* kcols, hipStream_t s);
+
+// Plain copy and fill kernels (kept out of runtime memset/memcpy so that a
+// captured graph holds kernel nodes only).
+void dcopy(int64_t n, const double* x, double* y, hipStream_t s);
+void dfill_int(int64_t n, int v, int* x, hipStream_t s);
+
+}  // namespace chns

@@ -1,0 +1,143 @@
+"""GPU parity of the batched form: every instance of a batch of uneven sizes and
+parameters against the oracle's exact (Fourier-mode) step, the hipGraph
+replays against the eager run, mixed precision, and the autotuner.
+
+Bars: FP64 instances within 1e-9 of the exact step at rtol 1e-12 (condition
+numbers <= 1e3 for these parameters); mixed precision within 1e-7 at rtol
+1e-10; graph replays equal to the eager run to 1e-13 (the same kernels run on
+the same data; the eager run only stops the restart loop earlier).
+"""
+import numpy as np
+import pytest
+
+from oracle import solvers, potential as pot
+from oracle.systems import Params
+from paper_2501_11767_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [32, 64, 32, 128, 64, 96]
+
+
+def _params(count, seed=11):
+    g = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        out.append(dict(eps=float(np.exp(g.uniform(np.log(0.01), np.log(0.05)))),
+                        tau=float(np.exp(g.uniform(np.log(1e-5), np.log(1e-3)))),
+                        mobility=float(np.exp(g.uniform(np.log(0.1), np.log(10.0)))),
+                        evap_rate=float(np.exp(g.uniform(np.log(0.01), np.log(1.0))))))
+    return out
+
+
+def _fields(sizes, seed=5):
+    phi, Phi = [], []
+    for k, n in enumerate(sizes):
+        st = inputs.initial_state(n, "ch_ac", 0.4, seed + k)
+        phi.append(st["phi"][0])
+        Phi.append(st["Phi_v"])
+    return np.concatenate(phi), np.concatenate(Phi)
+
+
+def _oracle(n, p, phi0, Phi0):
+    prm = Params(eps=p["eps"], tau=p["tau"], mobility=p["mobility"], evap_rate=p["evap_rate"])
+    Kh, Mh = solvers.p1_symbols(n)
+    Mx = lambda v: np.real(np.fft.ifft2(Mh * np.fft.fft2(v.reshape(n, n)))).ravel()
+    fp, fv = pot.dfdphi_bin(phi0, Phi0), pot.dfdPhi_bin(phi0, Phi0)
+    ph, mu = solvers.fft_ch_solve(n, prm, Mx(phi0), -(prm.tau * prm.gamma / prm.beta) * Mx(fp))
+    Ph = solvers.fft_ac_solve(n, prm, Mx(Phi0) - prm.tau * prm.gamma_v * Mx(fv))
+    return ph, mu, Ph
+
+
+@pytest.fixture(scope="module")
+def chns():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_11767_amd import chns as C
+    C.lib()
+    return C
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(chns, batch, phi0, Phi0, opts, **kw):
+    import torch
+    phi, Phi = _dev(phi0), _dev(Phi0)
+    mu = torch.zeros_like(phi)
+    rc, info = batch.timestep(phi, mu, Phi, 1, opts, **kw)
+    torch.cuda.synchronize()
+    return rc, info, phi.cpu().numpy(), mu.cpu().numpy(), Phi.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision,rtol,bar", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
+def test_batch_instances_match_oracle(chns, precision, rtol, bar):
+    prm = _params(len(SIZES))
+    batch = chns.Batch(SIZES, prm)
+    off = batch.offsets
+    assert list(np.diff(off)) == [n * n for n in SIZES]
+    phi0, Phi0 = _fields(SIZES)
+    rc, info, phi, mu, Phi = _run(chns, batch, phi0, Phi0,
+                                  chns.default_opts(rtol=rtol, precision=precision, maxiter=400))
+    assert rc == chns.OK and info["conv_ch"].all() and info["conv_ac"].all(), info
+    for i, n in enumerate(SIZES):
+        sl = slice(off[i], off[i + 1])
+        ph, m, Ph = _oracle(n, prm[i], phi0[sl], Phi0[sl])
+        rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+        assert rel(phi[sl], ph) < bar, (i, rel(phi[sl], ph))
+        assert rel(mu[sl], m) < 100 * bar, (i, rel(mu[sl], m))
+        assert rel(Phi[sl], Ph) < bar, (i, rel(Phi[sl], Ph))
+    batch.close()
+
+
+def test_batch_graph_replays_match_eager(chns):
+    import torch
+    prm = _params(len(SIZES), seed=3)
+    batch = chns.Batch(SIZES, prm)
+    phi0, Phi0 = _fields(SIZES, seed=9)
+    opts = chns.default_opts(rtol=1e-10, precision=1, maxiter=200)
+    _, info_e, phi_e, mu_e, Phi_e = _run(chns, batch, phi0, Phi0, opts)
+    s = torch.cuda.Stream()
+    phi, Phi = _dev(phi0), _dev(Phi0)
+    mu = torch.zeros_like(phi)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            phi.copy_(_dev(phi0))
+            Phi.copy_(_dev(Phi0))
+            mu.zero_()
+        s.synchronize()
+        rc, info = batch.timestep(phi, mu, Phi, 1, opts, use_graph=True, stream=s)
+        s.synchronize()
+        assert rc == chns.OK, info
+        # eager work between replays
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+        for got, ref in ((phi, phi_e), (mu, mu_e), (Phi, Phi_e)):
+            g = got.cpu().numpy()
+            assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max(), rep
+        assert (info["iters_ch"] == info_e["iters_ch"]).all()
+    batch.close()
+
+
+def test_batch_autotuner_keeps_results(chns, tmp_path):
+    prm = _params(4, seed=7)
+    sizes = [64, 32, 128, 64]
+    batch = chns.Batch(sizes, prm)
+    phi0, Phi0 = _fields(sizes, seed=1)
+    opts = chns.default_opts(rtol=1e-10, precision=0, maxiter=200)
+    _, _, a, _, _ = _run(chns, batch, phi0, Phi0, opts)
+    cache = str(tmp_path / "tune.txt")
+    batch.tune(cache)
+    lines = open(cache).read().split("\n")
+    assert lines[0] == "gfx950" and len([l for l in lines[1:] if l.strip()]) >= 3
+    _, _, b, _, _ = _run(chns, batch, phi0, Phi0, opts)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    batch.tune(cache)  # read back from the cache
+    batch.close()
+
+
+def test_batch_rejects_bad_sizes(chns):
+    with pytest.raises(chns.ChnsError):
+        chns.Batch([48], _params(1))
