@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--dry-steps", type=int, default=5)
+    ap.add_argument("--batch-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -181,6 +182,78 @@ def dry_section(chns, steps):
                 iters_ch_p_ch_n_ac_ns=its, steps=steps)
 
 
+def batch_section(chns, steps):
+    """64 independent CH + AC instances (sizes drawn from {64, 128, 256, 512}^2,
+    parameters log-uniform) advanced together: FP32 multigrid inside FP64
+    FGMRES, autotuned launch shapes, `steps` steps captured in one hipGraph
+    (each step solves the seeded first-step systems).  Compared with the
+    plain FP64 solve of the same 64 steps one instance at a time."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    inst = inputs.batch_instances()
+    sizes = [d["n"] for d in inst]
+    prm = [dict(eps=d["eps"], tau=d["tau"], mobility=d["mobility"], evap_rate=d["evap_rate"])
+           for d in inst]
+    phi0, Phi0 = [], []
+    for d in inst:
+        st = inputs.initial_state(d["n"], "ch_ac", 0.4, d["seed"])
+        phi0.append(st["phi"][0])
+        Phi0.append(st["Phi_v"])
+    phi0, Phi0 = np.concatenate(phi0), np.concatenate(Phi0)
+    Ntot = len(phi0)
+    t0 = time.perf_counter()
+    batch = chns.Batch(sizes, prm)
+    setup = time.perf_counter() - t0
+    s = torch.cuda.Stream()
+    zin = [dev(phi0), torch.zeros(Ntot, dtype=torch.float64, device="cuda"), dev(Phi0)]
+    out = [torch.empty(Ntot, dtype=torch.float64, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    batch.tune(None, stream=s)
+    opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=40, maxiter=120)
+    # capture (first call) then timed replay
+    batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out, each_from_input=True)
+    rc, info = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out,
+                              each_from_input=True)
+    graph_ms = info["ms"] / steps
+    rc_e, info_e = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=False, stream=s, out=out,
+                                  each_from_input=True)
+    eager_ms = info_e["ms"] / steps
+    o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=40, maxiter=120)
+    rc_f, info_f = batch.timestep(*zin, nsteps=1, opts=o64, use_graph=False, stream=s, out=out)
+    batch.close()
+    di = float(sum(2 * n * n * a + n * n * b for n, a, b in zip(sizes, info["iters_ch"], info["iters_ac"])))
+    # one instance at a time, plain FP64, one context per size
+    ctxs, seq_ms, seq_its = {}, 0.0, 0
+    off = np.concatenate([[0], np.cumsum([n * n for n in sizes])])
+    opts_seq = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=40, maxiter=600)
+    for i, (n, p) in enumerate(zip(sizes, prm)):
+        if n not in ctxs:
+            ctxs[n] = chns.Context(n, "ch_ac", **p)
+        c = ctxs[n]
+        c.set_params(**p)
+        sl = slice(int(off[i]), int(off[i + 1]))
+        fi = c.fields(phi=[zin[0][sl].contiguous()], mu=[zin[1][sl].contiguous()], Phi_v=zin[2][sl].contiguous())
+        fo = c.fields(phi=[out[0][sl].contiguous()], mu=[out[1][sl].contiguous()], Phi_v=out[2][sl].contiguous())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, inf = c.timestep(fi, fo, 1, opts_seq)
+        torch.cuda.synchronize()
+        seq_ms += (time.perf_counter() - t1) * 1e3
+        seq_its += inf[0]["iters"]
+    for c in ctxs.values():
+        c.close()
+    return dict(workload=f"batch64: 64 CH + AC instances, sizes {sorted(set(sizes))} "
+                         f"({Ntot} nodes, {3 * Ntot} unknowns), log-uniform eps, tau, mobility, "
+                         f"evaporation rate; FP32 multigrid in FP64 FGMRES(40), rtol 1e-8",
+                graph_ms_per_step=graph_ms, eager_ms_per_step=eager_ms,
+                sequential_fp64_ms_per_step=seq_ms, speedup_vs_sequential_fp64=seq_ms / graph_ms,
+                dof_iters_per_s=di / (graph_ms * 1e-3),
+                converged=int(info["conv_ch"].sum() + info["conv_ac"].sum()), solves=2 * len(sizes),
+                batch_fp64_converged=int(info_f["conv_ch"].sum() + info_f["conv_ac"].sum()),
+                iters_ch_max=int(info["iters_ch"].max()), iters_ch_mean=float(info["iters_ch"].mean()),
+                sequential_fp64_iters_ch_mean=seq_its / len(sizes), setup_s=setup, graph_steps=steps)
+
+
 def oracle_errors(cfg, n, st0, sweep, sweep_fields):
     """CPU leg: the oracle's exact solve of each swept step (convection-free
     periodic systems, one 2x2 solve per Fourier mode) and the relative error
@@ -267,6 +340,7 @@ def main():
             sweep.append(row)
         ctx.set_params(**p)
     dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
+    bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, n, args.tau)
@@ -301,6 +375,7 @@ def main():
         "kernels": kern,
         "sweep": sweep,
         "dry256": dry,
+        "batch64": bat,
     }
     ctx.close()
     print(json.dumps(line))

@@ -249,8 +249,10 @@ CHNS_API int chns_batch_create(int32_t count, const int32_t* h_n, const chns_par
 CHNS_API int chns_batch_destroy(chns_batch* b);
 /* h_offsets[count + 1]: node offsets of the instances in the packed fields. */
 CHNS_API int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets);
-/* Advance all instances nsteps steps in place (d_phi, d_mu, d_Phi packed,
- * FP64).  Each block (the stacked CH blocks, then the stacked AC matrices) is
+/* Advance all instances nsteps steps (packed FP64 fields): the first step
+ * reads in_*, every later step reads the previous step's output d_* (or
+ * in_* again when each_from_input != 0, which repeats the first step's
+ * systems); outputs go to d_*, which may equal in_* (in-place).  Each block (the stacked CH blocks, then the stacked AC matrices) is
  * solved by FGMRES with per-instance Krylov scalars on the device and a fixed
  * budget of ceil(maxiter / restart) restart cycles; an instance stops updating
  * once its true or estimated residual meets its own tolerance.  opts->mg_cycles
@@ -261,9 +263,11 @@ CHNS_API int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets);
  * steps of the last step, CH then AC; h_conv (2*count, may be NULL): 1 where
  * the recomputed true residual met the tolerance; h_ms: wall time.
  * Returns CHNS_WNOCONV if any instance did not converge.  Synchronising. */
-CHNS_API int chns_batch_timestep(chns_batch* b, double* d_phi, double* d_mu, double* d_Phi,
-                                 int32_t nsteps, const chns_solve_opts* opts, int32_t use_graph,
-                                 int32_t* h_iters, int32_t* h_conv, double* h_ms, void* stream);
+CHNS_API int chns_batch_timestep(chns_batch* b, const double* in_phi, const double* in_mu,
+                                 const double* in_Phi, double* d_phi, double* d_mu, double* d_Phi,
+                                 int32_t nsteps, int32_t each_from_input,
+                                 const chns_solve_opts* opts, int32_t use_graph, int32_t* h_iters,
+                                 int32_t* h_conv, double* h_ms, void* stream);
 /* Autotuner: time the batched smoothing kernel on every level in launch shapes
  * rows-per-thread {1, 2, 4} x workgroup {128, 256, 512, 1024} and keep the
  * fastest per level.  cache_path (may be NULL): a text file "gfx950" followed

@@ -96,8 +96,8 @@ def lib():
     L.chns_batch_create.argtypes = [i32, vp, vp, ct.POINTER(vp)]
     L.chns_batch_destroy.argtypes = [vp]
     L.chns_batch_offsets.argtypes = [vp, vp]
-    L.chns_batch_timestep.argtypes = [vp, vp, vp, vp, i32, ct.POINTER(SolveOpts), i32, vp, vp,
-                                      ct.POINTER(ct.c_double), vp]
+    L.chns_batch_timestep.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, ct.POINTER(SolveOpts),
+                                      i32, vp, vp, ct.POINTER(ct.c_double), vp]
     L.chns_batch_tune.argtypes = [vp, ct.c_char_p, vp]
     L.chns_batch_last_error.argtypes = [vp]
     L.chns_batch_last_error.restype = ct.c_char_p
@@ -283,15 +283,19 @@ class Batch:
         s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
         self._check(self.L.chns_batch_tune(self.h, cache_path.encode() if cache_path else None, s))
 
-    def timestep(self, phi, mu, Phi, nsteps=1, opts=None, use_graph=False, stream=None):
+    def timestep(self, phi, mu, Phi, nsteps=1, opts=None, use_graph=False, stream=None,
+                 out=None, each_from_input=False):
+        """Advance in place, or from (phi, mu, Phi) into out = (phi', mu', Phi')."""
         import numpy as np
         o = opts or default_opts()
+        dst = out if out is not None else (phi, mu, Phi)
         it = np.zeros(2 * self.count, dtype=np.int32)
         cv = np.zeros(2 * self.count, dtype=np.int32)
         ms = ct.c_double()
         s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
         rc = self._check(self.L.chns_batch_timestep(
-            self.h, _ptr(phi), _ptr(mu), _ptr(Phi), nsteps, ct.byref(o), int(use_graph),
+            self.h, _ptr(phi), _ptr(mu), _ptr(Phi), _ptr(dst[0]), _ptr(dst[1]), _ptr(dst[2]), nsteps,
+            int(each_from_input), ct.byref(o), int(use_graph),
             it.ctypes.data_as(ct.c_void_p), cv.ctypes.data_as(ct.c_void_p), ct.byref(ms), s))
         return rc, dict(iters_ch=it[:self.count], iters_ac=it[self.count:], conv_ch=cv[:self.count],
                         conv_ac=cv[self.count:], ms=ms.value)

@@ -565,8 +565,10 @@ int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_s
   return CHNS_OK;
 }
 
-int bstep(chns_batch* b, double* phi, double* mu, double* Phi, const chns_solve_opts& o, bool sync_check,
-          hipStream_t s) {
+// One step from (phi, mu, Phi) into (ophi, omu, oPhi); the sources are read
+// before any output is written, so the two sets may coincide.
+int bstep(chns_batch* b, const double* phi, const double* mu, const double* Phi, double* ophi,
+          double* omu, double* oPhi, const chns_solve_opts& o, bool sync_check, hipStream_t s) {
   const int64_t N = b->Ntot;
   BLevel& L0 = b->lv[0];
   brhs_binary(L0.st, L0.M, phi, Phi, b->cmu, b->cac, b->rhs_ch, b->rhs_ac, s);
@@ -575,9 +577,9 @@ int bstep(chns_batch* b, double* phi, double* mu, double* Phi, const chns_solve_
   dcopy(N, Phi, b->xac, s);
   BTRY(bfgmres(b, CHNS_BLOCK_CH, b->rhs_ch, b->xch, o, sync_check, s));
   BTRY(bfgmres(b, CHNS_BLOCK_AC, b->rhs_ac, b->xac, o, sync_check, s));
-  dcopy(N, b->xch, phi, s);
-  dcopy(N, b->xch + N, mu, s);
-  dcopy(N, b->xac, Phi, s);
+  dcopy(N, b->xch, ophi, s);
+  dcopy(N, b->xch + N, omu, s);
+  dcopy(N, b->xac, oPhi, s);
   BCHK(b, hipGetLastError());
   return CHNS_OK;
 }
@@ -778,30 +780,39 @@ int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets) {
   return CHNS_OK;
 }
 
-int chns_batch_timestep(chns_batch* b, double* d_phi, double* d_mu, double* d_Phi, int32_t nsteps,
-                        const chns_solve_opts* opts, int32_t use_graph, int32_t* h_iters,
-                        int32_t* h_conv, double* h_ms, void* stream) {
+int chns_batch_timestep(chns_batch* b, const double* in_phi, const double* in_mu, const double* in_Phi,
+                        double* d_phi, double* d_mu, double* d_Phi, int32_t nsteps,
+                        int32_t each_from_input, const chns_solve_opts* opts, int32_t use_graph,
+                        int32_t* h_iters, int32_t* h_conv, double* h_ms, void* stream) {
   if (!b) return CHNS_EINVAL;
   BTRY(check_bopts(b, opts));
-  if (!d_phi || !d_mu || !d_Phi || nsteps < 1 || nsteps > 1000)
+  if (!in_phi || !in_mu || !in_Phi || !d_phi || !d_mu || !d_Phi || nsteps < 1 || nsteps > 1000)
     return fail(b, CHNS_EINVAL, "fields must be non-NULL and nsteps in 1..1000");
+  auto run = [&](bool sync) -> int {
+    for (int k = 0; k < nsteps; ++k) {
+      const bool from_in = (k == 0) || each_from_input;
+      BTRY(bstep(b, from_in ? in_phi : d_phi, from_in ? in_mu : d_mu, from_in ? in_Phi : d_Phi, d_phi,
+                 d_mu, d_Phi, *opts, sync, static_cast<hipStream_t>(stream)));
+    }
+    return CHNS_OK;
+  };
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (use_graph && !s) return fail(b, CHNS_EINVAL, "graph capture needs a non-default stream");
   BTRY(prepare_cycles(b, *opts));
   BCHK(b, hipEventRecord(b->ev0, s));
   if (use_graph) {
     char key[512];
-    std::snprintf(key, sizeof key, "%p/%p/%p/%d/%p/%s/%d/%d/%d/%.17g/%.17g", (void*)d_phi, (void*)d_mu,
-                  (void*)d_Phi, nsteps, (void*)s, b->opts_key.c_str(), opts->restart, opts->maxiter,
-                  opts->precision, opts->rtol, opts->atol);
+    std::snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%p/%d/%d/%p/%s/%d/%d/%d/%.17g/%.17g", (const void*)in_phi,
+                  (const void*)in_mu, (const void*)in_Phi, (void*)d_phi, (void*)d_mu, (void*)d_Phi,
+                  nsteps, each_from_input, (void*)s, b->opts_key.c_str(), opts->restart,
+                  opts->maxiter, opts->precision, opts->rtol, opts->atol);
     if (b->graph_key != key) {
       if (b->exec) (void)hipGraphExecDestroy(b->exec);
       if (b->graph) (void)hipGraphDestroy(b->graph);
       b->exec = nullptr;
       b->graph = nullptr;
       BCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      int rc = CHNS_OK;
-      for (int k = 0; k < nsteps && rc == CHNS_OK; ++k) rc = bstep(b, d_phi, d_mu, d_Phi, *opts, false, s);
+      const int rc = run(false);
       hipGraph_t gr = nullptr;
       const hipError_t e = hipStreamEndCapture(s, &gr);
       if (rc < 0) {
@@ -815,7 +826,7 @@ int chns_batch_timestep(chns_batch* b, double* d_phi, double* d_mu, double* d_Ph
     }
     BCHK(b, hipGraphLaunch(b->exec, s));
   } else {
-    for (int k = 0; k < nsteps; ++k) BTRY(bstep(b, d_phi, d_mu, d_Phi, *opts, true, s));
+    BTRY(run(true));
   }
   BCHK(b, hipEventRecord(b->ev1, s));
   BCHK(b, hipEventSynchronize(b->ev1));
