@@ -47,6 +47,11 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def dev(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -201,6 +206,7 @@ def batch_section(chns, steps):
         Phi0.append(st["Phi_v"])
     phi0, Phi0 = np.concatenate(phi0), np.concatenate(Phi0)
     Ntot = len(phi0)
+    log(f"batch64: create ({Ntot} nodes)")
     t0 = time.perf_counter()
     batch = chns.Batch(sizes, prm)
     setup = time.perf_counter() - t0
@@ -208,16 +214,22 @@ def batch_section(chns, steps):
     zin = [dev(phi0), torch.zeros(Ntot, dtype=torch.float64, device="cuda"), dev(Phi0)]
     out = [torch.empty(Ntot, dtype=torch.float64, device="cuda") for _ in range(3)]
     torch.cuda.synchronize()
+    log("batch64: tune")
     batch.tune(None, stream=s)
     opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=40, maxiter=120)
-    # capture (first call) then timed replay
-    batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out, each_from_input=True)
-    rc, info = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out,
-                              each_from_input=True)
-    graph_ms = info["ms"] / steps
+    log("batch64: eager steps")
     rc_e, info_e = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=False, stream=s, out=out,
                                   each_from_input=True)
     eager_ms = info_e["ms"] / steps
+    # graph budgets from the eager step, one step captured and replayed
+    batch.calibrate_graph(info_e)
+    log("batch64: graph capture")
+    batch.timestep(*zin, nsteps=1, opts=opts, use_graph=True, stream=s, out=out, each_from_input=True)
+    log("batch64: graph steps")
+    rc, info = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out,
+                              each_from_input=True)
+    graph_ms = info["ms"] / steps
+    log("batch64: fp64 eager step")
     o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=40, maxiter=120)
     rc_f, info_f = batch.timestep(*zin, nsteps=1, opts=o64, use_graph=False, stream=s, out=out)
     batch.close()
@@ -226,6 +238,7 @@ def batch_section(chns, steps):
     ctxs, seq_ms, seq_its = {}, 0.0, 0
     off = np.concatenate([[0], np.cumsum([n * n for n in sizes])])
     opts_seq = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=40, maxiter=600)
+    log("batch64: sequential fp64 solves")
     for i, (n, p) in enumerate(zip(sizes, prm)):
         if n not in ctxs:
             ctxs[n] = chns.Context(n, "ch_ac", **p)
@@ -246,6 +259,7 @@ def batch_section(chns, steps):
                          f"({Ntot} nodes, {3 * Ntot} unknowns), log-uniform eps, tau, mobility, "
                          f"evaporation rate; FP32 multigrid in FP64 FGMRES(40), rtol 1e-8",
                 graph_ms_per_step=graph_ms, eager_ms_per_step=eager_ms,
+                graph_budget_ch_ac=[int(x.max()) for x in (info_e["iters_ch"], info_e["iters_ac"])],
                 sequential_fp64_ms_per_step=seq_ms, speedup_vs_sequential_fp64=seq_ms / graph_ms,
                 dof_iters_per_s=di / (graph_ms * 1e-3),
                 converged=int(info["conv_ch"].sum() + info["conv_ac"].sum()), solves=2 * len(sizes),
@@ -288,6 +302,7 @@ def main():
     n = args.n
     N = n * n
     p = dict(eps=cfg["eps"], tau=args.tau, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+    log(f"chac{n}: context")
     ctx = chns.Context(n, "ch_ac", **p)
     st0 = inputs.initial_state(n, "ch_ac", cfg["mean"], cfg["seed"])
     fields = {}
@@ -306,6 +321,7 @@ def main():
     res = {}
     for name, prec in (("mixed", chns.MIXED), ("fp64", chns.F64)):
         opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart)
+        log(f"chac{n}: {name} warmup {args.warmup} + {args.steps} timed steps")
         run_steps(ctx, chns, f_in, f_out, args.warmup, opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -319,11 +335,13 @@ def main():
             ch_iters=[i[0]["iters"] for i in infos], ac_iters=[i[1]["iters"] for i in infos],
             converged=all(i[0]["converged"] and i[1]["converged"] for i in infos),
             rel_res_ch=max(i[0]["res_true"] / i[0]["bnorm"] for i in infos))
+    log("kernels: event-timed single launches")
     kern = kernel_roofline(ctx, chns, N, args.kernel_reps)
 
     sweep, sweep_fields = [], {}
     if not args.no_sweep:
         for tau in cfg["tau_sweep"]:
+            log(f"sweep: tau {tau}")
             ctx.set_params(**dict(p, tau=tau))
             row = dict(tau=tau)
             for name, prec in (("fp64", chns.F64), ("mixed", chns.MIXED)):
@@ -339,10 +357,13 @@ def main():
                                  converged=bool(inf[0]["converged"] and inf[1]["converged"]))
             sweep.append(row)
         ctx.set_params(**p)
+    if args.dry_steps > 0:
+        log(f"dry256: {args.dry_steps} steps")
     dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
     bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
     cpu = None
     if not args.no_cpu:
+        log("cpu baseline: oracle on the host")
         cpu = cpu_baseline(cfg, n, args.tau)
         if sweep:
             oracle_errors(cfg, n, st0, sweep, sweep_fields)

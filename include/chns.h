@@ -252,17 +252,24 @@ CHNS_API int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets);
 /* Advance all instances nsteps steps (packed FP64 fields): the first step
  * reads in_*, every later step reads the previous step's output d_* (or
  * in_* again when each_from_input != 0, which repeats the first step's
- * systems); outputs go to d_*, which may equal in_* (in-place).  Each block (the stacked CH blocks, then the stacked AC matrices) is
- * solved by FGMRES with per-instance Krylov scalars on the device and a fixed
- * budget of ceil(maxiter / restart) restart cycles; an instance stops updating
- * once its true or estimated residual meets its own tolerance.  opts->mg_cycles
- * must be 1.  use_graph != 0: the nsteps steps are captured into a hipGraph on
- * a (non-default) stream the first time these arguments are seen and replayed
- * afterwards; otherwise the steps run eagerly and stop the restart loop early
- * once every instance has converged.  h_iters (2*count, may be NULL): Arnoldi
- * steps of the last step, CH then AC; h_conv (2*count, may be NULL): 1 where
- * the recomputed true residual met the tolerance; h_ms: wall time.
- * Returns CHNS_WNOCONV if any instance did not converge.  Synchronising. */
+ * systems); outputs go to d_*, which may equal in_* (in-place).  Each block
+ * (the stacked CH blocks, then the stacked AC matrices) is solved by
+ * right-preconditioned FGMRES with per-instance Krylov scalars on the device;
+ * an instance freezes once its estimated residual meets its own tolerance and
+ * every kernel then skips its rows.  opts->mg_cycles must be 1.
+ * use_graph == 0 (eager): FGMRES(restart) up to maxiter Arnoldi steps, ending
+ * as soon as every instance has converged (activity read back every few
+ * steps).  use_graph != 0: each step variant (from in_*, from d_*) is captured
+ * once on the given non-default stream into a hipGraph and replayed; the graph
+ * runs a fixed budget B = min(maxiter, graph budget of the block) of Arnoldi
+ * steps in cycles of min(restart, B) (chns_batch_set_graph_budget), so an
+ * instance that needs more than B steps is reported as not converged.
+ * Fails with CHNS_EUNSUPPORTED if one step's graph would exceed 100000 kernel
+ * launches.  h_iters (2*count, may be NULL): Arnoldi steps of the last step,
+ * CH then AC; h_conv (2*count, may be NULL): 1 where the recomputed true
+ * residual met the tolerance; h_ms: device time of the nsteps steps (graph
+ * capture excluded).  Returns CHNS_WNOCONV if any instance did not converge.
+ * Synchronising. */
 CHNS_API int chns_batch_timestep(chns_batch* b, const double* in_phi, const double* in_mu,
                                  const double* in_Phi, double* d_phi, double* d_mu, double* d_Phi,
                                  int32_t nsteps, int32_t each_from_input,
@@ -274,6 +281,10 @@ CHNS_API int chns_batch_timestep(chns_batch* b, const double* in_phi, const doub
  * by "rows rpt block" lines, read when present (cached levels are not timed)
  * and rewritten with the chosen shapes.  Synchronising. */
 CHNS_API int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream);
+/* Arnoldi-step budgets of the graph mode for the CH and the AC block (0: use
+ * maxiter), typically the largest iteration counts of an eager step plus a
+ * margin.  Changing them makes the next graph-mode call capture anew. */
+CHNS_API int chns_batch_set_graph_budget(chns_batch* b, int32_t ch_iters, int32_t ac_iters);
 CHNS_API const char* chns_batch_last_error(const chns_batch* b);
 
 #ifdef __cplusplus

@@ -25,7 +25,7 @@ EXPORTS = [
     "chns_matrix_shape", "chns_get_matrix", "chns_spmv", "chns_precond_apply",
     "chns_krylov_solve", "chns_step_rhs", "chns_timestep", "chns_last_error",
     "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
-    "chns_batch_tune", "chns_batch_last_error",
+    "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_last_error",
 ]
 
 
@@ -99,6 +99,7 @@ def lib():
     L.chns_batch_timestep.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, ct.POINTER(SolveOpts),
                                       i32, vp, vp, ct.POINTER(ct.c_double), vp]
     L.chns_batch_tune.argtypes = [vp, ct.c_char_p, vp]
+    L.chns_batch_set_graph_budget.argtypes = [vp, i32, i32]
     L.chns_batch_last_error.argtypes = [vp]
     L.chns_batch_last_error.restype = ct.c_char_p
     for name in EXPORTS:
@@ -282,6 +283,16 @@ class Batch:
     def tune(self, cache_path=None, stream=None):
         s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
         self._check(self.L.chns_batch_tune(self.h, cache_path.encode() if cache_path else None, s))
+
+    def set_graph_budget(self, ch_iters, ac_iters):
+        """Arnoldi-step budgets of the graph mode (0: maxiter)."""
+        self._check(self.L.chns_batch_set_graph_budget(self.h, int(ch_iters), int(ac_iters)))
+
+    def calibrate_graph(self, info, margin=0.125, extra=2):
+        """Graph budgets from an eager step's iteration counts: the largest
+        count of each block plus a relative margin and a few steps."""
+        b = [int(x.max()) for x in (info["iters_ch"], info["iters_ac"])]
+        self.set_graph_budget(*[k + extra + int(margin * k) for k in b])
 
     def timestep(self, phi, mu, Phi, nsteps=1, opts=None, use_graph=False, stream=None,
                  out=None, each_from_input=False):

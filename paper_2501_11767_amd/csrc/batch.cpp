@@ -1,9 +1,12 @@
 // Batched form: many independent CH + AC instances (uneven mesh sizes and
 // parameters) advanced together.  Every stage is one launch over all
 // instances: stacked per-level operators, stacked Krylov vectors, per-instance
-// Krylov scalars on the device, a fixed restart budget with per-instance
-// freezing (no host synchronisation inside a step, so the steps can be
-// captured in a hipGraph), and an autotuned launch shape per level.
+// Krylov scalars on the device, and an autotuned launch shape per level.
+// Converged instances freeze: inside the Arnoldi loop every kernel skips their
+// rows.  The eager mode reads the activity flags back now and then and stops
+// when every instance has converged; the graph mode runs a fixed budget of
+// Arnoldi steps per block without host synchronisation, captured once per
+// step variant and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +29,15 @@ namespace {
 
 constexpr int NOPS = 3;  // 0: L = M, 1: X = s M + tau g K, 2: AC = M + tau delta_v K
 constexpr int BMAX_RESTART = 64;
+constexpr size_t GRAPH_MAX_NODES = 100000;  // refuse to instantiate larger step graphs
+constexpr int GRAPH_CACHE = 4;              // step graphs kept per batch
+constexpr int EAGER_CHECK = 4;              // eager mode: Arnoldi steps between activity readbacks
+
+struct GraphEntry {
+  std::string key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct SizeTables {  // host tables of one mesh size, all its levels
   std::vector<int> n;
@@ -98,10 +110,9 @@ struct chns_batch {
   double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr, *xac = nullptr;
   double *w64a = nullptr, *w64b = nullptr;
   float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr;
-  // graph cache
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  std::string graph_key;
+  // graph mode: Arnoldi budget per block (0: maxiter) and cached step graphs
+  int budget[2] = {0, 0};
+  std::vector<GraphEntry> graphs;
   // current coarse-coefficient opts
   std::string opts_key;
   std::vector<void*> allocs;
@@ -409,10 +420,11 @@ template <> struct BSel<float> {
 };
 
 // Batched V-cycle of operator `op` on level l: instances with their cut
-// below l smooth and recurse, instances cut at l take Chebyshev steps.
+// below l smooth and recurse, instances cut at l take Chebyshev steps.  Rows of
+// instances with act 0 (act may be null) are skipped.
 template <typename T>
-void bvcycle(chns_batch* b, int op, int l, const T* rhs, T* x, const chns_solve_opts& o,
-             hipStream_t s) {
+void bvcycle(chns_batch* b, int op, int l, const T* rhs, T* x, const int* act,
+             const chns_solve_opts& o, hipStream_t s) {
   BLevel& L = b->lv[l];
   const T* v = BSel<T>::v(L, op);
   const T* di = BSel<T>::d(L, op);
@@ -425,22 +437,24 @@ void bvcycle(chns_batch* b, int op, int l, const T* rhs, T* x, const chns_solve_
     const uint8_t* m = L.smooth[op];
     T* cur = ((o.mg_pre - 1 + o.mg_post) % 2 == 0) ? x : t;
     T* oth = (cur == x) ? t : x;
-    bstencil<T>(L.st, v, 3, nullptr, rhs, di, d, T(0), pc2[0], nullptr, nullptr, m, cur, s);
+    bstencil<T>(L.st, v, 3, nullptr, rhs, di, d, T(0), pc2[0], nullptr, nullptr, m, act, cur, s);
     for (int k = 1; k < o.mg_pre; ++k) {
-      bstencil<T>(L.st, v, 2, cur, rhs, di, d, pc1[k], pc2[k], nullptr, nullptr, m, oth, s);
+      bstencil<T>(L.st, v, 2, cur, rhs, di, d, pc1[k], pc2[k], nullptr, nullptr, m, act, oth, s);
       std::swap(cur, oth);
     }
     T* r = BSel<T>::r(L);
-    bstencil<T>(L.st, v, 1, cur, rhs, nullptr, nullptr, T(0), T(0), nullptr, nullptr, m, r, s);
+    bstencil<T>(L.st, v, 1, cur, rhs, nullptr, nullptr, T(0), T(0), nullptr, nullptr, m, act, r, s);
     BLevel& G = b->lv[l + 1];
-    bspmv_uniform<T>(G.nrows, 7, L.Rcol, BSel<T>::R(L), G.present[op], r, BSel<T>::b(G), T(1), T(0), s);
-    bvcycle<T>(b, op, l + 1, BSel<T>::b(G), BSel<T>::x(G), o, s);
-    bspmv_uniform<T>(L.nrows, 2, L.Pcol, BSel<T>::P(L), m, BSel<T>::x(G), cur, T(1), T(1), s);
+    bspmv_uniform<T>(G.nrows, 7, L.Rcol, BSel<T>::R(L), G.present[op], G.sinst, act, r,
+                     BSel<T>::b(G), T(1), T(0), s);
+    bvcycle<T>(b, op, l + 1, BSel<T>::b(G), BSel<T>::x(G), act, o, s);
+    bspmv_uniform<T>(L.nrows, 2, L.Pcol, BSel<T>::P(L), m, L.sinst, act, BSel<T>::x(G), cur, T(1),
+                     T(1), s);
     if (o.mg_post > 0) {
       auto qc1 = cheb_seq<T>(lmax / 4.0, lmax, o.mg_post, false);
       auto qc2 = cheb_seq<T>(lmax / 4.0, lmax, o.mg_post, true);
       for (int k = 0; k < o.mg_post; ++k) {
-        bstencil<T>(L.st, v, 2, cur, rhs, di, d, qc1[k], qc2[k], nullptr, nullptr, m, oth, s);
+        bstencil<T>(L.st, v, 2, cur, rhs, di, d, qc1[k], qc2[k], nullptr, nullptr, m, act, oth, s);
         std::swap(cur, oth);
       }
     }
@@ -452,51 +466,60 @@ void bvcycle(chns_batch* b, int op, int l, const T* rhs, T* x, const chns_solve_
     const T* c2 = BSel<T>::cc(L, op, 1);
     T* cur = ((steps - 1) % 2 == 0) ? x : t;
     T* oth = (cur == x) ? t : x;
-    bstencil<T>(L.st, v, 3, nullptr, rhs, di, d, T(0), T(0), c1, c2, m, cur, s);
+    bstencil<T>(L.st, v, 3, nullptr, rhs, di, d, T(0), T(0), c1, c2, m, act, cur, s);
     for (int k = 1; k < steps; ++k) {
       bstencil<T>(L.st, v, 2, cur, rhs, di, d, T(0), T(0), c1 + size_t(k) * b->count,
-                  c2 + size_t(k) * b->count, m, oth, s);
+                  c2 + size_t(k) * b->count, m, act, oth, s);
       std::swap(cur, oth);
     }
   }
 }
 
 template <typename T>
-void bprecond_t(chns_batch* b, int block, const T* r, T* z, T* tmp1, T* tmp2,
+void bprecond_t(chns_batch* b, int block, const T* r, T* z, T* tmp1, T* tmp2, const int* act,
                 const chns_solve_opts& o, hipStream_t s) {
   const int64_t N = b->Ntot;
   BLevel& L0 = b->lv[0];
   if (block == CHNS_BLOCK_CH) {
-    bvcycle<T>(b, 0, 0, r, z, o, s);
-    bvcycle<T>(b, 1, 0, r + N, tmp1, o, s);
+    bvcycle<T>(b, 0, 0, r, z, act, o, s);
+    bvcycle<T>(b, 1, 0, r + N, tmp1, act, o, s);
     bstencil<T>(L0.st, BSel<T>::M(L0), 0, tmp1, nullptr, nullptr, nullptr, T(1), T(0), nullptr,
-                nullptr, nullptr, tmp2, s);
-    bvcycle<T>(b, 1, 0, tmp2, z + N, o, s);
+                nullptr, nullptr, act, tmp2, s);
+    bvcycle<T>(b, 1, 0, tmp2, z + N, act, o, s);
   } else {
-    bvcycle<T>(b, 2, 0, r, z, o, s);
+    bvcycle<T>(b, 2, 0, r, z, act, o, s);
   }
 }
 
-void bprecond(chns_batch* b, int block, const double* r, double* z, const chns_solve_opts& o,
-              hipStream_t s) {
+void bprecond(chns_batch* b, int block, const double* r, double* z, const int* act,
+              const chns_solve_opts& o, hipStream_t s) {
   const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
   if (o.precision == CHNS_F64) {
-    bprecond_t<double>(b, block, r, z, b->w64a, b->w64b, o, s);
+    bprecond_t<double>(b, block, r, z, b->w64a, b->w64b, act, o, s);
   } else {
-    convert<double, float>(n, r, b->r32, s);
-    bprecond_t<float>(b, block, b->r32, b->z32, b->w32a, b->w32b, o, s);
-    convert<float, double>(n, b->z32, z, s);
+    bconvert<double, float>(n, r, b->r32, b->cinst, act, s);
+    bprecond_t<float>(b, block, b->r32, b->z32, b->w32a, b->w32b, act, o, s);
+    bconvert<float, double>(n, b->z32, z, b->cinst, act, s);
   }
 }
 
 void bapply(chns_batch* b, int block, const double* x, double* y, double alpha, double beta,
-            hipStream_t s) {
+            const int* act, hipStream_t s) {
   BLevel& L0 = b->lv[0];
   if (block == CHNS_BLOCK_CH)
-    bch_block<double>(L0.st, L0.M, L0.K, L0.M, b->c12, b->c22, x, alpha, beta, y, s);
+    bch_block<double>(L0.st, L0.M, L0.K, L0.M, b->c12, b->c22, act, x, alpha, beta, y, s);
   else
     bstencil<double>(L0.st, L0.v64[2], 0, x, nullptr, nullptr, nullptr, alpha, beta, nullptr,
-                     nullptr, nullptr, y, s);
+                     nullptr, nullptr, act, y, s);
+}
+
+int any_active(chns_batch* b, hipStream_t s, bool& any) {
+  std::vector<int> act(b->count);
+  BCHK(b, hipMemcpyAsync(act.data(), b->active, b->count * sizeof(int), hipMemcpyDeviceToHost, s));
+  BCHK(b, hipStreamSynchronize(s));
+  any = false;
+  for (int a : act) any = any || a;
+  return CHNS_OK;
 }
 
 __global__ void k_not_into(int n, const int* __restrict__ a, int* __restrict__ o) {
@@ -504,60 +527,69 @@ __global__ void k_not_into(int n, const int* __restrict__ a, int* __restrict__ o
   if (i < n) o[i] = a[i] ? 0 : 1;
 }
 
-// Batched FGMRES with a fixed budget of restart cycles; instances freeze on
-// convergence.  sync_check: read the number of active instances back after
-// each cycle and stop early (not allowed under graph capture).
+// Batched right-preconditioned FGMRES.  Eager mode: FGMRES(restart) up to
+// maxiter Arnoldi steps, stopping once every instance has converged (activity
+// read back every EAGER_CHECK steps and after each cycle).  Graph mode: a fixed
+// budget B = min(maxiter, budget of the block) of Arnoldi steps in cycles of
+// min(restart, B) steps, with no host synchronisation; an instance that
+// converges within the first cycle takes exactly the eager iterations.
 int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_solve_opts& o,
-            bool sync_check, hipStream_t s) {
-  const int m = o.restart;
+            bool eager, hipStream_t s) {
+  const int bi = block == CHNS_BLOCK_CH ? 0 : 1;
+  int budget = o.maxiter;
+  if (!eager && b->budget[bi] > 0) budget = std::min(budget, b->budget[bi]);
+  const int m = eager ? o.restart : std::min(o.restart, budget);
+  const int cycles = (budget + m - 1) / m;
   const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
   const int nchunk = int(n / BCHUNK);
   const int half = (block == CHNS_BLOCK_CH) ? b->nchunk1 : 0;
-  const int cycles = (o.maxiter + m - 1) / m;
   const int hs = m + 2, Hs = (m + 1) * m, ldH = m + 1;
-  const int bi = block == CHNS_BLOCK_CH ? 0 : 1;
+  const int* act = b->active;
   double* V = b->V;
   dfill_int(b->count, 0, b->iters[bi], s);
   bnorm_partial(n, rhs, b->part, s);
   bnorm_finish(b->count, nchunk, b->part, b->cr, half, m, 1, o.rtol, o.atol, b->nrm, b->inv, b->g,
                b->tol, b->active, b->kcols, s);
   for (int cyc = 0; cyc <= cycles; ++cyc) {
+    // true residual of every instance decides its activity for this cycle
     dcopy(n, rhs, V, s);
-    bapply(b, block, x, V, -1.0, 1.0, s);
+    bapply(b, block, x, V, -1.0, 1.0, nullptr, s);
     bnorm_partial(n, V, b->part, s);
     bnorm_finish(b->count, nchunk, b->part, b->cr, half, m, 0, o.rtol, o.atol, b->nrm, b->inv,
                  b->g, b->tol, b->active, b->kcols, s);
     if (cyc == cycles) break;  // final true residual only
-    if (sync_check) {
-      std::vector<int> act(b->count);
-      BCHK(b, hipMemcpyAsync(act.data(), b->active, b->count * sizeof(int), hipMemcpyDeviceToHost, s));
-      BCHK(b, hipStreamSynchronize(s));
+    if (eager) {
       bool any = false;
-      for (int a : act) any = any || a;
+      BTRY(any_active(b, s, any));
       if (!any) break;
     }
-    bscale(n, V, b->inv, b->cinst, V, s);
+    bscale(n, V, b->inv, b->cinst, act, V, s);
     for (int j = 0; j < m; ++j) {
       double* vj = V + int64_t(j) * n;
       double* vn = V + int64_t(j + 1) * n;
       double* zj = b->Z + int64_t(j) * n;
-      bprecond(b, block, vj, zj, o, s);
-      bapply(b, block, zj, vn, 1.0, 0.0, s);
-      bmdot_partial(n, V, n, j + 2, vn, b->part, nullptr, b->cinst, s);
+      bprecond(b, block, vj, zj, act, o, s);
+      bapply(b, block, zj, vn, 1.0, 0.0, act, s);
+      bmdot_partial(n, V, n, j + 2, vn, b->part, nullptr, b->cinst, act, s);
       bmdot_reduce(b->count, nchunk, j + 2, b->part, b->cr, half, b->h, hs, b->H, Hs, j, ldH, 0,
                    nullptr, s);
-      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, nullptr, b->cinst, s);
+      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, nullptr, b->cinst, act, s);
       breorth_decide(b->count, nchunk, b->part2, b->cr, half, b->h, hs, j + 1, b->flag, b->nrm2, s);
-      bmdot_partial(n, V, n, j + 1, vn, b->part, b->flag, b->cinst, s);
+      bmdot_partial(n, V, n, j + 1, vn, b->part, b->flag, b->cinst, act, s);
       bmdot_reduce(b->count, nchunk, j + 1, b->part, b->cr, half, b->h, hs, b->H, Hs, j, ldH, 1,
                    b->flag, s);
-      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, b->flag, b->cinst, s);
+      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, b->flag, b->cinst, act, s);
       barnoldi_finish(b->count, nchunk, b->part2, b->cr, half, b->flag, b->nrm2, j, m, b->H, b->cs,
                       b->sn, b->g, b->inv, b->tol, b->active, b->kcols, b->iters[bi], s);
-      bscale(n, vn, b->inv, b->cinst, vn, s);
+      bscale(n, vn, b->inv, b->cinst, act, vn, s);
+      if (eager && (j + 1) % EAGER_CHECK == 0 && j + 1 < m) {
+        bool any = false;
+        BTRY(any_active(b, s, any));
+        if (!any) break;
+      }
     }
     blsq(b->count, m, b->H, b->g, b->kcols, b->y, s);
-    bxupdate(n, b->Z, n, m, b->y, x, b->cinst, s);
+    bxupdate(n, b->Z, n, m, b->y, x, b->cinst, b->kcols, s);
   }
   hipLaunchKernelGGL(k_not_into, dim3((b->count + 63) / 64), dim3(64), 0, s, b->count, b->active,
                      b->conv[bi]);
@@ -568,15 +600,15 @@ int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_s
 // One step from (phi, mu, Phi) into (ophi, omu, oPhi); the sources are read
 // before any output is written, so the two sets may coincide.
 int bstep(chns_batch* b, const double* phi, const double* mu, const double* Phi, double* ophi,
-          double* omu, double* oPhi, const chns_solve_opts& o, bool sync_check, hipStream_t s) {
+          double* omu, double* oPhi, const chns_solve_opts& o, bool eager, hipStream_t s) {
   const int64_t N = b->Ntot;
   BLevel& L0 = b->lv[0];
   brhs_binary(L0.st, L0.M, phi, Phi, b->cmu, b->cac, b->rhs_ch, b->rhs_ac, s);
   dcopy(N, phi, b->xch, s);
   dcopy(N, mu, b->xch + N, s);
   dcopy(N, Phi, b->xac, s);
-  BTRY(bfgmres(b, CHNS_BLOCK_CH, b->rhs_ch, b->xch, o, sync_check, s));
-  BTRY(bfgmres(b, CHNS_BLOCK_AC, b->rhs_ac, b->xac, o, sync_check, s));
+  BTRY(bfgmres(b, CHNS_BLOCK_CH, b->rhs_ch, b->xch, o, eager, s));
+  BTRY(bfgmres(b, CHNS_BLOCK_AC, b->rhs_ac, b->xac, o, eager, s));
   dcopy(N, b->xch, ophi, s);
   dcopy(N, b->xch + N, omu, s);
   dcopy(N, b->xac, oPhi, s);
@@ -699,9 +731,99 @@ int bbuild(chns_batch* b) {
   return CHNS_OK;
 }
 
+void drop_graphs(chns_batch* b) {
+  for (auto& g : b->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  b->graphs.clear();
+}
+
+// Kernel launches of one V-cycle of operator op from level l (mirrors bvcycle).
+size_t vcycle_launches(const chns_batch* b, int op, int l, const chns_solve_opts& o) {
+  const BLevel& L = b->lv[l];
+  size_t c = 0;
+  if (L.nsmooth[op] > 0) c += size_t(o.mg_pre) + 3 + o.mg_post + vcycle_launches(b, op, l + 1, o);
+  if (L.ncoarse[op] > 0) c += size_t(l > 0 ? o.mg_coarse : o.mg_pre + o.mg_post);
+  return c;
+}
+
+// Kernel launches of one graph-mode step (mirrors bstep and bfgmres), so that an
+// oversized graph is refused before it is captured.
+size_t step_launches(const chns_batch* b, const chns_solve_opts& o) {
+  size_t total = 1 + 3 + 3;  // right-hand sides, input copies, output copies
+  for (int bi = 0; bi < 2; ++bi) {
+    int budget = o.maxiter;
+    if (b->budget[bi] > 0) budget = std::min(budget, b->budget[bi]);
+    const int m = std::min(o.restart, budget);
+    const size_t cycles = size_t((budget + m - 1) / m);
+    const size_t pre = bi == 0 ? 3 * vcycle_launches(b, 0, 0, o) + 1 : vcycle_launches(b, 2, 0, o);
+    const size_t arnoldi = pre + (o.precision == CHNS_MIXED ? 2 : 0) + 1 + 9;
+    total += 3 + cycles * (4 + 1 + size_t(m) * arnoldi + 2) + 4 + 1;
+  }
+  return total;
+}
+
+// Executable graph of one step from (phi, mu, Phi) into the output fields,
+// captured on first use and cached by pointers, stream and options.
+int step_graph(chns_batch* b, const double* phi, const double* mu, const double* Phi, double* ophi,
+               double* omu, double* oPhi, const chns_solve_opts& o, hipStream_t s,
+               hipGraphExec_t* out) {
+  char key[512];
+  std::snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%p/%p/%s/%d/%d/%d/%.17g/%.17g/%d/%d", (const void*)phi,
+                (const void*)mu, (const void*)Phi, (void*)ophi, (void*)omu, (void*)oPhi, (void*)s,
+                b->opts_key.c_str(), o.restart, o.maxiter, o.precision, o.rtol, o.atol, b->budget[0],
+                b->budget[1]);
+  for (size_t i = 0; i < b->graphs.size(); ++i)
+    if (b->graphs[i].key == key) {  // most recently used goes last
+      GraphEntry g = b->graphs[i];
+      b->graphs.erase(b->graphs.begin() + i);
+      b->graphs.push_back(g);
+      *out = g.exec;
+      return CHNS_OK;
+    }
+  const size_t expect = step_launches(b, o);
+  if (expect > GRAPH_MAX_NODES)
+    return fail(b, CHNS_EUNSUPPORTED,
+                "a step graph of " + std::to_string(expect) + " kernels exceeds " +
+                    std::to_string(GRAPH_MAX_NODES) + "; set a smaller graph budget or maxiter");
+  BCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const int rc = bstep(b, phi, mu, Phi, ophi, omu, oPhi, o, false, s);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &gr);
+  if (rc < 0) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(b, CHNS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  size_t nodes = 0;
+  const hipError_t en = hipGraphGetNodes(gr, nullptr, &nodes);
+  if (en != hipSuccess || nodes > GRAPH_MAX_NODES) {
+    (void)hipGraphDestroy(gr);
+    if (en != hipSuccess) return fail(b, CHNS_EHIP, std::string("hipGraphGetNodes: ") + hipGetErrorString(en));
+    return fail(b, CHNS_EUNSUPPORTED, "captured " + std::to_string(nodes) + " graph nodes, over " +
+                                          std::to_string(GRAPH_MAX_NODES));
+  }
+  GraphEntry g;
+  g.key = key;
+  g.graph = gr;
+  const hipError_t ei = hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    return fail(b, CHNS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  if (int(b->graphs.size()) >= GRAPH_CACHE) {
+    (void)hipGraphExecDestroy(b->graphs.front().exec);
+    (void)hipGraphDestroy(b->graphs.front().graph);
+    b->graphs.erase(b->graphs.begin());
+  }
+  b->graphs.push_back(g);
+  *out = g.exec;
+  return CHNS_OK;
+}
+
 void brelease(chns_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  drop_graphs(b);
   for (void* p : b->allocs) (void)hipFree(p);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
@@ -788,45 +910,25 @@ int chns_batch_timestep(chns_batch* b, const double* in_phi, const double* in_mu
   BTRY(check_bopts(b, opts));
   if (!in_phi || !in_mu || !in_Phi || !d_phi || !d_mu || !d_Phi || nsteps < 1 || nsteps > 1000)
     return fail(b, CHNS_EINVAL, "fields must be non-NULL and nsteps in 1..1000");
-  auto run = [&](bool sync) -> int {
-    for (int k = 0; k < nsteps; ++k) {
-      const bool from_in = (k == 0) || each_from_input;
-      BTRY(bstep(b, from_in ? in_phi : d_phi, from_in ? in_mu : d_mu, from_in ? in_Phi : d_Phi, d_phi,
-                 d_mu, d_Phi, *opts, sync, static_cast<hipStream_t>(stream)));
-    }
-    return CHNS_OK;
-  };
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (use_graph && !s) return fail(b, CHNS_EINVAL, "graph capture needs a non-default stream");
   BTRY(prepare_cycles(b, *opts));
-  BCHK(b, hipEventRecord(b->ev0, s));
+  // step variants: 0 reads the input fields, 1 continues from the outputs
+  hipGraphExec_t ex[2] = {nullptr, nullptr};
   if (use_graph) {
-    char key[512];
-    std::snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%p/%d/%d/%p/%s/%d/%d/%d/%.17g/%.17g", (const void*)in_phi,
-                  (const void*)in_mu, (const void*)in_Phi, (void*)d_phi, (void*)d_mu, (void*)d_Phi,
-                  nsteps, each_from_input, (void*)s, b->opts_key.c_str(), opts->restart,
-                  opts->maxiter, opts->precision, opts->rtol, opts->atol);
-    if (b->graph_key != key) {
-      if (b->exec) (void)hipGraphExecDestroy(b->exec);
-      if (b->graph) (void)hipGraphDestroy(b->graph);
-      b->exec = nullptr;
-      b->graph = nullptr;
-      BCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const int rc = run(false);
-      hipGraph_t gr = nullptr;
-      const hipError_t e = hipStreamEndCapture(s, &gr);
-      if (rc < 0) {
-        if (gr) (void)hipGraphDestroy(gr);
-        return rc;
-      }
-      if (e != hipSuccess) return fail(b, CHNS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-      b->graph = gr;
-      BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-      b->graph_key = key;
+    BTRY(step_graph(b, in_phi, in_mu, in_Phi, d_phi, d_mu, d_Phi, *opts, s, &ex[0]));
+    if (nsteps > 1 && !each_from_input)
+      BTRY(step_graph(b, d_phi, d_mu, d_Phi, d_phi, d_mu, d_Phi, *opts, s, &ex[1]));
+  }
+  BCHK(b, hipEventRecord(b->ev0, s));
+  for (int k = 0; k < nsteps; ++k) {
+    const bool from_in = (k == 0) || each_from_input;
+    if (use_graph) {
+      BCHK(b, hipGraphLaunch(ex[from_in ? 0 : 1], s));
+    } else {
+      BTRY(bstep(b, from_in ? in_phi : d_phi, from_in ? in_mu : d_mu, from_in ? in_Phi : d_Phi, d_phi,
+                 d_mu, d_Phi, *opts, true, s));
     }
-    BCHK(b, hipGraphLaunch(b->exec, s));
-  } else {
-    BTRY(run(true));
   }
   BCHK(b, hipEventRecord(b->ev1, s));
   BCHK(b, hipEventSynchronize(b->ev1));
@@ -883,11 +985,11 @@ int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream) {
         st.block = blk;
         for (int w = 0; w < 2; ++w)
           bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
-                          nullptr, L.t32, s);
+                          nullptr, nullptr, L.t32, s);
         BCHK(b, hipEventRecord(b->ev0, s));
         for (int w = 0; w < 10; ++w)
           bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
-                          nullptr, L.t32, s);
+                          nullptr, nullptr, L.t32, s);
         BCHK(b, hipEventRecord(b->ev1, s));
         BCHK(b, hipEventSynchronize(b->ev1));
         float ms = 0.f;
@@ -909,7 +1011,16 @@ int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream) {
       std::fclose(f);
     }
   }
-  b->graph_key.clear();  // launch shapes changed
+  drop_graphs(b);  // launch shapes changed
+  return CHNS_OK;
+}
+
+int chns_batch_set_graph_budget(chns_batch* b, int32_t ch_iters, int32_t ac_iters) {
+  if (!b) return CHNS_EINVAL;
+  if (ch_iters < 0 || ch_iters > 4096 || ac_iters < 0 || ac_iters > 4096)
+    return fail(b, CHNS_EINVAL, "graph budgets must be in 0..4096");
+  b->budget[0] = ch_iters;
+  b->budget[1] = ac_iters;
   return CHNS_OK;
 }
 

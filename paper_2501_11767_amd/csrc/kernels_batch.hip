@@ -43,8 +43,8 @@ __global__ void k_bstencil(int nrows, const int* __restrict__ col, const T* __re
                            const T* __restrict__ x, const T* __restrict__ b,
                            const T* __restrict__ dinv, T* __restrict__ d, T p0, T p1,
                            const T* __restrict__ cc1, const T* __restrict__ cc2,
-                           const uint8_t* __restrict__ mask, const int* __restrict__ sinst,
-                           T* __restrict__ y) {
+                           const uint8_t* __restrict__ mask, const int* __restrict__ act,
+                           const int* __restrict__ sinst, T* __restrict__ y) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row0 = blk * blockDim.x * RPT + threadIdx.x;
 #pragma unroll
@@ -53,6 +53,7 @@ __global__ void k_bstencil(int nrows, const int* __restrict__ col, const T* __re
     if (row >= nrows) continue;
     const int slice = row >> 6;
     if (mask && !mask[slice]) continue;
+    if (act && !act[sinst[slice]]) continue;
     T c1 = p0, c2 = p1;
     if (cc1) {
       const int inst = sinst[slice];
@@ -92,6 +93,8 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_bspmv_uniform(int nrows, int width, const int* __restrict__ col,
                                                       const T* __restrict__ val,
                                                       const uint8_t* __restrict__ mask,
+                                                      const int* __restrict__ sinst,
+                                                      const int* __restrict__ act,
                                                       const T* __restrict__ x, T* __restrict__ y,
                                                       T alpha, T beta) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -99,6 +102,7 @@ __global__ __launch_bounds__(BS) void k_bspmv_uniform(int nrows, int width, cons
   if (row >= nrows) return;
   const int slice = row >> 6;
   if (mask && !mask[slice]) return;
+  if (act && !act[sinst[slice]]) return;
   const size_t base = size_t(slice) * 64 * width + (row & 63);
   T sum = T(0);
   for (int k = 0; k < width; ++k) sum += val[base + k * 64] * x[col[base + k * 64]];
@@ -108,6 +112,7 @@ __global__ __launch_bounds__(BS) void k_bspmv_uniform(int nrows, int width, cons
 template <typename T, bool L_IS_M>
 __global__ __launch_bounds__(BS) void k_bch_block(int n, const int* __restrict__ col,
                                                   const int* __restrict__ sinst,
+                                                  const int* __restrict__ act,
                                                   const T* __restrict__ Lv, const T* __restrict__ Kv,
                                                   const T* __restrict__ Mv,
                                                   const T* __restrict__ c12a,
@@ -118,6 +123,7 @@ __global__ __launch_bounds__(BS) void k_bch_block(int n, const int* __restrict__
   const int row = blk * BS + threadIdx.x;
   if (row >= n) return;
   const int inst = sinst[row >> 6];
+  if (act && !act[inst]) return;
   const T c12 = c12a[inst], c22 = c22a[inst];
   const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
   const T* x1 = x;
@@ -212,9 +218,11 @@ __global__ __launch_bounds__(BS) void k_bmdot_partial(int64_t n, const double* _
                                                       const double* __restrict__ w,
                                                       double* __restrict__ part,
                                                       const int* __restrict__ flag,
-                                                      const int* __restrict__ cinst) {
+                                                      const int* __restrict__ cinst,
+                                                      const int* __restrict__ act) {
   const int c = blockIdx.x;
   if (flag && flag[cinst[c]] == 0) return;
+  if (act && act[cinst[c]] == 0) return;
   __shared__ double sh[16];
   const int g0 = blockIdx.y * MD_G;
   const int kk = min(MD_G, k - g0);
@@ -265,10 +273,12 @@ __global__ __launch_bounds__(BS) void k_bmaxpy(int64_t n, const double* __restri
                                                double* __restrict__ w,
                                                double* __restrict__ nrm_part,
                                                const int* __restrict__ flag,
-                                               const int* __restrict__ cinst) {
+                                               const int* __restrict__ cinst,
+                                               const int* __restrict__ act) {
   const int c = blockIdx.x;
   const int inst = cinst[c];
   if (flag && flag[inst] == 0) return;
+  if (act && act[inst] == 0) return;
   __shared__ double hsh[80];
   __shared__ double sh[16];
   for (int i = threadIdx.x; i < k; i += BS) hsh[i] = h[inst * hs + i];
@@ -366,10 +376,13 @@ __global__ __launch_bounds__(BS) void k_barnoldi_finish(int nchunk, const double
 __global__ __launch_bounds__(BS) void k_bscale(int64_t n, const double* __restrict__ w,
                                                const double* __restrict__ inv,
                                                const int* __restrict__ cinst,
+                                               const int* __restrict__ act,
                                                double* __restrict__ v) {
   const int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (r >= n) return;
-  v[r] = w[r] * inv[cinst[r / BCHUNK]];
+  const int inst = cinst[r / BCHUNK];
+  if (act && act[inst] == 0) return;
+  v[r] = w[r] * inv[inst];
 }
 
 __global__ void k_blsq(int count, int m, const double* __restrict__ H, const double* __restrict__ g,
@@ -392,17 +405,20 @@ __global__ void k_blsq(int count, int m, const double* __restrict__ H, const dou
 __global__ __launch_bounds__(BS) void k_bxupdate(int64_t n, const double* __restrict__ Z,
                                                  int64_t ldz, int m, const double* __restrict__ y,
                                                  double* __restrict__ x,
-                                                 const int* __restrict__ cinst) {
+                                                 const int* __restrict__ cinst,
+                                                 const int* __restrict__ kcols) {
   const int c = blockIdx.x;
   const int inst = cinst[c];
+  const int k = kcols[inst];
+  if (k == 0) return;
   __shared__ double ys[80];
-  for (int i = threadIdx.x; i < m; i += BS) ys[i] = y[inst * (m + 1) + i];
+  for (int i = threadIdx.x; i < k; i += BS) ys[i] = y[inst * (m + 1) + i];
   __syncthreads();
 #pragma unroll
   for (int rr = 0; rr < RPC; ++rr) {
     const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
     double s = x[r];
-    for (int i = 0; i < m; ++i) s += ys[i] * Z[i * ldz + r];
+    for (int i = 0; i < k; ++i) s += ys[i] * Z[i * ldz + r];
     x[r] = s;
   }
 }
@@ -449,6 +465,16 @@ __global__ __launch_bounds__(BS) void k_bnorm_finish(int nchunk, const double* _
   for (int l = 1; l < m + 2; ++l) gi[l] = 0.0;
 }
 
+template <typename TI, typename TO>
+__global__ __launch_bounds__(BS) void k_bconvert(int64_t n, const TI* __restrict__ x, TO* __restrict__ y,
+                                                 const int* __restrict__ cinst,
+                                                 const int* __restrict__ act) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i >= n) return;
+  if (act && !act[cinst[i / BCHUNK]]) return;
+  y[i] = TO(x[i]);
+}
+
 __global__ __launch_bounds__(BS) void k_dcopy(int64_t n, const double* __restrict__ x,
                                               double* __restrict__ y) {
   const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
@@ -466,50 +492,56 @@ __global__ __launch_bounds__(BS) void k_dfill_int(int64_t n, int v, int* __restr
 
 template <typename T, int MODE>
 static void launch_bstencil(const BStencil& A, const T* val, const T* x, const T* b, const T* dinv,
-                            T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, T* y,
-                            hipStream_t s) {
+                            T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask,
+                            const int* act, T* y, hipStream_t s) {
   const int rows_per_block = A.block * A.rpt;
   const dim3 g(ceil_div(A.nrows, rows_per_block)), blk(A.block);
   if (A.rpt == 4)
     hipLaunchKernelGGL((k_bstencil<T, MODE, 4>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
-                       p0, p1, cc1, cc2, mask, A.sinst, y);
+                       p0, p1, cc1, cc2, mask, act, A.sinst, y);
   else if (A.rpt == 2)
     hipLaunchKernelGGL((k_bstencil<T, MODE, 2>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
-                       p0, p1, cc1, cc2, mask, A.sinst, y);
+                       p0, p1, cc1, cc2, mask, act, A.sinst, y);
   else
     hipLaunchKernelGGL((k_bstencil<T, MODE, 1>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
-                       p0, p1, cc1, cc2, mask, A.sinst, y);
+                       p0, p1, cc1, cc2, mask, act, A.sinst, y);
 }
 
 template <typename T>
 void bstencil(const BStencil& A, const T* val, int mode, const T* x, const T* b, const T* dinv,
-              T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, T* y,
-              hipStream_t s) {
+              T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, const int* act,
+              T* y, hipStream_t s) {
   switch (mode) {
-    case 0: launch_bstencil<T, 0>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
-    case 1: launch_bstencil<T, 1>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
-    case 2: launch_bstencil<T, 2>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
-    default: launch_bstencil<T, 3>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, y, s); break;
+    case 0: launch_bstencil<T, 0>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, act, y, s); break;
+    case 1: launch_bstencil<T, 1>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, act, y, s); break;
+    case 2: launch_bstencil<T, 2>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, act, y, s); break;
+    default: launch_bstencil<T, 3>(A, val, x, b, dinv, d, p0, p1, cc1, cc2, mask, act, y, s); break;
   }
 }
 
 template <typename T>
 void bspmv_uniform(int nrows, int width, const int* col, const T* val, const uint8_t* mask,
-                   const T* x, T* y, T alpha, T beta, hipStream_t s) {
+                   const int* sinst, const int* act, const T* x, T* y, T alpha, T beta,
+                   hipStream_t s) {
   hipLaunchKernelGGL((k_bspmv_uniform<T>), dim3(ceil_div(nrows, BS)), dim3(BS), 0, s, nrows, width,
-                     col, val, mask, x, y, alpha, beta);
+                     col, val, mask, sinst, act, x, y, alpha, beta);
 }
 
 template <typename T>
 void bch_block(const BStencil& A, const T* L, const T* K, const T* M, const T* c12, const T* c22,
-               const T* x, T alpha, T beta, T* y, hipStream_t s) {
+               const int* act, const T* x, T alpha, T beta, T* y, hipStream_t s) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (L == M)
-    hipLaunchKernelGGL((k_bch_block<T, true>), g, blk, 0, s, A.nrows, A.col, A.sinst, L, K, M, c12,
-                       c22, x, alpha, beta, y);
+    hipLaunchKernelGGL((k_bch_block<T, true>), g, blk, 0, s, A.nrows, A.col, A.sinst, act, L, K, M,
+                       c12, c22, x, alpha, beta, y);
   else
-    hipLaunchKernelGGL((k_bch_block<T, false>), g, blk, 0, s, A.nrows, A.col, A.sinst, L, K, M, c12,
-                       c22, x, alpha, beta, y);
+    hipLaunchKernelGGL((k_bch_block<T, false>), g, blk, 0, s, A.nrows, A.col, A.sinst, act, L, K, M,
+                       c12, c22, x, alpha, beta, y);
+}
+
+template <typename TI, typename TO>
+void bconvert(int64_t n, const TI* x, TO* y, const int* cinst, const int* act, hipStream_t s) {
+  hipLaunchKernelGGL((k_bconvert<TI, TO>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, y, cinst, act);
 }
 
 void brhs_binary(const BStencil& A, const double* Mv, const double* phi, const double* Phi,
@@ -526,10 +558,10 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
 }
 
 void bmdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                   const int* flag, const int* cinst, hipStream_t s) {
+                   const int* flag, const int* cinst, const int* act, hipStream_t s) {
   const int nchunk = int(n / BCHUNK);
   hipLaunchKernelGGL(k_bmdot_partial, dim3(nchunk, ceil_div(k, MD_G)), dim3(BS), 0, s, n, V, ldv, k,
-                     w, part, flag, cinst);
+                     w, part, flag, cinst, act);
 }
 
 void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* cr, int half,
@@ -540,9 +572,9 @@ void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* c
 }
 
 void bmaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, int hs, double* w,
-            double* nrm_part, const int* flag, const int* cinst, hipStream_t s) {
+            double* nrm_part, const int* flag, const int* cinst, const int* act, hipStream_t s) {
   hipLaunchKernelGGL(k_bmaxpy, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, V, ldv, k, h, hs, w,
-                     nrm_part, flag, cinst);
+                     nrm_part, flag, cinst, act);
 }
 
 void breorth_decide(int count, int nchunk, const double* part, const int* cr, int half,
@@ -559,9 +591,9 @@ void barnoldi_finish(int count, int nchunk, const double* part2, const int* cr, 
                      nrm2, j, m, H, cs, sn, g, inv, tol, active, kcols, iters);
 }
 
-void bscale(int64_t n, const double* w, const double* inv, const int* cinst, double* v,
-            hipStream_t s) {
-  hipLaunchKernelGGL(k_bscale, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, w, inv, cinst, v);
+void bscale(int64_t n, const double* w, const double* inv, const int* cinst, const int* act,
+            double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_bscale, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, w, inv, cinst, act, v);
 }
 
 void blsq(int count, int m, const double* H, const double* g, const int* kcols, double* y,
@@ -570,8 +602,9 @@ void blsq(int count, int m, const double* H, const double* g, const int* kcols, 
 }
 
 void bxupdate(int64_t n, const double* Z, int64_t ldz, int m, const double* y, double* x,
-              const int* cinst, hipStream_t s) {
-  hipLaunchKernelGGL(k_bxupdate, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, Z, ldz, m, y, x, cinst);
+              const int* cinst, const int* kcols, hipStream_t s) {
+  hipLaunchKernelGGL(k_bxupdate, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, Z, ldz, m, y, x, cinst,
+                     kcols);
 }
 
 void bnorm_partial(int64_t n, const double* w, double* part, hipStream_t s) {
@@ -595,16 +628,20 @@ void dfill_int(int64_t n, int v, int* x, hipStream_t s) {
 
 template void bstencil<double>(const BStencil&, const double*, int, const double*, const double*,
                                const double*, double*, double, double, const double*,
-                               const double*, const uint8_t*, double*, hipStream_t);
+                               const double*, const uint8_t*, const int*, double*, hipStream_t);
 template void bstencil<float>(const BStencil&, const float*, int, const float*, const float*,
                               const float*, float*, float, float, const float*, const float*,
-                              const uint8_t*, float*, hipStream_t);
-template void bspmv_uniform<double>(int, int, const int*, const double*, const uint8_t*,
-                                    const double*, double*, double, double, hipStream_t);
-template void bspmv_uniform<float>(int, int, const int*, const float*, const uint8_t*,
-                                   const float*, float*, float, float, hipStream_t);
+                              const uint8_t*, const int*, float*, hipStream_t);
+template void bspmv_uniform<double>(int, int, const int*, const double*, const uint8_t*, const int*,
+                                    const int*, const double*, double*, double, double, hipStream_t);
+template void bspmv_uniform<float>(int, int, const int*, const float*, const uint8_t*, const int*,
+                                   const int*, const float*, float*, float, float, hipStream_t);
 template void bch_block<double>(const BStencil&, const double*, const double*, const double*,
-                                const double*, const double*, const double*, double, double,
-                                double*, hipStream_t);
+                                const double*, const double*, const int*, const double*, double,
+                                double, double*, hipStream_t);
+template void bconvert<double, float>(int64_t, const double*, float*, const int*, const int*,
+                                      hipStream_t);
+template void bconvert<float, double>(int64_t, const float*, double*, const int*, const int*,
+                                      hipStream_t);
 
 }  // namespace chns

@@ -28,21 +28,28 @@ struct BStencil {
 // Modes: 0 SPMV (y = p0 A x + p1 y), 1 RESID (y = b - A x),
 // 2 CHEB (d <- c1 d + c2 dinv (b - A x), y = x + d; per-instance c1/c2 when
 // cc1/cc2 are given, else p0/p1), 3 CHEB0 (x = d = c2 dinv b).
-// mask (per slice, may be null): rows of slices with mask 0 are skipped.
+// mask (per slice, may be null): rows of slices with mask 0 are skipped;
+// act (per instance, may be null): rows of instances with act 0 are skipped.
 template <typename T>
 void bstencil(const BStencil& A, const T* val, int mode, const T* x, const T* b, const T* dinv,
-              T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, T* y,
-              hipStream_t s);
+              T* d, T p0, T p1, const T* cc1, const T* cc2, const uint8_t* mask, const int* act,
+              T* y, hipStream_t s);
 
-// General uniform-width SELL product with a per-slice mask of output rows.
+// General uniform-width SELL product with a per-slice mask of output rows and
+// per-instance activity (sinst: slice -> instance of the output rows).
 template <typename T>
 void bspmv_uniform(int nrows, int width, const int* col, const T* val, const uint8_t* mask,
-                   const T* x, T* y, T alpha, T beta, hipStream_t s);
+                   const int* sinst, const int* act, const T* x, T* y, T alpha, T beta,
+                   hipStream_t s);
 
-// Stacked CH block on [phi_all; mu_all]: per-instance c12, c22.
+// Stacked CH block on [phi_all; mu_all]: per-instance c12, c22; act may be null.
 template <typename T>
 void bch_block(const BStencil& A, const T* L, const T* K, const T* M, const T* c12, const T* c22,
-               const T* x, T alpha, T beta, T* y, hipStream_t s);
+               const int* act, const T* x, T alpha, T beta, T* y, hipStream_t s);
+
+// Precision conversion on chunks of active instances (cinst: chunk -> instance).
+template <typename TI, typename TO>
+void bconvert(int64_t n, const TI* x, TO* y, const int* cinst, const int* act, hipStream_t s);
 
 // Right-hand sides with per-instance c_mu, c_ac.
 void brhs_binary(const BStencil& A, const double* Mv, const double* phi, const double* Phi,
@@ -57,9 +64,12 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
 // Block vectors of length n (multiple of BCHUNK); chunk c belongs to
 // instance cinst[c].  Per-instance arrays are indexed [inst * stride + j].
 
+// Chunks of instances with flag 0 or act 0 (either may be null) are skipped by
+// the chunked kernels below; their partials and outputs keep stale values.
+
 // part[v * nchunk + c] = sum over chunk c of V_v . w (v < k); V_v = V + v*ldv.
 void bmdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                   const int* flag, const int* cinst, hipStream_t s);
+                   const int* flag, const int* cinst, const int* act, hipStream_t s);
 // For each instance: h[i*hs + v] = sum of its chunks; hcol (H column j of each
 // instance, stride Hs) set or accumulated.  Instance chunk list: ranges
 // [cr[2i], cr[2i+1]) and, when two_ranges, [cr[2i] + half, cr[2i+1] + half).
@@ -68,7 +78,7 @@ void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* c
                   const int* flag, hipStream_t s);
 // w -= V h_inst (k columns) with per-chunk w^2 partials.
 void bmaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, int hs, double* w,
-            double* nrm_part, const int* flag, const int* cinst, hipStream_t s);
+            double* nrm_part, const int* flag, const int* cinst, const int* act, hipStream_t s);
 // Per instance: ||w'||^2 from partials; flag_i = (||w'||^2 < ||w||^2 / 2), ww = h[i*hs + wwpos].
 void breorth_decide(int count, int nchunk, const double* part, const int* cr, int half,
                     const double* h, int hs, int wwpos, int* flag, double* nrm2, hipStream_t s);
@@ -77,15 +87,15 @@ void barnoldi_finish(int count, int nchunk, const double* part2, const int* cr, 
                      const int* flag, const double* nrm2, int j, int m, double* H, double* cs,
                      double* sn, double* g, double* inv, const double* tol, int* active,
                      int* kcols, int* iters, hipStream_t s);
-// x = x * inv[inst] on chunks (v may alias w).
-void bscale(int64_t n, const double* w, const double* inv, const int* cinst, double* v,
-            hipStream_t s);
+// v = w * inv[inst] (v may alias w).
+void bscale(int64_t n, const double* w, const double* inv, const int* cinst, const int* act,
+            double* v, hipStream_t s);
 // Per instance: y = R^{-1} g on its kcols columns (rest 0).
 void blsq(int count, int m, const double* H, const double* g, const int* kcols, double* y,
           hipStream_t s);
-// x += Z y_inst (m columns).
+// x += Z y_inst over the instance's first kcols columns (the rest of Z is not read).
 void bxupdate(int64_t n, const double* Z, int64_t ldz, int m, const double* y, double* x,
-              const int* cinst, hipStream_t s);
+              const int* cinst, const int* kcols, hipStream_t s);
 // Per-instance norms: part[c] = sum w^2 over chunk c; then norm_i, inv_i,
 // g_i = [norm, 0..]; first: tol_i = max(rtol norm_i, atol), active_i = 1;
 // else active_i = (norm_i > tol_i) and kcols_i = m.

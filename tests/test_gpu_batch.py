@@ -93,13 +93,17 @@ def test_batch_instances_match_oracle(chns, precision, rtol, bar):
     batch.close()
 
 
-def test_batch_graph_replays_match_eager(chns):
+@pytest.mark.parametrize("calibrate", [False, True])
+def test_batch_graph_replays_match_eager(chns, calibrate):
     import torch
     prm = _params(len(SIZES), seed=3)
     batch = chns.Batch(SIZES, prm)
     phi0, Phi0 = _fields(SIZES, seed=9)
     opts = chns.default_opts(rtol=1e-10, precision=1, maxiter=200)
+    print(f"batch graph replays: sizes {SIZES}, calibrate={calibrate}", flush=True)
     _, info_e, phi_e, mu_e, Phi_e = _run(chns, batch, phi0, Phi0, opts)
+    if calibrate:
+        batch.calibrate_graph(info_e)
     s = torch.cuda.Stream()
     phi, Phi = _dev(phi0), _dev(Phi0)
     mu = torch.zeros_like(phi)
@@ -118,6 +122,58 @@ def test_batch_graph_replays_match_eager(chns):
             g = got.cpu().numpy()
             assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max(), rep
         assert (info["iters_ch"] == info_e["iters_ch"]).all()
+        assert (info["iters_ac"] == info_e["iters_ac"]).all()
+    batch.close()
+
+
+def test_batch_graph_steps_continue_from_outputs(chns):
+    """Three graph steps (first from the inputs, then from the outputs) equal
+    three eager steps; the inputs stay untouched."""
+    import torch
+    sizes = [64, 32, 96]
+    prm = [dict(eps=0.03, tau=2e-5, mobility=1.0, evap_rate=0.1)] * len(sizes)
+    batch = chns.Batch(sizes, prm)
+    phi0, Phi0 = _fields(sizes, seed=4)
+    opts = chns.default_opts(rtol=1e-11, precision=0, maxiter=200)
+    print(f"batch graph 3 steps: sizes {sizes}", flush=True)
+    phi, Phi = _dev(phi0), _dev(Phi0)
+    mu = torch.zeros_like(phi)
+    rc, info_e = batch.timestep(phi, mu, Phi, 3, opts)
+    torch.cuda.synchronize()
+    assert rc == chns.OK, info_e
+    ref = [t.cpu().numpy() for t in (phi, mu, Phi)]
+    s = torch.cuda.Stream()
+    src = [_dev(phi0), torch.zeros_like(phi), _dev(Phi0)]
+    out = [torch.empty_like(phi) for _ in range(3)]
+    for rep in range(2):
+        torch.cuda.synchronize()
+        rc, info = batch.timestep(*src, nsteps=3, opts=opts, use_graph=True, stream=s, out=out)
+        s.synchronize()
+        assert rc == chns.OK, info
+        for got, r in zip(out, ref):
+            assert np.abs(got.cpu().numpy() - r).max() <= 1e-12 * np.abs(r).max(), rep
+        assert np.array_equal(src[0].cpu().numpy(), phi0)
+        assert np.array_equal(src[2].cpu().numpy(), Phi0)
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+    batch.close()
+
+
+def test_batch_graph_budget_too_small_reports_noconv(chns):
+    import torch
+    sizes = [64, 32]
+    batch = chns.Batch(sizes, _params(2, seed=5))
+    phi0, Phi0 = _fields(sizes, seed=2)
+    batch.set_graph_budget(2, 0)
+    s = torch.cuda.Stream()
+    phi, Phi = _dev(phi0), _dev(Phi0)
+    mu = torch.zeros_like(phi)
+    torch.cuda.synchronize()
+    rc, info = batch.timestep(phi, mu, Phi, 1, chns.default_opts(rtol=1e-12, maxiter=200),
+                              use_graph=True, stream=s)
+    assert rc == chns.WNOCONV
+    assert (info["iters_ch"] == 2).all() and not info["conv_ch"].any()
+    with pytest.raises(chns.ChnsError):
+        batch.set_graph_budget(-1, 0)
     batch.close()
 
 
