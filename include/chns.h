@@ -173,6 +173,23 @@ CHNS_API int chns_set_params(chns_ctx* ctx, const chns_params* params);
 CHNS_API int chns_assemble(chns_ctx* ctx, const double* d_vel, const double* const* d_mu,
                            void* stream);
 
+/* Transposed operators (differentiation form, ternary model): assemble at the
+ * state (d_vel, d_mu) exactly as chns_assemble, then replace each
+ * state-dependent convection part by its transpose (C -> C^T in the CH and AC
+ * blocks, J -> J^T in the Oseen velocity block, N_p -> N_p^T in the PCD
+ * matrix; values moved to the slots of the transposed entries of the
+ * symmetric patterns) before the coarse levels and block values are formed.
+ * M, K, K_sym and the mass terms are symmetric and B enters the Oseen
+ * operator as [[A, B^T], [B, 0]], so chns_spmv, chns_precond_apply and
+ * chns_krylov_solve then act on the transposed systems with the transposed
+ * block preconditioner: with mg_pre == mg_post each V-cycle on the transposed
+ * matrix is the exact transpose of the forward one (same Chebyshev polynomial
+ * before and after the Galerkin coarse correction, R = P^T), and the PCD
+ * factors are applied in reverse order.  chns_assemble restores the forward
+ * operators.  CHNS_EUNSUPPORTED for the binary models. */
+CHNS_API int chns_assemble_transposed(chns_ctx* ctx, const double* d_vel, const double* const* d_mu,
+                                      void* stream);
+
 /* Shape of an assembled operator (host query, no device work). */
 CHNS_API int chns_matrix_shape(chns_ctx* ctx, int32_t op, int64_t* nrows, int64_t* ncols,
                                int64_t* nnz);
@@ -229,6 +246,26 @@ CHNS_API int chns_step_rhs(chns_ctx* ctx, const chns_fields* in, double* d_rhs_c
 CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
                            int32_t nsteps, const chns_solve_opts* opts,
                            chns_solve_info* h_info, void* stream);
+
+/* Adjoint of one ternary step (differentiation form; the discrete adjoint of
+ * the scheme of section "Spatial & temporal discretization").  in: the state
+ * s^k; out: the state s^{k+1} that chns_timestep computes from it (the caller
+ * recomputes it from a checkpoint); lam_out: the adjoint lambda^{k+1} = dL/ds^{k+1}
+ * (phi[2], mu[3], Phi_v, vel; its pressure is ignored: the pressure enters no
+ * later step); lam_in: receives lambda^k = (ds^{k+1}/ds^k)^T lambda^{k+1}
+ * (pressure adjoint 0) and may coincide with lam_out; h_dtheta[3] +=
+ * (ds^{k+1}/dtheta)^T lambda^{k+1} for theta = (eps, mobility, evaporation
+ * rate), with beta = eps^2, delta_v = evap_rate eps^2 and Korteweg
+ * coefficients eps^2.  The four transposed systems (CH for each phase, AC,
+ * Oseen) are solved by FGMRES on the operators of chns_assemble_transposed at
+ * s^k; h_info (4 entries, may be NULL) receives their reports.  The initial
+ * state of a run is data (independent of theta).  Leaves the context holding
+ * the transposed operators.  Returns CHNS_WNOCONV if a solve did not
+ * converge; CHNS_EUNSUPPORTED for the binary models.  Synchronising. */
+CHNS_API int chns_timestep_adjoint(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
+                                   const chns_fields* lam_out, const chns_fields* lam_in,
+                                   double* h_dtheta, const chns_solve_opts* opts,
+                                   chns_solve_info* h_info, void* stream);
 
 /* Message of the last error on this context (never NULL). */
 CHNS_API const char* chns_last_error(const chns_ctx* ctx);

@@ -26,8 +26,8 @@ FLAGS = [
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]
-SOURCES = ["kernels.hip", "kernels_batch.hip", "api.cpp", "batch.cpp", "host_mesh.cpp"]
-HIP_LANG = {"kernels.hip", "kernels_batch.hip", "api.cpp", "batch.cpp"}
+SOURCES = ["kernels.hip", "kernels_batch.hip", "kernels_adj.hip", "api.cpp", "batch.cpp", "host_mesh.cpp"]
+HIP_LANG = {"kernels.hip", "kernels_batch.hip", "kernels_adj.hip", "api.cpp", "batch.cpp"}
 
 
 def _compile(src: str) -> str:

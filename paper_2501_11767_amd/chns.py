@@ -24,6 +24,7 @@ EXPORTS = [
     "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble",
     "chns_matrix_shape", "chns_get_matrix", "chns_spmv", "chns_precond_apply",
     "chns_krylov_solve", "chns_step_rhs", "chns_timestep", "chns_last_error",
+    "chns_assemble_transposed", "chns_timestep_adjoint",
     "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
     "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_last_error",
 ]
@@ -91,6 +92,9 @@ def lib():
     L.chns_step_rhs.argtypes = [vp, ct.POINTER(Fields), vp, vp, vp, vp]
     L.chns_timestep.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(Fields), i32,
                                 ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
+    L.chns_assemble_transposed.argtypes = [vp, vp, vp, vp]
+    L.chns_timestep_adjoint.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(Fields), ct.POINTER(Fields),
+                                        ct.POINTER(Fields), vp, ct.POINTER(SolveOpts), vp, vp]
     L.chns_last_error.argtypes = [vp]
     L.chns_last_error.restype = ct.c_char_p
     L.chns_batch_create.argtypes = [i32, vp, vp, ct.POINTER(vp)]
@@ -181,6 +185,14 @@ class Context:
             mu_arr = (ct.c_void_p * 3)(*[t.data_ptr() for t in mu])
         self._check(self.L.chns_assemble(self.h, _ptr(vel), mu_arr, _stream()))
 
+
+    def assemble_transposed(self, vel, mu=None):
+        """Transposed operators at the state (vel, mu) (ternary model)."""
+        mu_arr = None
+        if mu is not None:
+            self._mu_keep = list(mu)
+            mu_arr = (ct.c_void_p * 3)(*[t.data_ptr() if t is not None else None for t in mu])
+        self._check(self.L.chns_assemble_transposed(self.h, _ptr(vel), mu_arr, _stream()))
     def matrix(self, op):
         """Download an operator as (rowptr, col, val) numpy arrays."""
         import numpy as np
@@ -228,6 +240,18 @@ class Context:
     def step_rhs(self, fin: Fields, rhs_ch, rhs_ac=None, rhs_ns=None):
         self._check(self.L.chns_step_rhs(self.h, ct.byref(fin), _ptr(rhs_ch), _ptr(rhs_ac),
                                          _ptr(rhs_ns), _stream()))
+
+    def timestep_adjoint(self, fin: Fields, fout: Fields, lam_out: Fields, lam_in: Fields, opts=None):
+        """lambda^k from lambda^{k+1} (ternary step); returns (rc, dtheta, infos)
+        with dtheta = the step's contribution to dL/d(eps, mobility, evap_rate)."""
+        import numpy as np
+        o = opts or default_opts()
+        dth = np.zeros(3)
+        infos = (SolveInfo * 4)()
+        rc = self._check(self.L.chns_timestep_adjoint(
+            self.h, ct.byref(fin), ct.byref(fout), ct.byref(lam_out), ct.byref(lam_in),
+            dth.ctypes.data_as(ct.c_void_p), ct.byref(o), infos, _stream()))
+        return rc, dth, [i.as_dict() for i in infos]
 
     def timestep(self, fin: Fields, fout: Fields, nsteps=1, opts=None, nsolves=None):
         o = opts or default_opts()

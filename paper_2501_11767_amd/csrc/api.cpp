@@ -10,6 +10,7 @@
 #include <utility>
 
 #include "context.hpp"
+#include "kernels_adj.hpp"
 
 using namespace chns;
 
@@ -211,6 +212,61 @@ int assemble_base(chns_ctx* c, int kind, double* val, const double* vel, hipStre
                 1.0 / c->mesh.n, vel, n2, val, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
+}
+
+// State-dependent operators: the P1 convection C(v) of the CH and AC blocks,
+// and for the ternary model the P2 convection J(w) of the Oseen velocity block
+// and the P1 convection N_p(w) of the PCD matrix, w = rho v - alpha sum grad
+// mu_i; then the operator values on every level.  transposed: each of these
+// convection parts is replaced by its transpose (values moved to the slots of
+// the transposed entries of the symmetric patterns) before the coarse levels
+// and the combined operators are formed, so every block and preconditioner
+// acts on the transposed system.
+int transpose_values(chns_ctx* c, int64_t n, const int* tmap, double* val, hipStream_t s) {
+  gather_slots(n, tmap, val, c->tbuf, s);
+  HIPCHK(c, hipMemcpyAsync(val, c->tbuf, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return CHNS_OK;
+}
+
+int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bool transposed,
+                 hipStream_t s) {
+  if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
+  Level& L0 = c->lv[0];
+  if (c->ternary) {
+    P2Level& P = c->p2;
+    MuGrad mg{{nullptr, nullptr, nullptr}, c->prm.alpha};
+    if (d_mu)
+      for (int i = 0; i < 3; ++i) mg.mu[i] = d_mu[i];
+    HIPCHK(c, hipMemsetAsync(P.J, 0, P.sell.slots() * sizeof(double), s));
+    HIPCHK(c, hipMemsetAsync(L0.Cw, 0, L0.sell.slots() * sizeof(double), s));
+    double* jo[1] = {P.J};
+    for (int col = 0; col < 8; ++col) {
+      const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
+      assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb,
+                  0.0, d_vel, c->prm.rho, 4 * int64_t(c->N), mg, jo, s);
+      assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, 1.0 / c->mesh.n, d_vel,
+                       c->prm.rho, 4 * int64_t(c->N), mg, L0.Cw, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (transposed) {
+      TRY(transpose_values(c, P.sell.slots(), c->tslot2, P.J, s));
+      TRY(transpose_values(c, L0.sell.slots(), c->tslot1, L0.Cw, s));
+    }
+  }
+  if (d_vel) {
+    TRY(assemble_base(c, 2, L0.C, d_vel, s));
+    if (transposed) TRY(transpose_values(c, L0.sell.slots(), c->tslot1, L0.C, s));
+    galerkin_down(c, &Level::C, &Level::C32, s);
+    c->has_conv = true;
+  } else {
+    for (auto& L : c->lv) {
+      HIPCHK(c, hipMemsetAsync(L.C, 0, L.sell.slots() * sizeof(double), s));
+      HIPCHK(c, hipMemsetAsync(L.C32, 0, L.sell.slots() * sizeof(float), s));
+    }
+    c->has_conv = false;
+  }
+  c->transposed = transposed;
+  return form_operators(c, s);
 }
 
 // ------------------------------------------------------------------ multigrid
@@ -450,12 +506,21 @@ void mean_zero(chns_ctx* c, int64_t n, T* x, hipStream_t s) {
 }
 
 // Pressure convection-diffusion Schur approximation: z = M_p^{-1} A_p K_p^{-1} r
-// with K_p^{-1} on mean-zero pressures.
+// with K_p^{-1} on mean-zero pressures; on transposed operators the factors
+// are applied in reverse order (the exact transpose, M_p and K_p symmetric).
 template <typename T>
 void pcd_apply(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_solve_opts& o,
                hipStream_t s) {
   Level& L0 = c->lv[0];
   const int N = c->N;
+  if (c->transposed) {  // (M_p^{-1} A_p P0 K_p^{-1} P0)^T = P0 K_p^{-1} P0 A_p^T M_p^{-1}
+    mg_solve<T>(c, &Level::Mp, r, tmp1, o, s);
+    spmv<T, T>(L0.d, Sel<T>::v(L0.Ap), tmp1, tmp2, T(1), T(0), s);
+    mean_zero<T>(c, N, tmp2, s);
+    mg_solve<T>(c, &Level::Kp, tmp2, z, o, s);
+    mean_zero<T>(c, N, z, s);
+    return;
+  }
   HIPCHK_VOID(hipMemcpyAsync(tmp1, r, N * sizeof(T), hipMemcpyDeviceToDevice, s));
   mean_zero<T>(c, N, tmp1, s);
   mg_solve<T>(c, &Level::Kp, tmp1, tmp2, o, s);
@@ -852,6 +917,41 @@ int build(chns_ctx* c) {
   for (float** v : {&c->r32, &c->z32}) TRY(dalloc(c, v, NB));
   for (float** v : {&c->w32a, &c->w32b, &c->w32c}) TRY(dalloc(c, v, N1));
   TRY(dalloc(c, &c->red, 1024));
+  if (c->ternary) {
+    // slots of the transposed entries on the finest P1 and P2 patterns (both
+    // symmetric); padding slots map to themselves
+    std::string terr;
+    auto tmap = [&terr](const Csr& A, const Sell& S) {
+      std::vector<int> t(S.slots());
+      for (int64_t q = 0; q < S.slots(); ++q) t[q] = int(q);
+      for (int r = 0; r < A.nrows; ++r)
+        for (int p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+          const int pt = A.find(A.col[p], r);
+          if (pt < 0) {
+            terr = "pattern is not symmetric";
+            continue;
+          }
+          t[S.csr2sell[p]] = S.csr2sell[pt];
+        }
+      return t;
+    };
+    const std::vector<int> t1 = tmap(c->lv[0].csr, c->lv[0].sell), t2 = tmap(c->p2.csr, c->p2.sell);
+    if (!terr.empty()) return fail(c, CHNS_EINVAL, terr);
+    TRY(upload(c, &c->tslot1, t1));
+    TRY(upload(c, &c->tslot2, t2));
+    TRY(dalloc(c, &c->tbuf, size_t(std::max<int64_t>(c->lv[0].sell.slots(), c->p2.sell.slots()))));
+    AdjData& A = c->adj;
+    TRY(dalloc(c, &A.eta, 2 * N2));
+    TRY(dalloc(c, &A.zeta, N1));
+    TRY(dalloc(c, &A.xi, 9 * N1));
+    TRY(dalloc(c, &A.rhs, 9 * N1));
+    for (double*& v : A.v) TRY(dalloc(c, &v, N1));
+    TRY(dalloc(c, &A.q, N1));
+    TRY(dalloc(c, &A.gmu, N1));
+    TRY(dalloc(c, &A.F, 8 * N1));
+    TRY(dalloc(c, &A.part, 3 * size_t(ADJ_NBLK)));
+    TRY(dalloc(c, &A.acc, 4));
+  }
   // Krylov workspace, sized for the largest block
   Krylov& K = c->kr;
   K.nmax = int64_t(NB);
@@ -982,6 +1082,104 @@ int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   return CHNS_OK;
 }
 
+// Adjoint of one ternary step (differentiation form).  With the transposed
+// operators of state k: the closure adjoint q = beta K M^{-1} nu_s, the two CH
+// solves A^T eta_i = [lambda_phi_i - q; lambda_mu_i], the AC solve
+// A_ac^T zeta = lambda_Phi and the Oseen solve A^T xi = [lambda_v; 0]; then
+// the nodal Hessian terms of the explicit densities, the element
+// vector-Jacobian products of the convection, Oseen-convection and Korteweg
+// forms, and the parameter-derivative integrals accumulated in adj.acc.
+int ternary_adjoint(chns_ctx* c, const chns_fields& in, const chns_fields& out, const chns_fields& lo,
+                    const chns_fields& li, const chns_solve_opts& o, chns_solve_info** info,
+                    int& worst, hipStream_t s) {
+  const auto& p = c->prm;
+  const int N = c->N;
+  const int64_t N2 = 2 * int64_t(N), N4 = 4 * int64_t(N);
+  const size_t bytes = size_t(N) * sizeof(double);
+  const double beta = p.eps * p.eps;
+  AdjData& A = c->adj;
+  Level& L0 = c->lv[0];
+  P2Level& P = c->p2;
+  const double h = 1.0 / c->mesh.n;
+  const double* mu3[3] = {in.mu[0], in.mu[1], in.mu[2]};
+  TRY(assemble_ops(c, in.vel, mu3, true, s));
+  cheb_from_zero<double>(L0, L0.Mp, lo.mu[2], c->w64a, cheb_coef<double>(0.49, 2.01, 40), s);
+  spmv<double, double>(L0.d, L0.K, c->w64a, A.q, beta, 0.0, s);
+  for (int i = 0; i < 2; ++i) {
+    double* eta = A.eta + i * N2;
+    axpy_into(N, -1.0, A.q, lo.phi[i], A.rhs, s);
+    HIPCHK(c, hipMemcpyAsync(A.rhs + N, lo.mu[i], bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemsetAsync(eta, 0, 2 * bytes, s));
+    TRY(chns_solve_block(c, CHNS_BLOCK_CH, A.rhs, eta, o, info, worst, s));
+  }
+  HIPCHK(c, hipMemsetAsync(A.zeta, 0, bytes, s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_AC, lo.Phi_v, A.zeta, o, info, worst, s));
+  HIPCHK(c, hipMemcpyAsync(A.rhs, lo.vel, 8 * bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemsetAsync(A.rhs + 8 * int64_t(N), 0, bytes, s));
+  HIPCHK(c, hipMemsetAsync(A.xi, 0, 9 * bytes, s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_NS, A.rhs, A.xi, o, info, worst, s));
+  // M and K products of the CH and AC adjoint solutions
+  const double* src[10] = {A.eta, A.eta + N2, A.eta + N, A.eta + N2 + N, A.eta, A.eta + N2,
+                           A.eta + N, A.eta + N2 + N, A.zeta, A.zeta};
+  for (int k = 0; k < 10; ++k) {
+    const bool useK = (k >= 4 && k < 8) || k == 9;
+    spmv<double, double>(L0.d, useK ? L0.K : L0.M, src[k], A.v[k], 1.0, 0.0, s);
+  }
+  AdjNodal a{};
+  a.php = in.phi[0];
+  a.phn = in.phi[1];
+  a.Phi = in.Phi_v;
+  a.php1 = out.phi[0];
+  a.phn1 = out.phi[1];
+  a.mup1 = out.mu[0];
+  a.mun1 = out.mu[1];
+  a.mus1 = out.mu[2];
+  a.Phi1 = out.Phi_v;
+  a.Me1p = A.v[0];
+  a.Me1n = A.v[1];
+  a.Me2p = A.v[2];
+  a.Me2n = A.v[3];
+  a.Ke1p = A.v[4];
+  a.Ke1n = A.v[5];
+  a.Ke2p = A.v[6];
+  a.Ke2n = A.v[7];
+  a.Mz = A.v[8];
+  a.Kz = A.v[9];
+  a.nus = lo.mu[2];
+  a.lam_php = li.phi[0];
+  a.lam_phn = li.phi[1];
+  a.lam_Phi = li.Phi_v;
+  a.eps = p.eps;
+  a.tau = p.tau;
+  a.gam = p.mobility;
+  a.gv = p.evap_rate;
+  adj_nodal(N, a, A.part, s);
+  adj_finish(3, ADJ_NBLK, A.part, A.acc, s);
+  const double cm = p.rho / p.tau;
+  spmv<double, double>(P.d, P.Mv, A.xi, li.vel, cm, 0.0, s);
+  spmv<double, double>(P.d, P.Mv, A.xi + N4, li.vel + N4, cm, 0.0, s);
+  HIPCHK(c, hipMemsetAsync(A.gmu, 0, bytes, s));
+  const double* etas[3] = {A.eta, A.eta + N2, A.zeta};
+  const double* xs[3] = {out.phi[0], out.phi[1], out.Phi_v};
+  for (int col = 0; col < 8; ++col) {
+    const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
+    adj_p1conv(e0, e1, c->ep1, c->ep2, c->etype, h, N4, etas, xs, -p.tau, li.vel, s);
+    adj_ns(e0, e1, c->ep1, c->ep2, c->etype, h, c->ns.tb, N4, A.xi, out.vel, p.rho, p.alpha, in.phi[0],
+           in.phi[1], in.Phi_v, beta, beta, li.vel, A.gmu, li.phi[0], li.phi[1], li.Phi_v, s);
+  }
+  for (int i = 0; i < 3; ++i)
+    HIPCHK(c, hipMemcpyAsync(li.mu[i], A.gmu, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemsetAsync(li.p, 0, bytes, s));
+  // Korteweg coefficients beta_i = beta_v = eps^2: d/deps (xi^T F) = (2 / eps) xi^T F
+  HIPCHK(c, hipMemsetAsync(A.F, 0, 8 * bytes, s));
+  for (int col = 0; col < 8; ++col)
+    korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype, h, c->ns.tb,
+             in.phi[0], in.phi[1], in.Phi_v, beta, beta, N4, A.F, s);
+  dot_acc(8 * int64_t(N), A.xi, A.F, 2.0 / p.eps, A.part, A.acc, s);
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
 int chns_solve_block(chns_ctx* c, int block, const double* b, double* x, const chns_solve_opts& o,
                      chns_solve_info** info, int& worst, hipStream_t s) {
   chns_solve_info inf{};
@@ -1068,38 +1266,13 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
 
 int chns_assemble(chns_ctx* c, const double* d_vel, const double* const* d_mu, void* stream) {
   if (!c) return CHNS_EINVAL;
-  if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Level& L0 = c->lv[0];
-  if (c->ternary) {
-    P2Level& P = c->p2;
-    MuGrad mg{{nullptr, nullptr, nullptr}, c->prm.alpha};
-    if (d_mu)
-      for (int i = 0; i < 3; ++i) mg.mu[i] = d_mu[i];
-    HIPCHK(c, hipMemsetAsync(P.J, 0, P.sell.slots() * sizeof(double), s));
-    HIPCHK(c, hipMemsetAsync(L0.Cw, 0, L0.sell.slots() * sizeof(double), s));
-    double* jo[1] = {P.J};
-    for (int col = 0; col < 8; ++col) {
-      const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
-      assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb,
-                  0.0, d_vel, c->prm.rho, 4 * int64_t(c->N), mg, jo, s);
-      assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, 1.0 / c->mesh.n, d_vel,
-                       c->prm.rho, 4 * int64_t(c->N), mg, L0.Cw, s);
-    }
-    HIPCHK(c, hipGetLastError());
-  }
-  if (d_vel) {
-    TRY(assemble_base(c, 2, L0.C, d_vel, s));
-    galerkin_down(c, &Level::C, &Level::C32, s);
-    c->has_conv = true;
-  } else {
-    for (auto& L : c->lv) {
-      HIPCHK(c, hipMemsetAsync(L.C, 0, L.sell.slots() * sizeof(double), s));
-      HIPCHK(c, hipMemsetAsync(L.C32, 0, L.sell.slots() * sizeof(float), s));
-    }
-    c->has_conv = false;
-  }
-  return form_operators(c, s);
+  return assemble_ops(c, d_vel, d_mu, false, static_cast<hipStream_t>(stream));
+}
+
+int chns_assemble_transposed(chns_ctx* c, const double* d_vel, const double* const* d_mu, void* stream) {
+  if (!c) return CHNS_EINVAL;
+  if (!c->ternary) return fail(c, CHNS_EUNSUPPORTED, "transposed operators need the ternary model");
+  return assemble_ops(c, d_vel, d_mu, true, static_cast<hipStream_t>(stream));
 }
 
 int chns_matrix_shape(chns_ctx* c, int32_t op, int64_t* nrows, int64_t* ncols, int64_t* nnz) {
@@ -1369,6 +1542,31 @@ int chns_timestep(chns_ctx* c, const chns_fields* in, const chns_fields* out, in
     cur = *out;
   }
   HIPCHK(c, hipStreamSynchronize(s));
+  return worst;
+}
+
+int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields* out,
+                          const chns_fields* lam_out, const chns_fields* lam_in, double* h_dtheta,
+                          const chns_solve_opts* opts, chns_solve_info* h_info, void* stream) {
+  if (!c) return CHNS_EINVAL;
+  TRY(check_opts(c, opts));
+  if (!c->ternary) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is defined for the ternary model");
+  if (!in || !out || !lam_out || !lam_in || !h_dtheta) return fail(c, CHNS_EINVAL, "NULL argument");
+  const chns_fields* full[3] = {in, out, lam_in};
+  for (const chns_fields* f : full)
+    if (!f->phi[0] || !f->phi[1] || !f->mu[0] || !f->mu[1] || !f->mu[2] || !f->Phi_v || !f->vel || !f->p)
+      return fail(c, CHNS_EINVAL, "states and the output adjoint need every field");
+  if (!lam_out->phi[0] || !lam_out->phi[1] || !lam_out->mu[0] || !lam_out->mu[1] || !lam_out->mu[2] ||
+      !lam_out->Phi_v || !lam_out->vel)
+    return fail(c, CHNS_EINVAL, "the input adjoint needs phi, mu, Phi_v and vel");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(c, hipMemsetAsync(c->adj.acc, 0, 4 * sizeof(double), s));
+  int worst = CHNS_OK;
+  chns_solve_info* info = h_info;
+  TRY(ternary_adjoint(c, *in, *out, *lam_out, *lam_in, *opts, &info, worst, s));
+  HIPCHK(c, hipMemcpyAsync(c->kr.host, c->adj.acc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int i = 0; i < 3; ++i) h_dtheta[i] += c->kr.host[i];
   return worst;
 }
 

@@ -101,6 +101,19 @@ struct Krylov {
   double* host = nullptr;  // pinned readback
 };
 
+// Work vectors of the adjoint step (ternary contexts).
+struct AdjData {
+  double *eta = nullptr;   // two CH adjoint solutions, 2N each
+  double *zeta = nullptr;  // AC adjoint solution, N
+  double *xi = nullptr;    // Oseen adjoint solution, 9N
+  double *rhs = nullptr;   // staged right-hand side, 9N
+  double* v[10] = {};      // M and K products of the adjoint solutions, N each
+  double *q = nullptr, *gmu = nullptr;
+  double *F = nullptr;     // Korteweg load, 8N
+  double *part = nullptr;  // reduction partials
+  double *acc = nullptr;   // dL/d(eps, mobility, evaporation rate)
+};
+
 }  // namespace chns
 
 struct chns_ctx {
@@ -118,6 +131,12 @@ struct chns_ctx {
   chns::Elements el;
   int *ep1 = nullptr, *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;
   chns::Krylov kr;
+  // differentiation form: operators hold the transposed convection parts;
+  // slot maps of the transposed entries (finest P1 and P2 patterns)
+  bool transposed = false;
+  int *tslot1 = nullptr, *tslot2 = nullptr;
+  double* tbuf = nullptr;
+  chns::AdjData adj;
   // scratch: FP64 tmp1/tmp2/corr (N each), FP32 r/z (2N each) and
   // tmp1/tmp2/corr (N each), right-hand sides and the CH unknown [phi; mu]
   double *w64a = nullptr, *w64b = nullptr, *w64c = nullptr;

@@ -2,6 +2,7 @@
 // per-level P1 operators, stacked Krylov vectors with per-instance scalars).
 #include <hip/hip_runtime.h>
 
+#include "device_util.hpp"
 #include "kernels_batch.hpp"
 
 namespace chns {
@@ -13,20 +14,8 @@ constexpr int W7 = 7;
 
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-  const int per = nb >> 3, rem = nb & 7;
-  const int x = b & 7, k = b >> 3;
-  return x * per + (x < rem ? x : rem) + k;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // Sum over the workgroup (any multiple of 64 up to 1024); valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+__device__ __forceinline__ double block_sum_any(double v, double* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = v;
@@ -238,7 +227,7 @@ __global__ __launch_bounds__(BS) void k_bmdot_partial(int64_t n, const double* _
       if (i < kk) acc[i] += V[(g0 + i) * ldv + r] * wr;
   }
   for (int i = 0; i < kk; ++i) {
-    const double s = block_sum(acc[i], sh);
+    const double s = block_sum_any(acc[i], sh);
     if (threadIdx.x == 0) part[int64_t(g0 + i) * gridDim.x + c] = s;
   }
 }
@@ -260,7 +249,7 @@ __global__ __launch_bounds__(BS) void k_bmdot_reduce(int nchunk, int k, const do
   const int i = blockIdx.x, v = blockIdx.y;
   if (flag && flag[i] == 0) return;
   __shared__ double sh[16];
-  const double s = block_sum(chunk_sum(part + int64_t(v) * nchunk, cr, half, i), sh);
+  const double s = block_sum_any(chunk_sum(part + int64_t(v) * nchunk, cr, half, i), sh);
   if (threadIdx.x == 0) {
     h[i * hs + v] = s;
     double* hc = H + int64_t(i) * Hs + int64_t(j) * ldH;
@@ -292,7 +281,7 @@ __global__ __launch_bounds__(BS) void k_bmaxpy(int64_t n, const double* __restri
     w[r] = wr;
     acc += wr * wr;
   }
-  const double s = block_sum(acc, sh);
+  const double s = block_sum_any(acc, sh);
   if (threadIdx.x == 0) nrm_part[c] = s;
 }
 
@@ -303,7 +292,7 @@ __global__ __launch_bounds__(BS) void k_breorth_decide(int nchunk, const double*
                                                        double* __restrict__ nrm2) {
   const int i = blockIdx.x;
   __shared__ double sh[16];
-  const double s = block_sum(chunk_sum(part, cr, half, i), sh);
+  const double s = block_sum_any(chunk_sum(part, cr, half, i), sh);
   if (threadIdx.x == 0) {
     nrm2[i] = s;
     flag[i] = (s < 0.5 * h[i * hs + wwpos]) ? 1 : 0;
@@ -325,7 +314,7 @@ __global__ __launch_bounds__(BS) void k_barnoldi_finish(int nchunk, const double
                                                         int* __restrict__ iters) {
   const int i = blockIdx.x;
   __shared__ double sh[16];
-  const double s2 = block_sum(chunk_sum(part2, cr, half, i), sh);
+  const double s2 = block_sum_any(chunk_sum(part2, cr, half, i), sh);
   if (threadIdx.x != 0) return;
   if (!active[i]) {
     inv[i] = 0.0;
@@ -433,7 +422,7 @@ __global__ __launch_bounds__(BS) void k_bnorm_partial(int64_t n, const double* _
     const double v = w[int64_t(c) * BCHUNK + rr * BS + threadIdx.x];
     acc += v * v;
   }
-  const double s = block_sum(acc, sh);
+  const double s = block_sum_any(acc, sh);
   if (threadIdx.x == 0) part[c] = s;
 }
 
@@ -448,7 +437,7 @@ __global__ __launch_bounds__(BS) void k_bnorm_finish(int nchunk, const double* _
                                                      int* __restrict__ kcols) {
   const int i = blockIdx.x;
   __shared__ double sh[16];
-  const double s = block_sum(chunk_sum(part, cr, half, i), sh);
+  const double s = block_sum_any(chunk_sum(part, cr, half, i), sh);
   if (threadIdx.x != 0) return;
   const double v = sqrt(s);
   nrm[i] = v;
