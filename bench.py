@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--dry-steps", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--forms", default="mixed,fp64", help="timed forms of the 1024^2 step")
     return ap.parse_args()
 
 
@@ -268,6 +270,130 @@ def batch_section(chns, steps):
                 sequential_fp64_iters_ch_mean=seq_its / len(sizes), setup_s=setup, graph_steps=steps)
 
 
+def adjoint_state0(n, cfg):
+    """Seeded initial state of the differentiation workload (mu^0 = p^0 = 0)."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    f = inputs.initial_state(n, "ternary", cfg["mean"], cfg["seed"])
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    N = n * n
+    return dict(phi_p=dev(f["phi"][0]), phi_n=dev(f["phi"][1]), mu_p=z(N), mu_n=z(N), mu_s=z(N),
+                Phi=dev(f["Phi_v"]), vel=dev(np.asarray(f["vel"]).ravel()), p=z(N))
+
+
+def adjoint_section(chns):
+    """Differentiation form on the 128 x 128 ternary workload: 50 steps,
+    checkpoint every 10, loss = M-weighted L2 mismatch of the final volume
+    fractions to the run at theta_ref; gradient at theta0 by the adjoint
+    (FP64 FGMRES, FP32 multigrid, rtol 1e-10) against central differences
+    with absolute step 1e-6 (FP64 solves at rtol 1e-13)."""
+    import torch
+    from paper_2501_11767_amd import adjoint as A, inputs
+    cfg = inputs.CONFIGS["adjoint128"]
+    n, steps, K = cfg["n"], cfg["steps"], cfg["checkpoint"]
+    ref = (cfg["eps"], cfg["mobility"], cfg["evap_rate"])
+    th0 = tuple(cfg["theta0"])
+    ctx = chns.Context(n, "ternary", eps=ref[0], tau=cfg["tau"], mobility=ref[1], evap_rate=ref[2],
+                       viscosity=cfg["viscosity"], alpha=cfg["alpha"], rho=1.0)
+    st0 = adjoint_state0(n, cfg)
+    tight = chns.default_opts(rtol=1e-13, precision=chns.F64, maxiter=3000)
+    mixed = chns.default_opts(rtol=1e-10, precision=chns.MIXED, maxiter=2000)
+
+    def final(theta, opts):
+        with torch.no_grad():
+            th = torch.tensor(theta, dtype=torch.float64)
+            return A.rollout(ctx, th, st0, steps, checkpoint=K, opts=opts)
+
+    log("adjoint128: target run at theta_ref")
+    target = [t.clone() for t in final(ref, tight)]
+
+    def loss_at(theta, opts):
+        php, phn = final(theta, opts)
+        return float(A.loss(ctx, (php, phn), target))
+
+    res = {}
+    for name, opts in (("mixed", mixed), ("fp64", tight)):
+        log(f"adjoint128: rollout + adjoint at theta0 ({name})")
+        theta = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        php, phn = A.rollout(ctx, theta, st0, steps, checkpoint=K, opts=opts)
+        L = A.loss(ctx, (php, phn), target)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[name] = dict(loss=float(L.detach()), grad=theta.grad.tolist(), forward_ms=(t1 - t0) * 1e3,
+                         backward_ms=(t2 - t1) * 1e3)
+    log("adjoint128: central differences")
+    fd = []
+    for j in range(3):
+        h = 1e-6
+        tp, tm = list(th0), list(th0)
+        tp[j] += h
+        tm[j] -= h
+        fd.append((loss_at(tp, tight) - loss_at(tm, tight)) / (2 * h))
+    # fourth-order differences with relative steps 1e-3 (truncation O(h^4)):
+    # the evaporation-rate derivative is ~1e-10, so with h = 1e-6 the
+    # difference quotient is limited by the rounding of L itself
+    fd4 = []
+    for j in range(3):
+        h = 1e-3 * th0[j]
+        at = lambda k: loss_at([th0[i] + (k * h if i == j else 0.0) for i in range(3)], tight)
+        fd4.append((-at(2) + 8 * at(1) - 8 * at(-1) + at(-2)) / (12 * h))
+    L_ref = loss_at(ref, tight)
+    for name in ("mixed", "fp64"):
+        g = res[name]["grad"]
+        res[name]["rel_err_vs_fd"] = [abs(a - b) / abs(b) for a, b in zip(g, fd)]
+        res[name]["rel_err_vs_fd4"] = [abs(a - b) / abs(b) for a, b in zip(g, fd4)]
+    ctx.close()
+    return dict(workload=f"adjoint128: ternary CH + AC + Oseen, periodic {n}x{n}, {steps} steps at "
+                         f"tau {cfg['tau']} (the stated 1e-3 diverges with the explicit potential), "
+                         f"checkpoint every {K}; loss = 1/2 sum_i |phi_i^N - target_i|_M^2, target from "
+                         f"theta_ref = {ref}; gradient at theta0 = {th0}",
+                theta0=list(th0), fd_grad=fd, fd_step=1e-6, fd4_grad=fd4, fd4_rel_step=1e-3,
+                loss_at_ref=L_ref, **res)
+
+
+def cpu_adjoint_reference(chns, n=16, steps=10):
+    """CPU leg: the oracle's FP64 reverse-sweep gradient on a bounded sample
+    of the differentiation workload (same parameters, n x n, `steps` steps)
+    next to the GPU adjoint on the same sample."""
+    import torch
+    from oracle import adjoint as AD, step as S
+    from oracle.systems import Params
+    from paper_2501_11767_amd import adjoint as A, inputs
+    cfg = inputs.CONFIGS["adjoint128"]
+    ref = dict(eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"],
+               viscosity=cfg["viscosity"], alpha=cfg["alpha"])
+    th0 = dict(ref, eps=cfg["theta0"][0], mobility=cfg["theta0"][1], evap_rate=cfg["theta0"][2])
+    f = inputs.initial_state(n, "ternary", cfg["mean"], cfg["seed"])
+    N = n * n
+    st0 = dict(phi=[f["phi"][0], f["phi"][1]], mu=[np.zeros(N), np.zeros(N)], mu_s=np.zeros(N),
+               Phi_v=f["Phi_v"], vel=np.asarray(f["vel"]).reshape(2, 4 * N), p=np.zeros(N))
+    ops = S.Operators(n, need_p2=True)
+    t0 = time.perf_counter()
+    target = AD.rollout(ops, Params(**ref), st0, steps)[-1]["phi"]
+    L, g = AD.gradient(ops, Params(**th0), st0, target, steps)
+    cpu_s = time.perf_counter() - t0
+    ctx = chns.Context(n, "ternary", **dict(th0, rho=1.0))
+    theta = torch.tensor([th0["eps"], th0["mobility"], th0["evap_rate"]], dtype=torch.float64,
+                         requires_grad=True)
+    s0 = dict(phi_p=dev(st0["phi"][0]), phi_n=dev(st0["phi"][1]), mu_p=dev(st0["mu"][0]),
+              mu_n=dev(st0["mu"][1]), mu_s=dev(st0["mu_s"]), Phi=dev(st0["Phi_v"]),
+              vel=dev(st0["vel"].ravel()), p=dev(st0["p"]))
+    opts = chns.default_opts(rtol=1e-13, precision=chns.F64, maxiter=3000)
+    php, phn = A.rollout(ctx, theta, s0, steps, checkpoint=cfg["checkpoint"], opts=opts)
+    Lg = A.loss(ctx, (php, phn), (dev(target[0]), dev(target[1])))
+    Lg.backward()
+    ctx.close()
+    gg = theta.grad.tolist()
+    return dict(sample=f"{n}x{n}, {steps} steps, adjoint128 parameters, oracle FP64 direct solves",
+                oracle_grad=list(g), gpu_grad=gg, oracle_loss=L, gpu_loss=float(Lg.detach()),
+                rel_err=[abs(a - b) / abs(b) for a, b in zip(gg, g)], oracle_s=cpu_s, cores=1)
+
+
 def oracle_errors(cfg, n, st0, sweep, sweep_fields):
     """CPU leg: the oracle's exact solve of each swept step (convection-free
     periodic systems, one 2x2 solve per Fourier mode) and the relative error
@@ -319,7 +445,10 @@ def main():
                        mu=[torch.empty(N, dtype=torch.float64, device="cuda")],
                        Phi_v=torch.empty(N, dtype=torch.float64, device="cuda"))
     res = {}
+    forms = [f for f in args.forms.split(",") if f]
     for name, prec in (("mixed", chns.MIXED), ("fp64", chns.F64)):
+        if name not in forms:
+            continue
         opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart)
         log(f"chac{n}: {name} warmup {args.warmup} + {args.steps} timed steps")
         run_steps(ctx, chns, f_in, f_out, args.warmup, opts)
@@ -361,12 +490,18 @@ def main():
         log(f"dry256: {args.dry_steps} steps")
     dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
     bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
+    adj = None if args.no_adjoint else adjoint_section(chns)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: oracle on the host")
         cpu = cpu_baseline(cfg, n, args.tau)
         if sweep:
             oracle_errors(cfg, n, st0, sweep, sweep_fields)
+        if adj is not None:
+            log("cpu leg: oracle adjoint on a bounded sample")
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(1):
+                adj["cpu_reference"] = cpu_adjoint_reference(chns)
 
     dom = "ch_block_f64"
     kd = kern[dom]
@@ -391,12 +526,13 @@ def main():
                      "unit": "GB/s", "frac": kd["frac"], "traffic": None,
                      "bytes_per_launch": kd["bytes"], "us_per_launch": kd["us"]},
         "cpu_baseline": cpu,
-        "mixed": res["mixed"],
-        "fp64": res["fp64"],
+        "mixed": res.get("mixed"),
+        "fp64": res.get("fp64"),
         "kernels": kern,
         "sweep": sweep,
         "dry256": dry,
         "batch64": bat,
+        "adjoint128": adj,
     }
     ctx.close()
     print(json.dumps(line))
