@@ -659,20 +659,15 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       double* vj = K.V + j * ld;
       double* vn = K.V + (j + 1) * ld;
       double* zj = K.Z + j * ld;
-      double* hcol = K.H + int64_t(j) * (m + 1);
       TRY(precond(c, block, o, vj, zj, s));
       TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
-      // classical Gram-Schmidt; the first multi-dot also gives ||w||^2 (w is
-      // basis slot j+1), the update gives ||w'||^2, and a second pass runs
-      // only when ||w'||^2 < ||w||^2 / 2 (decided on the device).
-      mdot_partial(n, K.V, ld, j + 2, vn, K.part, nullptr, s);
-      mdot_reduce(nblk, j + 2, K.part, K.htmp, hcol, 0, nullptr, s);
-      maxpy(n, K.V, ld, j + 1, K.htmp, vn, K.nrm_part, nullptr, s);
-      reorth_decide(nblk, K.nrm_part, K.htmp + j + 1, K.flag, K.scal, s);
-      mdot_partial(n, K.V, ld, j + 1, vn, K.part, K.flag, s);
-      mdot_reduce(nblk, j + 1, K.part, K.htmp, hcol, 1, K.flag, s);
-      maxpy(n, K.V, ld, j + 1, K.htmp, vn, K.nrm_part2, K.flag, s);
-      arnoldi_finish(nblk, K.nrm_part2, K.flag, j, m, K.H, K.cs, K.sn, K.g, K.scal, s);
+      // DCGS2: one dot pass and one update pass over the basis (the previous
+      // vector's reorthogonalisation rides along with w's projection)
+      dcgs_dots(n, K.V, ld, j, K.part, s);
+      slot_reduce(nblk, 2 * j + 3, K.part, K.red, s);
+      dcgs_coef(j, m, K.red, K.H, K.coef, s);
+      dcgs_update(n, K.V, ld, j, K.coef, K.nrm_part, s);
+      dcgs_finish(nblk, K.nrm_part, j, m, K.H, K.HR, K.cs, K.sn, K.g, K.gp, K.scal, s);
       scale_by_inv(n, vn, K.scal + 1, vn, s);
       HIPCHK(c, hipGetLastError());
       k = j + 1;
@@ -681,7 +676,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       const double est = K.host[0], hnext = K.host[2];
       if (est <= tol || hnext == 0.0 || iters >= o.maxiter || !std::isfinite(est)) break;
     }
-    lsq_solve(k, m, K.H, K.g, K.y, s);
+    lsq_solve(k, m, K.HR, K.gp, K.y, s);
     xupdate(n, K.Z, ld, k, K.y, x, s);
     HIPCHK(c, hipGetLastError());
   }
@@ -963,11 +958,12 @@ int build(chns_ctx* c) {
   TRY(dalloc(c, &K.g, MAX_RESTART + 2));
   TRY(dalloc(c, &K.y, MAX_RESTART + 1));
   TRY(dalloc(c, &K.scal, 8));
-  TRY(dalloc(c, &K.htmp, MAX_RESTART + 2));
-  TRY(dalloc(c, &K.part, size_t(1024) * (MAX_RESTART + 2)));
+  TRY(dalloc(c, &K.part, size_t(1024) * (2 * MAX_RESTART + 4)));
+  TRY(dalloc(c, &K.HR, size_t(MAX_RESTART + 1) * MAX_RESTART));
+  TRY(dalloc(c, &K.gp, MAX_RESTART + 2));
+  TRY(dalloc(c, &K.red, 2 * MAX_RESTART + 4));
+  TRY(dalloc(c, &K.coef, 2 * MAX_RESTART + 4));
   TRY(dalloc(c, &K.nrm_part, 1024));
-  TRY(dalloc(c, &K.nrm_part2, 1024));
-  TRY(dalloc(c, &K.flag, 4));
   HIPCHK(c, hipHostMalloc((void**)&K.host, 8 * sizeof(double), hipHostMallocDefault));
   HIPCHK(c, hipEventCreate(&c->ev0));
   HIPCHK(c, hipEventCreate(&c->ev1));

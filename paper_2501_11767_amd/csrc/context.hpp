@@ -95,9 +95,8 @@ struct Krylov {
   int64_t nmax = 0;
   double *V = nullptr, *Z = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
-  double *scal = nullptr, *htmp = nullptr, *part = nullptr, *nrm_part = nullptr;
-  double* nrm_part2 = nullptr;
-  int* flag = nullptr;  // second Gram-Schmidt pass wanted
+  double *scal = nullptr, *part = nullptr, *nrm_part = nullptr;
+  double *HR = nullptr, *gp = nullptr, *red = nullptr, *coef = nullptr;  // DCGS2
   double* host = nullptr;  // pinned readback
 };
 

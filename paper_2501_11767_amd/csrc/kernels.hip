@@ -208,72 +208,143 @@ __global__ __launch_bounds__(BS) void k_scale_by_inv(int64_t n, const double* __
 
 // ------------------------------------------------------------------ Krylov reductions
 
-constexpr int MD_G = 8;  // basis vectors per multi-dot pass
+// Delayed classical Gram-Schmidt with reorthogonalisation (DCGS2): at Arnoldi
+// step j the stored vector V_j (= vt) is orthogonalised once; one pass over
+// V_0..V_{j-1} gives both its reorthogonalisation dots and the projection dots
+// of the new vector w = V_{j+1}, one pass applies both updates.
 
-__global__ __launch_bounds__(BS) void k_mdot_partial(int64_t n, const double* __restrict__ V,
-                                                     int64_t ldv, int k,
-                                                     const double* __restrict__ w,
-                                                     double* __restrict__ part,
-                                                     const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+constexpr int DG = 16;  // basis vectors per group of the dot pass
+
+// Dots of one group of basis vectors against vt and w.  Slots (per block
+// partial, stride gridDim.x): [0, j) V_i . vt, [j, 2j) V_i . w, then vt . vt,
+// vt . w, w . w (written by the last group).
+__global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __restrict__ V, int64_t ld,
+                                                  int j, double* __restrict__ part) {
   __shared__ double sh[4];
-  const int g0 = blockIdx.y * MD_G;
-  const int kk = min(MD_G, k - g0);
-  double acc[MD_G];
+  const double* vt = V + int64_t(j) * ld;
+  const double* w = V + int64_t(j + 1) * ld;
+  const int g0 = blockIdx.y * DG;
+  const int kk = max(0, min(DG, j - g0));
+  const bool last = (blockIdx.y == gridDim.y - 1);
+  double ac[DG], aw[DG];
 #pragma unroll
-  for (int i = 0; i < MD_G; ++i) acc[i] = 0.0;
+  for (int i = 0; i < DG; ++i) ac[i] = aw[i] = 0.0;
+  double nu = 0.0, tw = 0.0, ww = 0.0;
   const int64_t stride = int64_t(gridDim.x) * BS;
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
-    const double wr = w[r];
+    const double t = vt[r], wr = w[r];
 #pragma unroll
-    for (int i = 0; i < MD_G; ++i)
-      if (i < kk) acc[i] += V[(g0 + i) * ldv + r] * wr;
+    for (int i = 0; i < DG; ++i)
+      if (i < kk) {
+        const double v = V[(g0 + i) * ld + r];
+        ac[i] += v * t;
+        aw[i] += v * wr;
+      }
+    if (last) {
+      nu += t * t;
+      tw += t * wr;
+      ww += wr * wr;
+    }
   }
+  const int nb = gridDim.x, b = blockIdx.x;
   for (int i = 0; i < kk; ++i) {
-    const double s = block_sum(acc[i], sh);
-    if (threadIdx.x == 0) part[int64_t(g0 + i) * gridDim.x + blockIdx.x] = s;
+    const double s1 = block_sum(ac[i], sh);
+    const double s2 = block_sum(aw[i], sh);
+    if (threadIdx.x == 0) {
+      part[int64_t(g0 + i) * nb + b] = s1;
+      part[int64_t(j + g0 + i) * nb + b] = s2;
+    }
+  }
+  if (last) {
+    const double s1 = block_sum(nu, sh);
+    const double s2 = block_sum(tw, sh);
+    const double s3 = block_sum(ww, sh);
+    if (threadIdx.x == 0) {
+      part[int64_t(2 * j) * nb + b] = s1;
+      part[int64_t(2 * j + 1) * nb + b] = s2;
+      part[int64_t(2 * j + 2) * nb + b] = s3;
+    }
   }
 }
 
-// One workgroup per basis vector.
-__global__ __launch_bounds__(BS) void k_mdot_reduce(int nblk, int k, const double* __restrict__ part,
-                                                    double* __restrict__ h_tmp,
-                                                    double* __restrict__ h_col, int accumulate,
-                                                    const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
+// One workgroup per slot: red[i] = sum of the slot's partials.
+__global__ __launch_bounds__(BS) void k_slot_reduce(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ red) {
   __shared__ double sh[4];
   const int i = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += BS) s += part[int64_t(i) * nblk + b];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) {
-    h_tmp[i] = s;
-    h_col[i] = accumulate ? h_col[i] + s : s;
-  }
+  if (threadIdx.x == 0) red[i] = s;
 }
 
-__global__ __launch_bounds__(BS) void k_maxpy(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                              int k, const double* __restrict__ h,
-                                              double* __restrict__ w,
-                                              double* __restrict__ nrm_part,
-                                              const int* __restrict__ flag) {
-  if (flag && *flag == 0) return;
-  __shared__ double hs[257];
+// Coefficients of step j (one thread).  j >= 1: vt = sum c_i V_i + r v_j with
+// r = sqrt(vt.vt - |c|^2); column j-1 of the raw Hessenberg H (whose last entry
+// multiplied vt) becomes h_i += h_j c_i, h_j *= r.  Projection of w on the
+// final basis: a_i = V_i . w (i < j), b = (vt . w - c . a) / r; so
+// w' = w - sum (a_i - b c_i / r) V_i - (b / r) vt and v_j = (vt - sum c_i V_i) / r.
+// coef: [0, j) c_i, [j, 2j+1) the w coefficients (last one multiplies vt), 2j+1: 1/r.
+__global__ void k_dcgs_coef(int j, int m, const double* __restrict__ red, double* __restrict__ H,
+                            double* __restrict__ coef) {
+  if (threadIdx.x != 0) return;
+  const int ld = m + 1;
+  const double* c = red;
+  const double* a = red + j;
+  const double nu = red[2 * j], tw = red[2 * j + 1];
+  double r = 1.0, ca = 0.0;
+  if (j > 0) {
+    double cc = 0.0;
+    for (int i = 0; i < j; ++i) {
+      cc += c[i] * c[i];
+      ca += c[i] * a[i];
+    }
+    r = sqrt(fmax(nu - cc, 0.0));
+    double* hp = H + int64_t(j - 1) * ld;
+    const double hj = hp[j];
+    for (int i = 0; i < j; ++i) hp[i] += hj * c[i];
+    hp[j] = hj * r;
+  }
+  const double inv = r > 0.0 ? 1.0 / r : 0.0;
+  const double b = (tw - ca) * inv;
+  double* h = H + int64_t(j) * ld;
+  for (int i = 0; i < j; ++i) {
+    h[i] = a[i];
+    coef[i] = c[i];
+    coef[j + i] = a[i] - b * c[i] * inv;
+  }
+  h[j] = b;
+  coef[2 * j] = b * inv;
+  coef[2 * j + 1] = inv;
+}
+
+// w <- w - sum_{i<j} coef[j+i] V_i - coef[2j] vt; vt <- (vt - sum_{i<j} coef[i] V_i) / r
+// (j > 0); per-block partials of |w'|^2.
+__global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restrict__ V, int64_t ld, int j,
+                                                    const double* __restrict__ coef,
+                                                    double* __restrict__ nrm_part) {
+  __shared__ double cs[2 * 64 + 2];
   __shared__ double sh[4];
-  for (int i = threadIdx.x; i < k; i += BS) hs[i] = h[i];
+  for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cs[i] = coef[i];
   __syncthreads();
+  double* vt = V + int64_t(j) * ld;
+  double* w = V + int64_t(j + 1) * ld;
+  const double inv = cs[2 * j + 1], wt = cs[2 * j];
   double acc = 0.0;
   const int64_t stride = int64_t(gridDim.x) * BS;
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
-    double wr = w[r];
-    for (int i = 0; i < k; ++i) wr -= hs[i] * V[i * ldv + r];
-    w[r] = wr;
-    acc += wr * wr;
+    const double t = vt[r];
+    double wn = w[r] - wt * t, vn = t;
+    for (int i = 0; i < j; ++i) {
+      const double v = V[i * ld + r];
+      vn -= cs[i] * v;
+      wn -= cs[j + i] * v;
+    }
+    if (j > 0) vt[r] = vn * inv;
+    w[r] = wn;
+    acc += wn * wn;
   }
-  if (nrm_part) {
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) nrm_part[blockIdx.x] = s;
-  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) nrm_part[blockIdx.x] = s;
 }
 
 __device__ double sum_partials_wave(int nblk, const double* part) {
@@ -283,35 +354,7 @@ __device__ double sum_partials_wave(int nblk, const double* part) {
   return wave_sum(s);
 }
 
-__global__ void k_reorth_decide(int nblk, const double* __restrict__ nrm_part,
-                                const double* __restrict__ ww, int* __restrict__ flag,
-                                double* __restrict__ scal) {
-  const double w2 = sum_partials_wave(nblk, nrm_part);
-  if (threadIdx.x == 0) {
-    scal[3] = w2;
-    flag[0] = (w2 < 0.5 * ww[0]) ? 1 : 0;
-  }
-}
-
-// One wavefront.  H column-major with leading dimension m+1.
-__global__ void k_arnoldi_finish(int nblk, const double* __restrict__ nrm_part,
-                                 const int* __restrict__ flag, int j, int m,
-                                 double* __restrict__ H, double* __restrict__ cs,
-                                 double* __restrict__ sn, double* __restrict__ g,
-                                 double* __restrict__ scal) {
-  const bool second = (flag == nullptr) || (*flag != 0);
-  const double nrm = second ? sqrt(sum_partials_wave(nblk, nrm_part)) : sqrt(scal[3]);
-  if (threadIdx.x != 0) return;
-  const int ld = m + 1;
-  double* h = H + int64_t(j) * ld;
-  h[j + 1] = nrm;
-  for (int i = 0; i < j; ++i) {
-    const double a = h[i], b = h[i + 1];
-    h[i] = cs[i] * a + sn[i] * b;
-    h[i + 1] = -sn[i] * a + cs[i] * b;
-  }
-  const double a = h[j], b = h[j + 1];
-  double c, s;
+__device__ __forceinline__ void givens(double a, double b, double& c, double& s) {
   if (b == 0.0) {
     c = 1.0;
     s = 0.0;
@@ -324,13 +367,54 @@ __global__ void k_arnoldi_finish(int nblk, const double* __restrict__ nrm_part,
     c = 1.0 / sqrt(1.0 + t * t);
     s = t * c;
   }
-  cs[j] = c;
-  sn[j] = s;
-  h[j] = c * a + s * b;
-  h[j + 1] = 0.0;
-  g[j + 1] = -s * g[j];
-  g[j] = c * g[j];
-  scal[0] = fabs(g[j + 1]);
+}
+
+// End of step j: h_{j+1,j} = |w'| (provisional until the next step corrects
+// it); column j-1 is final now: rotate it into HR, fix rotation j-1 and the
+// right-hand side g.  Column j gets a provisional rotation: HR column j and gp
+// (g with the provisional rotation) serve the residual estimate and, if the
+// cycle ends here, the least-squares solve.  scal = (estimate, 1/|w'|, |w'|).
+__global__ void k_dcgs_finish(int nblk, const double* __restrict__ nrm_part, int j, int m,
+                              double* __restrict__ H, double* __restrict__ HR,
+                              double* __restrict__ cs, double* __restrict__ sn,
+                              double* __restrict__ g, double* __restrict__ gp,
+                              double* __restrict__ scal) {
+  const double nrm = sqrt(sum_partials_wave(nblk, nrm_part));
+  if (threadIdx.x != 0) return;
+  const int ld = m + 1;
+  H[int64_t(j) * ld + j + 1] = nrm;
+  auto rotate = [&](int col, int upto) {  // HR[col] = rotations 0..upto-1 applied to H[col]
+    const double* h = H + int64_t(col) * ld;
+    double* hr = HR + int64_t(col) * ld;
+    for (int i = 0; i <= col + 1; ++i) hr[i] = h[i];
+    for (int i = 0; i < upto; ++i) {
+      const double a = hr[i], b = hr[i + 1];
+      hr[i] = cs[i] * a + sn[i] * b;
+      hr[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+  };
+  if (j > 0) {
+    rotate(j - 1, j - 1);
+    double* hr = HR + int64_t(j - 1) * ld;
+    double c, s;
+    givens(hr[j - 1], hr[j], c, s);
+    cs[j - 1] = c;
+    sn[j - 1] = s;
+    hr[j - 1] = c * hr[j - 1] + s * hr[j];
+    hr[j] = 0.0;
+    g[j] = -s * g[j - 1];
+    g[j - 1] = c * g[j - 1];
+  }
+  rotate(j, j);
+  double* hr = HR + int64_t(j) * ld;
+  double c, s;
+  givens(hr[j], hr[j + 1], c, s);
+  hr[j] = c * hr[j] + s * hr[j + 1];
+  hr[j + 1] = 0.0;
+  for (int i = 0; i < j; ++i) gp[i] = g[i];
+  gp[j] = c * g[j];
+  gp[j + 1] = -s * g[j];
+  scal[0] = fabs(gp[j + 1]);
   scal[1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
   scal[2] = nrm;
 }
@@ -887,34 +971,29 @@ int reduce_blocks(int64_t n) {
   return int(b < 1 ? 1 : (b > MAXRED ? MAXRED : b));
 }
 
-void mdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                  const int* flag, hipStream_t s) {
+void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s) {
   const int nblk = reduce_blocks(n);
-  hipLaunchKernelGGL(k_mdot_partial, dim3(nblk, ceil_div(k, MD_G)), dim3(BS), 0, s, n, V, ldv, k,
-                     w, part, flag);
+  const int groups = j > 0 ? ceil_div(j, DG) : 1;
+  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblk, groups), dim3(BS), 0, s, n, V, ld, j, part);
 }
 
-void mdot_reduce(int nblk, int k, const double* part, double* h_tmp, double* h_col, int accumulate,
-                 const int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(k), dim3(BS), 0, s, nblk, k, part, h_tmp, h_col,
-                     accumulate, flag);
+void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_reduce, dim3(nslots), dim3(BS), 0, s, nblk, part, red);
 }
 
-void maxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
-           double* nrm_part, const int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_maxpy, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ldv, k, h, w, nrm_part,
-                     flag);
+void dcgs_coef(int j, int m, const double* red, double* H, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, m, red, H, coef);
 }
 
-void reorth_decide(int nblk, const double* nrm_part, const double* ww, int* flag, double* scal,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_reorth_decide, dim3(1), dim3(64), 0, s, nblk, nrm_part, ww, flag, scal);
+void dcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, double* nrm_part,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, coef, nrm_part);
 }
 
-void arnoldi_finish(int nblk, const double* nrm_part, const int* flag, int j, int m, double* H,
-                    double* cs, double* sn, double* g, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, s, nblk, nrm_part, flag, j, m, H, cs,
-                     sn, g, scal);
+void dcgs_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* HR, double* cs,
+                 double* sn, double* g, double* gp, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(64), 0, s, nblk, nrm_part, j, m, H, HR, cs, sn, g, gp,
+                     scal);
 }
 
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {

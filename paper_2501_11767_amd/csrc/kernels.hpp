@@ -66,24 +66,24 @@ void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipS
 // Krylov reductions (FP64).  Partial sums per workgroup go to `part`
 // (reduce_blocks(n) * cols doubles); reduce_* finish them deterministically.
 int reduce_blocks(int64_t n);
-// Kernels taking `flag` (may be null) return at once when *flag == 0.
-void mdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                  const int* flag, hipStream_t s);
-// h_col[i] (+)= sum of partials of vector i; also h_tmp[i] for the following maxpy.
-void mdot_reduce(int nblk, int k, const double* part, double* h_tmp, double* h_col, int accumulate,
-                 const int* flag, hipStream_t s);
-// w -= V h (k columns); with nrm_part != nullptr also partial sums of w^2.
-void maxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, double* w,
-           double* nrm_part, const int* flag, hipStream_t s);
-// Second Gram-Schmidt pass wanted?  flag = (||w'||^2 < ||w||^2 / 2) with
-// ||w'||^2 from nrm_part and ||w||^2 = *ww; scal[3] = ||w'||^2.
-void reorth_decide(int nblk, const double* nrm_part, const double* ww, int* flag, double* scal,
-                   hipStream_t s);
-// Norm of w (from nrm_part when *flag, else sqrt(scal[3])), Givens update of
-// Hessenberg column j, residual estimate, 1/h_{j+1,j}.  H is (m+1) x m
-// column-major with leading dim m+1.
-void arnoldi_finish(int nblk, const double* nrm_part, const int* flag, int j, int m, double* H,
-                    double* cs, double* sn, double* g, double* scal, hipStream_t s);
+// Delayed classical Gram-Schmidt with reorthogonalisation (DCGS2) at Arnoldi
+// step j, basis V (columns of length n, stride ld): V_j holds the vector used
+// for this step (orthogonalised once), V_{j+1} the new vector w = A z_j.
+// dots: partials of V_i . V_j, V_i . w (i < j), V_j . V_j, V_j . w, w . w
+// (2j + 3 slots of reduce_blocks(n) partials); slot_reduce sums them.
+void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s);
+void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s);
+// From the reduced dots: reorthogonalisation coefficients of V_j, correction of
+// Hessenberg column j-1, projection coefficients of w (raw H, ld m+1), into coef.
+void dcgs_coef(int j, int m, const double* red, double* H, double* coef, hipStream_t s);
+// Applies coef: V_j <- its reorthogonalised, normalised form (j > 0),
+// w <- w projected out of the final basis; partials of |w|^2.
+void dcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, double* nrm_part,
+                 hipStream_t s);
+// h_{j+1,j} = |w|; final Givens rotation of column j-1 into HR and g; a
+// provisional rotation of column j into HR and gp; scal = (|gp_{j+1}|, 1/|w|, |w|).
+void dcgs_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* HR, double* cs,
+                 double* sn, double* g, double* gp, double* scal, hipStream_t s);
 // Least squares back-substitution for k columns: y = R^{-1} g.
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // x += Z y (k columns).
