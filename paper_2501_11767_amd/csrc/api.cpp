@@ -67,6 +67,7 @@ int upload_sell(chns_ctx* c, const Sell& S, DSell& d) {
   d.nslices = S.nslices;
   d.width = S.width_max;
   d.uniform = S.uniform ? 1 : 0;
+  d.side = S.side;
   int *sp, *sw, *col, *perm;
   TRY(upload(c, &sp, S.slice_ptr));
   TRY(upload(c, &sw, S.slice_w));
@@ -812,8 +813,8 @@ int build(chns_ctx* c) {
     L.N = L.n * L.n;
     Elements E = make_elements(L.n);
     L.csr = pattern_from_elements(L.N, L.N, E.ne, E.v.data(), 3, E.v.data(), 3);
-    L.sell = make_sell(L.csr, 64, 1);
-    if (!L.sell.uniform || L.sell.width_max != 7)
+    L.sell = make_sell_p1(L.csr, L.n);
+    if (!L.sell.uniform || L.sell.width_max != 7 || L.sell.side != L.n)
       return fail(c, CHNS_EINVAL, "P1 pattern is not the uniform 7-point stencil");
     TRY(upload_sell(c, L.sell, L.d));
     TRY(upload(c, &L.diag, L.sell.diag));

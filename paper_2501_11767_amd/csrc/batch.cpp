@@ -174,7 +174,7 @@ SizeTables* tables_for(chns_batch* b, int n) {
   for (int nl : sz) {
     Elements E = make_elements(nl);
     T->csr.push_back(pattern_from_elements(nl * nl, nl * nl, E.ne, E.v.data(), 3, E.v.data(), 3));
-    T->sell.push_back(make_sell(T->csr.back(), 64, 1));
+    T->sell.push_back(make_sell_p1(T->csr.back(), nl));
     if (nl == n) T->el = std::move(E);
   }
   for (size_t l = 0; l + 1 < sz.size(); ++l) {

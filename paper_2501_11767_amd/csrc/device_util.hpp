@@ -44,6 +44,33 @@ __device__ __forceinline__ double w_p2p1(int k, int a) {
   return ((k - 3) == a) ? (1.0 / 15.0) : (2.0 / 15.0);
 }
 
+// Columns of P1 row `row` of the periodic side x side mesh, in the neighbour
+// order of the P1 storage: self, (-1,-1), (0,-1), (-1,0), (1,0), (0,1), (1,1).
+__device__ __forceinline__ void p1_cols(int row, int side, int* c) {
+  const int j = row / side, i = row - j * side;
+  const int im = (i == 0) ? side - 1 : i - 1, ip = (i == side - 1) ? 0 : i + 1;
+  const int jm = (j == 0) ? side - 1 : j - 1, jp = (j == side - 1) ? 0 : j + 1;
+  const int rj = side * j, rm = side * jm, rp = side * jp;
+  c[0] = row;
+  c[1] = im + rm;
+  c[2] = i + rm;
+  c[3] = im + rj;
+  c[4] = ip + rj;
+  c[5] = i + rp;
+  c[6] = ip + rp;
+}
+
+// Columns of a uniform width-7 row: computed when side > 0, else loaded.
+__device__ __forceinline__ void row_cols7(int row, int side, const int* __restrict__ col, size_t base,
+                                          int* c) {
+  if (side > 0) {
+    p1_cols(row, side, c);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) c[k] = col[base + k * 64];
+  }
+}
+
 struct ElemGeo {
   double area;
   double gx[3], gy[3];

@@ -71,6 +71,50 @@ Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, c
   return A;
 }
 
+Sell make_sell_p1(const Csr& A, int n) {
+  Sell S;
+  const int N = n * n;
+  S.nrows = N;
+  S.ncols = N;
+  S.C = 64;
+  S.sigma = 1;
+  S.side = n;
+  S.nslices = (N + 63) / 64;
+  S.width_max = 7;
+  S.uniform = true;
+  S.perm.assign(size_t(S.nslices) * 64, -1);
+  for (int r = 0; r < N; ++r) S.perm[r] = r;
+  S.slice_ptr.resize(S.nslices + 1);
+  for (int s = 0; s <= S.nslices; ++s) S.slice_ptr[s] = s * 448;
+  S.slice_w.assign(S.nslices, 7);
+  S.col.assign(size_t(S.nslices) * 448, 0);
+  S.csr2sell.assign(A.nnz(), -1);
+  S.diag.assign(N, -1);
+  for (int r = 0; r < S.nslices * 64; ++r) {
+    const int rr = r < N ? r : 0;  // padding lanes of a partial slice: valid column, value 0
+    const int i = rr % n, j = rr / n;
+    for (int k = 0; k < 7; ++k) {
+      const int ci = (i + P1_DI[k] + n) % n, cj = (j + P1_DJ[k] + n) % n;
+      S.col[size_t(r >> 6) * 448 + k * 64 + (r & 63)] = ci + n * cj;
+    }
+  }
+  for (int r = 0; r < N; ++r) {
+    const int i = r % n, j = r / n;
+    for (int q = A.rowptr[r]; q < A.rowptr[r + 1]; ++q) {
+      const int c = A.col[q], ci = c % n, cj = c / n;
+      const int di = (ci - i + n + 1) % n - 1, dj = (cj - j + n + 1) % n - 1;
+      int k = -1;
+      for (int t = 0; t < 7; ++t)
+        if (P1_DI[t] == di && P1_DJ[t] == dj) k = t;
+      if (k < 0) return Sell{};  // not the periodic 7-point pattern
+      const int slot = (r >> 6) * 448 + k * 64 + (r & 63);
+      S.csr2sell[q] = slot;
+      if (c == r) S.diag[r] = slot;
+    }
+  }
+  return S;
+}
+
 Sell make_sell(const Csr& A, int C, int sigma) {
   Sell S;
   S.nrows = A.nrows;

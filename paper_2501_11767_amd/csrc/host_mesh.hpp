@@ -39,6 +39,8 @@ struct Sell {
   std::vector<int> perm;         // nslices*C: row stored at that lane position (-1 = none)
   std::vector<int> csr2sell;     // CSR entry -> SELL slot
   std::vector<int> diag;         // per row: SELL slot of the diagonal entry (-1 if absent)
+  int side = 0;                  // > 0: P1 pattern of the periodic side x side mesh stored in
+                                 // the fixed neighbour order of p1_offset (columns computable)
   int64_t slots() const { return slice_ptr.empty() ? 0 : slice_ptr.back(); }
 };
 
@@ -58,6 +60,17 @@ Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, c
                           int nc);
 
 Sell make_sell(const Csr& A, int C, int sigma);
+
+// Neighbour offsets (di, dj) of a P1 row of the periodic right-diagonal mesh,
+// in the storage order of make_sell_p1: self, (-1,-1), (0,-1), (-1,0), (1,0),
+// (0,1), (1,1).
+constexpr int P1_DI[7] = {0, -1, 0, -1, 1, 0, 1};
+constexpr int P1_DJ[7] = {0, -1, -1, 0, 0, 1, 1};
+
+// SELL-C-64 of the P1 pattern of the periodic n x n mesh (vertex i + n j) with
+// entry k of every row at neighbour offset k (no padding, identity
+// permutation), so a kernel can compute the columns from the row index.
+Sell make_sell_p1(const Csr& A, int n);
 
 // Nested P1 prolongation from size n/2 to n (values: 1 or 1/2).
 void p1_prolongation(int nf, Csr& P, std::vector<double>& val);

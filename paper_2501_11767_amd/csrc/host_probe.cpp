@@ -30,7 +30,7 @@ __attribute__((visibility("default"))) int chns_probe_p1(int n, int32_t* rowptr,
                                                          int32_t* diag, int32_t* flags) {
   Elements E = make_elements(n);
   Csr A = pattern_from_elements(n * n, n * n, E.ne, E.v.data(), 3, E.v.data(), 3);
-  Sell S = make_sell(A, 64, 1);
+  Sell S = make_sell_p1(A, n);
   copy_out(A.rowptr, rowptr);
   copy_out(A.col, col);
   copy_out(S.col, sell_col);
@@ -62,7 +62,7 @@ __attribute__((visibility("default"))) int chns_probe_galerkin(int nf, const dou
   Elements Ef = make_elements(nf), Ec = make_elements(nf / 2);
   Csr Af = pattern_from_elements(nf * nf, nf * nf, Ef.ne, Ef.v.data(), 3, Ef.v.data(), 3);
   Csr Ac = pattern_from_elements(nf * nf / 4, nf * nf / 4, Ec.ne, Ec.v.data(), 3, Ec.v.data(), 3);
-  Sell Sf = make_sell(Af, 64, 1), Sc = make_sell(Ac, 64, 1);
+  Sell Sf = make_sell_p1(Af, nf), Sc = make_sell_p1(Ac, nf / 2);
   Csr P;
   std::vector<double> Pv;
   p1_prolongation(nf, P, Pv);

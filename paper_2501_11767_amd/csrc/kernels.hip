@@ -52,7 +52,7 @@ __global__ __launch_bounds__(BS) void k_spmv_sell(int nslices, int nrows, const 
 
 // Uniform width-7 patterns (P1): identity permutation, slice s = rows 64s..64s+63.
 template <typename T, typename TV, int MODE>
-__global__ __launch_bounds__(BS) void k_stencil7(int nrows, const int* __restrict__ col,
+__global__ __launch_bounds__(BS) void k_stencil7(int nrows, int side, const int* __restrict__ col,
                                                  const TV* __restrict__ val,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ b,
@@ -65,8 +65,7 @@ __global__ __launch_bounds__(BS) void k_stencil7(int nrows, const int* __restric
   const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
   int c[W7];
   TV v[W7];
-#pragma unroll
-  for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+  row_cols7(row, side, col, base, c);
 #pragma unroll
   for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
   T sum = T(0);
@@ -99,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_cheb0(int n, const T* __restrict__ dinv,
 // Chebyshev steps from x = 0 on a level of at most 1024 rows: one workgroup,
 // one row per thread, the row kept in registers, x in LDS.
 template <typename T, typename TV>
-__global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, const int* __restrict__ col,
+__global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const int* __restrict__ col,
                                                       const TV* __restrict__ val,
                                                       const T* __restrict__ dinv,
                                                       const T* __restrict__ b, ChebCoef<T> cc,
@@ -113,11 +112,9 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, const int* __re
   T di = T(0), br = T(0), dd = T(0);
   if (r < nrows) {
     const size_t base = size_t(r >> 6) * (64 * W7) + (r & 63);
+    row_cols7(r, side, col, base, c);
 #pragma unroll
-    for (int k = 0; k < W7; ++k) {
-      c[k] = col[base + k * 64];
-      v[k] = val[base + k * 64];
-    }
+    for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
     di = dinv[r];
     br = b[r];
     dd = cc.c2[0] * (di * br);
@@ -141,7 +138,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, const int* __re
 }
 
 template <typename T, typename TV, bool L_IS_M>
-__global__ __launch_bounds__(BS) void k_ch_block(int n, const int* __restrict__ col,
+__global__ __launch_bounds__(BS) void k_ch_block(int n, int side, const int* __restrict__ col,
                                                  const TV* __restrict__ Lv,
                                                  const TV* __restrict__ Kv,
                                                  const TV* __restrict__ Mv, T c12, T c22,
@@ -155,8 +152,7 @@ __global__ __launch_bounds__(BS) void k_ch_block(int n, const int* __restrict__ 
   const T* x2 = x + n;
   int c[W7];
   TV kv[W7], mv[W7], lv[W7];
-#pragma unroll
-  for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+  row_cols7(row, side, col, base, c);
 #pragma unroll
   for (int k = 0; k < W7; ++k) {
     kv[k] = Kv[base + k * 64];
@@ -583,7 +579,7 @@ __device__ __forceinline__ void binary_terms(double phi, const double* Phi, int 
   fv = 6.0 * P * (1.0 - P) * (fgas - fliq);
 }
 
-__global__ __launch_bounds__(BS) void k_rhs_binary(int n, const int* __restrict__ col,
+__global__ __launch_bounds__(BS) void k_rhs_binary(int n, int side, const int* __restrict__ col,
                                                    const double* __restrict__ Mv,
                                                    const double* __restrict__ phi,
                                                    const double* __restrict__ Phi, double c_mu,
@@ -594,9 +590,11 @@ __global__ __launch_bounds__(BS) void k_rhs_binary(int n, const int* __restrict_
   if (row >= n) return;
   const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
   double s_phi = 0.0, s_fp = 0.0, s_Phi = 0.0, s_fv = 0.0;
+  int cc[W7];
+  row_cols7(row, side, col, base, cc);
 #pragma unroll
   for (int k = 0; k < W7; ++k) {
-    const int j = col[base + k * 64];
+    const int j = cc[k];
     const double m = Mv[base + k * 64];
     const double ph = phi[j];
     double fp, fv;
@@ -821,7 +819,7 @@ __global__ __launch_bounds__(BS) void k_form_ns(int64_t n, const int8_t* __restr
   out[i] = v;
 }
 
-__global__ __launch_bounds__(BS) void k_rhs_ternary(int n, const int* __restrict__ col,
+__global__ __launch_bounds__(BS) void k_rhs_ternary(int n, int side, const int* __restrict__ col,
                                                     const double* __restrict__ Mv,
                                                     const double* __restrict__ php,
                                                     const double* __restrict__ phn,
@@ -835,9 +833,11 @@ __global__ __launch_bounds__(BS) void k_rhs_ternary(int n, const int* __restrict
   if (row >= n) return;
   const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
   double s_p = 0, s_n = 0, s_dp = 0, s_dn = 0, s_P = 0, s_fv = 0;
+  int cc[W7];
+  row_cols7(row, side, col, base, cc);
 #pragma unroll
   for (int k = 0; k < W7; ++k) {
-    const int j = col[base + k * 64];
+    const int j = cc[k];
     const double m = Mv[base + k * 64];
     const double a = php[j], b = phn[j], P = Phi[j];
     double dp, dn, fv, fs;
@@ -906,7 +906,7 @@ template <typename T, typename TV>
 void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s) {
   if (A.uniform && A.width == W7) {
     hipLaunchKernelGGL((k_stencil7<T, TV, ST_SPMV>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
-                       A.nrows, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       A.nrows, A.side, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
                        alpha, beta, y);
   } else {
     const int npos = A.nslices * 64;
@@ -921,10 +921,10 @@ void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, co
              T c1, T c2, T* y, hipStream_t s) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (mode == ST_RESID)
-    hipLaunchKernelGGL((k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.col, val, x, b,
+    hipLaunchKernelGGL((k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b,
                        dinv, d, c1, c2, y);
   else
-    hipLaunchKernelGGL((k_stencil7<T, TV, ST_CHEB>), g, blk, 0, s, A.nrows, A.col, val, x, b,
+    hipLaunchKernelGGL((k_stencil7<T, TV, ST_CHEB>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b,
                        dinv, d, c1, c2, y);
 }
 
@@ -936,7 +936,7 @@ void cheb0(int n, const T* dinv, const T* b, T c2, T* d, T* x, hipStream_t s) {
 template <typename T, typename TV>
 void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const ChebCoef<T>& cc,
                  T* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_cheb<T, TV>), dim3(1), dim3(1024), 0, s, A.nrows, A.col, val, dinv,
+  hipLaunchKernelGGL((k_coarse_cheb<T, TV>), dim3(1), dim3(1024), 0, s, A.nrows, A.side, A.col, val, dinv,
                      b, cc, x);
 }
 
@@ -945,10 +945,10 @@ void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c2
               T alpha, T beta, T* y, hipStream_t s) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (L == M)
-    hipLaunchKernelGGL((k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.col, L, K, M, c12, c22,
+    hipLaunchKernelGGL((k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
                        x, alpha, beta, y);
   else
-    hipLaunchKernelGGL((k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.col, L, K, M, c12, c22,
+    hipLaunchKernelGGL((k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
                        x, alpha, beta, y);
 }
 
@@ -1040,7 +1040,7 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
 
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,
                 double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col, Mv,
+  hipLaunchKernelGGL(k_rhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col, Mv,
                      phi, Phi, c_mu, c_ac, rhs_ch, rhs_ac);
 }
 
@@ -1102,7 +1102,7 @@ void form_ns(int64_t nslots, const int8_t* kind, const int* src, double cm, cons
 void rhs_ternary(const DSell& A, const double* Mv, const double* php, const double* phn,
                  const double* Phi, double c_mu, double c_ac, double* rhs_p, double* rhs_n,
                  double* rhs_ac, double* fs, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_ternary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col, Mv,
+  hipLaunchKernelGGL(k_rhs_ternary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col, Mv,
                      php, phn, Phi, c_mu, c_ac, rhs_p, rhs_n, rhs_ac, fs);
 }
 

@@ -15,6 +15,7 @@ struct DSell {
   const int* slice_w = nullptr;
   const int* col = nullptr;
   const int* perm = nullptr;              // lane position -> row (-1 padding)
+  int side = 0;  // > 0: periodic side x side P1 pattern in neighbour order (columns computed)
 };
 
 // Operator modes of the fused stencil kernel (uniform width-7 P1 patterns).

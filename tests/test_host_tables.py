@@ -65,12 +65,27 @@ def test_p1_pattern_bit_exact_and_sell_layout(probe, n):
     assert np.array_equal(rp, ref.indptr) and np.array_equal(col, ref.indices)
     assert flags[0] == 1 and flags[1] == 7
     N = n * n
+    # entry k of every row sits at neighbour offset k (self, (-1,-1), (0,-1),
+    # (-1,0), (1,0), (0,1), (1,1)) of the periodic mesh, vertex i + n j
+    di = [0, -1, 0, -1, 1, 0, 1]
+    dj = [0, -1, -1, 0, 0, 1, 1]
     rows = np.repeat(np.arange(N), 7)
-    k = np.tile(np.arange(7), N)
+    ri, rj = rows % n, rows // n
+    ci, cj = col % n, col // n
+    oi = (ci - ri + n + 1) % n - 1
+    oj = (cj - rj + n + 1) % n - 1
+    table = {(a, b): t for t, (a, b) in enumerate(zip(di, dj))}
+    k = np.array([table[(a, b)] for a, b in zip(oi, oj)])
     slot = (rows >> 6) * 448 + (rows & 63) + 64 * k
     assert np.array_equal(c2s, slot)
     assert np.array_equal(scol[slot], col)
     assert np.array_equal(scol[diag], np.arange(N))
+    # the stored columns follow the closed form the stencil kernels compute
+    r = np.arange(N)
+    i, j = r % n, r // n
+    for t in range(7):
+        expect = (i + di[t]) % n + n * ((j + dj[t]) % n)
+        assert np.array_equal(scol[(r >> 6) * 448 + (r & 63) + 64 * t], expect), t
 
 
 @pytest.mark.parametrize("n", [8, 16])
