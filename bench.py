@@ -28,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of a kernel from rocprofv3 counter runs of this
+# benchmark (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
+# copy of known size); filled in from profiles/ once measured for the kernel
+# as it stands, None otherwise.
+TRAFFIC = {}
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 
 
@@ -41,7 +46,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="one 512 MiB device copy (counter calibration in profiled runs)")
     ap.add_argument("--dry-steps", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -87,35 +93,38 @@ def dof_iters(infos, N):
     return di, ms
 
 
-def kernel_roofline(ctx, chns, N, reps):
-    """Average duration of single kernels, timed with events on the stream
-    the library launches on (torch's current stream)."""
-    import torch
+def kernel_ledger(ctx, chns, fin, fout, k, opts):
+    """Per kernel class: the same k timed steps again with the library's
+    ledger on, which brackets every launch of the class with HIP events on
+    the stream it runs on (the library launches on torch's current stream)
+    and records its algorithmic bytes.  Returns {class name: figures}."""
     out = {}
-    g = torch.Generator(device="cuda").manual_seed(0)
-    x = torch.rand(2 * N, dtype=torch.float64, device="cuda", generator=g)
-    y = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
-    x32, y32 = x[:N].float().contiguous(), torch.zeros(N, dtype=torch.float32, device="cuda")
-    cases = {
-        # name: (callable, algorithmic bytes per launch)
-        "ch_block_f64": (lambda: ctx.spmv(chns.OP_CH, x, y), N * (7 * 4 + 2 * 7 * 8 + 16 + 16)),
-        "spmv7_f64": (lambda: ctx.spmv(chns.OP_X, x[:N], y[:N]), N * (7 * 12 + 8 + 8)),
-        "spmv7_f32": (lambda: ctx.spmv(chns.OP_X, x32, y32, precision=chns.MIXED), N * (7 * 8 + 4 + 4)),
-    }
-    for name, (fn, nbytes) in cases.items():
-        for _ in range(3):
-            fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / reps
-        gbs = nbytes / (us * 1e-6) / 1e9
-        out[name] = dict(us=us, bytes=nbytes, gbs=gbs, frac=gbs / HBM_PEAK_GBS)
+    for kid in (chns.KERNEL_CHEB32, chns.KERNEL_CH_BLOCK, chns.KERNEL_DCGS_DOTS,
+                chns.KERNEL_DCGS_UPDATE):
+        ctx.ledger_start(kid)
+        run_steps(ctx, chns, fin, fout, k, opts)
+        launches, nbytes, ms = ctx.ledger_read()
+        ctx.ledger_start(-1)
+        if launches == 0:
+            continue
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[chns.KERNEL_NAMES[kid]] = dict(
+            launches=launches, ms_total=ms, ms_per_step=ms / k, us_per_launch=ms * 1e3 / launches,
+            bytes_per_launch=nbytes / launches, gbs=gbs, frac=gbs / HBM_PEAK_GBS)
     return out
+
+
+def copy_probe(mib=512):
+    """One plain streaming kernel of known traffic (b = -a over 512 MiB FP32,
+    one dispatch of torch's elementwise negation), for scaling the HBM
+    counters of a profiled run (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    import torch
+    a = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    return dict(kernel="neg (elementwise)", bytes_read=a.numel() * 4, bytes_written=b.numel() * 4)
 
 
 def cpu_baseline(cfg, n, tau, budget_s=20.0):
@@ -464,8 +473,10 @@ def main():
             ch_iters=[i[0]["iters"] for i in infos], ac_iters=[i[1]["iters"] for i in infos],
             converged=all(i[0]["converged"] and i[1]["converged"] for i in infos),
             rel_res_ch=max(i[0]["res_true"] / i[0]["bnorm"] for i in infos))
-    log("kernels: event-timed single launches")
-    kern = kernel_roofline(ctx, chns, N, args.kernel_reps)
+    log("kernels: ledger passes over the timed steps (mixed)")
+    kern = kernel_ledger(ctx, chns, f_in, f_out, args.steps,
+                         chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=args.restart))
+    probe = copy_probe() if args.copy_probe else None
 
     sweep, sweep_fields = [], {}
     if not args.no_sweep:
@@ -503,7 +514,7 @@ def main():
             with threadpool_limits(1):
                 adj["cpu_reference"] = cpu_adjoint_reference(chns)
 
-    dom = "ch_block_f64"
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
     kd = kern[dom]
     line = {
         "metric": METRIC,
@@ -523,12 +534,14 @@ def main():
                                f"rtol 1e-8, V(2,2) block preconditioner",
                    "n": n, "tau": args.tau, "restart": args.restart},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kd["frac"], "traffic": None,
-                     "bytes_per_launch": kd["bytes"], "us_per_launch": kd["us"]},
+                     "unit": "GB/s", "frac": kd["frac"], "traffic": TRAFFIC.get(dom),
+                     "bytes_per_launch": kd["bytes_per_launch"], "us_per_launch": kd["us_per_launch"],
+                     "launches": kd["launches"]},
         "cpu_baseline": cpu,
         "mixed": res.get("mixed"),
         "fp64": res.get("fp64"),
         "kernels": kern,
+        "copy_probe": probe,
         "sweep": sweep,
         "dry256": dry,
         "batch64": bat,

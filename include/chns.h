@@ -267,6 +267,26 @@ CHNS_API int chns_timestep_adjoint(chns_ctx* ctx, const chns_fields* in, const c
                                    double* h_dtheta, const chns_solve_opts* opts,
                                    chns_solve_info* h_info, void* stream);
 
+/* Kernel classes of the measurement ledger. */
+enum {
+  CHNS_KERNEL_CHEB32 = 0,      /* FP32 Chebyshev sweep of the P1 stencil kernel (every level) */
+  CHNS_KERNEL_CHEB64 = 1,      /* FP64 Chebyshev sweep of the P1 stencil kernel */
+  CHNS_KERNEL_CH_BLOCK = 2,    /* FP64 CH block operator inside FGMRES */
+  CHNS_KERNEL_DCGS_DOTS = 3,   /* Gram-Schmidt dot pass */
+  CHNS_KERNEL_DCGS_UPDATE = 4  /* Gram-Schmidt update pass */
+};
+
+/* Measurement ledger.  chns_ledger_start(kernel) clears the ledger and from
+ * then on brackets every launch of that kernel class on this context by a
+ * pair of HIP events recorded on the stream it is launched on, recording the
+ * launch's algorithmic bytes (what the method must move: matrix values,
+ * vectors read once, vectors written; computed indices excluded); -1 stops.
+ * chns_ledger_read returns the launches, summed bytes and summed event time
+ * in ms since the start (synchronising).  The events add a few microseconds
+ * of host work per bracketed launch. */
+CHNS_API int chns_ledger_start(chns_ctx* ctx, int32_t kernel);
+CHNS_API int chns_ledger_read(chns_ctx* ctx, int64_t* launches, double* bytes, double* ms);
+
 /* Message of the last error on this context (never NULL). */
 CHNS_API const char* chns_last_error(const chns_ctx* ctx);
 

@@ -17,6 +17,14 @@ OK, WNOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, 
 MODEL_CH, MODEL_CH_AC, MODEL_TERNARY = 0, 1, 2
 BLOCK_CH, BLOCK_AC, BLOCK_NS = 0, 1, 2
 OP_M, OP_K, OP_C, OP_CH, OP_AC, OP_X, OP_L, OP_NS, OP_VX, OP_AP = range(10)
+KERNEL_CHEB32, KERNEL_CHEB64, KERNEL_CH_BLOCK, KERNEL_DCGS_DOTS, KERNEL_DCGS_UPDATE = range(5)
+KERNEL_NAMES = {
+    KERNEL_CHEB32: "k_stencil7<float, float, 2>",
+    KERNEL_CHEB64: "k_stencil7<double, double, 2>",
+    KERNEL_CH_BLOCK: "k_ch_block<double, double, true>",
+    KERNEL_DCGS_DOTS: "k_dcgs_dots",
+    KERNEL_DCGS_UPDATE: "k_dcgs_update",
+}
 F64, MIXED = 0, 1
 MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}
 
@@ -24,7 +32,7 @@ EXPORTS = [
     "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble",
     "chns_matrix_shape", "chns_get_matrix", "chns_spmv", "chns_precond_apply",
     "chns_krylov_solve", "chns_step_rhs", "chns_timestep", "chns_last_error",
-    "chns_assemble_transposed", "chns_timestep_adjoint",
+    "chns_assemble_transposed", "chns_timestep_adjoint", "chns_ledger_start", "chns_ledger_read",
     "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
     "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_last_error",
 ]
@@ -95,6 +103,8 @@ def lib():
     L.chns_assemble_transposed.argtypes = [vp, vp, vp, vp]
     L.chns_timestep_adjoint.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(Fields), ct.POINTER(Fields),
                                         ct.POINTER(Fields), vp, ct.POINTER(SolveOpts), vp, vp]
+    L.chns_ledger_start.argtypes = [vp, i32]
+    L.chns_ledger_read.argtypes = [vp, vp, vp, vp]
     L.chns_last_error.argtypes = [vp]
     L.chns_last_error.restype = ct.c_char_p
     L.chns_batch_create.argtypes = [i32, vp, vp, ct.POINTER(vp)]
@@ -240,6 +250,16 @@ class Context:
     def step_rhs(self, fin: Fields, rhs_ch, rhs_ac=None, rhs_ns=None):
         self._check(self.L.chns_step_rhs(self.h, ct.byref(fin), _ptr(rhs_ch), _ptr(rhs_ac),
                                          _ptr(rhs_ns), _stream()))
+
+    def ledger_start(self, kernel):
+        """Time every launch of kernel class `kernel` (KERNEL_*) from now on; -1 stops."""
+        self._check(self.L.chns_ledger_start(self.h, int(kernel)))
+
+    def ledger_read(self):
+        """(launches, algorithmic bytes, event ms) since ledger_start."""
+        n, b, ms = ct.c_int64(), ct.c_double(), ct.c_double()
+        self._check(self.L.chns_ledger_read(self.h, ct.byref(n), ct.byref(b), ct.byref(ms)))
+        return n.value, b.value, ms.value
 
     def timestep_adjoint(self, fin: Fields, fout: Fields, lam_out: Fields, lam_in: Fields, opts=None):
         """lambda^k from lambda^{k+1} (ternary step); returns (rc, dtheta, infos)

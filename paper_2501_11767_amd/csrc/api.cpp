@@ -40,6 +40,40 @@ int fail(chns_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+// Fold the completed ledger slots into the running sums (synchronising).
+int ledger_fold(chns_ctx* c) {
+  Ledger& G = c->ledger;
+  if (G.used == 0) return CHNS_OK;
+  HIPCHK(c, hipEventSynchronize(G.ev[2 * (G.used - 1) + 1]));
+  for (int i = 0; i < G.used; ++i) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, G.ev[2 * i], G.ev[2 * i + 1]));
+    G.sum_ms += ms;
+    G.sum_bytes += G.bytes[i];
+  }
+  G.used = 0;
+  return CHNS_OK;
+}
+
+// Launch through the ledger: when class `kid` is being timed, the launch takes
+// an event pair that the dispatch itself timestamps (kernel start and end).
+template <typename F>
+void timed(chns_ctx* c, int kid, double bytes, hipStream_t s, F&& launch) {
+  Ledger& G = c->ledger;
+  if (G.kernel != kid) {
+    launch(LaunchEv{});
+    return;
+  }
+  if (G.used == G.cap) (void)ledger_fold(c);
+  LaunchEv ev;
+  ev.start = G.ev[2 * G.used];
+  ev.stop = G.ev[2 * G.used + 1];
+  launch(ev);
+  G.bytes[G.used] = bytes;
+  ++G.used;
+  ++G.launches;
+}
+
 template <typename T>
 int dalloc(chns_ctx* c, T** p, size_t n) {
   *p = nullptr;
@@ -342,20 +376,43 @@ const double* coef_of(chns_ctx* c, OpVals Level::*op) {
 
 bool singular_of(OpVals Level::*op) { return op == &Level::Kp; }
 
+// One Chebyshev sweep of the P1 stencil kernel, through the ledger.
+// Algorithmic bytes per row: the 7 values, x (own entry), b, 1/diag, d (read
+// when c1 != 0), d and y written; columns are computed, not read.
+template <typename T>
+void cheb_sweep(chns_ctx* c, Level& L, const OpVals& A, const T* x, const T* b, T* d, T c1, T c2,
+                T* y, hipStream_t s) {
+  const bool f32 = std::is_same<T, float>::value;
+  const double bytes = double(L.N) * sizeof(T) * (7 + 5 + (c1 != T(0) ? 1 : 0));
+  timed(c, f32 ? CHNS_KERNEL_CHEB32 : CHNS_KERNEL_CHEB64, bytes, s, [&](LaunchEv ev) {
+    stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, x, b, Sel<T>::d(A), d, c1, c2, y, s, ev);
+  });
+}
+
 // Chebyshev steps from x = 0 (cur/oth ping-pong so that the result lands in x).
 template <typename T>
-void cheb_from_zero(Level& L, const OpVals& A, const T* b, T* x, const ChebCoef<T>& cc,
+void cheb_from_zero(chns_ctx* c, Level& L, const OpVals& A, const T* b, T* x, const ChebCoef<T>& cc,
                     hipStream_t s) {
   if (L.N <= 1024) {
     coarse_cheb<T, T>(L.d, Sel<T>::v(A), Sel<T>::d(A), b, cc, x, s);
     return;
   }
+  T* d = Sel<T>::dd(L);
+  if (cc.steps >= 2 && L.d.side > 0) {  // steps 0 and 1 fused
+    T* cur = ((cc.steps - 2) % 2 == 0) ? x : Sel<T>::t(L);
+    T* oth = (cur == x) ? Sel<T>::t(L) : x;
+    cheb01<T, T>(L.d, Sel<T>::v(A), b, Sel<T>::d(A), cc.c2[0], cc.c1[1], cc.c2[1], d, cur, s);
+    for (int k = 2; k < cc.steps; ++k) {
+      cheb_sweep<T>(c, L, A, cur, b, d, cc.c1[k], cc.c2[k], oth, s);
+      std::swap(cur, oth);
+    }
+    return;
+  }
   T* cur = ((cc.steps - 1) % 2 == 0) ? x : Sel<T>::t(L);
   T* oth = (cur == x) ? Sel<T>::t(L) : x;
-  T* d = Sel<T>::dd(L);
   cheb0<T>(L.N, Sel<T>::d(A), b, cc.c2[0], d, cur, s);
   for (int k = 1; k < cc.steps; ++k) {
-    stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, cur, b, Sel<T>::d(A), d, cc.c1[k], cc.c2[k], oth, s);
+    cheb_sweep<T>(c, L, A, cur, b, d, cc.c1[k], cc.c2[k], oth, s);
     std::swap(cur, oth);
   }
 }
@@ -379,10 +436,38 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
       lo = 0.45 / (1.0 + 8.0 * cf[1] * nl * nl / cf[0]);
     }
     const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
-    cheb_from_zero<T>(L, A, b, x, cheb_coef<T>(lo, lmax, std::min(steps, MAXCHEB)), s);
+    cheb_from_zero<T>(c, L, A, b, x, cheb_coef<T>(lo, lmax, std::min(steps, MAXCHEB)), s);
     return;
   }
   const ChebCoef<T> pre = cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre);
+  if (L.d.side > 0 && o.mg_pre >= 2 && o.mg_post >= 1) {
+    // fused: the first two pre-smoothing steps, and the coarse correction
+    // with the first post-smoothing step; the result lands in x after
+    // pre + post - 2 swaps
+    const ChebCoef<T> post = cheb_coef<T>(lmax / 4.0, lmax, o.mg_post);
+    T* cur = ((o.mg_pre - 2 + o.mg_post) % 2 == 0) ? x : Sel<T>::t(L);
+    T* oth = (cur == x) ? Sel<T>::t(L) : x;
+    T* d = Sel<T>::dd(L);
+    const T* v = Sel<T>::v(A);
+    const T* di = Sel<T>::d(A);
+    cheb01<T, T>(L.d, v, b, di, pre.c2[0], pre.c1[1], pre.c2[1], d, cur, s);
+    for (int k = 2; k < o.mg_pre; ++k) {
+      cheb_sweep<T>(c, L, A, cur, b, d, pre.c1[k], pre.c2[k], oth, s);
+      std::swap(cur, oth);
+    }
+    Level& G = c->lv[l + 1];
+    T* r = Sel<T>::r(L);
+    stencil<T, T>(L.d, v, ST_RESID, cur, b, nullptr, nullptr, T(0), T(0), r, s);
+    spmv<T, T>(L.dR, Sel<T>::R(L), r, Sel<T>::b(G), T(1), T(0), s);
+    vcycle<T>(c, op, l + 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
+    pcheb<T, T>(L.d, v, cur, Sel<T>::x(G), b, di, post.c2[0], d, oth, s);
+    std::swap(cur, oth);
+    for (int k = 1; k < o.mg_post; ++k) {
+      cheb_sweep<T>(c, L, A, cur, b, d, post.c1[k], post.c2[k], oth, s);
+      std::swap(cur, oth);
+    }
+    return;
+  }
   const int swaps_post = o.mg_post;
   // pre-smoothing from zero: result must end in `cur`, then the post steps
   // alternate; choose the start buffer so that the final iterate is `x`.
@@ -391,7 +476,7 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
   T* d = Sel<T>::dd(L);
   cheb0<T>(L.N, Sel<T>::d(A), b, pre.c2[0], d, cur, s);
   for (int k = 1; k < o.mg_pre; ++k) {
-    stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, cur, b, Sel<T>::d(A), d, pre.c1[k], pre.c2[k], oth, s);
+    cheb_sweep<T>(c, L, A, cur, b, d, pre.c1[k], pre.c2[k], oth, s);
     std::swap(cur, oth);
   }
   T* r = Sel<T>::r(L);
@@ -403,8 +488,7 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
   if (o.mg_post > 0) {
     const ChebCoef<T> post = cheb_coef<T>(lmax / 4.0, lmax, o.mg_post);
     for (int k = 0; k < o.mg_post; ++k) {
-      stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, cur, b, Sel<T>::d(A), d, post.c1[k], post.c2[k],
-                    oth, s);
+      cheb_sweep<T>(c, L, A, cur, b, d, post.c1[k], post.c2[k], oth, s);
       std::swap(cur, oth);
     }
   }
@@ -600,7 +684,11 @@ int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha
   if (block == CHNS_BLOCK_CH) {
     const double tg = p.tau * p.mobility, beta_ = p.eps * p.eps;
     const double* Lv = c->has_conv ? L0.L.v64 : L0.M;
-    ch_block<double, double>(L0.d, Lv, L0.K, L0.M, tg, -tg / beta_, x, alpha, beta, y, s);
+    // values M, K (and L when C != 0), x and y of both rows; y read when beta != 0
+    const double bytes = double(c->N) * (8 * (14 + (c->has_conv ? 7 : 0)) + 32 + (beta != 0.0 ? 16 : 0));
+    timed(c, CHNS_KERNEL_CH_BLOCK, bytes, s, [&](LaunchEv ev) {
+      ch_block<double, double>(L0.d, Lv, L0.K, L0.M, tg, -tg / beta_, x, alpha, beta, y, s, ev);
+    });
   } else if (block == CHNS_BLOCK_AC) {
     spmv<double, double>(L0.d, L0.AC.v64, x, y, alpha, beta, s);
   } else if (block == CHNS_BLOCK_NS && c->ternary) {
@@ -664,10 +752,12 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
       // DCGS2: one dot pass and one update pass over the basis (the previous
       // vector's reorthogonalisation rides along with w's projection)
-      dcgs_dots(n, K.V, ld, j, K.part, s);
-      slot_reduce(nblk, 2 * j + 3, K.part, K.red, s);
+      timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (j + 2), s,
+            [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, K.part, s, ev); });
+      slot_reduce(dcgs_dot_blocks(n), 2 * j + 3, K.part, K.red, s);
       dcgs_coef(j, m, K.red, K.H, K.coef, s);
-      dcgs_update(n, K.V, ld, j, K.coef, K.nrm_part, s);
+      timed(c, CHNS_KERNEL_DCGS_UPDATE, 8.0 * n * (j + 2 + (j > 0 ? 1 : 0) + 1), s,
+            [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, K.coef, K.nrm_part, s, ev); });
       dcgs_finish(nblk, K.nrm_part, j, m, K.H, K.HR, K.cs, K.sn, K.g, K.gp, K.scal, s);
       scale_by_inv(n, vn, K.scal + 1, vn, s);
       HIPCHK(c, hipGetLastError());
@@ -1005,6 +1095,8 @@ void release(chns_ctx* c) {
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->kr.host) (void)hipHostFree(c->kr.host);
+  for (auto& e : c->ledger.ev) (void)hipEventDestroy(e);
+  c->ledger.ev.clear();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
@@ -1073,7 +1165,7 @@ int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   Level& L0 = c->lv[0];
   one_minus_sum(N, out->phi[0], out->phi[1], c->w64d, s);
   spmv<double, double>(L0.d, L0.K, c->w64d, c->w64a, 1.0, 0.0, s);
-  cheb_from_zero<double>(L0, L0.Mp, c->w64a, c->w64b, cheb_coef<double>(0.49, 2.01, 40), s);
+  cheb_from_zero<double>(c, L0, L0.Mp, c->w64a, c->w64b, cheb_coef<double>(0.49, 2.01, 40), s);
   axpy_into(N, beta, c->w64b, c->fs, out->mu[2], s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
@@ -1100,7 +1192,7 @@ int ternary_adjoint(chns_ctx* c, const chns_fields& in, const chns_fields& out, 
   const double h = 1.0 / c->mesh.n;
   const double* mu3[3] = {in.mu[0], in.mu[1], in.mu[2]};
   TRY(assemble_ops(c, in.vel, mu3, true, s));
-  cheb_from_zero<double>(L0, L0.Mp, lo.mu[2], c->w64a, cheb_coef<double>(0.49, 2.01, 40), s);
+  cheb_from_zero<double>(c, L0, L0.Mp, lo.mu[2], c->w64a, cheb_coef<double>(0.49, 2.01, 40), s);
   spmv<double, double>(L0.d, L0.K, c->w64a, A.q, beta, 0.0, s);
   for (int i = 0; i < 2; ++i) {
     double* eta = A.eta + i * N2;
@@ -1565,6 +1657,32 @@ int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields*
   HIPCHK(c, hipStreamSynchronize(s));
   for (int i = 0; i < 3; ++i) h_dtheta[i] += c->kr.host[i];
   return worst;
+}
+
+int chns_ledger_start(chns_ctx* c, int32_t kernel) {
+  if (!c) return CHNS_EINVAL;
+  if (kernel < -1 || kernel > CHNS_KERNEL_DCGS_UPDATE) return fail(c, CHNS_EINVAL, "unknown kernel class");
+  Ledger& G = c->ledger;
+  TRY(ledger_fold(c));
+  if (kernel >= 0 && G.cap == 0) {
+    G.cap = 4096;
+    G.ev.resize(2 * size_t(G.cap));
+    for (auto& e : G.ev) HIPCHK(c, hipEventCreate(&e));
+    G.bytes.assign(G.cap, 0.0);
+  }
+  G.kernel = kernel;
+  G.launches = 0;
+  G.sum_bytes = G.sum_ms = 0.0;
+  return CHNS_OK;
+}
+
+int chns_ledger_read(chns_ctx* c, int64_t* launches, double* bytes, double* ms) {
+  if (!c) return CHNS_EINVAL;
+  TRY(ledger_fold(c));
+  if (launches) *launches = c->ledger.launches;
+  if (bytes) *bytes = c->ledger.sum_bytes;
+  if (ms) *ms = c->ledger.sum_ms;
+  return CHNS_OK;
 }
 
 const char* chns_last_error(const chns_ctx* c) {

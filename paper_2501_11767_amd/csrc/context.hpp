@@ -113,6 +113,18 @@ struct AdjData {
   double *acc = nullptr;   // dL/d(eps, mobility, evaporation rate)
 };
 
+// Measurement ledger: launches of one kernel class bracketed by event pairs
+// on their stream, with the algorithmic bytes of each launch.
+struct Ledger {
+  int kernel = -1;  // class being timed, -1 off
+  int cap = 0, used = 0;
+  std::vector<hipEvent_t> ev;  // 2 per slot
+  std::vector<double> bytes;
+  int64_t launches = 0;
+  double sum_bytes = 0.0, sum_ms = 0.0;
+  hipStream_t stream = nullptr;
+};
+
 }  // namespace chns
 
 struct chns_ctx {
@@ -136,6 +148,7 @@ struct chns_ctx {
   int *tslot1 = nullptr, *tslot2 = nullptr;
   double* tbuf = nullptr;
   chns::AdjData adj;
+  chns::Ledger ledger;
   // scratch: FP64 tmp1/tmp2/corr (N each), FP32 r/z (2N each) and
   // tmp1/tmp2/corr (N each), right-hand sides and the CH unknown [phi; mu]
   double *w64a = nullptr, *w64b = nullptr, *w64c = nullptr;

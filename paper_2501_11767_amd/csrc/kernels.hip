@@ -9,6 +9,7 @@
 // loads of a row are issued before the arithmetic, and workgroups are
 // remapped so each of the 8 XCDs works on a contiguous range of rows (its L2
 // then also holds the neighbouring rows that the column gathers touch).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_util.hpp"
@@ -81,6 +82,82 @@ __global__ __launch_bounds__(BS) void k_stencil7(int nrows, int side, const int*
     d[row] = dn;
     y[row] = x[row] + dn;
   }
+}
+
+// Fused multigrid steps on the periodic P1 levels (structured columns).
+
+// First two Chebyshev steps from x = 0 in one pass: x0 = d0 = c20 D^{-1} b is
+// formed on the fly at the row and its neighbours, then
+// d = c11 d0 + c21 D^{-1} (b - A x0), y = x0 + d.
+template <typename T, typename TV>
+__global__ __launch_bounds__(BS) void k_cheb01(int nrows, int side, const TV* __restrict__ val,
+                                               const T* __restrict__ b, const T* __restrict__ dinv,
+                                               T c20, T c11, T c21, T* __restrict__ d,
+                                               T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= nrows) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  int c[W7];
+  TV v[W7];
+  p1_cols(row, side, c);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) sum += T(v[k]) * (c20 * (dinv[c[k]] * b[c[k]]));
+  const T di = dinv[row], br = b[row];
+  const T x0 = c20 * (di * br);
+  const T dn = c11 * x0 + c21 * (di * (br - sum));
+  d[row] = dn;
+  y[row] = x0 + dn;
+}
+
+// P1 interpolation from the coarse periodic side-nc mesh at fine vertex
+// (fi, fj): vertices copy, edge midpoints (horizontal, vertical, diagonal)
+// average their two coarse ends.
+template <typename T>
+__device__ __forceinline__ T p1_interp(const T* __restrict__ e, int fi, int fj, int nc) {
+  const int I = fi >> 1, J = fj >> 1;
+  const T a = e[I + nc * J];
+  if (!((fi | fj) & 1)) return a;
+  const int I1 = (fi & 1) ? (I + 1 == nc ? 0 : I + 1) : I;
+  const int J1 = (fj & 1) ? (J + 1 == nc ? 0 : J + 1) : J;
+  return T(0.5) * (a + e[I1 + nc * J1]);
+}
+
+// Coarse-grid correction and the first post-smoothing step in one pass:
+// x' = x + P e at the row and its neighbours, d = c2 D^{-1} (b - A x'),
+// y = x' + d.
+template <typename T, typename TV>
+__global__ __launch_bounds__(BS) void k_pcheb(int nrows, int side, const TV* __restrict__ val,
+                                              const T* __restrict__ x, const T* __restrict__ e,
+                                              const T* __restrict__ b, const T* __restrict__ dinv,
+                                              T c2, T* __restrict__ d, T* __restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= nrows) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  const int nc = side >> 1;
+  const int j = row / side, i = row - j * side;
+  TV v[W7];
+#pragma unroll
+  for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
+  constexpr int DI[W7] = {0, -1, 0, -1, 1, 0, 1};
+  constexpr int DJ[W7] = {0, -1, -1, 0, 0, 1, 1};
+  T sum = T(0), xs = T(0);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    int fi = i + DI[k], fj = j + DJ[k];
+    fi = fi < 0 ? fi + side : (fi >= side ? fi - side : fi);
+    fj = fj < 0 ? fj + side : (fj >= side ? fj - side : fj);
+    const T xn = x[fi + side * fj] + p1_interp(e, fi, fj, nc);
+    sum += T(v[k]) * xn;
+    if (k == 0) xs = xn;
+  }
+  const T dn = c2 * (dinv[row] * (b[row] - sum));
+  d[row] = dn;
+  y[row] = xs + dn;
 }
 
 template <typename T>
@@ -213,19 +290,21 @@ constexpr int DG = 16;  // basis vectors per group of the dot pass
 
 // Dots of one group of basis vectors against vt and w.  Slots (per block
 // partial, stride gridDim.x): [0, j) V_i . vt, [j, 2j) V_i . w, then vt . vt,
-// vt . w, w . w (written by the last group).
+// vt . w, w . w (written by the last group).  Each thread streams many rows;
+// the epilogue reduces all accumulators per wavefront by shuffles and then
+// across the 4 wavefronts with a single barrier.
 __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __restrict__ V, int64_t ld,
                                                   int j, double* __restrict__ part) {
-  __shared__ double sh[4];
+  constexpr int NV = 2 * DG + 3;
+  __shared__ double sh[4][NV];
   const double* vt = V + int64_t(j) * ld;
   const double* w = V + int64_t(j + 1) * ld;
   const int g0 = blockIdx.y * DG;
   const int kk = max(0, min(DG, j - g0));
   const bool last = (blockIdx.y == gridDim.y - 1);
-  double ac[DG], aw[DG];
+  double acc[NV];
 #pragma unroll
-  for (int i = 0; i < DG; ++i) ac[i] = aw[i] = 0.0;
-  double nu = 0.0, tw = 0.0, ww = 0.0;
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const int64_t stride = int64_t(gridDim.x) * BS;
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
     const double t = vt[r], wr = w[r];
@@ -233,32 +312,32 @@ __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __res
     for (int i = 0; i < DG; ++i)
       if (i < kk) {
         const double v = V[(g0 + i) * ld + r];
-        ac[i] += v * t;
-        aw[i] += v * wr;
+        acc[i] += v * t;
+        acc[DG + i] += v * wr;
       }
     if (last) {
-      nu += t * t;
-      tw += t * wr;
-      ww += wr * wr;
+      acc[2 * DG] += t * t;
+      acc[2 * DG + 1] += t * wr;
+      acc[2 * DG + 2] += wr * wr;
     }
   }
-  const int nb = gridDim.x, b = blockIdx.x;
-  for (int i = 0; i < kk; ++i) {
-    const double s1 = block_sum(ac[i], sh);
-    const double s2 = block_sum(aw[i], sh);
-    if (threadIdx.x == 0) {
-      part[int64_t(g0 + i) * nb + b] = s1;
-      part[int64_t(j + g0 + i) * nb + b] = s2;
-    }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) sh[wid][i] = v;
   }
-  if (last) {
-    const double s1 = block_sum(nu, sh);
-    const double s2 = block_sum(tw, sh);
-    const double s3 = block_sum(ww, sh);
-    if (threadIdx.x == 0) {
-      part[int64_t(2 * j) * nb + b] = s1;
-      part[int64_t(2 * j + 1) * nb + b] = s2;
-      part[int64_t(2 * j + 2) * nb + b] = s3;
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < NV) {
+    const bool used = (t < DG) ? (t < kk) : (t < 2 * DG) ? (t - DG < kk) : last;
+    if (used) {
+      const double s = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+      int64_t slot;
+      if (t < DG) slot = g0 + t;
+      else if (t < 2 * DG) slot = j + g0 + (t - DG);
+      else slot = 2 * j + (t - 2 * DG);
+      part[slot * gridDim.x + blockIdx.x] = s;
     }
   }
 }
@@ -902,6 +981,15 @@ __global__ __launch_bounds__(BS) void k_axpy_into(int64_t n, double a, const dou
 
 // ================================================================== launchers
 
+// Launch, with the dispatch's own start/stop timestamps into ev when given.
+#define LAUNCH_EV(ev, kern, grid, block, shm, st, ...)                                           \
+  do {                                                                                           \
+    if ((ev).start)                                                                              \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, st, (ev).start, (ev).stop, 0, __VA_ARGS__); \
+    else                                                                                         \
+      hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);                               \
+  } while (0)
+
 template <typename T, typename TV>
 void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s) {
   if (A.uniform && A.width == W7) {
@@ -918,19 +1006,33 @@ void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipS
 
 template <typename T, typename TV>
 void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv, T* d,
-             T c1, T c2, T* y, hipStream_t s) {
+             T c1, T c2, T* y, hipStream_t s, LaunchEv ev) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (mode == ST_RESID)
-    hipLaunchKernelGGL((k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b,
-                       dinv, d, c1, c2, y);
+    LAUNCH_EV(ev, (k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+              d, c1, c2, y);
   else
-    hipLaunchKernelGGL((k_stencil7<T, TV, ST_CHEB>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b,
-                       dinv, d, c1, c2, y);
+    LAUNCH_EV(ev, (k_stencil7<T, TV, ST_CHEB>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+              d, c1, c2, y);
 }
 
 template <typename T>
 void cheb0(int n, const T* dinv, const T* b, T c2, T* d, T* x, hipStream_t s) {
   hipLaunchKernelGGL((k_cheb0<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, dinv, b, c2, d, x);
+}
+
+template <typename T, typename TV>
+void cheb01(const DSell& A, const TV* val, const T* b, const T* dinv, T c20, T c11, T c21, T* d, T* y,
+            hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb01<T, TV>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, val,
+                     b, dinv, c20, c11, c21, d, y);
+}
+
+template <typename T, typename TV>
+void pcheb(const DSell& A, const TV* val, const T* x, const T* e, const T* b, const T* dinv, T c2, T* d,
+           T* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_pcheb<T, TV>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, val, x,
+                     e, b, dinv, c2, d, y);
 }
 
 template <typename T, typename TV>
@@ -942,14 +1044,14 @@ void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const
 
 template <typename T, typename TV>
 void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
-              T alpha, T beta, T* y, hipStream_t s) {
+              T alpha, T beta, T* y, hipStream_t s, LaunchEv ev) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (L == M)
-    hipLaunchKernelGGL((k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
-                       x, alpha, beta, y);
+    LAUNCH_EV(ev, (k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
+              alpha, beta, y);
   else
-    hipLaunchKernelGGL((k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
-                       x, alpha, beta, y);
+    LAUNCH_EV(ev, (k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
+              alpha, beta, y);
 }
 
 template <typename T>
@@ -971,10 +1073,13 @@ int reduce_blocks(int64_t n) {
   return int(b < 1 ? 1 : (b > MAXRED ? MAXRED : b));
 }
 
-void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s) {
-  const int nblk = reduce_blocks(n);
+int dcgs_dot_blocks(int64_t n) { return reduce_blocks(n); }
+
+void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s,
+               LaunchEv ev) {
+  const int nblk = dcgs_dot_blocks(n);
   const int groups = j > 0 ? ceil_div(j, DG) : 1;
-  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblk, groups), dim3(BS), 0, s, n, V, ld, j, part);
+  LAUNCH_EV(ev, k_dcgs_dots, dim3(nblk, groups), dim3(BS), 0, s, n, V, ld, j, part);
 }
 
 void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s) {
@@ -986,8 +1091,8 @@ void dcgs_coef(int j, int m, const double* red, double* H, double* coef, hipStre
 }
 
 void dcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, double* nrm_part,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, coef, nrm_part);
+                 hipStream_t s, LaunchEv ev) {
+  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, coef, nrm_part);
 }
 
 void dcgs_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* HR, double* cs,
@@ -1129,11 +1234,19 @@ template void spmv<double, double>(const DSell&, const double*, const double*, d
                                    double, hipStream_t);
 template void spmv<float, float>(const DSell&, const float*, const float*, float*, float, float,
                                  hipStream_t);
+template void cheb01<double, double>(const DSell&, const double*, const double*, const double*, double,
+                                     double, double, double*, double*, hipStream_t);
+template void cheb01<float, float>(const DSell&, const float*, const float*, const float*, float, float,
+                                   float, float*, float*, hipStream_t);
+template void pcheb<double, double>(const DSell&, const double*, const double*, const double*,
+                                    const double*, const double*, double, double*, double*, hipStream_t);
+template void pcheb<float, float>(const DSell&, const float*, const float*, const float*, const float*,
+                                  const float*, float, float*, float*, hipStream_t);
 template void stencil<double, double>(const DSell&, const double*, int, const double*,
                                       const double*, const double*, double*, double, double,
-                                      double*, hipStream_t);
+                                      double*, hipStream_t, LaunchEv);
 template void stencil<float, float>(const DSell&, const float*, int, const float*, const float*,
-                                    const float*, float*, float, float, float*, hipStream_t);
+                                    const float*, float*, float, float, float*, hipStream_t, LaunchEv);
 template void cheb0<double>(int, const double*, const double*, double, double*, double*,
                             hipStream_t);
 template void cheb0<float>(int, const float*, const float*, float, float*, float*, hipStream_t);
@@ -1144,9 +1257,9 @@ template void coarse_cheb<float, float>(const DSell&, const float*, const float*
                                         const ChebCoef<float>&, float*, hipStream_t);
 template void ch_block<double, double>(const DSell&, const double*, const double*, const double*,
                                        double, double, const double*, double, double, double*,
-                                       hipStream_t);
+                                       hipStream_t, LaunchEv);
 template void ch_block<float, float>(const DSell&, const float*, const float*, const float*, float,
-                                     float, const float*, float, float, float*, hipStream_t);
+                                     float, const float*, float, float, float*, hipStream_t, LaunchEv);
 template void axpby<double>(int64_t, double, const double*, double, double*, hipStream_t);
 template void axpby<float>(int64_t, float, const float*, float, float*, hipStream_t);
 template void convert<double, float>(int64_t, const double*, float*, hipStream_t);

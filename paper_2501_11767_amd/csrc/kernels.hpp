@@ -18,6 +18,12 @@ struct DSell {
   int side = 0;  // > 0: periodic side x side P1 pattern in neighbour order (columns computed)
 };
 
+// Optional start/stop events taken by the dispatch itself (the kernel's own
+// start and end timestamps), for the measurement ledger.
+struct LaunchEv {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Operator modes of the fused stencil kernel (uniform width-7 P1 patterns).
 enum StencilMode { ST_SPMV = 0, ST_RESID = 1, ST_CHEB = 2 };
 
@@ -39,7 +45,19 @@ void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipS
 // ST_CHEB: d <- c1 d + c2 dinv (b - A x) (d not read when c1 == 0), y = x + d.
 template <typename T, typename TV>
 void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv,
-             T* d, T c1, T c2, T* y, hipStream_t s);
+             T* d, T c1, T c2, T* y, hipStream_t s, LaunchEv ev = {});
+
+// Fused steps on the periodic P1 levels (A.side > 0):
+// cheb01: the first two Chebyshev steps from x = 0 (x0 = d0 = c20 dinv b formed on
+//   the fly): d = c11 d0 + c21 dinv (b - A x0), y = x0 + d.
+// pcheb: coarse-grid correction x' = x + P e (P1 interpolation from the side/2
+//   mesh) with the first post-smoothing step: d = c2 dinv (b - A x'), y = x' + d.
+template <typename T, typename TV>
+void cheb01(const DSell& A, const TV* val, const T* b, const T* dinv, T c20, T c11, T c21, T* d, T* y,
+            hipStream_t s);
+template <typename T, typename TV>
+void pcheb(const DSell& A, const TV* val, const T* x, const T* e, const T* b, const T* dinv, T c2, T* d,
+           T* y, hipStream_t s);
 
 // First Chebyshev step from x = 0: x = d = c2 dinv b.
 template <typename T>
@@ -55,7 +73,7 @@ void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const
 //   y1 = alpha (L x1 + c12 K x2) + beta y1,  y2 = alpha (c12 K x1 + c22 M x2) + beta y2.
 template <typename T, typename TV>
 void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
-              T alpha, T beta, T* y, hipStream_t s);
+              T alpha, T beta, T* y, hipStream_t s, LaunchEv ev = {});
 
 // Vector kernels.
 template <typename T>
@@ -71,8 +89,10 @@ int reduce_blocks(int64_t n);
 // step j, basis V (columns of length n, stride ld): V_j holds the vector used
 // for this step (orthogonalised once), V_{j+1} the new vector w = A z_j.
 // dots: partials of V_i . V_j, V_i . w (i < j), V_j . V_j, V_j . w, w . w
-// (2j + 3 slots of reduce_blocks(n) partials); slot_reduce sums them.
-void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s);
+// (2j + 3 slots of dcgs_dot_blocks(n) partials); slot_reduce sums them.
+int dcgs_dot_blocks(int64_t n);
+void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s,
+               LaunchEv ev = {});
 void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s);
 // From the reduced dots: reorthogonalisation coefficients of V_j, correction of
 // Hessenberg column j-1, projection coefficients of w (raw H, ld m+1), into coef.
@@ -80,7 +100,7 @@ void dcgs_coef(int j, int m, const double* red, double* H, double* coef, hipStre
 // Applies coef: V_j <- its reorthogonalised, normalised form (j > 0),
 // w <- w projected out of the final basis; partials of |w|^2.
 void dcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, double* nrm_part,
-                 hipStream_t s);
+                 hipStream_t s, LaunchEv ev = {});
 // h_{j+1,j} = |w|; final Givens rotation of column j-1 into HR and g; a
 // provisional rotation of column j into HR and gp; scal = (|gp_{j+1}|, 1/|w|, |w|).
 void dcgs_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* HR, double* cs,
