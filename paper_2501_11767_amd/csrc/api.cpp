@@ -743,6 +743,11 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
     if (iters >= o.maxiter || !std::isfinite(beta)) break;
     inf.restarts++;
     scale_by_inv(n, K.V, K.scal + 1, K.V, s);
+    // One-step lookahead: step j is enqueued before the host reads step
+    // j-1's residual estimate, so the stream never drains at the check.  If
+    // step j-1 turns out to be the last one, the speculative step j has only
+    // finalised column j-1 (its Givens rotation and g) and the least squares
+    // over k = j columns uses that final data.
     int k = 0;
     for (int j = 0; j < m; ++j) {
       double* vj = K.V + j * ld;
@@ -752,7 +757,8 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
       // DCGS2: one dot pass and one update pass over the basis (the previous
       // vector's reorthogonalisation rides along with w's projection)
-      timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (j + 2), s,
+      const int kk0 = j < 16 ? j : 16;
+      timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (kk0 + 2), s,
             [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, K.part, s, ev); });
       slot_reduce(dcgs_dot_blocks(n), 2 * j + 3, K.part, K.red, s);
       dcgs_coef(j, m, K.red, K.H, K.coef, s);
@@ -761,11 +767,24 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       dcgs_finish(nblk, K.nrm_part, j, m, K.H, K.HR, K.cs, K.sn, K.g, K.gp, K.scal, s);
       scale_by_inv(n, vn, K.scal + 1, vn, s);
       HIPCHK(c, hipGetLastError());
-      k = j + 1;
-      ++iters;
-      TRY(read_scal(c, s, 3));
-      const double est = K.host[0], hnext = K.host[2];
-      if (est <= tol || hnext == 0.0 || iters >= o.maxiter || !std::isfinite(est)) break;
+      double* slot = K.host + 4 * (j & 1);
+      HIPCHK(c, hipMemcpyAsync(slot, K.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipEventRecord(K.done[j & 1], s));
+      if (j > 0) {
+        HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));
+        ++iters;
+        const double* prev = K.host + 4 * ((j - 1) & 1);
+        const double est = prev[0], hnext = prev[2];
+        if (est <= tol || hnext == 0.0 || iters >= o.maxiter || !std::isfinite(est)) {
+          k = j;
+          break;
+        }
+      }
+      if (j == m - 1) {
+        HIPCHK(c, hipEventSynchronize(K.done[j & 1]));
+        ++iters;
+        k = m;
+      }
     }
     lsq_solve(k, m, K.HR, K.gp, K.y, s);
     xupdate(n, K.Z, ld, k, K.y, x, s);
@@ -1056,6 +1075,7 @@ int build(chns_ctx* c) {
   TRY(dalloc(c, &K.coef, 2 * MAX_RESTART + 4));
   TRY(dalloc(c, &K.nrm_part, 1024));
   HIPCHK(c, hipHostMalloc((void**)&K.host, 8 * sizeof(double), hipHostMallocDefault));
+  for (auto& e : K.done) HIPCHK(c, hipEventCreate(&e));
   HIPCHK(c, hipEventCreate(&c->ev0));
   HIPCHK(c, hipEventCreate(&c->ev1));
   // M and K on the finest level by coloured scatter, then Galerkin down
@@ -1095,6 +1115,8 @@ void release(chns_ctx* c) {
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->kr.host) (void)hipHostFree(c->kr.host);
+  for (auto& e : c->kr.done)
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : c->ledger.ev) (void)hipEventDestroy(e);
   c->ledger.ev.clear();
   if (c->ev0) (void)hipEventDestroy(c->ev0);

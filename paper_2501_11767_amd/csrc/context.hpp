@@ -97,7 +97,8 @@ struct Krylov {
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *scal = nullptr, *part = nullptr, *nrm_part = nullptr;
   double *HR = nullptr, *gp = nullptr, *red = nullptr, *coef = nullptr;  // DCGS2
-  double* host = nullptr;  // pinned readback
+  double* host = nullptr;  // pinned readback (two 4-double slots for the lookahead)
+  hipEvent_t done[2] = {nullptr, nullptr};
 };
 
 // Work vectors of the adjoint step (ternary contexts).

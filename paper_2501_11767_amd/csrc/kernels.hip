@@ -288,57 +288,54 @@ __global__ __launch_bounds__(BS) void k_scale_by_inv(int64_t n, const double* __
 
 constexpr int DG = 16;  // basis vectors per group of the dot pass
 
-// Dots of one group of basis vectors against vt and w.  Slots (per block
-// partial, stride gridDim.x): [0, j) V_i . vt, [j, 2j) V_i . w, then vt . vt,
-// vt . w, w . w (written by the last group).  Each thread streams many rows;
+// Dots of KK basis vectors V_g0 .. V_{g0+KK-1} against vt and w, and with
+// LAST also vt . vt, vt . w, w . w.  Slots (per block partial, stride
+// gridDim.x): [0, j) V_i . vt, [j, 2j) V_i . w, then 2j, 2j+1, 2j+2.  KK is a
+// compile-time count so that every load of a row is issued before its FMAs;
 // the epilogue reduces all accumulators per wavefront by shuffles and then
-// across the 4 wavefronts with a single barrier.
+// across the 4 wavefronts with one barrier.
+template <int KK, bool LAST>
 __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __restrict__ V, int64_t ld,
-                                                  int j, double* __restrict__ part) {
-  constexpr int NV = 2 * DG + 3;
-  __shared__ double sh[4][NV];
+                                                  int j, int g0, double* __restrict__ part) {
+  constexpr int NV = 2 * KK + (LAST ? 3 : 0);
+  __shared__ double sh[4][NV > 0 ? NV : 1];
   const double* vt = V + int64_t(j) * ld;
   const double* w = V + int64_t(j + 1) * ld;
-  const int g0 = blockIdx.y * DG;
-  const int kk = max(0, min(DG, j - g0));
-  const bool last = (blockIdx.y == gridDim.y - 1);
-  double acc[NV];
+  double acc[NV > 0 ? NV : 1];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const int64_t stride = int64_t(gridDim.x) * BS;
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
     const double t = vt[r], wr = w[r];
+    double v[KK > 0 ? KK : 1];
 #pragma unroll
-    for (int i = 0; i < DG; ++i)
-      if (i < kk) {
-        const double v = V[(g0 + i) * ld + r];
-        acc[i] += v * t;
-        acc[DG + i] += v * wr;
-      }
-    if (last) {
-      acc[2 * DG] += t * t;
-      acc[2 * DG + 1] += t * wr;
-      acc[2 * DG + 2] += wr * wr;
+    for (int i = 0; i < KK; ++i) v[i] = V[(g0 + i) * ld + r];
+#pragma unroll
+    for (int i = 0; i < KK; ++i) {
+      acc[i] += v[i] * t;
+      acc[KK + i] += v[i] * wr;
+    }
+    if (LAST) {
+      acc[2 * KK] += t * t;
+      acc[2 * KK + 1] += t * wr;
+      acc[2 * KK + 2] += wr * wr;
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    const double v = wave_sum(acc[i]);
-    if (lane == 0) sh[wid][i] = v;
+    const double s = wave_sum(acc[i]);
+    if (lane == 0) sh[wid][i] = s;
   }
   __syncthreads();
   const int t = threadIdx.x;
   if (t < NV) {
-    const bool used = (t < DG) ? (t < kk) : (t < 2 * DG) ? (t - DG < kk) : last;
-    if (used) {
-      const double s = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
-      int64_t slot;
-      if (t < DG) slot = g0 + t;
-      else if (t < 2 * DG) slot = j + g0 + (t - DG);
-      else slot = 2 * j + (t - 2 * DG);
-      part[slot * gridDim.x + blockIdx.x] = s;
-    }
+    const double s = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+    int64_t slot;
+    if (t < KK) slot = g0 + t;
+    else if (t < 2 * KK) slot = j + g0 + (t - KK);
+    else slot = 2 * j + (t - 2 * KK);
+    part[slot * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -1075,11 +1072,35 @@ int reduce_blocks(int64_t n) {
 
 int dcgs_dot_blocks(int64_t n) { return reduce_blocks(n); }
 
+template <int KK, bool LAST>
+static void launch_dots(int64_t n, const double* V, int64_t ld, int j, int g0, double* part, hipStream_t s,
+                        LaunchEv ev) {
+  LAUNCH_EV(ev, (k_dcgs_dots<KK, LAST>), dim3(dcgs_dot_blocks(n)), dim3(BS), 0, s, n, V, ld, j, g0, part);
+}
+
+template <bool LAST>
+static void launch_dots_kk(int kk, int64_t n, const double* V, int64_t ld, int j, int g0, double* part,
+                           hipStream_t s, LaunchEv ev) {
+  switch (kk) {
+#define CHNS_DOTS_CASE(K) \
+  case K: launch_dots<K, LAST>(n, V, ld, j, g0, part, s, ev); break;
+    CHNS_DOTS_CASE(0) CHNS_DOTS_CASE(1) CHNS_DOTS_CASE(2) CHNS_DOTS_CASE(3) CHNS_DOTS_CASE(4)
+    CHNS_DOTS_CASE(5) CHNS_DOTS_CASE(6) CHNS_DOTS_CASE(7) CHNS_DOTS_CASE(8) CHNS_DOTS_CASE(9)
+    CHNS_DOTS_CASE(10) CHNS_DOTS_CASE(11) CHNS_DOTS_CASE(12) CHNS_DOTS_CASE(13) CHNS_DOTS_CASE(14)
+    CHNS_DOTS_CASE(15) CHNS_DOTS_CASE(16)
+#undef CHNS_DOTS_CASE
+    default: break;
+  }
+}
+
+// Full groups of DG vectors, then the remainder group with vt . vt, vt . w,
+// w . w (one launch when j < DG).
 void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s,
                LaunchEv ev) {
-  const int nblk = dcgs_dot_blocks(n);
-  const int groups = j > 0 ? ceil_div(j, DG) : 1;
-  LAUNCH_EV(ev, k_dcgs_dots, dim3(nblk, groups), dim3(BS), 0, s, n, V, ld, j, part);
+  const int full = j / DG, rem = j - full * DG;
+  for (int g = 0; g < full; ++g)
+    launch_dots_kk<false>(DG, n, V, ld, j, g * DG, part, s, g == 0 ? ev : LaunchEv{});
+  launch_dots_kk<true>(rem, n, V, ld, j, full * DG, part, s, full == 0 ? ev : LaunchEv{});
 }
 
 void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s) {
