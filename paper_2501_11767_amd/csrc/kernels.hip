@@ -406,7 +406,18 @@ __global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restric
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
     const double t = vt[r];
     double wn = w[r] - wt * t, vn = t;
-    for (int i = 0; i < j; ++i) {
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {  // groups of 8: all loads issued before the FMAs
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = V[(i + q) * ld + r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        vn -= cs[i + q] * v[q];
+        wn -= cs[j + i + q] * v[q];
+      }
+    }
+    for (; i < j; ++i) {
       const double v = V[i * ld + r];
       vn -= cs[i] * v;
       wn -= cs[j + i] * v;
