@@ -702,6 +702,8 @@ int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha
 
 // ------------------------------------------------------------------ FGMRES
 
+constexpr int64_t KRYLOV_PAD = 640;  // doubles (5 KiB) between consecutive basis vectors
+
 int read_scal(chns_ctx* c, hipStream_t s, int count) {
   HIPCHK(c, hipMemcpyAsync(c->kr.host, c->kr.scal, count * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -714,7 +716,10 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   const int64_t n = block_size(c, block);
   const int m = o.restart;
   const int nblk = reduce_blocks(n);
-  const int64_t ld = n;  // basis vectors stored contiguously with stride n
+  // basis vectors with stride n + KRYLOV_PAD: without the pad the vectors of a
+  // large block sit a multiple of 16 MiB apart and the loads of one row of all
+  // of them fall into the same HBM channel
+  const int64_t ld = n + KRYLOV_PAD;
   chns_solve_info inf{};
   HIPCHK(c, hipEventRecord(c->ev0, s));
   norm_partial(n, b, K.nrm_part, s);
@@ -1059,7 +1064,7 @@ int build(chns_ctx* c) {
   }
   // Krylov workspace, sized for the largest block
   Krylov& K = c->kr;
-  K.nmax = int64_t(NB);
+  K.nmax = int64_t(NB) + KRYLOV_PAD;
   TRY(dalloc(c, &K.V, size_t(MAX_RESTART + 1) * K.nmax));
   TRY(dalloc(c, &K.Z, size_t(MAX_RESTART) * K.nmax));
   TRY(dalloc(c, &K.H, size_t(MAX_RESTART + 1) * MAX_RESTART));
