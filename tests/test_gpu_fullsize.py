@@ -1,0 +1,268 @@
+"""GPU parity at the workloads' full sizes, in the configurations the benchmark
+times (through the C-ABI).
+
+* chac1024 (1024 x 1024 CH + AC): one step against the oracle's exact
+  Fourier-mode solve.  Bench configuration (FGMRES(20), rtol 1e-8): true
+  residual in the oracle's arithmetic <= 2 rtol, and the forward error <=
+  2 kappa rtol with kappa the condition number of the CH block from its
+  Fourier symbols.  Tighter solves reach the stated accuracy: FP64 at rtol
+  1e-11 within 1e-10 relative, mixed at rtol 1e-9 within 1e-8.
+* dry256 (ternary + AC + Oseen on 256 x 256): the GPU step's outputs satisfy
+  the oracle's independently assembled systems (CH for both phases, AC,
+  Oseen with B v = 0 rows, the solvent closure) to 2 rtol.
+* batch64: every instance's true residual (oracle symbols) <= 2 rtol and the
+  four sampled instances (one per mesh size) within 2 kappa rtol of the exact
+  solve; the calibrated graph replay equals the eager run.
+* adjoint128: the gradient of the 50-step rollout (checkpoint every 10) by the
+  mixed-precision adjoint within 1e-6 of fourth-order central differences.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, potential as pot, solvers, step as S, systems
+from oracle.systems import Params
+from paper_2501_11767_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_11767_amd import adjoint as A, chns as C
+    C.lib()
+    return C, A
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel())).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+class Fourier:
+    """Periodic P1 operators by their Fourier symbols (oracle), for exact
+    solves, residuals and condition numbers of convection-free systems."""
+
+    def __init__(self, n):
+        self.n = n
+        self.Kh, self.Mh = solvers.p1_symbols(n)
+
+    def apply(self, sym, v):
+        n = self.n
+        return np.real(np.fft.ifft2(sym * np.fft.fft2(v.reshape(n, n)))).ravel()
+
+    def ch_residual(self, prm, x1, x2, b1, b2):
+        tg, c = prm.tau * prm.gamma, prm.tau * prm.gamma / prm.beta
+        r1 = b1 - (self.apply(self.Mh, x1) + tg * self.apply(self.Kh, x2))
+        r2 = b2 - (tg * self.apply(self.Kh, x1) - c * self.apply(self.Mh, x2))
+        return np.sqrt(r1 @ r1 + r2 @ r2) / np.sqrt(b1 @ b1 + b2 @ b2)
+
+    def ac_residual(self, prm, x, b):
+        r = b - (self.apply(self.Mh, x) + prm.tau * prm.delta_v * self.apply(self.Kh, x))
+        return np.linalg.norm(r) / np.linalg.norm(b)
+
+    def ch_kappa(self, prm):
+        """Condition number of the CH block: extreme singular values of the
+        per-mode 2 x 2 symbol matrices."""
+        tg, c = prm.tau * prm.gamma, prm.tau * prm.gamma / prm.beta
+        m, k = self.Mh.ravel(), self.Kh.ravel()
+        a, b, d = m, tg * k, -c * m  # symmetric [[a, b], [b, d]]: |eigenvalues| = singular values
+        tr, det = a + d, a * d - b * b
+        disc = np.sqrt(np.maximum(tr * tr / 4 - det, 0.0))
+        ev = np.abs(np.concatenate([tr / 2 + disc, tr / 2 - disc]))
+        return float(ev.max() / ev.min())
+
+
+def _binary_rhs(F, prm, phi0, Phi0):
+    fp, fv = pot.dfdphi_bin(phi0, Phi0), pot.dfdPhi_bin(phi0, Phi0)
+    b1 = F.apply(F.Mh, phi0)
+    b2 = -(prm.tau * prm.gamma / prm.beta) * F.apply(F.Mh, fp)
+    bac = F.apply(F.Mh, Phi0) - prm.tau * prm.gamma_v * F.apply(F.Mh, fv)
+    return b1, b2, bac
+
+
+@pytest.mark.parametrize("precision,rtol,bar", [("f64", 1e-8, None), ("mixed", 1e-8, None),
+                                                ("f64", 1e-11, 1e-10), ("mixed", 1e-9, 1e-8)])
+def test_chac1024_step_matches_exact_solve(mods, precision, rtol, bar):
+    import torch
+    C, _ = mods
+    cfg = inputs.CONFIGS["chac1024"]
+    n, N = cfg["n"], cfg["n"] ** 2
+    print(f"chac1024 full size: {precision} rtol {rtol}", flush=True)
+    st = inputs.initial_state(n, "ch_ac", cfg["mean"], cfg["seed"])
+    p = dict(eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+    ctx = C.Context(n, "ch_ac", **p)
+    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
+    fin = ctx.fields(phi=[_dev(st["phi"][0])], mu=[z()], Phi_v=_dev(st["Phi_v"]))
+    out = [z(), z(), z()]
+    fout = ctx.fields(phi=[out[0]], mu=[out[1]], Phi_v=out[2])
+    prec = C.F64 if precision == "f64" else C.MIXED
+    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=prec, restart=20, maxiter=600))
+    torch.cuda.synchronize()
+    assert rc == C.OK, info
+    phi, mu, Phi = (t.cpu().numpy() for t in out)
+    ctx.close()
+    prm = Params(**p)
+    F = Fourier(n)
+    b1, b2, bac = _binary_rhs(F, prm, st["phi"][0], st["Phi_v"])
+    ex_phi, ex_mu = solvers.fft_ch_solve(n, prm, b1, b2)
+    ex_Phi = solvers.fft_ac_solve(n, prm, bac)
+    assert F.ch_residual(prm, phi, mu, b1, b2) <= 2 * rtol
+    assert F.ac_residual(prm, Phi, bac) <= 2 * rtol
+    kappa = F.ch_kappa(prm)
+    e_ch = np.sqrt(np.sum((phi - ex_phi) ** 2) + np.sum((mu - ex_mu) ** 2)) / \
+        np.sqrt(np.sum(ex_phi ** 2) + np.sum(ex_mu ** 2))
+    assert e_ch <= 2 * kappa * rtol, (e_ch, kappa)
+    if bar is not None:
+        assert _rel(phi, ex_phi) <= bar, _rel(phi, ex_phi)
+        assert _rel(Phi, ex_Phi) <= bar, _rel(Phi, ex_Phi)
+
+
+def test_dry256_step_satisfies_oracle_systems(mods):
+    import torch
+    C, _ = mods
+    cfg = inputs.CONFIGS["dry256"]
+    n, N = cfg["n"], cfg["n"] ** 2
+    rtol = 1e-8
+    print("dry256 full size: ternary step vs the oracle's systems", flush=True)
+    p = dict(eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"],
+             viscosity=cfg["viscosity"], alpha=1e-8, rho=1.0)
+    st = inputs.initial_state(n, "ternary", cfg["mean"], cfg["seed"])
+    vel0 = np.asarray(st["vel"]).reshape(2, 4 * N)
+    ctx = C.Context(n, "ternary", **p)
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    fin = ctx.fields(phi=[_dev(st["phi"][0]), _dev(st["phi"][1])], mu=[z(N), z(N), z(N)],
+                     Phi_v=_dev(st["Phi_v"]), vel=_dev(vel0), p=z(N))
+    o = dict(phi=[z(N), z(N)], mu=[z(N), z(N), z(N)], Phi_v=z(N), vel=z(8 * N), p=z(N))
+    fout = ctx.fields(**o)
+    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=C.F64, maxiter=1000))
+    torch.cuda.synchronize()
+    assert rc == C.OK, info
+    g = {k: ([t.cpu().numpy() for t in v] if isinstance(v, list) else v.cpu().numpy()) for k, v in o.items()}
+    ctx.close()
+
+    prm = Params(**p)
+    ops = S.Operators(n, need_p2=True)
+    m, M, K = ops.mesh, ops.M, ops.K
+    pp, pn, Phi0 = st["phi"][0], st["phi"][1], st["Phi_v"]
+    Cv = fem.p1_convection(m, vel0)
+    Ach = systems.ch_matrix(M, K, Cv, prm)
+    fps = pot.dfdphi_ter(pp, pn, Phi0)
+    for i, ph0 in enumerate((pp, pn)):
+        b = systems.ch_rhs(M, ph0, fps[i], prm)
+        x = np.concatenate([g["phi"][i], g["mu"][i]])
+        assert np.linalg.norm(b - Ach @ x) <= 2 * rtol * np.linalg.norm(b), i
+    Aac = systems.ac_matrix(M, K, Cv, prm)
+    bac = systems.ac_rhs(M, Phi0, pot.dfdPhi_ter(pp, pn, Phi0), prm)
+    assert np.linalg.norm(bac - Aac @ g["Phi_v"]) <= 2 * rtol * np.linalg.norm(bac)
+    # Oseen: w = rho v^0 (mu^0 = 0), Korteweg load from phi_p, phi_N, phi_s, Phi at level 0
+    J = fem.p2_convection(m, prm.rho * vel0, np.zeros((m.ne, 2)))
+    Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm)
+    ps0 = 1.0 - pp - pn
+    grads = [fem.p1_grad(m, u) for u in (pp, pn, ps0, Phi0)]
+    Fk = fem.korteweg_load(m, grads, [prm.beta, prm.beta, prm.beta, prm.beta_v])
+    rhs = systems.oseen_rhs(ops.Mv, vel0, Fk, prm)
+    A = systems.oseen_matrix(Avel, ops.B)
+    x = np.concatenate([g["vel"], g["p"]])
+    full_rhs = np.concatenate([rhs, np.zeros(N)])
+    assert np.linalg.norm(full_rhs - A @ x) <= 2 * rtol * np.linalg.norm(full_rhs)
+    assert abs(g["p"].sum()) <= 1e-9 * np.abs(g["p"]).sum()
+    # closure: mu_s = f_s'(phi_s^0, Phi^0) + beta M^{-1} K phi_s^1
+    ps1 = 1.0 - g["phi"][0] - g["phi"][1]
+    mus = pot.dfdphis_ter(ps0, Phi0) + prm.beta * ops.mass_solve(K @ ps1)
+    assert _rel(g["mu"][2], mus) <= 1e-10
+
+
+def test_batch64_instances_residuals_and_sampled_errors(mods):
+    import torch
+    C, _ = mods
+    inst = inputs.batch_instances()
+    sizes = [d["n"] for d in inst]
+    prm = [dict(eps=d["eps"], tau=d["tau"], mobility=d["mobility"], evap_rate=d["evap_rate"]) for d in inst]
+    print(f"batch64 full size: {len(sizes)} instances", flush=True)
+    phi0, Phi0 = [], []
+    for d in inst:
+        st = inputs.initial_state(d["n"], "ch_ac", 0.4, d["seed"])
+        phi0.append(st["phi"][0])
+        Phi0.append(st["Phi_v"])
+    phi0, Phi0 = np.concatenate(phi0), np.concatenate(Phi0)
+    batch = C.Batch(sizes, prm)
+    off = batch.offsets
+    rtol = 1e-8
+    opts = C.default_opts(rtol=rtol, precision=C.MIXED, restart=40, maxiter=120)
+    zin = [_dev(phi0), torch.zeros(len(phi0), dtype=torch.float64, device="cuda"), _dev(Phi0)]
+    out = [torch.zeros_like(zin[0]) for _ in range(3)]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    rc, info = batch.timestep(*zin, nsteps=1, opts=opts, stream=s, out=out, each_from_input=True)
+    assert rc == C.OK, info
+    eager = [t.cpu().numpy() for t in out]
+    batch.calibrate_graph(info)
+    rc, info_g = batch.timestep(*zin, nsteps=1, opts=opts, use_graph=True, stream=s, out=out,
+                                each_from_input=True)
+    assert rc == C.OK, info_g
+    graph = [t.cpu().numpy() for t in out]
+    batch.close()
+    for a, b in zip(graph, eager):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    sampled = {}
+    for i, n in enumerate(sizes):
+        sampled.setdefault(n, i)
+    fouriers = {}
+    for i, (n, pi) in enumerate(zip(sizes, prm)):
+        sl = slice(int(off[i]), int(off[i + 1]))
+        P = Params(**pi)
+        F = fouriers.setdefault(n, Fourier(n))
+        b1, b2, bac = _binary_rhs(F, P, phi0[sl], Phi0[sl])
+        phi, mu, Phi = (e[sl] for e in eager)
+        assert F.ch_residual(P, phi, mu, b1, b2) <= 2 * rtol, i
+        assert F.ac_residual(P, Phi, bac) <= 2 * rtol, i
+        if sampled[n] == i:
+            ex_phi, ex_mu = solvers.fft_ch_solve(n, P, b1, b2)
+            e = np.sqrt(np.sum((phi - ex_phi) ** 2) + np.sum((mu - ex_mu) ** 2)) / \
+                np.sqrt(np.sum(ex_phi ** 2) + np.sum(ex_mu ** 2))
+            assert e <= 2 * F.ch_kappa(P) * rtol, (i, n, e)
+
+
+def test_adjoint128_gradient_matches_fourth_order_differences(mods):
+    import torch
+    C, A = mods
+    cfg = inputs.CONFIGS["adjoint128"]
+    n, N, steps, K = cfg["n"], cfg["n"] ** 2, cfg["steps"], cfg["checkpoint"]
+    print(f"adjoint128 full size: {steps} steps, checkpoint {K}", flush=True)
+    ref = (cfg["eps"], cfg["mobility"], cfg["evap_rate"])
+    th0 = tuple(cfg["theta0"])
+    ctx = C.Context(n, "ternary", eps=ref[0], tau=cfg["tau"], mobility=ref[1], evap_rate=ref[2],
+                    viscosity=cfg["viscosity"], alpha=cfg["alpha"], rho=1.0)
+    f = inputs.initial_state(n, "ternary", cfg["mean"], cfg["seed"])
+    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
+    st0 = dict(phi_p=_dev(f["phi"][0]), phi_n=_dev(f["phi"][1]), mu_p=z(), mu_n=z(), mu_s=z(),
+               Phi=_dev(f["Phi_v"]), vel=_dev(f["vel"]), p=z())
+    tight = C.default_opts(rtol=1e-13, precision=C.F64, maxiter=3000)
+    mixed = C.default_opts(rtol=1e-10, precision=C.MIXED, maxiter=2000)
+
+    def loss(theta):
+        with torch.no_grad():
+            php, phn = A.rollout(ctx, torch.tensor(theta, dtype=torch.float64), st0, steps, K, tight)
+            return float(A.loss(ctx, (php, phn), target))
+
+    with torch.no_grad():
+        target = [t.clone() for t in A.rollout(ctx, torch.tensor(ref, dtype=torch.float64), st0, steps, K,
+                                                tight)]
+    theta = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    php, phn = A.rollout(ctx, theta, st0, steps, K, mixed)
+    L = A.loss(ctx, (php, phn), target)
+    L.backward()
+    grad = theta.grad.numpy()
+    for j in range(3):
+        h = 1e-3 * th0[j]
+        at = lambda k: loss([th0[i] + (k * h if i == j else 0.0) for i in range(3)])
+        fd = (-at(2) + 8 * at(1) - 8 * at(-1) + at(-2)) / (12 * h)
+        assert abs(grad[j] - fd) <= 1e-6 * abs(fd), (j, grad[j], fd)
+    ctx.close()
