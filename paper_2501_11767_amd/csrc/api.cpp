@@ -420,23 +420,113 @@ void cheb_from_zero(chns_ctx* c, Level& L, const OpVals& A, const T* b, T* x, co
 // One V(pre, post) cycle from x = 0 on level l (down to the cut level):
 // x = V b.  `x` and `b` may be external buffers on level 0; the level's t, r
 // and d vectors are scratch.
+// Chebyshev coefficients of the cut level l: interval [lo, lmax] with lo the
+// lower spectral bound of D^{-1}A for a M + b K on that level (the smallest
+// nonzero eigenvalue for the singular Neumann Laplacian).
+template <typename T>
+ChebCoef<T> cut_coef(chns_ctx* c, OpVals Level::*op, size_t l, const chns_solve_opts& o) {
+  const double* cf = coef_of(c, op);
+  const double nl = c->lv[l].n;
+  double lo;
+  if (singular_of(op)) {
+    lo = 0.9 * (1.0 - std::cos(2.0 * M_PI / nl)) / 2.0;  // smallest nonzero eigenvalue of D^-1 K
+  } else {
+    lo = 0.45 / (1.0 + 8.0 * cf[1] * nl * nl / cf[0]);
+  }
+  const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
+  return cheb_coef<T>(lo, o.mg_lmax, std::min(steps, MAXCHEB));
+}
+
+template <typename T>
+TileArgs<T> tile_args(Level& L, const OpVals& A, int steps, const ChebCoef<T>& cc) {
+  TileArgs<T> a;
+  a.side = L.d.side;
+  a.steps = steps;
+  a.val = Sel<T>::v(A);
+  a.dinv = Sel<T>::d(A);
+  for (int k = 0; k < steps && k < TILE_MAXSTEPS; ++k) {
+    a.c1[k] = cc.c1[k];
+    a.c2[k] = cc.c2[k];
+  }
+  return a;
+}
+
+// Levels l..cut in one workgroup launch when they are periodic P1 levels
+// small enough for LDS; false when they are not.
+template <typename T>
+bool vcycle_tail(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T* x,
+                 const chns_solve_opts& o, hipStream_t s) {
+  const int nlev = int(cut - l + 1);
+  if (nlev > TAIL_MAXLEV || o.mg_pre > TAIL_MAXSM || o.mg_post > TAIL_MAXSM) return false;
+  int sides[TAIL_MAXLEV];
+  for (int t = 0; t < nlev; ++t) {
+    sides[t] = c->lv[l + t].d.side;
+    if (sides[t] <= 0) return false;
+  }
+  if (!tail_fits<T>(sides, nlev)) return false;
+  TailArgs<T> a{};
+  a.nlev = nlev;
+  for (int t = 0; t < nlev; ++t) {
+    const OpVals& A = c->lv[l + t].*op;
+    a.side[t] = sides[t];
+    a.val[t] = Sel<T>::v(A);
+    a.dinv[t] = Sel<T>::d(A);
+  }
+  a.b = b;
+  a.x = x;
+  a.pre = o.mg_pre;
+  a.post = o.mg_post;
+  const ChebCoef<T> pre = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre);
+  const ChebCoef<T> post = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post);
+  for (int k = 0; k < o.mg_pre; ++k) {
+    a.pre_c1[k] = pre.c1[k];
+    a.pre_c2[k] = pre.c2[k];
+  }
+  for (int k = 0; k < o.mg_post; ++k) {
+    a.post_c1[k] = post.c1[k];
+    a.post_c2[k] = post.c2[k];
+  }
+  a.coarse = cut_coef<T>(c, op, cut, o);
+  vtail<T>(a, s);
+  return true;
+}
+
 template <typename T>
 void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T* x,
             const chns_solve_opts& o, hipStream_t s) {
   Level& L = c->lv[l];
   const OpVals& A = L.*op;
   const double lmax = o.mg_lmax;
+  if (vcycle_tail<T>(c, op, l, cut, b, x, o, s)) return;
   if (l == cut) {
-    const double* cf = coef_of(c, op);
-    const double nl = L.n;
-    double lo;
-    if (singular_of(op)) {
-      lo = 0.9 * (1.0 - std::cos(2.0 * M_PI / nl)) / 2.0;  // smallest nonzero eigenvalue of D^-1 K
-    } else {
-      lo = 0.45 / (1.0 + 8.0 * cf[1] * nl * nl / cf[0]);
+    const ChebCoef<T> cc = cut_coef<T>(c, op, l, o);
+    if (L.d.side > 0 && tile_fits<T>(TILE_ZERO, L.d.side, cc.steps)) {
+      TileArgs<T> ta = tile_args<T>(L, A, cc.steps, cc);
+      ta.b = b;
+      ta.x = x;
+      vtile<T>(TILE_ZERO, ta, s);
+      return;
     }
-    const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
-    cheb_from_zero<T>(c, L, A, b, x, cheb_coef<T>(lo, lmax, std::min(steps, MAXCHEB)), s);
+    cheb_from_zero<T>(c, L, A, b, x, cc, s);
+    return;
+  }
+  if (L.d.side > 0 && tile_fits<T>(TILE_DOWN, L.d.side, o.mg_pre) &&
+      tile_fits<T>(TILE_UP, L.d.side, o.mg_post)) {
+    // two launches per level: pre-smoothing, residual and restriction in one,
+    // coarse correction and post-smoothing in the other
+    Level& G = c->lv[l + 1];
+    TileArgs<T> dn = tile_args<T>(L, A, o.mg_pre, cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre));
+    dn.b = b;
+    dn.x = Sel<T>::t(L);
+    dn.bc = Sel<T>::b(G);
+    vtile<T>(TILE_DOWN, dn, s);
+    vcycle<T>(c, op, l + 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
+    TileArgs<T> up = tile_args<T>(L, A, o.mg_post, cheb_coef<T>(lmax / 4.0, lmax, o.mg_post));
+    up.b = b;
+    up.xin = Sel<T>::t(L);
+    up.e = Sel<T>::x(G);
+    up.x = x;
+    vtile<T>(TILE_UP, up, s);
     return;
   }
   const ChebCoef<T> pre = cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre);

@@ -214,6 +214,323 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const
   if (r < nrows) x[r] = cur[r];
 }
 
+// ------------------------------------------------------------------ tiled levels
+
+// Tiled multigrid kernels: tile interior side TT, rows per thread RPT (1024
+// threads cover the tile and a halo of up to TILE_HMAX rings).  A row's 7
+// values, 1/diag, right-hand side and Chebyshev direction are held by its
+// thread for all steps of the launch; the iterates, which the neighbours
+// gather, sit in two LDS buffers.  Large levels take 64 x 64 tiles (less halo
+// traffic), smaller ones 32 x 32 tiles (more workgroups, fewer rows per
+// thread: these levels are latency-bound).
+constexpr int TILE_THREADS = 1024;
+constexpr int TILE_HMAX = 4;
+template <int TT> struct TileRpt;
+template <> struct TileRpt<64> { static constexpr int RPT = 6; };
+template <> struct TileRpt<32> { static constexpr int RPT = 2; };
+// float levels of at least this side take 64 x 64 tiles (256 or more tiles)
+constexpr int TILE64_MIN_SIDE = 1024;
+template <typename T>
+inline int tile_side(int side) {
+  return (sizeof(T) == 4 && side >= TILE64_MIN_SIDE) ? 64 : 32;
+}
+
+__device__ __forceinline__ int wrap_once(int x, int s) { return x < 0 ? x + s : (x >= s ? x - s : x); }
+
+template <typename T, int MODE, int TT>
+__global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
+  constexpr int RPT = TileRpt<TT>::RPT;
+  constexpr int WMAX = TT + 2 * TILE_HMAX;
+  __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
+  const int s = a.side, steps = a.steps;
+  const int H = (MODE == TILE_ZERO) ? steps - 1 : (MODE == TILE_DOWN ? steps + 1 : steps);
+  const int W = TT + 2 * H, R = W * W;
+  const int nt = (s + TT - 1) / TT;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int ty = tile / nt, tx = tile - ty * nt;
+  const int i0 = tx * TT - H, j0 = ty * TT - H;
+  const int tid = threadIdx.x;
+  // neighbour offsets in the tile, in the order of the stored values:
+  // self, (-1,-1), (0,-1), (-1,0), (1,0), (0,1), (1,1)
+  const int off[W7] = {0, -W - 1, -W, -1, 1, W, W + 1};
+  T v[RPT][W7], di[RPT], bb[RPT], d[RPT];
+  int gr[RPT], ring[RPT];
+  bool own[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int idx = tid + q * TILE_THREADS;
+    ring[q] = -1;
+    own[q] = false;
+    if (idx < R) {
+      const int rj = idx / W, ri = idx - rj * W;
+      const int gi = wrap_once(i0 + ri, s), gj = wrap_once(j0 + rj, s);
+      const int row = gi + s * gj;
+      gr[q] = row;
+      ring[q] = min(min(ri, rj), min(W - 1 - ri, W - 1 - rj));
+      own[q] = ring[q] >= H && tx * TT + (ri - H) < s && ty * TT + (rj - H) < s;
+      const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) v[q][k] = a.val[base + k * 64];
+      di[q] = a.dinv[row];
+      bb[q] = a.b[row];
+      if (MODE == TILE_UP) xa[idx] = a.xin[row] + p1_interp(a.e, gi, gj, s >> 1);
+    }
+  }
+  if (MODE != TILE_UP) {  // first step from zero: x = d = c2 D^{-1} b
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int idx = tid + q * TILE_THREADS;
+      if (idx < R) {
+        d[q] = a.c2[0] * (di[q] * bb[q]);
+        xa[idx] = d[q];
+      }
+    }
+  }
+  __syncthreads();
+  T* cur = xa;
+  T* nxt = xb;
+  // Chebyshev steps k0.. on shrinking rings: step k is valid at ring >= k - k0 + 1
+  const int k0 = (MODE == TILE_UP) ? 0 : 1;
+  for (int k = k0; k < steps; ++k) {
+    const T c1 = a.c1[k], c2 = a.c2[k];
+    const int rmin = k - k0 + 1;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int idx = tid + q * TILE_THREADS;
+      if (ring[q] >= rmin) {
+        T sum = T(0);
+#pragma unroll
+        for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + off[m]];
+        const T r = di[q] * (bb[q] - sum);
+        const T dn = (k == 0) ? c2 * r : c1 * d[q] + c2 * r;
+        d[q] = dn;
+        nxt[idx] = cur[idx] + dn;
+      }
+    }
+    __syncthreads();
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+    if (own[q]) a.x[gr[q]] = cur[tid + q * TILE_THREADS];
+  if (MODE == TILE_DOWN) {
+    // residual on ring >= steps, then R = P^T into the coarse rows whose fine
+    // vertex lies in the tile interior
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int idx = tid + q * TILE_THREADS;
+      if (ring[q] >= steps) {
+        T sum = T(0);
+#pragma unroll
+        for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + off[m]];
+        nxt[idx] = bb[q] - sum;
+      }
+    }
+    __syncthreads();
+    constexpr int TC = TT / 2;
+    const int nc = s >> 1;
+    if (tid < TC * TC) {
+      const int lj = tid / TC, li = tid - lj * TC;
+      const int cI = tx * TC + li, cJ = ty * TC + lj;
+      if (cI < nc && cJ < nc) {
+        const int idx = (2 * li + H) + W * (2 * lj + H);
+        T sm = T(0);
+#pragma unroll
+        for (int m = 1; m < W7; ++m) sm += nxt[idx + off[m]];
+        a.bc[cI + nc * cJ] = nxt[idx] + T(0.5) * sm;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ V-cycle tail
+
+// Rows per thread of the tail kernel and its LDS budget (three vectors per
+// level: two iterate buffers, the second also holding the residual, and the
+// right-hand side).
+template <typename T> struct TailCfg;
+template <> struct TailCfg<float> { static constexpr int RPT = 1; };
+template <> struct TailCfg<double> { static constexpr int RPT = 2; };
+constexpr size_t TAIL_LDS = 65536;
+
+__device__ __forceinline__ int tail_off(const int* side, int t) {
+  int o = 0;
+  for (int u = 0; u < t; ++u) o += 3 * side[u] * side[u];
+  return o;
+}
+
+// The tail levels of one V-cycle in one workgroup (see vtail).  Each thread
+// owns rows tid + q * 1024; a row's 7 values, 1/diag, right-hand side and
+// Chebyshev direction stay in registers while its level is being smoothed,
+// the iterates (which neighbours gather) in LDS.  Between the level's
+// dependent steps only a workgroup barrier is needed, where each step of the
+// launch-per-step cycle pays a kernel launch.
+template <typename T, int RPT>
+__global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
+  __shared__ T lds[TAIL_LDS / sizeof(T)];
+  __shared__ TailArgs<T> a;
+  const int tid = threadIdx.x;
+  {
+    // the arguments to LDS in one parallel copy: the cycle reads level
+    // descriptors and step coefficients at every step, and each scalar load
+    // of a fresh argument buffer would wait for memory
+    const unsigned* src = reinterpret_cast<const unsigned*>(&ka);
+    unsigned* dst = reinterpret_cast<unsigned*>(&a);
+    for (int i = tid; i < int(sizeof(TailArgs<T>) / 4); i += TAIL_THREADS) dst[i] = src[i];
+    __syncthreads();
+  }
+  const int last = a.nlev - 1;
+  unsigned in_y = 0;  // bit t: level t's iterate is in its second buffer
+  T v[RPT][W7], di[RPT], br[RPT], d[RPT];
+  int c[RPT][W7];
+
+  // Registers of level t: values, 1/diag, columns and the right-hand side
+  // (from LDS, or from global memory on the first level).
+  auto load_level = [&](int t, const T* B) {
+    const int side = a.side[t], rows = side * side;
+    const T* val = a.val[t];
+    const T* dv = a.dinv[t];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = tid + q * TAIL_THREADS;
+      if (row < rows) {
+        const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) v[q][k] = val[base + k * 64];
+        p1_cols(row, side, c[q]);
+        di[q] = dv[row];
+        br[q] = B[row];
+      }
+    }
+  };
+  // One Chebyshev step on level t: d <- c1 d + c2 D^{-1} (b - A cur), nxt = cur + d
+  // (c1 == 0: d not read).
+  auto sweep = [&](int rows, const T* cur, T* nxt, T c1, T c2) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = tid + q * TAIL_THREADS;
+      if (row < rows) {
+        T sum = T(0);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) sum += v[q][k] * cur[c[q][k]];
+        const T r = di[q] * (br[q] - sum);
+        const T dn = (c1 == T(0)) ? c2 * r : c1 * d[q] + c2 * r;
+        d[q] = dn;
+        nxt[row] = cur[row] + dn;
+      }
+    }
+    __syncthreads();
+  };
+  // Chebyshev steps from zero with coefficients (c1, c2)[0..steps); returns
+  // whether the iterate ends in the second buffer.
+  auto from_zero = [&](int rows, T* X, T* Y, const T* c1, const T* c2, int steps) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = tid + q * TAIL_THREADS;
+      if (row < rows) {
+        d[q] = c2[0] * (di[q] * br[q]);
+        X[row] = d[q];
+      }
+    }
+    __syncthreads();
+    T* cur = X;
+    T* nxt = Y;
+    for (int k = 1; k < steps; ++k) {
+      sweep(rows, cur, nxt, c1[k], c2[k]);
+      T* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    return cur == Y;
+  };
+
+  // down: pre-smoothing, residual and restriction on each smoothing level
+  for (int t = 0; t < last; ++t) {
+    const int side = a.side[t], rows = side * side;
+    T* X = lds + tail_off(a.side, t);
+    T* Y = X + rows;
+    T* B = Y + rows;
+    load_level(t, t == 0 ? a.b : B);
+    const bool y = from_zero(rows, X, Y, a.pre_c1, a.pre_c2, a.pre);
+    if (y) in_y |= 1u << t;
+    const T* cur = y ? Y : X;
+    T* res = y ? X : Y;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = tid + q * TAIL_THREADS;
+      if (row < rows) {
+        T sum = T(0);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) sum += v[q][k] * cur[c[q][k]];
+        res[row] = br[q] - sum;
+      }
+    }
+    __syncthreads();
+    // R = P^T: a coarse vertex collects its fine vertex and, with weight 1/2,
+    // the six edge midpoints around it (the neighbours of the fine vertex)
+    const int nc = side >> 1, rows_c = nc * nc;
+    T* Bc = lds + tail_off(a.side, t + 1) + 2 * rows_c;
+    for (int rc = tid; rc < rows_c; rc += TAIL_THREADS) {
+      const int J = rc / nc, I = rc - J * nc;
+      int cf[W7];
+      p1_cols(2 * I + side * (2 * J), side, cf);
+      T s = T(0);
+#pragma unroll
+      for (int k = 1; k < W7; ++k) s += res[cf[k]];
+      Bc[rc] = res[cf[0]] + T(0.5) * s;
+    }
+    __syncthreads();
+  }
+  // the cut level
+  {
+    const int side = a.side[last], rows = side * side;
+    T* X = lds + tail_off(a.side, last);
+    T* Y = X + rows;
+    T* B = Y + rows;
+    load_level(last, last == 0 ? a.b : B);
+    if (from_zero(rows, X, Y, a.coarse.c1, a.coarse.c2, a.coarse.steps)) in_y |= 1u << last;
+  }
+  // up: interpolation of the coarse iterate and post-smoothing
+  for (int t = last - 1; t >= 0; --t) {
+    const int side = a.side[t], rows = side * side, nc = side >> 1;
+    T* X = lds + tail_off(a.side, t);
+    T* Y = X + rows;
+    T* B = Y + rows;
+    const T* E = lds + tail_off(a.side, t + 1) + ((in_y >> (t + 1)) & 1u ? nc * nc : 0);
+    T* cur = (in_y >> t) & 1u ? Y : X;
+    T* nxt = (cur == X) ? Y : X;
+    load_level(t, t == 0 ? a.b : B);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = tid + q * TAIL_THREADS;
+      if (row < rows) {
+        const int j = row / side, i = row - j * side;
+        cur[row] += p1_interp(E, i, j, nc);
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < a.post; ++k) {
+      sweep(rows, cur, nxt, a.post_c1[k], a.post_c2[k]);
+      T* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
+    if (t == 0) {
+      in_y = (cur == Y) ? 1u : 0u;
+    } else {
+      in_y = (in_y & ~(1u << t)) | ((cur == Y ? 1u : 0u) << t);
+    }
+  }
+  // result of the first level
+  {
+    const int rows = a.side[0] * a.side[0];
+    const T* src = lds + (in_y & 1u ? rows : 0);
+    for (int row = tid; row < rows; row += TAIL_THREADS) a.x[row] = src[row];
+  }
+}
+
 template <typename T, typename TV, bool L_IS_M>
 __global__ __launch_bounds__(BS) void k_ch_block(int n, int side, const int* __restrict__ col,
                                                  const TV* __restrict__ Lv,
@@ -1050,6 +1367,52 @@ void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const
                      b, cc, x);
 }
 
+template <typename T>
+bool tile_fits(int mode, int side, int steps) {
+  const int H = (mode == TILE_ZERO) ? steps - 1 : (mode == TILE_DOWN ? steps + 1 : steps);
+  if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > TILE_HMAX) return false;
+  if (side < tile_side<T>(side) + TILE_HMAX) return false;  // one wrap reaches every halo row
+  return mode != TILE_DOWN || side % 2 == 0;
+}
+
+template <typename T, int TT>
+void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s) {
+  const int nt = (a.side + TT - 1) / TT;
+  const dim3 g(nt * nt), b(TILE_THREADS);
+  if (mode == TILE_ZERO) hipLaunchKernelGGL((k_vtile<T, TILE_ZERO, TT>), g, b, 0, s, a);
+  else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_vtile<T, TILE_DOWN, TT>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_vtile<T, TILE_UP, TT>), g, b, 0, s, a);
+}
+
+template <typename T>
+void vtile(int mode, const TileArgs<T>& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (tile_side<T>(a.side) == 64) {
+      vtile_tt<T, 64>(mode, a, s);
+      return;
+    }
+  }
+  vtile_tt<T, 32>(mode, a, s);
+}
+
+template <typename T>
+bool tail_fits(const int* sides, int nlev) {
+  if (nlev < 1 || nlev > TAIL_MAXLEV) return false;
+  size_t rows = 0;
+  for (int t = 0; t < nlev; ++t) {
+    if (sides[t] < 3) return false;
+    if (t + 1 < nlev && (sides[t] % 2 != 0 || sides[t + 1] != sides[t] / 2)) return false;
+    rows += size_t(sides[t]) * sides[t];
+  }
+  return size_t(sides[0]) * sides[0] <= size_t(TailCfg<T>::RPT) * TAIL_THREADS &&
+         3 * rows * sizeof(T) <= TAIL_LDS;
+}
+
+template <typename T>
+void vtail(const TailArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_vtail<T, TailCfg<T>::RPT>), dim3(1), dim3(TAIL_THREADS), 0, s, a);
+}
+
 template <typename T, typename TV>
 void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
               T alpha, T beta, T* y, hipStream_t s, LaunchEv ev) {
@@ -1287,6 +1650,14 @@ template void coarse_cheb<double, double>(const DSell&, const double*, const dou
                                           hipStream_t);
 template void coarse_cheb<float, float>(const DSell&, const float*, const float*, const float*,
                                         const ChebCoef<float>&, float*, hipStream_t);
+template bool tile_fits<double>(int, int, int);
+template bool tile_fits<float>(int, int, int);
+template void vtile<double>(int, const TileArgs<double>&, hipStream_t);
+template void vtile<float>(int, const TileArgs<float>&, hipStream_t);
+template bool tail_fits<double>(const int*, int);
+template bool tail_fits<float>(const int*, int);
+template void vtail<double>(const TailArgs<double>&, hipStream_t);
+template void vtail<float>(const TailArgs<float>&, hipStream_t);
 template void ch_block<double, double>(const DSell&, const double*, const double*, const double*,
                                        double, double, const double*, double, double, double*,
                                        hipStream_t, LaunchEv);

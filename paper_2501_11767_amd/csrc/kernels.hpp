@@ -69,6 +69,66 @@ template <typename T, typename TV>
 void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const ChebCoef<T>& cc,
                  T* x, hipStream_t s);
 
+// The small levels of a V-cycle in one workgroup (periodic P1 levels only):
+// levels 0..nlev-1 of `a` are consecutive levels of the hierarchy, the last one
+// the cut level.  Each smoothing level takes `pre` Chebyshev steps from zero,
+// restricts its residual (R = P^T), recurses, adds the P1 interpolation of the
+// coarse iterate and takes `post` steps; the cut level takes coarse.steps steps
+// from zero.  x = V b on the first level.  Every level's vectors live in LDS:
+// tail_fits() says whether a chain of levels fits.
+constexpr int TAIL_MAXLEV = 8;
+constexpr int TAIL_MAXSM = 32;
+constexpr int TAIL_THREADS = 1024;
+template <typename T>
+struct TailArgs {
+  int nlev;
+  int side[TAIL_MAXLEV];
+  const T* val[TAIL_MAXLEV];
+  const T* dinv[TAIL_MAXLEV];
+  const T* b;
+  T* x;
+  int pre, post;
+  T pre_c1[TAIL_MAXSM], pre_c2[TAIL_MAXSM];
+  T post_c1[TAIL_MAXSM], post_c2[TAIL_MAXSM];
+  ChebCoef<T> coarse;
+};
+// sides: the chain's level sides (each even side halves into the next).
+template <typename T>
+bool tail_fits(const int* sides, int nlev);
+template <typename T>
+void vtail(const TailArgs<T>& a, hipStream_t s);
+
+// Tiled multigrid kernels on one periodic P1 level: one workgroup per square
+// tile of the level's grid plus a halo of H rings, every dependent step of the
+// level run in LDS (the halo is recomputed by both tiles that touch it).
+//   TILE_ZERO: `steps` Chebyshev steps from x = 0 (H = steps - 1); x written.
+//   TILE_DOWN: `steps` pre-smoothing steps from zero, the residual and its
+//              restriction (H = steps + 1); x (pre-smoothed) and bc (coarse
+//              right-hand side, side/2 grid) written.
+//   TILE_UP:   x' = xin + P e (e on the side/2 grid), then `steps`
+//              post-smoothing steps (H = steps); x written (x != xin).
+// c1/c2: the Chebyshev coefficients of the steps (c1[0] unused).
+enum TileMode { TILE_ZERO = 0, TILE_DOWN = 1, TILE_UP = 2 };
+constexpr int TILE_MAXSTEPS = 5;
+template <typename T>
+struct TileArgs {
+  int side = 0, steps = 0;
+  const T* val = nullptr;
+  const T* dinv = nullptr;
+  const T* b = nullptr;
+  const T* xin = nullptr;
+  const T* e = nullptr;
+  T* x = nullptr;
+  T* bc = nullptr;
+  T c1[TILE_MAXSTEPS] = {};
+  T c2[TILE_MAXSTEPS] = {};
+};
+// Whether a level of this side takes the tiled kernel of `mode` with `steps`.
+template <typename T>
+bool tile_fits(int mode, int side, int steps);
+template <typename T>
+void vtile(int mode, const TileArgs<T>& a, hipStream_t s);
+
 // CH block on [x1; x2] with value streams L = M + tau C, K, M (uniform P1):
 //   y1 = alpha (L x1 + c12 K x2) + beta y1,  y2 = alpha (c12 K x1 + c22 M x2) + beta y2.
 template <typename T, typename TV>
