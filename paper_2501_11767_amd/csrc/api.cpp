@@ -724,39 +724,43 @@ void ch_precond_t(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_so
   mg_solve<T>(c, &Level::X, tmp2, z + N, o, s);
 }
 
-int precond(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, double* z,
-            hipStream_t s) {
+// Preconditioner of a block: z = P^{-1} r.  When inv is given, r is first
+// scaled in place by inv[0] (fused with the FP32 conversion in mixed
+// precision): the Krylov basis vector is normalised on its way in.
+int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, double* r, const double* inv,
+                   double* z, hipStream_t s) {
   const int N = c->N;
-  if (block == CHNS_BLOCK_CH) {
-    if (o.precision == CHNS_F64) {
-      ch_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
-    } else {
-      convert<double, float>(2 * int64_t(N), r, c->r32, s);
-      ch_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
-      convert<float, double>(2 * int64_t(N), c->z32, z, s);
-    }
-  } else if (block == CHNS_BLOCK_AC) {
-    if (c->mesh.model == CHNS_MODEL_CH) return fail(c, CHNS_EUNSUPPORTED, "model has no AC block");
-    if (o.precision == CHNS_F64) {
-      mg_solve<double>(c, &Level::AC, r, z, o, s);
-    } else {
-      convert<double, float>(N, r, c->r32, s);
-      mg_solve<float>(c, &Level::AC, c->r32, c->z32, o, s);
-      convert<float, double>(N, c->z32, z, s);
-    }
-  } else if (block == CHNS_BLOCK_NS && c->ternary) {
-    if (o.precision == CHNS_F64) {
-      ns_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
-    } else {
-      convert<double, float>(9 * int64_t(N), r, c->r32, s);
-      ns_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
-      convert<float, double>(9 * int64_t(N), c->z32, z, s);
-    }
+  int64_t n = 0;
+  if (block == CHNS_BLOCK_CH) n = 2 * int64_t(N);
+  else if (block == CHNS_BLOCK_AC && c->mesh.model != CHNS_MODEL_CH) n = N;
+  else if (block == CHNS_BLOCK_NS && c->ternary) n = 9 * int64_t(N);
+  else return fail(c, CHNS_EUNSUPPORTED, "block not available");
+  const bool f64 = o.precision == CHNS_F64;
+  if (f64) {
+    if (inv) scale_by_inv(n, r, inv, r, s);
+  } else if (inv) {
+    convert_scaled(n, r, inv, c->r32, s);
   } else {
-    return fail(c, CHNS_EUNSUPPORTED, "block not available");
+    convert<double, float>(n, r, c->r32, s);
   }
+  if (block == CHNS_BLOCK_CH) {
+    if (f64) ch_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
+    else ch_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
+  } else if (block == CHNS_BLOCK_AC) {
+    if (f64) mg_solve<double>(c, &Level::AC, r, z, o, s);
+    else mg_solve<float>(c, &Level::AC, c->r32, c->z32, o, s);
+  } else {
+    if (f64) ns_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
+    else ns_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
+  }
+  if (!f64) convert<float, double>(n, c->z32, z, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
+}
+
+int precond(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, double* z,
+            hipStream_t s) {
+  return precond_scaled(c, block, o, const_cast<double*>(r), nullptr, z, s);  // r not written
 }
 
 int64_t block_size(chns_ctx* c, int block) {
@@ -810,6 +814,19 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   // large block sit a multiple of 16 MiB apart and the loads of one row of all
   // of them fall into the same HBM channel
   const int64_t ld = n + KRYLOV_PAD;
+  DcgsState st;
+  st.part = K.part;
+  st.red = K.red;
+  st.nrm_part = K.nrm_part;
+  st.H = K.H;
+  st.HR = K.HR;
+  st.cs = K.cs;
+  st.sn = K.sn;
+  st.g = K.g;
+  st.gp = K.gp;
+  st.coef = K.coef;
+  st.scal = K.scal;
+  st.m = m;
   chns_solve_info inf{};
   HIPCHK(c, hipEventRecord(c->ev0, s));
   norm_partial(n, b, K.nrm_part, s);
@@ -848,22 +865,19 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       double* vj = K.V + j * ld;
       double* vn = K.V + (j + 1) * ld;
       double* zj = K.Z + j * ld;
-      TRY(precond(c, block, o, vj, zj, s));
+      TRY(precond_scaled(c, block, o, vj, j > 0 ? K.scal + 1 : nullptr, zj, s));
       TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
       // DCGS2: one dot pass and one update pass over the basis (the previous
-      // vector's reorthogonalisation rides along with w's projection)
+      // vector's reorthogonalisation rides along with w's projection); the
+      // end-of-step scalars land in the pinned host slot, and w is scaled by
+      // 1/|w| in the input stage of the next step's preconditioner
       const int kk0 = j < 16 ? j : 16;
       timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (kk0 + 2), s,
-            [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, K.part, s, ev); });
-      slot_reduce(dcgs_dot_blocks(n), 2 * j + 3, K.part, K.red, s);
-      dcgs_coef(j, m, K.red, K.H, K.coef, s);
-      timed(c, CHNS_KERNEL_DCGS_UPDATE, 8.0 * n * (j + 2 + (j > 0 ? 1 : 0) + 1), s,
-            [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, K.coef, K.nrm_part, s, ev); });
-      dcgs_finish(nblk, K.nrm_part, j, m, K.H, K.HR, K.cs, K.sn, K.g, K.gp, K.scal, s);
-      scale_by_inv(n, vn, K.scal + 1, vn, s);
-      HIPCHK(c, hipGetLastError());
+            [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, st, s, ev); });
       double* slot = K.host + 4 * (j & 1);
-      HIPCHK(c, hipMemcpyAsync(slot, K.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      timed(c, CHNS_KERNEL_DCGS_UPDATE, 8.0 * n * (j + 2 + (j > 0 ? 1 : 0) + 1), s,
+            [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, st, slot, s, ev); });
+      HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipEventRecord(K.done[j & 1], s));
       if (j > 0) {
         HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));

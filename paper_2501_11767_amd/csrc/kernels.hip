@@ -589,6 +589,18 @@ __global__ __launch_bounds__(BS) void k_convert(int64_t n, const TI* __restrict_
   if (i < n) y[i] = TO(x[i]);
 }
 
+// x <- x * inv[0] (written back) and y = float(x * inv[0]).
+__global__ __launch_bounds__(BS) void k_convert_scaled(int64_t n, double* __restrict__ x,
+                                                       const double* __restrict__ inv,
+                                                       float* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) {
+    const double v = x[i] * inv[0];
+    x[i] = v;
+    y[i] = float(v);
+  }
+}
+
 __global__ __launch_bounds__(BS) void k_scale_by_inv(int64_t n, const double* __restrict__ x,
                                                      const double* __restrict__ inv,
                                                      double* __restrict__ y) {
@@ -604,6 +616,53 @@ __global__ __launch_bounds__(BS) void k_scale_by_inv(int64_t n, const double* __
 // of the new vector w = V_{j+1}, one pass applies both updates.
 
 constexpr int DG = 16;  // basis vectors per group of the dot pass
+
+// One workgroup per slot: red[k] = sum of slot k's nblk partials
+// (part[k * nblk + b]), in a fixed order.
+__global__ __launch_bounds__(BS) void k_slot_reduce(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ red) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += BS) a += part[int64_t(k) * nblk + b];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) red[k] = a;
+}
+
+// Coefficients of step j from the reduced dots (one wavefront).  j >= 1:
+// vt = sum c_i V_i + r v_j with r = sqrt(vt.vt - |c|^2); column j-1 of the
+// raw Hessenberg H (whose last entry multiplied vt) becomes h_i += h_j c_i,
+// h_j *= r.  Projection of w on the final basis: a_i = V_i . w (i < j),
+// b = (vt . w - c . a) / r; so w' = w - sum (a_i - b c_i / r) V_i - (b / r) vt
+// and v_j = (vt - sum c_i V_i) / r.  coef: [0, j) c_i, [j, 2j+1) the w
+// coefficients (last one multiplies vt), 2j+1: 1/r.  j < 64.
+__global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double* __restrict__ red,
+                                                  double* __restrict__ H, double* __restrict__ coef) {
+  const int t = threadIdx.x, ld = m + 1;
+  const double c = t < j ? red[t] : 0.0;
+  const double a = t < j ? red[j + t] : 0.0;
+  const double hj = j > 0 ? H[int64_t(j - 1) * ld + j] : 0.0;
+  const double cc = wave_sum(c * c), ca = wave_sum(c * a);
+  const double nu = red[2 * j], tw = red[2 * j + 1];
+  const double r = j > 0 ? sqrt(fmax(nu - cc, 0.0)) : 1.0;
+  const double inv = r > 0.0 ? 1.0 / r : 0.0;
+  const double b = (tw - ca) * inv;
+  if (j > 0 && t <= j) {
+    double* hp = H + int64_t(j - 1) * ld;
+    hp[t] = (t < j) ? hp[t] + hj * c : hj * r;
+  }
+  double* h = H + int64_t(j) * ld;
+  if (t < j) {
+    h[t] = a;
+    coef[t] = c;
+    coef[j + t] = a - b * c * inv;
+  }
+  if (t == 0) {
+    h[j] = b;
+    coef[2 * j] = b * inv;
+    coef[2 * j + 1] = inv;
+  }
+}
 
 // Dots of KK basis vectors V_g0 .. V_{g0+KK-1} against vt and w, and with
 // LAST also vt . vt, vt . w, w . w.  Slots (per block partial, stride
@@ -656,103 +715,6 @@ __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __res
   }
 }
 
-// One workgroup per slot: red[i] = sum of the slot's partials.
-__global__ __launch_bounds__(BS) void k_slot_reduce(int nblk, const double* __restrict__ part,
-                                                    double* __restrict__ red) {
-  __shared__ double sh[4];
-  const int i = blockIdx.x;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += BS) s += part[int64_t(i) * nblk + b];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) red[i] = s;
-}
-
-// Coefficients of step j (one thread).  j >= 1: vt = sum c_i V_i + r v_j with
-// r = sqrt(vt.vt - |c|^2); column j-1 of the raw Hessenberg H (whose last entry
-// multiplied vt) becomes h_i += h_j c_i, h_j *= r.  Projection of w on the
-// final basis: a_i = V_i . w (i < j), b = (vt . w - c . a) / r; so
-// w' = w - sum (a_i - b c_i / r) V_i - (b / r) vt and v_j = (vt - sum c_i V_i) / r.
-// coef: [0, j) c_i, [j, 2j+1) the w coefficients (last one multiplies vt), 2j+1: 1/r.
-__global__ void k_dcgs_coef(int j, int m, const double* __restrict__ red, double* __restrict__ H,
-                            double* __restrict__ coef) {
-  if (threadIdx.x != 0) return;
-  const int ld = m + 1;
-  const double* c = red;
-  const double* a = red + j;
-  const double nu = red[2 * j], tw = red[2 * j + 1];
-  double r = 1.0, ca = 0.0;
-  if (j > 0) {
-    double cc = 0.0;
-    for (int i = 0; i < j; ++i) {
-      cc += c[i] * c[i];
-      ca += c[i] * a[i];
-    }
-    r = sqrt(fmax(nu - cc, 0.0));
-    double* hp = H + int64_t(j - 1) * ld;
-    const double hj = hp[j];
-    for (int i = 0; i < j; ++i) hp[i] += hj * c[i];
-    hp[j] = hj * r;
-  }
-  const double inv = r > 0.0 ? 1.0 / r : 0.0;
-  const double b = (tw - ca) * inv;
-  double* h = H + int64_t(j) * ld;
-  for (int i = 0; i < j; ++i) {
-    h[i] = a[i];
-    coef[i] = c[i];
-    coef[j + i] = a[i] - b * c[i] * inv;
-  }
-  h[j] = b;
-  coef[2 * j] = b * inv;
-  coef[2 * j + 1] = inv;
-}
-
-// w <- w - sum_{i<j} coef[j+i] V_i - coef[2j] vt; vt <- (vt - sum_{i<j} coef[i] V_i) / r
-// (j > 0); per-block partials of |w'|^2.
-__global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restrict__ V, int64_t ld, int j,
-                                                    const double* __restrict__ coef,
-                                                    double* __restrict__ nrm_part) {
-  __shared__ double cs[2 * 64 + 2];
-  __shared__ double sh[4];
-  for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cs[i] = coef[i];
-  __syncthreads();
-  double* vt = V + int64_t(j) * ld;
-  double* w = V + int64_t(j + 1) * ld;
-  const double inv = cs[2 * j + 1], wt = cs[2 * j];
-  double acc = 0.0;
-  const int64_t stride = int64_t(gridDim.x) * BS;
-  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
-    const double t = vt[r];
-    double wn = w[r] - wt * t, vn = t;
-    int i = 0;
-    for (; i + 8 <= j; i += 8) {  // groups of 8: all loads issued before the FMAs
-      double v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = V[(i + q) * ld + r];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        vn -= cs[i + q] * v[q];
-        wn -= cs[j + i + q] * v[q];
-      }
-    }
-    for (; i < j; ++i) {
-      const double v = V[i * ld + r];
-      vn -= cs[i] * v;
-      wn -= cs[j + i] * v;
-    }
-    if (j > 0) vt[r] = vn * inv;
-    w[r] = wn;
-    acc += wn * wn;
-  }
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) nrm_part[blockIdx.x] = s;
-}
-
-__device__ double sum_partials_wave(int nblk, const double* part) {
-  const int lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int b = lane; b < nblk; b += 64) s += part[b];
-  return wave_sum(s);
-}
 
 __device__ __forceinline__ void givens(double a, double b, double& c, double& s) {
   if (b == 0.0) {
@@ -769,54 +731,137 @@ __device__ __forceinline__ void givens(double a, double b, double& c, double& s)
   }
 }
 
-// End of step j: h_{j+1,j} = |w'| (provisional until the next step corrects
-// it); column j-1 is final now: rotate it into HR, fix rotation j-1 and the
-// right-hand side g.  Column j gets a provisional rotation: HR column j and gp
-// (g with the provisional rotation) serve the residual estimate and, if the
-// cycle ends here, the least-squares solve.  scal = (estimate, 1/|w'|, |w'|).
-__global__ void k_dcgs_finish(int nblk, const double* __restrict__ nrm_part, int j, int m,
-                              double* __restrict__ H, double* __restrict__ HR,
-                              double* __restrict__ cs, double* __restrict__ sn,
-                              double* __restrict__ g, double* __restrict__ gp,
-                              double* __restrict__ scal) {
-  const double nrm = sqrt(sum_partials_wave(nblk, nrm_part));
-  if (threadIdx.x != 0) return;
-  const int ld = m + 1;
-  H[int64_t(j) * ld + j + 1] = nrm;
-  auto rotate = [&](int col, int upto) {  // HR[col] = rotations 0..upto-1 applied to H[col]
-    const double* h = H + int64_t(col) * ld;
-    double* hr = HR + int64_t(col) * ld;
-    for (int i = 0; i <= col + 1; ++i) hr[i] = h[i];
-    for (int i = 0; i < upto; ++i) {
-      const double a = hr[i], b = hr[i + 1];
-      hr[i] = cs[i] * a + sn[i] * b;
-      hr[i + 1] = -sn[i] * a + cs[i] * b;
-    }
-  };
-  if (j > 0) {
-    rotate(j - 1, j - 1);
-    double* hr = HR + int64_t(j - 1) * ld;
-    double c, s;
-    givens(hr[j - 1], hr[j], c, s);
-    cs[j - 1] = c;
-    sn[j - 1] = s;
-    hr[j - 1] = c * hr[j - 1] + s * hr[j];
-    hr[j] = 0.0;
-    g[j] = -s * g[j - 1];
-    g[j - 1] = c * g[j - 1];
+// Rotations 0..upto-1 applied in order to x[0..upto] (x[upto+1..] untouched):
+// rotation i maps (x_i, x_{i+1}) to (c_i x_i + s_i x_{i+1}, -s_i x_i + c_i x_{i+1}).
+__device__ __forceinline__ void apply_rotations(double* x, int upto, const double* c, const double* s) {
+  double carry = x[0];
+  for (int i = 0; i < upto; ++i) {
+    const double b = x[i + 1];
+    x[i] = c[i] * carry + s[i] * b;
+    carry = -s[i] * carry + c[i] * b;
   }
-  rotate(j, j);
-  double* hr = HR + int64_t(j) * ld;
-  double c, s;
-  givens(hr[j], hr[j + 1], c, s);
-  hr[j] = c * hr[j] + s * hr[j + 1];
-  hr[j + 1] = 0.0;
-  for (int i = 0; i < j; ++i) gp[i] = g[i];
-  gp[j] = c * g[j];
-  gp[j + 1] = -s * g[j];
-  scal[0] = fabs(gp[j + 1]);
-  scal[1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  scal[2] = nrm;
+  x[upto] = carry;
+}
+
+// End of step j, by one workgroup: h_{j+1,j} = |w'| (provisional until the
+// next step corrects it); column j-1 is final now: rotate it into HR, fix
+// rotation j-1 and the right-hand side g.  Column j gets a provisional
+// rotation: HR column j and gp (g with the provisional rotation) serve the
+// residual estimate and, if the cycle ends here, the least-squares solve.
+// scal = (estimate, 1/|w'|, |w'|), also written to `host` (pinned host memory)
+// when given.  The columns, rotations and g are staged in LDS (their loads in
+// flight with those of the norm partials) so that the serial rotation chain
+// runs at LDS latency.
+__global__ __launch_bounds__(BS) void k_dcgs_finish(int nblk, const double* __restrict__ nrm_part, int j,
+                                                    int m, double* __restrict__ H, double* __restrict__ HR,
+                                                    double* __restrict__ cs, double* __restrict__ sn,
+                                                    double* __restrict__ g, double* __restrict__ gp,
+                                                    double* __restrict__ scal, double* __restrict__ host) {
+  __shared__ double hp[66], hc[66], cs_s[64], sn_s[64], g_s[66], res[3];
+  __shared__ double sh[4];
+  const int ld = m + 1, t = threadIdx.x;
+  if (t <= j) hc[t] = H[int64_t(j) * ld + t];
+  if (j > 0 && t <= j) hp[t] = H[int64_t(j - 1) * ld + t];
+  if (t + 1 < j) {
+    cs_s[t] = cs[t];
+    sn_s[t] = sn[t];
+  }
+  if (t <= j) g_s[t] = g[t];
+  double a = 0.0;
+  for (int b = t; b < nblk; b += BS) a += nrm_part[b];
+  const double nrm = sqrt(block_sum(a, sh));  // valid in thread 0, which alone uses it
+  if (t == 0) {
+    hc[j + 1] = nrm;
+    if (j > 0) {
+      apply_rotations(hp, j - 1, cs_s, sn_s);
+      double c, s;
+      givens(hp[j - 1], hp[j], c, s);
+      cs_s[j - 1] = c;
+      sn_s[j - 1] = s;
+      hp[j - 1] = c * hp[j - 1] + s * hp[j];
+      hp[j] = 0.0;
+      g_s[j] = -s * g_s[j - 1];
+      g_s[j - 1] = c * g_s[j - 1];
+    }
+    apply_rotations(hc, j, cs_s, sn_s);
+    double c, s;
+    givens(hc[j], hc[j + 1], c, s);
+    hc[j] = c * hc[j] + s * hc[j + 1];
+    hc[j + 1] = 0.0;
+    res[0] = c * g_s[j];
+    res[1] = -s * g_s[j];
+    res[2] = nrm;
+  }
+  __syncthreads();
+  const double nr = res[2];
+  if (t == 0) H[int64_t(j) * ld + j + 1] = nr;
+  if (t <= j + 1) HR[int64_t(j) * ld + t] = hc[t];
+  if (j > 0 && t <= j) HR[int64_t(j - 1) * ld + t] = hp[t];
+  if (j > 0 && t == 0) {
+    cs[j - 1] = cs_s[j - 1];
+    sn[j - 1] = sn_s[j - 1];
+    g[j - 1] = g_s[j - 1];
+    g[j] = g_s[j];
+  }
+  if (t < j) gp[t] = g_s[t];
+  if (t == 0) {
+    gp[j] = res[0];
+    gp[j + 1] = res[1];
+    const double sv[3] = {fabs(res[1]), nr > 0.0 ? 1.0 / nr : 0.0, nr};
+    for (int i = 0; i < 3; ++i) scal[i] = sv[i];
+    if (host) {
+      for (int i = 0; i < 3; ++i) host[i] = sv[i];
+      __threadfence_system();
+    }
+  }
+}
+
+// w <- w - sum_{i<j} coef[j+i] V_i - coef[2j] vt; vt <- (vt - sum_{i<j} coef[i] V_i) / r
+// (j > 0); per-block partials of |w'|^2.
+__global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restrict__ V, int64_t ld, int j,
+                                                    const double* __restrict__ coef,
+                                                    double* __restrict__ nrm_part) {
+  __shared__ double cs_l[2 * 64 + 2];
+  __shared__ double sh[4];
+  for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cs_l[i] = coef[i];
+  __syncthreads();
+  double* vt = V + int64_t(j) * ld;
+  double* w = V + int64_t(j + 1) * ld;
+  const double inv = cs_l[2 * j + 1], wt = cs_l[2 * j];
+  double acc = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
+    const double t = vt[r];
+    double wn = w[r] - wt * t, vn = t;
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {  // groups of 8: all loads issued before the FMAs
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = V[(i + q) * ld + r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        vn -= cs_l[i + q] * v[q];
+        wn -= cs_l[j + i + q] * v[q];
+      }
+    }
+    for (; i < j; ++i) {
+      const double v = V[i * ld + r];
+      vn -= cs_l[i] * v;
+      wn -= cs_l[j + i] * v;
+    }
+    if (j > 0) vt[r] = vn * inv;
+    w[r] = wn;
+    acc += wn * wn;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) nrm_part[blockIdx.x] = s;
+}
+
+__device__ double sum_partials_wave(int nblk, const double* part) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += part[b];
+  return wave_sum(s);
 }
 
 __global__ void k_lsq_solve(int k, int m, const double* __restrict__ H, const double* __restrict__ g,
@@ -1435,6 +1480,10 @@ void convert(int64_t n, const TI* x, TO* y, hipStream_t s) {
   hipLaunchKernelGGL((k_convert<TI, TO>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, y);
 }
 
+void convert_scaled(int64_t n, double* x, const double* inv, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_scaled, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y);
+}
+
 void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_by_inv, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y);
 }
@@ -1447,17 +1496,17 @@ int reduce_blocks(int64_t n) {
 int dcgs_dot_blocks(int64_t n) { return reduce_blocks(n); }
 
 template <int KK, bool LAST>
-static void launch_dots(int64_t n, const double* V, int64_t ld, int j, int g0, double* part, hipStream_t s,
-                        LaunchEv ev) {
-  LAUNCH_EV(ev, (k_dcgs_dots<KK, LAST>), dim3(dcgs_dot_blocks(n)), dim3(BS), 0, s, n, V, ld, j, g0, part);
+static void launch_dots(int64_t n, const double* V, int64_t ld, int j, int g0, const DcgsState& st,
+                        hipStream_t s, LaunchEv ev) {
+  LAUNCH_EV(ev, (k_dcgs_dots<KK, LAST>), dim3(dcgs_dot_blocks(n)), dim3(BS), 0, s, n, V, ld, j, g0, st.part);
 }
 
 template <bool LAST>
-static void launch_dots_kk(int kk, int64_t n, const double* V, int64_t ld, int j, int g0, double* part,
-                           hipStream_t s, LaunchEv ev) {
+static void launch_dots_kk(int kk, int64_t n, const double* V, int64_t ld, int j, int g0,
+                           const DcgsState& st, hipStream_t s, LaunchEv ev) {
   switch (kk) {
 #define CHNS_DOTS_CASE(K) \
-  case K: launch_dots<K, LAST>(n, V, ld, j, g0, part, s, ev); break;
+  case K: launch_dots<K, LAST>(n, V, ld, j, g0, st, s, ev); break;
     CHNS_DOTS_CASE(0) CHNS_DOTS_CASE(1) CHNS_DOTS_CASE(2) CHNS_DOTS_CASE(3) CHNS_DOTS_CASE(4)
     CHNS_DOTS_CASE(5) CHNS_DOTS_CASE(6) CHNS_DOTS_CASE(7) CHNS_DOTS_CASE(8) CHNS_DOTS_CASE(9)
     CHNS_DOTS_CASE(10) CHNS_DOTS_CASE(11) CHNS_DOTS_CASE(12) CHNS_DOTS_CASE(13) CHNS_DOTS_CASE(14)
@@ -1468,32 +1517,22 @@ static void launch_dots_kk(int kk, int64_t n, const double* V, int64_t ld, int j
 }
 
 // Full groups of DG vectors, then the remainder group with vt . vt, vt . w,
-// w . w (one launch when j < DG).
-void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s,
+// w . w (one launch when j < DG), then the slot sums and the coefficients.
+void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
                LaunchEv ev) {
   const int full = j / DG, rem = j - full * DG;
   for (int g = 0; g < full; ++g)
-    launch_dots_kk<false>(DG, n, V, ld, j, g * DG, part, s, g == 0 ? ev : LaunchEv{});
-  launch_dots_kk<true>(rem, n, V, ld, j, full * DG, part, s, full == 0 ? ev : LaunchEv{});
+    launch_dots_kk<false>(DG, n, V, ld, j, g * DG, st, s, g == 0 ? ev : LaunchEv{});
+  launch_dots_kk<true>(rem, n, V, ld, j, full * DG, st, s, full == 0 ? ev : LaunchEv{});
+  hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(n), st.part, st.red);
+  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, st.m, st.red, st.H, st.coef);
 }
 
-void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s) {
-  hipLaunchKernelGGL(k_slot_reduce, dim3(nslots), dim3(BS), 0, s, nblk, part, red);
-}
-
-void dcgs_coef(int j, int m, const double* red, double* H, double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, m, red, H, coef);
-}
-
-void dcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, double* nrm_part,
-                 hipStream_t s, LaunchEv ev) {
-  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, coef, nrm_part);
-}
-
-void dcgs_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* HR, double* cs,
-                 double* sn, double* g, double* gp, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(64), 0, s, nblk, nrm_part, j, m, H, HR, cs, sn, g, gp,
-                     scal);
+void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, hipStream_t s,
+                 LaunchEv ev) {
+  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, st.coef, st.nrm_part);
+  hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(BS), 0, s, reduce_blocks(n), st.nrm_part, j, st.m, st.H,
+                     st.HR, st.cs, st.sn, st.g, st.gp, st.scal, host);
 }
 
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {

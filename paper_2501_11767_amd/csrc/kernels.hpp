@@ -141,6 +141,8 @@ void axpby(int64_t n, T a, const T* x, T b, T* y, hipStream_t s);
 template <typename TI, typename TO>
 void convert(int64_t n, const TI* x, TO* y, hipStream_t s);
 void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipStream_t s);
+// x <- x * inv[0] in place and y = float(x) (input stage of an FP32 preconditioner).
+void convert_scaled(int64_t n, double* x, const double* inv, float* y, hipStream_t s);
 
 // Krylov reductions (FP64).  Partial sums per workgroup go to `part`
 // (reduce_blocks(n) * cols doubles); reduce_* finish them deterministically.
@@ -149,22 +151,30 @@ int reduce_blocks(int64_t n);
 // step j, basis V (columns of length n, stride ld): V_j holds the vector used
 // for this step (orthogonalised once), V_{j+1} the new vector w = A z_j.
 // dots: partials of V_i . V_j, V_i . w (i < j), V_j . V_j, V_j . w, w . w
-// (2j + 3 slots of dcgs_dot_blocks(n) partials); slot_reduce sums them.
+// (2j + 3 slots of dcgs_dot_blocks(n) partials).
 int dcgs_dot_blocks(int64_t n);
-void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, hipStream_t s,
+// Device state of one FGMRES cycle used by the two passes: slot partials
+// (2j + 3 slots of dcgs_dot_blocks(n)) and their sums, |w|^2 partials
+// (reduce_blocks(n)), raw Hessenberg H and its rotated form HR (ld m + 1),
+// rotations, g, gp, coefficients and scal.
+struct DcgsState {
+  double *part = nullptr, *red = nullptr, *nrm_part = nullptr;
+  double *H = nullptr, *HR = nullptr, *cs = nullptr, *sn = nullptr;
+  double *g = nullptr, *gp = nullptr, *coef = nullptr, *scal = nullptr;
+  int m = 0;
+};
+// Dot pass, slot sums, then one wavefront that forms the
+// reorthogonalisation coefficients of V_j, the correction of Hessenberg
+// column j-1 and the projection coefficients of w (into coef and H).
+void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
                LaunchEv ev = {});
-void slot_reduce(int nblk, int nslots, const double* part, double* red, hipStream_t s);
-// From the reduced dots: reorthogonalisation coefficients of V_j, correction of
-// Hessenberg column j-1, projection coefficients of w (raw H, ld m+1), into coef.
-void dcgs_coef(int j, int m, const double* red, double* H, double* coef, hipStream_t s);
-// Applies coef: V_j <- its reorthogonalised, normalised form (j > 0),
-// w <- w projected out of the final basis; partials of |w|^2.
-void dcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, double* nrm_part,
-                 hipStream_t s, LaunchEv ev = {});
-// h_{j+1,j} = |w|; final Givens rotation of column j-1 into HR and g; a
-// provisional rotation of column j into HR and gp; scal = (|gp_{j+1}|, 1/|w|, |w|).
-void dcgs_finish(int nblk, const double* nrm_part, int j, int m, double* H, double* HR, double* cs,
-                 double* sn, double* g, double* gp, double* scal, hipStream_t s);
+// Update pass: V_j <- its reorthogonalised, normalised form (j > 0), w <-
+// w projected out of the final basis; then one workgroup sets h_{j+1,j} = |w|,
+// takes the final Givens rotation of column j-1 into HR and g, a provisional
+// rotation of column j into HR and gp, and scal = (|gp_{j+1}|, 1/|w|, |w|)
+// (also into pinned host memory `host` when given; w itself is not scaled).
+void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, hipStream_t s,
+                 LaunchEv ev = {});
 // Least squares back-substitution for k columns: y = R^{-1} g.
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // x += Z y (k columns).
