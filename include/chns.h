@@ -342,6 +342,14 @@ CHNS_API int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream
  * maxiter), typically the largest iteration counts of an eager step plus a
  * margin.  Changing them makes the next graph-mode call capture anew. */
 CHNS_API int chns_batch_set_graph_budget(chns_batch* b, int32_t ch_iters, int32_t ac_iters);
+/* One application of the batched block preconditioner (the paper's block
+ * preconditioners with geometric multigrid, Sec. 3) of block CHNS_BLOCK_CH
+ * (r, z: [phi_all; mu_all], 2 * off[count] doubles) or CHNS_BLOCK_AC (off[count]
+ * doubles) to every instance: z = P^{-1} r with opts' multigrid settings and
+ * precision, the same operator as the one inside chns_batch_timestep.  r and z
+ * are device arrays and must not overlap.  Asynchronous on `stream`. */
+CHNS_API int chns_batch_precond_apply(chns_batch* b, int32_t block, const double* d_r, double* d_z,
+                                      const chns_solve_opts* opts, void* stream);
 CHNS_API const char* chns_batch_last_error(const chns_batch* b);
 
 #ifdef __cplusplus

@@ -34,7 +34,8 @@ EXPORTS = [
     "chns_krylov_solve", "chns_step_rhs", "chns_timestep", "chns_last_error",
     "chns_assemble_transposed", "chns_timestep_adjoint", "chns_ledger_start", "chns_ledger_read",
     "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
-    "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_last_error",
+    "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_precond_apply",
+    "chns_batch_last_error",
 ]
 
 
@@ -114,6 +115,7 @@ def lib():
                                       i32, vp, vp, ct.POINTER(ct.c_double), vp]
     L.chns_batch_tune.argtypes = [vp, ct.c_char_p, vp]
     L.chns_batch_set_graph_budget.argtypes = [vp, i32, i32]
+    L.chns_batch_precond_apply.argtypes = [vp, i32, vp, vp, ct.POINTER(SolveOpts), vp]
     L.chns_batch_last_error.argtypes = [vp]
     L.chns_batch_last_error.restype = ct.c_char_p
     for name in EXPORTS:
@@ -331,6 +333,12 @@ class Batch:
     def set_graph_budget(self, ch_iters, ac_iters):
         """Arnoldi-step budgets of the graph mode (0: maxiter)."""
         self._check(self.L.chns_batch_set_graph_budget(self.h, int(ch_iters), int(ac_iters)))
+
+    def precond(self, block, r, z, opts=None, stream=None):
+        """z = P^{-1} r for every instance (block BLOCK_CH or BLOCK_AC, packed fields)."""
+        o = opts or default_opts()
+        s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+        self._check(self.L.chns_batch_precond_apply(self.h, int(block), _ptr(r), _ptr(z), ct.byref(o), s))
 
     def calibrate_graph(self, info, margin=0.125, extra=2):
         """Graph budgets from an eager step's iteration counts: the largest

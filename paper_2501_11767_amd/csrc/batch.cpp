@@ -82,6 +82,13 @@ struct BLevel {
   double* cc64[NOPS][2] = {};
   float* cc32[NOPS][2] = {};
   double* aco[NOPS][2] = {};  // per-instance a, b of each op
+  // tiled cycle, per op: tiles of the instances smoothing on this level
+  // (down/up pass) and of those cut here, and the instances whose
+  // one-workgroup tail starts on this level (indices into the tail tables)
+  BTile* tdown[NOPS] = {};
+  BTile* tzero[NOPS] = {};
+  int* tail_idx[NOPS] = {};
+  int ntdown[NOPS] = {}, ntzero[NOPS] = {}, ntail[NOPS] = {};
 };
 
 }  // namespace
@@ -113,8 +120,12 @@ struct chns_batch {
   // graph mode: Arnoldi budget per block (0: maxiter) and cached step graphs
   int budget[2] = {0, 0};
   std::vector<GraphEntry> graphs;
-  // current coarse-coefficient opts
+  // current coarse-coefficient opts; whether they run the tiled cycle, and
+  // its tail tables (per op, one entry per instance)
   std::string opts_key;
+  bool tiled = false;
+  TailArgs<float>* tails32[NOPS] = {};
+  TailArgs<double>* tails64[NOPS] = {};
   std::vector<void*> allocs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -327,13 +338,139 @@ std::vector<T> cheb_seq(double lo, double hi, int steps, bool first) {
   return out;
 }
 
+template <typename T> struct BSel;
+template <> struct BSel<double> {
+  static double* v(BLevel& L, int op) { return L.v64[op]; }
+  static double* d(BLevel& L, int op) { return L.d64[op]; }
+  static double* cc(BLevel& L, int op, int w) { return L.cc64[op][w]; }
+  static double* b(BLevel& L) { return L.b64; }
+  static double* x(BLevel& L) { return L.x64; }
+  static double* t(BLevel& L) { return L.t64; }
+  static double* r(BLevel& L) { return L.r64; }
+  static double* dd(BLevel& L) { return L.dd64; }
+  static double* P(BLevel& L) { return L.P64; }
+  static double* R(BLevel& L) { return L.R64; }
+  static double* M(BLevel& L) { return L.M; }
+};
+template <> struct BSel<float> {
+  static float* v(BLevel& L, int op) { return L.v32[op]; }
+  static float* d(BLevel& L, int op) { return L.d32[op]; }
+  static float* cc(BLevel& L, int op, int w) { return L.cc32[op][w]; }
+  static float* b(BLevel& L) { return L.b32; }
+  static float* x(BLevel& L) { return L.x32; }
+  static float* t(BLevel& L) { return L.t32; }
+  static float* r(BLevel& L) { return L.r32; }
+  static float* dd(BLevel& L) { return L.dd32; }
+  static float* P(BLevel& L) { return L.P32; }
+  static float* R(BLevel& L) { return L.R32; }
+  static float* M(BLevel& L) { return L.M32; }
+};
+
+// Tail table entry of instance i from level ts to its cut level c.
+template <typename T>
+TailArgs<T> tail_entry(chns_batch* b, const chns_solve_opts& o, int op, int i, int ts, int c) {
+  TailArgs<T> a{};
+  a.inst = i;
+  a.roff = b->lv[ts].roff[i];
+  a.nlev = c - ts + 1;
+  for (int t = 0; t < a.nlev; ++t) {
+    BLevel& L = b->lv[ts + t];
+    const int64_t r = L.roff[i];
+    a.side[t] = b->n[i] >> (ts + t);
+    a.val[t] = BSel<T>::v(L, op) + r * 7;
+    a.dinv[t] = BSel<T>::d(L, op) + r;
+  }
+  a.pre = o.mg_pre;
+  a.post = o.mg_post;
+  auto p1 = cheb_seq<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre, false);
+  auto p2 = cheb_seq<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre, true);
+  for (int k = 0; k < o.mg_pre; ++k) {
+    a.pre_c1[k] = p1[k];
+    a.pre_c2[k] = p2[k];
+  }
+  auto q1 = cheb_seq<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post, false);
+  auto q2 = cheb_seq<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post, true);
+  for (int k = 0; k < o.mg_post; ++k) {
+    a.post_c1[k] = q1[k];
+    a.post_c2[k] = q2[k];
+  }
+  const double aa = op_a(b->prm[i], op), bb = op_b(b->prm[i], op);
+  const double nl = double(b->n[i] >> c);
+  const double lo = 0.45 / (1.0 + 8.0 * bb * nl * nl / aa);
+  const int steps = std::min(c > 0 ? o.mg_coarse : o.mg_pre + o.mg_post, MAXCHEB);
+  auto c1 = cheb_seq<T>(lo, o.mg_lmax, steps, false);
+  auto c2 = cheb_seq<T>(lo, o.mg_lmax, steps, true);
+  a.coarse.steps = steps;
+  for (int k = 0; k < steps; ++k) {
+    a.coarse.c1[k] = c1[k];
+    a.coarse.c2[k] = c2[k];
+  }
+  return a;
+}
+
+// Tiled cycle of operator op: per instance, the levels above its tail take
+// tiles (down/up on smoothing levels, from-zero steps on its cut level), the
+// tail (one workgroup) takes the rest.  `tiled` turns false when a level does
+// not fit the tiled kernels with these options.
+int prepare_tiles(chns_batch* b, const chns_solve_opts& o, int op, const std::vector<int>& cut, bool& tiled) {
+  const int Lmax = int(b->lv.size());
+  const bool f32 = o.precision == CHNS_MIXED;
+  std::vector<std::vector<BTile>> down(Lmax), zero(Lmax);
+  std::vector<std::vector<int>> tails(Lmax);
+  std::vector<TailArgs<float>> t32(b->count);
+  std::vector<TailArgs<double>> t64(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    const int c = cut[i];
+    int ts = -1;
+    for (int l = 0; l <= c && ts < 0; ++l) {
+      int sides[TAIL_MAXLEV];
+      const int nlev = c - l + 1;
+      if (nlev > TAIL_MAXLEV) continue;
+      for (int t = 0; t < nlev; ++t) sides[t] = b->n[i] >> (l + t);
+      if (f32 ? tail_fits<float>(sides, nlev) : tail_fits<double>(sides, nlev)) ts = l;
+    }
+    const int lend = ts < 0 ? c + 1 : ts;
+    for (int l = 0; l < lend; ++l) {
+      const int side = b->n[i] >> l;
+      const int roff = b->lv[l].roff[i];
+      if (l < c) {
+        if (!btile_fits(TILE_DOWN, side, o.mg_pre) || !btile_fits(TILE_UP, side, o.mg_post)) tiled = false;
+        const int croff = b->lv[l + 1].roff[i];
+        for (int t = 0; t < btile_count(side); ++t) down[l].push_back({i, t, side, roff, croff});
+      } else {
+        const int zs = l > 0 ? o.mg_coarse : o.mg_pre + o.mg_post;
+        if (!btile_fits(TILE_ZERO, side, zs)) tiled = false;
+        for (int t = 0; t < btile_count(side); ++t) zero[l].push_back({i, t, side, roff, 0});
+      }
+    }
+    if (ts >= 0) {
+      tails[ts].push_back(i);
+      t32[i] = tail_entry<float>(b, o, op, i, ts, c);
+      t64[i] = tail_entry<double>(b, o, op, i, ts, c);
+    }
+  }
+  for (int l = 0; l < Lmax; ++l) {
+    BLevel& L = b->lv[l];
+    L.ntdown[op] = int(down[l].size());
+    L.ntzero[op] = int(zero[l].size());
+    L.ntail[op] = int(tails[l].size());
+    BTRY(bupload(b, &L.tdown[op], down[l]));
+    BTRY(bupload(b, &L.tzero[op], zero[l]));
+    BTRY(bupload(b, &L.tail_idx[op], tails[l]));
+  }
+  BTRY(bupload(b, &b->tails32[op], t32));
+  BTRY(bupload(b, &b->tails64[op], t64));
+  return CHNS_OK;
+}
+
 // Masks and coarse Chebyshev coefficients for the given options.
 int prepare_cycles(chns_batch* b, const chns_solve_opts& o) {
   char key[256];
-  std::snprintf(key, sizeof key, "%d/%d/%d/%.17g/%.17g", o.mg_pre, o.mg_post, o.mg_coarse, o.mg_lmax,
-                o.mg_rho_cut);
+  std::snprintf(key, sizeof key, "%d/%d/%d/%.17g/%.17g/%d", o.mg_pre, o.mg_post, o.mg_coarse, o.mg_lmax,
+                o.mg_rho_cut, o.precision);
   if (b->opts_key == key) return CHNS_OK;
   const int Lmax = int(b->lv.size());
+  bool tiled = o.mg_pre <= TAIL_MAXSM && o.mg_post <= TAIL_MAXSM;
   for (int op = 0; op < NOPS; ++op) {
     std::vector<int> cut(b->count);
     for (int i = 0; i < b->count; ++i) {
@@ -386,38 +523,12 @@ int prepare_cycles(chns_batch* b, const chns_solve_opts& o) {
       BTRY(bupload(b, &L.cc32[op][0], c1f));
       BTRY(bupload(b, &L.cc32[op][1], c2f));
     }
+    BTRY(prepare_tiles(b, o, op, cut, tiled));
   }
+  b->tiled = tiled;
   b->opts_key = key;
   return CHNS_OK;
 }
-
-template <typename T> struct BSel;
-template <> struct BSel<double> {
-  static double* v(BLevel& L, int op) { return L.v64[op]; }
-  static double* d(BLevel& L, int op) { return L.d64[op]; }
-  static double* cc(BLevel& L, int op, int w) { return L.cc64[op][w]; }
-  static double* b(BLevel& L) { return L.b64; }
-  static double* x(BLevel& L) { return L.x64; }
-  static double* t(BLevel& L) { return L.t64; }
-  static double* r(BLevel& L) { return L.r64; }
-  static double* dd(BLevel& L) { return L.dd64; }
-  static double* P(BLevel& L) { return L.P64; }
-  static double* R(BLevel& L) { return L.R64; }
-  static double* M(BLevel& L) { return L.M; }
-};
-template <> struct BSel<float> {
-  static float* v(BLevel& L, int op) { return L.v32[op]; }
-  static float* d(BLevel& L, int op) { return L.d32[op]; }
-  static float* cc(BLevel& L, int op, int w) { return L.cc32[op][w]; }
-  static float* b(BLevel& L) { return L.b32; }
-  static float* x(BLevel& L) { return L.x32; }
-  static float* t(BLevel& L) { return L.t32; }
-  static float* r(BLevel& L) { return L.r32; }
-  static float* dd(BLevel& L) { return L.dd32; }
-  static float* P(BLevel& L) { return L.P32; }
-  static float* R(BLevel& L) { return L.R32; }
-  static float* M(BLevel& L) { return L.M32; }
-};
 
 // Batched V-cycle of operator `op` on level l: instances with their cut
 // below l smooth and recurse, instances cut at l take Chebyshev steps.  Rows of
@@ -475,19 +586,88 @@ void bvcycle(chns_batch* b, int op, int l, const T* rhs, T* x, const int* act,
   }
 }
 
+template <typename T> TailArgs<T>* btails(chns_batch* b, int op);
+template <> TailArgs<float>* btails<float>(chns_batch* b, int op) { return b->tails32[op]; }
+template <> TailArgs<double>* btails<double>(chns_batch* b, int op) { return b->tails64[op]; }
+
+template <typename T>
+void set_cheb(BTileLaunch<T>& a, double lmax, int steps) {
+  auto c1 = cheb_seq<T>(lmax / 4.0, lmax, steps, false);
+  auto c2 = cheb_seq<T>(lmax / 4.0, lmax, steps, true);
+  a.steps = steps;
+  for (int k = 0; k < steps && k < TILE_MAXSTEPS; ++k) {
+    a.c1[k] = c1[k];
+    a.c2[k] = c2[k];
+  }
+}
+
+// Tiled batched V-cycle of operator op from level l: on each level one launch
+// per role (the smoothing instances' down pass, the instances cut here, the
+// instances whose one-workgroup tail starts here), the coarser levels, then
+// the smoothing instances' up pass.
+template <typename T>
+void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* act,
+                   const chns_solve_opts& o, hipStream_t s) {
+  BLevel& L = b->lv[l];
+  const T* v = BSel<T>::v(L, op);
+  const T* di = BSel<T>::d(L, op);
+  if (L.ntzero[op] > 0) {
+    BTileLaunch<T> a;
+    a.tiles = L.tzero[op];
+    a.act = act;
+    a.count = b->count;
+    a.steps = l > 0 ? o.mg_coarse : o.mg_pre + o.mg_post;
+    a.val = v;
+    a.dinv = di;
+    a.b = rhs;
+    a.x = x;
+    a.cc1 = BSel<T>::cc(L, op, 0);
+    a.cc2 = BSel<T>::cc(L, op, 1);
+    bvtile<T>(TILE_ZERO, L.ntzero[op], a, s);
+  }
+  if (L.ntail[op] > 0) bvtail<T>(L.ntail[op], btails<T>(b, op), L.tail_idx[op], act, rhs, x, s);
+  if (L.ntdown[op] == 0) return;
+  BLevel& G = b->lv[l + 1];
+  BTileLaunch<T> a;
+  a.tiles = L.tdown[op];
+  a.act = act;
+  a.count = b->count;
+  a.val = v;
+  a.dinv = di;
+  a.b = rhs;
+  set_cheb<T>(a, o.mg_lmax, o.mg_pre);
+  a.x = BSel<T>::t(L);
+  a.bc = BSel<T>::b(G);
+  bvtile<T>(TILE_DOWN, L.ntdown[op], a, s);
+  bvcycle_tiled<T>(b, op, l + 1, BSel<T>::b(G), BSel<T>::x(G), act, o, s);
+  set_cheb<T>(a, o.mg_lmax, o.mg_post);
+  a.xin = BSel<T>::t(L);
+  a.e = BSel<T>::x(G);
+  a.x = x;
+  a.bc = nullptr;
+  bvtile<T>(TILE_UP, L.ntdown[op], a, s);
+}
+
+template <typename T>
+void bcycle(chns_batch* b, int op, const T* rhs, T* x, const int* act, const chns_solve_opts& o,
+            hipStream_t s) {
+  if (b->tiled) bvcycle_tiled<T>(b, op, 0, rhs, x, act, o, s);
+  else bvcycle<T>(b, op, 0, rhs, x, act, o, s);
+}
+
 template <typename T>
 void bprecond_t(chns_batch* b, int block, const T* r, T* z, T* tmp1, T* tmp2, const int* act,
                 const chns_solve_opts& o, hipStream_t s) {
   const int64_t N = b->Ntot;
   BLevel& L0 = b->lv[0];
   if (block == CHNS_BLOCK_CH) {
-    bvcycle<T>(b, 0, 0, r, z, act, o, s);
-    bvcycle<T>(b, 1, 0, r + N, tmp1, act, o, s);
+    bcycle<T>(b, 0, r, z, act, o, s);
+    bcycle<T>(b, 1, r + N, tmp1, act, o, s);
     bstencil<T>(L0.st, BSel<T>::M(L0), 0, tmp1, nullptr, nullptr, nullptr, T(1), T(0), nullptr,
                 nullptr, nullptr, act, tmp2, s);
-    bvcycle<T>(b, 1, 0, tmp2, z + N, act, o, s);
+    bcycle<T>(b, 1, tmp2, z + N, act, o, s);
   } else {
-    bvcycle<T>(b, 2, 0, r, z, act, o, s);
+    bcycle<T>(b, 2, r, z, act, o, s);
   }
 }
 
@@ -739,10 +919,16 @@ void drop_graphs(chns_batch* b) {
   b->graphs.clear();
 }
 
-// Kernel launches of one V-cycle of operator op from level l (mirrors bvcycle).
+// Kernel launches of one V-cycle of operator op from level l (mirrors bvcycle
+// and bvcycle_tiled).
 size_t vcycle_launches(const chns_batch* b, int op, int l, const chns_solve_opts& o) {
   const BLevel& L = b->lv[l];
   size_t c = 0;
+  if (b->tiled) {
+    c += (L.ntzero[op] > 0 ? 1 : 0) + (L.ntail[op] > 0 ? 1 : 0);
+    if (L.ntdown[op] > 0) c += 2 + vcycle_launches(b, op, l + 1, o);
+    return c;
+  }
   if (L.nsmooth[op] > 0) c += size_t(o.mg_pre) + 3 + o.mg_post + vcycle_launches(b, op, l + 1, o);
   if (L.ncoarse[op] > 0) c += size_t(l > 0 ? o.mg_coarse : o.mg_pre + o.mg_post);
   return c;
@@ -1021,6 +1207,21 @@ int chns_batch_set_graph_budget(chns_batch* b, int32_t ch_iters, int32_t ac_iter
     return fail(b, CHNS_EINVAL, "graph budgets must be in 0..4096");
   b->budget[0] = ch_iters;
   b->budget[1] = ac_iters;
+  return CHNS_OK;
+}
+
+int chns_batch_precond_apply(chns_batch* b, int32_t block, const double* d_r, double* d_z,
+                             const chns_solve_opts* opts, void* stream) {
+  if (!b) return CHNS_EINVAL;
+  BTRY(check_bopts(b, opts));
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_AC) return fail(b, CHNS_EINVAL, "block must be CH or AC");
+  if (!d_r || !d_z) return fail(b, CHNS_EINVAL, "r and z must be non-NULL");
+  const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
+  if (d_r < d_z + n && d_z < d_r + n) return fail(b, CHNS_EINVAL, "r and z overlap");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BTRY(prepare_cycles(b, *opts));
+  bprecond(b, block, d_r, d_z, nullptr, *opts, s);
+  BCHK(b, hipGetLastError());
   return CHNS_OK;
 }
 

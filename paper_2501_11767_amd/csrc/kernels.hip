@@ -217,17 +217,17 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const
 // ------------------------------------------------------------------ tiled levels
 
 // Tiled multigrid kernels: tile interior side TT, rows per thread RPT (1024
-// threads cover the tile and a halo of up to TILE_HMAX rings).  A row's 7
-// values, 1/diag, right-hand side and Chebyshev direction are held by its
-// thread for all steps of the launch; the iterates, which the neighbours
-// gather, sit in two LDS buffers.  Large levels take 64 x 64 tiles (less halo
-// traffic), smaller ones 32 x 32 tiles (more workgroups, fewer rows per
-// thread: these levels are latency-bound).
+// threads cover the tile and a halo of up to HMAX rings).  A row's 7 values,
+// 1/diag, right-hand side and Chebyshev direction are held by its thread for
+// all steps of the launch; the iterates, which the neighbours gather, sit in
+// two LDS buffers.  Large levels take 64 x 64 tiles (less halo traffic),
+// smaller ones 32 x 32 tiles (more workgroups, fewer rows per thread: these
+// levels are latency-bound; their halo may reach 8 rings, enough for the
+// Chebyshev steps of a cut level).
 constexpr int TILE_THREADS = 1024;
-constexpr int TILE_HMAX = 4;
-template <int TT> struct TileRpt;
-template <> struct TileRpt<64> { static constexpr int RPT = 6; };
-template <> struct TileRpt<32> { static constexpr int RPT = 2; };
+template <int TT> struct TileCfg;
+template <> struct TileCfg<64> { static constexpr int HMAX = 4, RPT = 6; };
+template <> struct TileCfg<32> { static constexpr int HMAX = 8, RPT = 3; };
 // float levels of at least this side take 64 x 64 tiles (256 or more tiles)
 constexpr int TILE64_MIN_SIDE = 1024;
 template <typename T>
@@ -237,16 +237,24 @@ inline int tile_side(int side) {
 
 __device__ __forceinline__ int wrap_once(int x, int s) { return x < 0 ? x + s : (x >= s ? x - s : x); }
 
+// Halo rings of a tiled launch.
+__host__ __device__ constexpr int tile_halo(int mode, int steps) {
+  return mode == TILE_ZERO ? steps - 1 : (mode == TILE_DOWN ? steps + 1 : steps);
+}
+
+// One tile of a level (tile index `tile` of the side x side grid, row-major
+// over ceil(side / TT)^2 tiles).  Pointers address the level (or, batched,
+// one instance's block of it); c1/c2 the step coefficients.
 template <typename T, int MODE, int TT>
-__global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
-  constexpr int RPT = TileRpt<TT>::RPT;
-  constexpr int WMAX = TT + 2 * TILE_HMAX;
-  __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
-  const int s = a.side, steps = a.steps;
-  const int H = (MODE == TILE_ZERO) ? steps - 1 : (MODE == TILE_DOWN ? steps + 1 : steps);
+__device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict__ val,
+                                           const T* __restrict__ dinv, const T* __restrict__ b,
+                                           const T* __restrict__ xin, const T* __restrict__ e,
+                                           T* __restrict__ x, T* __restrict__ bc, const T* c1s,
+                                           const T* c2s, int tile, T* xa, T* xb) {
+  constexpr int RPT = TileCfg<TT>::RPT;
+  const int H = tile_halo(MODE, steps);
   const int W = TT + 2 * H, R = W * W;
   const int nt = (s + TT - 1) / TT;
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
   const int ty = tile / nt, tx = tile - ty * nt;
   const int i0 = tx * TT - H, j0 = ty * TT - H;
   const int tid = threadIdx.x;
@@ -270,18 +278,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
       own[q] = ring[q] >= H && tx * TT + (ri - H) < s && ty * TT + (rj - H) < s;
       const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
 #pragma unroll
-      for (int k = 0; k < W7; ++k) v[q][k] = a.val[base + k * 64];
-      di[q] = a.dinv[row];
-      bb[q] = a.b[row];
-      if (MODE == TILE_UP) xa[idx] = a.xin[row] + p1_interp(a.e, gi, gj, s >> 1);
+      for (int k = 0; k < W7; ++k) v[q][k] = val[base + k * 64];
+      di[q] = dinv[row];
+      bb[q] = b[row];
+      if (MODE == TILE_UP) xa[idx] = xin[row] + p1_interp(e, gi, gj, s >> 1);
     }
   }
   if (MODE != TILE_UP) {  // first step from zero: x = d = c2 D^{-1} b
+    const T c20 = c2s[0];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int idx = tid + q * TILE_THREADS;
       if (idx < R) {
-        d[q] = a.c2[0] * (di[q] * bb[q]);
+        d[q] = c20 * (di[q] * bb[q]);
         xa[idx] = d[q];
       }
     }
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
   // Chebyshev steps k0.. on shrinking rings: step k is valid at ring >= k - k0 + 1
   const int k0 = (MODE == TILE_UP) ? 0 : 1;
   for (int k = k0; k < steps; ++k) {
-    const T c1 = a.c1[k], c2 = a.c2[k];
+    const T c1 = c1s[k], c2 = c2s[k];
     const int rmin = k - k0 + 1;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -314,7 +323,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q)
-    if (own[q]) a.x[gr[q]] = cur[tid + q * TILE_THREADS];
+    if (own[q]) x[gr[q]] = cur[tid + q * TILE_THREADS];
   if (MODE == TILE_DOWN) {
     // residual on ring >= steps, then R = P^T into the coarse rows whose fine
     // vertex lies in the tile interior
@@ -339,10 +348,40 @@ __global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
         T sm = T(0);
 #pragma unroll
         for (int m = 1; m < W7; ++m) sm += nxt[idx + off[m]];
-        a.bc[cI + nc * cJ] = nxt[idx] + T(0.5) * sm;
+        bc[cI + nc * cJ] = nxt[idx] + T(0.5) * sm;
       }
     }
   }
+}
+
+template <typename T, int MODE, int TT>
+__global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
+  constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
+  __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
+  vtile_body<T, MODE, TT>(a.side, a.steps, a.val, a.dinv, a.b, a.xin, a.e, a.x, a.bc, a.c1, a.c2,
+                          xcd_block(blockIdx.x, gridDim.x), xa, xb);
+}
+
+// Batched: workgroup -> (instance, tile) from the tile list; the launch's
+// pointers address the stacked level, offset per instance by its row offsets
+// (values by 7 slots per row); c1/c2 shared, or per instance ([step][count]).
+template <typename T, int MODE, int TT>
+__global__ __launch_bounds__(TILE_THREADS) void k_bvtile(BTileLaunch<T> a) {
+  constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
+  __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
+  __shared__ T c1s[TILE_MAXSTEPS], c2s[TILE_MAXSTEPS];
+  const BTile t = a.tiles[xcd_block(blockIdx.x, gridDim.x)];
+  if (a.act && !a.act[t.inst]) return;
+  if (threadIdx.x < a.steps) {
+    const int k = threadIdx.x;
+    c1s[k] = a.cc1 ? a.cc1[k * a.count + t.inst] : a.c1[k];
+    c2s[k] = a.cc2 ? a.cc2[k * a.count + t.inst] : a.c2[k];
+  }
+  __syncthreads();
+  const int64_t r = t.roff, rc = t.croff;
+  vtile_body<T, MODE, TT>(t.side, a.steps, a.val + r * W7, a.dinv + r, a.b + r, a.xin ? a.xin + r : nullptr,
+                          a.e ? a.e + rc : nullptr, a.x + r, a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile,
+                          xa, xb);
 }
 
 // ------------------------------------------------------------------ V-cycle tail
@@ -368,7 +407,7 @@ __device__ __forceinline__ int tail_off(const int* side, int t) {
 // dependent steps only a workgroup barrier is needed, where each step of the
 // launch-per-step cycle pays a kernel launch.
 template <typename T, int RPT>
-__global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
+__device__ void vtail_body(const TailArgs<T>* ka, const T* bbase, T* xbase) {
   __shared__ T lds[TAIL_LDS / sizeof(T)];
   __shared__ TailArgs<T> a;
   const int tid = threadIdx.x;
@@ -376,11 +415,14 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
     // the arguments to LDS in one parallel copy: the cycle reads level
     // descriptors and step coefficients at every step, and each scalar load
     // of a fresh argument buffer would wait for memory
-    const unsigned* src = reinterpret_cast<const unsigned*>(&ka);
+    const unsigned* src = reinterpret_cast<const unsigned*>(ka);
     unsigned* dst = reinterpret_cast<unsigned*>(&a);
     for (int i = tid; i < int(sizeof(TailArgs<T>) / 4); i += TAIL_THREADS) dst[i] = src[i];
     __syncthreads();
   }
+  // right-hand side and result of the first level
+  const T* b0 = bbase ? bbase + a.roff : a.b;
+  T* x0 = xbase ? xbase + a.roff : a.x;
   const int last = a.nlev - 1;
   unsigned in_y = 0;  // bit t: level t's iterate is in its second buffer
   T v[RPT][W7], di[RPT], br[RPT], d[RPT];
@@ -452,7 +494,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
     T* X = lds + tail_off(a.side, t);
     T* Y = X + rows;
     T* B = Y + rows;
-    load_level(t, t == 0 ? a.b : B);
+    load_level(t, t == 0 ? b0 : B);
     const bool y = from_zero(rows, X, Y, a.pre_c1, a.pre_c2, a.pre);
     if (y) in_y |= 1u << t;
     const T* cur = y ? Y : X;
@@ -489,7 +531,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
     T* X = lds + tail_off(a.side, last);
     T* Y = X + rows;
     T* B = Y + rows;
-    load_level(last, last == 0 ? a.b : B);
+    load_level(last, last == 0 ? b0 : B);
     if (from_zero(rows, X, Y, a.coarse.c1, a.coarse.c2, a.coarse.steps)) in_y |= 1u << last;
   }
   // up: interpolation of the coarse iterate and post-smoothing
@@ -501,7 +543,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
     const T* E = lds + tail_off(a.side, t + 1) + ((in_y >> (t + 1)) & 1u ? nc * nc : 0);
     T* cur = (in_y >> t) & 1u ? Y : X;
     T* nxt = (cur == X) ? Y : X;
-    load_level(t, t == 0 ? a.b : B);
+    load_level(t, t == 0 ? b0 : B);
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int row = tid + q * TAIL_THREADS;
@@ -527,8 +569,26 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
   {
     const int rows = a.side[0] * a.side[0];
     const T* src = lds + (in_y & 1u ? rows : 0);
-    for (int row = tid; row < rows; row += TAIL_THREADS) a.x[row] = src[row];
+    for (int row = tid; row < rows; row += TAIL_THREADS) x0[row] = src[row];
   }
+}
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(TAIL_THREADS) void k_vtail(TailArgs<T> ka) {
+  vtail_body<T, RPT>(&ka, nullptr, nullptr);
+}
+
+// Batched: workgroup w runs the tail described by list[idx[w]] (skipped when
+// its instance is inactive), with right-hand side and result at row offset
+// roff of bbase and xbase.
+template <typename T, int RPT>
+__global__ __launch_bounds__(TAIL_THREADS) void k_bvtail(const TailArgs<T>* __restrict__ list,
+                                                         const int* __restrict__ idx,
+                                                         const int* __restrict__ act, const T* bbase,
+                                                         T* xbase) {
+  const TailArgs<T>* t = list + idx[blockIdx.x];
+  if (act && !act[t->inst]) return;
+  vtail_body<T, RPT>(t, bbase, xbase);
 }
 
 template <typename T, typename TV, bool L_IS_M>
@@ -1414,9 +1474,11 @@ void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const
 
 template <typename T>
 bool tile_fits(int mode, int side, int steps) {
-  const int H = (mode == TILE_ZERO) ? steps - 1 : (mode == TILE_DOWN ? steps + 1 : steps);
-  if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > TILE_HMAX) return false;
-  if (side < tile_side<T>(side) + TILE_HMAX) return false;  // one wrap reaches every halo row
+  const int H = tile_halo(mode, steps);
+  const int TT = tile_side<T>(side);
+  const int hmax = TT == 64 ? TileCfg<64>::HMAX : TileCfg<32>::HMAX;
+  if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > hmax) return false;
+  if (side < TT + hmax) return false;  // one wrap reaches every halo row
   return mode != TILE_DOWN || side % 2 == 0;
 }
 
@@ -1440,6 +1502,28 @@ void vtile(int mode, const TileArgs<T>& a, hipStream_t s) {
   vtile_tt<T, 32>(mode, a, s);
 }
 
+bool btile_fits(int mode, int side, int steps) {
+  const int H = tile_halo(mode, steps);
+  if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > TileCfg<32>::HMAX)
+    return false;
+  if (side < 32 + TileCfg<32>::HMAX) return false;
+  return mode != TILE_DOWN || side % 2 == 0;
+}
+
+int btile_count(int side) {
+  const int nt = (side + 31) / 32;
+  return nt * nt;
+}
+
+template <typename T>
+void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const dim3 g(ntiles), b(TILE_THREADS);
+  if (mode == TILE_ZERO) hipLaunchKernelGGL((k_bvtile<T, TILE_ZERO, 32>), g, b, 0, s, a);
+  else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_bvtile<T, TILE_DOWN, 32>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_bvtile<T, TILE_UP, 32>), g, b, 0, s, a);
+}
+
 template <typename T>
 bool tail_fits(const int* sides, int nlev) {
   if (nlev < 1 || nlev > TAIL_MAXLEV) return false;
@@ -1451,6 +1535,14 @@ bool tail_fits(const int* sides, int nlev) {
   }
   return size_t(sides[0]) * sides[0] <= size_t(TailCfg<T>::RPT) * TAIL_THREADS &&
          3 * rows * sizeof(T) <= TAIL_LDS;
+}
+
+template <typename T>
+void bvtail(int n, const TailArgs<T>* list, const int* idx, const int* act, const T* bbase, T* xbase,
+            hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_bvtail<T, TailCfg<T>::RPT>), dim3(n), dim3(TAIL_THREADS), 0, s, list, idx, act,
+                     bbase, xbase);
 }
 
 template <typename T>
@@ -1689,6 +1781,12 @@ template void coarse_cheb<double, double>(const DSell&, const double*, const dou
                                           hipStream_t);
 template void coarse_cheb<float, float>(const DSell&, const float*, const float*, const float*,
                                         const ChebCoef<float>&, float*, hipStream_t);
+template void bvtile<double>(int, int, const BTileLaunch<double>&, hipStream_t);
+template void bvtile<float>(int, int, const BTileLaunch<float>&, hipStream_t);
+template void bvtail<double>(int, const TailArgs<double>*, const int*, const int*, const double*, double*,
+                             hipStream_t);
+template void bvtail<float>(int, const TailArgs<float>*, const int*, const int*, const float*, float*,
+                            hipStream_t);
 template bool tile_fits<double>(int, int, int);
 template bool tile_fits<float>(int, int, int);
 template void vtile<double>(int, const TileArgs<double>&, hipStream_t);

@@ -81,6 +81,8 @@ constexpr int TAIL_MAXSM = 32;
 constexpr int TAIL_THREADS = 1024;
 template <typename T>
 struct TailArgs {
+  int inst;  // batched: the instance (activity check)
+  int roff;  // batched: row offset of b and x in the launch's base vectors
   int nlev;
   int side[TAIL_MAXLEV];
   const T* val[TAIL_MAXLEV];
@@ -97,6 +99,12 @@ template <typename T>
 bool tail_fits(const int* sides, int nlev);
 template <typename T>
 void vtail(const TailArgs<T>& a, hipStream_t s);
+// Batched: n workgroups, workgroup w runs list[idx[w]] (device arrays) with
+// b = bbase + roff and x = xbase + roff (the entries' own b and x unused);
+// tails of instances with act[inst] == 0 (act may be null) do nothing.
+template <typename T>
+void bvtail(int n, const TailArgs<T>* list, const int* idx, const int* act, const T* bbase, T* xbase,
+            hipStream_t s);
 
 // Tiled multigrid kernels on one periodic P1 level: one workgroup per square
 // tile of the level's grid plus a halo of H rings, every dependent step of the
@@ -109,7 +117,7 @@ void vtail(const TailArgs<T>& a, hipStream_t s);
 //              post-smoothing steps (H = steps); x written (x != xin).
 // c1/c2: the Chebyshev coefficients of the steps (c1[0] unused).
 enum TileMode { TILE_ZERO = 0, TILE_DOWN = 1, TILE_UP = 2 };
-constexpr int TILE_MAXSTEPS = 5;
+constexpr int TILE_MAXSTEPS = 9;
 template <typename T>
 struct TileArgs {
   int side = 0, steps = 0;
@@ -128,6 +136,37 @@ template <typename T>
 bool tile_fits(int mode, int side, int steps);
 template <typename T>
 void vtile(int mode, const TileArgs<T>& a, hipStream_t s);
+
+// Batched tiled kernels (32 x 32 tiles): one workgroup per entry of a tile
+// list; each entry names its instance, its tile, the instance's level side and
+// its row offsets on the level (roff) and on the next coarser level (croff).
+// Tiles of instances with act[inst] == 0 (act may be null) do nothing.
+// Coefficients: c1/c2 for every instance, or per instance from cc1/cc2
+// ([step * count + inst]) when those are given.
+struct BTile {
+  int inst, tile, side, roff, croff;
+};
+template <typename T>
+struct BTileLaunch {
+  const BTile* tiles = nullptr;
+  const int* act = nullptr;
+  int count = 0, steps = 0;
+  const T* val = nullptr;
+  const T* dinv = nullptr;
+  const T* b = nullptr;
+  const T* xin = nullptr;
+  const T* e = nullptr;
+  T* x = nullptr;
+  T* bc = nullptr;
+  T c1[TILE_MAXSTEPS] = {};
+  T c2[TILE_MAXSTEPS] = {};
+  const T* cc1 = nullptr;
+  const T* cc2 = nullptr;
+};
+bool btile_fits(int mode, int side, int steps);
+int btile_count(int side);  // tiles of one instance level
+template <typename T>
+void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s);
 
 // CH block on [x1; x2] with value streams L = M + tau C, K, M (uniform P1):
 //   y1 = alpha (L x1 + c12 K x2) + beta y1,  y2 = alpha (c12 K x1 + c22 M x2) + beta y2.
