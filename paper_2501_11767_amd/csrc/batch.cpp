@@ -29,6 +29,7 @@ namespace {
 
 constexpr int NOPS = 3;  // 0: L = M, 1: X = s M + tau g K, 2: AC = M + tau delta_v K
 constexpr int BMAX_RESTART = 64;
+constexpr int64_t KRYLOV_PAD = 640;  // doubles between consecutive basis vectors (HBM channel spread)
 constexpr size_t GRAPH_MAX_NODES = 100000;  // refuse to instantiate larger step graphs
 constexpr int GRAPH_CACHE = 4;              // step graphs kept per batch
 constexpr int EAGER_CHECK = 4;              // eager mode: Arnoldi steps between activity readbacks
@@ -107,11 +108,15 @@ struct chns_batch {
   int* cinst = nullptr;      // chunk -> instance over [phi_all; mu_all]
   int *cr = nullptr;         // chunk ranges per instance (first half)
   int nchunk1 = 0;
-  // Krylov
-  double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-  double *y = nullptr, *h = nullptr, *inv = nullptr, *nrm = nullptr, *nrm2 = nullptr, *tol = nullptr;
+  // Krylov (DCGS2): basis and preconditioned vectors with stride ld, per
+  // instance Hessenberg (raw H, rotated HR), rotations, g, gp, slot sums and
+  // coefficients
+  int64_t ld = 0;
+  double *V = nullptr, *Z = nullptr, *H = nullptr, *HR = nullptr, *cs = nullptr, *sn = nullptr;
+  double *g = nullptr, *gp = nullptr, *y = nullptr, *red = nullptr, *coef = nullptr;
+  double *inv = nullptr, *nrm = nullptr, *tol = nullptr;
   double *part = nullptr, *part2 = nullptr;
-  int *flag = nullptr, *active = nullptr, *kcols = nullptr;
+  int *active = nullptr, *kcols = nullptr;
   int *iters[2] = {}, *conv[2] = {};
   // step buffers
   double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr, *xac = nullptr;
@@ -671,13 +676,18 @@ void bprecond_t(chns_batch* b, int block, const T* r, T* z, T* tmp1, T* tmp2, co
   }
 }
 
-void bprecond(chns_batch* b, int block, const double* r, double* z, const int* act,
+// z = P^{-1} r for every active instance.  When inv is given, r is first
+// scaled in place by inv[inst] (fused with the FP32 conversion in mixed
+// precision): the Krylov basis vector is normalised on its way in.
+void bprecond(chns_batch* b, int block, double* r, const double* inv, double* z, const int* act,
               const chns_solve_opts& o, hipStream_t s) {
   const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
   if (o.precision == CHNS_F64) {
+    if (inv) bscale(n, r, inv, b->cinst, act, r, s);
     bprecond_t<double>(b, block, r, z, b->w64a, b->w64b, act, o, s);
   } else {
-    bconvert<double, float>(n, r, b->r32, b->cinst, act, s);
+    if (inv) bconvert_scaled(n, r, inv, b->r32, b->cinst, act, s);
+    else bconvert<double, float>(n, r, b->r32, b->cinst, act, s);
     bprecond_t<float>(b, block, b->r32, b->z32, b->w32a, b->w32b, act, o, s);
     bconvert<float, double>(n, b->z32, z, b->cinst, act, s);
   }
@@ -723,9 +733,10 @@ int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_s
   const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
   const int nchunk = int(n / BCHUNK);
   const int half = (block == CHNS_BLOCK_CH) ? b->nchunk1 : 0;
-  const int hs = m + 2, Hs = (m + 1) * m, ldH = m + 1;
   const int* act = b->active;
   double* V = b->V;
+  const int64_t ld = b->ld;
+  const int rs = 2 * BMAX_RESTART + 3, cstride = 2 * BMAX_RESTART + 2;
   dfill_int(b->count, 0, b->iters[bi], s);
   bnorm_partial(n, rhs, b->part, s);
   bnorm_finish(b->count, nchunk, b->part, b->cr, half, m, 1, o.rtol, o.atol, b->nrm, b->inv, b->g,
@@ -745,31 +756,27 @@ int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_s
     }
     bscale(n, V, b->inv, b->cinst, act, V, s);
     for (int j = 0; j < m; ++j) {
-      double* vj = V + int64_t(j) * n;
-      double* vn = V + int64_t(j + 1) * n;
-      double* zj = b->Z + int64_t(j) * n;
-      bprecond(b, block, vj, zj, act, o, s);
+      double* vj = V + int64_t(j) * ld;
+      double* vn = V + int64_t(j + 1) * ld;
+      double* zj = b->Z + int64_t(j) * ld;
+      // v_j is normalised in the preconditioner's input stage (j > 0)
+      bprecond(b, block, vj, j > 0 ? b->inv : nullptr, zj, act, o, s);
       bapply(b, block, zj, vn, 1.0, 0.0, act, s);
-      bmdot_partial(n, V, n, j + 2, vn, b->part, nullptr, b->cinst, act, s);
-      bmdot_reduce(b->count, nchunk, j + 2, b->part, b->cr, half, b->h, hs, b->H, Hs, j, ldH, 0,
-                   nullptr, s);
-      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, nullptr, b->cinst, act, s);
-      breorth_decide(b->count, nchunk, b->part2, b->cr, half, b->h, hs, j + 1, b->flag, b->nrm2, s);
-      bmdot_partial(n, V, n, j + 1, vn, b->part, b->flag, b->cinst, act, s);
-      bmdot_reduce(b->count, nchunk, j + 1, b->part, b->cr, half, b->h, hs, b->H, Hs, j, ldH, 1,
-                   b->flag, s);
-      bmaxpy(n, V, n, j + 1, b->h, hs, vn, b->part2, b->flag, b->cinst, act, s);
-      barnoldi_finish(b->count, nchunk, b->part2, b->cr, half, b->flag, b->nrm2, j, m, b->H, b->cs,
-                      b->sn, b->g, b->inv, b->tol, b->active, b->kcols, b->iters[bi], s);
-      bscale(n, vn, b->inv, b->cinst, act, vn, s);
+      // DCGS2: one dot pass and one update pass over each instance's basis
+      bdcgs_dots(n, V, ld, j, b->part, b->cinst, act, s);
+      bslot_reduce(b->count, nchunk, 2 * j + 3, b->part, b->cr, half, b->red, rs, act, s);
+      bdcgs_coef(b->count, j, m, b->red, rs, b->H, b->coef, cstride, act, s);
+      bdcgs_update(n, V, ld, j, b->coef, cstride, b->part2, b->cinst, act, s);
+      bdcgs_finish(b->count, nchunk, b->part2, b->cr, half, j, m, b->H, b->HR, b->cs, b->sn, b->g,
+                   b->gp, b->inv, b->tol, b->active, b->kcols, b->iters[bi], s);
       if (eager && (j + 1) % EAGER_CHECK == 0 && j + 1 < m) {
         bool any = false;
         BTRY(any_active(b, s, any));
         if (!any) break;
       }
     }
-    blsq(b->count, m, b->H, b->g, b->kcols, b->y, s);
-    bxupdate(n, b->Z, n, m, b->y, x, b->cinst, b->kcols, s);
+    blsq(b->count, m, b->HR, b->gp, b->kcols, b->y, s);
+    bxupdate(n, b->Z, ld, m, b->y, x, b->cinst, b->kcols, s);
   }
   hipLaunchKernelGGL(k_not_into, dim3((b->count + 63) / 64), dim3(64), 0, s, b->count, b->active,
                      b->conv[bi]);
@@ -888,18 +895,22 @@ int bbuild(chns_batch* b) {
   BCHK(b, hipGetLastError());
   // Krylov workspace for the CH block (2N) with restart <= BMAX_RESTART
   const size_t n2 = 2 * size_t(N), cnt = size_t(b->count), m = BMAX_RESTART;
-  BTRY(balloc(b, &b->V, (m + 1) * n2));
-  BTRY(balloc(b, &b->Z, m * n2));
+  b->ld = int64_t(n2) + KRYLOV_PAD;
+  BTRY(balloc(b, &b->V, (m + 1) * size_t(b->ld)));
+  BTRY(balloc(b, &b->Z, m * size_t(b->ld)));
   BTRY(balloc(b, &b->H, cnt * (m + 1) * m));
+  BTRY(balloc(b, &b->HR, cnt * (m + 1) * m));
   BTRY(balloc(b, &b->cs, cnt * (m + 1)));
   BTRY(balloc(b, &b->sn, cnt * (m + 1)));
   BTRY(balloc(b, &b->g, cnt * (m + 2)));
+  BTRY(balloc(b, &b->gp, cnt * (m + 2)));
   BTRY(balloc(b, &b->y, cnt * (m + 1)));
-  BTRY(balloc(b, &b->h, cnt * (m + 2)));
-  for (double** v : {&b->inv, &b->nrm, &b->nrm2, &b->tol}) BTRY(balloc(b, v, cnt));
-  for (int** v : {&b->flag, &b->active, &b->kcols, &b->iters[0], &b->iters[1], &b->conv[0], &b->conv[1]})
+  BTRY(balloc(b, &b->red, cnt * (2 * m + 3)));
+  BTRY(balloc(b, &b->coef, cnt * (2 * m + 2)));
+  for (double** v : {&b->inv, &b->nrm, &b->tol}) BTRY(balloc(b, v, cnt));
+  for (int** v : {&b->active, &b->kcols, &b->iters[0], &b->iters[1], &b->conv[0], &b->conv[1]})
     BTRY(balloc(b, v, cnt));
-  BTRY(balloc(b, &b->part, (m + 2) * n2 / BCHUNK));
+  BTRY(balloc(b, &b->part, (2 * m + 3) * n2 / BCHUNK));
   BTRY(balloc(b, &b->part2, n2 / BCHUNK));
   for (double** v : {&b->rhs_ch, &b->xch}) BTRY(balloc(b, v, n2));
   for (double** v : {&b->rhs_ac, &b->xac, &b->w64a, &b->w64b}) BTRY(balloc(b, v, size_t(N)));
@@ -944,7 +955,9 @@ size_t step_launches(const chns_batch* b, const chns_solve_opts& o) {
     const int m = std::min(o.restart, budget);
     const size_t cycles = size_t((budget + m - 1) / m);
     const size_t pre = bi == 0 ? 3 * vcycle_launches(b, 0, 0, o) + 1 : vcycle_launches(b, 2, 0, o);
-    const size_t arnoldi = pre + (o.precision == CHNS_MIXED ? 2 : 0) + 1 + 9;
+    // input stage (convert or scale) and output conversion, operator, dot
+    // launches, slot sums, coefficients, update, finish
+    const size_t arnoldi = pre + (o.precision == CHNS_MIXED ? 2 : 1) + 1 + (1 + size_t(m - 1) / 16) + 4;
     total += 3 + cycles * (4 + 1 + size_t(m) * arnoldi + 2) + 4 + 1;
   }
   return total;
@@ -1220,7 +1233,7 @@ int chns_batch_precond_apply(chns_batch* b, int32_t block, const double* d_r, do
   if (d_r < d_z + n && d_z < d_r + n) return fail(b, CHNS_EINVAL, "r and z overlap");
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTRY(prepare_cycles(b, *opts));
-  bprecond(b, block, d_r, d_z, nullptr, *opts, s);
+  bprecond(b, block, const_cast<double*>(d_r), nullptr, d_z, nullptr, *opts, s);  // r not written
   BCHK(b, hipGetLastError());
   return CHNS_OK;
 }

@@ -24,6 +24,40 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Reduce-scatter over the wavefront by recursive halving: every lane holds C
+// values v[0..C); at the step with lane offset O each lane keeps one half of
+// its values (the upper half when its bit O is set; an odd count pads the
+// upper half with a zero), adds the partner's copy of that half and sends the
+// other half, one shuffle per kept value.  base tracks the index of the
+// lane's first kept value and lim how many of its kept values are real.
+// After the steps O = 32 .. 1 (C <= 64), a lane with lim >= 1 holds in v[0]
+// the wavefront total of value index base; every index is held by exactly
+// one lane.  About C shuffles in all, where C separate wavefront sums take 6 C.
+template <int C, int O>
+struct WaveRS {
+  static __device__ __forceinline__ void run(double* v, int lane, int& base, int& lim) {
+    constexpr int HH = (C + 1) / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < HH; ++i) {
+      const double lo = v[i];
+      const double hi = (i + HH < C) ? v[(i + HH < C) ? i + HH : 0] : 0.0;
+      v[i] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, O, 64);
+    }
+    if (up) {
+      base += HH;
+      lim = lim > HH ? lim - HH : 0;
+    } else {
+      lim = lim < HH ? lim : HH;
+    }
+    WaveRS<HH, O / 2>::run(v, lane, base, lim);
+  }
+};
+template <int C>
+struct WaveRS<C, 0> {
+  static __device__ __forceinline__ void run(double*, int, int&, int&) {}
+};
+
 // Sum over a 256-thread workgroup (sh: 4 doubles); result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum(v);

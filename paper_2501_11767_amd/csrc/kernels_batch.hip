@@ -199,167 +199,298 @@ __global__ __launch_bounds__(BS) void k_bcombine(int64_t n, const int* __restric
 
 // ---------------------------------------------------------------- Krylov
 
-constexpr int MD_G = 8;
 constexpr int RPC = BCHUNK / BS;  // rows per thread in a chunk
+constexpr int BDG = 16;          // basis vectors per dot launch
 
-__global__ __launch_bounds__(BS) void k_bmdot_partial(int64_t n, const double* __restrict__ V,
-                                                      int64_t ldv, int k,
-                                                      const double* __restrict__ w,
-                                                      double* __restrict__ part,
-                                                      const int* __restrict__ flag,
-                                                      const int* __restrict__ cinst,
-                                                      const int* __restrict__ act) {
+// Delayed classical Gram-Schmidt with reorthogonalisation (DCGS2), batched:
+// per 1024-row chunk partial sums, reduced per instance over its chunk list
+// ([cr[2i], cr[2i+1]) and, for the CH block, the same range shifted by half).
+
+// Dots of one chunk: KK basis vectors V_g0.. against vt = V_j and w = V_{j+1},
+// and with LAST vt.vt, vt.w, w.w; slot s of chunk c goes to
+// part[s * nchunk + c] (slots [0, j) V_i.vt, [j, 2j) V_i.w, then 2j, 2j+1,
+// 2j+2).  The accumulators are reduced by a wavefront reduce-scatter, then
+// across the 4 wavefronts.  Chunks of inactive instances are skipped.
+template <int KK, bool LAST>
+__global__ __launch_bounds__(BS) void k_bdots(const double* __restrict__ V, int64_t ld, int j, int g0,
+                                              double* __restrict__ part, const int* __restrict__ cinst,
+                                              const int* __restrict__ act) {
+  constexpr int NV = 2 * KK + (LAST ? 3 : 0);
   const int c = blockIdx.x;
-  if (flag && flag[cinst[c]] == 0) return;
-  if (act && act[cinst[c]] == 0) return;
-  __shared__ double sh[16];
-  const int g0 = blockIdx.y * MD_G;
-  const int kk = min(MD_G, k - g0);
-  double acc[MD_G];
+  if (act && !act[cinst[c]]) return;
+  __shared__ double sh[4][NV];
+  const double* vt = V + int64_t(j) * ld;
+  const double* w = V + int64_t(j + 1) * ld;
+  double acc[NV];
 #pragma unroll
-  for (int i = 0; i < MD_G; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
 #pragma unroll
   for (int rr = 0; rr < RPC; ++rr) {
     const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
-    const double wr = w[r];
+    const double t = vt[r], wr = w[r];
+    double v[KK > 0 ? KK : 1];
 #pragma unroll
-    for (int i = 0; i < MD_G; ++i)
-      if (i < kk) acc[i] += V[(g0 + i) * ldv + r] * wr;
+    for (int i = 0; i < KK; ++i) v[i] = V[(g0 + i) * ld + r];
+#pragma unroll
+    for (int i = 0; i < KK; ++i) {
+      acc[i] += v[i] * t;
+      acc[KK + i] += v[i] * wr;
+    }
+    if constexpr (LAST) {
+      acc[2 * KK] += t * t;
+      acc[2 * KK + 1] += t * wr;
+      acc[2 * KK + 2] += wr * wr;
+    }
   }
-  for (int i = 0; i < kk; ++i) {
-    const double s = block_sum_any(acc[i], sh);
-    if (threadIdx.x == 0) part[int64_t(g0 + i) * gridDim.x + c] = s;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int base = 0, lim = NV;
+  WaveRS<NV, 32>::run(acc, lane, base, lim);
+  if (lim >= 1) sh[wid][base] = acc[0];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < NV) {
+    int64_t slot;
+    if (t < KK) slot = g0 + t;
+    else if (t < 2 * KK) slot = j + g0 + (t - KK);
+    else slot = 2 * j + (t - 2 * KK);
+    part[slot * gridDim.x + c] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
   }
 }
 
-__device__ double chunk_sum(const double* part, const int* cr, int half, int i) {
-  double s = 0.0;
-  for (int c = cr[2 * i] + int(threadIdx.x); c < cr[2 * i + 1]; c += blockDim.x) {
-    s += part[c];
-    if (half) s += part[c + half];
-  }
-  return s;
-}
-
-__global__ __launch_bounds__(BS) void k_bmdot_reduce(int nchunk, int k, const double* __restrict__ part,
+// One wavefront per (slot, instance): red[i * rs + k] = slot k summed over the
+// instance's chunks.
+__global__ __launch_bounds__(64) void k_bslot_reduce(int nchunk, const double* __restrict__ part,
                                                      const int* __restrict__ cr, int half,
-                                                     double* __restrict__ h, int hs,
-                                                     double* __restrict__ H, int Hs, int j, int ldH,
-                                                     int accumulate, const int* __restrict__ flag) {
-  const int i = blockIdx.x, v = blockIdx.y;
-  if (flag && flag[i] == 0) return;
-  __shared__ double sh[16];
-  const double s = block_sum_any(chunk_sum(part + int64_t(v) * nchunk, cr, half, i), sh);
-  if (threadIdx.x == 0) {
-    h[i * hs + v] = s;
-    double* hc = H + int64_t(i) * Hs + int64_t(j) * ldH;
-    hc[v] = accumulate ? hc[v] + s : s;
+                                                     double* __restrict__ red, int rs,
+                                                     const int* __restrict__ act) {
+  const int k = blockIdx.x, i = blockIdx.y;
+  if (act && !act[i]) return;
+  const double* p = part + int64_t(k) * nchunk;
+  double a = 0.0;
+  for (int c = cr[2 * i] + int(threadIdx.x); c < cr[2 * i + 1]; c += 64) {
+    a += p[c];
+    if (half) a += p[c + half];
+  }
+  a = wave_sum(a);
+  if (threadIdx.x == 0) red[int64_t(i) * rs + k] = a;
+}
+
+// One wavefront per instance: coefficients of step j from its reduced dots
+// (the per-instance form of the FGMRES coefficient stage): c_i = V_i.vt,
+// a_i = V_i.w, r = sqrt(vt.vt - |c|^2); column j-1 of the raw Hessenberg H
+// becomes h_i += h_j c_i, h_j *= r; column j: a_i and b = (vt.w - c.a) / r;
+// coef: [0, j) c_i, [j, 2j) a_i - b c_i / r, 2j: b / r, 2j+1: 1/r.
+__global__ __launch_bounds__(64) void k_bdcgs_coef(int j, int m, const double* __restrict__ red, int rs,
+                                                   double* __restrict__ H, double* __restrict__ coef,
+                                                   int cstride, const int* __restrict__ act) {
+  const int i = blockIdx.x;
+  if (act && !act[i]) return;
+  const double* ri = red + int64_t(i) * rs;
+  double* Hi = H + int64_t(i) * (m + 1) * m;
+  double* ci = coef + int64_t(i) * cstride;
+  const int t = threadIdx.x, ld = m + 1;
+  const double c = t < j ? ri[t] : 0.0;
+  const double a = t < j ? ri[j + t] : 0.0;
+  const double hj = j > 0 ? Hi[int64_t(j - 1) * ld + j] : 0.0;
+  const double cc = wave_sum(c * c), ca = wave_sum(c * a);
+  const double nu = ri[2 * j], tw = ri[2 * j + 1];
+  const double r = j > 0 ? sqrt(fmax(nu - cc, 0.0)) : 1.0;
+  const double inv = r > 0.0 ? 1.0 / r : 0.0;
+  const double b = (tw - ca) * inv;
+  if (j > 0 && t <= j) {
+    double* hp = Hi + int64_t(j - 1) * ld;
+    hp[t] = (t < j) ? hp[t] + hj * c : hj * r;
+  }
+  double* h = Hi + int64_t(j) * ld;
+  if (t < j) {
+    h[t] = a;
+    ci[t] = c;
+    ci[j + t] = a - b * c * inv;
+  }
+  if (t == 0) {
+    h[j] = b;
+    ci[2 * j] = b * inv;
+    ci[2 * j + 1] = inv;
   }
 }
 
-__global__ __launch_bounds__(BS) void k_bmaxpy(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                               int k, const double* __restrict__ h, int hs,
-                                               double* __restrict__ w,
-                                               double* __restrict__ nrm_part,
-                                               const int* __restrict__ flag,
-                                               const int* __restrict__ cinst,
-                                               const int* __restrict__ act) {
+// Update of one chunk with its instance's coefficients: w <- w - sum coef[j+i]
+// V_i - coef[2j] vt, vt <- (vt - sum coef[i] V_i) / r (j > 0); chunk partial
+// of |w'|^2.
+__global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int64_t ld, int j,
+                                                     const double* __restrict__ coef, int cstride,
+                                                     double* __restrict__ nrm_part,
+                                                     const int* __restrict__ cinst,
+                                                     const int* __restrict__ act) {
   const int c = blockIdx.x;
   const int inst = cinst[c];
-  if (flag && flag[inst] == 0) return;
-  if (act && act[inst] == 0) return;
-  __shared__ double hsh[80];
+  if (act && !act[inst]) return;
+  __shared__ double cl[2 * 64 + 2];
   __shared__ double sh[16];
-  for (int i = threadIdx.x; i < k; i += BS) hsh[i] = h[inst * hs + i];
+  for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cl[i] = coef[int64_t(inst) * cstride + i];
   __syncthreads();
+  double* vt = V + int64_t(j) * ld;
+  double* w = V + int64_t(j + 1) * ld;
+  const double inv = cl[2 * j + 1], wt = cl[2 * j];
   double acc = 0.0;
 #pragma unroll
   for (int rr = 0; rr < RPC; ++rr) {
     const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
-    double wr = w[r];
-    for (int i = 0; i < k; ++i) wr -= hsh[i] * V[i * ldv + r];
-    w[r] = wr;
-    acc += wr * wr;
+    const double t = vt[r];
+    double wn = w[r] - wt * t, vn = t;
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = V[(i + q) * ld + r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        vn -= cl[i + q] * v[q];
+        wn -= cl[j + i + q] * v[q];
+      }
+    }
+    for (; i < j; ++i) {
+      const double v = V[i * ld + r];
+      vn -= cl[i] * v;
+      wn -= cl[j + i] * v;
+    }
+    if (j > 0) vt[r] = vn * inv;
+    w[r] = wn;
+    acc += wn * wn;
   }
   const double s = block_sum_any(acc, sh);
   if (threadIdx.x == 0) nrm_part[c] = s;
 }
 
-__global__ __launch_bounds__(BS) void k_breorth_decide(int nchunk, const double* __restrict__ part,
-                                                       const int* __restrict__ cr, int half,
-                                                       const double* __restrict__ h, int hs,
-                                                       int wwpos, int* __restrict__ flag,
-                                                       double* __restrict__ nrm2) {
-  const int i = blockIdx.x;
-  __shared__ double sh[16];
-  const double s = block_sum_any(chunk_sum(part, cr, half, i), sh);
-  if (threadIdx.x == 0) {
-    nrm2[i] = s;
-    flag[i] = (s < 0.5 * h[i * hs + wwpos]) ? 1 : 0;
+__device__ __forceinline__ void bgivens(double a, double b, double& c, double& s) {
+  if (b == 0.0) {
+    c = 1.0;
+    s = 0.0;
+  } else if (fabs(b) > fabs(a)) {
+    const double t = a / b;
+    s = 1.0 / sqrt(1.0 + t * t);
+    c = t * s;
+  } else {
+    const double t = b / a;
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
   }
 }
 
-__global__ __launch_bounds__(BS) void k_barnoldi_finish(int nchunk, const double* __restrict__ part2,
-                                                        const int* __restrict__ cr, int half,
-                                                        const int* __restrict__ flag,
-                                                        const double* __restrict__ nrm2, int j,
-                                                        int m, double* __restrict__ H,
-                                                        double* __restrict__ cs,
-                                                        double* __restrict__ sn,
-                                                        double* __restrict__ g,
-                                                        double* __restrict__ inv,
-                                                        const double* __restrict__ tol,
-                                                        int* __restrict__ active,
-                                                        int* __restrict__ kcols,
-                                                        int* __restrict__ iters) {
-  const int i = blockIdx.x;
-  __shared__ double sh[16];
-  const double s2 = block_sum_any(chunk_sum(part2, cr, half, i), sh);
-  if (threadIdx.x != 0) return;
+// Rotations 0..upto-1 applied in order to x[0..upto].
+__device__ __forceinline__ void brotate(double* x, int upto, const double* c, const double* s) {
+  double carry = x[0];
+  for (int i = 0; i < upto; ++i) {
+    const double b = x[i + 1];
+    x[i] = c[i] * carry + s[i] * b;
+    carry = -s[i] * carry + c[i] * b;
+  }
+  x[upto] = carry;
+}
+
+// One wavefront per instance, end of step j: h_{j+1,j} = |w'| (provisional),
+// column j-1 rotated into HR with its final rotation (and g), column j with a
+// provisional one into HR and gp; the residual estimate |gp_{j+1}| decides
+// the activity (an instance that stops keeps j + 1 columns); inv = 1/|w'|.
+// The columns, rotations and g are staged in LDS for the serial chain.
+__global__ __launch_bounds__(64) void k_bdcgs_finish(int nchunk, const double* __restrict__ part2,
+                                                     const int* __restrict__ cr, int half, int j, int m,
+                                                     double* __restrict__ H, double* __restrict__ HR,
+                                                     double* __restrict__ cs, double* __restrict__ sn,
+                                                     double* __restrict__ g, double* __restrict__ gp,
+                                                     double* __restrict__ inv,
+                                                     const double* __restrict__ tol,
+                                                     int* __restrict__ active, int* __restrict__ kcols,
+                                                     int* __restrict__ iters) {
+  const int i = blockIdx.x, t = threadIdx.x;
   if (!active[i]) {
-    inv[i] = 0.0;
+    if (t == 0) inv[i] = 0.0;
     return;
   }
-  const double nrm = flag[i] ? sqrt(s2) : sqrt(nrm2[i]);
+  __shared__ double hp[66], hc[66], cs_s[64], sn_s[64], g_s[66], res[3];
   const int ld = m + 1;
   double* Hi = H + int64_t(i) * (m + 1) * m;
-  double* h = Hi + int64_t(j) * ld;
-  double* csi = cs + i * (m + 1);
-  double* sni = sn + i * (m + 1);
-  double* gi = g + i * (m + 2);
-  h[j + 1] = nrm;
-  for (int l = 0; l < j; ++l) {
-    const double a = h[l], b = h[l + 1];
-    h[l] = csi[l] * a + sni[l] * b;
-    h[l + 1] = -sni[l] * a + csi[l] * b;
+  double* HRi = HR + int64_t(i) * (m + 1) * m;
+  double* csi = cs + int64_t(i) * (m + 1);
+  double* sni = sn + int64_t(i) * (m + 1);
+  double* gi = g + int64_t(i) * (m + 2);
+  double* gpi = gp + int64_t(i) * (m + 2);
+  for (int q = t; q <= j; q += 64) {
+    hc[q] = Hi[int64_t(j) * ld + q];
+    if (j > 0) hp[q] = Hi[int64_t(j - 1) * ld + q];
+    g_s[q] = gi[q];
+    if (q + 1 < j) {
+      cs_s[q] = csi[q];
+      sn_s[q] = sni[q];
+    }
   }
-  const double a = h[j], b = h[j + 1];
-  double cc, ss;
-  if (b == 0.0) {
-    cc = 1.0;
-    ss = 0.0;
-  } else if (fabs(b) > fabs(a)) {
-    const double t = a / b;
-    ss = 1.0 / sqrt(1.0 + t * t);
-    cc = t * ss;
-  } else {
-    const double t = b / a;
-    cc = 1.0 / sqrt(1.0 + t * t);
-    ss = t * cc;
+  double a = 0.0;
+  for (int c = cr[2 * i] + t; c < cr[2 * i + 1]; c += 64) {
+    a += part2[c];
+    if (half) a += part2[c + half];
   }
-  csi[j] = cc;
-  sni[j] = ss;
-  h[j] = cc * a + ss * b;
-  h[j + 1] = 0.0;
-  gi[j + 1] = -ss * gi[j];
-  gi[j] = cc * gi[j];
-  iters[i] += 1;
-  const double est = fabs(gi[j + 1]);
-  if (!(est > tol[i]) || nrm == 0.0 || !isfinite(est)) {
-    active[i] = 0;
-    kcols[i] = j + 1;
+  const double nrm = sqrt(wave_sum(a));
+  __syncthreads();
+  if (t == 0) {
+    hc[j + 1] = nrm;
+    if (j > 0) {
+      brotate(hp, j - 1, cs_s, sn_s);
+      double c, s;
+      bgivens(hp[j - 1], hp[j], c, s);
+      cs_s[j - 1] = c;
+      sn_s[j - 1] = s;
+      hp[j - 1] = c * hp[j - 1] + s * hp[j];
+      hp[j] = 0.0;
+      g_s[j] = -s * g_s[j - 1];
+      g_s[j - 1] = c * g_s[j - 1];
+    }
+    brotate(hc, j, cs_s, sn_s);
+    double c, s;
+    bgivens(hc[j], hc[j + 1], c, s);
+    hc[j] = c * hc[j] + s * hc[j + 1];
+    hc[j + 1] = 0.0;
+    res[0] = c * g_s[j];
+    res[1] = -s * g_s[j];
+    Hi[int64_t(j) * ld + j + 1] = nrm;
+    iters[i] += 1;
+    const double est = fabs(res[1]);
+    if (!(est > tol[i]) || nrm == 0.0 || !isfinite(est)) {
+      active[i] = 0;
+      kcols[i] = j + 1;
+    }
+    inv[i] = nrm > 0.0 ? 1.0 / nrm : 0.0;
   }
-  inv[i] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  __syncthreads();
+  for (int q = t; q <= j + 1; q += 64) {
+    HRi[int64_t(j) * ld + q] = hc[q];
+    if (j > 0 && q <= j) HRi[int64_t(j - 1) * ld + q] = hp[q];
+    if (q < j) gpi[q] = g_s[q];
+  }
+  if (t == 0) {
+    if (j > 0) {
+      csi[j - 1] = cs_s[j - 1];
+      sni[j - 1] = sn_s[j - 1];
+      gi[j - 1] = g_s[j - 1];
+      gi[j] = g_s[j];
+    }
+    gpi[j] = res[0];
+    gpi[j + 1] = res[1];
+  }
+}
+
+// x <- x * inv[inst] in place and y = float(x) on chunks of active instances.
+__global__ __launch_bounds__(BS) void k_bconvert_scaled(int64_t n, double* __restrict__ x,
+                                                        const double* __restrict__ inv,
+                                                        float* __restrict__ y,
+                                                        const int* __restrict__ cinst,
+                                                        const int* __restrict__ act) {
+  const int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (r >= n) return;
+  const int inst = cinst[r / BCHUNK];
+  if (act && act[inst] == 0) return;
+  const double v = x[r] * inv[inst];
+  x[r] = v;
+  y[r] = float(v);
 }
 
 __global__ __launch_bounds__(BS) void k_bscale(int64_t n, const double* __restrict__ w,
@@ -424,6 +555,15 @@ __global__ __launch_bounds__(BS) void k_bnorm_partial(int64_t n, const double* _
   }
   const double s = block_sum_any(acc, sh);
   if (threadIdx.x == 0) part[c] = s;
+}
+
+__device__ double chunk_sum(const double* part, const int* cr, int half, int i) {
+  double s = 0.0;
+  for (int c = cr[2 * i] + int(threadIdx.x); c < cr[2 * i + 1]; c += blockDim.x) {
+    s += part[c];
+    if (half) s += part[c + half];
+  }
+  return s;
 }
 
 __global__ __launch_bounds__(BS) void k_bnorm_finish(int nchunk, const double* __restrict__ part,
@@ -546,38 +686,61 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
                      b, B, out64, out32);
 }
 
-void bmdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                   const int* flag, const int* cinst, const int* act, hipStream_t s) {
+// The last group (kk < BDG vectors plus the vt, w products).
+static void launch_bdots_last(int kk, int nchunk, const double* V, int64_t ld, int j, int g0, double* part,
+                              const int* cinst, const int* act, hipStream_t s) {
+  switch (kk) {
+#define CHNS_BDOTS_CASE(K)                                                                        \
+  case K:                                                                                          \
+    hipLaunchKernelGGL((k_bdots<K, true>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g0, part, cinst, \
+                       act);                                                                       \
+    break;
+    CHNS_BDOTS_CASE(0) CHNS_BDOTS_CASE(1) CHNS_BDOTS_CASE(2) CHNS_BDOTS_CASE(3) CHNS_BDOTS_CASE(4)
+    CHNS_BDOTS_CASE(5) CHNS_BDOTS_CASE(6) CHNS_BDOTS_CASE(7) CHNS_BDOTS_CASE(8) CHNS_BDOTS_CASE(9)
+    CHNS_BDOTS_CASE(10) CHNS_BDOTS_CASE(11) CHNS_BDOTS_CASE(12) CHNS_BDOTS_CASE(13)
+    CHNS_BDOTS_CASE(14) CHNS_BDOTS_CASE(15)
+#undef CHNS_BDOTS_CASE
+    default: break;
+  }
+}
+
+void bdcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, const int* cinst,
+                const int* act, hipStream_t s) {
   const int nchunk = int(n / BCHUNK);
-  hipLaunchKernelGGL(k_bmdot_partial, dim3(nchunk, ceil_div(k, MD_G)), dim3(BS), 0, s, n, V, ldv, k,
-                     w, part, flag, cinst, act);
+  const int full = j / BDG, rem = j - full * BDG;
+  for (int g = 0; g < full; ++g)
+    hipLaunchKernelGGL((k_bdots<BDG, false>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g * BDG, part, cinst,
+                       act);
+  launch_bdots_last(rem, nchunk, V, ld, j, full * BDG, part, cinst, act, s);
 }
 
-void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* cr, int half,
-                  double* h, int hs, double* H, int Hs, int j, int ldH, int accumulate,
-                  const int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_bmdot_reduce, dim3(count, k), dim3(BS), 0, s, nchunk, k, part, cr, half, h,
-                     hs, H, Hs, j, ldH, accumulate, flag);
+void bslot_reduce(int count, int nchunk, int nslots, const double* part, const int* cr, int half,
+                  double* red, int rs, const int* act, hipStream_t s) {
+  hipLaunchKernelGGL(k_bslot_reduce, dim3(nslots, count), dim3(64), 0, s, nchunk, part, cr, half, red, rs,
+                     act);
 }
 
-void bmaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, int hs, double* w,
-            double* nrm_part, const int* flag, const int* cinst, const int* act, hipStream_t s) {
-  hipLaunchKernelGGL(k_bmaxpy, dim3(int(n / BCHUNK)), dim3(BS), 0, s, n, V, ldv, k, h, hs, w,
-                     nrm_part, flag, cinst, act);
+void bdcgs_coef(int count, int j, int m, const double* red, int rs, double* H, double* coef, int cstride,
+                const int* act, hipStream_t s) {
+  hipLaunchKernelGGL(k_bdcgs_coef, dim3(count), dim3(64), 0, s, j, m, red, rs, H, coef, cstride, act);
 }
 
-void breorth_decide(int count, int nchunk, const double* part, const int* cr, int half,
-                    const double* h, int hs, int wwpos, int* flag, double* nrm2, hipStream_t s) {
-  hipLaunchKernelGGL(k_breorth_decide, dim3(count), dim3(BS), 0, s, nchunk, part, cr, half, h, hs,
-                     wwpos, flag, nrm2);
+void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, int cstride,
+                  double* nrm_part, const int* cinst, const int* act, hipStream_t s) {
+  hipLaunchKernelGGL(k_bdcgs_update, dim3(int(n / BCHUNK)), dim3(BS), 0, s, V, ld, j, coef, cstride,
+                     nrm_part, cinst, act);
 }
 
-void barnoldi_finish(int count, int nchunk, const double* part2, const int* cr, int half,
-                     const int* flag, const double* nrm2, int j, int m, double* H, double* cs,
-                     double* sn, double* g, double* inv, const double* tol, int* active,
-                     int* kcols, int* iters, hipStream_t s) {
-  hipLaunchKernelGGL(k_barnoldi_finish, dim3(count), dim3(BS), 0, s, nchunk, part2, cr, half, flag,
-                     nrm2, j, m, H, cs, sn, g, inv, tol, active, kcols, iters);
+void bdcgs_finish(int count, int nchunk, const double* part2, const int* cr, int half, int j, int m,
+                  double* H, double* HR, double* cs, double* sn, double* g, double* gp, double* inv,
+                  const double* tol, int* active, int* kcols, int* iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_bdcgs_finish, dim3(count), dim3(64), 0, s, nchunk, part2, cr, half, j, m, H, HR, cs,
+                     sn, g, gp, inv, tol, active, kcols, iters);
+}
+
+void bconvert_scaled(int64_t n, double* x, const double* inv, float* y, const int* cinst, const int* act,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_bconvert_scaled, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y, cinst, act);
 }
 
 void bscale(int64_t n, const double* w, const double* inv, const int* cinst, const int* act,

@@ -64,29 +64,39 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
 // Block vectors of length n (multiple of BCHUNK); chunk c belongs to
 // instance cinst[c].  Per-instance arrays are indexed [inst * stride + j].
 
-// Chunks of instances with flag 0 or act 0 (either may be null) are skipped by
-// the chunked kernels below; their partials and outputs keep stale values.
+// Chunks of instances with act 0 (act may be null) are skipped by the chunked
+// kernels below; their partials and outputs keep stale values.
 
-// part[v * nchunk + c] = sum over chunk c of V_v . w (v < k); V_v = V + v*ldv.
-void bmdot_partial(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* part,
-                   const int* flag, const int* cinst, const int* act, hipStream_t s);
-// For each instance: h[i*hs + v] = sum of its chunks; hcol (H column j of each
-// instance, stride Hs) set or accumulated.  Instance chunk list: ranges
-// [cr[2i], cr[2i+1]) and, when two_ranges, [cr[2i] + half, cr[2i+1] + half).
-void bmdot_reduce(int count, int nchunk, int k, const double* part, const int* cr, int half,
-                  double* h, int hs, double* H, int Hs, int j, int ldH, int accumulate,
-                  const int* flag, hipStream_t s);
-// w -= V h_inst (k columns) with per-chunk w^2 partials.
-void bmaxpy(int64_t n, const double* V, int64_t ldv, int k, const double* h, int hs, double* w,
-            double* nrm_part, const int* flag, const int* cinst, const int* act, hipStream_t s);
-// Per instance: ||w'||^2 from partials; flag_i = (||w'||^2 < ||w||^2 / 2), ww = h[i*hs + wwpos].
-void breorth_decide(int count, int nchunk, const double* part, const int* cr, int half,
-                    const double* h, int hs, int wwpos, int* flag, double* nrm2, hipStream_t s);
-// Per instance: norm, Givens update of column j, residual estimate, activity.
-void barnoldi_finish(int count, int nchunk, const double* part2, const int* cr, int half,
-                     const int* flag, const double* nrm2, int j, int m, double* H, double* cs,
-                     double* sn, double* g, double* inv, const double* tol, int* active,
-                     int* kcols, int* iters, hipStream_t s);
+// Delayed classical Gram-Schmidt with reorthogonalisation (DCGS2) at Arnoldi
+// step j, per instance: V_j (vt) holds the vector of this step orthogonalised
+// once, V_{j+1} (w) the new vector.  Chunk partials of V_i.vt, V_i.w (i < j),
+// vt.vt, vt.w, w.w go to part[slot * nchunk + c] (slots 2j + 3; chunks of
+// inactive instances skipped).
+void bdcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, const int* cinst,
+                const int* act, hipStream_t s);
+// red[i * rs + k] = slot k summed over instance i's chunks [cr[2i], cr[2i+1])
+// and, when half != 0, the same range shifted by half; active instances only.
+void bslot_reduce(int count, int nchunk, int nslots, const double* part, const int* cr, int half,
+                  double* red, int rs, const int* act, hipStream_t s);
+// Per instance: reorthogonalisation coefficients of V_j, correction of
+// Hessenberg column j-1 (H per instance, (m+1) x m, column-major ld m+1) and
+// projection coefficients of w, into coef[i * cstride ..].
+void bdcgs_coef(int count, int j, int m, const double* red, int rs, double* H, double* coef, int cstride,
+                const int* act, hipStream_t s);
+// Per chunk: V_j <- its reorthogonalised, normalised form (j > 0), w <- w
+// projected out of the final basis; chunk partials of |w|^2 into nrm_part.
+void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, int cstride,
+                  double* nrm_part, const int* cinst, const int* act, hipStream_t s);
+// Per active instance: h_{j+1,j} = |w|, final rotation of column j-1 into HR
+// and g, provisional rotation of column j into HR and gp, iteration count,
+// activity (estimate |gp_{j+1}| <= tol_i, |w| == 0 or non-finite: inactive with
+// kcols = j + 1), inv = 1/|w| (0 for inactive instances).
+void bdcgs_finish(int count, int nchunk, const double* part2, const int* cr, int half, int j, int m,
+                  double* H, double* HR, double* cs, double* sn, double* g, double* gp, double* inv,
+                  const double* tol, int* active, int* kcols, int* iters, hipStream_t s);
+// x <- x * inv[inst] in place and y = float(x), on chunks of active instances.
+void bconvert_scaled(int64_t n, double* x, const double* inv, float* y, const int* cinst, const int* act,
+                     hipStream_t s);
 // v = w * inv[inst] (v may alias w).
 void bscale(int64_t n, const double* w, const double* inv, const int* cinst, const int* act,
             double* v, hipStream_t s);
