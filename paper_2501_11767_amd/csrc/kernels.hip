@@ -728,8 +728,8 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double* __
 // LAST also vt . vt, vt . w, w . w.  Slots (per block partial, stride
 // gridDim.x): [0, j) V_i . vt, [j, 2j) V_i . w, then 2j, 2j+1, 2j+2.  KK is a
 // compile-time count so that every load of a row is issued before its FMAs;
-// the epilogue reduces all accumulators per wavefront by shuffles and then
-// across the 4 wavefronts with one barrier.
+// the epilogue reduces the accumulators per wavefront by a reduce-scatter and
+// then across the 4 wavefronts with one barrier.
 template <int KK, bool LAST>
 __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __restrict__ V, int64_t ld,
                                                   int j, int g0, double* __restrict__ part) {
@@ -758,10 +758,10 @@ __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __res
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(acc[i]);
-    if (lane == 0) sh[wid][i] = s;
+  if constexpr (NV > 0) {
+    int base = 0, lim = NV;
+    WaveRS<NV, 32>::run(acc, lane, base, lim);
+    if (lim >= 1) sh[wid][base] = acc[0];
   }
   __syncthreads();
   const int t = threadIdx.x;
