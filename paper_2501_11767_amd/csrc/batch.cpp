@@ -256,6 +256,20 @@ int build_levels(chns_batch* b) {
     L.st.nrows = L.nrows;
     L.st.col = L.col;
     L.st.sinst = L.sinst;
+    // computed columns where no instance block has padding rows
+    bool whole = true;
+    std::vector<int2> geo(L.nslices);
+    for (int i = 0; i < b->count; ++i) {
+      if (L.roff[i] < 0) continue;
+      const int nl = tab[i]->n[l];
+      if ((nl * nl) % 64 != 0) whole = false;
+      for (int s0 = L.roff[i] / 64, s = s0; s < s0 + (nl * nl + 63) / 64; ++s) geo[s] = make_int2(nl, L.roff[i]);
+    }
+    if (whole) {
+      int2* dgeo = nullptr;
+      BTRY(bupload(b, &dgeo, geo));
+      L.st.geo = dgeo;
+    }
   }
   // transfers and Galerkin maps between l and l+1
   for (int l = 0; l + 1 < Lmax; ++l) {

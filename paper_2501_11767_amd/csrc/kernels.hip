@@ -226,13 +226,17 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const
 // Chebyshev steps of a cut level).
 constexpr int TILE_THREADS = 1024;
 template <int TT> struct TileCfg;
-template <> struct TileCfg<64> { static constexpr int HMAX = 4, RPT = 6; };
-template <> struct TileCfg<32> { static constexpr int HMAX = 8, RPT = 3; };
-// float levels of at least this side take 64 x 64 tiles (256 or more tiles)
+template <> struct TileCfg<64> { static constexpr int HMAX = 4, RPT = 6, NTH = 1024; };
+template <> struct TileCfg<32> { static constexpr int HMAX = 8, RPT = 3, NTH = 1024; };
+template <> struct TileCfg<16> { static constexpr int HMAX = 8, RPT = 4, NTH = 256; };
+// float levels of at least this side take 64 x 64 tiles (256 or more tiles);
+// levels of at most TILE16_MAX_SIDE take 16 x 16 tiles
 constexpr int TILE64_MIN_SIDE = 1024;
+constexpr int TILE16_MAX_SIDE = 256;
 template <typename T>
 inline int tile_side(int side) {
-  return (sizeof(T) == 4 && side >= TILE64_MIN_SIDE) ? 64 : 32;
+  if (sizeof(T) == 4 && side >= TILE64_MIN_SIDE) return 64;
+  return side <= TILE16_MAX_SIDE ? 16 : 32;
 }
 
 __device__ __forceinline__ int wrap_once(int x, int s) { return x < 0 ? x + s : (x >= s ? x - s : x); }
@@ -251,7 +255,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
                                            const T* __restrict__ xin, const T* __restrict__ e,
                                            T* __restrict__ x, T* __restrict__ bc, const T* c1s,
                                            const T* c2s, int tile, T* xa, T* xb) {
-  constexpr int RPT = TileCfg<TT>::RPT;
+  constexpr int RPT = TileCfg<TT>::RPT, NTH = TileCfg<TT>::NTH;
   const int H = tile_halo(MODE, steps);
   const int W = TT + 2 * H, R = W * W;
   const int nt = (s + TT - 1) / TT;
@@ -266,7 +270,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
   bool own[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int idx = tid + q * TILE_THREADS;
+    const int idx = tid + q * NTH;
     ring[q] = -1;
     own[q] = false;
     if (idx < R) {
@@ -288,7 +292,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
     const T c20 = c2s[0];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int idx = tid + q * TILE_THREADS;
+      const int idx = tid + q * NTH;
       if (idx < R) {
         d[q] = c20 * (di[q] * bb[q]);
         xa[idx] = d[q];
@@ -305,7 +309,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
     const int rmin = k - k0 + 1;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int idx = tid + q * TILE_THREADS;
+      const int idx = tid + q * NTH;
       if (ring[q] >= rmin) {
         T sum = T(0);
 #pragma unroll
@@ -323,13 +327,13 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q)
-    if (own[q]) x[gr[q]] = cur[tid + q * TILE_THREADS];
+    if (own[q]) x[gr[q]] = cur[tid + q * NTH];
   if (MODE == TILE_DOWN) {
     // residual on ring >= steps, then R = P^T into the coarse rows whose fine
     // vertex lies in the tile interior
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int idx = tid + q * TILE_THREADS;
+      const int idx = tid + q * NTH;
       if (ring[q] >= steps) {
         T sum = T(0);
 #pragma unroll
@@ -355,7 +359,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
 }
 
 template <typename T, int MODE, int TT>
-__global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
+__global__ __launch_bounds__(TileCfg<TT>::NTH) void k_vtile(TileArgs<T> a) {
   constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
   __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
   vtile_body<T, MODE, TT>(a.side, a.steps, a.val, a.dinv, a.b, a.xin, a.e, a.x, a.bc, a.c1, a.c2,
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_vtile(TileArgs<T> a) {
 // pointers address the stacked level, offset per instance by its row offsets
 // (values by 7 slots per row); c1/c2 shared, or per instance ([step][count]).
 template <typename T, int MODE, int TT>
-__global__ __launch_bounds__(TILE_THREADS) void k_bvtile(BTileLaunch<T> a) {
+__global__ __launch_bounds__(TileCfg<TT>::NTH) void k_bvtile(BTileLaunch<T> a) {
   constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
   __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
   __shared__ T c1s[TILE_MAXSTEPS], c2s[TILE_MAXSTEPS];
@@ -1476,7 +1480,7 @@ template <typename T>
 bool tile_fits(int mode, int side, int steps) {
   const int H = tile_halo(mode, steps);
   const int TT = tile_side<T>(side);
-  const int hmax = TT == 64 ? TileCfg<64>::HMAX : TileCfg<32>::HMAX;
+  const int hmax = TT == 64 ? TileCfg<64>::HMAX : (TT == 32 ? TileCfg<32>::HMAX : TileCfg<16>::HMAX);
   if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > hmax) return false;
   if (side < TT + hmax) return false;  // one wrap reaches every halo row
   return mode != TILE_DOWN || side % 2 == 0;
@@ -1485,7 +1489,7 @@ bool tile_fits(int mode, int side, int steps) {
 template <typename T, int TT>
 void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s) {
   const int nt = (a.side + TT - 1) / TT;
-  const dim3 g(nt * nt), b(TILE_THREADS);
+  const dim3 g(nt * nt), b(TileCfg<TT>::NTH);
   if (mode == TILE_ZERO) hipLaunchKernelGGL((k_vtile<T, TILE_ZERO, TT>), g, b, 0, s, a);
   else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_vtile<T, TILE_DOWN, TT>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_vtile<T, TILE_UP, TT>), g, b, 0, s, a);
@@ -1493,13 +1497,15 @@ void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 void vtile(int mode, const TileArgs<T>& a, hipStream_t s) {
+  const int tt = tile_side<T>(a.side);
   if constexpr (sizeof(T) == 4) {
-    if (tile_side<T>(a.side) == 64) {
+    if (tt == 64) {
       vtile_tt<T, 64>(mode, a, s);
       return;
     }
   }
-  vtile_tt<T, 32>(mode, a, s);
+  if (tt == 16) vtile_tt<T, 16>(mode, a, s);
+  else vtile_tt<T, 32>(mode, a, s);
 }
 
 bool btile_fits(int mode, int side, int steps) {

@@ -27,8 +27,24 @@ __device__ __forceinline__ double block_sum_any(double v, double* sh) {
   return r;
 }
 
+// Columns of a uniform width-7 row of the stacked level: computed from the
+// slice's (side, first row) when geo is given, else read.
+__device__ __forceinline__ void bcols7(int row, const int* __restrict__ col, const int2* __restrict__ geo,
+                                       size_t base, int* c) {
+  if (geo) {
+    const int2 g = geo[row >> 6];
+    p1_cols(row - g.y, g.x, c);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) c[k] += g.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+  }
+}
+
 template <typename T, int MODE, int RPT>
-__global__ void k_bstencil(int nrows, const int* __restrict__ col, const T* __restrict__ val,
+__global__ void k_bstencil(int nrows, const int* __restrict__ col, const int2* __restrict__ geo,
+                           const T* __restrict__ val,
                            const T* __restrict__ x, const T* __restrict__ b,
                            const T* __restrict__ dinv, T* __restrict__ d, T p0, T p1,
                            const T* __restrict__ cc1, const T* __restrict__ cc2,
@@ -58,8 +74,7 @@ __global__ void k_bstencil(int nrows, const int* __restrict__ col, const T* __re
     const size_t base = size_t(slice) * (64 * W7) + (row & 63);
     int c[W7];
     T v[W7];
-#pragma unroll
-    for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+    bcols7(row, col, geo, base, c);
 #pragma unroll
     for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
     T sum = T(0);
@@ -100,6 +115,7 @@ __global__ __launch_bounds__(BS) void k_bspmv_uniform(int nrows, int width, cons
 
 template <typename T, bool L_IS_M>
 __global__ __launch_bounds__(BS) void k_bch_block(int n, const int* __restrict__ col,
+                                                  const int2* __restrict__ geo,
                                                   const int* __restrict__ sinst,
                                                   const int* __restrict__ act,
                                                   const T* __restrict__ Lv, const T* __restrict__ Kv,
@@ -119,8 +135,7 @@ __global__ __launch_bounds__(BS) void k_bch_block(int n, const int* __restrict__
   const T* x2 = x + n;
   int c[W7];
   T kv[W7], mv[W7], lv[W7];
-#pragma unroll
-  for (int k = 0; k < W7; ++k) c[k] = col[base + k * 64];
+  bcols7(row, col, geo, base, c);
 #pragma unroll
   for (int k = 0; k < W7; ++k) {
     kv[k] = Kv[base + k * 64];
@@ -148,6 +163,7 @@ __global__ __launch_bounds__(BS) void k_bch_block(int n, const int* __restrict__
 }
 
 __global__ __launch_bounds__(BS) void k_brhs_binary(int n, const int* __restrict__ col,
+                                                    const int2* __restrict__ geo,
                                                     const int* __restrict__ sinst,
                                                     const double* __restrict__ Mv,
                                                     const double* __restrict__ phi,
@@ -162,9 +178,11 @@ __global__ __launch_bounds__(BS) void k_brhs_binary(int n, const int* __restrict
   const int inst = sinst[row >> 6];
   const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
   double s_phi = 0.0, s_fp = 0.0, s_Phi = 0.0, s_fv = 0.0;
+  int cc[W7];
+  bcols7(row, col, geo, base, cc);
 #pragma unroll
   for (int k = 0; k < W7; ++k) {
-    const int j = col[base + k * 64];
+    const int j = cc[k];
     const double m = Mv[base + k * 64];
     const double ph = phi[j], P = Phi[j];
     const double om = 1.0 - ph;
@@ -626,13 +644,13 @@ static void launch_bstencil(const BStencil& A, const T* val, const T* x, const T
   const int rows_per_block = A.block * A.rpt;
   const dim3 g(ceil_div(A.nrows, rows_per_block)), blk(A.block);
   if (A.rpt == 4)
-    hipLaunchKernelGGL((k_bstencil<T, MODE, 4>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
+    hipLaunchKernelGGL((k_bstencil<T, MODE, 4>), g, blk, 0, s, A.nrows, A.col, A.geo, val, x, b, dinv, d,
                        p0, p1, cc1, cc2, mask, act, A.sinst, y);
   else if (A.rpt == 2)
-    hipLaunchKernelGGL((k_bstencil<T, MODE, 2>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
+    hipLaunchKernelGGL((k_bstencil<T, MODE, 2>), g, blk, 0, s, A.nrows, A.col, A.geo, val, x, b, dinv, d,
                        p0, p1, cc1, cc2, mask, act, A.sinst, y);
   else
-    hipLaunchKernelGGL((k_bstencil<T, MODE, 1>), g, blk, 0, s, A.nrows, A.col, val, x, b, dinv, d,
+    hipLaunchKernelGGL((k_bstencil<T, MODE, 1>), g, blk, 0, s, A.nrows, A.col, A.geo, val, x, b, dinv, d,
                        p0, p1, cc1, cc2, mask, act, A.sinst, y);
 }
 
@@ -661,10 +679,10 @@ void bch_block(const BStencil& A, const T* L, const T* K, const T* M, const T* c
                const int* act, const T* x, T alpha, T beta, T* y, hipStream_t s) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (L == M)
-    hipLaunchKernelGGL((k_bch_block<T, true>), g, blk, 0, s, A.nrows, A.col, A.sinst, act, L, K, M,
+    hipLaunchKernelGGL((k_bch_block<T, true>), g, blk, 0, s, A.nrows, A.col, A.geo, A.sinst, act, L, K, M,
                        c12, c22, x, alpha, beta, y);
   else
-    hipLaunchKernelGGL((k_bch_block<T, false>), g, blk, 0, s, A.nrows, A.col, A.sinst, act, L, K, M,
+    hipLaunchKernelGGL((k_bch_block<T, false>), g, blk, 0, s, A.nrows, A.col, A.geo, A.sinst, act, L, K, M,
                        c12, c22, x, alpha, beta, y);
 }
 
@@ -676,7 +694,7 @@ void bconvert(int64_t n, const TI* x, TO* y, const int* cinst, const int* act, h
 void brhs_binary(const BStencil& A, const double* Mv, const double* phi, const double* Phi,
                  const double* c_mu, const double* c_ac, double* rhs_ch, double* rhs_ac,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_brhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col,
+  hipLaunchKernelGGL(k_brhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.col, A.geo,
                      A.sinst, Mv, phi, Phi, c_mu, c_ac, rhs_ch, rhs_ac);
 }
 

@@ -21,6 +21,10 @@ struct BStencil {
   int nrows = 0;
   const int* col = nullptr;
   const int* sinst = nullptr;     // slice -> instance
+  // slice -> (instance's level side, instance's first row): when given, the
+  // kernels compute the P1 columns (periodic side x side block in neighbour
+  // order) instead of reading col; only for levels without padding rows
+  const int2* geo = nullptr;
   int rpt = 1;                    // rows per thread (1, 2, 4)
   int block = 256;                // workgroup size
 };
