@@ -411,7 +411,7 @@ __device__ __forceinline__ int tail_off(const int* side, int t) {
 // dependent steps only a workgroup barrier is needed, where each step of the
 // launch-per-step cycle pays a kernel launch.
 template <typename T, int RPT>
-__device__ void vtail_body(const TailArgs<T>* ka, const T* bbase, T* xbase) {
+__device__ __forceinline__ void vtail_body(const TailArgs<T>* ka, const T* bbase, T* xbase) {
   __shared__ T lds[TAIL_LDS / sizeof(T)];
   __shared__ TailArgs<T> a;
   const int tid = threadIdx.x;
