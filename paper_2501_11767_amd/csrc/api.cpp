@@ -493,6 +493,70 @@ bool vcycle_tail(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
 
 template <typename T>
 void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T* x,
+            const chns_solve_opts& o, hipStream_t s);
+
+// Levels l and l + 1 both smoothing, below the 64 x 64 tiles and above the
+// tail: one launch for both down passes, the coarser levels, one for both up
+// passes.  False when they do not qualify.
+template <typename T>
+bool vcycle_pair(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T* x,
+                 const chns_solve_opts& o, hipStream_t s) {
+  if (l + 1 >= cut || l + 2 >= c->lv.size()) return false;
+  Level& L = c->lv[l];
+  Level& G = c->lv[l + 1];
+  Level& GG = c->lv[l + 2];
+  const int side = L.d.side;
+  if (side <= 0 || G.d.side != side / 2 || GG.d.side != side / 4) return false;
+  if (tile_side<T>(side) == 64 || !tile2_fits(side, o.mg_pre, o.mg_post)) return false;
+  {  // the tail would start at l + 1: keep the level-by-level kernels
+    const int nlev = int(cut - l);
+    if (nlev <= TAIL_MAXLEV) {
+      int sides[TAIL_MAXLEV];
+      bool all = true;
+      for (int t = 0; t < nlev; ++t) {
+        sides[t] = c->lv[l + 1 + t].d.side;
+        all = all && sides[t] > 0;
+      }
+      if (all && tail_fits<T>(sides, nlev)) return false;
+    }
+  }
+  const OpVals& A = L.*op;
+  const OpVals& AG = G.*op;
+  Tile2Args<T> a;
+  a.side = side;
+  a.valf = Sel<T>::v(A);
+  a.dinvf = Sel<T>::d(A);
+  a.bf = b;
+  a.valc = Sel<T>::v(AG);
+  a.dinvc = Sel<T>::d(AG);
+  a.bc = Sel<T>::b(G);
+  a.xc = Sel<T>::t(G);
+  const ChebCoef<T> pre = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre);
+  a.steps = o.mg_pre;
+  for (int k = 0; k < o.mg_pre; ++k) {
+    a.c1[k] = pre.c1[k];
+    a.c2[k] = pre.c2[k];
+  }
+  a.xf = Sel<T>::t(L);
+  a.bcc = Sel<T>::b(GG);
+  vdown2<T>(a, s);
+  vcycle<T>(c, op, l + 2, cut, Sel<T>::b(GG), Sel<T>::x(GG), o, s);
+  const ChebCoef<T> post = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post);
+  a.steps = o.mg_post;
+  for (int k = 0; k < o.mg_post; ++k) {
+    a.c1[k] = post.c1[k];
+    a.c2[k] = post.c2[k];
+  }
+  a.xinf = Sel<T>::t(L);
+  a.e = Sel<T>::x(GG);
+  a.xf = x;
+  a.bcc = nullptr;
+  vup2<T>(a, s);
+  return true;
+}
+
+template <typename T>
+void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T* x,
             const chns_solve_opts& o, hipStream_t s) {
   Level& L = c->lv[l];
   const OpVals& A = L.*op;
@@ -510,6 +574,7 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
     cheb_from_zero<T>(c, L, A, b, x, cc, s);
     return;
   }
+  if (vcycle_pair<T>(c, op, l, cut, b, x, o, s)) return;
   if (L.d.side > 0 && tile_fits<T>(TILE_DOWN, L.d.side, o.mg_pre) &&
       tile_fits<T>(TILE_UP, L.d.side, o.mg_post)) {
     // two launches per level: pre-smoothing, residual and restriction in one,

@@ -229,15 +229,6 @@ template <int TT> struct TileCfg;
 template <> struct TileCfg<64> { static constexpr int HMAX = 4, RPT = 6, NTH = 1024; };
 template <> struct TileCfg<32> { static constexpr int HMAX = 8, RPT = 3, NTH = 1024; };
 template <> struct TileCfg<16> { static constexpr int HMAX = 8, RPT = 4, NTH = 256; };
-// float levels of at least this side take 64 x 64 tiles (256 or more tiles);
-// levels of at most TILE16_MAX_SIDE take 16 x 16 tiles
-constexpr int TILE64_MIN_SIDE = 1024;
-constexpr int TILE16_MAX_SIDE = 256;
-template <typename T>
-inline int tile_side(int side) {
-  if (sizeof(T) == 4 && side >= TILE64_MIN_SIDE) return 64;
-  return side <= TILE16_MAX_SIDE ? 16 : 32;
-}
 
 __device__ __forceinline__ int wrap_once(int x, int s) { return x < 0 ? x + s : (x >= s ? x - s : x); }
 
@@ -386,6 +377,297 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_bvtile(BTileLaunch<T> a) {
   vtile_body<T, MODE, TT>(t.side, a.steps, a.val + r * W7, a.dinv + r, a.b + r, a.xin ? a.xin + r : nullptr,
                           a.e ? a.e + rc : nullptr, a.x + r, a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile,
                           xa, xb);
+}
+
+// ------------------------------------------------------------------ paired levels
+
+// Two consecutive smoothing levels per launch: a 32 x 32 fine tile and the
+// 16 x 16 coarse tile under it.  Region sizes for up to T2_PMAX pre / post
+// steps; every workgroup has 1024 threads.
+constexpr int T2_TT = 32, T2_TC = 16, T2_PMAX = 3;
+constexpr int T2_WF = T2_TT + 2 * (3 * T2_PMAX + 3);                  // down2 fine region side
+constexpr int T2_WC = T2_TC + 2 * (T2_PMAX + 1);                      // down2 coarse region side
+constexpr int T2_WCU = T2_TC + 2 * ((T2_PMAX + 1) / 2 + 1 + T2_PMAX);  // up2 coarse region side
+constexpr int T2_WFU = T2_TT + 2 * T2_PMAX;                           // up2 fine region side
+constexpr int T2_RPTF = (T2_WF * T2_WF + 1023) / 1024;
+constexpr int T2_RPTU = (T2_WFU * T2_WFU + 1023) / 1024;
+static_assert(T2_WC * T2_WC <= 1024 && T2_WCU * T2_WCU <= 1024, "one coarse row per thread");
+
+// down2: fine pre-smoothing from zero over a halo of Hf = 3P + 3 rings (the
+// residual must hold on the fine points restricted into the coarse region),
+// coarse right-hand side on the coarse region (halo Hc = P + 1), coarse
+// pre-smoothing, residual and restriction to the level below.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_vdown2(Tile2Args<T> a) {
+  __shared__ T fx[T2_WF * T2_WF], fy[T2_WF * T2_WF];
+  __shared__ T cx[T2_WC * T2_WC], cy[T2_WC * T2_WC];
+  const int s = a.side, sc = s >> 1, scc = sc >> 1, P = a.steps;
+  const int Hc = P + 1, Hf = 3 * P + 3;
+  const int Wf = T2_TT + 2 * Hf, Rf = Wf * Wf;
+  const int Wc = T2_TC + 2 * Hc, Rc = Wc * Wc;
+  const int nt = (s + T2_TT - 1) / T2_TT;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int ty = tile / nt, tx = tile - ty * nt;
+  const int i0 = tx * T2_TT - Hf, j0 = ty * T2_TT - Hf;
+  const int ci0 = tx * T2_TC - Hc, cj0 = ty * T2_TC - Hc;
+  const int tid = threadIdx.x;
+  const int offf[W7] = {0, -Wf - 1, -Wf, -1, 1, Wf, Wf + 1};
+  const int offc[W7] = {0, -Wc - 1, -Wc, -1, 1, Wc, Wc + 1};
+  T v[T2_RPTF][W7], di[T2_RPTF], bb[T2_RPTF], d[T2_RPTF];
+  int gr[T2_RPTF], ring[T2_RPTF];
+  bool own[T2_RPTF];
+#pragma unroll
+  for (int q = 0; q < T2_RPTF; ++q) {
+    const int idx = tid + q * 1024;
+    ring[q] = -1;
+    own[q] = false;
+    if (idx < Rf) {
+      const int rj = idx / Wf, ri = idx - rj * Wf;
+      const int gi = wrap_once(i0 + ri, s), gj = wrap_once(j0 + rj, s);
+      const int row = gi + s * gj;
+      gr[q] = row;
+      ring[q] = min(min(ri, rj), min(Wf - 1 - ri, Wf - 1 - rj));
+      own[q] = ring[q] >= Hf && tx * T2_TT + (ri - Hf) < s && ty * T2_TT + (rj - Hf) < s;
+      const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) v[q][k] = a.valf[base + k * 64];
+      di[q] = a.dinvf[row];
+      bb[q] = a.bf[row];
+    }
+  }
+  // this thread's coarse row, loaded with the fine rows
+  T cv[W7], cdi = T(0), cd = T(0), cbv = T(0);
+  int cring = -1, crow = 0;
+  bool cown = false;
+  int cri = 0, crj = 0;
+  if (tid < Rc) {
+    crj = tid / Wc;
+    cri = tid - crj * Wc;
+    const int cgi = wrap_once(ci0 + cri, sc), cgj = wrap_once(cj0 + crj, sc);
+    crow = cgi + sc * cgj;
+    cring = min(min(cri, crj), min(Wc - 1 - cri, Wc - 1 - crj));
+    cown = cring >= Hc && tx * T2_TC + (cri - Hc) < sc && ty * T2_TC + (crj - Hc) < sc;
+    const size_t base = size_t(crow >> 6) * (64 * W7) + (crow & 63);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) cv[k] = a.valc[base + k * 64];
+    cdi = a.dinvc[crow];
+  }
+  // fine pre-smoothing from zero on shrinking rings
+  {
+    const T c20 = a.c2[0];
+#pragma unroll
+    for (int q = 0; q < T2_RPTF; ++q) {
+      const int idx = tid + q * 1024;
+      if (idx < Rf) {
+        d[q] = c20 * (di[q] * bb[q]);
+        fx[idx] = d[q];
+      }
+    }
+  }
+  __syncthreads();
+  T* cur = fx;
+  T* nxt = fy;
+  for (int k = 1; k < P; ++k) {
+    const T c1 = a.c1[k], c2 = a.c2[k];
+#pragma unroll
+    for (int q = 0; q < T2_RPTF; ++q) {
+      const int idx = tid + q * 1024;
+      if (ring[q] >= k) {
+        T sum = T(0);
+#pragma unroll
+        for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + offf[m]];
+        const T r = di[q] * (bb[q] - sum);
+        const T dn = c1 * d[q] + c2 * r;
+        d[q] = dn;
+        nxt[idx] = cur[idx] + dn;
+      }
+    }
+    __syncthreads();
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+#pragma unroll
+  for (int q = 0; q < T2_RPTF; ++q)
+    if (own[q]) a.xf[gr[q]] = cur[tid + q * 1024];
+#pragma unroll
+  for (int q = 0; q < T2_RPTF; ++q) {
+    const int idx = tid + q * 1024;
+    if (ring[q] >= P) {
+      T sum = T(0);
+#pragma unroll
+      for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + offf[m]];
+      nxt[idx] = bb[q] - sum;
+    }
+  }
+  __syncthreads();
+  // coarse right-hand side (R = P^T) on the coarse region: the fine vertex
+  // of coarse point (cri, crj) sits at fine-region column P + 1 + 2 cri
+  if (tid < Rc) {
+    const int f = (P + 1 + 2 * cri) + Wf * (P + 1 + 2 * crj);
+    T sm = T(0);
+#pragma unroll
+    for (int m = 1; m < W7; ++m) sm += nxt[f + offf[m]];
+    cbv = nxt[f] + T(0.5) * sm;
+    if (cown) a.bc[crow] = cbv;
+    cd = a.c2[0] * (cdi * cbv);
+    cx[tid] = cd;
+  }
+  __syncthreads();
+  T* ccur = cx;
+  T* cnxt = cy;
+  for (int k = 1; k < P; ++k) {
+    if (cring >= k) {
+      T sum = T(0);
+#pragma unroll
+      for (int m = 0; m < W7; ++m) sum += cv[m] * ccur[tid + offc[m]];
+      const T r = cdi * (cbv - sum);
+      cd = a.c1[k] * cd + a.c2[k] * r;
+      cnxt[tid] = ccur[tid] + cd;
+    }
+    __syncthreads();
+    T* t = ccur;
+    ccur = cnxt;
+    cnxt = t;
+  }
+  if (cown) a.xc[crow] = ccur[tid];
+  if (cring >= P) {
+    T sum = T(0);
+#pragma unroll
+    for (int m = 0; m < W7; ++m) sum += cv[m] * ccur[tid + offc[m]];
+    cnxt[tid] = cbv - sum;
+  }
+  __syncthreads();
+  constexpr int TCC = T2_TC / 2;
+  if (tid < TCC * TCC) {
+    const int lj = tid / TCC, li = tid - lj * TCC;
+    const int I = tx * TCC + li, J = ty * TCC + lj;
+    if (I < scc && J < scc) {
+      const int q = (2 * li + Hc) + Wc * (2 * lj + Hc);
+      T sm = T(0);
+#pragma unroll
+      for (int m = 1; m < W7; ++m) sm += cnxt[q + offc[m]];
+      a.bcc[I + scc * J] = cnxt[q] + T(0.5) * sm;
+    }
+  }
+}
+
+// up2: coarse correction x_c + P e and post-smoothing on a coarse region of
+// halo Hcu = D + Q (D = (Q + 1) / 2 + 1 coarse rings feed the fine
+// interpolation), then the fine correction and post-smoothing (halo Q).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
+  __shared__ T fx[T2_WFU * T2_WFU], fy[T2_WFU * T2_WFU];
+  __shared__ T cx[T2_WCU * T2_WCU], cy[T2_WCU * T2_WCU];
+  const int s = a.side, sc = s >> 1, scc = sc >> 1, Q = a.steps;
+  const int D = (Q + 1) / 2 + 1, Hcu = D + Q;
+  const int W = T2_TT + 2 * Q, R = W * W;
+  const int Wc = T2_TC + 2 * Hcu, Rc = Wc * Wc;
+  const int nt = (s + T2_TT - 1) / T2_TT;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int ty = tile / nt, tx = tile - ty * nt;
+  const int i0 = tx * T2_TT - Q, j0 = ty * T2_TT - Q;
+  const int ci0 = tx * T2_TC - Hcu, cj0 = ty * T2_TC - Hcu;
+  const int tid = threadIdx.x;
+  const int off[W7] = {0, -W - 1, -W, -1, 1, W, W + 1};
+  const int offc[W7] = {0, -Wc - 1, -Wc, -1, 1, Wc, Wc + 1};
+  // coarse row: corrected iterate into LDS
+  T cv[W7], cdi = T(0), cd = T(0), cbv = T(0);
+  int cring = -1;
+  if (tid < Rc) {
+    const int crj = tid / Wc, cri = tid - crj * Wc;
+    const int cgi = wrap_once(ci0 + cri, sc), cgj = wrap_once(cj0 + crj, sc);
+    const int crow = cgi + sc * cgj;
+    cring = min(min(cri, crj), min(Wc - 1 - cri, Wc - 1 - crj));
+    const size_t base = size_t(crow >> 6) * (64 * W7) + (crow & 63);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) cv[k] = a.valc[base + k * 64];
+    cdi = a.dinvc[crow];
+    cbv = a.bc[crow];
+    cx[tid] = a.xc[crow] + p1_interp(a.e, cgi, cgj, scc);
+  }
+  // fine rows: operands now, corrections after the coarse smoothing
+  T v[T2_RPTU][W7], di[T2_RPTU], bb[T2_RPTU], d[T2_RPTU], xi[T2_RPTU];
+  int gr[T2_RPTU], ring[T2_RPTU];
+  bool own[T2_RPTU];
+#pragma unroll
+  for (int q = 0; q < T2_RPTU; ++q) {
+    const int idx = tid + q * 1024;
+    ring[q] = -1;
+    own[q] = false;
+    if (idx < R) {
+      const int rj = idx / W, ri = idx - rj * W;
+      const int gi = wrap_once(i0 + ri, s), gj = wrap_once(j0 + rj, s);
+      const int row = gi + s * gj;
+      gr[q] = row;
+      ring[q] = min(min(ri, rj), min(W - 1 - ri, W - 1 - rj));
+      own[q] = ring[q] >= Q && tx * T2_TT + (ri - Q) < s && ty * T2_TT + (rj - Q) < s;
+      const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) v[q][k] = a.valf[base + k * 64];
+      di[q] = a.dinvf[row];
+      bb[q] = a.bf[row];
+      xi[q] = a.xinf[row];
+    }
+  }
+  __syncthreads();
+  T* ccur = cx;
+  T* cnxt = cy;
+  for (int k = 0; k < Q; ++k) {
+    if (cring >= k + 1) {
+      T sum = T(0);
+#pragma unroll
+      for (int m = 0; m < W7; ++m) sum += cv[m] * ccur[tid + offc[m]];
+      const T r = cdi * (cbv - sum);
+      cd = (k == 0) ? a.c2[0] * r : a.c1[k] * cd + a.c2[k] * r;
+      cnxt[tid] = ccur[tid] + cd;
+    }
+    __syncthreads();
+    T* t = ccur;
+    ccur = cnxt;
+    cnxt = t;
+  }
+  // fine correction: P1 interpolation of the coarse result (fine-region
+  // column ri maps to coarse-region column floor((ri - Q) / 2) + Hcu)
+#pragma unroll
+  for (int q = 0; q < T2_RPTU; ++q) {
+    const int idx = tid + q * 1024;
+    if (idx < R) {
+      const int rj = idx / W, ri = idx - rj * W;
+      const int ai = ri - Q, aj = rj - Q;
+      const int qi = ((ai + 2 * Q) >> 1) - Q + Hcu, qj = ((aj + 2 * Q) >> 1) - Q + Hcu;
+      const int oi = ai & 1, oj = aj & 1;
+      const T e0 = ccur[qi + Wc * qj];
+      const T val = (oi | oj) ? T(0.5) * (e0 + ccur[(qi + oi) + Wc * (qj + oj)]) : e0;
+      fx[idx] = xi[q] + val;
+    }
+  }
+  __syncthreads();
+  T* cur = fx;
+  T* nxt = fy;
+  for (int k = 0; k < Q; ++k) {
+    const T c1 = a.c1[k], c2 = a.c2[k];
+#pragma unroll
+    for (int q = 0; q < T2_RPTU; ++q) {
+      const int idx = tid + q * 1024;
+      if (ring[q] >= k + 1) {
+        T sum = T(0);
+#pragma unroll
+        for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + off[m]];
+        const T r = di[q] * (bb[q] - sum);
+        const T dn = (k == 0) ? c2 * r : c1 * d[q] + c2 * r;
+        d[q] = dn;
+        nxt[idx] = cur[idx] + dn;
+      }
+    }
+    __syncthreads();
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+#pragma unroll
+  for (int q = 0; q < T2_RPTU; ++q)
+    if (own[q]) a.xf[gr[q]] = cur[tid + q * 1024];
 }
 
 // ------------------------------------------------------------------ V-cycle tail
@@ -1508,6 +1790,24 @@ void vtile(int mode, const TileArgs<T>& a, hipStream_t s) {
   else vtile_tt<T, 32>(mode, a, s);
 }
 
+bool tile2_fits(int side, int pre, int post) {
+  // both levels even (the coarse one restricts again); one wrap reaches
+  // every halo row of both regions
+  return side % 4 == 0 && side >= 64 && pre >= 1 && pre <= T2_PMAX && post >= 0 && post <= T2_PMAX;
+}
+
+template <typename T>
+void vdown2(const Tile2Args<T>& a, hipStream_t s) {
+  const int nt = (a.side + T2_TT - 1) / T2_TT;
+  hipLaunchKernelGGL((k_vdown2<T>), dim3(nt * nt), dim3(1024), 0, s, a);
+}
+
+template <typename T>
+void vup2(const Tile2Args<T>& a, hipStream_t s) {
+  const int nt = (a.side + T2_TT - 1) / T2_TT;
+  hipLaunchKernelGGL((k_vup2<T>), dim3(nt * nt), dim3(1024), 0, s, a);
+}
+
 bool btile_fits(int mode, int side, int steps) {
   const int H = tile_halo(mode, steps);
   if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > TileCfg<32>::HMAX)
@@ -1793,6 +2093,10 @@ template void bvtail<double>(int, const TailArgs<double>*, const int*, const int
                              hipStream_t);
 template void bvtail<float>(int, const TailArgs<float>*, const int*, const int*, const float*, float*,
                             hipStream_t);
+template void vdown2<double>(const Tile2Args<double>&, hipStream_t);
+template void vdown2<float>(const Tile2Args<float>&, hipStream_t);
+template void vup2<double>(const Tile2Args<double>&, hipStream_t);
+template void vup2<float>(const Tile2Args<float>&, hipStream_t);
 template bool tile_fits<double>(int, int, int);
 template bool tile_fits<float>(int, int, int);
 template void vtile<double>(int, const TileArgs<double>&, hipStream_t);

@@ -131,11 +131,57 @@ struct TileArgs {
   T c1[TILE_MAXSTEPS] = {};
   T c2[TILE_MAXSTEPS] = {};
 };
+// Tile side of a level: float levels of side >= 1024 take 64 x 64 tiles
+// (256 or more tiles), levels of side <= 256 take 16 x 16 tiles (256-thread
+// workgroups), the others 32 x 32.
+constexpr int TILE64_MIN_SIDE = 1024;
+constexpr int TILE16_MAX_SIDE = 256;
+template <typename T>
+inline int tile_side(int side) {
+  if (sizeof(T) == 4 && side >= TILE64_MIN_SIDE) return 64;
+  return side <= TILE16_MAX_SIDE ? 16 : 32;
+}
 // Whether a level of this side takes the tiled kernel of `mode` with `steps`.
 template <typename T>
 bool tile_fits(int mode, int side, int steps);
 template <typename T>
 void vtile(int mode, const TileArgs<T>& a, hipStream_t s);
+
+// Two consecutive smoothing levels in one launch (32 x 32 fine tiles, the
+// 16 x 16 coarse tile under each):
+//   down2: pre-smoothing, residual and restriction on the fine level over a
+//     halo of 3 pre + 3 rings, then on the coarse region it restricts to
+//     (halo pre + 1); writes the fine and coarse pre-smoothed iterates (xf,
+//     xc), the coarse right-hand side (bc) and that of the level below (bcc).
+//   up2: coarse correction by e (level below) and post-smoothing on a coarse
+//     region of halo (post + 1) / 2 + 1 + post, then the fine correction and
+//     post-smoothing; writes the fine result xf.
+// The rows computed are those of the level-by-level kernels (the halos
+// recomputed by every tile that touches them).
+template <typename T>
+struct Tile2Args {
+  int side = 0, steps = 0;  // fine side; pre (down2) or post (up2) steps
+  const T* valf = nullptr;
+  const T* dinvf = nullptr;
+  const T* bf = nullptr;
+  const T* xinf = nullptr;  // up2: fine pre-smoothed iterate
+  T* xf = nullptr;
+  const T* valc = nullptr;
+  const T* dinvc = nullptr;
+  T* bc = nullptr;          // down2 writes, up2 reads
+  T* xc = nullptr;          // down2 writes, up2 reads (pre-smoothed coarse iterate)
+  T* bcc = nullptr;         // down2: right-hand side of the level below
+  const T* e = nullptr;     // up2: result of the level below
+  T c1[TILE_MAXSTEPS] = {};
+  T c2[TILE_MAXSTEPS] = {};
+};
+// Whether two levels (fine side `side`) take the paired kernels with pre and
+// post steps.
+bool tile2_fits(int side, int pre, int post);
+template <typename T>
+void vdown2(const Tile2Args<T>& a, hipStream_t s);
+template <typename T>
+void vup2(const Tile2Args<T>& a, hipStream_t s);
 
 // Batched tiled kernels (32 x 32 tiles): one workgroup per entry of a tile
 // list; each entry names its instance, its tile, the instance's level side and
