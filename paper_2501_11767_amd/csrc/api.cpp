@@ -507,7 +507,9 @@ bool vcycle_pair(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
   Level& GG = c->lv[l + 2];
   const int side = L.d.side;
   if (side <= 0 || G.d.side != side / 2 || GG.d.side != side / 4) return false;
-  if (tile_side<T>(side) == 64 || !tile2_fits(side, o.mg_pre, o.mg_post)) return false;
+  // the paired kernels recompute wide halos: only for latency-bound levels
+  if (tile_side<T>(side) == 64 || side > TILE64_MIN_SIDE / 2 || !tile2_fits(side, o.mg_pre, o.mg_post))
+    return false;
   {  // the tail would start at l + 1: keep the level-by-level kernels
     const int nlev = int(cut - l);
     if (nlev <= TAIL_MAXLEV) {
