@@ -791,10 +791,57 @@ void ch_precond_t(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_so
   mg_solve<T>(c, &Level::X, tmp2, z + N, o, s);
 }
 
-// Preconditioner of a block: z = P^{-1} r.  When inv is given, r is first
-// scaled in place by inv[0] (fused with the FP32 conversion in mixed
-// precision): the Krylov basis vector is normalised on its way in.
-int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, double* r, const double* inv,
+// One V-cycle of op whose finest level takes the tiled down and up passes,
+// with the FP64 boundary at that level: the right-hand side read from b64
+// when given (else b), the result written to x64 times xs[0] when x64 is
+// given (else to x).
+template <typename T>
+void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const double* b64, T* x,
+                double* x64, const double* xs, const chns_solve_opts& o, hipStream_t s) {
+  Level& L = c->lv[0];
+  Level& G = c->lv[1];
+  const OpVals& A = L.*op;
+  TileArgs<T> dn = tile_args<T>(L, A, o.mg_pre, cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre));
+  dn.b = b;
+  dn.b64 = b64;
+  dn.x = Sel<T>::t(L);
+  dn.bc = Sel<T>::b(G);
+  vtile<T>(TILE_DOWN, dn, s);
+  vcycle<T>(c, op, 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
+  TileArgs<T> up = tile_args<T>(L, A, o.mg_post, cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post));
+  up.b = b;
+  up.b64 = b64;
+  up.xin = Sel<T>::t(L);
+  up.e = Sel<T>::x(G);
+  up.x = x;
+  up.x64 = x64;
+  up.xs = xs;
+  vtile<T>(TILE_UP, up, s);
+}
+
+// Whether the FP32 cycles of a block can take their FP64 input and write
+// their FP64 output inside the finest level's tiled launches: one cycle per
+// inner solve, a finest level of 64 x 64 tiles, the mass-like inverses ((1,1)
+// block of CH, the AC matrix) cut on the finest level, X not.
+bool fused_mixed(chns_ctx* c, int block, const chns_solve_opts& o) {
+  const int side = c->lv[0].d.side;
+  if (o.precision == CHNS_F64 || o.mg_cycles != 1 || side < TILE64_MIN_SIDE || c->lv.size() < 2) return false;
+  const int z = std::min(o.mg_pre + o.mg_post, MAXCHEB);
+  auto cut0 = [&](OpVals Level::*op) {
+    return cut_level(c, coef_of(c, op), o.mg_rho_cut) == 0 && tile_fits<float>(TILE_ZERO, side, z);
+  };
+  if (block == CHNS_BLOCK_AC) return c->mesh.model != CHNS_MODEL_CH && cut0(&Level::AC);
+  if (block != CHNS_BLOCK_CH) return false;
+  return cut0(&Level::L) && cut_level(c, coef_of(c, &Level::X), o.mg_rho_cut) > 0 &&
+         tile_fits<float>(TILE_DOWN, side, o.mg_pre) && tile_fits<float>(TILE_UP, side, o.mg_post);
+}
+
+// Preconditioner of a block: z = inv[0] P^{-1} r (inv may be null: 1); r is
+// not written.  The Krylov basis vector arrives unnormalised and its 1/|w|
+// rides on the output (P is linear).  In mixed precision the FP32 cycles read
+// r and write z through the finest level's tiles where fused_mixed() holds,
+// else through conversion passes.
+int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, const double* inv,
                    double* z, hipStream_t s) {
   const int N = c->N;
   int64_t n = 0;
@@ -803,13 +850,29 @@ int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, double* r, 
   else if (block == CHNS_BLOCK_NS && c->ternary) n = 9 * int64_t(N);
   else return fail(c, CHNS_EUNSUPPORTED, "block not available");
   const bool f64 = o.precision == CHNS_F64;
-  if (f64) {
-    if (inv) scale_by_inv(n, r, inv, r, s);
-  } else if (inv) {
-    convert_scaled(n, r, inv, c->r32, s);
-  } else {
-    convert<double, float>(n, r, c->r32, s);
+  if (fused_mixed(c, block, o)) {
+    Level& L0 = c->lv[0];
+    const int z0 = std::min(o.mg_pre + o.mg_post, MAXCHEB);
+    auto zero_cut = [&](OpVals Level::*op, const double* b, double* x) {
+      TileArgs<float> a = tile_args<float>(L0, L0.*op, z0, cut_coef<float>(c, op, 0, o));
+      a.b64 = b;
+      a.x64 = x;
+      a.xs = inv;
+      vtile<float>(TILE_ZERO, a, s);
+    };
+    if (block == CHNS_BLOCK_AC) {
+      zero_cut(&Level::AC, r, z);
+    } else {
+      const size_t cutX = cut_level(c, coef_of(c, &Level::X), o.mg_rho_cut);
+      zero_cut(&Level::L, r, z);
+      vcycle_top<float>(c, &Level::X, cutX, nullptr, r + N, c->w32a, nullptr, nullptr, o, s);
+      spmv<float, float>(L0.d, Sel<float>::M(L0), c->w32a, c->w32b, 1.0f, 0.0f, s);
+      vcycle_top<float>(c, &Level::X, cutX, c->w32b, nullptr, nullptr, z + N, inv, o, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    return CHNS_OK;
   }
+  if (!f64) convert<double, float>(n, r, c->r32, s);
   if (block == CHNS_BLOCK_CH) {
     if (f64) ch_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
     else ch_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
@@ -820,14 +883,18 @@ int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, double* r, 
     if (f64) ns_precond_t<double>(c, r, z, c->w64a, c->w64b, o, s);
     else ns_precond_t<float>(c, c->r32, c->z32, c->w32a, c->w32b, o, s);
   }
-  if (!f64) convert<float, double>(n, c->z32, z, s);
+  if (f64) {
+    if (inv) scale_by_inv(n, z, inv, z, s);
+  } else {
+    convert_out(n, c->z32, inv, z, s);
+  }
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
 
 int precond(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, double* z,
             hipStream_t s) {
-  return precond_scaled(c, block, o, const_cast<double*>(r), nullptr, z, s);  // r not written
+  return precond_scaled(c, block, o, r, nullptr, z, s);
 }
 
 int64_t block_size(chns_ctx* c, int block) {
@@ -932,12 +999,16 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       double* vj = K.V + j * ld;
       double* vn = K.V + (j + 1) * ld;
       double* zj = K.Z + j * ld;
-      TRY(precond_scaled(c, block, o, vj, j > 0 ? K.scal + 1 : nullptr, zj, s));
+      // v_j is stored unnormalised (j > 0): its 1/|w| scales the preconditioner's
+      // output and is applied on load by the two Gram-Schmidt passes, which
+      // store v_j normalised
+      const double* vsc = j > 0 ? K.scal + 1 : nullptr;
+      st.vscale = vsc;
+      TRY(precond_scaled(c, block, o, vj, vsc, zj, s));
       TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
       // DCGS2: one dot pass and one update pass over the basis (the previous
       // vector's reorthogonalisation rides along with w's projection); the
-      // end-of-step scalars land in the pinned host slot, and w is scaled by
-      // 1/|w| in the input stage of the next step's preconditioner
+      // end-of-step scalars land in the pinned host slot
       const int kk0 = j < 16 ? j : 16;
       timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (kk0 + 2), s,
             [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, st, s, ev); });

@@ -245,7 +245,10 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
                                            const T* __restrict__ dinv, const T* __restrict__ b,
                                            const T* __restrict__ xin, const T* __restrict__ e,
                                            T* __restrict__ x, T* __restrict__ bc, const T* c1s,
-                                           const T* c2s, int tile, T* xa, T* xb) {
+                                           const T* c2s, int tile, T* xa, T* xb,
+                                           const double* __restrict__ b64 = nullptr,
+                                           double* __restrict__ x64 = nullptr,
+                                           const double* __restrict__ xs = nullptr) {
   constexpr int RPT = TileCfg<TT>::RPT, NTH = TileCfg<TT>::NTH;
   const int H = tile_halo(MODE, steps);
   const int W = TT + 2 * H, R = W * W;
@@ -275,7 +278,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
 #pragma unroll
       for (int k = 0; k < W7; ++k) v[q][k] = val[base + k * 64];
       di[q] = dinv[row];
-      bb[q] = b[row];
+      bb[q] = b64 ? T(b64[row]) : b[row];
       if (MODE == TILE_UP) xa[idx] = xin[row] + p1_interp(e, gi, gj, s >> 1);
     }
   }
@@ -316,9 +319,16 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
     cur = nxt;
     nxt = t;
   }
+  if (x64) {
+    const double sc = xs ? xs[0] : 1.0;
 #pragma unroll
-  for (int q = 0; q < RPT; ++q)
-    if (own[q]) x[gr[q]] = cur[tid + q * NTH];
+    for (int q = 0; q < RPT; ++q)
+      if (own[q]) x64[gr[q]] = double(cur[tid + q * NTH]) * sc;
+  } else {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (own[q]) x[gr[q]] = cur[tid + q * NTH];
+  }
   if (MODE == TILE_DOWN) {
     // residual on ring >= steps, then R = P^T into the coarse rows whose fine
     // vertex lies in the tile interior
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_vtile(TileArgs<T> a) {
   constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
   __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
   vtile_body<T, MODE, TT>(a.side, a.steps, a.val, a.dinv, a.b, a.xin, a.e, a.x, a.bc, a.c1, a.c2,
-                          xcd_block(blockIdx.x, gridDim.x), xa, xb);
+                          xcd_block(blockIdx.x, gridDim.x), xa, xb, a.b64, a.x64, a.xs);
 }
 
 // Batched: workgroup -> (instance, tile) from the tile list; the launch's
@@ -935,6 +945,14 @@ __global__ __launch_bounds__(BS) void k_convert(int64_t n, const TI* __restrict_
   if (i < n) y[i] = TO(x[i]);
 }
 
+// y = double(x) * inv[0] (inv may be null: plain conversion).
+__global__ __launch_bounds__(BS) void k_convert_out(int64_t n, const float* __restrict__ x,
+                                                    const double* __restrict__ inv,
+                                                    double* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) y[i] = inv ? double(x[i]) * inv[0] : double(x[i]);
+}
+
 // x <- x * inv[0] (written back) and y = float(x * inv[0]).
 __global__ __launch_bounds__(BS) void k_convert_scaled(int64_t n, double* __restrict__ x,
                                                        const double* __restrict__ inv,
@@ -1018,17 +1036,19 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double* __
 // then across the 4 wavefronts with one barrier.
 template <int KK, bool LAST>
 __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __restrict__ V, int64_t ld,
-                                                  int j, int g0, double* __restrict__ part) {
+                                                  int j, int g0, double* __restrict__ part,
+                                                  const double* __restrict__ vscale) {
   constexpr int NV = 2 * KK + (LAST ? 3 : 0);
   __shared__ double sh[4][NV > 0 ? NV : 1];
   const double* vt = V + int64_t(j) * ld;
   const double* w = V + int64_t(j + 1) * ld;
+  const double sv = vscale ? vscale[0] : 1.0;
   double acc[NV > 0 ? NV : 1];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const int64_t stride = int64_t(gridDim.x) * BS;
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
-    const double t = vt[r], wr = w[r];
+    const double t = vt[r] * sv, wr = w[r];
     double v[KK > 0 ? KK : 1];
 #pragma unroll
     for (int i = 0; i < KK; ++i) v[i] = V[(g0 + i) * ld + r];
@@ -1166,7 +1186,8 @@ __global__ __launch_bounds__(BS) void k_dcgs_finish(int nblk, const double* __re
 // (j > 0); per-block partials of |w'|^2.
 __global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restrict__ V, int64_t ld, int j,
                                                     const double* __restrict__ coef,
-                                                    double* __restrict__ nrm_part) {
+                                                    double* __restrict__ nrm_part,
+                                                    const double* __restrict__ vscale) {
   __shared__ double cs_l[2 * 64 + 2];
   __shared__ double sh[4];
   for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cs_l[i] = coef[i];
@@ -1174,10 +1195,11 @@ __global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restric
   double* vt = V + int64_t(j) * ld;
   double* w = V + int64_t(j + 1) * ld;
   const double inv = cs_l[2 * j + 1], wt = cs_l[2 * j];
+  const double sv = vscale ? vscale[0] : 1.0;
   double acc = 0.0;
   const int64_t stride = int64_t(gridDim.x) * BS;
   for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) {
-    const double t = vt[r];
+    const double t = vt[r] * sv;
     double wn = w[r] - wt * t, vn = t;
     int i = 0;
     for (; i + 8 <= j; i += 8) {  // groups of 8: all loads issued before the FMAs
@@ -1878,6 +1900,10 @@ void convert(int64_t n, const TI* x, TO* y, hipStream_t s) {
   hipLaunchKernelGGL((k_convert<TI, TO>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, y);
 }
 
+void convert_out(int64_t n, const float* x, const double* inv, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_out, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y);
+}
+
 void convert_scaled(int64_t n, double* x, const double* inv, float* y, hipStream_t s) {
   hipLaunchKernelGGL(k_convert_scaled, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y);
 }
@@ -1896,7 +1922,8 @@ int dcgs_dot_blocks(int64_t n) { return reduce_blocks(n); }
 template <int KK, bool LAST>
 static void launch_dots(int64_t n, const double* V, int64_t ld, int j, int g0, const DcgsState& st,
                         hipStream_t s, LaunchEv ev) {
-  LAUNCH_EV(ev, (k_dcgs_dots<KK, LAST>), dim3(dcgs_dot_blocks(n)), dim3(BS), 0, s, n, V, ld, j, g0, st.part);
+  LAUNCH_EV(ev, (k_dcgs_dots<KK, LAST>), dim3(dcgs_dot_blocks(n)), dim3(BS), 0, s, n, V, ld, j, g0, st.part,
+            st.vscale);
 }
 
 template <bool LAST>
@@ -1928,7 +1955,8 @@ void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& s
 
 void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, hipStream_t s,
                  LaunchEv ev) {
-  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, st.coef, st.nrm_part);
+  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, st.coef, st.nrm_part,
+            st.vscale);
   hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(BS), 0, s, reduce_blocks(n), st.nrm_part, j, st.m, st.H,
                      st.HR, st.cs, st.sn, st.g, st.gp, st.scal, host);
 }

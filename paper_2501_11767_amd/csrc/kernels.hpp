@@ -130,6 +130,13 @@ struct TileArgs {
   T* bc = nullptr;
   T c1[TILE_MAXSTEPS] = {};
   T c2[TILE_MAXSTEPS] = {};
+  // FP64 boundary of an FP32 cycle: when b64 is given the right-hand side is
+  // read from it (converted on load) instead of b; when x64 is given the
+  // result goes there as FP64, multiplied by xs[0] when xs is given, instead
+  // of into x
+  const double* b64 = nullptr;
+  double* x64 = nullptr;
+  const double* xs = nullptr;
 };
 // Tile side of a level: float levels of side >= 1024 take 64 x 64 tiles
 // (256 or more tiles), levels of side <= 256 take 16 x 16 tiles (256-thread
@@ -228,6 +235,8 @@ void convert(int64_t n, const TI* x, TO* y, hipStream_t s);
 void scale_by_inv(int64_t n, const double* x, const double* inv, double* y, hipStream_t s);
 // x <- x * inv[0] in place and y = float(x) (input stage of an FP32 preconditioner).
 void convert_scaled(int64_t n, double* x, const double* inv, float* y, hipStream_t s);
+// y = double(x) * inv[0] (inv may be null) (output stage of an FP32 preconditioner).
+void convert_out(int64_t n, const float* x, const double* inv, double* y, hipStream_t s);
 
 // Krylov reductions (FP64).  Partial sums per workgroup go to `part`
 // (reduce_blocks(n) * cols doubles); reduce_* finish them deterministically.
@@ -246,6 +255,9 @@ struct DcgsState {
   double *part = nullptr, *red = nullptr, *nrm_part = nullptr;
   double *H = nullptr, *HR = nullptr, *cs = nullptr, *sn = nullptr;
   double *g = nullptr, *gp = nullptr, *coef = nullptr, *scal = nullptr;
+  // V_j as stored times vscale[0] is the step's vector (may be null: 1); the
+  // passes scale it on load and the update pass stores it normalised
+  const double* vscale = nullptr;
   int m = 0;
 };
 // Dot pass, slot sums, then one wavefront that forms the
