@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     # profiles/chac1024_dcgs_update_hbm_counters.md: FETCH_SIZE x 2.0 (read
     # scale from the 512 MiB negation probe) + WRITE_SIZE x 1.0, per dispatch
-    "k_dcgs_update": 216571000,
+    "k_dcgs_update": 216571940,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 
