@@ -624,9 +624,13 @@ void set_cheb(BTileLaunch<T>& a, double lmax, int steps) {
 // per role (the smoothing instances' down pass, the instances cut here, the
 // instances whose one-workgroup tail starts here), the coarser levels, then
 // the smoothing instances' up pass.
+// b64 / x64 / xs (level 0 only, no tails there): the FP64 boundary of the
+// cycle, as in the single-instance tiles (right-hand side read as FP64,
+// result written as FP64 times xs[inst]).
 template <typename T>
 void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* act,
-                   const chns_solve_opts& o, hipStream_t s) {
+                   const chns_solve_opts& o, hipStream_t s, const double* b64 = nullptr,
+                   double* x64 = nullptr, const double* xs = nullptr) {
   BLevel& L = b->lv[l];
   const T* v = BSel<T>::v(L, op);
   const T* di = BSel<T>::d(L, op);
@@ -640,6 +644,9 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
     a.dinv = di;
     a.b = rhs;
     a.x = x;
+    a.b64 = b64;
+    a.x64 = x64;
+    a.xs = xs;
     a.cc1 = BSel<T>::cc(L, op, 0);
     a.cc2 = BSel<T>::cc(L, op, 1);
     bvtile<T>(TILE_ZERO, L.ntzero[op], a, s);
@@ -654,6 +661,7 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
   a.val = v;
   a.dinv = di;
   a.b = rhs;
+  a.b64 = b64;
   set_cheb<T>(a, o.mg_lmax, o.mg_pre);
   a.x = BSel<T>::t(L);
   a.bc = BSel<T>::b(G);
@@ -663,6 +671,8 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
   a.xin = BSel<T>::t(L);
   a.e = BSel<T>::x(G);
   a.x = x;
+  a.x64 = x64;
+  a.xs = xs;
   a.bc = nullptr;
   bvtile<T>(TILE_UP, L.ntdown[op], a, s);
 }
@@ -690,20 +700,46 @@ void bprecond_t(chns_batch* b, int block, const T* r, T* z, T* tmp1, T* tmp2, co
   }
 }
 
-// z = P^{-1} r for every active instance.  When inv is given, r is first
-// scaled in place by inv[inst] (fused with the FP32 conversion in mixed
-// precision): the Krylov basis vector is normalised on its way in.
-void bprecond(chns_batch* b, int block, double* r, const double* inv, double* z, const int* act,
+// Whether the FP32 cycles of a block take their FP64 input and write their
+// FP64 output in the finest level's tiles: the tiled cycle, and on level 0
+// no tails, the mass-like inverses cut there for every instance and X cut
+// there for none.
+bool bfused(chns_batch* b, int block, const chns_solve_opts& o) {
+  if (o.precision == CHNS_F64 || !b->tiled) return false;
+  const BLevel& L0 = b->lv[0];
+  for (int op = 0; op < NOPS; ++op)
+    if (L0.ntail[op] > 0) return false;
+  if (block == CHNS_BLOCK_AC) return L0.ntdown[2] == 0;
+  return L0.ntdown[0] == 0 && L0.ntzero[1] == 0;
+}
+
+// z = inv[inst] P^{-1} r for every active instance (inv may be null: 1); r is
+// not written.  The Krylov basis vector arrives unnormalised and its 1/|w|
+// rides on the output (P is linear).
+void bprecond(chns_batch* b, int block, const double* r, const double* inv, double* z, const int* act,
               const chns_solve_opts& o, hipStream_t s) {
-  const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * b->Ntot;
+  const int64_t N = b->Ntot;
+  const int64_t n = (block == CHNS_BLOCK_CH ? 2 : 1) * N;
+  if (bfused(b, block, o)) {
+    if (block == CHNS_BLOCK_AC) {
+      bvcycle_tiled<float>(b, 2, 0, nullptr, nullptr, act, o, s, r, z, inv);
+    } else {
+      BLevel& L0 = b->lv[0];
+      bvcycle_tiled<float>(b, 0, 0, nullptr, nullptr, act, o, s, r, z, inv);
+      bvcycle_tiled<float>(b, 1, 0, nullptr, b->w32a, act, o, s, r + N, nullptr, nullptr);
+      bstencil<float>(L0.st, L0.M32, 0, b->w32a, nullptr, nullptr, nullptr, 1.0f, 0.0f, nullptr, nullptr,
+                      nullptr, act, b->w32b, s);
+      bvcycle_tiled<float>(b, 1, 0, b->w32b, nullptr, act, o, s, nullptr, z + N, inv);
+    }
+    return;
+  }
   if (o.precision == CHNS_F64) {
-    if (inv) bscale(n, r, inv, b->cinst, act, r, s);
     bprecond_t<double>(b, block, r, z, b->w64a, b->w64b, act, o, s);
+    if (inv) bscale(n, z, inv, b->cinst, act, z, s);
   } else {
-    if (inv) bconvert_scaled(n, r, inv, b->r32, b->cinst, act, s);
-    else bconvert<double, float>(n, r, b->r32, b->cinst, act, s);
+    bconvert<double, float>(n, r, b->r32, b->cinst, act, s);
     bprecond_t<float>(b, block, b->r32, b->z32, b->w32a, b->w32b, act, o, s);
-    bconvert<float, double>(n, b->z32, z, b->cinst, act, s);
+    bconvert_out(n, b->z32, inv, z, b->cinst, act, s);
   }
 }
 
@@ -773,14 +809,17 @@ int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_s
       double* vj = V + int64_t(j) * ld;
       double* vn = V + int64_t(j + 1) * ld;
       double* zj = b->Z + int64_t(j) * ld;
-      // v_j is normalised in the preconditioner's input stage (j > 0)
-      bprecond(b, block, vj, j > 0 ? b->inv : nullptr, zj, act, o, s);
+      // v_j is stored unnormalised (j > 0): its 1/|w| scales the
+      // preconditioner's output and is applied on load by the two passes,
+      // which store v_j normalised
+      const double* vs = j > 0 ? b->inv : nullptr;
+      bprecond(b, block, vj, vs, zj, act, o, s);
       bapply(b, block, zj, vn, 1.0, 0.0, act, s);
       // DCGS2: one dot pass and one update pass over each instance's basis
-      bdcgs_dots(n, V, ld, j, b->part, b->cinst, act, s);
+      bdcgs_dots(n, V, ld, j, b->part, b->cinst, act, vs, s);
       bslot_reduce(b->count, nchunk, 2 * j + 3, b->part, b->cr, half, b->red, rs, act, s);
       bdcgs_coef(b->count, j, m, b->red, rs, b->H, b->coef, cstride, act, s);
-      bdcgs_update(n, V, ld, j, b->coef, cstride, b->part2, b->cinst, act, s);
+      bdcgs_update(n, V, ld, j, b->coef, cstride, b->part2, b->cinst, act, vs, s);
       bdcgs_finish(b->count, nchunk, b->part2, b->cr, half, j, m, b->H, b->HR, b->cs, b->sn, b->g,
                    b->gp, b->inv, b->tol, b->active, b->kcols, b->iters[bi], s);
       if (eager && (j + 1) % EAGER_CHECK == 0 && j + 1 < m) {
@@ -1247,7 +1286,7 @@ int chns_batch_precond_apply(chns_batch* b, int32_t block, const double* d_r, do
   if (d_r < d_z + n && d_z < d_r + n) return fail(b, CHNS_EINVAL, "r and z overlap");
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTRY(prepare_cycles(b, *opts));
-  bprecond(b, block, const_cast<double*>(d_r), nullptr, d_z, nullptr, *opts, s);  // r not written
+  bprecond(b, block, d_r, nullptr, d_z, nullptr, *opts, s);
   BCHK(b, hipGetLastError());
   return CHNS_OK;
 }

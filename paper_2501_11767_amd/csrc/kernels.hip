@@ -384,9 +384,10 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_bvtile(BTileLaunch<T> a) {
   }
   __syncthreads();
   const int64_t r = t.roff, rc = t.croff;
-  vtile_body<T, MODE, TT>(t.side, a.steps, a.val + r * W7, a.dinv + r, a.b + r, a.xin ? a.xin + r : nullptr,
-                          a.e ? a.e + rc : nullptr, a.x + r, a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile,
-                          xa, xb);
+  vtile_body<T, MODE, TT>(t.side, a.steps, a.val + r * W7, a.dinv + r, a.b ? a.b + r : nullptr,
+                          a.xin ? a.xin + r : nullptr, a.e ? a.e + rc : nullptr, a.x ? a.x + r : nullptr,
+                          a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile, xa, xb, a.b64 ? a.b64 + r : nullptr,
+                          a.x64 ? a.x64 + r : nullptr, a.xs ? a.xs + t.inst : nullptr);
 }
 
 // ------------------------------------------------------------------ paired levels
@@ -1232,15 +1233,28 @@ __device__ double sum_partials_wave(int nblk, const double* part) {
   return wave_sum(s);
 }
 
-__global__ void k_lsq_solve(int k, int m, const double* __restrict__ H, const double* __restrict__ g,
-                            double* __restrict__ y) {
-  if (threadIdx.x != 0) return;
+// y = R^{-1} g for the k x k upper triangle R of H (column-major, ld m + 1):
+// the triangle and g are staged in LDS by the whole workgroup, then one
+// thread back-substitutes at LDS latency.
+__global__ __launch_bounds__(BS) void k_lsq_solve(int k, int m, const double* __restrict__ H,
+                                                  const double* __restrict__ g, double* __restrict__ y) {
+  __shared__ double R[64 * 65], gs[64], ys[64];
   const int ld = m + 1;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int l = i + 1; l < k; ++l) s -= H[int64_t(l) * ld + i] * y[l];
-    y[i] = s / H[int64_t(i) * ld + i];
+  for (int q = threadIdx.x; q < k * k; q += BS) {
+    const int l = q / k, i = q - l * k;  // column l, row i
+    if (i <= l) R[l * 65 + i] = H[int64_t(l) * ld + i];
   }
+  for (int i = threadIdx.x; i < k; i += BS) gs[i] = g[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gs[i];
+      for (int l = i + 1; l < k; ++l) s -= R[l * 65 + i] * ys[l];
+      ys[i] = s / R[i * 65 + i];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += BS) y[i] = ys[i];
 }
 
 __global__ __launch_bounds__(BS) void k_xupdate(int64_t n, const double* __restrict__ Z,
@@ -1962,7 +1976,7 @@ void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, d
 }
 
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(64), 0, s, k, m, H, g, y);
+  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(BS), 0, s, k, m, H, g, y);
 }
 
 void xupdate(int64_t n, const double* Z, int64_t ldz, int k, const double* y, double* x,

@@ -215,6 +215,11 @@ struct BTileLaunch {
   T c2[TILE_MAXSTEPS] = {};
   const T* cc1 = nullptr;
   const T* cc2 = nullptr;
+  // FP64 boundary (as in TileArgs), offset per instance like b and x; xs per
+  // instance (xs[inst])
+  const double* b64 = nullptr;
+  double* x64 = nullptr;
+  const double* xs = nullptr;
 };
 bool btile_fits(int mode, int side, int steps);
 int btile_count(int side);  // tiles of one instance level

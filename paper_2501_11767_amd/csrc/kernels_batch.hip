@@ -228,14 +228,16 @@ constexpr int BDG = 16;          // basis vectors per dot launch
 // and with LAST vt.vt, vt.w, w.w; slot s of chunk c goes to
 // part[s * nchunk + c] (slots [0, j) V_i.vt, [j, 2j) V_i.w, then 2j, 2j+1,
 // 2j+2).  The accumulators are reduced by a wavefront reduce-scatter, then
-// across the 4 wavefronts.  Chunks of inactive instances are skipped.
+// across the 4 wavefronts.  Chunks of inactive instances are skipped.  vs
+// (may be null): vt is V_j as stored times vs[inst].
 template <int KK, bool LAST>
 __global__ __launch_bounds__(BS) void k_bdots(const double* __restrict__ V, int64_t ld, int j, int g0,
                                               double* __restrict__ part, const int* __restrict__ cinst,
-                                              const int* __restrict__ act) {
+                                              const int* __restrict__ act, const double* __restrict__ vs) {
   constexpr int NV = 2 * KK + (LAST ? 3 : 0);
   const int c = blockIdx.x;
   if (act && !act[cinst[c]]) return;
+  const double sv = vs ? vs[cinst[c]] : 1.0;
   __shared__ double sh[4][NV];
   const double* vt = V + int64_t(j) * ld;
   const double* w = V + int64_t(j + 1) * ld;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(BS) void k_bdots(const double* __restrict__ V, int6
 #pragma unroll
   for (int rr = 0; rr < RPC; ++rr) {
     const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
-    const double t = vt[r], wr = w[r];
+    const double t = vt[r] * sv, wr = w[r];
     double v[KK > 0 ? KK : 1];
 #pragma unroll
     for (int i = 0; i < KK; ++i) v[i] = V[(g0 + i) * ld + r];
@@ -334,15 +336,17 @@ __global__ __launch_bounds__(64) void k_bdcgs_coef(int j, int m, const double* _
 
 // Update of one chunk with its instance's coefficients: w <- w - sum coef[j+i]
 // V_i - coef[2j] vt, vt <- (vt - sum coef[i] V_i) / r (j > 0); chunk partial
-// of |w'|^2.
+// of |w'|^2.  vs (may be null): vt is V_j as stored times vs[inst].
 __global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int64_t ld, int j,
                                                      const double* __restrict__ coef, int cstride,
                                                      double* __restrict__ nrm_part,
                                                      const int* __restrict__ cinst,
-                                                     const int* __restrict__ act) {
+                                                     const int* __restrict__ act,
+                                                     const double* __restrict__ vs) {
   const int c = blockIdx.x;
   const int inst = cinst[c];
   if (act && !act[inst]) return;
+  const double sv = vs ? vs[inst] : 1.0;
   __shared__ double cl[2 * 64 + 2];
   __shared__ double sh[16];
   for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cl[i] = coef[int64_t(inst) * cstride + i];
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int
 #pragma unroll
   for (int rr = 0; rr < RPC; ++rr) {
     const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
-    const double t = vt[r];
+    const double t = vt[r] * sv;
     double wn = w[r] - wt * t, vn = t;
     int i = 0;
     for (; i + 8 <= j; i += 8) {
@@ -496,19 +500,18 @@ __global__ __launch_bounds__(64) void k_bdcgs_finish(int nchunk, const double* _
   }
 }
 
-// x <- x * inv[inst] in place and y = float(x) on chunks of active instances.
-__global__ __launch_bounds__(BS) void k_bconvert_scaled(int64_t n, double* __restrict__ x,
-                                                        const double* __restrict__ inv,
-                                                        float* __restrict__ y,
-                                                        const int* __restrict__ cinst,
-                                                        const int* __restrict__ act) {
+// y = double(x) * inv[inst] (inv may be null) on chunks of active instances.
+__global__ __launch_bounds__(BS) void k_bconvert_out(int64_t n, const float* __restrict__ x,
+                                                     const double* __restrict__ inv,
+                                                     double* __restrict__ y,
+                                                     const int* __restrict__ cinst,
+                                                     const int* __restrict__ act) {
   const int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (r >= n) return;
   const int inst = cinst[r / BCHUNK];
   if (act && act[inst] == 0) return;
-  const double v = x[r] * inv[inst];
-  x[r] = v;
-  y[r] = float(v);
+  const double v = double(x[r]);
+  y[r] = inv ? v * inv[inst] : v;
 }
 
 __global__ __launch_bounds__(BS) void k_bscale(int64_t n, const double* __restrict__ w,
@@ -706,12 +709,12 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
 
 // The last group (kk < BDG vectors plus the vt, w products).
 static void launch_bdots_last(int kk, int nchunk, const double* V, int64_t ld, int j, int g0, double* part,
-                              const int* cinst, const int* act, hipStream_t s) {
+                              const int* cinst, const int* act, const double* vs, hipStream_t s) {
   switch (kk) {
 #define CHNS_BDOTS_CASE(K)                                                                        \
   case K:                                                                                          \
     hipLaunchKernelGGL((k_bdots<K, true>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g0, part, cinst, \
-                       act);                                                                       \
+                       act, vs);                                                                   \
     break;
     CHNS_BDOTS_CASE(0) CHNS_BDOTS_CASE(1) CHNS_BDOTS_CASE(2) CHNS_BDOTS_CASE(3) CHNS_BDOTS_CASE(4)
     CHNS_BDOTS_CASE(5) CHNS_BDOTS_CASE(6) CHNS_BDOTS_CASE(7) CHNS_BDOTS_CASE(8) CHNS_BDOTS_CASE(9)
@@ -723,13 +726,13 @@ static void launch_bdots_last(int kk, int nchunk, const double* V, int64_t ld, i
 }
 
 void bdcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, const int* cinst,
-                const int* act, hipStream_t s) {
+                const int* act, const double* vs, hipStream_t s) {
   const int nchunk = int(n / BCHUNK);
   const int full = j / BDG, rem = j - full * BDG;
   for (int g = 0; g < full; ++g)
     hipLaunchKernelGGL((k_bdots<BDG, false>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g * BDG, part, cinst,
-                       act);
-  launch_bdots_last(rem, nchunk, V, ld, j, full * BDG, part, cinst, act, s);
+                       act, vs);
+  launch_bdots_last(rem, nchunk, V, ld, j, full * BDG, part, cinst, act, vs, s);
 }
 
 void bslot_reduce(int count, int nchunk, int nslots, const double* part, const int* cr, int half,
@@ -744,9 +747,9 @@ void bdcgs_coef(int count, int j, int m, const double* red, int rs, double* H, d
 }
 
 void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, int cstride,
-                  double* nrm_part, const int* cinst, const int* act, hipStream_t s) {
+                  double* nrm_part, const int* cinst, const int* act, const double* vs, hipStream_t s) {
   hipLaunchKernelGGL(k_bdcgs_update, dim3(int(n / BCHUNK)), dim3(BS), 0, s, V, ld, j, coef, cstride,
-                     nrm_part, cinst, act);
+                     nrm_part, cinst, act, vs);
 }
 
 void bdcgs_finish(int count, int nchunk, const double* part2, const int* cr, int half, int j, int m,
@@ -756,9 +759,9 @@ void bdcgs_finish(int count, int nchunk, const double* part2, const int* cr, int
                      sn, g, gp, inv, tol, active, kcols, iters);
 }
 
-void bconvert_scaled(int64_t n, double* x, const double* inv, float* y, const int* cinst, const int* act,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_bconvert_scaled, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y, cinst, act);
+void bconvert_out(int64_t n, const float* x, const double* inv, double* y, const int* cinst, const int* act,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_bconvert_out, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, x, inv, y, cinst, act);
 }
 
 void bscale(int64_t n, const double* w, const double* inv, const int* cinst, const int* act,

@@ -76,8 +76,9 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
 // once, V_{j+1} (w) the new vector.  Chunk partials of V_i.vt, V_i.w (i < j),
 // vt.vt, vt.w, w.w go to part[slot * nchunk + c] (slots 2j + 3; chunks of
 // inactive instances skipped).
+// vs (may be null): V_j as stored times vs[inst] is the step's vector.
 void bdcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, const int* cinst,
-                const int* act, hipStream_t s);
+                const int* act, const double* vs, hipStream_t s);
 // red[i * rs + k] = slot k summed over instance i's chunks [cr[2i], cr[2i+1])
 // and, when half != 0, the same range shifted by half; active instances only.
 void bslot_reduce(int count, int nchunk, int nslots, const double* part, const int* cr, int half,
@@ -90,7 +91,7 @@ void bdcgs_coef(int count, int j, int m, const double* red, int rs, double* H, d
 // Per chunk: V_j <- its reorthogonalised, normalised form (j > 0), w <- w
 // projected out of the final basis; chunk partials of |w|^2 into nrm_part.
 void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, int cstride,
-                  double* nrm_part, const int* cinst, const int* act, hipStream_t s);
+                  double* nrm_part, const int* cinst, const int* act, const double* vs, hipStream_t s);
 // Per active instance: h_{j+1,j} = |w|, final rotation of column j-1 into HR
 // and g, provisional rotation of column j into HR and gp, iteration count,
 // activity (estimate |gp_{j+1}| <= tol_i, |w| == 0 or non-finite: inactive with
@@ -98,9 +99,9 @@ void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, i
 void bdcgs_finish(int count, int nchunk, const double* part2, const int* cr, int half, int j, int m,
                   double* H, double* HR, double* cs, double* sn, double* g, double* gp, double* inv,
                   const double* tol, int* active, int* kcols, int* iters, hipStream_t s);
-// x <- x * inv[inst] in place and y = float(x), on chunks of active instances.
-void bconvert_scaled(int64_t n, double* x, const double* inv, float* y, const int* cinst, const int* act,
-                     hipStream_t s);
+// y = double(x) * inv[inst] (inv may be null), on chunks of active instances.
+void bconvert_out(int64_t n, const float* x, const double* inv, double* y, const int* cinst, const int* act,
+                  hipStream_t s);
 // v = w * inv[inst] (v may alias w).
 void bscale(int64_t n, const double* w, const double* inv, const int* cinst, const int* act,
             double* v, hipStream_t s);
