@@ -162,16 +162,23 @@ int form_operators(chns_ctx* c, hipStream_t s) {
   c->coefX[1] = tg;
   c->coefAC[0] = 1.0;
   c->coefAC[1] = p.tau * delta_v;
-  for (auto& L : c->lv) {
-    const int64_t ns = L.sell.slots();
-    const double* C = c->has_conv ? L.C : nullptr;
-    combine(ns, 1.0, L.M, 0.0, nullptr, p.tau, C, L.L.v64, L.L.v32, s);
-    combine(ns, smatch, L.M, tg, L.K, 0.0, nullptr, L.X.v64, L.X.v32, s);
-    combine(ns, 1.0, L.M, p.tau * delta_v, L.K, p.tau, C, L.AC.v64, L.AC.v32, s);
-    diag_inverse(L.N, L.diag, L.L.v64, L.L.d64, L.L.d32, s);
-    diag_inverse(L.N, L.diag, L.X.v64, L.X.d64, L.X.d32, s);
-    diag_inverse(L.N, L.diag, L.AC.v64, L.AC.d64, L.AC.d32, s);
-  }
+  // one launch over all levels: L = M (+ tau C), X = smatch M + tg K,
+  // AC = M + tau delta_v K (+ tau C)
+  FormCoef k{};
+  k.a[0] = 1.0;
+  k.useK[0] = 0;
+  k.c[0] = p.tau;
+  k.useC[0] = 1;
+  k.a[1] = smatch;
+  k.b[1] = tg;
+  k.useK[1] = 1;
+  k.useC[1] = 0;
+  k.a[2] = 1.0;
+  k.b[2] = p.tau * delta_v;
+  k.useK[2] = 1;
+  k.c[2] = p.tau;
+  k.useC[2] = 1;
+  form_ops(int(c->lv.size()), c->form_tab, c->form_total, k, c->has_conv, s);
   HIPCHK(c, hipGetLastError());
   if (c->ternary) TRY(form_ternary(c, s));
   return CHNS_OK;
@@ -289,15 +296,18 @@ int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bo
     }
   }
   if (d_vel) {
+    c->c_zero = false;
     TRY(assemble_base(c, 2, L0.C, d_vel, s));
     if (transposed) TRY(transpose_values(c, L0.sell.slots(), c->tslot1, L0.C, s));
     galerkin_down(c, &Level::C, &Level::C32, s);
     c->has_conv = true;
   } else {
-    for (auto& L : c->lv) {
-      HIPCHK(c, hipMemsetAsync(L.C, 0, L.sell.slots() * sizeof(double), s));
-      HIPCHK(c, hipMemsetAsync(L.C32, 0, L.sell.slots() * sizeof(float), s));
-    }
+    if (!c->c_zero)  // C = 0 without a velocity
+      for (auto& L : c->lv) {
+        HIPCHK(c, hipMemsetAsync(L.C, 0, L.sell.slots() * sizeof(double), s));
+        HIPCHK(c, hipMemsetAsync(L.C32, 0, L.sell.slots() * sizeof(float), s));
+      }
+    c->c_zero = true;
     c->has_conv = false;
   }
   c->transposed = transposed;
@@ -932,12 +942,6 @@ int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha
 
 constexpr int64_t KRYLOV_PAD = 640;  // doubles (5 KiB) between consecutive basis vectors
 
-int read_scal(chns_ctx* c, hipStream_t s, int count) {
-  HIPCHK(c, hipMemcpyAsync(c->kr.host, c->kr.scal, count * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  return CHNS_OK;
-}
-
 int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_opts& o,
            chns_solve_info* info, hipStream_t s) {
   Krylov& K = c->kr;
@@ -963,31 +967,60 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   st.m = m;
   chns_solve_info inf{};
   HIPCHK(c, hipEventRecord(c->ev0, s));
+  // ||b|| into scal[4]; the host reads it together with the first residual
   norm_partial(n, b, K.nrm_part, s);
-  norm_finish(nblk, K.nrm_part, K.scal, nullptr, m, s);
-  TRY(read_scal(c, s, 3));
-  inf.bnorm = K.host[0];
-  if (!std::isfinite(inf.bnorm)) return fail(c, CHNS_EINVAL, "right-hand side is not finite");
-  const double tol = std::fmax(o.rtol * inf.bnorm, o.atol);
+  norm_finish(nblk, K.nrm_part, K.scal + 4, nullptr, m, s);
+  double* rslot = K.host + 8;  // restart read-back: beta, 1/beta, beta, -, ||b||
+  double tol = 0.0;
   int iters = 0;
-  bool first = true;
+  bool first = true, stop = false;
+  // The host reads a restart's residual norm only after the cycle's first
+  // Arnoldi step is enqueued (speculation), unless the previous cycle may
+  // have converged (its last residual estimate was below the tolerance or is
+  // still unread): then it waits for the norm first.  A speculative step whose
+  // cycle turns out not to be needed changes nothing but the basis.
+  bool spec = true;
+  int unread = -1;  // host slot of a finished cycle's last step, not yet read
+  auto check = [&]() -> int {
+    HIPCHK(c, hipEventSynchronize(K.rdone));
+    if (first) {
+      inf.bnorm = rslot[4];
+      if (!std::isfinite(inf.bnorm)) return fail(c, CHNS_EINVAL, "right-hand side is not finite");
+      tol = std::fmax(o.rtol * inf.bnorm, o.atol);
+      inf.res0 = rslot[0];
+      first = false;
+    }
+    const double beta = rslot[0];
+    inf.res_true = beta;
+    if (beta <= tol) {
+      inf.converged = 1;
+      stop = true;
+    } else if (iters >= o.maxiter || !std::isfinite(beta)) {
+      stop = true;
+    } else {
+      inf.restarts++;
+    }
+    return CHNS_OK;
+  };
   while (true) {
     // V0 = b - A x, beta = ||V0||, g = beta e1
     HIPCHK(c, hipMemcpyAsync(K.V, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     TRY(apply_block(c, block, x, K.V, -1.0, 1.0, s));
     norm_partial(n, K.V, K.nrm_part, s);
     norm_finish(nblk, K.nrm_part, K.scal, K.g, m, s);
-    TRY(read_scal(c, s, 3));
-    const double beta = K.host[0];
-    if (first) inf.res0 = beta;
-    first = false;
-    inf.res_true = beta;
-    if (beta <= tol) {
-      inf.converged = 1;
-      break;
+    HIPCHK(c, hipMemcpyAsync(rslot, K.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(K.rdone, s));
+    if (unread >= 0) {  // the previous cycle's last estimate
+      HIPCHK(c, hipEventSynchronize(K.done[unread]));
+      const double est = K.host[4 * unread];
+      if (!(est > tol)) spec = false;
+      unread = -1;
     }
-    if (iters >= o.maxiter || !std::isfinite(beta)) break;
-    inf.restarts++;
+    if (iters >= o.maxiter) spec = false;
+    if (!spec) {
+      TRY(check());
+      if (stop) break;
+    }
     scale_by_inv(n, K.V, K.scal + 1, K.V, s);
     // One-step lookahead: step j is enqueued before the host reads step
     // j-1's residual estimate, so the stream never drains at the check.  If
@@ -1017,6 +1050,10 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
             [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, st, slot, s, ev); });
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipEventRecord(K.done[j & 1], s));
+      if (j == 0 && spec) {
+        TRY(check());
+        if (stop) break;
+      }
       if (j > 0) {
         HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));
         ++iters;
@@ -1027,15 +1064,17 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
           break;
         }
       }
-      if (j == m - 1) {
-        HIPCHK(c, hipEventSynchronize(K.done[j & 1]));
+      if (j == m - 1) {  // the cycle ends at its length: no wait for this step
         ++iters;
         k = m;
+        unread = j & 1;
       }
     }
+    if (stop) break;
     lsq_solve(k, m, K.HR, K.gp, K.y, s);
     xupdate(n, K.Z, ld, k, K.y, x, s);
     HIPCHK(c, hipGetLastError());
+    spec = k == m;
   }
   if (block == CHNS_BLOCK_NS) mean_zero<double>(c, c->N, x + 8 * int64_t(c->N), s);
   HIPCHK(c, hipEventRecord(c->ev1, s));
@@ -1259,6 +1298,32 @@ int build(chns_ctx* c) {
     HIPCHK(c, hipMemset(L.C, 0, ns * sizeof(double)));
     HIPCHK(c, hipMemset(L.C32, 0, ns * sizeof(float)));
   }
+  {  // table of the fused operator formation
+    std::vector<FormLevel> tab;
+    int64_t at = 0;
+    for (auto& L : c->lv) {
+      FormLevel f;
+      f.begin = at;
+      f.ns = L.sell.slots();
+      f.N = L.N;
+      f.diag = L.diag;
+      f.M = L.M;
+      f.K = L.K;
+      f.C = L.C;
+      int o = 0;
+      for (OpVals* v : {&L.L, &L.X, &L.AC}) {
+        f.v64[o] = v->v64;
+        f.v32[o] = v->v32;
+        f.d64[o] = v->d64;
+        f.d32[o] = v->d32;
+        ++o;
+      }
+      tab.push_back(f);
+      at += f.ns + f.N;
+    }
+    TRY(upload(c, &c->form_tab, tab));
+    c->form_total = at;
+  }
   const size_t N1 = size_t(c->N), N2 = 2 * N1;
   const size_t NB = c->ternary ? 9 * N1 : N2;  // largest block
   for (double** v : {&c->w64a, &c->w64b, &c->w64c, &c->w64d, &c->rhs_ac, &c->xac, &c->fs})
@@ -1321,8 +1386,9 @@ int build(chns_ctx* c) {
   TRY(dalloc(c, &K.red, 2 * MAX_RESTART + 4));
   TRY(dalloc(c, &K.coef, 2 * MAX_RESTART + 4));
   TRY(dalloc(c, &K.nrm_part, 1024));
-  HIPCHK(c, hipHostMalloc((void**)&K.host, 8 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&K.host, 16 * sizeof(double), hipHostMallocDefault));
   for (auto& e : K.done) HIPCHK(c, hipEventCreate(&e));
+  HIPCHK(c, hipEventCreate(&K.rdone));
   HIPCHK(c, hipEventCreate(&c->ev0));
   HIPCHK(c, hipEventCreate(&c->ev1));
   // M and K on the finest level by coloured scatter, then Galerkin down
@@ -1364,6 +1430,7 @@ void release(chns_ctx* c) {
   if (c->kr.host) (void)hipHostFree(c->kr.host);
   for (auto& e : c->kr.done)
     if (e) (void)hipEventDestroy(e);
+  if (c->kr.rdone) (void)hipEventDestroy(c->kr.rdone);
   for (auto& e : c->ledger.ev) (void)hipEventDestroy(e);
   c->ledger.ev.clear();
   if (c->ev0) (void)hipEventDestroy(c->ev0);

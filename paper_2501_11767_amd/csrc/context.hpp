@@ -97,8 +97,9 @@ struct Krylov {
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *scal = nullptr, *part = nullptr, *nrm_part = nullptr;
   double *HR = nullptr, *gp = nullptr, *red = nullptr, *coef = nullptr;  // DCGS2
-  double* host = nullptr;  // pinned readback (two 4-double slots for the lookahead)
+  double* host = nullptr;  // pinned readback: two 4-double slots for the lookahead, 8 for restarts
   hipEvent_t done[2] = {nullptr, nullptr};
+  hipEvent_t rdone = nullptr;  // restart norms read back
 };
 
 // Work vectors of the adjoint step (ternary contexts).
@@ -133,7 +134,11 @@ struct chns_ctx {
   chns_params prm{};
   int N = 0;            // P1 nodes
   bool has_conv = false;
+  bool c_zero = true;   // C and C32 hold zeros on every level
   bool ternary = false;
+  // device table of the fused operator formation (one entry per level)
+  chns::FormLevel* form_tab = nullptr;
+  int64_t form_total = 0;
   chns::P2Level p2;
   chns::NSData ns;
   double coefV[2] = {1, 0};

@@ -1391,6 +1391,45 @@ __global__ __launch_bounds__(BS) void k_diag_inverse(int n, const int* __restric
   if (d32) d32[i] = float(d);
 }
 
+__device__ __forceinline__ double form_value(const FormCoef& k, int o, bool conv, double m, double kk,
+                                             double cc) {
+  double v = k.a[o] * m;
+  if (k.useK[o]) v += k.b[o] * kk;
+  if (conv && k.useC[o]) v += k.c[o] * cc;
+  return v;
+}
+
+__global__ __launch_bounds__(BS) void k_form_ops(int nlev, const FormLevel* __restrict__ tab, int64_t total,
+                                                 FormCoef k, int conv) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i >= total) return;
+  int l = 0;
+  while (l + 1 < nlev && i >= tab[l + 1].begin) ++l;
+  const FormLevel& t = tab[l];
+  int64_t q = i - t.begin;
+  if (q < t.ns) {
+    const double m = t.M[q], kk = t.K[q], cc = conv ? t.C[q] : 0.0;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      const double v = form_value(k, o, conv, m, kk, cc);
+      t.v64[o][q] = v;
+      if (t.v32[o]) t.v32[o][q] = float(v);
+    }
+  } else {
+    q -= t.ns;
+    if (q >= t.N) return;
+    const int ds = t.diag[q];
+    const double m = t.M[ds], kk = t.K[ds], cc = conv ? t.C[ds] : 0.0;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      const double v = form_value(k, o, conv, m, kk, cc);
+      const double d = (v != 0.0) ? 1.0 / v : 0.0;
+      t.d64[o][q] = d;
+      if (t.d32[o]) t.d32[o][q] = float(d);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ right-hand sides
 
 __device__ __forceinline__ void binary_terms(double phi, const double* Phi, int j, double& fp,
@@ -2015,6 +2054,11 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
                   hipStream_t s) {
   hipLaunchKernelGGL(k_diag_inverse, dim3(ceil_div(nrows, BS)), dim3(BS), 0, s, nrows, diag, val,
                      d64, d32);
+}
+
+void form_ops(int nlev, const FormLevel* tab, int64_t total, const FormCoef& k, bool conv, hipStream_t s) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_form_ops, dim3(ceil_div(total, BS)), dim3(BS), 0, s, nlev, tab, total, k, conv ? 1 : 0);
 }
 
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,

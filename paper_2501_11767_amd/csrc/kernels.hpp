@@ -297,6 +297,26 @@ void galerkin(int64_t nslots, const int* ptr, const int* src, const double* w, c
 // out = a A + b B + c C (C may be null) with FP32 copy; dinv from diagonal slots.
 void combine(int64_t nslots, double a, const double* A, double b, const double* B, double c,
              const double* C, double* out64, float* out32, hipStream_t s);
+// The three preconditioner operators of every P1 level in one launch.
+// Operator o of a level: values a[o] M (+ b[o] K if useK[o]) (+ c[o] C if
+// useC[o] and conv) on every SELL slot, FP64 and FP32, and 1/diagonal (0 where
+// the diagonal is 0) in both precisions; work items of level l are
+// [begin, begin + ns + N): first the slots, then the rows.
+struct FormLevel {
+  int64_t begin = 0, ns = 0;
+  int N = 0;
+  const int* diag = nullptr;
+  const double *M = nullptr, *K = nullptr, *C = nullptr;
+  double* v64[3] = {};
+  float* v32[3] = {};
+  double* d64[3] = {};
+  float* d32[3] = {};
+};
+struct FormCoef {
+  double a[3], b[3], c[3];
+  int useK[3], useC[3];
+};
+void form_ops(int nlev, const FormLevel* tab, int64_t total, const FormCoef& k, bool conv, hipStream_t s);
 void diag_inverse(int nrows, const int* diag, const double* val, double* d64, float* d32,
                   hipStream_t s);
 
