@@ -1052,7 +1052,10 @@ __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double* __res
     const double t = vt[r] * sv, wr = w[r];
     double v[KK > 0 ? KK : 1];
 #pragma unroll
-    for (int i = 0; i < KK; ++i) v[i] = V[(g0 + i) * ld + r];
+    // basis vectors: non-temporal loads, so that the streamed basis does not
+    // evict the operator values the preconditioner and the matrix product reuse
+    // from the last-level cache
+    for (int i = 0; i < KK; ++i) v[i] = __builtin_nontemporal_load(V + (g0 + i) * ld + r);
 #pragma unroll
     for (int i = 0; i < KK; ++i) {
       acc[i] += v[i] * t;
@@ -1203,10 +1206,12 @@ __global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restric
     const double t = vt[r] * sv;
     double wn = w[r] - wt * t, vn = t;
     int i = 0;
-    for (; i + 8 <= j; i += 8) {  // groups of 8: all loads issued before the FMAs
+    // groups of 8: all loads issued before the FMAs; basis vectors loaded
+    // non-temporally (last use in this step)
+    for (; i + 8 <= j; i += 8) {
       double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = V[(i + q) * ld + r];
+      for (int q = 0; q < 8; ++q) v[q] = __builtin_nontemporal_load(V + (i + q) * ld + r);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         vn -= cs_l[i + q] * v[q];
@@ -1214,7 +1219,7 @@ __global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restric
       }
     }
     for (; i < j; ++i) {
-      const double v = V[i * ld + r];
+      const double v = __builtin_nontemporal_load(V + i * ld + r);
       vn -= cs_l[i] * v;
       wn -= cs_l[j + i] * v;
     }

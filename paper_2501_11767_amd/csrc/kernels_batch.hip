@@ -250,7 +250,7 @@ __global__ __launch_bounds__(BS) void k_bdots(const double* __restrict__ V, int6
     const double t = vt[r] * sv, wr = w[r];
     double v[KK > 0 ? KK : 1];
 #pragma unroll
-    for (int i = 0; i < KK; ++i) v[i] = V[(g0 + i) * ld + r];
+    for (int i = 0; i < KK; ++i) v[i] = __builtin_nontemporal_load(V + (g0 + i) * ld + r);  // last use this step
 #pragma unroll
     for (int i = 0; i < KK; ++i) {
       acc[i] += v[i] * t;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int
     for (; i + 8 <= j; i += 8) {
       double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = V[(i + q) * ld + r];
+      for (int q = 0; q < 8; ++q) v[q] = __builtin_nontemporal_load(V + (i + q) * ld + r);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         vn -= cl[i + q] * v[q];
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int
       }
     }
     for (; i < j; ++i) {
-      const double v = V[i * ld + r];
+      const double v = __builtin_nontemporal_load(V + i * ld + r);
       vn -= cl[i] * v;
       wn -= cl[j + i] * v;
     }

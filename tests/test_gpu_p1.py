@@ -226,6 +226,34 @@ def test_krylov_maxiter_reports_no_convergence(chns):
     ctx.close()
 
 
+def test_krylov_restart_edges(chns):
+    """Restart bookkeeping: a cycle may start before its residual norm is read
+    back, so a solve that starts converged must leave x untouched, and the
+    iteration limit must hold at and between cycle boundaries."""
+    import torch
+    n = 32
+    ctx = chns.Context(n, "ch", **PRM)
+    b = _t(np.random.default_rng(5).standard_normal(2 * n * n))
+    x = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+    info = ctx.solve(chns.BLOCK_CH, b, x, chns.default_opts(rtol=1e-10, restart=5, maxiter=400))
+    assert info["converged"] == 1 and info["iters"] > 5
+    # cycles run (the last one possibly short; one more if an estimate stopped a
+    # cycle that the true residual then did not confirm)
+    assert -(-info["iters"] // 5) <= info["restarts"] <= -(-info["iters"] // 5) + 1
+    # restart from the converged iterate: no iteration, x bit for bit unchanged
+    x0 = x.clone()
+    info = ctx.solve(chns.BLOCK_CH, b, x, chns.default_opts(rtol=1e-10, restart=5, maxiter=400))
+    torch.cuda.synchronize()
+    assert info["converged"] == 1 and info["iters"] == 0 and info["restarts"] == 0
+    assert torch.equal(x, x0)
+    # the iteration limit at a cycle boundary and inside a cycle
+    for maxiter in (5, 7, 10):
+        info = ctx.solve(chns.BLOCK_CH, b, x.zero_(), chns.default_opts(rtol=1e-14, restart=5, maxiter=maxiter))
+        assert info["converged"] == 0 and info["iters"] == maxiter
+        assert info["restarts"] == -(-maxiter // 5)
+    ctx.close()
+
+
 @pytest.mark.parametrize("model,n", [("ch", 32), ("ch_ac", 48)])
 def test_timestep_matches_fourier_oracle(chns, model, n):
     import torch
