@@ -1271,7 +1271,7 @@ __global__ __launch_bounds__(BS) void k_xupdate(int64_t n, const double* __restr
   const int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (r >= n) return;
   double s = x[r];
-  for (int i = 0; i < k; ++i) s += ys[i] * Z[i * ldz + r];
+  for (int i = 0; i < k; ++i) s += ys[i] * __builtin_nontemporal_load(Z + i * ldz + r);  // last use of Z
   x[r] = s;
 }
 

@@ -559,7 +559,7 @@ __global__ __launch_bounds__(BS) void k_bxupdate(int64_t n, const double* __rest
   for (int rr = 0; rr < RPC; ++rr) {
     const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
     double s = x[r];
-    for (int i = 0; i < k; ++i) s += ys[i] * Z[i * ldz + r];
+    for (int i = 0; i < k; ++i) s += ys[i] * __builtin_nontemporal_load(Z + i * ldz + r);  // last use of Z
     x[r] = s;
   }
 }
