@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--kernel-passes", action="store_true",
                     help="extra passes timing the other kernel classes (CH block, Gram-Schmidt)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="one 512 MiB device copy (counter calibration in profiled runs)")
+                    help="(default) the 512 MiB streaming probe: attainable bandwidth, counter calibration")
+    ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--dry-steps", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -131,17 +132,31 @@ def kernel_ledger(ctx, chns, fin, fout, k, opts, all_classes=False):
     return out
 
 
-def copy_probe(mib=512):
+def copy_probe(mib=512, reps=9):
     """One plain streaming kernel of known traffic (b = -a over 512 MiB FP32,
-    one dispatch of torch's elementwise negation), for scaling the HBM
-    counters of a profiled run (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    torch's elementwise negation): its event-timed median gives the streaming
+    bandwidth this GPU attains in practice, and in a profiled run its
+    FETCH_SIZE / WRITE_SIZE per dispatch scale the HBM counters."""
     import torch
     a = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     torch.neg(a, out=b)
-    torch.cuda.synchronize()
-    return dict(kernel="neg (elementwise)", bytes_read=a.numel() * 4, bytes_written=b.numel() * 4)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.neg(a, out=b)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[reps // 2]
+    nbytes = 2 * a.numel() * 4
+    out = dict(kernel="neg (elementwise)", bytes_read=a.numel() * 4, bytes_written=b.numel() * 4,
+               dispatches=reps + 1, us=ms * 1e3, gbs=nbytes / (ms * 1e6), frac=nbytes / (ms * 1e6) / HBM_PEAK_GBS)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(cfg, n, tau, budget_s=20.0):
@@ -496,7 +511,7 @@ def main():
         kern = kernel_ledger(ctx, chns, f_in, f_out, args.steps,
                              chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=args.restart),
                              args.kernel_passes)
-    probe = copy_probe() if args.copy_probe else None
+    probe = None if args.no_copy_probe else copy_probe()
 
     sweep, sweep_fields = [], {}
     if not args.no_sweep:
@@ -560,7 +575,8 @@ def main():
             "bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": kd["frac"], "traffic": TRAFFIC.get(dom),
             "bytes_per_launch": kd["bytes_per_launch"], "us_per_launch": kd["us_per_launch"],
-            "launches": kd["launches"]},
+            "launches": kd["launches"],
+            "frac_of_streaming_probe": None if probe is None else kd["gbs"] / probe["gbs"]},
         "cpu_baseline": cpu,
         "mixed": res.get("mixed"),
         "fp64": res.get("fp64"),
