@@ -28,14 +28,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BATCH_RESTART = 60  # restart length of the batched workload and its sequential comparison
 # HBM bytes per launch of a kernel from rocprofv3 counter runs of this
 # benchmark (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
 # copy of known size); filled in from profiles/ once measured for the kernel
 # as it stands, None otherwise.
 TRAFFIC = {
-    # profiles/chac1024_dcgs_update_hbm_counters.md: FETCH_SIZE x 2.0 (read
-    # scale from the 512 MiB negation probe) + WRITE_SIZE x 1.0, per dispatch
-    "k_dcgs_update": 216571940,
+    # filled in from profiles/chac1024_dcgs_update_hbm_counters.md (FETCH_SIZE and
+    # WRITE_SIZE per dispatch, scaled by the 512 MiB negation probe) once the
+    # counters are taken for the pass as it stands: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+    "k_dcgs_update": 167859762,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 
@@ -47,7 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--tau", type=float, default=1e-4)
-    ap.add_argument("--restart", type=int, default=20)
+    ap.add_argument("--restart", type=int, default=15)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ledger", action="store_true", help="no kernel events in the timed steps")
@@ -259,7 +261,7 @@ def batch_section(chns, steps):
     torch.cuda.synchronize()
     log("batch64: tune")
     batch.tune(None, stream=s)
-    opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=40, maxiter=120)
+    opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=BATCH_RESTART, maxiter=120)
     log("batch64: eager steps")
     rc_e, info_e = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=False, stream=s, out=out,
                                   each_from_input=True)
@@ -273,14 +275,14 @@ def batch_section(chns, steps):
                               each_from_input=True)
     graph_ms = info["ms"] / steps
     log("batch64: fp64 eager step")
-    o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=40, maxiter=120)
+    o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=120)
     rc_f, info_f = batch.timestep(*zin, nsteps=1, opts=o64, use_graph=False, stream=s, out=out)
     batch.close()
     di = float(sum(2 * n * n * a + n * n * b for n, a, b in zip(sizes, info["iters_ch"], info["iters_ac"])))
     # one instance at a time, plain FP64, one context per size
     ctxs, seq_ms, seq_its = {}, 0.0, 0
     off = np.concatenate([[0], np.cumsum([n * n for n in sizes])])
-    opts_seq = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=40, maxiter=600)
+    opts_seq = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=600)
     log("batch64: sequential fp64 solves")
     for i, (n, p) in enumerate(zip(sizes, prm)):
         if n not in ctxs:
@@ -300,7 +302,7 @@ def batch_section(chns, steps):
         c.close()
     return dict(workload=f"batch64: 64 CH + AC instances, sizes {sorted(set(sizes))} "
                          f"({Ntot} nodes, {3 * Ntot} unknowns), log-uniform eps, tau, mobility, "
-                         f"evaporation rate; FP32 multigrid in FP64 FGMRES(40), rtol 1e-8",
+                         f"evaporation rate; FP32 multigrid in FP64 FGMRES({BATCH_RESTART}), rtol 1e-8",
                 graph_ms_per_step=graph_ms, eager_ms_per_step=eager_ms,
                 graph_budget_ch_ac=[int(x.max()) for x in (info_e["iters_ch"], info_e["iters_ac"])],
                 sequential_fp64_ms_per_step=seq_ms, speedup_vs_sequential_fp64=seq_ms / graph_ms,

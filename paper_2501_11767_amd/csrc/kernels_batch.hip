@@ -371,10 +371,18 @@ __global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int
         wn -= cl[j + i + q] * v[q];
       }
     }
-    for (; i < j; ++i) {
-      const double v = __builtin_nontemporal_load(V + i * ld + r);
-      vn -= cl[i] * v;
-      wn -= cl[j + i] * v;
+    const int rem = j - i;
+    if (rem > 0) {  // the rest (< 8): all loads issued before the FMAs
+      double v[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+        if (q < rem) v[q] = __builtin_nontemporal_load(V + (i + q) * ld + r);
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+        if (q < rem) {
+          vn -= cl[i + q] * v[q];
+          wn -= cl[j + i + q] * v[q];
+        }
     }
     if (j > 0) vt[r] = vn * inv;
     w[r] = wn;
