@@ -115,15 +115,16 @@ def kernel_ledger(ctx, chns, fin, fout, k, opts, all_classes=False):
     ledger on, which launches every kernel of the class with a pair of HIP
     events timestamped by the dispatch itself, on the stream it runs on (the
     library launches on torch's current stream), and records its algorithmic
-    bytes.  The roofline class (the Gram-Schmidt update pass) always; with
-    all_classes also the others.  The events cost the step time, so these
-    passes are separate from the value pass; on short kernels (the multigrid
-    sweeps, ~3-10 us) they also lengthen the kernels themselves, so those
-    figures are indicative only.  Returns {kernel name: figures}."""
+    bytes.  Always the roofline class (the Gram-Schmidt update pass), the CH
+    block operator and the finest-level multigrid passes; with all_classes
+    also the dot pass and the launch-per-step Chebyshev sweeps.  The events
+    cost the step time, so these passes are separate from the value pass; on
+    short kernels (~3-10 us) they also lengthen the kernels themselves, so
+    those figures are indicative only.  Returns {kernel name: figures}."""
     out = {}
-    classes = [chns.KERNEL_DCGS_UPDATE]
+    classes = [chns.KERNEL_DCGS_UPDATE, chns.KERNEL_CH_BLOCK, chns.KERNEL_MG_FINE]
     if all_classes:
-        classes += [chns.KERNEL_CH_BLOCK, chns.KERNEL_DCGS_DOTS, chns.KERNEL_CHEB32]
+        classes += [chns.KERNEL_DCGS_DOTS, chns.KERNEL_CHEB32]
     for kid in classes:
         ctx.ledger_start(kid)
         run_steps(ctx, chns, fin, fout, k, opts)
@@ -582,7 +583,8 @@ def main():
         "cpu_baseline": cpu,
         "mixed": res.get("mixed"),
         "fp64": res.get("fp64"),
-        "kernels": kern,
+        "kernels": {name: dict(f, frac_of_streaming_probe=None if probe is None else f["gbs"] / probe["gbs"])
+                    for name, f in kern.items()},
         "copy_probe": probe,
         "sweep": sweep,
         "dry256": dry,

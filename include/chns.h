@@ -273,7 +273,8 @@ enum {
   CHNS_KERNEL_CHEB64 = 1,      /* FP64 Chebyshev sweep of the P1 stencil kernel */
   CHNS_KERNEL_CH_BLOCK = 2,    /* FP64 CH block operator inside FGMRES */
   CHNS_KERNEL_DCGS_DOTS = 3,   /* Gram-Schmidt dot pass */
-  CHNS_KERNEL_DCGS_UPDATE = 4  /* Gram-Schmidt update pass */
+  CHNS_KERNEL_DCGS_UPDATE = 4, /* Gram-Schmidt update pass */
+  CHNS_KERNEL_MG_FINE = 5      /* tiled multigrid passes on the finest level (down, up, steps from zero) */
 };
 
 /* Measurement ledger.  chns_ledger_start(kernel) clears the ledger and from

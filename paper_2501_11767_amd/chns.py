@@ -17,13 +17,14 @@ OK, WNOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, 
 MODEL_CH, MODEL_CH_AC, MODEL_TERNARY = 0, 1, 2
 BLOCK_CH, BLOCK_AC, BLOCK_NS = 0, 1, 2
 OP_M, OP_K, OP_C, OP_CH, OP_AC, OP_X, OP_L, OP_NS, OP_VX, OP_AP = range(10)
-KERNEL_CHEB32, KERNEL_CHEB64, KERNEL_CH_BLOCK, KERNEL_DCGS_DOTS, KERNEL_DCGS_UPDATE = range(5)
+KERNEL_CHEB32, KERNEL_CHEB64, KERNEL_CH_BLOCK, KERNEL_DCGS_DOTS, KERNEL_DCGS_UPDATE, KERNEL_MG_FINE = range(6)
 KERNEL_NAMES = {
     KERNEL_CHEB32: "k_stencil7<float, float, 2>",
     KERNEL_CHEB64: "k_stencil7<double, double, 2>",
     KERNEL_CH_BLOCK: "k_ch_block<double, double, true>",
     KERNEL_DCGS_DOTS: "k_dcgs_dots",
     KERNEL_DCGS_UPDATE: "k_dcgs_update",
+    KERNEL_MG_FINE: "k_vtile (finest level)",
 }
 F64, MIXED = 0, 1
 MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}

@@ -314,6 +314,27 @@ int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bo
   return form_operators(c, s);
 }
 
+// A tiled pass; on the finest level it goes through the ledger (class
+// CHNS_KERNEL_MG_FINE) with its algorithmic bytes per fine row: 7 values,
+// 1/diag and the right-hand side read; down: the pre-smoothed iterate and
+// the coarse right-hand side (a quarter row) written; up: the pre-smoothed
+// iterate and the coarse correction read, the result written; from zero:
+// the result written.
+template <typename T>
+void vtile_at(chns_ctx* c, int mode, const TileArgs<T>& a, bool finest, hipStream_t s) {
+  if (!finest) {
+    vtile<T>(mode, a, s);
+    return;
+  }
+  const double t = sizeof(T), rows = double(a.side) * a.side;
+  const double bin = a.b64 ? 8.0 : t, xout = a.x64 ? 8.0 : t;
+  double per = 8.0 * t + bin;
+  if (mode == TILE_DOWN) per += 1.25 * t;
+  else if (mode == TILE_UP) per += 1.25 * t + xout;
+  else per += xout;
+  timed(c, CHNS_KERNEL_MG_FINE, rows * per, s, [&](LaunchEv ev) { vtile<T>(mode, a, s, ev); });
+}
+
 // ------------------------------------------------------------------ multigrid
 
 template <typename T> struct Sel;
@@ -580,7 +601,7 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
       TileArgs<T> ta = tile_args<T>(L, A, cc.steps, cc);
       ta.b = b;
       ta.x = x;
-      vtile<T>(TILE_ZERO, ta, s);
+      vtile_at<T>(c, TILE_ZERO, ta, l == 0, s);
       return;
     }
     cheb_from_zero<T>(c, L, A, b, x, cc, s);
@@ -596,14 +617,14 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
     dn.b = b;
     dn.x = Sel<T>::t(L);
     dn.bc = Sel<T>::b(G);
-    vtile<T>(TILE_DOWN, dn, s);
+    vtile_at<T>(c, TILE_DOWN, dn, l == 0, s);
     vcycle<T>(c, op, l + 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
     TileArgs<T> up = tile_args<T>(L, A, o.mg_post, cheb_coef<T>(lmax / 4.0, lmax, o.mg_post));
     up.b = b;
     up.xin = Sel<T>::t(L);
     up.e = Sel<T>::x(G);
     up.x = x;
-    vtile<T>(TILE_UP, up, s);
+    vtile_at<T>(c, TILE_UP, up, l == 0, s);
     return;
   }
   const ChebCoef<T> pre = cheb_coef<T>(lmax / 4.0, lmax, o.mg_pre);
@@ -816,7 +837,7 @@ void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const do
   dn.b64 = b64;
   dn.x = Sel<T>::t(L);
   dn.bc = Sel<T>::b(G);
-  vtile<T>(TILE_DOWN, dn, s);
+  vtile_at<T>(c, TILE_DOWN, dn, true, s);
   vcycle<T>(c, op, 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
   TileArgs<T> up = tile_args<T>(L, A, o.mg_post, cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post));
   up.b = b;
@@ -826,7 +847,7 @@ void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const do
   up.x = x;
   up.x64 = x64;
   up.xs = xs;
-  vtile<T>(TILE_UP, up, s);
+  vtile_at<T>(c, TILE_UP, up, true, s);
 }
 
 // Whether the FP32 cycles of a block can take their FP64 input and write
@@ -868,7 +889,7 @@ int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, const doubl
       a.b64 = b;
       a.x64 = x;
       a.xs = inv;
-      vtile<float>(TILE_ZERO, a, s);
+      vtile_at<float>(c, TILE_ZERO, a, true, s);
     };
     if (block == CHNS_BLOCK_AC) {
       zero_cut(&Level::AC, r, z);
@@ -1997,7 +2018,7 @@ int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields*
 
 int chns_ledger_start(chns_ctx* c, int32_t kernel) {
   if (!c) return CHNS_EINVAL;
-  if (kernel < -1 || kernel > CHNS_KERNEL_DCGS_UPDATE) return fail(c, CHNS_EINVAL, "unknown kernel class");
+  if (kernel < -1 || kernel > CHNS_KERNEL_MG_FINE) return fail(c, CHNS_EINVAL, "unknown kernel class");
   Ledger& G = c->ledger;
   TRY(ledger_fold(c));
   if (kernel >= 0 && G.cap == 0) {

@@ -1857,25 +1857,25 @@ bool tile_fits(int mode, int side, int steps) {
 }
 
 template <typename T, int TT>
-void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s) {
+void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev) {
   const int nt = (a.side + TT - 1) / TT;
   const dim3 g(nt * nt), b(TileCfg<TT>::NTH);
-  if (mode == TILE_ZERO) hipLaunchKernelGGL((k_vtile<T, TILE_ZERO, TT>), g, b, 0, s, a);
-  else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_vtile<T, TILE_DOWN, TT>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_vtile<T, TILE_UP, TT>), g, b, 0, s, a);
+  if (mode == TILE_ZERO) LAUNCH_EV(ev, (k_vtile<T, TILE_ZERO, TT>), g, b, 0, s, a);
+  else if (mode == TILE_DOWN) LAUNCH_EV(ev, (k_vtile<T, TILE_DOWN, TT>), g, b, 0, s, a);
+  else LAUNCH_EV(ev, (k_vtile<T, TILE_UP, TT>), g, b, 0, s, a);
 }
 
 template <typename T>
-void vtile(int mode, const TileArgs<T>& a, hipStream_t s) {
+void vtile(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev) {
   const int tt = tile_side<T>(a.side);
   if constexpr (sizeof(T) == 4) {
     if (tt == 64) {
-      vtile_tt<T, 64>(mode, a, s);
+      vtile_tt<T, 64>(mode, a, s, ev);
       return;
     }
   }
-  if (tt == 16) vtile_tt<T, 16>(mode, a, s);
-  else vtile_tt<T, 32>(mode, a, s);
+  if (tt == 16) vtile_tt<T, 16>(mode, a, s, ev);
+  else vtile_tt<T, 32>(mode, a, s, ev);
 }
 
 bool tile2_fits(int side, int pre, int post) {
@@ -2198,8 +2198,8 @@ template void vup2<double>(const Tile2Args<double>&, hipStream_t);
 template void vup2<float>(const Tile2Args<float>&, hipStream_t);
 template bool tile_fits<double>(int, int, int);
 template bool tile_fits<float>(int, int, int);
-template void vtile<double>(int, const TileArgs<double>&, hipStream_t);
-template void vtile<float>(int, const TileArgs<float>&, hipStream_t);
+template void vtile<double>(int, const TileArgs<double>&, hipStream_t, LaunchEv);
+template void vtile<float>(int, const TileArgs<float>&, hipStream_t, LaunchEv);
 template bool tail_fits<double>(const int*, int);
 template bool tail_fits<float>(const int*, int);
 template void vtail<double>(const TailArgs<double>&, hipStream_t);

@@ -152,7 +152,7 @@ inline int tile_side(int side) {
 template <typename T>
 bool tile_fits(int mode, int side, int steps);
 template <typename T>
-void vtile(int mode, const TileArgs<T>& a, hipStream_t s);
+void vtile(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev = {});
 
 // Two consecutive smoothing levels in one launch (32 x 32 fine tiles, the
 // 16 x 16 coarse tile under each):
