@@ -275,10 +275,19 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
       ring[q] = min(min(ri, rj), min(W - 1 - ri, W - 1 - rj));
       own[q] = ring[q] >= H && tx * TT + (ri - H) < s && ty * TT + (rj - H) < s;
       const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+      // ring 0 is never updated by a step with neighbours (its rows only take
+      // the first step from zero, and in the up pass not even that): no values
+      // there, nor 1/diag and right-hand side in the up pass
+      const bool upd = ring[q] >= 1;
 #pragma unroll
-      for (int k = 0; k < W7; ++k) v[q][k] = val[base + k * 64];
-      di[q] = dinv[row];
-      bb[q] = b64 ? T(b64[row]) : b[row];
+      for (int k = 0; k < W7; ++k) v[q][k] = upd ? val[base + k * 64] : T(0);
+      if (MODE == TILE_UP && !upd) {
+        di[q] = T(0);
+        bb[q] = T(0);
+      } else {
+        di[q] = dinv[row];
+        bb[q] = b64 ? T(b64[row]) : b[row];
+      }
       if (MODE == TILE_UP) xa[idx] = xin[row] + p1_interp(e, gi, gj, s >> 1);
     }
   }
