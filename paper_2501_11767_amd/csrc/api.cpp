@@ -850,28 +850,58 @@ void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const do
   vtile_at<T>(c, TILE_UP, up, true, s);
 }
 
-// Whether the FP32 cycles of a block can take their FP64 input and write
-// their FP64 output inside the finest level's tiled launches: one cycle per
-// inner solve, a finest level of 64 x 64 tiles, the mass-like inverses ((1,1)
-// block of CH, the AC matrix) cut on the finest level, X not.
-bool fused_mixed(chns_ctx* c, int block, const chns_solve_opts& o) {
+// Whether the cycles of a block (precision T) can take their FP64 input and
+// write their FP64 output, times the output scale, inside the finest level's
+// tiled launches: one cycle per inner solve, a finest level of side >= 1024
+// (64 x 64 tiles in FP32, 32 x 32 in FP64; never paired), the mass-like
+// inverses ((1,1) block of CH, the AC matrix) cut on the finest level, X not.
+template <typename T>
+bool fused_top(chns_ctx* c, int block, const chns_solve_opts& o) {
   const int side = c->lv[0].d.side;
-  if (o.precision == CHNS_F64 || o.mg_cycles != 1 || side < TILE64_MIN_SIDE || c->lv.size() < 2) return false;
+  if (o.mg_cycles != 1 || side < TILE64_MIN_SIDE || c->lv.size() < 2) return false;
   const int z = std::min(o.mg_pre + o.mg_post, MAXCHEB);
   auto cut0 = [&](OpVals Level::*op) {
-    return cut_level(c, coef_of(c, op), o.mg_rho_cut) == 0 && tile_fits<float>(TILE_ZERO, side, z);
+    return cut_level(c, coef_of(c, op), o.mg_rho_cut) == 0 && tile_fits<T>(TILE_ZERO, side, z);
   };
   if (block == CHNS_BLOCK_AC) return c->mesh.model != CHNS_MODEL_CH && cut0(&Level::AC);
   if (block != CHNS_BLOCK_CH) return false;
   return cut0(&Level::L) && cut_level(c, coef_of(c, &Level::X), o.mg_rho_cut) > 0 &&
-         tile_fits<float>(TILE_DOWN, side, o.mg_pre) && tile_fits<float>(TILE_UP, side, o.mg_post);
+         tile_fits<T>(TILE_DOWN, side, o.mg_pre) && tile_fits<T>(TILE_UP, side, o.mg_post);
+}
+
+// The block preconditioner with the boundary in the finest tiles (see
+// fused_top): z = inv[0] P^{-1} r.
+template <typename T>
+void fused_precond(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, const double* inv,
+                   double* z, hipStream_t s) {
+  const int N = c->N;
+  Level& L0 = c->lv[0];
+  const int z0 = std::min(o.mg_pre + o.mg_post, MAXCHEB);
+  auto zero_cut = [&](OpVals Level::*op, const double* b, double* x) {
+    TileArgs<T> a = tile_args<T>(L0, L0.*op, z0, cut_coef<T>(c, op, 0, o));
+    a.b64 = b;
+    a.x64 = x;
+    a.xs = inv;
+    vtile_at<T>(c, TILE_ZERO, a, true, s);
+  };
+  if (block == CHNS_BLOCK_AC) {
+    zero_cut(&Level::AC, r, z);
+    return;
+  }
+  T* t1 = std::is_same<T, double>::value ? (T*)c->w64a : (T*)c->w32a;
+  T* t2 = std::is_same<T, double>::value ? (T*)c->w64b : (T*)c->w32b;
+  const size_t cutX = cut_level(c, coef_of(c, &Level::X), o.mg_rho_cut);
+  zero_cut(&Level::L, r, z);
+  vcycle_top<T>(c, &Level::X, cutX, nullptr, r + N, t1, nullptr, nullptr, o, s);
+  spmv<T, T>(L0.d, Sel<T>::M(L0), t1, t2, T(1), T(0), s);
+  vcycle_top<T>(c, &Level::X, cutX, t2, nullptr, nullptr, z + N, inv, o, s);
 }
 
 // Preconditioner of a block: z = inv[0] P^{-1} r (inv may be null: 1); r is
 // not written.  The Krylov basis vector arrives unnormalised and its 1/|w|
-// rides on the output (P is linear).  In mixed precision the FP32 cycles read
-// r and write z through the finest level's tiles where fused_mixed() holds,
-// else through conversion passes.
+// rides on the output (P is linear).  Where fused_top() holds the cycles read
+// r and write the scaled z in the finest level's tiles; else through
+// conversion (mixed precision) and scaling passes.
 int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, const double* r, const double* inv,
                    double* z, hipStream_t s) {
   const int N = c->N;
@@ -881,25 +911,9 @@ int precond_scaled(chns_ctx* c, int block, const chns_solve_opts& o, const doubl
   else if (block == CHNS_BLOCK_NS && c->ternary) n = 9 * int64_t(N);
   else return fail(c, CHNS_EUNSUPPORTED, "block not available");
   const bool f64 = o.precision == CHNS_F64;
-  if (fused_mixed(c, block, o)) {
-    Level& L0 = c->lv[0];
-    const int z0 = std::min(o.mg_pre + o.mg_post, MAXCHEB);
-    auto zero_cut = [&](OpVals Level::*op, const double* b, double* x) {
-      TileArgs<float> a = tile_args<float>(L0, L0.*op, z0, cut_coef<float>(c, op, 0, o));
-      a.b64 = b;
-      a.x64 = x;
-      a.xs = inv;
-      vtile_at<float>(c, TILE_ZERO, a, true, s);
-    };
-    if (block == CHNS_BLOCK_AC) {
-      zero_cut(&Level::AC, r, z);
-    } else {
-      const size_t cutX = cut_level(c, coef_of(c, &Level::X), o.mg_rho_cut);
-      zero_cut(&Level::L, r, z);
-      vcycle_top<float>(c, &Level::X, cutX, nullptr, r + N, c->w32a, nullptr, nullptr, o, s);
-      spmv<float, float>(L0.d, Sel<float>::M(L0), c->w32a, c->w32b, 1.0f, 0.0f, s);
-      vcycle_top<float>(c, &Level::X, cutX, c->w32b, nullptr, nullptr, z + N, inv, o, s);
-    }
+  if (f64 ? fused_top<double>(c, block, o) : fused_top<float>(c, block, o)) {
+    if (f64) fused_precond<double>(c, block, o, r, inv, z, s);
+    else fused_precond<float>(c, block, o, r, inv, z, s);
     HIPCHK(c, hipGetLastError());
     return CHNS_OK;
   }
