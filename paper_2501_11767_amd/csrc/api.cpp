@@ -1063,17 +1063,46 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
     // finalised column j-1 (its Givens rotation and g) and the least squares
     // over k = j columns uses that final data.
     int k = 0;
+    double hist[MAX_RESTART];  // residual estimates of this cycle, as read
     for (int j = 0; j < m; ++j) {
       double* vj = K.V + j * ld;
       double* vn = K.V + (j + 1) * ld;
       double* zj = K.Z + j * ld;
+      // Step j - 1's estimate predicted from the last known one and the mean
+      // reduction per step of the block's previous solve (else this cycle's
+      // last ratio; the estimates of these systems alternate plateaus and
+      // drops, so one ratio alone predicts badly): when it is likely to meet
+      // the tolerance the host reads it before enqueuing step j, and if it
+      // does, step j only closes column j - 1 (the DCGS2 correction and final
+      // rotation the least squares needs) with w = 0 instead of a full
+      // speculative step.
+      bool checked = false, closing = false;
+      if (j > 0) {
+        const double last = j == 1 ? inf.res_true : hist[j - 2];
+        double rate = K.rate[block];
+        if (!(rate > 0.0) && j >= 3 && hist[j - 3] > 0.0) rate = hist[j - 2] / hist[j - 3];
+        const double pred = rate > 0.0 ? last * rate : -1.0;
+        if (pred >= 0.0 && pred <= 2.0 * tol) {
+          HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));
+          ++iters;
+          checked = true;
+          const double* prev = K.host + 4 * ((j - 1) & 1);
+          const double est = prev[0], hnext = prev[2];
+          hist[j - 1] = est;
+          closing = est <= tol || hnext == 0.0 || iters >= o.maxiter || !std::isfinite(est);
+        }
+      }
       // v_j is stored unnormalised (j > 0): its 1/|w| scales the preconditioner's
       // output and is applied on load by the two Gram-Schmidt passes, which
       // store v_j normalised
       const double* vsc = j > 0 ? K.scal + 1 : nullptr;
       st.vscale = vsc;
-      TRY(precond_scaled(c, block, o, vj, vsc, zj, s));
-      TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
+      if (closing) {
+        HIPCHK(c, hipMemsetAsync(vn, 0, size_t(n) * sizeof(double), s));
+      } else {
+        TRY(precond_scaled(c, block, o, vj, vsc, zj, s));
+        TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
+      }
       // DCGS2: one dot pass and one update pass over the basis (the previous
       // vector's reorthogonalisation rides along with w's projection); the
       // end-of-step scalars land in the pinned host slot
@@ -1085,15 +1114,20 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
             [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, st, slot, s, ev); });
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipEventRecord(K.done[j & 1], s));
+      if (closing) {
+        k = j;
+        break;
+      }
       if (j == 0 && spec) {
         TRY(check());
         if (stop) break;
       }
-      if (j > 0) {
+      if (j > 0 && !checked) {
         HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));
         ++iters;
         const double* prev = K.host + 4 * ((j - 1) & 1);
         const double est = prev[0], hnext = prev[2];
+        hist[j - 1] = est;
         if (est <= tol || hnext == 0.0 || iters >= o.maxiter || !std::isfinite(est)) {
           k = j;
           break;
@@ -1111,6 +1145,8 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
     HIPCHK(c, hipGetLastError());
     spec = k == m;
   }
+  if (iters > 0 && inf.res0 > 0.0 && inf.res_true > 0.0)
+    K.rate[block] = std::pow(inf.res_true / inf.res0, 1.0 / iters);
   if (block == CHNS_BLOCK_NS) mean_zero<double>(c, c->N, x + 8 * int64_t(c->N), s);
   HIPCHK(c, hipEventRecord(c->ev1, s));
   HIPCHK(c, hipEventSynchronize(c->ev1));

@@ -100,6 +100,7 @@ struct Krylov {
   double* host = nullptr;  // pinned readback: two 4-double slots for the lookahead, 8 for restarts
   hipEvent_t done[2] = {nullptr, nullptr};
   hipEvent_t rdone = nullptr;  // restart norms read back
+  double rate[3] = {-1.0, -1.0, -1.0};  // per block: mean residual reduction per step of the last solve
 };
 
 // Work vectors of the adjoint step (ternary contexts).
