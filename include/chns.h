@@ -227,6 +227,23 @@ CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, const double* d_b, 
                                const chns_solve_opts* opts, chns_solve_info* h_info,
                                void* stream);
 
+/* Diagnostics of a field set, in FP64 on the GPU (synchronises the stream):
+ * the discrete mass 1^T M u of every phase field and the discrete free energy
+ * of the paper's functional (section "Free energy functional"; mass
+ * conservation of the Cahn-Hilliard phases).  h_out[0]: 1^T M phi (binary) or
+ * 1^T M phi_p (ternary); h_out[1]: 1^T M phi_N (ternary, else 0); h_out[2]:
+ * 1^T M phi_s of the eliminated solvent phi_s = 1 - phi_p - phi_N (ternary,
+ * else 0); h_out[3]: 1^T M Phi_v (models with a vapour field, else 0);
+ * h_out[4]: E_h = sum_i beta/2 phi_i^T K phi_i + sum_j (M 1)_j f(x_j), the
+ * phases i of the model (ternary: polymer, NFA and solvent), f the model's
+ * local density (binary: double-well, interpolated with the gas form by
+ * p(Phi_v) when there is a vapour field; ternary: the fitted quartic with
+ * air = 0) at the nodal values, beta = eps^2.  Fields: phi[0] (and phi[1]
+ * for the ternary model; Phi_v for models with a vapour field) are device
+ * pointers of n^2 doubles; other members are ignored.  h_out: 5 doubles on
+ * the host.  CHNS_EINVAL for a missing field or output. */
+CHNS_API int chns_diagnostics(chns_ctx* ctx, const chns_fields* f, double* h_out, void* stream);
+
 /* Right-hand sides of one step from the level-k fields (paper: [M phi^k;
  * -(tau g/beta) f^k] per CH phase with f^k = M f'(phi^k) nodal, the AC
  * right-hand side, and for the ternary model (rho/tau) M v^k + F^k with the

@@ -160,3 +160,15 @@ def energy_ch(ops: Operators, prm: Params, phi, Phi=None):
     """E_h = beta/2 phi^T K phi + sum_i (M 1)_i f(phi_i) (binary potential)."""
     lump = ops.M @ np.ones(ops.n * ops.n)
     return 0.5 * prm.beta * phi @ (ops.K @ phi) + lump @ pot.f_bin(phi, Phi)
+
+
+def energy_ternary(ops: Operators, prm: Params, pp, pn, Phi):
+    """Section "Free energy functional" discretised like energy_ch: the
+    gradient term beta/2 |grad phi_i|^2 of every phase present (polymer, NFA and
+    the eliminated solvent phi_s = 1 - phi_p - phi_N) plus the fitted quartic
+    density of the reduced ternary model, nodal with the row sums of M:
+    E_h = sum_i beta/2 phi_i^T K phi_i + sum_j (M 1)_j f(phi_p, phi_N, Phi)_j."""
+    lump = ops.M @ np.ones(ops.n * ops.n)
+    ps = 1.0 - pp - pn
+    grad = sum(u @ (ops.K @ u) for u in (pp, pn, ps))
+    return 0.5 * prm.beta * grad + lump @ pot.f_ter(pp, pn, Phi)

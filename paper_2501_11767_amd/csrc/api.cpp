@@ -1405,6 +1405,7 @@ int build(chns_ctx* c) {
   for (float** v : {&c->r32, &c->z32}) TRY(dalloc(c, v, NB));
   for (float** v : {&c->w32a, &c->w32b, &c->w32c}) TRY(dalloc(c, v, N1));
   TRY(dalloc(c, &c->red, 1024));
+  TRY(dalloc(c, &c->diag, NDIAG));
   if (c->ternary) {
     // slots of the transposed entries on the finest P1 and P2 patterns (both
     // symmetric); padding slots map to themselves
@@ -1981,6 +1982,22 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
              -(p.tau * p.mobility / beta), -p.tau * p.evap_rate, d_rhs_ch, ac ? d_rhs_ac : nullptr,
              static_cast<hipStream_t>(stream));
   HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
+int chns_diagnostics(chns_ctx* c, const chns_fields* f, double* h_out, void* stream) {
+  if (!c) return CHNS_EINVAL;
+  if (!f || !f->phi[0] || !h_out) return fail(c, CHNS_EINVAL, "phi[0] and the output are required");
+  const bool vapour = c->mesh.model != CHNS_MODEL_CH;
+  if (c->ternary && !f->phi[1]) return fail(c, CHNS_EINVAL, "the ternary model needs phi[1]");
+  if (vapour && !f->Phi_v) return fail(c, CHNS_EINVAL, "model needs Phi_v");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Level& L0 = c->lv[0];
+  diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, vapour ? f->Phi_v : nullptr,
+              c->ternary, c->prm.eps * c->prm.eps, c->kr.part, c->diag, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(h_out, c->diag, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
   return CHNS_OK;
 }
 

@@ -162,6 +162,7 @@ struct chns_ctx {
   double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr;
   double *rhs_ns = nullptr, *xns = nullptr, *xac = nullptr, *fs = nullptr, *w64d = nullptr;
   double* red = nullptr;  // reduction partials for mean projections
+  double* diag = nullptr;  // diagnostics results (NDIAG)
   float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr, *w32c = nullptr;
   std::vector<void*> allocs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -1452,6 +1452,87 @@ __global__ __launch_bounds__(BS) void k_form_ops(int nlev, const FormLevel* __re
   }
 }
 
+// ------------------------------------------------------------------ diagnostics
+
+// Local free-energy densities: the binary double-well phi^2 (1 - phi)^2 for the
+// liquid and phi^2 + (1 - phi)^2 for the gas, interpolated by p(Phi) =
+// Phi^2 (3 - 2 Phi) (no vapour field: the liquid form alone); the ternary
+// fitted quartic with air = 0 and phi_s = 1 - phi_p - phi_N.
+__device__ __forceinline__ double density_binary(double phi, const double* Phi, int j) {
+  const double om = 1.0 - phi;
+  const double liq = phi * phi * om * om;
+  if (!Phi) return liq;
+  const double P = Phi[j], p = P * P * (3.0 - 2.0 * P);
+  return (1.0 - p) * liq + p * (phi * phi + om * om);
+}
+
+__device__ __forceinline__ double density_ternary(double pp, double pn, double P) {
+  const double ps = 1.0 - pp - pn, p = P * P * (3.0 - 2.0 * P);
+  const double liq = 3.5 * pp * pp * pn * pn + 0.3 * ps * ps;
+  const double gas = 3.5 * pp * pp + 3.5 * pn * pn + 2.0 * ps * ps;
+  return (1.0 - p) * liq + p * gas;
+}
+
+// Per row: the row sum of M (the nodal weight), the masses weight * u, the
+// gradient terms u (K u) of each phase and weight * density; per block the
+// five sums.
+__global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restrict__ col,
+                                             const double* __restrict__ Mv, const double* __restrict__ Kv,
+                                             const double* __restrict__ p0, const double* __restrict__ p1,
+                                             const double* __restrict__ Phi, int ternary, double beta,
+                                             double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int stride = gridDim.x * BS;
+  for (int row = blockIdx.x * BS + threadIdx.x; row < n; row += stride) {
+    const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+    int c[W7];
+    row_cols7(row, side, col, base, c);
+    double w = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < W7; ++k) {
+      const double kv = Kv[base + k * 64], a = p0[c[k]];
+      w += Mv[base + k * 64];
+      k0 += kv * a;
+      if (ternary) {
+        const double b = p1[c[k]];
+        k1 += kv * b;
+        k2 += kv * (1.0 - a - b);
+      }
+    }
+    const double u0 = p0[row];
+    double grad = u0 * k0, f;
+    acc[0] += w * u0;
+    if (ternary) {
+      const double u1 = p1[row], us = 1.0 - u0 - u1;
+      acc[1] += w * u1;
+      acc[2] += w * us;
+      grad += u1 * k1 + us * k2;
+      f = density_ternary(u0, u1, Phi ? Phi[row] : 0.0);
+    } else {
+      f = density_binary(u0, Phi, row);
+    }
+    if (Phi) acc[3] += w * Phi[row];
+    acc[4] += 0.5 * beta * grad + w * f;
+  }
+#pragma unroll
+  for (int q = 0; q < NDIAG; ++q) {
+    const double v = block_sum(acc[q], sh);
+    if (threadIdx.x == 0) part[q * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_diag_finish(int nblk, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[4];
+  for (int q = 0; q < NDIAG; ++q) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += BS) a += part[q * nblk + b];
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) out[q] = a;
+  }
+}
+
 // ------------------------------------------------------------------ right-hand sides
 
 __device__ __forceinline__ void binary_terms(double phi, const double* Phi, int j, double& fp,
@@ -2081,6 +2162,14 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
 void form_ops(int nlev, const FormLevel* tab, int64_t total, const FormCoef& k, bool conv, hipStream_t s) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_form_ops, dim3(ceil_div(total, BS)), dim3(BS), 0, s, nlev, tab, total, k, conv ? 1 : 0);
+}
+
+void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
+                 const double* Phi, bool ternary, double beta, double* part, double* out, hipStream_t s) {
+  const int nblk = reduce_blocks(A.nrows);
+  hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, Phi,
+                     ternary ? 1 : 0, beta, part);
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(BS), 0, s, nblk, part, out);
 }
 
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,

@@ -323,6 +323,13 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
 // Right-hand sides of the binary models (uniform P1 pattern of M):
 // rhs_ch = [M phi; -(tau g/beta) M f'(phi, Phi)], rhs_ac = M Phi - tau g_v M f_v(phi, Phi).
 // Phi == nullptr selects the pure double-well (no vapour field).
+// Masses and discrete energy of a field set on the finest P1 level (uniform
+// width-7 pattern; M and K values): out[0..4] as chns_diagnostics documents,
+// through per-block partials (part: 5 x reduce_blocks(n)) and one summing
+// workgroup.  p1 (ternary second phase) and Phi may be null.
+constexpr int NDIAG = 5;
+void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
+                 const double* Phi, bool ternary, double beta, double* part, double* out, hipStream_t s);
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
                 double c_mu, double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s);
 

@@ -196,3 +196,20 @@ def test_ternary_timestep_matches_oracle(chns):
     assert _rel(_np(fld["p"]), out["p"]) < 1e-7
     assert _rel(_np(fld["mu"][2]), out["mu_s"]) < 1e-9
     ctx.close()
+
+
+def test_ternary_diagnostics_match_oracle(chns):
+    """Per-phase masses (polymer, NFA, the eliminated solvent, vapour) and the
+    discrete free energy of a ternary field set against the oracle's
+    definitions (1e-12 relative; the sums run in another order)."""
+    n = 32
+    ops, prm, st, out, sysr, Ap = _setup(n)
+    ctx = chns.Context(n, "ternary", **P)
+    fld = dict(phi=[_t(out["phi"][0]), _t(out["phi"][1])], Phi_v=_t(out["Phi_v"]))
+    got = ctx.diagnostics(ctx.fields(**fld))
+    pp, pn, Phi = out["phi"][0], out["phi"][1], out["Phi_v"]
+    ref = [S.mass(ops, pp), S.mass(ops, pn), S.mass(ops, 1.0 - pp - pn), S.mass(ops, Phi),
+           S.energy_ternary(ops, prm, pp, pn, Phi)]
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= 1e-12 * abs(r), (got, ref)
+    ctx.close()

@@ -226,6 +226,38 @@ def test_krylov_maxiter_reports_no_convergence(chns):
     ctx.close()
 
 
+@pytest.mark.parametrize("model", ["ch", "ch_ac"])
+def test_diagnostics_match_oracle_and_mass_is_conserved(chns, model):
+    """Masses and discrete energy against the oracle's definitions (1e-12
+    relative), then one GPU step with v = 0 conserves the CH mass (the first
+    block row sums to 1^T M (phi^{k+1} - phi^k) = -tau g 1^T K mu = 0, up to the
+    solve's residual)."""
+    import torch
+    n = 48
+    ctx = chns.Context(n, model, **PRM)
+    ops = S.Operators(n)
+    prm = _oracle_prm(PRM)
+    f = inputs.initial_state(n, model, 0.4, 5)
+    st = S.initial_state(ops, prm, model, f)
+    phi = _t(st["phi"][0])
+    mu = _t(st["mu"][0])
+    Phi = _t(st["Phi_v"]) if model == "ch_ac" else None
+    fin = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+    got = ctx.diagnostics(fin)
+    P = st["Phi_v"] if model == "ch_ac" else None
+    ref = [S.mass(ops, st["phi"][0]), 0.0, 0.0, S.mass(ops, P) if P is not None else 0.0,
+           S.energy_ch(ops, prm, st["phi"][0], P)]
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= 1e-12 * abs(r) if r != 0.0 else g == 0.0, (got, ref)
+    e = lambda: torch.empty(n * n, dtype=torch.float64, device="cuda")
+    fout = ctx.fields(phi=[e()], mu=[e()], Phi_v=e() if model == "ch_ac" else None)
+    rc, info = ctx.timestep(fin, fout, 1, chns.default_opts(rtol=1e-13, maxiter=400))
+    assert rc == chns.OK
+    after = ctx.diagnostics(fout)
+    assert abs(after[0] - got[0]) <= 1e-11 * abs(got[0])
+    ctx.close()
+
+
 def test_krylov_restart_edges(chns):
     """Restart bookkeeping: a cycle may start before its residual norm is read
     back, so a solve that starts converged must leave x untouched, and the

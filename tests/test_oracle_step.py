@@ -178,6 +178,30 @@ def test_energy_decays_at_small_tau():
     assert np.all(np.diff(E) < 0.0)
 
 
+def test_energies_constant_fields_and_gradient_term():
+    """Pins of the discrete energies: constant fields have no gradient energy and
+    the density integrates exactly (sum of the M row sums = |Omega| = 1); the
+    gradient term of phi = sin(2 pi x) tends to beta/2 int |grad phi|^2 = beta pi^2
+    (second order in h); the ternary energy of phi_p = phi, phi_N = 0 adds the
+    same gradient energy again through the solvent phi_s = 1 - phi."""
+    from oracle import potential as pot
+    n = 64
+    ops = S.Operators(n)
+    prm = Params(eps=0.05, tau=1e-3)
+    one = np.ones(n * n)
+    for c, P in ((0.3, 0.0), (0.6, 0.7)):
+        assert abs(S.energy_ch(ops, prm, c * one, P * one) - float(pot.f_bin(c, P))) < 1e-14
+        assert abs(S.energy_ternary(ops, prm, c * one, 0.2 * one, P * one)
+                   - float(pot.f_ter(c, 0.2, P))) < 1e-14
+    x = (np.arange(n * n) % n) / n
+    phi = np.sin(2.0 * np.pi * x)
+    grad = S.energy_ch(ops, prm, phi, None) - float((ops.M @ one) @ pot.f_bin(phi))
+    assert abs(grad - prm.beta * np.pi ** 2) < 2e-3 * prm.beta * np.pi ** 2
+    zero = np.zeros(n * n)
+    gt = S.energy_ternary(ops, prm, phi, zero, zero) - float((ops.M @ one) @ pot.f_ter(phi, zero, zero))
+    assert abs(gt - 2.0 * grad) < 1e-12 * abs(grad)
+
+
 def test_ternary_step_dense_equals_splu_and_invariants():
     n = 8
     ops = S.Operators(n, need_p2=True)
