@@ -502,12 +502,15 @@ def main():
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         di, solve_ms = dof_iters(infos, N)
+        d0, d1 = ctx.diagnostics(f_in), ctx.diagnostics(f_out)  # FP64 GPU reductions, outside the timing
         res[name] = dict(
             value=di / (solve_ms * 1e-3), ms_per_step=total * 1e3 / args.steps,
             ms_per_step_median=float(np.median(walls)),
             ch_iters=[i[0]["iters"] for i in infos], ac_iters=[i[1]["iters"] for i in infos],
             converged=all(i[0]["converged"] and i[1]["converged"] for i in infos),
-            rel_res_ch=max(i[0]["res_true"] / i[0]["bnorm"] for i in infos))
+            rel_res_ch=max(i[0]["res_true"] / i[0]["bnorm"] for i in infos),
+            mass_phi_rel_change=(d1[0] - d0[0]) / d0[0], mass_Phi_v=[d0[3], d1[3]],
+            energy=[d0[4], d1[4]])
     kern = {}
     if not args.no_ledger and "mixed" in forms:
         log("kernels: ledger passes (the timed steps again, one kernel class per pass)")
