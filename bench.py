@@ -560,7 +560,8 @@ def main():
     # spread over 7 levels, most launches latency-bound, see profiles/)
     dom = chns.KERNEL_NAMES[chns.KERNEL_DCGS_UPDATE]
     kd = kern.get(dom)
-    head = res.get("mixed") or res.get("fp64")  # the value is the mixed form's unless only FP64 ran
+    # the value is the mixed form's unless only FP64 ran (--forms "" for runs of the other sections only)
+    head = res.get("mixed") or res.get("fp64") or {"value": None, "ms_per_step": None}
     line = {
         "metric": METRIC,
         "value": head["value"],
