@@ -21,7 +21,7 @@ KERNEL_CHEB32, KERNEL_CHEB64, KERNEL_CH_BLOCK, KERNEL_DCGS_DOTS, KERNEL_DCGS_UPD
 KERNEL_NAMES = {
     KERNEL_CHEB32: "k_stencil7<float, float, 2>",
     KERNEL_CHEB64: "k_stencil7<double, double, 2>",
-    KERNEL_CH_BLOCK: "k_ch_block<double, double, true>",
+    KERNEL_CH_BLOCK: "CH operator (k_ch_block; k_ch_dots with the dot pass)",
     KERNEL_DCGS_DOTS: "k_dcgs_dots",
     KERNEL_DCGS_UPDATE: "k_dcgs_update",
     KERNEL_MG_FINE: "k_vtile (finest level)",

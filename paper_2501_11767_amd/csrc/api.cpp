@@ -1097,18 +1097,32 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
       // store v_j normalised
       const double* vsc = j > 0 ? K.scal + 1 : nullptr;
       st.vscale = vsc;
+      // the CH operator and the dot pass share one launch where the group fits
+      const bool fuse = !closing && block == CHNS_BLOCK_CH && ch_dots_fits(j);
       if (closing) {
         HIPCHK(c, hipMemsetAsync(vn, 0, size_t(n) * sizeof(double), s));
       } else {
         TRY(precond_scaled(c, block, o, vj, vsc, zj, s));
-        TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
+        if (!fuse) TRY(apply_block(c, block, zj, vn, 1.0, 0.0, s));
       }
       // DCGS2: one dot pass and one update pass over the basis (the previous
       // vector's reorthogonalisation rides along with w's projection); the
       // end-of-step scalars land in the pinned host slot
       const int kk0 = j < 16 ? j : 16;
-      timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (kk0 + 2), s,
-            [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, st, s, ev); });
+      if (fuse) {
+        const auto& p = c->prm;
+        Level& L0 = c->lv[0];
+        const double tg = p.tau * p.mobility;
+        const double* Lv = c->has_conv ? L0.L.v64 : L0.M;
+        // CH operator (values, z read, w written) and the dots of V_0..V_j-1, vt
+        const double bytes = double(c->N) * (8 * (14 + (c->has_conv ? 7 : 0)) + 32) + 8.0 * n * (j + 1);
+        timed(c, CHNS_KERNEL_CH_BLOCK, bytes, s, [&](LaunchEv ev) {
+          ch_dcgs_dots(L0.d, Lv, L0.K, L0.M, tg, -tg / (p.eps * p.eps), zj, K.V, ld, j, st, s, ev);
+        });
+      } else {
+        timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (kk0 + 2), s,
+              [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, st, s, ev); });
+      }
       double* slot = K.host + 4 * (j & 1);
       timed(c, CHNS_KERNEL_DCGS_UPDATE, 8.0 * n * (j + 2 + (j > 0 ? 1 : 0) + 1), s,
             [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, st, slot, s, ev); });

@@ -1038,6 +1038,76 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double* __
   }
 }
 
+// The CH block product w = A z (both block rows of node r: y1 = L z1 + c12 K
+// z2, y2 = c12 K z1 + c22 M z2, as k_ch_block with alpha = 1, beta = 0) fused
+// with the dot pass of Arnoldi step j = KK < DG: w is written once and its dots
+// are taken from registers (the separate pass would read it back).  Slots as
+// k_dcgs_dots with LAST; partials per block, grid-stride over the nodes.
+template <int KK, bool L_IS_M>
+__global__ __launch_bounds__(BS) void k_ch_dots(int N, int side, const int* __restrict__ col,
+                                                const double* __restrict__ Lv, const double* __restrict__ Kv,
+                                                const double* __restrict__ Mv, double c12, double c22,
+                                                const double* __restrict__ z, double* __restrict__ V,
+                                                int64_t ld, double* __restrict__ part,
+                                                const double* __restrict__ vscale) {
+  constexpr int NV = 2 * KK + 3;
+  constexpr int j = KK;
+  __shared__ double sh[4][NV];
+  const double* vt = V + int64_t(j) * ld;
+  double* w = V + int64_t(j + 1) * ld;
+  const double sv = vscale ? vscale[0] : 1.0;
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const int stride = gridDim.x * BS;
+  for (int row = blockIdx.x * BS + threadIdx.x; row < N; row += stride) {
+    const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+    int c[W7];
+    row_cols7(row, side, col, base, c);
+    double sl = 0.0, sk1 = 0.0, sk2 = 0.0, sm = 0.0;
+#pragma unroll
+    for (int k = 0; k < W7; ++k) {
+      const double kv = Kv[base + k * 64], mv = Mv[base + k * 64];
+      const double lv = L_IS_M ? mv : Lv[base + k * 64];
+      const double a = z[c[k]], bb = z[N + c[k]];
+      sl += lv * a;
+      sk1 += kv * a;
+      sk2 += kv * bb;
+      sm += mv * bb;
+    }
+    const double y[2] = {sl + c12 * sk2, c12 * sk1 + c22 * sm};
+    w[row] = y[0];
+    w[N + row] = y[1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t e = row + int64_t(h) * N;
+      const double t = vt[e] * sv, wr = y[h];
+      double v[KK > 0 ? KK : 1];
+#pragma unroll
+      for (int i = 0; i < KK; ++i) v[i] = __builtin_nontemporal_load(V + i * ld + e);
+#pragma unroll
+      for (int i = 0; i < KK; ++i) {
+        acc[i] += v[i] * t;
+        acc[KK + i] += v[i] * wr;
+      }
+      acc[2 * KK] += t * t;
+      acc[2 * KK + 1] += t * wr;
+      acc[2 * KK + 2] += wr * wr;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int sbase = 0, lim = NV;
+  WaveRS<NV, 32>::run(acc, lane, sbase, lim);
+  if (lim >= 1) sh[wid][sbase] = acc[0];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < NV) {
+    const double sum = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+    const int64_t slot = t < KK ? t : (t < 2 * KK ? j + (t - KK) : 2 * j + (t - 2 * KK));
+    part[slot * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
 // Dots of KK basis vectors V_g0 .. V_{g0+KK-1} against vt and w, and with
 // LAST also vt . vt, vt . w, w . w.  Slots (per block partial, stride
 // gridDim.x): [0, j) V_i . vt, [j, 2j) V_i . w, then 2j, 2j+1, 2j+2.  KK is a
@@ -2106,6 +2176,37 @@ void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& s
     launch_dots_kk<false>(DG, n, V, ld, j, g * DG, st, s, g == 0 ? ev : LaunchEv{});
   launch_dots_kk<true>(rem, n, V, ld, j, full * DG, st, s, full == 0 ? ev : LaunchEv{});
   hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(n), st.part, st.red);
+  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, st.m, st.red, st.H, st.coef);
+}
+
+template <bool LM>
+static void launch_ch_dots(int j, int N, const DSell& A, const double* Lv, const double* Kv, const double* Mv,
+                           double c12, double c22, const double* z, double* V, int64_t ld, const DcgsState& st,
+                           hipStream_t s, LaunchEv ev) {
+  const dim3 g(dcgs_dot_blocks(2 * int64_t(N))), b(BS);
+  switch (j) {
+#define CHNS_CHD_CASE(K)                                                                                 \
+  case K:                                                                                                 \
+    LAUNCH_EV(ev, (k_ch_dots<K, LM>), g, b, 0, s, N, A.side, A.col, Lv, Kv, Mv, c12, c22, z, V, ld, st.part, \
+              st.vscale);                                                                                 \
+    break;
+    CHNS_CHD_CASE(0) CHNS_CHD_CASE(1) CHNS_CHD_CASE(2) CHNS_CHD_CASE(3) CHNS_CHD_CASE(4) CHNS_CHD_CASE(5)
+    CHNS_CHD_CASE(6) CHNS_CHD_CASE(7) CHNS_CHD_CASE(8) CHNS_CHD_CASE(9) CHNS_CHD_CASE(10) CHNS_CHD_CASE(11)
+    CHNS_CHD_CASE(12) CHNS_CHD_CASE(13) CHNS_CHD_CASE(14) CHNS_CHD_CASE(15)
+#undef CHNS_CHD_CASE
+    default: break;
+  }
+}
+
+bool ch_dots_fits(int j) { return j >= 0 && j < DG; }
+
+void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const double* Mv, double c12, double c22,
+                  const double* z, double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s, LaunchEv ev) {
+  const int N = A.nrows;
+  if (Lv == Mv) launch_ch_dots<true>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+  else launch_ch_dots<false>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+  hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(2 * int64_t(N)), st.part,
+                     st.red);
   hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, st.m, st.red, st.H, st.coef);
 }
 

@@ -270,6 +270,14 @@ struct DcgsState {
 // column j-1 and the projection coefficients of w (into coef and H).
 void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
                LaunchEv ev = {});
+// The CH block operator (as ch_block with alpha = 1, beta = 0; L == M
+// selects the convection-free form) applied to z into V_{j+1} and the dot pass
+// of step j in one launch, then the slot sums and coefficients as dcgs_dots;
+// for j with ch_dots_fits(j) (j < 16).
+bool ch_dots_fits(int j);
+void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const double* Mv, double c12, double c22,
+                  const double* z, double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
+                  LaunchEv ev = {});
 // Update pass: V_j <- its reorthogonalised, normalised form (j > 0), w <-
 // w projected out of the final basis; then one workgroup sets h_{j+1,j} = |w|,
 // takes the final Givens rotation of column j-1 into HR and g, a provisional
