@@ -555,9 +555,11 @@ def main():
             with threadpool_limits(1):
                 adj["cpu_reference"] = cpu_adjoint_reference(chns)
 
-    # roofline kernel: the largest total time among the kernels that run on
-    # the finest level only (the HBM-bound population; the multigrid sweeps
-    # spread over 7 levels, most launches latency-bound, see profiles/)
+    # roofline kernel: the single kernel with the largest total time in the
+    # rocprofv3 statistics of this run (profiles/): the Gram-Schmidt update
+    # pass; the fused CH operator + dot pass is one kernel per step index j and
+    # the multigrid passes one per mode and level (their ledger figures are in
+    # "kernels")
     dom = chns.KERNEL_NAMES[chns.KERNEL_DCGS_UPDATE]
     kd = kern.get(dom)
     # the value is the mixed form's unless only FP64 ran (--forms "" for runs of the other sections only)
