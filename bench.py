@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BATCH_RESTART = 60  # restart length of the batched workload and its sequential comparison
+# multigrid of the 1024^2 workload: V(1,2), 4 Chebyshev steps on the cut level,
+# hierarchies cut at the first level with rho <= 4 (measured fastest over the
+# tau sweep, same iteration counts within 2; the library default is V(2,2),
+# 8 steps, rho <= 0.25)
+MG = dict(mg_pre=1, mg_post=2, mg_coarse=4, mg_rho_cut=4.0)
 # HBM bytes per launch of a kernel from rocprofv3 counter runs of this
 # benchmark (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
 # copy of known size); filled in from profiles/ once measured for the kernel
@@ -179,7 +184,8 @@ def cpu_baseline(cfg, n, tau, budget_s=20.0):
         from oracle import potential as pot
         A = systems.ch_matrix(M, K, None, prm)
         b = systems.ch_rhs(M, f["phi"][0], pot.dfdphi_bin(f["phi"][0], f["Phi_v"]), prm)
-        P = PC.CHPreconditioner(M, K, None, prm, n, inner="mg")
+        P = PC.CHPreconditioner(M, K, None, prm, n, inner="mg", rho_cut=MG["mg_rho_cut"], pre=MG["mg_pre"],
+                                post=MG["mg_post"], coarse=MG["mg_coarse"])
         setup = time.perf_counter() - t0
         # one Arnoldi step to size the sample, then as many as fit the budget
         t1 = time.perf_counter()
@@ -191,7 +197,7 @@ def cpu_baseline(cfg, n, tau, budget_s=20.0):
         dt = time.perf_counter() - t2
     N2 = 2 * n * n
     return dict(value=N2 * k / dt, unit="DOF·iters/s", cores=1, kind="oracle",
-                sample=f"oracle FGMRES + V(2,2) block preconditioner, CH system of the "
+                sample=f"oracle FGMRES + V({MG['mg_pre']},{MG['mg_post']}) block preconditioner, CH system of the "
                        f"{n}x{n} mesh ({N2} unknowns), {k} Arnoldi steps in {dt:.1f} s "
                        f"after {setup:.1f} s of set-up, FP64, 1 thread")
 
@@ -493,7 +499,7 @@ def main():
     for name, prec in (("mixed", chns.MIXED), ("fp64", chns.F64)):
         if name not in forms:
             continue
-        opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart)
+        opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, **MG)
         log(f"chac{n}: {name} warmup {args.warmup} + {args.steps} timed steps")
         run_steps(ctx, chns, f_in, f_out, args.warmup, opts)
         torch.cuda.synchronize()
@@ -515,7 +521,7 @@ def main():
     if not args.no_ledger and "mixed" in forms:
         log("kernels: ledger passes (the timed steps again, one kernel class per pass)")
         kern = kernel_ledger(ctx, chns, f_in, f_out, args.steps,
-                             chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=args.restart),
+                             chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=args.restart, **MG),
                              args.kernel_passes)
     probe = None if args.no_copy_probe else copy_probe()
 
@@ -526,7 +532,7 @@ def main():
             ctx.set_params(**dict(p, tau=tau))
             row = dict(tau=tau)
             for name, prec in (("fp64", chns.F64), ("mixed", chns.MIXED)):
-                opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, maxiter=2000)
+                opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, maxiter=2000, **MG)
                 f = fresh()
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -579,7 +585,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"chac{n}: coupled CH + AC step, periodic {n}x{n} P1 ({N} nodes, "
                                f"{3 * N} unknowns), eps {cfg['eps']}, tau {args.tau}, FGMRES({args.restart}) "
-                               f"rtol 1e-8, V(2,2) block preconditioner",
+                               f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) block preconditioner (hierarchies cut "
+                               f"at rho <= {MG['mg_rho_cut']}, {MG['mg_coarse']} coarse steps)",
                    "n": n, "tau": args.tau, "restart": args.restart},
         "roofline": None if kd is None else {
             "bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,

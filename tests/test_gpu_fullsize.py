@@ -2,7 +2,7 @@
 times (through the C-ABI).
 
 * chac1024 (1024 x 1024 CH + AC): one step against the oracle's exact
-  Fourier-mode solve.  Bench configuration (FGMRES(15), rtol 1e-8): true
+  Fourier-mode solve.  Bench configuration (FGMRES(15), V(1,2) cut at rho <= 4, rtol 1e-8): true
   residual in the oracle's arithmetic <= 2 rtol, and the forward error <=
   2 kappa rtol with kappa the condition number of the CH block from its
   Fourier symbols.  Tighter solves reach the stated accuracy: FP64 at rtol
@@ -27,6 +27,9 @@ from oracle.systems import Params
 from paper_2501_11767_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+# the multigrid options bench.py times the 1024^2 workload with
+BENCH_MG = dict(mg_pre=1, mg_post=2, mg_coarse=4, mg_rho_cut=4.0)
 
 
 @pytest.fixture(scope="module")
@@ -106,7 +109,7 @@ def test_chac1024_step_matches_exact_solve(mods, precision, rtol, bar):
     out = [z(), z(), z()]
     fout = ctx.fields(phi=[out[0]], mu=[out[1]], Phi_v=out[2])
     prec = C.F64 if precision == "f64" else C.MIXED
-    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=prec, restart=15, maxiter=600))
+    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=prec, restart=15, maxiter=600, **BENCH_MG))
     torch.cuda.synchronize()
     assert rc == C.OK, info
     phi, mu, Phi = (t.cpu().numpy() for t in out)
@@ -130,9 +133,9 @@ def test_chac1024_step_matches_exact_solve(mods, precision, rtol, bar):
 def test_precond_ragged_finest_tiles_matches_oracle_cycle(mods):
     """CH and AC preconditioners of the 1024^2 workload's parameters on a
     1040 x 1040 mesh (1040 = 16 * 64 + 16: a ragged last row and column of
-    finest-level tiles), V(2,2) with the default coarse steps: FP64 cycle
-    within 1e-12 of the oracle's cycle, FP32 cycle (with the fused FP64
-    boundary) within 1e-5."""
+    finest-level tiles), with the library's default multigrid options and with
+    the benchmark's: FP64 cycle within 1e-12 of the oracle's cycle, FP32 cycle
+    (with the fused FP64 boundary) within 1e-5."""
     import torch
     from oracle import precond as PC
     C, _ = mods
@@ -144,24 +147,25 @@ def test_precond_ragged_finest_tiles_matches_oracle_cycle(mods):
     m = fem.Mesh(n)
     prm = Params(**p)
     M, K = fem.p1_mass(m), fem.p1_stiffness(m)
-    o = C.default_opts()
-    kw = dict(pre=o.mg_pre, post=o.mg_post, coarse=o.mg_coarse)
     g = np.random.default_rng(11)
-    P = PC.CHPreconditioner(M, K, None, prm, n, inner="mg", cycles=1, **kw)
     r = g.standard_normal(2 * n * n)
-    ref = P.apply(r)
-    Pa = PC.ACPreconditioner(systems.ac_matrix(M, K, None, prm), n, prm, inner="mg", cycles=1, **kw)
     ra = g.standard_normal(n * n)
-    refa = Pa.apply(ra)
-    for prec, bar in ((C.F64, 1e-12), (C.MIXED, 1e-5)):
-        o = C.default_opts(precision=prec)
-        z = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
-        ctx.precond(C.BLOCK_CH, _dev(r), z, o)
-        za = torch.zeros(n * n, dtype=torch.float64, device="cuda")
-        ctx.precond(C.BLOCK_AC, _dev(ra), za, o)
-        torch.cuda.synchronize()
-        assert _rel(z.cpu().numpy(), ref) < bar, prec
-        assert _rel(za.cpu().numpy(), refa) < bar, prec
+    d = C.default_opts()
+    for mgo in (dict(mg_pre=d.mg_pre, mg_post=d.mg_post, mg_coarse=d.mg_coarse, mg_rho_cut=d.mg_rho_cut),
+                BENCH_MG):
+        kw = dict(pre=mgo["mg_pre"], post=mgo["mg_post"], coarse=mgo["mg_coarse"], rho_cut=mgo["mg_rho_cut"])
+        ref = PC.CHPreconditioner(M, K, None, prm, n, inner="mg", cycles=1, **kw).apply(r)
+        Pa = PC.ACPreconditioner(systems.ac_matrix(M, K, None, prm), n, prm, inner="mg", cycles=1, **kw)
+        refa = Pa.apply(ra)
+        for prec, bar in ((C.F64, 1e-12), (C.MIXED, 1e-5)):
+            o = C.default_opts(precision=prec, **mgo)
+            z = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+            ctx.precond(C.BLOCK_CH, _dev(r), z, o)
+            za = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+            ctx.precond(C.BLOCK_AC, _dev(ra), za, o)
+            torch.cuda.synchronize()
+            assert _rel(z.cpu().numpy(), ref) < bar, (prec, mgo)
+            assert _rel(za.cpu().numpy(), refa) < bar, (prec, mgo)
     ctx.close()
 
 
