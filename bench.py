@@ -42,7 +42,7 @@ TRAFFIC = {
     # filled in from profiles/chac1024_dcgs_update_hbm_counters.md (FETCH_SIZE and
     # WRITE_SIZE per dispatch, scaled by the 512 MiB negation probe) once the
     # counters are taken for the pass as it stands: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-    "k_dcgs_update": 167859740,
+    "k_dcgs_update": 145230503,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 
@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--tau", type=float, default=1e-4)
-    ap.add_argument("--restart", type=int, default=15)
+    ap.add_argument("--restart", type=int, default=12)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ledger", action="store_true", help="no kernel events in the timed steps")
@@ -460,6 +460,15 @@ def oracle_errors(cfg, n, st0, sweep, sweep_fields):
         ph, mu = solvers.fft_ch_solve(n, prm, Mx(phi0), -(prm.tau * prm.gamma / prm.beta) * Mx(fp))
         Ph = solvers.fft_ac_solve(n, prm, Mx(Phi0) - prm.tau * prm.gamma_v * Mx(fv))
         row["oracle_ms"] = (time.perf_counter() - t0) * 1e3
+        # condition number of the CH block from its per-mode symbols: the forward
+        # error of a solve stopped at true residual rtol is bounded by kappa rtol
+        tg, cc = prm.tau * prm.gamma, prm.tau * prm.gamma / prm.beta
+        m_, k_ = Mh.ravel(), Kh.ravel()
+        tr, det = m_ - cc * m_, -cc * m_ * m_ - (tg * k_) ** 2
+        disc = np.sqrt(np.maximum(tr * tr / 4 - det, 0.0))
+        ev = np.abs(np.concatenate([tr / 2 + disc, tr / 2 - disc]))
+        row["kappa_ch"] = float(ev.max() / ev.min())
+        row["error_bound_kappa_rtol"] = row["kappa_ch"] * 1e-8
         rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
         for name in ("fp64", "mixed"):
             g = sweep_fields[(row["tau"], name)]
