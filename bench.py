@@ -29,11 +29,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BATCH_RESTART = 60  # restart length of the batched workload and its sequential comparison
-# multigrid of the 1024^2 workload: V(1,2), 4 Chebyshev steps on the cut level,
-# hierarchies cut at the first level with rho <= 4 (measured fastest over the
-# tau sweep, same iteration counts within 2; the library default is V(2,2),
-# 8 steps, rho <= 0.25)
-MG = dict(mg_pre=1, mg_post=2, mg_coarse=4, mg_rho_cut=4.0)
+# multigrid of the 1024^2 workload: V(1,2), 8 Chebyshev steps on the cut level,
+# hierarchies cut at the first level with rho <= 16 (measured fastest over the
+# tau sweep, mixed and FP64; the library default is V(2,2), 8 steps, rho <= 0.25)
+MG = dict(mg_pre=1, mg_post=2, mg_coarse=8, mg_rho_cut=16.0)
 # HBM bytes per launch of a kernel from rocprofv3 counter runs of this
 # benchmark (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
 # copy of known size); filled in from profiles/ once measured for the kernel

@@ -2,7 +2,7 @@
 times (through the C-ABI).
 
 * chac1024 (1024 x 1024 CH + AC): one step against the oracle's exact
-  Fourier-mode solve.  Bench configuration (FGMRES(12), V(1,2) cut at rho <= 4, rtol 1e-8): true
+  Fourier-mode solve.  Bench configuration (FGMRES(12), V(1,2) cut at rho <= 16, rtol 1e-8): true
   residual in the oracle's arithmetic <= 2 rtol, and the forward error <=
   2 kappa rtol with kappa the condition number of the CH block from its
   Fourier symbols.  Tighter solves reach the stated accuracy: FP64 at rtol
@@ -29,7 +29,7 @@ from paper_2501_11767_amd import inputs
 pytestmark = pytest.mark.gpu
 
 # the multigrid options bench.py times the 1024^2 workload with
-BENCH_MG = dict(mg_pre=1, mg_post=2, mg_coarse=4, mg_rho_cut=4.0)
+BENCH_MG = dict(mg_pre=1, mg_post=2, mg_coarse=8, mg_rho_cut=16.0)
 
 
 @pytest.fixture(scope="module")
