@@ -7,7 +7,8 @@ times (through the C-ABI).
   2 kappa rtol with kappa the condition number of the CH block from its
   Fourier symbols.  Tighter solves reach the stated accuracy: FP64 at rtol
   1e-11 within 1e-10 relative, mixed at rtol 1e-9 within 1e-8.
-* dry256 (ternary + AC + Oseen on 256 x 256): the GPU step's outputs satisfy
+* dry256 (ternary + AC + Oseen on 256 x 256, the benchmark's FGMRES(15) and
+  multigrid options): the GPU step's outputs satisfy
   the oracle's independently assembled systems (CH for both phases, AC,
   Oseen with B v = 0 rows, the solvent closure) to 2 rtol.
 * batch64: every instance's true residual (oracle symbols) <= 2 rtol and the
@@ -186,7 +187,7 @@ def test_dry256_step_satisfies_oracle_systems(mods):
                      Phi_v=_dev(st["Phi_v"]), vel=_dev(vel0), p=z(N))
     o = dict(phi=[z(N), z(N)], mu=[z(N), z(N), z(N)], Phi_v=z(N), vel=z(8 * N), p=z(N))
     fout = ctx.fields(**o)
-    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=C.F64, maxiter=1000))
+    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=C.F64, maxiter=1000, restart=15, **BENCH_MG))
     torch.cuda.synchronize()
     assert rc == C.OK, info
     g = {k: ([t.cpu().numpy() for t in v] if isinstance(v, list) else v.cpu().numpy()) for k, v in o.items()}
