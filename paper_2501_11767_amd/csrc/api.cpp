@@ -331,6 +331,7 @@ void vtile_at(chns_ctx* c, int mode, const TileArgs<T>& a, bool finest, hipStrea
   double per = 8.0 * t + bin;
   if (mode == TILE_DOWN) per += 1.25 * t;
   else if (mode == TILE_UP) per += 1.25 * t + xout;
+  else if (mode == TILE_UPM) per += 8.25 * t + xout;  // and the values of M
   else per += xout;
   timed(c, CHNS_KERNEL_MG_FINE, rows * per, s, [&](LaunchEv ev) { vtile<T>(mode, a, s, ev); });
 }
@@ -828,7 +829,8 @@ void ch_precond_t(chns_ctx* c, const T* r, T* z, T* tmp1, T* tmp2, const chns_so
 // given (else to x).
 template <typename T>
 void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const double* b64, T* x,
-                double* x64, const double* xs, const chns_solve_opts& o, hipStream_t s) {
+                double* x64, const double* xs, const chns_solve_opts& o, hipStream_t s,
+                const T* mval = nullptr) {
   Level& L = c->lv[0];
   Level& G = c->lv[1];
   const OpVals& A = L.*op;
@@ -847,7 +849,8 @@ void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const do
   up.x = x;
   up.x64 = x64;
   up.xs = xs;
-  vtile_at<T>(c, TILE_UP, up, true, s);
+  up.mval = mval;  // when given, the pass writes M times the result
+  vtile_at<T>(c, mval ? TILE_UPM : TILE_UP, up, true, s);
 }
 
 // Whether the cycles of a block (precision T) can take their FP64 input and
@@ -892,8 +895,13 @@ void fused_precond(chns_ctx* c, int block, const chns_solve_opts& o, const doubl
   T* t2 = std::is_same<T, double>::value ? (T*)c->w64b : (T*)c->w32b;
   const size_t cutX = cut_level(c, coef_of(c, &Level::X), o.mg_rho_cut);
   zero_cut(&Level::L, r, z);
-  vcycle_top<T>(c, &Level::X, cutX, nullptr, r + N, t1, nullptr, nullptr, o, s);
-  spmv<T, T>(L0.d, Sel<T>::M(L0), t1, t2, T(1), T(0), s);
+  if (tile_fits<T>(TILE_UPM, L0.d.side, o.mg_post)) {
+    // the first cycle's up pass writes M X^{-1} r2 directly
+    vcycle_top<T>(c, &Level::X, cutX, nullptr, r + N, t2, nullptr, nullptr, o, s, Sel<T>::M(L0));
+  } else {
+    vcycle_top<T>(c, &Level::X, cutX, nullptr, r + N, t1, nullptr, nullptr, o, s);
+    spmv<T, T>(L0.d, Sel<T>::M(L0), t1, t2, T(1), T(0), s);
+  }
   vcycle_top<T>(c, &Level::X, cutX, t2, nullptr, nullptr, z + N, inv, o, s);
 }
 

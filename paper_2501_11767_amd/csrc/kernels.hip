@@ -234,7 +234,7 @@ __device__ __forceinline__ int wrap_once(int x, int s) { return x < 0 ? x + s : 
 
 // Halo rings of a tiled launch.
 __host__ __device__ constexpr int tile_halo(int mode, int steps) {
-  return mode == TILE_ZERO ? steps - 1 : (mode == TILE_DOWN ? steps + 1 : steps);
+  return mode == TILE_ZERO ? steps - 1 : (mode == TILE_DOWN || mode == TILE_UPM ? steps + 1 : steps);
 }
 
 // One tile of a level (tile index `tile` of the side x side grid, row-major
@@ -248,8 +248,10 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
                                            const T* c2s, int tile, T* xa, T* xb,
                                            const double* __restrict__ b64 = nullptr,
                                            double* __restrict__ x64 = nullptr,
-                                           const double* __restrict__ xs = nullptr) {
+                                           const double* __restrict__ xs = nullptr,
+                                           const T* __restrict__ mval = nullptr) {
   constexpr int RPT = TileCfg<TT>::RPT, NTH = TileCfg<TT>::NTH;
+  constexpr bool UPLIKE = MODE == TILE_UP || MODE == TILE_UPM;
   const int H = tile_halo(MODE, steps);
   const int W = TT + 2 * H, R = W * W;
   const int nt = (s + TT - 1) / TT;
@@ -281,17 +283,17 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
       const bool upd = ring[q] >= 1;
 #pragma unroll
       for (int k = 0; k < W7; ++k) v[q][k] = upd ? val[base + k * 64] : T(0);
-      if (MODE == TILE_UP && !upd) {
+      if (UPLIKE && !upd) {
         di[q] = T(0);
         bb[q] = T(0);
       } else {
         di[q] = dinv[row];
         bb[q] = b64 ? T(b64[row]) : b[row];
       }
-      if (MODE == TILE_UP) xa[idx] = xin[row] + p1_interp(e, gi, gj, s >> 1);
+      if (UPLIKE) xa[idx] = xin[row] + p1_interp(e, gi, gj, s >> 1);
     }
   }
-  if (MODE != TILE_UP) {  // first step from zero: x = d = c2 D^{-1} b
+  if (!UPLIKE) {  // first step from zero: x = d = c2 D^{-1} b
     const T c20 = c2s[0];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -306,7 +308,7 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
   T* cur = xa;
   T* nxt = xb;
   // Chebyshev steps k0.. on shrinking rings: step k is valid at ring >= k - k0 + 1
-  const int k0 = (MODE == TILE_UP) ? 0 : 1;
+  const int k0 = UPLIKE ? 0 : 1;
   for (int k = k0; k < steps; ++k) {
     const T c1 = c1s[k], c2 = c2s[k];
     const int rmin = k - k0 + 1;
@@ -328,7 +330,24 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
     cur = nxt;
     nxt = t;
   }
-  if (x64) {
+  if constexpr (MODE == TILE_UPM) {
+    // the result is valid at ring >= steps, so on every neighbour of an own row
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (own[q]) {
+        const int idx = tid + q * NTH;
+        const size_t base = size_t(gr[q] >> 6) * (64 * W7) + (gr[q] & 63);
+        T m[W7];
+#pragma unroll
+        for (int k = 0; k < W7; ++k) m[k] = mval[base + k * 64];
+        T y = T(0);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) y += m[k] * cur[idx + off[k]];
+        if (x64) x64[gr[q]] = double(y) * (xs ? xs[0] : 1.0);
+        else x[gr[q]] = y;
+      }
+    }
+  } else if (x64) {
     const double sc = xs ? xs[0] : 1.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q)
@@ -373,7 +392,7 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_vtile(TileArgs<T> a) {
   constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
   __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
   vtile_body<T, MODE, TT>(a.side, a.steps, a.val, a.dinv, a.b, a.xin, a.e, a.x, a.bc, a.c1, a.c2,
-                          xcd_block(blockIdx.x, gridDim.x), xa, xb, a.b64, a.x64, a.xs);
+                          xcd_block(blockIdx.x, gridDim.x), xa, xb, a.b64, a.x64, a.xs, a.mval);
 }
 
 // Batched: workgroup -> (instance, tile) from the tile list; the launch's
@@ -2011,7 +2030,8 @@ bool tile_fits(int mode, int side, int steps) {
   const int H = tile_halo(mode, steps);
   const int TT = tile_side<T>(side);
   const int hmax = TT == 64 ? TileCfg<64>::HMAX : (TT == 32 ? TileCfg<32>::HMAX : TileCfg<16>::HMAX);
-  if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > hmax) return false;
+  if (steps < (mode == TILE_UP || mode == TILE_UPM ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > hmax)
+    return false;
   if (side < TT + hmax) return false;  // one wrap reaches every halo row
   return mode != TILE_DOWN || side % 2 == 0;
 }
@@ -2022,6 +2042,7 @@ void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev) {
   const dim3 g(nt * nt), b(TileCfg<TT>::NTH);
   if (mode == TILE_ZERO) LAUNCH_EV(ev, (k_vtile<T, TILE_ZERO, TT>), g, b, 0, s, a);
   else if (mode == TILE_DOWN) LAUNCH_EV(ev, (k_vtile<T, TILE_DOWN, TT>), g, b, 0, s, a);
+  else if (mode == TILE_UPM) LAUNCH_EV(ev, (k_vtile<T, TILE_UPM, TT>), g, b, 0, s, a);
   else LAUNCH_EV(ev, (k_vtile<T, TILE_UP, TT>), g, b, 0, s, a);
 }
 

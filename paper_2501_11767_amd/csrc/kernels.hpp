@@ -116,7 +116,9 @@ void bvtail(int n, const TailArgs<T>* list, const int* idx, const int* act, cons
 //   TILE_UP:   x' = xin + P e (e on the side/2 grid), then `steps`
 //              post-smoothing steps (H = steps); x written (x != xin).
 // c1/c2: the Chebyshev coefficients of the steps (c1[0] unused).
-enum TileMode { TILE_ZERO = 0, TILE_DOWN = 1, TILE_UP = 2 };
+//   TILE_UPM:  as TILE_UP over one more halo ring (H = steps + 1), then writes
+//              M x (mval: the values of M, same pattern) instead of x.
+enum TileMode { TILE_ZERO = 0, TILE_DOWN = 1, TILE_UP = 2, TILE_UPM = 3 };
 constexpr int TILE_MAXSTEPS = 9;
 template <typename T>
 struct TileArgs {
@@ -137,6 +139,7 @@ struct TileArgs {
   const double* b64 = nullptr;
   double* x64 = nullptr;
   const double* xs = nullptr;
+  const T* mval = nullptr;  // TILE_UPM: values of the matrix applied to the result
 };
 // Tile side of a level: float levels of side >= 1024 take 64 x 64 tiles
 // (256 or more tiles), levels of side <= 256 take 16 x 16 tiles (256-thread
