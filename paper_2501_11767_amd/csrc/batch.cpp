@@ -630,7 +630,7 @@ void set_cheb(BTileLaunch<T>& a, double lmax, int steps) {
 template <typename T>
 void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* act,
                    const chns_solve_opts& o, hipStream_t s, const double* b64 = nullptr,
-                   double* x64 = nullptr, const double* xs = nullptr) {
+                   double* x64 = nullptr, const double* xs = nullptr, const T* mval = nullptr) {
   BLevel& L = b->lv[l];
   const T* v = BSel<T>::v(L, op);
   const T* di = BSel<T>::d(L, op);
@@ -674,7 +674,8 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
   a.x64 = x64;
   a.xs = xs;
   a.bc = nullptr;
-  bvtile<T>(TILE_UP, L.ntdown[op], a, s);
+  a.mval = mval;  // when given (level 0), the up pass writes M times the result
+  bvtile<T>(mval ? TILE_UPM : TILE_UP, L.ntdown[op], a, s);
 }
 
 template <typename T>
@@ -726,9 +727,13 @@ void bprecond(chns_batch* b, int block, const double* r, const double* inv, doub
     } else {
       BLevel& L0 = b->lv[0];
       bvcycle_tiled<float>(b, 0, 0, nullptr, nullptr, act, o, s, r, z, inv);
-      bvcycle_tiled<float>(b, 1, 0, nullptr, b->w32a, act, o, s, r + N, nullptr, nullptr);
-      bstencil<float>(L0.st, L0.M32, 0, b->w32a, nullptr, nullptr, nullptr, 1.0f, 0.0f, nullptr, nullptr,
-                      nullptr, act, b->w32b, s);
+      if (btile_fits(TILE_UPM, 64, o.mg_post)) {  // the first cycle's up pass writes M X^{-1} r2
+        bvcycle_tiled<float>(b, 1, 0, nullptr, b->w32b, act, o, s, r + N, nullptr, nullptr, L0.M32);
+      } else {
+        bvcycle_tiled<float>(b, 1, 0, nullptr, b->w32a, act, o, s, r + N, nullptr, nullptr);
+        bstencil<float>(L0.st, L0.M32, 0, b->w32a, nullptr, nullptr, nullptr, 1.0f, 0.0f, nullptr, nullptr,
+                        nullptr, act, b->w32b, s);
+      }
       bvcycle_tiled<float>(b, 1, 0, b->w32b, nullptr, act, o, s, nullptr, z + N, inv);
     }
     return;

@@ -415,7 +415,8 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_bvtile(BTileLaunch<T> a) {
   vtile_body<T, MODE, TT>(t.side, a.steps, a.val + r * W7, a.dinv + r, a.b ? a.b + r : nullptr,
                           a.xin ? a.xin + r : nullptr, a.e ? a.e + rc : nullptr, a.x ? a.x + r : nullptr,
                           a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile, xa, xb, a.b64 ? a.b64 + r : nullptr,
-                          a.x64 ? a.x64 + r : nullptr, a.xs ? a.xs + t.inst : nullptr);
+                          a.x64 ? a.x64 + r : nullptr, a.xs ? a.xs + t.inst : nullptr,
+                          a.mval ? a.mval + r * W7 : nullptr);
 }
 
 // ------------------------------------------------------------------ paired levels
@@ -2079,7 +2080,8 @@ void vup2(const Tile2Args<T>& a, hipStream_t s) {
 
 bool btile_fits(int mode, int side, int steps) {
   const int H = tile_halo(mode, steps);
-  if (steps < (mode == TILE_UP ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 || H > TileCfg<32>::HMAX)
+  if (steps < (mode == TILE_UP || mode == TILE_UPM ? 0 : 1) || steps > TILE_MAXSTEPS || H < 0 ||
+      H > TileCfg<32>::HMAX)
     return false;
   if (side < 32 + TileCfg<32>::HMAX) return false;
   return mode != TILE_DOWN || side % 2 == 0;
@@ -2096,6 +2098,7 @@ void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s) {
   const dim3 g(ntiles), b(TILE_THREADS);
   if (mode == TILE_ZERO) hipLaunchKernelGGL((k_bvtile<T, TILE_ZERO, 32>), g, b, 0, s, a);
   else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_bvtile<T, TILE_DOWN, 32>), g, b, 0, s, a);
+  else if (mode == TILE_UPM) hipLaunchKernelGGL((k_bvtile<T, TILE_UPM, 32>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_bvtile<T, TILE_UP, 32>), g, b, 0, s, a);
 }
 

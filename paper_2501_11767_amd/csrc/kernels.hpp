@@ -223,6 +223,7 @@ struct BTileLaunch {
   const double* b64 = nullptr;
   double* x64 = nullptr;
   const double* xs = nullptr;
+  const T* mval = nullptr;  // TILE_UPM (as in TileArgs), offset per instance like val
 };
 bool btile_fits(int mode, int side, int steps);
 int btile_count(int side);  // tiles of one instance level
