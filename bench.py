@@ -44,7 +44,7 @@ TRAFFIC = {
     # filled in from profiles/chac1024_dcgs_update_hbm_counters.md (FETCH_SIZE and
     # WRITE_SIZE per dispatch, scaled by the 512 MiB negation probe) once the
     # counters are taken for the pass as it stands: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-    "k_dcgs_update": 145230503,
+    "k_dcgs_update": 145224356,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 
