@@ -1005,7 +1005,6 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   st.sn = K.sn;
   st.g = K.g;
   st.gp = K.gp;
-  st.coef = K.coef;
   st.scal = K.scal;
   st.m = m;
   chns_solve_info inf{};
@@ -1478,7 +1477,6 @@ int build(chns_ctx* c) {
   TRY(dalloc(c, &K.HR, size_t(MAX_RESTART + 1) * MAX_RESTART));
   TRY(dalloc(c, &K.gp, MAX_RESTART + 2));
   TRY(dalloc(c, &K.red, 2 * MAX_RESTART + 4));
-  TRY(dalloc(c, &K.coef, 2 * MAX_RESTART + 4));
   TRY(dalloc(c, &K.nrm_part, 1024));
   HIPCHK(c, hipHostMalloc((void**)&K.host, 16 * sizeof(double), hipHostMallocDefault));
   for (auto& e : K.done) HIPCHK(c, hipEventCreate(&e));

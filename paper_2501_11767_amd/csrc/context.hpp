@@ -96,7 +96,7 @@ struct Krylov {
   double *V = nullptr, *Z = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *scal = nullptr, *part = nullptr, *nrm_part = nullptr;
-  double *HR = nullptr, *gp = nullptr, *red = nullptr, *coef = nullptr;  // DCGS2
+  double *HR = nullptr, *gp = nullptr, *red = nullptr;  // DCGS2
   double* host = nullptr;  // pinned readback: two 4-double slots for the lookahead, 8 for restarts
   hipEvent_t done[2] = {nullptr, nullptr};
   hipEvent_t rdone = nullptr;  // restart norms read back

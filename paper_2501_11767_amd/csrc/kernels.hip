@@ -1023,39 +1023,42 @@ __global__ __launch_bounds__(BS) void k_slot_reduce(int nblk, const double* __re
   if (threadIdx.x == 0) red[k] = a;
 }
 
-// Coefficients of step j from the reduced dots (one wavefront).  j >= 1:
-// vt = sum c_i V_i + r v_j with r = sqrt(vt.vt - |c|^2); column j-1 of the
-// raw Hessenberg H (whose last entry multiplied vt) becomes h_i += h_j c_i,
-// h_j *= r.  Projection of w on the final basis: a_i = V_i . w (i < j),
-// b = (vt . w - c . a) / r; so w' = w - sum (a_i - b c_i / r) V_i - (b / r) vt
-// and v_j = (vt - sum c_i V_i) / r.  coef: [0, j) c_i, [j, 2j+1) the w
-// coefficients (last one multiplies vt), 2j+1: 1/r.  j < 64.
-__global__ __launch_bounds__(64) void k_dcgs_coef(int j, int m, const double* __restrict__ red,
-                                                  double* __restrict__ H, double* __restrict__ coef) {
+// Coefficients of step j from the reduced dots, formed by the first wavefront
+// of a workgroup into LDS.  j >= 1: vt = sum c_i V_i + r v_j with
+// r = sqrt(vt.vt - |c|^2); column j-1 of the raw Hessenberg H (whose last entry
+// multiplied vt) becomes h_i += h_j c_i, h_j *= r.  Projection of w on the
+// final basis: a_i = V_i . w (i < j), b = (vt . w - c . a) / r; so
+// w' = w - sum (a_i - b c_i / r) V_i - (b / r) vt and v_j = (vt - sum c_i V_i) / r.
+// cf: [0, j) c_i, [j, 2j+1) the w coefficients (last one multiplies vt),
+// 2j+1: 1/r.  H is written only when write_h (one workgroup of the launch).
+// j < 64.
+__device__ void form_coefs(int j, int m, const double* __restrict__ red, double* __restrict__ H,
+                           double* __restrict__ cf, bool write_h) {
   const int t = threadIdx.x, ld = m + 1;
   const double c = t < j ? red[t] : 0.0;
   const double a = t < j ? red[j + t] : 0.0;
-  const double hj = j > 0 ? H[int64_t(j - 1) * ld + j] : 0.0;
   const double cc = wave_sum(c * c), ca = wave_sum(c * a);
   const double nu = red[2 * j], tw = red[2 * j + 1];
   const double r = j > 0 ? sqrt(fmax(nu - cc, 0.0)) : 1.0;
   const double inv = r > 0.0 ? 1.0 / r : 0.0;
   const double b = (tw - ca) * inv;
+  if (t < j) {
+    cf[t] = c;
+    cf[j + t] = a - b * c * inv;
+  }
+  if (t == 0) {
+    cf[2 * j] = b * inv;
+    cf[2 * j + 1] = inv;
+  }
+  if (!write_h) return;
+  const double hj = j > 0 ? H[int64_t(j - 1) * ld + j] : 0.0;
   if (j > 0 && t <= j) {
     double* hp = H + int64_t(j - 1) * ld;
     hp[t] = (t < j) ? hp[t] + hj * c : hj * r;
   }
   double* h = H + int64_t(j) * ld;
-  if (t < j) {
-    h[t] = a;
-    coef[t] = c;
-    coef[j + t] = a - b * c * inv;
-  }
-  if (t == 0) {
-    h[j] = b;
-    coef[2 * j] = b * inv;
-    coef[2 * j + 1] = inv;
-  }
+  if (t < j) h[t] = a;
+  if (t == 0) h[j] = b;
 }
 
 // The CH block product w = A z (both block rows of node r: y1 = L z1 + c12 K
@@ -1285,15 +1288,17 @@ __global__ __launch_bounds__(BS) void k_dcgs_finish(int nblk, const double* __re
   }
 }
 
-// w <- w - sum_{i<j} coef[j+i] V_i - coef[2j] vt; vt <- (vt - sum_{i<j} coef[i] V_i) / r
+// w <- w - sum_{i<j} cf[j+i] V_i - cf[2j] vt; vt <- (vt - sum_{i<j} cf[i] V_i) / r
 // (j > 0); per-block partials of |w'|^2.
+// Every workgroup forms the coefficients from the slot sums `red` itself
+// (form_coefs); workgroup 0 also corrects H.
 __global__ __launch_bounds__(BS) void k_dcgs_update(int64_t n, double* __restrict__ V, int64_t ld, int j,
-                                                    const double* __restrict__ coef,
-                                                    double* __restrict__ nrm_part,
+                                                    int m, const double* __restrict__ red,
+                                                    double* __restrict__ H, double* __restrict__ nrm_part,
                                                     const double* __restrict__ vscale) {
   __shared__ double cs_l[2 * 64 + 2];
   __shared__ double sh[4];
-  for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cs_l[i] = coef[i];
+  if (threadIdx.x < 64) form_coefs(j, m, red, H, cs_l, blockIdx.x == 0);
   __syncthreads();
   double* vt = V + int64_t(j) * ld;
   double* w = V + int64_t(j + 1) * ld;
@@ -2192,7 +2197,7 @@ static void launch_dots_kk(int kk, int64_t n, const double* V, int64_t ld, int j
 }
 
 // Full groups of DG vectors, then the remainder group with vt . vt, vt . w,
-// w . w (one launch when j < DG), then the slot sums and the coefficients.
+// w . w (one launch when j < DG), then the slot sums.
 void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
                LaunchEv ev) {
   const int full = j / DG, rem = j - full * DG;
@@ -2200,7 +2205,6 @@ void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& s
     launch_dots_kk<false>(DG, n, V, ld, j, g * DG, st, s, g == 0 ? ev : LaunchEv{});
   launch_dots_kk<true>(rem, n, V, ld, j, full * DG, st, s, full == 0 ? ev : LaunchEv{});
   hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(n), st.part, st.red);
-  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, st.m, st.red, st.H, st.coef);
 }
 
 template <bool LM>
@@ -2231,13 +2235,12 @@ void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const doub
   else launch_ch_dots<false>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
   hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(2 * int64_t(N)), st.part,
                      st.red);
-  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, s, j, st.m, st.red, st.H, st.coef);
 }
 
 void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, hipStream_t s,
                  LaunchEv ev) {
-  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, st.coef, st.nrm_part,
-            st.vscale);
+  LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, st.m, st.red, st.H,
+            st.nrm_part, st.vscale);
   hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(BS), 0, s, reduce_blocks(n), st.nrm_part, j, st.m, st.H,
                      st.HR, st.cs, st.sn, st.g, st.gp, st.scal, host);
 }

@@ -263,27 +263,29 @@ int dcgs_dot_blocks(int64_t n);
 struct DcgsState {
   double *part = nullptr, *red = nullptr, *nrm_part = nullptr;
   double *H = nullptr, *HR = nullptr, *cs = nullptr, *sn = nullptr;
-  double *g = nullptr, *gp = nullptr, *coef = nullptr, *scal = nullptr;
+  double *g = nullptr, *gp = nullptr, *scal = nullptr;
   // V_j as stored times vscale[0] is the step's vector (may be null: 1); the
   // passes scale it on load and the update pass stores it normalised
   const double* vscale = nullptr;
   int m = 0;
 };
-// Dot pass, slot sums, then one wavefront that forms the
-// reorthogonalisation coefficients of V_j, the correction of Hessenberg
-// column j-1 and the projection coefficients of w (into coef and H).
+// Dot pass and slot sums (into red: V_i . v_j, V_i . w for i < j, then
+// v_j . v_j, v_j . w, w . w); the update pass forms the coefficients.
 void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
                LaunchEv ev = {});
 // The CH block operator (as ch_block with alpha = 1, beta = 0; L == M
 // selects the convection-free form) applied to z into V_{j+1} and the dot pass
-// of step j in one launch, then the slot sums and coefficients as dcgs_dots;
+// of step j in one launch, then the slot sums as dcgs_dots;
 // for j with ch_dots_fits(j) (j < 16).
 bool ch_dots_fits(int j);
 void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const double* Mv, double c12, double c22,
                   const double* z, double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s,
                   LaunchEv ev = {});
-// Update pass: V_j <- its reorthogonalised, normalised form (j > 0), w <-
-// w projected out of the final basis; then one workgroup sets h_{j+1,j} = |w|,
+// Update pass: the reorthogonalisation coefficients of V_j and the projection
+// coefficients of w from the slot sums (and the correction of Hessenberg
+// column j-1 and column j of H); V_j <- its reorthogonalised, normalised form
+// (j > 0), w <- w projected out of the final basis; then one workgroup sets
+// h_{j+1,j} = |w|,
 // takes the final Givens rotation of column j-1 into HR and g, a provisional
 // rotation of column j into HR and gp, and scal = (|gp_{j+1}|, 1/|w|, |w|)
 // (also into pinned host memory `host` when given; w itself is not scaled).
