@@ -4,6 +4,8 @@
 
 #include <cmath>
 #include <algorithm>
+#include <atomic>
+#include <immintrin.h>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -985,6 +987,28 @@ int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha
 
 constexpr int64_t KRYLOV_PAD = 640;  // doubles (5 KiB) between consecutive basis vectors
 
+// Waits until a kernel on stream s has stored `tag` in slot[3] of pinned host
+// memory (after the slot's values, behind a system-scope fence: they are then
+// visible too).  Every few thousand polls it queries the stream, so that a
+// failed launch ends the wait with its error, and a stream found idle without
+// the tag is an error rather than a hang.
+int wait_slot(chns_ctx* c, const double* slot, double tag, hipStream_t s) {
+  const volatile double* t = slot + 3;
+  for (uint32_t it = 1; *t != tag; ++it) {
+    if ((it & 4095) == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (*t == tag) break;
+        return fail(c, CHNS_EHIP, "stream idle but the step's scalars were not written");
+      }
+      if (e != hipErrorNotReady) HIPCHK(c, e);
+    }
+    _mm_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return CHNS_OK;
+}
+
 int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_opts& o,
            chns_solve_info* info, hipStream_t s) {
   Krylov& K = c->kr;
@@ -1011,8 +1035,10 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   HIPCHK(c, hipEventRecord(c->ev0, s));
   // ||b|| into scal[4]; the host reads it together with the first residual
   norm_partial(n, b, K.nrm_part, s);
-  norm_finish(nblk, K.nrm_part, K.scal + 4, nullptr, m, s);
-  double* rslot = K.host + 8;  // restart read-back: beta, 1/beta, beta, -, ||b||
+  double* rslot = K.host + 8;  // restart read-back: beta, 1/beta, beta, tag, ||b||, -, -, tag
+  const double btag = ++K.tag;
+  norm_finish(nblk, K.nrm_part, K.scal + 4, nullptr, m, s, rslot + 4, btag);
+  double rtag = 0.0;
   double tol = 0.0;
   int iters = 0;
   bool first = true, stop = false;
@@ -1024,8 +1050,9 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   bool spec = true;
   int unread = -1;  // host slot of a finished cycle's last step, not yet read
   auto check = [&]() -> int {
-    HIPCHK(c, hipEventSynchronize(K.rdone));
+    TRY(wait_slot(c, rslot, rtag, s));
     if (first) {
+      TRY(wait_slot(c, rslot + 4, btag, s));
       inf.bnorm = rslot[4];
       if (!std::isfinite(inf.bnorm)) return fail(c, CHNS_EINVAL, "right-hand side is not finite");
       tol = std::fmax(o.rtol * inf.bnorm, o.atol);
@@ -1049,11 +1076,10 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
     HIPCHK(c, hipMemcpyAsync(K.V, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     TRY(apply_block(c, block, x, K.V, -1.0, 1.0, s));
     norm_partial(n, K.V, K.nrm_part, s);
-    norm_finish(nblk, K.nrm_part, K.scal, K.g, m, s);
-    HIPCHK(c, hipMemcpyAsync(rslot, K.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipEventRecord(K.rdone, s));
+    rtag = ++K.tag;
+    norm_finish(nblk, K.nrm_part, K.scal, K.g, m, s, rslot, rtag);
     if (unread >= 0) {  // the previous cycle's last estimate
-      HIPCHK(c, hipEventSynchronize(K.done[unread]));
+      TRY(wait_slot(c, K.host + 4 * unread, K.stag[unread], s));
       const double est = K.host[4 * unread];
       if (!(est > tol)) spec = false;
       unread = -1;
@@ -1090,7 +1116,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
         if (!(rate > 0.0) && j >= 3 && hist[j - 3] > 0.0) rate = hist[j - 2] / hist[j - 3];
         const double pred = rate > 0.0 ? last * rate : -1.0;
         if (pred >= 0.0 && pred <= 2.0 * tol) {
-          HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));
+          TRY(wait_slot(c, K.host + 4 * ((j - 1) & 1), K.stag[(j - 1) & 1], s));
           ++iters;
           checked = true;
           const double* prev = K.host + 4 * ((j - 1) & 1);
@@ -1131,10 +1157,10 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
               [&](LaunchEv ev) { dcgs_dots(n, K.V, ld, j, st, s, ev); });
       }
       double* slot = K.host + 4 * (j & 1);
+      const double tag = K.stag[j & 1] = ++K.tag;
       timed(c, CHNS_KERNEL_DCGS_UPDATE, 8.0 * n * (j + 2 + (j > 0 ? 1 : 0) + 1), s,
-            [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, st, slot, s, ev); });
+            [&](LaunchEv ev) { dcgs_update(n, K.V, ld, j, st, slot, tag, s, ev); });
       HIPCHK(c, hipGetLastError());
-      HIPCHK(c, hipEventRecord(K.done[j & 1], s));
       if (closing) {
         k = j;
         break;
@@ -1144,7 +1170,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
         if (stop) break;
       }
       if (j > 0 && !checked) {
-        HIPCHK(c, hipEventSynchronize(K.done[(j - 1) & 1]));
+        TRY(wait_slot(c, K.host + 4 * ((j - 1) & 1), K.stag[(j - 1) & 1], s));
         ++iters;
         const double* prev = K.host + 4 * ((j - 1) & 1);
         const double est = prev[0], hnext = prev[2];
@@ -1478,9 +1504,8 @@ int build(chns_ctx* c) {
   TRY(dalloc(c, &K.gp, MAX_RESTART + 2));
   TRY(dalloc(c, &K.red, 2 * MAX_RESTART + 4));
   TRY(dalloc(c, &K.nrm_part, 1024));
-  HIPCHK(c, hipHostMalloc((void**)&K.host, 16 * sizeof(double), hipHostMallocDefault));
-  for (auto& e : K.done) HIPCHK(c, hipEventCreate(&e));
-  HIPCHK(c, hipEventCreate(&K.rdone));
+  HIPCHK(c, hipHostMalloc((void**)&K.host, 16 * sizeof(double), hipHostMallocCoherent));
+  std::memset(K.host, 0, 16 * sizeof(double));
   HIPCHK(c, hipEventCreate(&c->ev0));
   HIPCHK(c, hipEventCreate(&c->ev1));
   // M and K on the finest level by coloured scatter, then Galerkin down
@@ -1520,9 +1545,6 @@ void release(chns_ctx* c) {
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->kr.host) (void)hipHostFree(c->kr.host);
-  for (auto& e : c->kr.done)
-    if (e) (void)hipEventDestroy(e);
-  if (c->kr.rdone) (void)hipEventDestroy(c->kr.rdone);
   for (auto& e : c->ledger.ev) (void)hipEventDestroy(e);
   c->ledger.ev.clear();
   if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -97,9 +97,12 @@ struct Krylov {
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *scal = nullptr, *part = nullptr, *nrm_part = nullptr;
   double *HR = nullptr, *gp = nullptr, *red = nullptr;  // DCGS2
-  double* host = nullptr;  // pinned readback: two 4-double slots for the lookahead, 8 for restarts
-  hipEvent_t done[2] = {nullptr, nullptr};
-  hipEvent_t rdone = nullptr;  // restart norms read back
+  // pinned readback: two 4-double slots for the lookahead, two for restarts
+  // (the residual norm, ||b||); a kernel writes a slot's three values, then,
+  // behind a system-scope fence, the slot's tag into its fourth entry
+  double* host = nullptr;
+  double tag = 0.0;                 // last tag issued
+  double stag[2] = {0.0, 0.0};      // tag awaited in each lookahead slot
   double rate[3] = {-1.0, -1.0, -1.0};  // per block: mean residual reduction per step of the last solve
 };
 

@@ -1228,7 +1228,8 @@ __global__ __launch_bounds__(BS) void k_dcgs_finish(int nblk, const double* __re
                                                     int m, double* __restrict__ H, double* __restrict__ HR,
                                                     double* __restrict__ cs, double* __restrict__ sn,
                                                     double* __restrict__ g, double* __restrict__ gp,
-                                                    double* __restrict__ scal, double* __restrict__ host) {
+                                                    double* __restrict__ scal, double* __restrict__ host,
+                                                    double tag) {
   __shared__ double hp[66], hc[66], cs_s[64], sn_s[64], g_s[66], res[3];
   __shared__ double sh[4];
   const int ld = m + 1, t = threadIdx.x;
@@ -1283,6 +1284,8 @@ __global__ __launch_bounds__(BS) void k_dcgs_finish(int nblk, const double* __re
     for (int i = 0; i < 3; ++i) scal[i] = sv[i];
     if (host) {
       for (int i = 0; i < 3; ++i) host[i] = sv[i];
+      __threadfence_system();
+      host[3] = tag;
       __threadfence_system();
     }
   }
@@ -1398,15 +1401,20 @@ __global__ __launch_bounds__(BS) void k_norm_partial(int64_t n, const double* __
 }
 
 __global__ void k_norm_finish(int nblk, const double* __restrict__ part, double* __restrict__ scal,
-                              double* __restrict__ g, int m) {
+                              double* __restrict__ g, int m, double* __restrict__ host, double tag) {
   const double nrm = sqrt(sum_partials_wave(nblk, part));
   if (threadIdx.x == 0) {
-    scal[0] = nrm;
-    scal[1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    scal[2] = nrm;
+    const double sv[3] = {nrm, nrm > 0.0 ? 1.0 / nrm : 0.0, nrm};
+    for (int i = 0; i < 3; ++i) scal[i] = sv[i];
     if (g) {
       g[0] = nrm;
       for (int i = 1; i <= m; ++i) g[i] = 0.0;
+    }
+    if (host) {
+      for (int i = 0; i < 3; ++i) host[i] = sv[i];
+      __threadfence_system();
+      host[3] = tag;
+      __threadfence_system();
     }
   }
 }
@@ -2237,12 +2245,12 @@ void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const doub
                      st.red);
 }
 
-void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, hipStream_t s,
-                 LaunchEv ev) {
+void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, double tag,
+                 hipStream_t s, LaunchEv ev) {
   LAUNCH_EV(ev, k_dcgs_update, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, V, ld, j, st.m, st.red, st.H,
             st.nrm_part, st.vscale);
   hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(BS), 0, s, reduce_blocks(n), st.nrm_part, j, st.m, st.H,
-                     st.HR, st.cs, st.sn, st.g, st.gp, st.scal, host);
+                     st.HR, st.cs, st.sn, st.g, st.gp, st.scal, host, tag);
 }
 
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s) {
@@ -2258,8 +2266,9 @@ void norm_partial(int64_t n, const double* w, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_norm_partial, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, w, part);
 }
 
-void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, nblk, part, scal, g, m);
+void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s, double* host,
+                 double tag) {
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, nblk, part, scal, g, m, host, tag);
 }
 
 void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, const int* eslot,

@@ -288,17 +288,21 @@ void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const doub
 // h_{j+1,j} = |w|,
 // takes the final Givens rotation of column j-1 into HR and g, a provisional
 // rotation of column j into HR and gp, and scal = (|gp_{j+1}|, 1/|w|, |w|)
-// (also into pinned host memory `host` when given; w itself is not scaled).
-void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, hipStream_t s,
-                 LaunchEv ev = {});
+// (also into pinned host memory `host` when given, followed, behind a
+// system-scope fence, by host[3] = tag; w itself is not scaled).
+void dcgs_update(int64_t n, double* V, int64_t ld, int j, const DcgsState& st, double* host, double tag,
+                 hipStream_t s, LaunchEv ev = {});
 // Least squares back-substitution for k columns: y = R^{-1} g.
 void lsq_solve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // x += Z y (k columns).
 void xupdate(int64_t n, const double* Z, int64_t ldz, int k, const double* y, double* x,
              hipStream_t s);
-// ||w||: partials then scal[0] = norm, scal[1] = 1/norm (0 if norm == 0), g = [norm, 0...].
+// ||w||: partials then scal[0..2] = (norm, 1/norm (0 if norm == 0), norm),
+// g = [norm, 0...] when given; the three values also into pinned host memory
+// `host` when given, then, behind a system-scope fence, host[3] = tag.
 void norm_partial(int64_t n, const double* w, double* part, hipStream_t s);
-void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s);
+void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s,
+                 double* host = nullptr, double tag = 0.0);
 
 // Assembly: coloured element scatter into a SELL value array.  kind 0: P1
 // mass, 1: P1 stiffness, 2: P1 convection by a P2 velocity vel (2 x n2 nodes).
