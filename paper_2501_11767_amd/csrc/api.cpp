@@ -576,7 +576,14 @@ bool vcycle_pair(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
   a.xf = Sel<T>::t(L);
   a.bcc = Sel<T>::b(GG);
   vdown2<T>(a, s);
-  vcycle<T>(c, op, l + 2, cut, Sel<T>::b(GG), Sel<T>::x(GG), o, s);
+  // a cut level right below the pair is solved inside the up launch
+  ChebCoef<T> cc{};
+  bool cut_in_up = false;
+  if (l + 2 == cut && GG.d.side > 0) {
+    cc = cut_coef<T>(c, op, cut, o);
+    cut_in_up = tile2_cut_fits(side, o.mg_post, cc.steps);
+  }
+  if (!cut_in_up) vcycle<T>(c, op, l + 2, cut, Sel<T>::b(GG), Sel<T>::x(GG), o, s);
   const ChebCoef<T> post = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post);
   a.steps = o.mg_post;
   for (int k = 0; k < o.mg_post; ++k) {
@@ -584,9 +591,20 @@ bool vcycle_pair(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
     a.c2[k] = post.c2[k];
   }
   a.xinf = Sel<T>::t(L);
-  a.e = Sel<T>::x(GG);
   a.xf = x;
-  a.bcc = nullptr;
+  if (cut_in_up) {
+    const OpVals& AGG = GG.*op;
+    a.csteps = cc.steps;
+    a.valcc = Sel<T>::v(AGG);
+    a.dinvcc = Sel<T>::d(AGG);
+    for (int k = 0; k < cc.steps; ++k) {
+      a.cc1[k] = cc.c1[k];
+      a.cc2[k] = cc.c2[k];
+    }
+  } else {
+    a.e = Sel<T>::x(GG);
+    a.bcc = nullptr;
+  }
   vup2<T>(a, s);
   return true;
 }

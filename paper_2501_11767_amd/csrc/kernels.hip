@@ -592,9 +592,18 @@ __global__ __launch_bounds__(1024) void k_vdown2(Tile2Args<T> a) {
   }
 }
 
+// Side of the cut-level region vup2 solves: the cut-level nodes its coarse
+// region's interpolation reads (coarse region side wc starting at a coarse
+// column of parity p), widened by steps - 1 rings (a step from zero at ring
+// r >= k stays exact after k + 1 steps).
+__host__ __device__ constexpr int t2_cut_side(int wc, int p, int steps) {
+  return ((wc - 1 + p) >> 1) + 2 + 2 * (steps - 1);
+}
+
 // up2: coarse correction x_c + P e and post-smoothing on a coarse region of
 // halo Hcu = D + Q (D = (Q + 1) / 2 + 1 coarse rings feed the fine
 // interpolation), then the fine correction and post-smoothing (halo Q).
+// With a.csteps > 0, e comes from the cut level solved in LDS first.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
   __shared__ T fx[T2_WFU * T2_WFU], fy[T2_WFU * T2_WFU];
@@ -612,19 +621,68 @@ __global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
   const int off[W7] = {0, -W - 1, -W, -1, 1, W, W + 1};
   const int offc[W7] = {0, -Wc - 1, -Wc, -1, 1, Wc, Wc + 1};
   // coarse row: corrected iterate into LDS
-  T cv[W7], cdi = T(0), cd = T(0), cbv = T(0);
-  int cring = -1;
+  T cv[W7], cdi = T(0), cd = T(0), cbv = T(0), cxv = T(0);
+  int cring = -1, crow = 0, cri = 0, crj = 0;
   if (tid < Rc) {
-    const int crj = tid / Wc, cri = tid - crj * Wc;
+    crj = tid / Wc;
+    cri = tid - crj * Wc;
     const int cgi = wrap_once(ci0 + cri, sc), cgj = wrap_once(cj0 + crj, sc);
-    const int crow = cgi + sc * cgj;
+    crow = cgi + sc * cgj;
     cring = min(min(cri, crj), min(Wc - 1 - cri, Wc - 1 - crj));
     const size_t base = size_t(crow >> 6) * (64 * W7) + (crow & 63);
 #pragma unroll
     for (int k = 0; k < W7; ++k) cv[k] = a.valc[base + k * 64];
     cdi = a.dinvc[crow];
     cbv = a.bc[crow];
-    cx[tid] = a.xc[crow] + p1_interp(a.e, cgi, cgj, scc);
+    cxv = a.xc[crow];
+    if (a.csteps == 0) cx[tid] = cxv + p1_interp(a.e, cgi, cgj, scc);
+  }
+  if (a.csteps > 0) {
+    // the cut level (side scc) from zero on the region the interpolation
+    // reads (origin floor(ci0 / 2) - (S - 1)), in the fine buffers, which
+    // are free until the fine correction
+    const int S = a.csteps, pi = ci0 & 1, pj = cj0 & 1;
+    const int We = t2_cut_side(Wc, pi, S), Re = We * We;
+    const int ei0 = ((ci0 + 2 * Hcu) >> 1) - Hcu - (S - 1), ej0 = ((cj0 + 2 * Hcu) >> 1) - Hcu - (S - 1);
+    const int offe[W7] = {0, -We - 1, -We, -1, 1, We, We + 1};
+    T ev[W7], edi = T(0), eb = T(0), ed = T(0);
+    int ering = -1;
+    if (tid < Re) {
+      const int erj = tid / We, eri = tid - erj * We;
+      const int row = wrap_once(ei0 + eri, scc) + scc * wrap_once(ej0 + erj, scc);
+      ering = min(min(eri, erj), min(We - 1 - eri, We - 1 - erj));
+      const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) ev[k] = a.valcc[base + k * 64];
+      edi = a.dinvcc[row];
+      eb = a.bcc[row];
+    }
+    T* ecur = fx;
+    T* enxt = fy;
+    for (int k = 0; k < S; ++k) {
+      if (ering >= k) {
+        T sum = T(0);
+        if (k > 0) {
+#pragma unroll
+          for (int m = 0; m < W7; ++m) sum += ev[m] * ecur[tid + offe[m]];
+        }
+        const T r = edi * (eb - sum);
+        ed = (k == 0) ? a.cc2[0] * r : a.cc1[k] * ed + a.cc2[k] * r;
+        enxt[tid] = (k == 0) ? ed : ecur[tid] + ed;
+      }
+      __syncthreads();
+      T* t = ecur;
+      ecur = enxt;
+      enxt = t;
+    }
+    // P1 interpolation from the region (coarse column ci0 + cri maps to
+    // region column S - 1 + floor((cri + pi) / 2))
+    if (tid < Rc) {
+      const int I = S - 1 + ((cri + pi) >> 1), J = S - 1 + ((crj + pj) >> 1);
+      const int oi = (cri + pi) & 1, oj = (crj + pj) & 1;
+      const T e0 = ecur[I + We * J];
+      cx[tid] = cxv + ((oi | oj) ? T(0.5) * (e0 + ecur[(I + oi) + We * (J + oj)]) : e0);
+    }
   }
   // fine rows: operands now, corrections after the coarse smoothing
   T v[T2_RPTU][W7], di[T2_RPTU], bb[T2_RPTU], d[T2_RPTU], xi[T2_RPTU];
@@ -2071,6 +2129,14 @@ void vtile(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev) {
   }
   if (tt == 16) vtile_tt<T, 16>(mode, a, s, ev);
   else vtile_tt<T, 32>(mode, a, s, ev);
+}
+
+bool tile2_cut_fits(int side, int post, int steps) {
+  const int scc = side / 4, Q = post;
+  const int wc = T2_TC + 2 * ((Q + 1) / 2 + 1 + Q);
+  const int w = std::max(t2_cut_side(wc, 0, steps), t2_cut_side(wc, 1, steps));
+  // one node per thread in buffers of T2_WFU^2; one wrap reaches every row
+  return steps >= 1 && steps <= TILE_MAXSTEPS && w * w <= 1024 && w * w <= T2_WFU * T2_WFU && w <= scc;
 }
 
 bool tile2_fits(int side, int pre, int post) {

@@ -184,10 +184,22 @@ struct Tile2Args {
   const T* e = nullptr;     // up2: result of the level below
   T c1[TILE_MAXSTEPS] = {};
   T c2[TILE_MAXSTEPS] = {};
+  // up2 with csteps > 0: the level below the pair is the cut level; every
+  // workgroup takes its csteps Chebyshev steps from zero (coefficients cc1,
+  // cc2; operator valcc, dinvcc; right-hand side bcc) itself on the region its
+  // interpolation reads, and e is not read
+  int csteps = 0;
+  const T* valcc = nullptr;
+  const T* dinvcc = nullptr;
+  T cc1[TILE_MAXSTEPS] = {};
+  T cc2[TILE_MAXSTEPS] = {};
 };
 // Whether two levels (fine side `side`) take the paired kernels with pre and
 // post steps.
 bool tile2_fits(int side, int pre, int post);
+// Whether vup2 can solve the cut level below the pair (side / 4) itself with
+// `steps` steps from zero.
+bool tile2_cut_fits(int side, int post, int steps);
 template <typename T>
 void vdown2(const Tile2Args<T>& a, hipStream_t s);
 template <typename T>
