@@ -29,12 +29,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BATCH_RESTART = 60  # restart length of the batched workload and its sequential comparison
-# multigrid of the 1024^2 workload: V(1,2), 8 Chebyshev steps on the cut level,
-# hierarchies cut at the first level with rho <= 16 (measured fastest over the
-# tau sweep, mixed and FP64; the library default is V(2,2), 8 steps, rho <= 0.25)
-MG = dict(mg_pre=1, mg_post=2, mg_coarse=8, mg_rho_cut=16.0)
-# the 256^2 ternary workload: the same multigrid with FGMRES(15) (measured
-# fastest of restart 15/25/40 and five multigrid settings)
+# multigrid of the 1024^2 workload: V(1,3), 8 Chebyshev steps on the cut level,
+# hierarchies cut at the first level with rho <= 16 (measured fastest, summed
+# over the tau sweep and two initial states, mixed and FP64, of V(1,2), V(1,3),
+# V(2,2), V(2,3) with 7-9 cut steps; the library default is V(2,2), 8 steps,
+# rho <= 0.25)
+MG = dict(mg_pre=1, mg_post=3, mg_coarse=8, mg_rho_cut=16.0)
+# the 256^2 ternary workload: the same multigrid with FGMRES(15) (restart 15
+# measured fastest of 12/15/20 with this multigrid)
 DRY_OPTS = dict(MG, restart=15)
 # HBM bytes per launch of a kernel from rocprofv3 counter runs of this
 # benchmark (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
@@ -44,7 +46,7 @@ TRAFFIC = {
     # filled in from profiles/chac1024_dcgs_update_hbm_counters.md (FETCH_SIZE and
     # WRITE_SIZE per dispatch, scaled by the 512 MiB negation probe) once the
     # counters are taken for the pass as it stands: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-    "k_dcgs_update": 145224356,
+    "k_dcgs_update": 151545276,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 

@@ -2,7 +2,7 @@
 times (through the C-ABI).
 
 * chac1024 (1024 x 1024 CH + AC): one step against the oracle's exact
-  Fourier-mode solve.  Bench configuration (FGMRES(12), V(1,2) cut at rho <= 16, rtol 1e-8): true
+  Fourier-mode solve.  Bench configuration (FGMRES(12), V(1,3) cut at rho <= 16, rtol 1e-8): true
   residual in the oracle's arithmetic <= 2 rtol, and the forward error <=
   2 kappa rtol with kappa the condition number of the CH block from its
   Fourier symbols.  Tighter solves reach the stated accuracy: FP64 at rtol
@@ -18,7 +18,8 @@ times (through the C-ABI).
   mixed-precision adjoint within 1e-6 of fourth-order central differences.
 * The block preconditioners at 1040 x 1040 (finest level in 64 x 64 tiles with
   a ragged last row and column of tiles; in mixed precision the FP64 boundary
-  fused into those tiles) against the oracle's cycle on the same hierarchy.
+  fused into those tiles) and at 1024 x 1024 (the cut level solved inside the
+  paired up pass) against the oracle's cycle on the same hierarchy.
 """
 import numpy as np
 import pytest
@@ -30,7 +31,7 @@ from paper_2501_11767_amd import inputs
 pytestmark = pytest.mark.gpu
 
 # the multigrid options bench.py times the 1024^2 workload with
-BENCH_MG = dict(mg_pre=1, mg_post=2, mg_coarse=8, mg_rho_cut=16.0)
+BENCH_MG = dict(mg_pre=1, mg_post=3, mg_coarse=8, mg_rho_cut=16.0)
 
 
 @pytest.fixture(scope="module")
@@ -131,19 +132,15 @@ def test_chac1024_step_matches_exact_solve(mods, precision, rtol, bar):
         assert _rel(Phi, ex_Phi) <= bar, _rel(Phi, ex_Phi)
 
 
-def test_precond_ragged_finest_tiles_matches_oracle_cycle(mods):
-    """CH and AC preconditioners of the 1024^2 workload's parameters on a
-    1040 x 1040 mesh (1040 = 16 * 64 + 16: a ragged last row and column of
-    finest-level tiles), with the library's default multigrid options and with
-    the benchmark's: FP64 cycle within 1e-12 of the oracle's cycle, FP32 cycle
-    (with the fused FP64 boundary) within 1e-5."""
+def _precond_parity(mods, n, option_sets):
+    """The CH and AC preconditioners with each multigrid option set against
+    the oracle's cycle on the same hierarchy: FP64 within 1e-12, FP32 (with
+    the fused FP64 boundary) within 1e-5."""
     import torch
     from oracle import precond as PC
     C, _ = mods
-    n = 1040
     cfg = inputs.CONFIGS["chac1024"]
     p = dict(eps=cfg["eps"], tau=1e-4, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
-    print(f"precond n={n}", flush=True)
     ctx = C.Context(n, "ch_ac", **p)
     m = fem.Mesh(n)
     prm = Params(**p)
@@ -151,11 +148,8 @@ def test_precond_ragged_finest_tiles_matches_oracle_cycle(mods):
     g = np.random.default_rng(11)
     r = g.standard_normal(2 * n * n)
     ra = g.standard_normal(n * n)
-    d = C.default_opts()
-    # the defaults, the benchmark's options, and no post-smoothing (the up pass
-    # that writes M x then only corrects)
-    for mgo in (dict(mg_pre=d.mg_pre, mg_post=d.mg_post, mg_coarse=d.mg_coarse, mg_rho_cut=d.mg_rho_cut),
-                BENCH_MG, dict(mg_pre=2, mg_post=0, mg_coarse=8, mg_rho_cut=16.0)):
+    for mgo in option_sets:
+        print(f"precond n={n} {mgo}", flush=True)
         kw = dict(pre=mgo["mg_pre"], post=mgo["mg_post"], coarse=mgo["mg_coarse"], rho_cut=mgo["mg_rho_cut"])
         ref = PC.CHPreconditioner(M, K, None, prm, n, inner="mg", cycles=1, **kw).apply(r)
         Pa = PC.ACPreconditioner(systems.ac_matrix(M, K, None, prm), n, prm, inner="mg", cycles=1, **kw)
@@ -170,6 +164,30 @@ def test_precond_ragged_finest_tiles_matches_oracle_cycle(mods):
             assert _rel(z.cpu().numpy(), ref) < bar, (prec, mgo)
             assert _rel(za.cpu().numpy(), refa) < bar, (prec, mgo)
     ctx.close()
+
+
+def test_precond_ragged_finest_tiles_matches_oracle_cycle(mods):
+    """1040 x 1040 mesh (1040 = 16 * 64 + 16: a ragged last row and column of
+    finest-level tiles) with the 1024^2 workload's parameters: the library's
+    default multigrid options, the benchmark's, V(1,2) with 9 cut steps, and
+    no post-smoothing (the up pass that writes M x then only corrects)."""
+    d = mods[0].default_opts()
+    _precond_parity(mods, 1040, (
+        dict(mg_pre=d.mg_pre, mg_post=d.mg_post, mg_coarse=d.mg_coarse, mg_rho_cut=d.mg_rho_cut),
+        BENCH_MG, dict(mg_pre=1, mg_post=2, mg_coarse=9, mg_rho_cut=16.0),
+        dict(mg_pre=2, mg_post=0, mg_coarse=8, mg_rho_cut=16.0)))
+
+
+def test_precond_paired_levels_with_cut_matches_oracle_cycle(mods):
+    """1024 x 1024 with rho <= 16: the X hierarchy's 512^2 and 256^2 levels
+    take the paired kernels and its cut level, 128^2, lies right below them, so
+    the paired up pass solves it in every workgroup.  Post-smoothing 0 to 3 and
+    6 to 9 cut steps (the cut-level region side the kernel needs grows with
+    both)."""
+    _precond_parity(mods, 1024, (
+        BENCH_MG, dict(mg_pre=1, mg_post=2, mg_coarse=9, mg_rho_cut=16.0),
+        dict(mg_pre=2, mg_post=0, mg_coarse=6, mg_rho_cut=16.0),
+        dict(mg_pre=1, mg_post=1, mg_coarse=7, mg_rho_cut=16.0)))
 
 
 def test_dry256_step_satisfies_oracle_systems(mods):
