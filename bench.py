@@ -29,6 +29,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BATCH_RESTART = 60  # restart length of the batched workload and its sequential comparison
+# multigrid of the batched workload and its sequential comparison: V(2,4) with
+# the default cut (8 steps, rho <= 0.25); measured against V(2,2) (the library
+# default), V(1,3), V(2,3), V(1,4), V(3,3), V(2,5), V(2,6), V(3,4), V(3,5),
+# V(4,4), V(1,5), cut at rho <= 0.25/0.5/1/4 and 6-9 cut steps: V(2,4) is where
+# more smoothing stops paying (batched eager step 73.1 -> 58.0 ms; the best,
+# V(3,4), 56.6 ms)
+BATCH_MG = dict(mg_pre=2, mg_post=4, mg_coarse=8, mg_rho_cut=0.25)
 # multigrid of the 1024^2 workload: V(1,3), 8 Chebyshev steps on the cut level,
 # hierarchies cut at the first level with rho <= 16 (measured fastest, summed
 # over the tau sweep and two initial states, mixed and FP64, of V(1,2), V(1,3),
@@ -273,7 +280,7 @@ def batch_section(chns, steps):
     torch.cuda.synchronize()
     log("batch64: tune")
     batch.tune(None, stream=s)
-    opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=BATCH_RESTART, maxiter=120)
+    opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=BATCH_RESTART, maxiter=120, **BATCH_MG)
     log("batch64: eager steps")
     rc_e, info_e = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=False, stream=s, out=out,
                                   each_from_input=True)
@@ -287,14 +294,14 @@ def batch_section(chns, steps):
                               each_from_input=True)
     graph_ms = info["ms"] / steps
     log("batch64: fp64 eager step")
-    o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=120)
+    o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=120, **BATCH_MG)
     rc_f, info_f = batch.timestep(*zin, nsteps=1, opts=o64, use_graph=False, stream=s, out=out)
     batch.close()
     di = float(sum(2 * n * n * a + n * n * b for n, a, b in zip(sizes, info["iters_ch"], info["iters_ac"])))
     # one instance at a time, plain FP64, one context per size
     ctxs, seq_ms, seq_its = {}, 0.0, 0
     off = np.concatenate([[0], np.cumsum([n * n for n in sizes])])
-    opts_seq = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=600)
+    opts_seq = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=600, **BATCH_MG)
     log("batch64: sequential fp64 solves")
     for i, (n, p) in enumerate(zip(sizes, prm)):
         if n not in ctxs:
@@ -314,7 +321,8 @@ def batch_section(chns, steps):
         c.close()
     return dict(workload=f"batch64: 64 CH + AC instances, sizes {sorted(set(sizes))} "
                          f"({Ntot} nodes, {3 * Ntot} unknowns), log-uniform eps, tau, mobility, "
-                         f"evaporation rate; FP32 multigrid in FP64 FGMRES({BATCH_RESTART}), rtol 1e-8",
+                         f"evaporation rate; FP32 V({BATCH_MG['mg_pre']},{BATCH_MG['mg_post']}) multigrid in FP64 "
+                         f"FGMRES({BATCH_RESTART}), rtol 1e-8",
                 graph_ms_per_step=graph_ms, eager_ms_per_step=eager_ms,
                 graph_budget_ch_ac=[int(x.max()) for x in (info_e["iters_ch"], info_e["iters_ac"])],
                 sequential_fp64_ms_per_step=seq_ms, speedup_vs_sequential_fp64=seq_ms / graph_ms,

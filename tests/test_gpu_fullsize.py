@@ -32,6 +32,8 @@ pytestmark = pytest.mark.gpu
 
 # the multigrid options bench.py times the 1024^2 workload with
 BENCH_MG = dict(mg_pre=1, mg_post=3, mg_coarse=8, mg_rho_cut=16.0)
+# and the batched workload (with FGMRES(60))
+BATCH_MG = dict(mg_pre=2, mg_post=4, mg_coarse=8, mg_rho_cut=0.25)
 
 
 @pytest.fixture(scope="module")
@@ -261,7 +263,7 @@ def test_batch64_instances_residuals_and_sampled_errors(mods):
     batch = C.Batch(sizes, prm)
     off = batch.offsets
     rtol = 1e-8
-    opts = C.default_opts(rtol=rtol, precision=C.MIXED, restart=40, maxiter=120)
+    opts = C.default_opts(rtol=rtol, precision=C.MIXED, restart=60, maxiter=120, **BATCH_MG)
     zin = [_dev(phi0), torch.zeros(len(phi0), dtype=torch.float64, device="cuda"), _dev(Phi0)]
     out = [torch.zeros_like(zin[0]) for _ in range(3)]
     s = torch.cuda.Stream()
