@@ -53,7 +53,7 @@ TRAFFIC = {
     # filled in from profiles/chac1024_dcgs_update_hbm_counters.md (FETCH_SIZE and
     # WRITE_SIZE per dispatch, scaled by the 512 MiB negation probe) once the
     # counters are taken for the pass as it stands: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-    "k_dcgs_update": 151545276,
+    "k_dcgs_update": 152869730,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 
@@ -65,7 +65,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--tau", type=float, default=1e-4)
-    ap.add_argument("--restart", type=int, default=12)
+    # FGMRES restart length of the 1024^2 workload: 13 measured fastest (summed
+    # over the tau sweep, mixed and FP64) of 10-14 and 16 with its multigrid
+    ap.add_argument("--restart", type=int, default=13)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ledger", action="store_true", help="no kernel events in the timed steps")
