@@ -493,7 +493,7 @@ def oracle_errors(cfg, n, st0, sweep, sweep_fields):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (no sharding across GPUs); --gpus must be 1"}))
         sys.exit(2)
     import torch
 
