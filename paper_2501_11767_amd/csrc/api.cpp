@@ -977,18 +977,24 @@ int64_t block_size(chns_ctx* c, int block) {
   return 0;
 }
 
-// y = alpha A x + beta y for a block operator (FP64).
+// y = alpha A x + beta u for a block operator (FP64), u = yin when given (not
+// overlapping y), else y.
 int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha, double beta,
-                hipStream_t s) {
+                hipStream_t s, const double* yin = nullptr) {
   const auto& p = c->prm;
   Level& L0 = c->lv[0];
+  if (yin && block != CHNS_BLOCK_CH) {  // the other blocks' products update y in place
+    const int64_t n = block_size(c, block);
+    HIPCHK(c, hipMemcpyAsync(y, yin, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    yin = nullptr;
+  }
   if (block == CHNS_BLOCK_CH) {
     const double tg = p.tau * p.mobility, beta_ = p.eps * p.eps;
     const double* Lv = c->has_conv ? L0.L.v64 : L0.M;
     // values M, K (and L when C != 0), x and y of both rows; y read when beta != 0
     const double bytes = double(c->N) * (8 * (14 + (c->has_conv ? 7 : 0)) + 32 + (beta != 0.0 ? 16 : 0));
     timed(c, CHNS_KERNEL_CH_BLOCK, bytes, s, [&](LaunchEv ev) {
-      ch_block<double, double>(L0.d, Lv, L0.K, L0.M, tg, -tg / beta_, x, alpha, beta, y, s, ev);
+      ch_block<double, double>(L0.d, Lv, L0.K, L0.M, tg, -tg / beta_, x, alpha, beta, y, s, ev, yin);
     });
   } else if (block == CHNS_BLOCK_AC) {
     spmv<double, double>(L0.d, L0.AC.v64, x, y, alpha, beta, s);
@@ -1091,8 +1097,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   };
   while (true) {
     // V0 = b - A x, beta = ||V0||, g = beta e1
-    HIPCHK(c, hipMemcpyAsync(K.V, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    TRY(apply_block(c, block, x, K.V, -1.0, 1.0, s));
+    TRY(apply_block(c, block, x, K.V, -1.0, 1.0, s, b));
     norm_partial(n, K.V, K.nrm_part, s);
     rtag = ++K.tag;
     norm_finish(nblk, K.nrm_part, K.scal, K.g, m, s, rslot, rtag);

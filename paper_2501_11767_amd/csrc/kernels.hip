@@ -981,7 +981,7 @@ __global__ __launch_bounds__(BS) void k_ch_block(int n, int side, const int* __r
                                                  const TV* __restrict__ Kv,
                                                  const TV* __restrict__ Mv, T c12, T c22,
                                                  const T* __restrict__ x, T alpha, T beta,
-                                                 T* __restrict__ y) {
+                                                 T* y, const T* yin) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * BS + threadIdx.x;
   if (row >= n) return;
@@ -1012,8 +1012,9 @@ __global__ __launch_bounds__(BS) void k_ch_block(int n, int side, const int* __r
     y[row] = y1;
     y[n + row] = y2;
   } else {
-    y[row] = y1 + beta * y[row];
-    y[n + row] = y2 + beta * y[n + row];
+    const T* yb = yin ? yin : y;
+    y[row] = y1 + beta * yb[row];
+    y[n + row] = y2 + beta * yb[n + row];
   }
 }
 
@@ -2209,14 +2210,14 @@ void vtail(const TailArgs<T>& a, hipStream_t s) {
 
 template <typename T, typename TV>
 void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
-              T alpha, T beta, T* y, hipStream_t s, LaunchEv ev) {
+              T alpha, T beta, T* y, hipStream_t s, LaunchEv ev, const T* yin) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (L == M)
     LAUNCH_EV(ev, (k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
-              alpha, beta, y);
+              alpha, beta, y, yin);
   else
     LAUNCH_EV(ev, (k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
-              alpha, beta, y);
+              alpha, beta, y, yin);
 }
 
 template <typename T>
@@ -2507,9 +2508,10 @@ template void vtail<double>(const TailArgs<double>&, hipStream_t);
 template void vtail<float>(const TailArgs<float>&, hipStream_t);
 template void ch_block<double, double>(const DSell&, const double*, const double*, const double*,
                                        double, double, const double*, double, double, double*,
-                                       hipStream_t, LaunchEv);
+                                       hipStream_t, LaunchEv, const double*);
 template void ch_block<float, float>(const DSell&, const float*, const float*, const float*, float,
-                                     float, const float*, float, float, float*, hipStream_t, LaunchEv);
+                                     float, const float*, float, float, float*, hipStream_t, LaunchEv,
+                                     const float*);
 template void axpby<double>(int64_t, double, const double*, double, double*, hipStream_t);
 template void axpby<float>(int64_t, float, const float*, float, float*, hipStream_t);
 template void convert<double, float>(int64_t, const double*, float*, hipStream_t);

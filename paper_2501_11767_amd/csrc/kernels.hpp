@@ -243,10 +243,11 @@ template <typename T>
 void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s);
 
 // CH block on [x1; x2] with value streams L = M + tau C, K, M (uniform P1):
-//   y1 = alpha (L x1 + c12 K x2) + beta y1,  y2 = alpha (c12 K x1 + c22 M x2) + beta y2.
+//   y1 = alpha (L x1 + c12 K x2) + beta u1,  y2 = alpha (c12 K x1 + c22 M x2) + beta u2
+// with u = yin when given (of the size of y, not overlapping it), else u = y.
 template <typename T, typename TV>
 void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
-              T alpha, T beta, T* y, hipStream_t s, LaunchEv ev = {});
+              T alpha, T beta, T* y, hipStream_t s, LaunchEv ev = {}, const T* yin = nullptr);
 
 // Vector kernels.
 template <typename T>
