@@ -30,8 +30,9 @@
  *   - "stream" is a hipStream_t (NULL = the default stream).  Calls are
  *     asynchronous on that stream unless documented as synchronising.
  *   - The context owns all matrices, multigrid levels and Krylov workspace;
- *     it allocates device memory only in chns_create.  A context is not
- *     thread-safe; use one context per stream.
+ *     it allocates device memory only in chns_create, through the caller's
+ *     allocator when one is given.  A context is not thread-safe; use one
+ *     context per stream.
  *   - Return values: CHNS_OK, the warning CHNS_WNOCONV (outputs written with
  *     the best iterate), or a negative error.  Invalid arguments are rejected
  *     with CHNS_EINVAL before anything is launched; chns_last_error() then
@@ -40,6 +41,7 @@
 #ifndef CHNS_H
 #define CHNS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -150,11 +152,33 @@ typedef struct {
  * mg_pre + mg_post when the operator is cut on the finest level). */
 CHNS_API void chns_default_opts(chns_solve_opts* opts);
 
-/* Build the mesh tables, sparsity patterns (CSR -> SELL-C-sigma), multigrid
- * hierarchy and Krylov workspace, and assemble M and K on the device
- * (coloured element scatter).  Synchronising.  *out is NULL on failure. */
-CHNS_API int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out);
+/* Device allocator supplied by the caller: alloc(bytes, alloc_ctx) returns
+ * device memory aligned to at least 256 bytes, or NULL on failure;
+ * free_(ptr, alloc_ctx) releases it.  A caching allocator (PyTorch's, for
+ * example) may hand the memory out again as soon as free_ returns: the library
+ * calls free_ only after synchronising the device. */
+typedef void* (*chns_alloc_fn)(size_t bytes, void* alloc_ctx);
+typedef void (*chns_free_fn)(void* ptr, void* alloc_ctx);
 
+/* Set up a context for the discretisation of section "Spatial & temporal
+ * discretization" (P1 phase fields, potentials and vapour field, Taylor-Hood
+ * P2-P1 velocity and pressure on the triangulated box) with the parameters
+ * of the nondimensional model (section "Nondimensionalized governing
+ * equations", eq. (model)):
+ * build the mesh tables, sparsity patterns (CSR -> SELL-C-sigma), multigrid
+ * hierarchy and Krylov workspace, and assemble M and K on the device
+ * (coloured element scatter).  Every device buffer of the context comes from
+ * alloc (freed through free_ by chns_destroy); alloc and free_ both NULL
+ * means hipMalloc / hipFree, exactly one of them NULL is CHNS_EINVAL.  A
+ * 128-byte pinned host slot for the solver's residual read-back is the only
+ * host allocation (hipHostMalloc).  No later call allocates device memory.
+ * Synchronising.  *out is NULL on failure; CHNS_ENOMEM when alloc returns
+ * NULL. */
+CHNS_API int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn alloc,
+                         chns_free_fn free_, void* alloc_ctx, chns_ctx** out);
+
+/* Synchronise the device, then release every buffer of the context (through
+ * the caller's free_ when chns_create was given an allocator). */
 CHNS_API int chns_destroy(chns_ctx* ctx);
 
 /* Replace the parameters and re-form every parameter-dependent operator
@@ -200,31 +224,51 @@ CHNS_API int chns_matrix_shape(chns_ctx* ctx, int32_t op, int64_t* nrows, int64_
 CHNS_API int chns_get_matrix(chns_ctx* ctx, int32_t op, int32_t* h_rowptr, int32_t* h_col,
                              double* h_val, void* stream);
 
-/* y = alpha * A x + beta * y for op in CHNS_OP_*.  precision CHNS_F64: x, y
- * double; CHNS_MIXED: x, y float with FP32 matrix values (not for CHNS_OP_NS).
- * x and y must not overlap.  With beta == 0, y is not read. */
-CHNS_API int chns_spmv(chns_ctx* ctx, int32_t op, int32_t precision, double alpha,
+/* y = alpha * op(A) x + beta * y for A in CHNS_OP_* (the matrices of section
+ * "Iterative solvers and preconditioning": M, K, C(v^k) and the blocks of
+ * eq. (CH_linear), the Allen-Cahn matrix, the matching factor X, and the
+ * Oseen saddle point of eq. (linearnav)), op(A) = A for transpose == 0 and
+ * A^T for transpose == 1.  The transposed product reads the transposed
+ * operators that chns_assemble_transposed leaves in the context; operators
+ * equal to their transpose in the current state (M, K, X always; C, L, AC and
+ * the CH block when no velocity is assembled) accept either value, any other
+ * mismatch between transpose and the context's orientation returns
+ * CHNS_ESTATE.  precision CHNS_F64: x, y double; CHNS_MIXED: x, y float with
+ * FP32 matrix values (not for CHNS_OP_NS).  x and y must not overlap.  With
+ * beta == 0, y is not read. */
+CHNS_API int chns_spmv(chns_ctx* ctx, int32_t op, int32_t precision, int32_t transpose, double alpha,
                        const void* d_x, double beta, void* d_y, void* stream);
 
-/* z = P^{-1} r for a block (paper: CH diag(L, X M^{-1} X) with L ~ M + tau C
- * and X = tau g K + sqrt(tau g / beta) M; AC multigrid on its matrix; NS
- * diag(A^, M_p^{-1} A_p K_p^{-1}) with A^ = diag of the two velocity component
- * blocks and K_p^{-1} applied to mean-zero pressures).  Inner inverses are
- * opts->mg_cycles geometric V-cycles in the precision opts->precision (the
- * velocity blocks start on their P2 level and continue on the P1 levels); r
- * and z are FP64 and must not overlap. */
-CHNS_API int chns_precond_apply(chns_ctx* ctx, int32_t block, const chns_solve_opts* opts,
-                                const double* d_r, double* d_z, void* stream);
+/* z = P^{-1} r for a block (section "Iterative solvers and preconditioning":
+ * CH diag(L, X M^{-1} X) with L ~ M + tau C and X = tau g K + sqrt(tau g /
+ * beta) M, the matching approximation of eq. (schurCH); AC multigrid on its
+ * matrix; NS diag(A^, M_p^{-1} A_p K_p^{-1}) with A^ = diag of the two
+ * velocity component blocks and K_p^{-1} applied to mean-zero pressures).
+ * Inner inverses are opts->mg_cycles geometric V-cycles in the precision
+ * opts->precision (the velocity blocks start on their P2 level and continue
+ * on the P1 levels); r and z are FP64 and must not overlap.  transpose == 1
+ * applies the preconditioner built on the transposed operators of
+ * chns_assemble_transposed, which is (P^{-1})^T when mg_pre == mg_post (each
+ * V-cycle then the transpose of the forward one, the PCD factors in reverse
+ * order); the orientation rule of chns_spmv applies (the CH and AC blocks
+ * accept either value when no velocity is assembled). */
+CHNS_API int chns_precond_apply(chns_ctx* ctx, int32_t block, int32_t transpose,
+                                const chns_solve_opts* opts, const double* d_r, double* d_z,
+                                void* stream);
 
-/* Solve block * x = b by right-preconditioned restarted FGMRES (classical
- * Gram-Schmidt with a second pass only when the first loses more than half
- * of the vector's norm squared, Givens least squares on the device), stopping rule
- * ||b - A x|| <= max(rtol ||b||, atol) on the recomputed true residual.
- * d_x holds the initial guess and receives the solution.  Synchronising
- * (reads the residual estimate back once per Arnoldi step).  h_info may be NULL.
- * For CHNS_BLOCK_NS the returned pressure is projected to mean zero. */
-CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, const double* d_b, double* d_x,
-                               const chns_solve_opts* opts, chns_solve_info* h_info,
+/* Solve op(block) x = b (the systems of eq. (CH_linear), the Allen-Cahn
+ * system and eq. (linearnav)) by right-preconditioned restarted FGMRES with
+ * the block preconditioner of chns_precond_apply: Gram-Schmidt by delayed
+ * classical Gram-Schmidt with reorthogonalisation (two passes over the basis
+ * per step), Givens least squares on the device, stopping rule ||b - A x|| <=
+ * max(rtol ||b||, atol) on the recomputed true residual (section "Numerical
+ * results" states the same rule for its GMRES).  op and the orientation rule
+ * as in chns_spmv.  d_x holds the initial guess and receives the solution.
+ * Synchronising (the host reads the residual estimate once per Arnoldi
+ * step).  h_info may be NULL.  For CHNS_BLOCK_NS the returned pressure is
+ * projected to mean zero. */
+CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, int32_t transpose, const double* d_b,
+                               double* d_x, const chns_solve_opts* opts, chns_solve_info* h_info,
                                void* stream);
 
 /* Diagnostics of a field set, in FP64 on the GPU (synchronises the stream):
@@ -255,11 +299,16 @@ CHNS_API int chns_diagnostics(chns_ctx* ctx, const chns_fields* f, double* h_out
 CHNS_API int chns_step_rhs(chns_ctx* ctx, const chns_fields* in, double* d_rhs_ch,
                            double* d_rhs_ac, double* d_rhs_ns, void* stream);
 
-/* Advance nsteps time steps from *in to *out (both field sets complete for
- * the model; in and out may be the same set).  Per step: assemble, right-hand
- * sides, one FGMRES solve per CH phase, the AC solve, the Oseen solve, the
- * closure of the eliminated phase.  h_info (may be NULL) receives one entry
- * per solve, in the order CH phases, AC, NS, per step.  Synchronising. */
+/* Advance nsteps steps of the semi-implicit scheme of section "Spatial &
+ * temporal discretization" (linear terms implicit, potential terms explicit,
+ * the Navier-Stokes convection lagged; every coupling at level k) from *in to
+ * *out (both field sets complete for the model; in and out may be the same
+ * set).  Per step: assemble C(v^k) (and J(w^k), A_p(w^k)), the right-hand
+ * sides of chns_step_rhs, one FGMRES solve of eq. (CH_linear) per CH phase,
+ * the AC solve, the Oseen solve of eq. (linearnav), and the closure of the
+ * eliminated phase (section "Numerical results", air elimination applied to
+ * the solvent).  h_info (may be NULL) receives one entry per solve, in the
+ * order CH phases, AC, NS, per step.  Synchronising. */
 CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
                            int32_t nsteps, const chns_solve_opts* opts,
                            chns_solve_info* h_info, void* stream);
@@ -317,10 +366,16 @@ CHNS_API const char* chns_last_error(const chns_ctx* ctx);
  * (off from chns_batch_offsets, off[i+1] - off[i] = n_i^2). */
 typedef struct chns_batch chns_batch;
 
-/* count instances with sizes h_n[i] (multiples of 32 in 32..2048) and
- * parameters h_params[i].  Synchronising.  *out is NULL on failure. */
+/* count instances of the CH + AC systems (eq. (CH_linear) and the Allen-Cahn
+ * system of section "Iterative solvers and preconditioning", v = 0) with
+ * sizes h_n[i] (multiples of 32 in 32..2048) and parameters h_params[i]
+ * (read as in chns_create).  Device memory comes from alloc / free_ as in
+ * chns_create (both NULL: hipMalloc / hipFree); no later call allocates.
+ * Synchronising.  *out is NULL on failure. */
 CHNS_API int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_params,
+                               chns_alloc_fn alloc, chns_free_fn free_, void* alloc_ctx,
                                chns_batch** out);
+/* Synchronise the device and release the batch's buffers and graphs. */
 CHNS_API int chns_batch_destroy(chns_batch* b);
 /* h_offsets[count + 1]: node offsets of the instances in the packed fields. */
 CHNS_API int chns_batch_offsets(const chns_batch* b, int64_t* h_offsets);

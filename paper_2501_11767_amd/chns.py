@@ -65,6 +65,43 @@ class SolveInfo(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
+FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of the library's contexts from PyTorch's caching
+    allocator (chns_create / chns_batch_create allocator callbacks).  The
+    counters record every call the library makes, so that a caller can check
+    that no entry point allocates after creation."""
+
+    alloc_calls = 0
+    free_calls = 0
+
+    @staticmethod
+    def _alloc(nbytes, _ctx):
+        import torch
+        TorchAllocator.alloc_calls += 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+    @staticmethod
+    def _free(ptr, _ctx):
+        import torch
+        TorchAllocator.free_calls += 1
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# module-level references keep the ctypes thunks alive as long as the library
+_ALLOC_THUNK = ALLOC_FN(TorchAllocator._alloc)
+_FREE_THUNK = FREE_FN(TorchAllocator._free)
+
+
+def _allocator(use_torch):
+    if use_torch:
+        return _ALLOC_THUNK, _FREE_THUNK
+    return ALLOC_FN(), FREE_FN()  # NULL: the library's own hipMalloc / hipFree
+
+
 class Fields(ct.Structure):
     _fields_ = [("phi", ct.c_void_p * 2), ("mu", ct.c_void_p * 3), ("Phi_v", ct.c_void_p),
                 ("vel", ct.c_void_p), ("p", ct.c_void_p)]
@@ -88,16 +125,17 @@ def lib():
     vp, i32, dbl = ct.c_void_p, ct.c_int32, ct.c_double
     L.chns_default_opts.argtypes = [ct.POINTER(SolveOpts)]
     L.chns_default_opts.restype = None
-    L.chns_create.argtypes = [ct.POINTER(Mesh), ct.POINTER(Params), ct.POINTER(vp)]
+    L.chns_create.argtypes = [ct.POINTER(Mesh), ct.POINTER(Params), ALLOC_FN, FREE_FN, vp,
+                              ct.POINTER(vp)]
     L.chns_destroy.argtypes = [vp]
     L.chns_set_params.argtypes = [vp, ct.POINTER(Params)]
     L.chns_assemble.argtypes = [vp, vp, vp, vp]
     L.chns_matrix_shape.argtypes = [vp, i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                                     ct.POINTER(ct.c_int64)]
     L.chns_get_matrix.argtypes = [vp, i32, vp, vp, vp, vp]
-    L.chns_spmv.argtypes = [vp, i32, i32, dbl, vp, dbl, vp, vp]
-    L.chns_precond_apply.argtypes = [vp, i32, ct.POINTER(SolveOpts), vp, vp, vp]
-    L.chns_krylov_solve.argtypes = [vp, i32, vp, vp, ct.POINTER(SolveOpts),
+    L.chns_spmv.argtypes = [vp, i32, i32, i32, dbl, vp, dbl, vp, vp]
+    L.chns_precond_apply.argtypes = [vp, i32, i32, ct.POINTER(SolveOpts), vp, vp, vp]
+    L.chns_krylov_solve.argtypes = [vp, i32, i32, vp, vp, ct.POINTER(SolveOpts),
                                     ct.POINTER(SolveInfo), vp]
     L.chns_step_rhs.argtypes = [vp, ct.POINTER(Fields), vp, vp, vp, vp]
     L.chns_diagnostics.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(ct.c_double), vp]
@@ -110,7 +148,7 @@ def lib():
     L.chns_ledger_read.argtypes = [vp, vp, vp, vp]
     L.chns_last_error.argtypes = [vp]
     L.chns_last_error.restype = ct.c_char_p
-    L.chns_batch_create.argtypes = [i32, vp, vp, ct.POINTER(vp)]
+    L.chns_batch_create.argtypes = [i32, vp, vp, ALLOC_FN, FREE_FN, vp, ct.POINTER(vp)]
     L.chns_batch_destroy.argtypes = [vp]
     L.chns_batch_offsets.argtypes = [vp, vp]
     L.chns_batch_timestep.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, ct.POINTER(SolveOpts),
@@ -141,12 +179,26 @@ def default_opts(**kw) -> SolveOpts:
     return o
 
 
-def _ptr(t):
-    if t is None:
-        return None
+def _ptr(t, numel, dtype=None, name="tensor", optional=False):
+    """Device pointer of a tensor after checking everything the library
+    assumes about it: a contiguous CUDA tensor of `dtype` (float64 unless
+    given) with exactly `numel` elements.  The kernels read and write numel
+    elements through the pointer, so a short or mistyped tensor would be
+    accessed past its end."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
-        raise ValueError("expected a contiguous CUDA tensor")
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name}: a tensor is required")
+    dtype = torch.float64 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
     return ct.c_void_p(t.data_ptr())
 
 
@@ -158,7 +210,7 @@ def _stream():
 class Context:
     """Owns a chns_ctx for one mesh/model/parameter set."""
 
-    def __init__(self, n: int, model: str = "ch_ac", **params):
+    def __init__(self, n: int, model: str = "ch_ac", torch_alloc: bool = True, **params):
         self.L = lib()
         self.n, self.model = n, model
         self.N = n * n
@@ -168,7 +220,8 @@ class Context:
         self.params = p
         m = Mesh(n, MODELS[model])
         h = ct.c_void_p()
-        rc = self.L.chns_create(ct.byref(m), ct.byref(Params(**p)), ct.byref(h))
+        af, ff = _allocator(torch_alloc)
+        rc = self.L.chns_create(ct.byref(m), ct.byref(Params(**p)), af, ff, None, ct.byref(h))
         if rc != OK:
             raise ChnsError(rc, self.L.chns_last_error(None).decode())
         self.h = h
@@ -193,20 +246,32 @@ class Context:
         self.params.update(params)
         self._check(self.L.chns_set_params(self.h, ct.byref(Params(**self.params))))
 
-    def assemble(self, vel=None, mu=None):
-        mu_arr = None
-        if mu is not None:
-            mu_arr = (ct.c_void_p * 3)(*[t.data_ptr() for t in mu])
-        self._check(self.L.chns_assemble(self.h, _ptr(vel), mu_arr, _stream()))
+    def _mu_array(self, mu):
+        if mu is None:
+            return None
+        mu = list(mu)
+        if len(mu) != 3:
+            raise ValueError("mu: expected three chemical potentials (polymer, NFA, solvent)")
+        self._mu_keep = mu
+        return (ct.c_void_p * 3)(*[_ptr(t, self.N, name=f"mu[{i}]", optional=True)
+                                   for i, t in enumerate(mu)])
 
+    def assemble(self, vel=None, mu=None):
+        self._check(self.L.chns_assemble(self.h, _ptr(vel, 8 * self.N, name="vel", optional=True),
+                                         self._mu_array(mu), _stream()))
 
     def assemble_transposed(self, vel, mu=None):
         """Transposed operators at the state (vel, mu) (ternary model)."""
-        mu_arr = None
-        if mu is not None:
-            self._mu_keep = list(mu)
-            mu_arr = (ct.c_void_p * 3)(*[t.data_ptr() if t is not None else None for t in mu])
-        self._check(self.L.chns_assemble_transposed(self.h, _ptr(vel), mu_arr, _stream()))
+        self._check(self.L.chns_assemble_transposed(
+            self.h, _ptr(vel, 8 * self.N, name="vel", optional=True), self._mu_array(mu), _stream()))
+
+    def op_size(self, op):
+        """Rows (= columns) of an operator of chns_spmv."""
+        return {OP_CH: 2 * self.N, OP_NS: 9 * self.N, OP_VX: 4 * self.N}.get(op, self.N)
+
+    def block_size(self, block):
+        return {BLOCK_CH: 2 * self.N, BLOCK_AC: self.N, BLOCK_NS: 9 * self.N}[block]
+
     def matrix(self, op):
         """Download an operator as (rowptr, col, val) numpy arrays."""
         import numpy as np
@@ -220,40 +285,50 @@ class Context:
                                            val.ctypes.data_as(ct.c_void_p), _stream()))
         return rp, col, val, (r.value, c.value)
 
-    def spmv(self, op, x, y, alpha=1.0, beta=0.0, precision=F64):
-        self._check(self.L.chns_spmv(self.h, op, precision, alpha, _ptr(x), beta, _ptr(y),
-                                     _stream()))
+    def spmv(self, op, x, y, alpha=1.0, beta=0.0, precision=F64, transpose=False):
+        import torch
+        k, dt = self.op_size(op), (torch.float32 if precision == MIXED else torch.float64)
+        self._check(self.L.chns_spmv(self.h, op, precision, int(bool(transpose)), alpha,
+                                     _ptr(x, k, dt, "x"), beta, _ptr(y, k, dt, "y"), _stream()))
 
-    def precond(self, block, r, z, opts=None):
+    def precond(self, block, r, z, opts=None, transpose=False):
         o = opts or default_opts()
-        self._check(self.L.chns_precond_apply(self.h, block, ct.byref(o), _ptr(r), _ptr(z),
-                                              _stream()))
+        k = self.block_size(block)
+        self._check(self.L.chns_precond_apply(self.h, block, int(bool(transpose)), ct.byref(o),
+                                              _ptr(r, k, name="r"), _ptr(z, k, name="z"), _stream()))
 
-    def solve(self, block, b, x, opts=None):
+    def solve(self, block, b, x, opts=None, transpose=False):
         o = opts or default_opts()
         info = SolveInfo()
-        self._check(self.L.chns_krylov_solve(self.h, block, _ptr(b), _ptr(x), ct.byref(o),
-                                             ct.byref(info), _stream()))
+        k = self.block_size(block)
+        self._check(self.L.chns_krylov_solve(self.h, block, int(bool(transpose)), _ptr(b, k, name="b"),
+                                             _ptr(x, k, name="x"), ct.byref(o), ct.byref(info),
+                                             _stream()))
         return info.as_dict()
 
-    @staticmethod
-    def fields(phi=(), mu=(), Phi_v=None, vel=None, p=None) -> Fields:
-        """Field set of device pointers; the tensors stay referenced by the
-        returned structure so they outlive the calls that use it."""
+    def fields(self, phi=(), mu=(), Phi_v=None, vel=None, p=None) -> Fields:
+        """Field set of device pointers (each tensor checked for dtype, device,
+        layout and size); the tensors stay referenced by the returned
+        structure so they outlive the calls that use it."""
+        phi, mu = tuple(phi), tuple(mu)
+        if len(phi) > 2 or len(mu) > 3:
+            raise ValueError("at most two phase fields and three chemical potentials")
         f = Fields()
-        f._keep = (tuple(phi), tuple(mu), Phi_v, vel, p)
+        f._keep = (phi, mu, Phi_v, vel, p)
         for i, t in enumerate(phi):
-            f.phi[i] = t.data_ptr()
+            f.phi[i] = _ptr(t, self.N, name=f"phi[{i}]")
         for i, t in enumerate(mu):
-            f.mu[i] = t.data_ptr()
-        f.Phi_v = Phi_v.data_ptr() if Phi_v is not None else None
-        f.vel = vel.data_ptr() if vel is not None else None
-        f.p = p.data_ptr() if p is not None else None
+            f.mu[i] = _ptr(t, self.N, name=f"mu[{i}]", optional=True)
+        f.Phi_v = _ptr(Phi_v, self.N, name="Phi_v", optional=True)
+        f.vel = _ptr(vel, 8 * self.N, name="vel", optional=True)
+        f.p = _ptr(p, self.N, name="p", optional=True)
         return f
 
     def step_rhs(self, fin: Fields, rhs_ch, rhs_ac=None, rhs_ns=None):
-        self._check(self.L.chns_step_rhs(self.h, ct.byref(fin), _ptr(rhs_ch), _ptr(rhs_ac),
-                                         _ptr(rhs_ns), _stream()))
+        nch = 2 if self.model == "ternary" else 1
+        self._check(self.L.chns_step_rhs(self.h, ct.byref(fin), _ptr(rhs_ch, 2 * nch * self.N, name="rhs_ch"),
+                                         _ptr(rhs_ac, self.N, name="rhs_ac", optional=True),
+                                         _ptr(rhs_ns, 9 * self.N, name="rhs_ns", optional=True), _stream()))
 
     def diagnostics(self, f: Fields):
         """[mass phi (or phi_p), mass phi_N, mass phi_s, mass Phi_v, energy] (FP64, synchronising)."""
@@ -296,7 +371,7 @@ class Context:
 class Batch:
     """Owns a chns_batch: independent CH + AC instances advanced together."""
 
-    def __init__(self, sizes, params):
+    def __init__(self, sizes, params, torch_alloc: bool = True):
         import numpy as np
         self.L = lib()
         self.count = len(sizes)
@@ -309,14 +384,16 @@ class Batch:
             full.append(Params(**q))
         arr = (Params * self.count)(*full)
         h = ct.c_void_p()
+        af, ff = _allocator(torch_alloc)
         rc = self.L.chns_batch_create(self.count, ct.cast(n, ct.c_void_p), ct.cast(arr, ct.c_void_p),
-                                      ct.byref(h))
+                                      af, ff, None, ct.byref(h))
         if rc != OK:
             raise ChnsError(rc, self.L.chns_batch_last_error(None).decode())
         self.h = h
         off = np.zeros(self.count + 1, dtype=np.int64)
         self.L.chns_batch_offsets(self.h, off.ctypes.data_as(ct.c_void_p))
         self.offsets = off
+        self.Ntot = int(off[-1])
 
     def close(self):
         if getattr(self, "h", None):
@@ -346,7 +423,9 @@ class Batch:
         """z = P^{-1} r for every instance (block BLOCK_CH or BLOCK_AC, packed fields)."""
         o = opts or default_opts()
         s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
-        self._check(self.L.chns_batch_precond_apply(self.h, int(block), _ptr(r), _ptr(z), ct.byref(o), s))
+        k = (2 if block == BLOCK_CH else 1) * self.Ntot
+        self._check(self.L.chns_batch_precond_apply(self.h, int(block), _ptr(r, k, name="r"),
+                                                    _ptr(z, k, name="z"), ct.byref(o), s))
 
     def calibrate_graph(self, info, margin=0.125, extra=2):
         """Graph budgets from an eager step's iteration counts: the largest
@@ -364,8 +443,11 @@ class Batch:
         cv = np.zeros(2 * self.count, dtype=np.int32)
         ms = ct.c_double()
         s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+        N = self.Ntot
         rc = self._check(self.L.chns_batch_timestep(
-            self.h, _ptr(phi), _ptr(mu), _ptr(Phi), _ptr(dst[0]), _ptr(dst[1]), _ptr(dst[2]), nsteps,
+            self.h, _ptr(phi, N, name="phi"), _ptr(mu, N, name="mu"), _ptr(Phi, N, name="Phi"),
+            _ptr(dst[0], N, name="out phi"), _ptr(dst[1], N, name="out mu"), _ptr(dst[2], N, name="out Phi"),
+            nsteps,
             int(each_from_input), ct.byref(o), int(use_graph),
             it.ctypes.data_as(ct.c_void_p), cv.ctypes.data_as(ct.c_void_p), ct.byref(ms), s))
         return rc, dict(iters_ch=it[:self.count], iters_ac=it[self.count:], conv_ch=cv[:self.count],

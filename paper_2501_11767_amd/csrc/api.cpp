@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <immintrin.h>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -76,15 +77,31 @@ void timed(chns_ctx* c, int kid, double bytes, hipStream_t s, F&& launch) {
   ++G.launches;
 }
 
+// Device memory of the context: the caller's allocator when one was given to
+// chns_create, else hipMalloc.  Only set-up calls allocate.
 template <typename T>
 int dalloc(chns_ctx* c, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) return CHNS_OK;
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, n * sizeof(T));
-  if (e != hipSuccess) {
-    c->err = std::string("hipMalloc: ") + hipGetErrorString(e);
-    return CHNS_ENOMEM;
+  const size_t bytes = n * sizeof(T);
+  if (c->alloc) {
+    q = c->alloc(bytes, c->alloc_ctx);
+    if (!q) {
+      c->err = "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes";
+      return CHNS_ENOMEM;
+    }
+    if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+      c->allocs.push_back(q);
+      c->err = "the caller's allocator returned memory not aligned to 256 bytes";
+      return CHNS_EINVAL;
+    }
+  } else {
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+      c->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+      return CHNS_ENOMEM;
+    }
   }
   c->allocs.push_back(q);
   *p = static_cast<T*>(q);
@@ -117,6 +134,30 @@ int upload_sell(chns_ctx* c, const Sell& S, DSell& d) {
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
+
+// Whether an operator equals its transpose in the context's current state:
+// M, K and the matching factor X always; the P1 operators with a convection
+// part (C, L, AC and the CH block) when no velocity is assembled; the Oseen
+// operators (convection J(w), PCD N_p(w)) never.
+bool op_symmetric(const chns_ctx* c, int op) {
+  switch (op) {
+    case CHNS_OP_M: case CHNS_OP_K: case CHNS_OP_X: return true;
+    case CHNS_OP_C: case CHNS_OP_L: case CHNS_OP_AC: case CHNS_OP_CH: return !c->has_conv;
+    default: return false;
+  }
+}
+
+bool block_symmetric(const chns_ctx* c, int block) { return block != CHNS_BLOCK_NS && !c->has_conv; }
+
+// The transposed products need the transposed operators in the context
+// (chns_assemble_transposed) and the forward ones the forward operators.
+int check_orientation(chns_ctx* c, bool symmetric, int32_t transpose) {
+  if (transpose != 0 && transpose != 1) return fail(c, CHNS_EINVAL, "transpose must be 0 or 1");
+  if (symmetric || (transpose != 0) == c->transposed) return CHNS_OK;
+  return fail(c, CHNS_ESTATE,
+              transpose ? "the context holds the forward operators: call chns_assemble_transposed first"
+                        : "the context holds the transposed operators: call chns_assemble first");
+}
 
 int check_params(chns_ctx* c, const chns_params* p) {
   if (!p) return fail(c, CHNS_EINVAL, "params is NULL");
@@ -1565,7 +1606,12 @@ int build(chns_ctx* c) {
 
 void release(chns_ctx* c) {
   if (!c) return;
-  for (void* p : c->allocs) (void)hipFree(p);
+  for (void* p : c->allocs) {
+    if (c->free_)
+      c->free_(p, c->alloc_ctx);
+    else
+      (void)hipFree(p);
+  }
   c->allocs.clear();
   if (c->kr.host) (void)hipHostFree(c->kr.host);
   for (auto& e : c->ledger.ev) (void)hipEventDestroy(e);
@@ -1773,9 +1819,14 @@ void chns_default_opts(chns_solve_opts* o) {
   o->mg_rho_cut = 0.25;
 }
 
-int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out) {
+int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn alloc, chns_free_fn free_,
+                void* alloc_ctx, chns_ctx** out) {
   if (!out) return CHNS_EINVAL;
   *out = nullptr;
+  if ((alloc == nullptr) != (free_ == nullptr)) {
+    g_create_err = "alloc and free must both be given or both be NULL";
+    return CHNS_EINVAL;
+  }
   if (!mesh) {
     g_create_err = "mesh is NULL";
     return CHNS_EINVAL;
@@ -1794,6 +1845,9 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_ctx** out
     return CHNS_EINVAL;
   }
   chns_ctx* c = new chns_ctx();
+  c->alloc = alloc;
+  c->free_ = free_;
+  c->alloc_ctx = alloc_ctx;
   c->mesh = *mesh;
   c->prm = *params;
   c->ternary = (mesh->model == CHNS_MODEL_TERNARY);
@@ -1947,9 +2001,10 @@ int chns_get_matrix(chns_ctx* c, int32_t op, int32_t* h_rowptr, int32_t* h_col, 
   return CHNS_OK;
 }
 
-int chns_spmv(chns_ctx* c, int32_t op, int32_t precision, double alpha, const void* d_x, double beta,
-              void* d_y, void* stream) {
+int chns_spmv(chns_ctx* c, int32_t op, int32_t precision, int32_t transpose, double alpha, const void* d_x,
+              double beta, void* d_y, void* stream) {
   if (!c) return CHNS_EINVAL;
+  TRY(check_orientation(c, op_symmetric(c, op), transpose));
   if (!d_x || !d_y) return fail(c, CHNS_EINVAL, "x or y is NULL");
   if (d_x == d_y) return fail(c, CHNS_EINVAL, "x and y must not overlap");
   if (precision != CHNS_F64 && precision != CHNS_MIXED) return fail(c, CHNS_EINVAL, "unknown precision");
@@ -2007,18 +2062,19 @@ int chns_spmv(chns_ctx* c, int32_t op, int32_t precision, double alpha, const vo
   return CHNS_OK;
 }
 
-int chns_precond_apply(chns_ctx* c, int32_t block, const chns_solve_opts* opts, const double* d_r,
-                       double* d_z, void* stream) {
+int chns_precond_apply(chns_ctx* c, int32_t block, int32_t transpose, const chns_solve_opts* opts,
+                       const double* d_r, double* d_z, void* stream) {
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
   if (!d_r || !d_z) return fail(c, CHNS_EINVAL, "r or z is NULL");
   if (d_r == d_z) return fail(c, CHNS_EINVAL, "r and z must not overlap");
   if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_AC && !(block == CHNS_BLOCK_NS && c->ternary))
     return fail(c, CHNS_EUNSUPPORTED, "block not available");
+  TRY(check_orientation(c, block_symmetric(c, block), transpose));
   return precond(c, block, *opts, d_r, d_z, static_cast<hipStream_t>(stream));
 }
 
-int chns_krylov_solve(chns_ctx* c, int32_t block, const double* d_b, double* d_x,
+int chns_krylov_solve(chns_ctx* c, int32_t block, int32_t transpose, const double* d_b, double* d_x,
                       const chns_solve_opts* opts, chns_solve_info* h_info, void* stream) {
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
@@ -2027,6 +2083,7 @@ int chns_krylov_solve(chns_ctx* c, int32_t block, const double* d_b, double* d_x
     return fail(c, CHNS_EUNSUPPORTED, "block not available");
   if (block == CHNS_BLOCK_AC && c->mesh.model == CHNS_MODEL_CH)
     return fail(c, CHNS_EUNSUPPORTED, "model has no AC block");
+  TRY(check_orientation(c, block_symmetric(c, block), transpose));
   return fgmres(c, block, d_b, d_x, *opts, h_info, static_cast<hipStream_t>(stream));
 }
 

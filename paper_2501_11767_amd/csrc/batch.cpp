@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -90,6 +91,7 @@ struct BLevel {
   BTile* tzero[NOPS] = {};
   int* tail_idx[NOPS] = {};
   int ntdown[NOPS] = {}, ntzero[NOPS] = {}, ntail[NOPS] = {};
+  size_t tile_cap = 0;  // tiles of every instance present on this level
 };
 
 }  // namespace
@@ -132,6 +134,10 @@ struct chns_batch {
   TailArgs<float>* tails32[NOPS] = {};
   TailArgs<double>* tails64[NOPS] = {};
   std::vector<void*> allocs;
+  // device allocator of the caller (chns_batch_create), or hipMalloc/hipFree when NULL
+  chns_alloc_fn alloc = nullptr;
+  chns_free_fn free_ = nullptr;
+  void* alloc_ctx = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -139,6 +145,11 @@ struct chns_batch {
 namespace {
 
 thread_local std::string g_batch_err;
+
+int fail_cap(chns_batch* b) {
+  b->err = "internal: an options table exceeds its buffer";
+  return CHNS_EINVAL;
+}
 
 #define BCHK(b, expr)                                                  \
   do {                                                                 \
@@ -159,12 +170,34 @@ int balloc(chns_batch* b, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) return CHNS_OK;
   void* q = nullptr;
-  if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) {
-    b->err = "hipMalloc failed";
-    return CHNS_ENOMEM;
+  if (b->alloc) {
+    q = b->alloc(n * sizeof(T), b->alloc_ctx);
+    if (!q) {
+      b->err = "the caller's allocator returned NULL";
+      return CHNS_ENOMEM;
+    }
+    b->allocs.push_back(q);
+    if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+      b->err = "the caller's allocator returned memory not aligned to 256 bytes";
+      return CHNS_EINVAL;
+    }
+  } else {
+    if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) {
+      b->err = "hipMalloc failed";
+      return CHNS_ENOMEM;
+    }
+    b->allocs.push_back(q);
   }
-  b->allocs.push_back(q);
   *p = static_cast<T*>(q);
+  return CHNS_OK;
+}
+
+// Copy a host table into a buffer allocated at creation (tables that depend
+// on the solve options are rewritten in place, never reallocated).
+template <typename T>
+int bput(chns_batch* b, T* dst, const std::vector<T>& h, size_t cap) {
+  if (h.size() > cap) return fail_cap(b);
+  if (!h.empty()) BCHK(b, hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return CHNS_OK;
 }
 
@@ -473,14 +506,16 @@ int prepare_tiles(chns_batch* b, const chns_solve_opts& o, int op, const std::ve
     L.ntdown[op] = int(down[l].size());
     L.ntzero[op] = int(zero[l].size());
     L.ntail[op] = int(tails[l].size());
-    BTRY(bupload(b, &L.tdown[op], down[l]));
-    BTRY(bupload(b, &L.tzero[op], zero[l]));
-    BTRY(bupload(b, &L.tail_idx[op], tails[l]));
+    BTRY(bput(b, L.tdown[op], down[l], L.tile_cap));
+    BTRY(bput(b, L.tzero[op], zero[l], L.tile_cap));
+    BTRY(bput(b, L.tail_idx[op], tails[l], size_t(b->count)));
   }
-  BTRY(bupload(b, &b->tails32[op], t32));
-  BTRY(bupload(b, &b->tails64[op], t64));
+  BTRY(bput(b, b->tails32[op], t32, size_t(b->count)));
+  BTRY(bput(b, b->tails64[op], t64, size_t(b->count)));
   return CHNS_OK;
 }
+
+void drop_graphs(chns_batch* b);
 
 // Masks and coarse Chebyshev coefficients for the given options.
 int prepare_cycles(chns_batch* b, const chns_solve_opts& o) {
@@ -488,6 +523,11 @@ int prepare_cycles(chns_batch* b, const chns_solve_opts& o) {
   std::snprintf(key, sizeof key, "%d/%d/%d/%.17g/%.17g/%d", o.mg_pre, o.mg_post, o.mg_coarse, o.mg_lmax,
                 o.mg_rho_cut, o.precision);
   if (b->opts_key == key) return CHNS_OK;
+  // the tables are rewritten in place: no launch may still read them, and no
+  // captured graph may keep launching with the old ones
+  BCHK(b, hipDeviceSynchronize());
+  drop_graphs(b);
+  b->opts_key.clear();
   const int Lmax = int(b->lv.size());
   bool tiled = o.mg_pre <= TAIL_MAXSM && o.mg_post <= TAIL_MAXSM;
   for (int op = 0; op < NOPS; ++op) {
@@ -534,13 +574,14 @@ int prepare_cycles(chns_batch* b, const chns_solve_opts& o) {
         }
       }
       std::vector<float> c1f(c1.begin(), c1.end()), c2f(c2.begin(), c2.end());
-      BTRY(bupload(b, &L.smooth[op], sm));
-      BTRY(bupload(b, &L.coarse[op], co));
-      BTRY(bupload(b, &L.present[op], pr));
-      BTRY(bupload(b, &L.cc64[op][0], c1));
-      BTRY(bupload(b, &L.cc64[op][1], c2));
-      BTRY(bupload(b, &L.cc32[op][0], c1f));
-      BTRY(bupload(b, &L.cc32[op][1], c2f));
+      const size_t ns = size_t(L.nslices), nc = size_t(MAXCHEB) * b->count;
+      BTRY(bput(b, L.smooth[op], sm, ns));
+      BTRY(bput(b, L.coarse[op], co, ns));
+      BTRY(bput(b, L.present[op], pr, ns));
+      BTRY(bput(b, L.cc64[op][0], c1, nc));
+      BTRY(bput(b, L.cc64[op][1], c2, nc));
+      BTRY(bput(b, L.cc32[op][0], c1f, nc));
+      BTRY(bput(b, L.cc32[op][1], c2f, nc));
     }
     BTRY(prepare_tiles(b, o, op, cut, tiled));
   }
@@ -915,6 +956,24 @@ int bbuild(chns_batch* b) {
     }
     for (double** v : {&L.b64, &L.x64, &L.t64, &L.r64, &L.dd64}) BTRY(balloc(b, v, nr));
     for (float** v : {&L.b32, &L.x32, &L.t32, &L.r32, &L.dd32}) BTRY(balloc(b, v, nr));
+    // tables of the options-dependent cycle (masks, coarse Chebyshev
+    // coefficients, tile and tail lists), rewritten when the options change
+    L.tile_cap = 0;
+    for (int i = 0; i < b->count; ++i)
+      if (L.roff[i] >= 0) L.tile_cap += size_t(btile_count(b->n[i] >> l));
+    const size_t nc = size_t(MAXCHEB) * b->count;
+    for (int op = 0; op < NOPS; ++op) {
+      BTRY(balloc(b, &L.smooth[op], size_t(L.nslices)));
+      BTRY(balloc(b, &L.coarse[op], size_t(L.nslices)));
+      BTRY(balloc(b, &L.present[op], size_t(L.nslices)));
+      BTRY(balloc(b, &L.cc64[op][0], nc));
+      BTRY(balloc(b, &L.cc64[op][1], nc));
+      BTRY(balloc(b, &L.cc32[op][0], nc));
+      BTRY(balloc(b, &L.cc32[op][1], nc));
+      BTRY(balloc(b, &L.tdown[op], std::max<size_t>(L.tile_cap, 1)));
+      BTRY(balloc(b, &L.tzero[op], std::max<size_t>(L.tile_cap, 1)));
+      BTRY(balloc(b, &L.tail_idx[op], size_t(b->count)));
+    }
     BCHK(b, hipMemset(L.M, 0, ns * sizeof(double)));
     BCHK(b, hipMemset(L.K, 0, ns * sizeof(double)));
     // padding rows (partial slices of tiny levels): unit diagonal keeps 1/diag finite
@@ -965,6 +1024,10 @@ int bbuild(chns_batch* b) {
   BTRY(balloc(b, &b->y, cnt * (m + 1)));
   BTRY(balloc(b, &b->red, cnt * (2 * m + 3)));
   BTRY(balloc(b, &b->coef, cnt * (2 * m + 2)));
+  for (int op = 0; op < NOPS; ++op) {
+    BTRY(balloc(b, &b->tails32[op], cnt));
+    BTRY(balloc(b, &b->tails64[op], cnt));
+  }
   for (double** v : {&b->inv, &b->nrm, &b->tol}) BTRY(balloc(b, v, cnt));
   for (int** v : {&b->active, &b->kcols, &b->iters[0], &b->iters[1], &b->conv[0], &b->conv[1]})
     BTRY(balloc(b, v, cnt));
@@ -1081,7 +1144,13 @@ int step_graph(chns_batch* b, const double* phi, const double* mu, const double*
 
 void brelease(chns_batch* b) {
   drop_graphs(b);
-  for (void* p : b->allocs) (void)hipFree(p);
+  for (void* p : b->allocs) {
+    if (b->free_)
+      b->free_(p, b->alloc_ctx);
+    else
+      (void)hipFree(p);
+  }
+  b->allocs.clear();
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
 }
@@ -1106,9 +1175,14 @@ int check_bopts(chns_batch* b, const chns_solve_opts* o) {
 
 extern "C" {
 
-int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_params, chns_batch** out) {
+int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_params, chns_alloc_fn alloc,
+                      chns_free_fn free_, void* alloc_ctx, chns_batch** out) {
   if (!out) return CHNS_EINVAL;
   *out = nullptr;
+  if ((alloc == nullptr) != (free_ == nullptr)) {
+    g_batch_err = "alloc and free must both be given or both be NULL";
+    return CHNS_EINVAL;
+  }
   if (count < 1 || count > 4096 || !h_n || !h_params) {
     g_batch_err = "count must be in 1..4096 with sizes and parameters";
     return CHNS_EINVAL;
@@ -1131,6 +1205,9 @@ int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_pa
     }
   }
   chns_batch* b = new chns_batch();
+  b->alloc = alloc;
+  b->free_ = free_;
+  b->alloc_ctx = alloc_ctx;
   b->count = count;
   b->n.assign(h_n, h_n + count);
   b->prm.assign(h_params, h_params + count);

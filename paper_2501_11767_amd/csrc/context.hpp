@@ -168,6 +168,10 @@ struct chns_ctx {
   double* diag = nullptr;  // diagnostics results (NDIAG)
   float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr, *w32c = nullptr;
   std::vector<void*> allocs;
+  // device allocator of the caller (chns_create), or hipMalloc/hipFree when NULL
+  chns_alloc_fn alloc = nullptr;
+  chns_free_fn free_ = nullptr;
+  void* alloc_ctx = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };

@@ -42,7 +42,7 @@ def test_default_opts(L):
 def test_create_rejects_bad_mesh(L, n, model):
     h = ct.c_void_p()
     rc = L.chns_create(ct.byref(chns.Mesh(n, model)), ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)),
-                       ct.byref(h))
+                       chns.ALLOC_FN(), chns.FREE_FN(), None, ct.byref(h))
     assert rc == chns.EINVAL and not h.value
     assert len(L.chns_last_error(None)) > 0
 
@@ -53,10 +53,38 @@ def test_create_rejects_bad_params(L, bad):
     p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.1, viscosity=1.0, alpha=1e-8, rho=1.0)
     p.update(bad)
     h = ct.c_void_p()
-    rc = L.chns_create(ct.byref(chns.Mesh(16, chns.MODEL_CH_AC)), ct.byref(chns.Params(**p)), ct.byref(h))
+    rc = L.chns_create(ct.byref(chns.Mesh(16, chns.MODEL_CH_AC)), ct.byref(chns.Params(**p)),
+                       chns.ALLOC_FN(), chns.FREE_FN(), None, ct.byref(h))
     assert rc == chns.EINVAL and not h.value
 
 
 def test_null_context_is_rejected(L):
     assert L.chns_destroy(None) == chns.EINVAL
-    assert L.chns_spmv(None, 0, 0, 1.0, None, 0.0, None, None) == chns.EINVAL
+    assert L.chns_spmv(None, 0, 0, 0, 1.0, None, 0.0, None, None) == chns.EINVAL
+    assert L.chns_precond_apply(None, 0, 0, None, None, None, None) == chns.EINVAL
+    assert L.chns_krylov_solve(None, 0, 0, None, None, None, None, None) == chns.EINVAL
+
+
+def test_create_rejects_half_an_allocator(L):
+    # an allocator without its free function (or the reverse) is refused
+    # before any device work
+    h = ct.c_void_p()
+    p = chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)
+    rc = L.chns_create(ct.byref(chns.Mesh(16, chns.MODEL_CH)), ct.byref(p), chns._ALLOC_THUNK,
+                       chns.FREE_FN(), None, ct.byref(h))
+    assert rc == chns.EINVAL and not h.value
+    n = (ct.c_int32 * 1)(32)
+    rc = L.chns_batch_create(1, ct.cast(n, ct.c_void_p), ct.cast(ct.pointer(p), ct.c_void_p),
+                             chns.ALLOC_FN(), chns._FREE_THUNK, None, ct.byref(h))
+    assert rc == chns.EINVAL and not h.value
+
+
+def test_binding_checks_tensors_before_any_call():
+    # dtype, device, layout and size are checked on the host: a float32 or a
+    # short tensor never reaches the library
+    import torch
+    with pytest.raises(ValueError, match="CUDA"):
+        chns._ptr(torch.zeros(4, dtype=torch.float64), 4)
+    with pytest.raises(ValueError, match="required"):
+        chns._ptr(None, 4)
+    assert chns._ptr(None, 4, optional=True) is None

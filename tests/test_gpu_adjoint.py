@@ -85,14 +85,25 @@ def test_transposed_operators_and_preconditioners(mods, n):
         px = torch.empty_like(x)
         ctx.precond(blocks[op], x, px, opts)
         prec[op] = float(torch.dot(y, px))
+    # the transposed products need the transposed operators first
+    for op, (x, y) in vecs.items():
+        with pytest.raises(C.ChnsError) as e:
+            ctx.spmv(op, y, torch.empty_like(y), transpose=True)
+        assert e.value.code == C.ESTATE
+        with pytest.raises(C.ChnsError) as e:
+            ctx.precond(blocks[op], y, torch.empty_like(y), opts, transpose=True)
+        assert e.value.code == C.ESTATE
     ctx.assemble_transposed(g["vel"], mu)
     for op, (x, y) in vecs.items():
+        with pytest.raises(C.ChnsError) as e:  # and the forward ones the forward operators
+            ctx.spmv(op, y, torch.empty_like(y))
+        assert e.value.code == C.ESTATE
         aty = torch.empty_like(y)
-        ctx.spmv(op, y, aty)
+        ctx.spmv(op, y, aty, transpose=True)
         got = float(torch.dot(aty, x))
         assert abs(got - fwd[op]) <= 1e-12 * abs(fwd[op]), (op, got, fwd[op])
         pty = torch.empty_like(y)
-        ctx.precond(blocks[op], y, pty, opts)
+        ctx.precond(blocks[op], y, pty, opts, transpose=True)
         got = float(torch.dot(pty, x))
         assert abs(got - prec[op]) <= 1e-11 * abs(prec[op]), (op, got, prec[op])
     ctx.close()

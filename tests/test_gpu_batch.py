@@ -2,10 +2,11 @@
 parameters against the oracle's exact (Fourier-mode) step, the hipGraph
 replays against the eager run, mixed precision, and the autotuner.
 
-Bars: FP64 instances within 1e-9 of the exact step at rtol 1e-12 (condition
-numbers <= 1e3 for these parameters); mixed precision within 1e-7 at rtol
-1e-10; graph replays equal to the eager run to 1e-13 (the same kernels run on
-the same data; the eager run only stops the restart loop earlier).
+Bars: every field of every instance (phi, mu, Phi) within 1e-10 of the exact
+step in FP64 (rtol 1e-13) and within 1e-8 in mixed precision (rtol 1e-12),
+as relative 2-norms and entrywise relative to the field's largest entry;
+graph replays equal to the eager run to 1e-13 (the same kernels run on the
+same data; the eager run only stops the restart loop earlier).
 """
 import numpy as np
 import pytest
@@ -73,7 +74,7 @@ def _run(chns, batch, phi0, Phi0, opts, **kw):
     return rc, info, phi.cpu().numpy(), mu.cpu().numpy(), Phi.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision,rtol,bar", [(0, 1e-12, 1e-9), (1, 1e-10, 1e-7)])
+@pytest.mark.parametrize("precision,rtol,bar", [(0, 1e-13, 1e-10), (1, 1e-12, 1e-8)])
 def test_batch_instances_match_oracle(chns, precision, rtol, bar):
     prm = _params(len(SIZES))
     batch = chns.Batch(SIZES, prm)
@@ -81,15 +82,15 @@ def test_batch_instances_match_oracle(chns, precision, rtol, bar):
     assert list(np.diff(off)) == [n * n for n in SIZES]
     phi0, Phi0 = _fields(SIZES)
     rc, info, phi, mu, Phi = _run(chns, batch, phi0, Phi0,
-                                  chns.default_opts(rtol=rtol, precision=precision, maxiter=400))
+                                  chns.default_opts(rtol=rtol, precision=precision, maxiter=1000))
     assert rc == chns.OK and info["conv_ch"].all() and info["conv_ac"].all(), info
     for i, n in enumerate(SIZES):
         sl = slice(off[i], off[i + 1])
         ph, m, Ph = _oracle(n, prm[i], phi0[sl], Phi0[sl])
         rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
-        assert rel(phi[sl], ph) < bar, (i, rel(phi[sl], ph))
-        assert rel(mu[sl], m) < 100 * bar, (i, rel(mu[sl], m))
-        assert rel(Phi[sl], Ph) < bar, (i, rel(Phi[sl], Ph))
+        mrel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
+        for name, got, ref in (("phi", phi[sl], ph), ("mu", mu[sl], m), ("Phi", Phi[sl], Ph)):
+            assert rel(got, ref) < bar and mrel(got, ref) < bar, (i, name, rel(got, ref), mrel(got, ref))
     batch.close()
 
 

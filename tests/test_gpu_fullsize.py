@@ -2,11 +2,16 @@
 times (through the C-ABI).
 
 * chac1024 (1024 x 1024 CH + AC): one step against the oracle's exact
-  Fourier-mode solve.  Bench configuration (FGMRES(13), V(1,3) cut at rho <= 16, rtol 1e-8): true
-  residual in the oracle's arithmetic <= 2 rtol, and the forward error <=
-  2 kappa rtol with kappa the condition number of the CH block from its
-  Fourier symbols.  Tighter solves reach the stated accuracy: FP64 at rtol
-  1e-11 within 1e-10 relative, mixed at rtol 1e-9 within 1e-8.
+  Fourier-mode solve at every tau of the sweep (1e-5 ... 1e-2), FP64 and
+  mixed.  Bench configuration (FGMRES(13), V(1,3) cut at rho <= 16, rtol
+  1e-8): true residual in the oracle's arithmetic <= 2 rtol, and the forward
+  error <= 2 kappa rtol with kappa the condition number of the CH block from
+  its Fourier symbols.  At the stated accuracy: FP64 within 1e-10 and mixed
+  within 1e-8 for each of phi, mu and Phi, as relative 2-norms and entrywise
+  relative to the field's largest entry, with rtol = max(bar / (2 kappa),
+  1e-13); 1e-13 sits above the FP64 residual floor of this system (measured
+  2.5e-14 ... 5e-14), and where it exceeds bar / (2 kappa) (tau >= 1e-3 in
+  FP64) the measured error, not the bound, is what the test checks.
 * dry256 (ternary + AC + Oseen on 256 x 256, the benchmark's FGMRES(15) and
   multigrid options): the GPU step's outputs satisfy
   the oracle's independently assembled systems (CH for both phases, AC,
@@ -55,6 +60,10 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _maxrel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 class Fourier:
     """Periodic P1 operators by their Fourier symbols (oracle), for exact
     solves, residuals and condition numbers of convection-free systems."""
@@ -97,41 +106,44 @@ def _binary_rhs(F, prm, phi0, Phi0):
     return b1, b2, bac
 
 
-@pytest.mark.parametrize("precision,rtol,bar", [("f64", 1e-8, None), ("mixed", 1e-8, None),
-                                                ("f64", 1e-11, 1e-10), ("mixed", 1e-9, 1e-8)])
-def test_chac1024_step_matches_exact_solve(mods, precision, rtol, bar):
+@pytest.mark.parametrize("tau", inputs.CONFIGS["chac1024"]["tau_sweep"])
+def test_chac1024_step_matches_exact_solve(mods, tau):
     import torch
     C, _ = mods
     cfg = inputs.CONFIGS["chac1024"]
     n, N = cfg["n"], cfg["n"] ** 2
-    print(f"chac1024 full size: {precision} rtol {rtol}", flush=True)
     st = inputs.initial_state(n, "ch_ac", cfg["mean"], cfg["seed"])
-    p = dict(eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
-    ctx = C.Context(n, "ch_ac", **p)
-    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
-    fin = ctx.fields(phi=[_dev(st["phi"][0])], mu=[z()], Phi_v=_dev(st["Phi_v"]))
-    out = [z(), z(), z()]
-    fout = ctx.fields(phi=[out[0]], mu=[out[1]], Phi_v=out[2])
-    prec = C.F64 if precision == "f64" else C.MIXED
-    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=prec, restart=13, maxiter=600, **BENCH_MG))
-    torch.cuda.synchronize()
-    assert rc == C.OK, info
-    phi, mu, Phi = (t.cpu().numpy() for t in out)
-    ctx.close()
+    p = dict(eps=cfg["eps"], tau=tau, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
     prm = Params(**p)
     F = Fourier(n)
     b1, b2, bac = _binary_rhs(F, prm, st["phi"][0], st["Phi_v"])
     ex_phi, ex_mu = solvers.fft_ch_solve(n, prm, b1, b2)
     ex_Phi = solvers.fft_ac_solve(n, prm, bac)
-    assert F.ch_residual(prm, phi, mu, b1, b2) <= 2 * rtol
-    assert F.ac_residual(prm, Phi, bac) <= 2 * rtol
     kappa = F.ch_kappa(prm)
-    e_ch = np.sqrt(np.sum((phi - ex_phi) ** 2) + np.sum((mu - ex_mu) ** 2)) / \
-        np.sqrt(np.sum(ex_phi ** 2) + np.sum(ex_mu ** 2))
-    assert e_ch <= 2 * kappa * rtol, (e_ch, kappa)
-    if bar is not None:
-        assert _rel(phi, ex_phi) <= bar, _rel(phi, ex_phi)
-        assert _rel(Phi, ex_Phi) <= bar, _rel(Phi, ex_Phi)
+    ctx = C.Context(n, "ch_ac", **p)
+    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
+    fin = ctx.fields(phi=[_dev(st["phi"][0])], mu=[z()], Phi_v=_dev(st["Phi_v"]))
+    for precision, bar in (("f64", 1e-10), ("mixed", 1e-8)):
+        prec = C.F64 if precision == "f64" else C.MIXED
+        for rtol in (1e-8, max(bar / (2 * kappa), 1e-13)):
+            print(f"chac1024 full size: tau {tau:g} {precision} rtol {rtol:.3g}", flush=True)
+            out = [z(), z(), z()]
+            fout = ctx.fields(phi=[out[0]], mu=[out[1]], Phi_v=out[2])
+            o = C.default_opts(rtol=rtol, precision=prec, restart=13, maxiter=1500, **BENCH_MG)
+            rc, info = ctx.timestep(fin, fout, 1, o)
+            torch.cuda.synchronize()
+            assert rc == C.OK, info
+            phi, mu, Phi = (t.cpu().numpy() for t in out)
+            assert F.ch_residual(prm, phi, mu, b1, b2) <= 2 * rtol
+            assert F.ac_residual(prm, Phi, bac) <= 2 * rtol
+            e_ch = np.sqrt(np.sum((phi - ex_phi) ** 2) + np.sum((mu - ex_mu) ** 2)) / \
+                np.sqrt(np.sum(ex_phi ** 2) + np.sum(ex_mu ** 2))
+            assert e_ch <= 2 * kappa * rtol, (e_ch, kappa)
+            if rtol < 1e-8:
+                for name, got, ref in (("phi", phi, ex_phi), ("mu", mu, ex_mu), ("Phi", Phi, ex_Phi)):
+                    e2, em = _rel(got, ref), _maxrel(got, ref)
+                    assert e2 <= bar and em <= bar, (tau, precision, name, e2, em)
+    ctx.close()
 
 
 def _precond_parity(mods, n, option_sets):
@@ -163,8 +175,13 @@ def _precond_parity(mods, n, option_sets):
             za = torch.zeros(n * n, dtype=torch.float64, device="cuda")
             ctx.precond(C.BLOCK_AC, _dev(ra), za, o)
             torch.cuda.synchronize()
-            assert _rel(z.cpu().numpy(), ref) < bar, (prec, mgo)
-            assert _rel(za.cpu().numpy(), refa) < bar, (prec, mgo)
+            zc, zac = z.cpu().numpy(), za.cpu().numpy()
+            N = n * n
+            assert _rel(zc, ref) < bar, (prec, mgo)
+            assert _rel(zac, refa) < bar, (prec, mgo)
+            # entrywise: the ragged last tile row/column and the tile seams
+            assert _maxrel(zc[:N], ref[:N]) < 2 * bar and _maxrel(zc[N:], ref[N:]) < 2 * bar, (prec, mgo)
+            assert _maxrel(zac, refa) < 2 * bar, (prec, mgo)
     ctx.close()
 
 

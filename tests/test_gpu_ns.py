@@ -5,9 +5,13 @@ Bars: Taylor-Hood sparsity patterns equal the element connectivity, values
 within 1e-12 relative to the largest entry (entries the oracle's sparse sums
 dropped as exact zeros compare against 0); products within 1e-13; the PCD
 block preconditioner (a fixed linear operator) within 1e-11 of the oracle's;
-solutions within the conditioning bound of the direct (bordered) solve; one
-full ternary step within 1e-9 (velocity, CH, AC fields) and 1e-7 (pressure,
-which the residual controls least).
+solutions and one full FP64 ternary step within 1e-10 for every field but the
+pressure, both as relative 2-norms and entrywise relative to the field's
+largest entry.  The pressure's bar is measured, not chosen: the oracle's own
+bordered solve moves by ~7e-11 (n = 16) when its matrix and right-hand side
+are perturbed at the rounding level (relative 2e-16 per entry), which is the
+size of the GPU-oracle difference at any tolerance below 1e-13; the tests
+take ten times the perturbed solve's change.
 """
 import numpy as np
 import pytest
@@ -33,6 +37,26 @@ def _np(t):
 
 def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _maxrel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _pressure_sensitivity(ops, sysr, p_ref, trials=3):
+    """Largest relative change of the oracle's pressure when the assembled
+    Oseen matrix, B and the right-hand side are perturbed entrywise by a
+    relative 2e-16 (rounding-level differences between two assemblies)."""
+    A, B, rhs = sysr["ns_A"].tocsr(), ops.B.tocsr(), sysr["ns_rhs"]
+    g = np.random.default_rng(1)
+    worst = 0.0
+    for _ in range(trials):
+        A2, B2 = A.copy(), B.copy()
+        A2.data = A2.data * (1 + 2e-16 * g.uniform(-1, 1, A2.data.size))
+        B2.data = B2.data * (1 + 2e-16 * g.uniform(-1, 1, B2.data.size))
+        _, p2, _ = solvers.bordered_oseen_solve(A2, B2, ops.M, rhs * (1 + 2e-16 * g.uniform(-1, 1, rhs.size)))
+        worst = max(worst, _rel(p2, p_ref), _maxrel(p2, p_ref))
+    return worst
 
 
 @pytest.fixture(scope="module")
@@ -109,6 +133,7 @@ def test_ns_spmv(chns):
     ctx.spmv(chns.OP_NS, _t(x), yt, alpha=0.5, beta=-2.0)
     torch.cuda.synchronize()
     assert _rel(_np(yt), 0.5 * (A @ x) - 2.0 * y0) < 1e-13
+    assert _maxrel(_np(yt), 0.5 * (A @ x) - 2.0 * y0) < 1e-13
     ctx.close()
 
 
@@ -145,9 +170,9 @@ def test_ns_precond_matches_oracle(chns, n):
     torch.cuda.synchronize()
     ref = Pc.apply(r)
     N4 = 4 * n * n
-    assert _rel(_np(z)[:N4], ref[:N4]) < 1e-11
-    assert _rel(_np(z)[N4:2 * N4], ref[N4:2 * N4]) < 1e-11
-    assert _rel(_np(z)[2 * N4:], ref[2 * N4:]) < 1e-11
+    for sl in (slice(0, N4), slice(N4, 2 * N4), slice(2 * N4, None)):
+        assert _rel(_np(z)[sl], ref[sl]) < 1e-11
+        assert _maxrel(_np(z)[sl], ref[sl]) < 1e-11
     z32 = torch.zeros_like(z)
     ctx.precond(chns.BLOCK_NS, _t(r), z32, chns.default_opts(precision=chns.MIXED))
     torch.cuda.synchronize()
@@ -169,9 +194,11 @@ def test_ns_solve_matches_bordered_direct_solve(chns, precision):
     xv = _np(x)
     ref_v = np.concatenate([out["vel"][0], out["vel"][1]])
     assert info["converged"] == 1, info
-    assert _rel(xv[:8 * N], ref_v) < 1e-9
+    assert _rel(xv[:8 * N], ref_v) < 1e-10 and _maxrel(xv[:8 * N], ref_v) < 1e-10
     assert abs(xv[8 * N:].mean()) < 1e-12 * np.abs(out["p"]).max()
-    assert _rel(xv[8 * N:], out["p"]) < 1e-7
+    pbar = 10 * _pressure_sensitivity(ops, sysr, out["p"])
+    assert pbar < 1e-8, pbar
+    assert _rel(xv[8 * N:], out["p"]) < pbar and _maxrel(xv[8 * N:], out["p"]) < pbar, pbar
     ctx.close()
 
 
@@ -188,13 +215,14 @@ def test_ternary_timestep_matches_oracle(chns):
     rc, infos = ctx.timestep(f, f, nsteps=1, opts=chns.default_opts(rtol=1e-13, maxiter=400))
     torch.cuda.synchronize()
     assert rc == chns.OK and len(infos) == 4 and all(i["converged"] for i in infos), infos
-    for i in range(2):
-        assert _rel(_np(fld["phi"][i]), out["phi"][i]) < 1e-10
-        assert _rel(_np(fld["mu"][i]), out["mu"][i]) < 1e-9
-    assert _rel(_np(fld["Phi_v"]), out["Phi_v"]) < 1e-10
-    assert _rel(_np(fld["vel"]), out["vel"].ravel()) < 1e-9
-    assert _rel(_np(fld["p"]), out["p"]) < 1e-7
-    assert _rel(_np(fld["mu"][2]), out["mu_s"]) < 1e-9
+    pairs = [(fld["phi"][i], out["phi"][i]) for i in range(2)] + \
+            [(fld["mu"][i], out["mu"][i]) for i in range(2)] + \
+            [(fld["Phi_v"], out["Phi_v"]), (fld["vel"], out["vel"].ravel()), (fld["mu"][2], out["mu_s"])]
+    for got, ref in pairs:
+        assert _rel(_np(got), ref) < 1e-10 and _maxrel(_np(got), ref) < 1e-10
+    pbar = 10 * _pressure_sensitivity(ops, sysr, out["p"])
+    assert pbar < 1e-8, pbar
+    assert _rel(_np(fld["p"]), out["p"]) < pbar and _maxrel(_np(fld["p"]), out["p"]) < pbar, pbar
     ctx.close()
 
 
