@@ -288,6 +288,20 @@ CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, int32_t transpose, 
  * the host.  CHNS_EINVAL for a missing field or output. */
 CHNS_API int chns_diagnostics(chns_ctx* ctx, const chns_fields* f, double* h_out, void* stream);
 
+/* chns_diagnostics for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same results, bit for bit, from the same kernels, with the reduction's
+ * per-block partials and results in a library-owned static device array of
+ * 5 * 1025 doubles per GPU (held until the process ends) instead of the
+ * context's workspace.  Allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine).  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (several
+ * streams, threads or contexts) race and must be serialised by the caller.
+ * Must be called with the context's GPU current (CHNS_ESTATE otherwise);
+ * CHNS_EINVAL for a reduction that would not fit the array (none does for n
+ * <= 8192) and for a missing field or output.  Synchronises the stream. */
+CHNS_API int chns_diagnostics_noalloc(chns_ctx* ctx, const chns_fields* f, double* h_out, void* stream);
+
 /* Right-hand sides of one step from the level-k fields (paper: [M phi^k;
  * -(tau g/beta) f^k] per CH phase with f^k = M f'(phi^k) nodal, the AC
  * right-hand side, and for the ternary model (rho/tau) M v^k + F^k with the

@@ -32,7 +32,8 @@ MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}
 EXPORTS = [
     "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble",
     "chns_matrix_shape", "chns_get_matrix", "chns_spmv", "chns_precond_apply",
-    "chns_krylov_solve", "chns_step_rhs", "chns_diagnostics", "chns_timestep", "chns_last_error",
+    "chns_krylov_solve", "chns_step_rhs", "chns_diagnostics", "chns_diagnostics_noalloc",
+    "chns_timestep", "chns_last_error",
     "chns_assemble_transposed", "chns_timestep_adjoint", "chns_ledger_start", "chns_ledger_read",
     "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
     "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_precond_apply",
@@ -139,6 +140,7 @@ def lib():
                                     ct.POINTER(SolveInfo), vp]
     L.chns_step_rhs.argtypes = [vp, ct.POINTER(Fields), vp, vp, vp, vp]
     L.chns_diagnostics.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(ct.c_double), vp]
+    L.chns_diagnostics_noalloc.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(ct.c_double), vp]
     L.chns_timestep.argtypes = [vp, ct.POINTER(Fields), ct.POINTER(Fields), i32,
                                 ct.POINTER(SolveOpts), ct.POINTER(SolveInfo), vp]
     L.chns_assemble_transposed.argtypes = [vp, vp, vp, vp]
@@ -334,6 +336,13 @@ class Context:
         """[mass phi (or phi_p), mass phi_N, mass phi_s, mass Phi_v, energy] (FP64, synchronising)."""
         out = (ct.c_double * 5)()
         self._check(self.L.chns_diagnostics(self.h, ct.byref(f), out, _stream()))
+        return [out[i] for i in range(5)]
+
+    def diagnostics_noalloc(self, f: Fields):
+        """As diagnostics(), through the entry point that allocates nothing
+        (library-owned static device scratch, shared by every call on a GPU)."""
+        out = (ct.c_double * 5)()
+        self._check(self.L.chns_diagnostics_noalloc(self.h, ct.byref(f), out, _stream()))
         return [out[i] for i in range(5)]
 
     def ledger_start(self, kernel):

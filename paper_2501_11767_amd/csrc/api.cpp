@@ -1851,7 +1851,16 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
   c->mesh = *mesh;
   c->prm = *params;
   c->ternary = (mesh->model == CHNS_MODEL_TERNARY);
-  const int rc = build(c);
+  int rc = CHNS_OK;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    c->err = "hipGetDevice failed";
+    rc = CHNS_EHIP;
+  } else if (hipError_t e = static_scratch_init(); e != hipSuccess) {
+    c->err = std::string("static scratch address: ") + hipGetErrorString(e);
+    rc = CHNS_EHIP;
+  } else {
+    rc = build(c);
+  }
   if (rc < 0) {
     g_create_err = c->err;
     release(c);
@@ -2119,6 +2128,34 @@ int chns_diagnostics(chns_ctx* c, const chns_fields* f, double* h_out, void* str
               c->ternary, c->prm.eps * c->prm.eps, c->kr.part, c->diag, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(h_out, c->diag, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return CHNS_OK;
+}
+
+int chns_diagnostics_noalloc(chns_ctx* c, const chns_fields* f, double* h_out, void* stream) {
+  if (!c) return CHNS_EINVAL;
+  if (!f || !f->phi[0] || !h_out) return fail(c, CHNS_EINVAL, "phi[0] and the output are required");
+  const bool vapour = c->mesh.model != CHNS_MODEL_CH;
+  if (c->ternary && !f->phi[1]) return fail(c, CHNS_EINVAL, "the ternary model needs phi[1]");
+  if (vapour && !f->Phi_v) return fail(c, CHNS_EINVAL, "model needs Phi_v");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev != c->device) return fail(c, CHNS_ESTATE, "the context's GPU is not the current device");
+  double* scr = static_scratch(dev);
+  if (!scr) return fail(c, CHNS_ESTATE, "static scratch not set up on this device");
+  Level& L0 = c->lv[0];
+  const int64_t nblk = diag_part_blocks(L0.d.nrows);
+  if (int64_t(NDIAG) * (nblk + 1) > STATIC_SCRATCH)
+    return fail(c, CHNS_EINVAL, "the reduction needs " + std::to_string(NDIAG * (nblk + 1)) +
+                                    " doubles of static scratch, more than its " +
+                                    std::to_string(STATIC_SCRATCH));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* part = scr;                  // NDIAG x nblk partials, each written before it is read
+  double* res = scr + NDIAG * nblk;    // NDIAG results
+  diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, vapour ? f->Phi_v : nullptr,
+              c->ternary, c->prm.eps * c->prm.eps, part, res, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(h_out, res, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   return CHNS_OK;
 }

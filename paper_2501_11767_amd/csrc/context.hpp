@@ -136,6 +136,7 @@ struct Ledger {
 struct chns_ctx {
   chns_mesh mesh{};
   chns_params prm{};
+  int device = 0;       // the GPU current at chns_create
   int N = 0;            // P1 nodes
   bool has_conv = false;
   bool c_zero = true;   // C and C32 hold zeros on every level

@@ -12,6 +12,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_util.hpp"
 #include "kernels.hpp"
 
@@ -2368,6 +2370,8 @@ void form_ops(int nlev, const FormLevel* tab, int64_t total, const FormCoef& k, 
   hipLaunchKernelGGL(k_form_ops, dim3(ceil_div(total, BS)), dim3(BS), 0, s, nlev, tab, total, k, conv ? 1 : 0);
 }
 
+int diag_part_blocks(int64_t n) { return reduce_blocks(n); }
+
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
                  const double* Phi, bool ternary, double beta, double* part, double* out, hipStream_t s) {
   const int nblk = reduce_blocks(A.nrows);
@@ -2524,5 +2528,44 @@ template void sum_partial<double>(int64_t, const double*, double*, hipStream_t);
 template void sum_partial<float>(int64_t, const float*, double*, hipStream_t);
 template void sub_mean<double>(int64_t, int, const double*, double*, hipStream_t);
 template void sub_mean<float>(int64_t, int, const double*, float*, hipStream_t);
+
+}  // namespace chns
+
+// ------------------------------------------------------------------ static scratch
+// Device memory of the allocation-free diagnostics entry point.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, not the device array: host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[chns::STATIC_SCRATCH];
+static_assert(chns::STATIC_SCRATCH >= int64_t(chns::NDIAG) * (chns::MAXRED + 1),
+              "static scratch holds the partials of the largest reduction grid and the results");
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+}  // namespace
+
+namespace chns {
+
+hipError_t static_scratch_init() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev]) return hipSuccess;
+  double* p = nullptr;
+  e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[dev] = p;
+  return hipSuccess;
+}
+
+double* static_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
 
 }  // namespace chns

@@ -359,10 +359,21 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
 // through per-block partials (part: 5 x reduce_blocks(n)) and one summing
 // workgroup.  p1 (ternary second phase) and Phi may be null.
 constexpr int NDIAG = 5;
+int diag_part_blocks(int64_t n);  // per-block partial sums diagnostics() writes per quantity
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
                  const double* Phi, bool ternary, double beta, double* part, double* out, hipStream_t s);
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
                 double c_mu, double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s);
+
+// Library-owned device scratch of the allocation-free diagnostics entry
+// point: a file-scope device array (one copy per GPU) of STATIC_SCRATCH
+// doubles, the per-block partials (NDIAG x at most 1024 blocks) and the NDIAG
+// results.  static_scratch_init() resolves the array's device address on the
+// current device once and caches it; static_scratch(device) returns the
+// cached address (null before the init on that device).
+constexpr int64_t STATIC_SCRATCH = int64_t(NDIAG) * (1024 + 1);
+hipError_t static_scratch_init();
+double* static_scratch(int device);
 
 // ------------------------------------------------------------ Taylor-Hood / ternary
 

@@ -1,0 +1,71 @@
+"""The allocation-free diagnostics entry point (chns_diagnostics_noalloc):
+through the C-ABI, bit for bit the results of chns_diagnostics, on two calls in
+a row of which the second has a smaller input, with no allocator call and no
+change of torch's allocated memory.  The static scratch keeps the last call's
+contents, so the second call also shows that nothing stale leaks into it.
+"""
+import numpy as np
+import pytest
+
+from paper_2501_11767_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_11767_amd import chns
+    chns.lib()
+    return chns
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _case(C, n, model, seed):
+    p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.1, viscosity=1.0, alpha=1e-8, rho=1.0)
+    ctx = C.Context(n, model, **p)
+    st = inputs.initial_state(n, model, 0.3 if model == "ternary" else 0.45, seed)
+    phi = [_dev(u) for u in st["phi"]]
+    f = ctx.fields(phi=phi, Phi_v=_dev(st["Phi_v"]) if st.get("Phi_v") is not None else None)
+    return ctx, f
+
+
+def test_noalloc_diagnostics_equal_the_allocating_entry_point(C):
+    import torch
+    cases = [(512, "ternary", 3), (64, "ch_ac", 4), (32, "ch", 5)]  # each smaller than the last
+    ctxs = [_case(C, n, model, seed) for n, model, seed in cases]
+    torch.cuda.synchronize()
+    a0 = C.TorchAllocator.alloc_calls
+    m0 = torch.cuda.memory_allocated()
+    got = []
+    for ctx, f in ctxs:
+        print(f"no-alloc diagnostics n={ctx.n} {ctx.model}", flush=True)
+        got.append(ctx.diagnostics_noalloc(f))
+    assert C.TorchAllocator.alloc_calls == a0
+    assert torch.cuda.memory_allocated() == m0
+    for (ctx, f), g in zip(ctxs, got):
+        ref = ctx.diagnostics(f)
+        assert g == ref, (ctx.n, ctx.model, g, ref)
+        assert np.all(np.isfinite(g)) and g[0] > 0.0
+    # repeated calls keep giving the same numbers (the scratch holds the last
+    # call's partials, each overwritten before it is read)
+    for ctx, f in reversed(ctxs):
+        assert ctx.diagnostics_noalloc(f) == ctx.diagnostics(f)
+    for ctx, _ in ctxs:
+        ctx.close()
+
+
+def test_noalloc_diagnostics_reject_missing_fields(C):
+    import torch
+    ctx = C.Context(16, "ternary", eps=0.02, tau=1e-3)
+    one = torch.zeros(256, dtype=torch.float64, device="cuda")
+    with pytest.raises(C.ChnsError) as e:
+        ctx.diagnostics_noalloc(ctx.fields(phi=[one]))  # the second phase is missing
+    assert e.value.code == C.EINVAL
+    ctx.close()
