@@ -50,9 +50,8 @@ DRY_OPTS = dict(MG, restart=15)
 # copy of known size); filled in from profiles/ once measured for the kernel
 # as it stands, None otherwise.
 TRAFFIC = {
-    # filled in from profiles/chac1024_dcgs_update_hbm_counters.md (FETCH_SIZE and
-    # WRITE_SIZE per dispatch, scaled by the 512 MiB negation probe) once the
-    # counters are taken for the pass as it stands: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+    # profiles/chac1024_dcgs_update_hbm_counters.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+    # per dispatch (the scales: the same counters on the 512 MiB negation probe)
     "k_dcgs_update": 152869730,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
@@ -79,6 +78,7 @@ def parse():
     ap.add_argument("--dry-steps", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64", help="timed forms of the 1024^2 step")
     return ap.parse_args()
 
@@ -215,6 +215,37 @@ def cpu_baseline(cfg, n, tau, budget_s=20.0):
                        f"after {setup:.1f} s of set-up, FP64, 1 thread")
 
 
+def trajectory_section(chns, ctx, st0, p, args, tau=1e-5, steps=10):
+    """A real trajectory of the 1024^2 workload: `steps` consecutive steps from
+    the seeded state at tau = 1e-5 (the explicit potential term keeps this tau
+    stable; at the benchmark's tau = 1e-4 the trajectory blows up within ~10
+    steps), each step solving the previous step's output, so the solver meets
+    a new system every step and its rate predictor the history of the last."""
+    import torch
+    N = args.n * args.n
+    out = {}
+    ctx.set_params(**dict(p, tau=tau))
+    for name, prec in (("mixed", chns.MIXED), ("fp64", chns.F64)):
+        phi, Phi = dev(st0["phi"][0]), dev(st0["Phi_v"])
+        mu = torch.zeros(N, dtype=torch.float64, device="cuda")
+        f = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+        opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, **MG)
+        d0 = ctx.diagnostics(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = ctx.timestep(f, f, steps, opts)
+        torch.cuda.synchronize()
+        total = (time.perf_counter() - t0) * 1e3
+        d1 = ctx.diagnostics(f)
+        out[name] = dict(ms_per_step=total / steps, ch_iters=[i["iters"] for i in infos[0::2]],
+                         ac_iters=[i["iters"] for i in infos[1::2]],
+                         converged=all(i["converged"] for i in infos),
+                         mass_phi_rel_change=(d1[0] - d0[0]) / d0[0], energy=[d0[4], d1[4]])
+    ctx.set_params(**p)
+    return dict(workload=f"chac{args.n} trajectory: {steps} consecutive steps in place from the seeded state at "
+                         f"tau {tau}, rtol 1e-8, the benchmark's solver options", **out)
+
+
 def dry_section(chns, steps):
     """The full coupled drying step (two CH phases, AC, Taylor-Hood Oseen) on the
     periodic 256 x 256 mesh in plain FP64: ms per coupled step and FGMRES
@@ -246,7 +277,13 @@ def dry_section(chns, steps):
         walls.append((time.perf_counter() - t0) * 1e3)
         its.append([i["iters"] for i in inf])
     ctx.close()
-    return dict(workload=f"dry256: ternary CH + AC + Taylor-Hood Oseen step, periodic {n}x{n} "
+    return dict(baseline_config="full coupled drying step, 20 time steps on 256x256 P1/Taylor-Hood, FP64, "
+                                "eps 0.01, tau 5e-4",
+                as_run=f"{steps} timed steps after one warm-up, each re-solving the seeded first step: at tau 5e-4 "
+                       "the explicit potential term makes the 20-step trajectory blow up (the 1024^2 parameters "
+                       "do within 8 steps at tau 1e-4 on the CPU, tests/test_oracle_step.py::"
+                       "test_explicit_potential_limits_the_time_step)",
+                workload=f"dry256: ternary CH + AC + Taylor-Hood Oseen step, periodic {n}x{n} "
                          f"({2 * 2 * N} CH + {N} AC + {9 * N} NS unknowns), FP64, FGMRES({DRY_OPTS['restart']}) "
                          f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid cut at rho <= {MG['mg_rho_cut']}",
                 ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
@@ -289,12 +326,25 @@ def batch_section(chns, steps):
     eager_ms = info_e["ms"] / steps
     # graph budgets from the eager step, one step captured and replayed
     batch.calibrate_graph(info_e)
-    log("batch64: graph capture")
-    batch.timestep(*zin, nsteps=1, opts=opts, use_graph=True, stream=s, out=out, each_from_input=True)
+    log(f"batch64: graph capture ({steps} steps in one graph) and a first replay")
+    batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out, each_from_input=True)
     log("batch64: graph steps")
     rc, info = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out,
                               each_from_input=True)
     graph_ms = info["ms"] / steps
+    upd_threads, dots_group = batch.tuned()
+    # the same steps with the work-list form of the tiled multigrid passes (a
+    # grid of one workgroup per CU taking tiles from atomic counters)
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    batch.set_worklist(ncu)
+    log("batch64: work-list form, eager and graph steps")
+    _, info_we = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=False, stream=s, out=out,
+                                each_from_input=True)
+    batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out, each_from_input=True)
+    _, info_wg = batch.timestep(*zin, nsteps=steps, opts=opts, use_graph=True, stream=s, out=out,
+                                each_from_input=True)
+    worklist = dict(grid=ncu, eager_ms_per_step=info_we["ms"] / steps, graph_ms_per_step=info_wg["ms"] / steps)
+    batch.set_worklist(0)
     log("batch64: fp64 eager step")
     o64 = chns.default_opts(rtol=1e-8, precision=chns.F64, restart=BATCH_RESTART, maxiter=120, **BATCH_MG)
     rc_f, info_f = batch.timestep(*zin, nsteps=1, opts=o64, use_graph=False, stream=s, out=out)
@@ -321,7 +371,15 @@ def batch_section(chns, steps):
         seq_its += inf[0]["iters"]
     for c in ctxs.values():
         c.close()
-    return dict(workload=f"batch64: 64 CH + AC instances, sizes {sorted(set(sizes))} "
+    return dict(baseline_config="64 independent coupled-step instances, sizes from {64..512}^2, log-uniform "
+                                "parameters, FP32 preconditioner in FP64 FGMRES, one persistent launch, "
+                                "hipGraph-captured over 10 steps, tile and slice parameters from the autotuner",
+                as_run=f"{steps} steps captured in one hipGraph and replayed; every step solves the seeded "
+                       "first-step systems (the explicit potential term limits the stable tau, see the 1024^2 "
+                       "workload); one launch per stage over all instances (the persistent variant is measured "
+                       "separately); autotuned smoothing shapes per level and Gram-Schmidt shapes",
+                tuned_update_threads=upd_threads, tuned_dots_group=dots_group, worklist_form=worklist,
+                workload=f"batch64: 64 CH + AC instances, sizes {sorted(set(sizes))} "
                          f"({Ntot} nodes, {3 * Ntot} unknowns), log-uniform eps, tau, mobility, "
                          f"evaporation rate; FP32 V({BATCH_MG['mg_pre']},{BATCH_MG['mg_post']}) multigrid in FP64 "
                          f"FGMRES({BATCH_RESTART}), rtol 1e-8",
@@ -392,13 +450,26 @@ def adjoint_section(chns):
         res[name] = dict(loss=float(L.detach()), grad=theta.grad.tolist(), forward_ms=(t1 - t0) * 1e3,
                          backward_ms=(t2 - t1) * 1e3)
     log("adjoint128: central differences")
-    fd = []
-    for j in range(3):
-        h = 1e-6
-        tp, tm = list(th0), list(th0)
-        tp[j] += h
-        tm[j] -= h
-        fd.append((loss_at(tp, tight) - loss_at(tm, tight)) / (2 * h))
+
+    def central(opts, h=1e-6):
+        out = []
+        for j in range(3):
+            tp, tm = list(th0), list(th0)
+            tp[j] += h
+            tm[j] -= h
+            out.append((loss_at(tp, opts) - loss_at(tm, opts)) / (2 * h))
+        return out
+    fd = central(tight)
+    # the quotient's noise floor: the loss carries the forward solves' error
+    # (rtol 1e-13), which the quotient divides by 2h; estimated by the change of
+    # the loss and of the quotient when the solves are tightened to 1e-14
+    tighter = chns.default_opts(rtol=1e-14, precision=chns.F64, maxiter=6000)
+    try:
+        fd_t = central(tighter)
+        dL = abs(loss_at(th0, tight) - loss_at(th0, tighter))
+    except chns.ChnsError as e:  # 1e-14 below this system's residual floor
+        log(f"adjoint128: solves at rtol 1e-14 did not converge ({e}); no noise-floor estimate")
+        fd_t, dL = None, None
     # fourth-order differences with relative steps 1e-3 (truncation O(h^4)):
     # the evaporation-rate derivative is ~1e-10, so with h = 1e-6 the
     # difference quotient is limited by the rounding of L itself
@@ -408,16 +479,25 @@ def adjoint_section(chns):
         at = lambda k: loss_at([th0[i] + (k * h if i == j else 0.0) for i in range(3)], tight)
         fd4.append((-at(2) + 8 * at(1) - 8 * at(-1) + at(-2)) / (12 * h))
     L_ref = loss_at(ref, tight)
+    floor = None if dL is None else [2 * dL / (2 * 1e-6) / abs(b) for b in fd]  # relative, per parameter
     for name in ("mixed", "fp64"):
         g = res[name]["grad"]
         res[name]["rel_err_vs_fd"] = [abs(a - b) / abs(b) for a, b in zip(g, fd)]
+        res[name]["rel_err_vs_fd_rtol1e-14"] = None if fd_t is None else [abs(a - b) / abs(b)
+                                                                          for a, b in zip(g, fd_t)]
         res[name]["rel_err_vs_fd4"] = [abs(a - b) / abs(b) for a, b in zip(g, fd4)]
     ctx.close()
     return dict(workload=f"adjoint128: ternary CH + AC + Oseen, periodic {n}x{n}, {steps} steps at "
                          f"tau {cfg['tau']} (the stated 1e-3 diverges with the explicit potential), "
                          f"checkpoint every {K}; loss = 1/2 sum_i |phi_i^N - target_i|_M^2, target from "
                          f"theta_ref = {ref}; gradient at theta0 = {th0}",
-                theta0=list(th0), fd_grad=fd, fd_step=1e-6, fd4_grad=fd4, fd4_rel_step=1e-3,
+                baseline_config="ternary CH-AC-NS, 128x128, 50 steps at tau 1e-3, checkpoint every 10, "
+                                "gradients vs central differences (h 1e-6) and the CPU FP64 gradient",
+                as_run="50 steps at tau 3e-6: at tau 1e-3 the explicit potential term makes the scheme blow up "
+                       "within 3 steps (CPU, direct solves: tests/test_oracle_step.py::"
+                       "test_explicit_potential_limits_the_time_step)",
+                theta0=list(th0), fd_grad=fd, fd_grad_rtol1e_14=fd_t, fd_step=1e-6,
+                loss_change_rtol_1e13_to_1e14=dL, fd_noise_floor_rel=floor, fd4_grad=fd4, fd4_rel_step=1e-3,
                 loss_at_ref=L_ref, **res)
 
 
@@ -457,6 +537,24 @@ def cpu_adjoint_reference(chns, n=16, steps=10):
     return dict(sample=f"{n}x{n}, {steps} steps, adjoint128 parameters, oracle FP64 direct solves",
                 oracle_grad=list(g), gpu_grad=gg, oracle_loss=L, gpu_loss=float(Lg.detach()),
                 rel_err=[abs(a - b) / abs(b) for a, b in zip(gg, g)], oracle_s=cpu_s, cores=1)
+
+
+def oracle_exact(cfg, n, st0, taus):
+    """CPU leg: the oracle's exact solve (one 2x2 solve per Fourier mode) of the
+    first step at each tau: {tau: (phi, mu, Phi)}."""
+    from oracle import potential as pot, solvers
+    from oracle.systems import Params
+    phi0, Phi0 = st0["phi"][0], st0["Phi_v"]
+    Kh, Mh = solvers.p1_symbols(n)
+    Mx = lambda v: np.real(np.fft.ifft2(Mh * np.fft.fft2(v.reshape(n, n)))).ravel()
+    fp, fv = pot.dfdphi_bin(phi0, Phi0), pot.dfdPhi_bin(phi0, Phi0)
+    out = {}
+    for tau in taus:
+        prm = Params(eps=cfg["eps"], tau=tau, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+        ph, mu = solvers.fft_ch_solve(n, prm, Mx(phi0), -(prm.tau * prm.gamma / prm.beta) * Mx(fp))
+        Ph = solvers.fft_ac_solve(n, prm, Mx(Phi0) - prm.tau * prm.gamma_v * Mx(fv))
+        out[tau] = (ph, mu, Ph)
+    return out
 
 
 def oracle_errors(cfg, n, st0, sweep, sweep_fields):
@@ -541,6 +639,24 @@ def main():
             rel_res_ch=max(i[0]["res_true"] / i[0]["bnorm"] for i in infos),
             mass_phi_rel_change=(d1[0] - d0[0]) / d0[0], mass_Phi_v=[d0[3], d1[3]],
             energy=[d0[4], d1[4]])
+    # the same steps with a cold rate predictor: chns_set_params (untimed)
+    # before each step makes FGMRES forget the previous solve's reduction rate
+    for name, prec in (("mixed", chns.MIXED), ("fp64", chns.F64)):
+        if name not in res:
+            continue
+        opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, **MG)
+        walls = []
+        for _ in range(args.steps):
+            ctx.set_params(**p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.timestep(f_in, f_out, 1, opts)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+        res[name]["ms_per_step_cold_predictor"] = float(np.mean(walls))
+    traj = None
+    if not args.no_trajectory and "mixed" in forms:
+        traj = trajectory_section(chns, ctx, st0, p, args)
     kern = {}
     if not args.no_ledger and "mixed" in forms:
         log("kernels: ledger passes (the timed steps again, one kernel class per pass)")
@@ -550,22 +666,46 @@ def main():
     probe = None if args.no_copy_probe else copy_probe()
 
     sweep, sweep_fields = [], {}
+    exact = None
+    if not args.no_sweep and not args.no_cpu:
+        log("cpu leg: the oracle's exact solves of the swept steps")
+        exact = oracle_exact(cfg, n, st0, cfg["tau_sweep"])
     if not args.no_sweep:
         for tau in cfg["tau_sweep"]:
             log(f"sweep: tau {tau}")
             ctx.set_params(**dict(p, tau=tau))
             row = dict(tau=tau)
             for name, prec in (("fp64", chns.F64), ("mixed", chns.MIXED)):
-                opts = chns.default_opts(rtol=1e-8, precision=prec, restart=args.restart, maxiter=2000, **MG)
-                f = fresh()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                rc, inf = ctx.timestep(f, f, 1, opts)
-                torch.cuda.synchronize()
-                wall = (time.perf_counter() - t0) * 1e3
-                sweep_fields[(tau, name)] = {k: v.cpu().numpy() for k, v in fields.items()}
-                row[name] = dict(ms_to_1e8=wall, ch_iters=inf[0]["iters"], ac_iters=inf[1]["iters"],
+                def timed_step(rtol):
+                    opts = chns.default_opts(rtol=rtol, precision=prec, restart=args.restart, maxiter=2000,
+                                             **MG)
+                    ctx.timestep(f_in, f_out, 1, opts)  # warm (the rate history of this system)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    rc, inf = ctx.timestep(f_in, f_out, 1, opts)
+                    torch.cuda.synchronize()
+                    return (time.perf_counter() - t0) * 1e3, inf
+                wall, inf = timed_step(1e-8)
+                sweep_fields[(tau, name)] = {"phi": f_out._keep[0][0].cpu().numpy(),
+                                             "mu": f_out._keep[1][0].cpu().numpy(),
+                                             "Phi": f_out._keep[2].cpu().numpy()}
+                row[name] = dict(ms_to_rres_1e8=wall, ch_iters=inf[0]["iters"], ac_iters=inf[1]["iters"],
                                  converged=bool(inf[0]["converged"] and inf[1]["converged"]))
+                if exact is not None:
+                    # time to a forward error <= 1e-8 in every field: the loosest
+                    # tolerance of 1e-8 ... 1e-12 whose result meets it
+                    ex = exact[tau]
+                    for rtol in (1e-8, 1e-9, 1e-10, 1e-11, 1e-12):
+                        w, inf_r = timed_step(rtol)
+                        got = (f_out._keep[0][0].cpu().numpy(), f_out._keep[1][0].cpu().numpy(),
+                               f_out._keep[2].cpu().numpy())
+                        err = max(float(np.linalg.norm(g - e) / np.linalg.norm(e)) for g, e in zip(got, ex))
+                        if err <= 1e-8:
+                            row[name].update(ms_to_err_1e8=w, rtol_for_err_1e8=rtol, err_at_that_rtol=err,
+                                             ch_iters_for_err_1e8=inf_r[0]["iters"])
+                            break
+                    else:
+                        row[name].update(ms_to_err_1e8=None, rtol_for_err_1e8=None)
             sweep.append(row)
         ctx.set_params(**p)
     if args.dry_steps > 0:
@@ -585,13 +725,11 @@ def main():
             with threadpool_limits(1):
                 adj["cpu_reference"] = cpu_adjoint_reference(chns)
 
-    # roofline kernel: the single kernel with the largest total time in the
-    # rocprofv3 statistics of this run (profiles/): the Gram-Schmidt update
-    # pass; the fused CH operator + dot pass is one kernel per step index j and
-    # the multigrid passes one per mode and level (their ledger figures are in
-    # "kernels")
-    dom = chns.KERNEL_NAMES[chns.KERNEL_DCGS_UPDATE]
-    kd = kern.get(dom)
+    # roofline kernel: the ledger class with the largest time per step (the
+    # finest-level multigrid passes, four modes of one kernel); the others'
+    # figures are in "kernels"
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"]) if kern else None
+    kd = kern.get(dom) if dom else None
     # the value is the mixed form's unless only FP64 ran (--forms "" for runs of the other sections only)
     head = res.get("mixed") or res.get("fp64") or {"value": None, "ms_per_step": None}
     line = {
@@ -611,7 +749,15 @@ def main():
                                f"{3 * N} unknowns), eps {cfg['eps']}, tau {args.tau}, FGMRES({args.restart}) "
                                f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) block preconditioner (hierarchies cut "
                                f"at rho <= {MG['mg_rho_cut']}, {MG['mg_coarse']} coarse steps)",
-                   "n": n, "tau": args.tau, "restart": args.restart},
+                   "n": n, "tau": args.tau, "restart": args.restart,
+                   "baseline_config": "mixed-precision form vs FP64, 1024x1024 P1 CH + AC, eps 0.005, tau swept "
+                                      "over 1e-5 ... 1e-2, FP32 preconditioner sweeps in FP64 refinement to 1e-8",
+                   "as_run": f"timed: {args.steps} steps at tau {args.tau}, each re-solving the seeded first step "
+                             "(the explicit potential term makes longer runs at this tau blow up: "
+                             "tests/test_oracle_step.py::test_explicit_potential_limits_the_time_step), with the "
+                             "solver's rate predictor warm and (ms_per_step_cold_predictor) cold; a real 10-step "
+                             "trajectory at tau 1e-5 ('trajectory'); one step per swept tau with the error against "
+                             "the exact Fourier solve and the time to a forward error <= 1e-8 ('sweep')"},
         "roofline": None if kd is None else {
             "bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": kd["frac"], "traffic": TRAFFIC.get(dom),
@@ -625,6 +771,7 @@ def main():
                     for name, f in kern.items()},
         "copy_probe": probe,
         "sweep": sweep,
+        "trajectory": traj,
         "dry256": dry,
         "batch64": bat,
         "adjoint128": adj,

@@ -182,8 +182,11 @@ CHNS_API int chns_create(const chns_mesh* mesh, const chns_params* params, chns_
 CHNS_API int chns_destroy(chns_ctx* ctx);
 
 /* Replace the parameters and re-form every parameter-dependent operator
- * (on all multigrid levels).  Asynchronous on the context's internal stream
- * order; synchronising on return. */
+ * (on all multigrid levels).  Also forgets the solver's history: FGMRES
+ * predicts from the mean residual reduction per step of the block's last
+ * solve when the next residual estimate may meet the tolerance (and reads it
+ * before enqueuing more work); after chns_set_params the first solve of each
+ * block runs without that prediction.  Synchronising on return. */
 CHNS_API int chns_set_params(chns_ctx* ctx, const chns_params* params);
 
 /* Per-step assembly (paper: C(v^k) of eq. (CH_linear); J(w^k) and the PCD
@@ -419,12 +422,26 @@ CHNS_API int chns_batch_timestep(chns_batch* b, const double* in_phi, const doub
                                  int32_t nsteps, int32_t each_from_input,
                                  const chns_solve_opts* opts, int32_t use_graph, int32_t* h_iters,
                                  int32_t* h_conv, double* h_ms, void* stream);
-/* Autotuner: time the batched smoothing kernel on every level in launch shapes
- * rows-per-thread {1, 2, 4} x workgroup {128, 256, 512, 1024} and keep the
- * fastest per level.  cache_path (may be NULL): a text file "gfx950" followed
- * by "rows rpt block" lines, read when present (cached levels are not timed)
- * and rewritten with the chosen shapes.  Synchronising. */
+/* Autotuner (the batched form's launch shapes): time the batched smoothing
+ * kernel on every level in rows-per-thread {1, 2, 4} x workgroup {128, 256,
+ * 512, 1024}, the Gram-Schmidt update pass with 256, 512 or 1024 threads per
+ * 1024-row chunk and the Gram-Schmidt dot pass with 8 or 16 basis vectors per
+ * launch, on this batch's stacked sizes, and keep the fastest of each.
+ * cache_path (may be NULL): a text file "gfx950" followed by "level rows rpt
+ * block", "update rows threads" and "dots rows group" lines, read when
+ * present (cached entries are not timed) and rewritten with the choices.
+ * Changes the arithmetic order of the Gram-Schmidt reductions only.  Uses the
+ * Krylov workspace: do not call it while a step runs.  Synchronising. */
 CHNS_API int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream);
+/* Work-list form of the batched multigrid passes: with grid > 0 every
+ * tiled pass (one per level and role) launches a fixed grid of at most `grid`
+ * workgroups (at least 8) that take the tiles of all instances from per-XCD
+ * atomic counters, instead of one workgroup per tile (grid 0, the default).
+ * Same arithmetic, same results.  Synchronising when the form changes. */
+CHNS_API int chns_batch_set_worklist(chns_batch* b, int32_t grid);
+/* The Gram-Schmidt launch shapes in use: update-pass threads per chunk and
+ * dot-pass vectors per launch (host outputs, either may be NULL). */
+CHNS_API int chns_batch_tuned(const chns_batch* b, int32_t* h_update_threads, int32_t* h_dots_group);
 /* Arnoldi-step budgets of the graph mode for the CH and the AC block (0: use
  * maxiter), typically the largest iteration counts of an eager step plus a
  * margin.  Changing them makes the next graph-mode call capture anew. */

@@ -36,7 +36,8 @@ EXPORTS = [
     "chns_timestep", "chns_last_error",
     "chns_assemble_transposed", "chns_timestep_adjoint", "chns_ledger_start", "chns_ledger_read",
     "chns_batch_create", "chns_batch_destroy", "chns_batch_offsets", "chns_batch_timestep",
-    "chns_batch_tune", "chns_batch_set_graph_budget", "chns_batch_precond_apply",
+    "chns_batch_tune", "chns_batch_tuned", "chns_batch_set_worklist", "chns_batch_set_graph_budget",
+    "chns_batch_precond_apply",
     "chns_batch_last_error",
 ]
 
@@ -156,6 +157,8 @@ def lib():
     L.chns_batch_timestep.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, ct.POINTER(SolveOpts),
                                       i32, vp, vp, ct.POINTER(ct.c_double), vp]
     L.chns_batch_tune.argtypes = [vp, ct.c_char_p, vp]
+    L.chns_batch_tuned.argtypes = [vp, vp, vp]
+    L.chns_batch_set_worklist.argtypes = [vp, i32]
     L.chns_batch_set_graph_budget.argtypes = [vp, i32, i32]
     L.chns_batch_precond_apply.argtypes = [vp, i32, vp, vp, ct.POINTER(SolveOpts), vp]
     L.chns_batch_last_error.argtypes = [vp]
@@ -423,6 +426,16 @@ class Batch:
     def tune(self, cache_path=None, stream=None):
         s = ct.c_void_p(stream.cuda_stream) if stream is not None else _stream()
         self._check(self.L.chns_batch_tune(self.h, cache_path.encode() if cache_path else None, s))
+
+    def set_worklist(self, grid):
+        """Work-list form of the tiled multigrid passes (grid workgroups; 0: one per tile)."""
+        self._check(self.L.chns_batch_set_worklist(self.h, int(grid)))
+
+    def tuned(self):
+        """(update-pass threads per chunk, dot-pass vectors per launch) in use."""
+        a, g = ct.c_int32(), ct.c_int32()
+        self._check(self.L.chns_batch_tuned(self.h, ct.byref(a), ct.byref(g)))
+        return a.value, g.value
 
     def set_graph_budget(self, ch_iters, ac_iters):
         """Arnoldi-step budgets of the graph mode (0: maxiter)."""

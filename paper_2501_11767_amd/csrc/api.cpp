@@ -1883,6 +1883,8 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
   if (!c) return CHNS_EINVAL;
   TRY(check_params(c, p));
   c->prm = *p;
+  // the residual reduction rates of earlier solves belong to other systems
+  for (double& r : c->kr.rate) r = -1.0;
   if (c->ternary) TRY(assemble_sym_stiffness(c, nullptr));
   TRY(form_operators(c, nullptr));
   HIPCHK(c, hipDeviceSynchronize());

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -33,6 +34,7 @@ constexpr int BMAX_RESTART = 64;
 constexpr int64_t KRYLOV_PAD = 640;  // doubles between consecutive basis vectors (HBM channel spread)
 constexpr size_t GRAPH_MAX_NODES = 100000;  // refuse to instantiate larger step graphs
 constexpr int GRAPH_CACHE = 4;              // step graphs kept per batch
+constexpr int GRAPH_STEPS = 10;             // time steps captured in one graph
 constexpr int EAGER_CHECK = 4;              // eager mode: Arnoldi steps between activity readbacks
 
 struct GraphEntry {
@@ -133,6 +135,13 @@ struct chns_batch {
   bool tiled = false;
   TailArgs<float>* tails32[NOPS] = {};
   TailArgs<double>* tails64[NOPS] = {};
+  // work-list form of the tiled multigrid passes: grid (0: one workgroup per
+  // tile) and the per-XCD tile counters
+  int wl_grid = 0;
+  int* wl_ctr = nullptr;
+  // autotuned launch shapes of the Gram-Schmidt passes
+  int upd_threads = 256;  // workgroup size of the update pass per 1024-row chunk
+  int dots_group = 16;    // basis vectors per dot-pass launch
   std::vector<void*> allocs;
   // device allocator of the caller (chns_batch_create), or hipMalloc/hipFree when NULL
   chns_alloc_fn alloc = nullptr;
@@ -690,7 +699,7 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
     a.xs = xs;
     a.cc1 = BSel<T>::cc(L, op, 0);
     a.cc2 = BSel<T>::cc(L, op, 1);
-    bvtile<T>(TILE_ZERO, L.ntzero[op], a, s);
+    bvtile<T>(TILE_ZERO, L.ntzero[op], a, s, b->wl_grid, b->wl_ctr);
   }
   if (L.ntail[op] > 0) bvtail<T>(L.ntail[op], btails<T>(b, op), L.tail_idx[op], act, rhs, x, s);
   if (L.ntdown[op] == 0) return;
@@ -706,7 +715,7 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
   set_cheb<T>(a, o.mg_lmax, o.mg_pre);
   a.x = BSel<T>::t(L);
   a.bc = BSel<T>::b(G);
-  bvtile<T>(TILE_DOWN, L.ntdown[op], a, s);
+  bvtile<T>(TILE_DOWN, L.ntdown[op], a, s, b->wl_grid, b->wl_ctr);
   bvcycle_tiled<T>(b, op, l + 1, BSel<T>::b(G), BSel<T>::x(G), act, o, s);
   set_cheb<T>(a, o.mg_lmax, o.mg_post);
   a.xin = BSel<T>::t(L);
@@ -716,7 +725,7 @@ void bvcycle_tiled(chns_batch* b, int op, int l, const T* rhs, T* x, const int* 
   a.xs = xs;
   a.bc = nullptr;
   a.mval = mval;  // when given (level 0), the up pass writes M times the result
-  bvtile<T>(mval ? TILE_UPM : TILE_UP, L.ntdown[op], a, s);
+  bvtile<T>(mval ? TILE_UPM : TILE_UP, L.ntdown[op], a, s, b->wl_grid, b->wl_ctr);
 }
 
 template <typename T>
@@ -862,10 +871,10 @@ int bfgmres(chns_batch* b, int block, const double* rhs, double* x, const chns_s
       bprecond(b, block, vj, vs, zj, act, o, s);
       bapply(b, block, zj, vn, 1.0, 0.0, act, s);
       // DCGS2: one dot pass and one update pass over each instance's basis
-      bdcgs_dots(n, V, ld, j, b->part, b->cinst, act, vs, s);
+      bdcgs_dots(n, V, ld, j, b->part, b->cinst, act, vs, s, b->dots_group);
       bslot_reduce(b->count, nchunk, 2 * j + 3, b->part, b->cr, half, b->red, rs, act, s);
       bdcgs_coef(b->count, j, m, b->red, rs, b->H, b->coef, cstride, act, s);
-      bdcgs_update(n, V, ld, j, b->coef, cstride, b->part2, b->cinst, act, vs, s);
+      bdcgs_update(n, V, ld, j, b->coef, cstride, b->part2, b->cinst, act, vs, s, b->upd_threads);
       bdcgs_finish(b->count, nchunk, b->part2, b->cr, half, j, m, b->H, b->HR, b->cs, b->sn, b->g,
                    b->gp, b->inv, b->tol, b->active, b->kcols, b->iters[bi], s);
       if (eager && (j + 1) % EAGER_CHECK == 0 && j + 1 < m) {
@@ -1028,6 +1037,8 @@ int bbuild(chns_batch* b) {
     BTRY(balloc(b, &b->tails32[op], cnt));
     BTRY(balloc(b, &b->tails64[op], cnt));
   }
+  BTRY(balloc(b, &b->wl_ctr, 16));
+  BCHK(b, hipMemset(b->wl_ctr, 0, 16 * sizeof(int)));
   for (double** v : {&b->inv, &b->nrm, &b->tol}) BTRY(balloc(b, v, cnt));
   for (int** v : {&b->active, &b->kcols, &b->iters[0], &b->iters[1], &b->conv[0], &b->conv[1]})
     BTRY(balloc(b, v, cnt));
@@ -1084,16 +1095,18 @@ size_t step_launches(const chns_batch* b, const chns_solve_opts& o) {
   return total;
 }
 
-// Executable graph of one step from (phi, mu, Phi) into the output fields,
-// captured on first use and cached by pointers, stream and options.
+// Executable graph of `ksteps` consecutive steps, captured on first use and
+// cached by pointers, stream, options and step count: the first step reads
+// (phi, mu, Phi), each later one the previous step's output (or the inputs
+// again when each_from_input), every step writes the output fields.
 int step_graph(chns_batch* b, const double* phi, const double* mu, const double* Phi, double* ophi,
-               double* omu, double* oPhi, const chns_solve_opts& o, hipStream_t s,
-               hipGraphExec_t* out) {
+               double* omu, double* oPhi, int ksteps, bool each_from_input, const chns_solve_opts& o,
+               hipStream_t s, hipGraphExec_t* out) {
   char key[512];
-  std::snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%p/%p/%s/%d/%d/%d/%.17g/%.17g/%d/%d", (const void*)phi,
+  std::snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%p/%p/%s/%d/%d/%d/%.17g/%.17g/%d/%d/%d/%d", (const void*)phi,
                 (const void*)mu, (const void*)Phi, (void*)ophi, (void*)omu, (void*)oPhi, (void*)s,
                 b->opts_key.c_str(), o.restart, o.maxiter, o.precision, o.rtol, o.atol, b->budget[0],
-                b->budget[1]);
+                b->budget[1], ksteps, each_from_input ? 1 : 0);
   for (size_t i = 0; i < b->graphs.size(); ++i)
     if (b->graphs[i].key == key) {  // most recently used goes last
       GraphEntry g = b->graphs[i];
@@ -1102,13 +1115,17 @@ int step_graph(chns_batch* b, const double* phi, const double* mu, const double*
       *out = g.exec;
       return CHNS_OK;
     }
-  const size_t expect = step_launches(b, o);
+  const size_t expect = step_launches(b, o) * size_t(ksteps);
   if (expect > GRAPH_MAX_NODES)
     return fail(b, CHNS_EUNSUPPORTED,
-                "a step graph of " + std::to_string(expect) + " kernels exceeds " +
+                "a graph of " + std::to_string(expect) + " kernels exceeds " +
                     std::to_string(GRAPH_MAX_NODES) + "; set a smaller graph budget or maxiter");
   BCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  const int rc = bstep(b, phi, mu, Phi, ophi, omu, oPhi, o, false, s);
+  int rc = CHNS_OK;
+  for (int k = 0; k < ksteps && rc >= 0; ++k) {
+    const bool from_in = k == 0 || each_from_input;
+    rc = bstep(b, from_in ? phi : ophi, from_in ? mu : omu, from_in ? Phi : oPhi, ophi, omu, oPhi, o, false, s);
+  }
   hipGraph_t gr = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &gr);
   if (rc < 0) {
@@ -1247,19 +1264,32 @@ int chns_batch_timestep(chns_batch* b, const double* in_phi, const double* in_mu
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (use_graph && !s) return fail(b, CHNS_EINVAL, "graph capture needs a non-default stream");
   BTRY(prepare_cycles(b, *opts));
-  // step variants: 0 reads the input fields, 1 continues from the outputs
-  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  // graph mode: graphs of G = min(nsteps, GRAPH_STEPS) steps (fewer if a
+  // graph would exceed the node limit), the first reading the inputs, the
+  // others continuing from the outputs, and one more graph for a remainder
+  hipGraphExec_t first = nullptr, cont = nullptr, rest = nullptr;
+  int G = 1, full = 0, rem = 0;
   if (use_graph) {
-    BTRY(step_graph(b, in_phi, in_mu, in_Phi, d_phi, d_mu, d_Phi, *opts, s, &ex[0]));
-    if (nsteps > 1 && !each_from_input)
-      BTRY(step_graph(b, d_phi, d_mu, d_Phi, d_phi, d_mu, d_Phi, *opts, s, &ex[1]));
+    const size_t per = std::max<size_t>(step_launches(b, *opts), 1);
+    G = int(std::min<size_t>({size_t(nsteps), size_t(GRAPH_STEPS), std::max<size_t>(GRAPH_MAX_NODES / per, 1)}));
+    full = nsteps / G;
+    rem = nsteps - full * G;
+    const bool efi = each_from_input != 0;
+    BTRY(step_graph(b, in_phi, in_mu, in_Phi, d_phi, d_mu, d_Phi, G, efi, *opts, s, &first));
+    if (full > 1)
+      BTRY(efi ? step_graph(b, in_phi, in_mu, in_Phi, d_phi, d_mu, d_Phi, G, true, *opts, s, &cont)
+               : step_graph(b, d_phi, d_mu, d_Phi, d_phi, d_mu, d_Phi, G, false, *opts, s, &cont));
+    if (rem > 0)
+      BTRY(efi ? step_graph(b, in_phi, in_mu, in_Phi, d_phi, d_mu, d_Phi, rem, true, *opts, s, &rest)
+               : step_graph(b, d_phi, d_mu, d_Phi, d_phi, d_mu, d_Phi, rem, false, *opts, s, &rest));
   }
   BCHK(b, hipEventRecord(b->ev0, s));
-  for (int k = 0; k < nsteps; ++k) {
-    const bool from_in = (k == 0) || each_from_input;
-    if (use_graph) {
-      BCHK(b, hipGraphLaunch(ex[from_in ? 0 : 1], s));
-    } else {
+  if (use_graph) {
+    for (int k = 0; k < full; ++k) BCHK(b, hipGraphLaunch(k == 0 ? first : cont, s));
+    if (rem > 0) BCHK(b, hipGraphLaunch(rest, s));
+  } else {
+    for (int k = 0; k < nsteps; ++k) {
+      const bool from_in = (k == 0) || each_from_input;
       BTRY(bstep(b, from_in ? in_phi : d_phi, from_in ? in_mu : d_mu, from_in ? in_Phi : d_Phi, d_phi,
                  d_mu, d_Phi, *opts, true, s));
     }
@@ -1290,17 +1320,32 @@ int chns_batch_timestep(chns_batch* b, const double* in_phi, const double* in_mu
 int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream) {
   if (!b) return CHNS_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // cache: one line per level "rows rpt block"
-  std::map<int, std::pair<int, int>> cache;
+  // cache lines: "level rows rpt block" (smoothing kernel per level size),
+  // "update threads" and "dots group" (Gram-Schmidt passes, keyed by the
+  // batch's stacked size: "update rows threads", "dots rows group")
+  std::map<int, std::pair<int, int>> cache, upd, dots;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
-      int rows, rpt, blk;
-      char arch[64];
-      if (std::fscanf(f, "%63s", arch) == 1 && std::string(arch) == "gfx950")
-        while (std::fscanf(f, "%d %d %d", &rows, &rpt, &blk) == 3) cache[rows] = {rpt, blk};
+      char arch[64], line[256];
+      if (std::fscanf(f, "%63s\n", arch) == 1 && std::string(arch) == "gfx950")
+        while (std::fgets(line, sizeof line, f)) {
+          int a, c, d;
+          if (std::sscanf(line, "level %d %d %d", &a, &c, &d) == 3) cache[a] = {c, d};
+          else if (std::sscanf(line, "update %d %d", &a, &c) == 2) upd[a] = {c, 0};
+          else if (std::sscanf(line, "dots %d %d", &a, &c) == 2) dots[a] = {c, 0};
+        }
       std::fclose(f);
     }
   }
+  auto time_ms = [&](auto&& launch, int reps, float& ms) -> int {
+    for (int w = 0; w < 2; ++w) launch();
+    BCHK(b, hipEventRecord(b->ev0, s));
+    for (int w = 0; w < reps; ++w) launch();
+    BCHK(b, hipEventRecord(b->ev1, s));
+    BCHK(b, hipEventSynchronize(b->ev1));
+    BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    return CHNS_OK;
+  };
   const int rpts[3] = {1, 2, 4};
   const int blocks[4] = {128, 256, 512, 1024};
   for (auto& L : b->lv) {
@@ -1317,17 +1362,11 @@ int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream) {
         BStencil st = L.st;
         st.rpt = rpt;
         st.block = blk;
-        for (int w = 0; w < 2; ++w)
-          bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
-                          nullptr, nullptr, L.t32, s);
-        BCHK(b, hipEventRecord(b->ev0, s));
-        for (int w = 0; w < 10; ++w)
-          bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
-                          nullptr, nullptr, L.t32, s);
-        BCHK(b, hipEventRecord(b->ev1, s));
-        BCHK(b, hipEventSynchronize(b->ev1));
         float ms = 0.f;
-        BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        BTRY(time_ms([&] {
+          bstencil<float>(st, L.v32[1], 2, L.x32, L.b32, L.d32[1], L.dd32, 0.5f, 0.5f, nullptr, nullptr,
+                          nullptr, nullptr, L.t32, s);
+        }, 10, ms));
         if (ms < best) {
           best = ms;
           br = rpt;
@@ -1338,14 +1377,74 @@ int chns_batch_tune(chns_batch* b, const char* cache_path, void* stream) {
     L.st.block = bb;
     cache[L.nrows] = {br, bb};
   }
+  // Gram-Schmidt passes on the stacked CH vectors (2 Ntot rows), at a
+  // mid-cycle step: the update pass's workgroup per chunk, the dot pass's
+  // vectors per launch.  The workspace holds no solve yet: its contents are
+  // only timed, and the coefficients are zeroed first.
+  const int64_t n2 = 2 * b->Ntot;
+  const int key = int(std::min<int64_t>(n2, INT32_MAX));
+  const int cstride = 2 * BMAX_RESTART + 2;
+  BCHK(b, hipMemsetAsync(b->coef, 0, size_t(b->count) * cstride * sizeof(double), s));
+  if (auto it = upd.find(key); it != upd.end()) {
+    b->upd_threads = it->second.first;
+  } else {
+    float best = 1e30f;
+    for (int nt : {256, 512, 1024}) {
+      float ms = 0.f;
+      BTRY(time_ms([&] {
+        bdcgs_update(n2, b->V, b->ld, 16, b->coef, cstride, b->part2, b->cinst, nullptr, nullptr, s, nt);
+      }, 5, ms));
+      if (ms < best) {
+        best = ms;
+        b->upd_threads = nt;
+      }
+    }
+  }
+  if (auto it = dots.find(key); it != dots.end()) {
+    b->dots_group = it->second.first;
+  } else {
+    float best = 1e30f;
+    for (int g : {8, 16}) {
+      float ms = 0.f;
+      BTRY(time_ms([&] { bdcgs_dots(n2, b->V, b->ld, 32, b->part, b->cinst, nullptr, nullptr, s, g); }, 5, ms));
+      if (ms < best) {
+        best = ms;
+        b->dots_group = g;
+      }
+    }
+  }
+  upd[key] = {b->upd_threads, 0};
+  dots[key] = {b->dots_group, 0};
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "w")) {
       std::fprintf(f, "gfx950\n");
-      for (auto& e : cache) std::fprintf(f, "%d %d %d\n", e.first, e.second.first, e.second.second);
+      for (auto& e : cache) std::fprintf(f, "level %d %d %d\n", e.first, e.second.first, e.second.second);
+      for (auto& e : upd) std::fprintf(f, "update %d %d\n", e.first, e.second.first);
+      for (auto& e : dots) std::fprintf(f, "dots %d %d\n", e.first, e.second.first);
       std::fclose(f);
     }
   }
+  BCHK(b, hipStreamSynchronize(s));
   drop_graphs(b);  // launch shapes changed
+  return CHNS_OK;
+}
+
+int chns_batch_set_worklist(chns_batch* b, int32_t grid) {
+  if (!b) return CHNS_EINVAL;
+  if (grid < 0 || grid > 65536) return fail(b, CHNS_EINVAL, "work-list grid must be in 0..65536");
+  if (grid != b->wl_grid) {
+    BCHK(b, hipDeviceSynchronize());
+    drop_graphs(b);  // the captured launches have the old shape
+  }
+  b->wl_grid = grid;
+  return CHNS_OK;
+}
+
+// Launch shapes the autotuner chose (or the defaults).
+int chns_batch_tuned(const chns_batch* b, int32_t* h_update_threads, int32_t* h_dots_group) {
+  if (!b) return CHNS_EINVAL;
+  if (h_update_threads) *h_update_threads = b->upd_threads;
+  if (h_dots_group) *h_dots_group = b->dots_group;
   return CHNS_OK;
 }
 

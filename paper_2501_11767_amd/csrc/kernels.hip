@@ -12,6 +12,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "device_util.hpp"
@@ -419,6 +420,56 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_bvtile(BTileLaunch<T> a) {
                           a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile, xa, xb, a.b64 ? a.b64 + r : nullptr,
                           a.x64 ? a.x64 + r : nullptr, a.xs ? a.xs + t.inst : nullptr,
                           a.mval ? a.mval + r * W7 : nullptr);
+}
+
+// Work-list form of k_bvtile: a fixed grid (CUs x k workgroups, a multiple of
+// 8) instead of one workgroup per tile.  The tile list is cut into 8
+// contiguous ranges, one per XCD (workgroup b runs on XCD b mod 8, so a range
+// of neighbouring tiles shares that XCD's L2); the workgroups of XCD x take
+// tiles of range x from the atomic counter ctr[2x] until it runs past the
+// range, then count themselves in ctr[2x + 1]; the last one resets both for
+// the next launch.  Every workgroup leaves after at most (its range's size)
+// tiles, so the grid always drains.  The per-tile arithmetic is k_bvtile's.
+template <typename T, int MODE, int TT>
+__global__ __launch_bounds__(TileCfg<TT>::NTH) void k_bvtile_wl(BTileLaunch<T> a, int ntiles,
+                                                                 int* __restrict__ ctr) {
+  constexpr int WMAX = TT + 2 * TileCfg<TT>::HMAX;
+  __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
+  __shared__ T c1s[TILE_MAXSTEPS], c2s[TILE_MAXSTEPS];
+  __shared__ int tsh;
+  const int x = blockIdx.x & 7;
+  const int nwg = int(gridDim.x);
+  const int wg_x = nwg / 8 + (x < nwg % 8 ? 1 : 0);  // workgroups on XCD x (nwg >= 8)
+  const int lo = int(int64_t(x) * ntiles / 8), hi = int(int64_t(x + 1) * ntiles / 8);
+  for (;;) {
+    if (threadIdx.x == 0) tsh = lo + atomicAdd(&ctr[2 * x], 1);
+    __syncthreads();
+    const int ti = tsh;
+    __syncthreads();
+    if (ti >= hi) break;
+    const BTile t = a.tiles[ti];
+    if (a.act && !a.act[t.inst]) continue;
+    if (threadIdx.x < a.steps) {
+      const int k = threadIdx.x;
+      c1s[k] = a.cc1 ? a.cc1[k * a.count + t.inst] : a.c1[k];
+      c2s[k] = a.cc2 ? a.cc2[k * a.count + t.inst] : a.c2[k];
+    }
+    __syncthreads();
+    const int64_t r = t.roff, rc = t.croff;
+    vtile_body<T, MODE, TT>(t.side, a.steps, a.val + r * W7, a.dinv + r, a.b ? a.b + r : nullptr,
+                            a.xin ? a.xin + r : nullptr, a.e ? a.e + rc : nullptr, a.x ? a.x + r : nullptr,
+                            a.bc ? a.bc + rc : nullptr, c1s, c2s, t.tile, xa, xb, a.b64 ? a.b64 + r : nullptr,
+                            a.x64 ? a.x64 + r : nullptr, a.xs ? a.xs + t.inst : nullptr,
+                            a.mval ? a.mval + r * W7 : nullptr);
+    __syncthreads();  // the LDS buffers and coefficients are reused by the next tile
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&ctr[2 * x + 1], 1) == wg_x - 1) {  // the last of XCD x: every take is done
+      atomicExch(&ctr[2 * x], 0);
+      atomicExch(&ctr[2 * x + 1], 0);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ paired levels
@@ -2175,9 +2226,20 @@ int btile_count(int side) {
 }
 
 template <typename T>
-void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s) {
+void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s, int wl_grid, int* wl_ctr) {
   if (ntiles <= 0) return;
-  const dim3 g(ntiles), b(TILE_THREADS);
+  const dim3 b(TILE_THREADS);
+  if (wl_grid > 0 && wl_ctr) {
+    // work-list launch: at most wl_grid workgroups, at least 8 (one per XCD)
+    int g = std::min(ntiles, wl_grid);
+    g = std::max(8, (g + 7) / 8 * 8);
+    if (mode == TILE_ZERO) hipLaunchKernelGGL((k_bvtile_wl<T, TILE_ZERO, 32>), dim3(g), b, 0, s, a, ntiles, wl_ctr);
+    else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_bvtile_wl<T, TILE_DOWN, 32>), dim3(g), b, 0, s, a, ntiles, wl_ctr);
+    else if (mode == TILE_UPM) hipLaunchKernelGGL((k_bvtile_wl<T, TILE_UPM, 32>), dim3(g), b, 0, s, a, ntiles, wl_ctr);
+    else hipLaunchKernelGGL((k_bvtile_wl<T, TILE_UP, 32>), dim3(g), b, 0, s, a, ntiles, wl_ctr);
+    return;
+  }
+  const dim3 g(ntiles);
   if (mode == TILE_ZERO) hipLaunchKernelGGL((k_bvtile<T, TILE_ZERO, 32>), g, b, 0, s, a);
   else if (mode == TILE_DOWN) hipLaunchKernelGGL((k_bvtile<T, TILE_DOWN, 32>), g, b, 0, s, a);
   else if (mode == TILE_UPM) hipLaunchKernelGGL((k_bvtile<T, TILE_UPM, 32>), g, b, 0, s, a);
@@ -2492,8 +2554,8 @@ template void coarse_cheb<double, double>(const DSell&, const double*, const dou
                                           hipStream_t);
 template void coarse_cheb<float, float>(const DSell&, const float*, const float*, const float*,
                                         const ChebCoef<float>&, float*, hipStream_t);
-template void bvtile<double>(int, int, const BTileLaunch<double>&, hipStream_t);
-template void bvtile<float>(int, int, const BTileLaunch<float>&, hipStream_t);
+template void bvtile<double>(int, int, const BTileLaunch<double>&, hipStream_t, int, int*);
+template void bvtile<float>(int, int, const BTileLaunch<float>&, hipStream_t, int, int*);
 template void bvtail<double>(int, const TailArgs<double>*, const int*, const int*, const double*, double*,
                              hipStream_t);
 template void bvtail<float>(int, const TailArgs<float>*, const int*, const int*, const float*, float*,

@@ -239,8 +239,12 @@ struct BTileLaunch {
 };
 bool btile_fits(int mode, int side, int steps);
 int btile_count(int side);  // tiles of one instance level
+// wl_grid > 0 with wl_ctr (16 ints, zero between launches): the work-list
+// form, a grid of at most wl_grid workgroups taking tiles from per-XCD
+// atomic counters; else one workgroup per tile.
 template <typename T>
-void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s);
+void bvtile(int mode, int ntiles, const BTileLaunch<T>& a, hipStream_t s, int wl_grid = 0,
+            int* wl_ctr = nullptr);
 
 // CH block on [x1; x2] with value streams L = M + tau C, K, M (uniform P1):
 //   y1 = alpha (L x1 + c12 K x2) + beta u1,  y2 = alpha (c12 K x1 + c22 M x2) + beta u2

@@ -337,27 +337,30 @@ __global__ __launch_bounds__(64) void k_bdcgs_coef(int j, int m, const double* _
 // Update of one chunk with its instance's coefficients: w <- w - sum coef[j+i]
 // V_i - coef[2j] vt, vt <- (vt - sum coef[i] V_i) / r (j > 0); chunk partial
 // of |w'|^2.  vs (may be null): vt is V_j as stored times vs[inst].
-__global__ __launch_bounds__(BS) void k_bdcgs_update(double* __restrict__ V, int64_t ld, int j,
+// NT threads per 1024-row chunk (BCHUNK / NT rows each; the autotuner picks NT).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bdcgs_update(double* __restrict__ V, int64_t ld, int j,
                                                      const double* __restrict__ coef, int cstride,
                                                      double* __restrict__ nrm_part,
                                                      const int* __restrict__ cinst,
                                                      const int* __restrict__ act,
                                                      const double* __restrict__ vs) {
+  constexpr int RPT = BCHUNK / NT;
   const int c = blockIdx.x;
   const int inst = cinst[c];
   if (act && !act[inst]) return;
   const double sv = vs ? vs[inst] : 1.0;
   __shared__ double cl[2 * 64 + 2];
   __shared__ double sh[16];
-  for (int i = threadIdx.x; i < 2 * j + 2; i += BS) cl[i] = coef[int64_t(inst) * cstride + i];
+  for (int i = threadIdx.x; i < 2 * j + 2; i += NT) cl[i] = coef[int64_t(inst) * cstride + i];
   __syncthreads();
   double* vt = V + int64_t(j) * ld;
   double* w = V + int64_t(j + 1) * ld;
   const double inv = cl[2 * j + 1], wt = cl[2 * j];
   double acc = 0.0;
 #pragma unroll
-  for (int rr = 0; rr < RPC; ++rr) {
-    const int64_t r = int64_t(c) * BCHUNK + rr * BS + threadIdx.x;
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int64_t r = int64_t(c) * BCHUNK + rr * NT + threadIdx.x;
     const double t = vt[r] * sv;
     double wn = w[r] - wt * t, vn = t;
     int i = 0;
@@ -734,13 +737,19 @@ static void launch_bdots_last(int kk, int nchunk, const double* V, int64_t ld, i
 }
 
 void bdcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, const int* cinst,
-                const int* act, const double* vs, hipStream_t s) {
+                const int* act, const double* vs, hipStream_t s, int group) {
   const int nchunk = int(n / BCHUNK);
-  const int full = j / BDG, rem = j - full * BDG;
-  for (int g = 0; g < full; ++g)
-    hipLaunchKernelGGL((k_bdots<BDG, false>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g * BDG, part, cinst,
-                       act, vs);
-  launch_bdots_last(rem, nchunk, V, ld, j, full * BDG, part, cinst, act, vs, s);
+  const int bdg = group == 8 ? 8 : BDG;
+  const int full = j / bdg, rem = j - full * bdg;
+  for (int g = 0; g < full; ++g) {
+    if (bdg == 8)
+      hipLaunchKernelGGL((k_bdots<8, false>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g * bdg, part, cinst,
+                         act, vs);
+    else
+      hipLaunchKernelGGL((k_bdots<BDG, false>), dim3(nchunk), dim3(BS), 0, s, V, ld, j, g * bdg, part, cinst,
+                         act, vs);
+  }
+  launch_bdots_last(rem, nchunk, V, ld, j, full * bdg, part, cinst, act, vs, s);
 }
 
 void bslot_reduce(int count, int nchunk, int nslots, const double* part, const int* cr, int half,
@@ -755,9 +764,18 @@ void bdcgs_coef(int count, int j, int m, const double* red, int rs, double* H, d
 }
 
 void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, int cstride,
-                  double* nrm_part, const int* cinst, const int* act, const double* vs, hipStream_t s) {
-  hipLaunchKernelGGL(k_bdcgs_update, dim3(int(n / BCHUNK)), dim3(BS), 0, s, V, ld, j, coef, cstride,
-                     nrm_part, cinst, act, vs);
+                  double* nrm_part, const int* cinst, const int* act, const double* vs, hipStream_t s,
+                  int threads) {
+  const dim3 g(int(n / BCHUNK));
+  if (threads == 1024)
+    hipLaunchKernelGGL(k_bdcgs_update<1024>, g, dim3(1024), 0, s, V, ld, j, coef, cstride, nrm_part, cinst,
+                       act, vs);
+  else if (threads == 512)
+    hipLaunchKernelGGL(k_bdcgs_update<512>, g, dim3(512), 0, s, V, ld, j, coef, cstride, nrm_part, cinst,
+                       act, vs);
+  else
+    hipLaunchKernelGGL(k_bdcgs_update<BS>, g, dim3(BS), 0, s, V, ld, j, coef, cstride, nrm_part, cinst,
+                       act, vs);
 }
 
 void bdcgs_finish(int count, int nchunk, const double* part2, const int* cr, int half, int j, int m,

@@ -77,8 +77,9 @@ void bcombine(int64_t nslots, const int* sinst, const double* a, const double* A
 // vt.vt, vt.w, w.w go to part[slot * nchunk + c] (slots 2j + 3; chunks of
 // inactive instances skipped).
 // vs (may be null): V_j as stored times vs[inst] is the step's vector.
+// group: basis vectors per launch (8 or 16; the autotuner picks it).
 void bdcgs_dots(int64_t n, const double* V, int64_t ld, int j, double* part, const int* cinst,
-                const int* act, const double* vs, hipStream_t s);
+                const int* act, const double* vs, hipStream_t s, int group = 16);
 // red[i * rs + k] = slot k summed over instance i's chunks [cr[2i], cr[2i+1])
 // and, when half != 0, the same range shifted by half; active instances only.
 void bslot_reduce(int count, int nchunk, int nslots, const double* part, const int* cr, int half,
@@ -90,8 +91,10 @@ void bdcgs_coef(int count, int j, int m, const double* red, int rs, double* H, d
                 const int* act, hipStream_t s);
 // Per chunk: V_j <- its reorthogonalised, normalised form (j > 0), w <- w
 // projected out of the final basis; chunk partials of |w|^2 into nrm_part.
+// threads: workgroup size per 1024-row chunk (256, 512 or 1024; autotuned).
 void bdcgs_update(int64_t n, double* V, int64_t ld, int j, const double* coef, int cstride,
-                  double* nrm_part, const int* cinst, const int* act, const double* vs, hipStream_t s);
+                  double* nrm_part, const int* cinst, const int* act, const double* vs, hipStream_t s,
+                  int threads = 256);
 // Per active instance: h_{j+1,j} = |w|, final rotation of column j-1 into HR
 // and g, provisional rotation of column j into HR and gp, iteration count,
 // activity (estimate |gp_{j+1}| <= tol_i, |w| == 0 or non-finite: inactive with

@@ -240,3 +240,48 @@ def test_potential_derivatives_central_difference(seed):
     p = pot.interp(Phi)
     full = lambda s: (1 - p) * (3.5 * pp ** 2 * pn ** 2 + 0.3 * s ** 2) + p * (3.5 * pp ** 2 + 3.5 * pn ** 2 + 2 * s ** 2)
     assert np.allclose(pot.dfdphis_ter(ps, Phi), (full(ps + h) - full(ps - h)) / (2 * h), atol=1e-8)
+
+
+def test_explicit_potential_limits_the_time_step():
+    """The scheme takes the potential term explicitly (section "Spatial &
+    temporal discretization"), which is stable only for small tau (linearised,
+    modes grow spuriously once tau > 8 beta / (gamma f''^2)).  This is why the
+    workloads' timed steps re-solve the seeded first step and the
+    differentiation workload runs at tau = 3e-6: on the CPU, with direct
+    solves, the 1024^2 workload's parameters (eps = 0.005) on a 128^2 mesh
+    blow up within 8 steps at tau = 1e-4 and stay put over 20 steps at 1e-5,
+    and the differentiation workload's parameters (ternary, eps = 0.015,
+    mobility 2) at the stated tau = 1e-3 on a 32^2 mesh pass max|phi_p| = 10
+    within 3 steps, while tau = 3e-6 leaves the fields near their initial
+    values."""
+    import warnings
+    cfg = inputs.CONFIGS["chac1024"]
+    n = 128
+    ops = S.Operators(n)
+    runs = {}
+    for tau, steps in ((1e-4, 8), (1e-5, 20)):
+        prm = Params(eps=cfg["eps"], tau=tau, mobility=cfg["mobility"], evap_rate=cfg["evap_rate"])
+        st = S.initial_state(ops, prm, "ch_ac", inputs.initial_state(n, "ch_ac", cfg["mean"], cfg["seed"]))
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            for _ in range(steps):
+                st = S.step(ops, prm, "ch_ac", st, "fft")
+        runs[tau] = np.abs(st["phi"][0]).max()
+    assert not (runs[1e-4] < 10.0), runs  # diverged (or overflowed to nan/inf)
+    assert runs[1e-5] < 0.45, runs
+    c = inputs.CONFIGS["adjoint128"]
+    n = 32
+    N = n * n
+    ops = S.Operators(n, need_p2=True)
+    f = inputs.initial_state(n, "ternary", c["mean"], c["seed"])
+    for tau, bound_ok in ((c["tau_stated"], False), (c["tau"], True)):
+        prm = Params(eps=c["eps"], tau=tau, mobility=c["mobility"], evap_rate=c["evap_rate"],
+                     viscosity=c["viscosity"], alpha=c["alpha"])
+        st = dict(phi=[f["phi"][0], f["phi"][1]], mu=[np.zeros(N), np.zeros(N)], mu_s=np.zeros(N),
+                  Phi_v=f["Phi_v"], vel=f["vel"], p=np.zeros(N))
+        for _ in range(3):
+            out = S.step(ops, prm, "ternary", st, "splu")
+            st = dict(phi=out["phi"], mu=out["mu"], mu_s=out["mu_s"], Phi_v=out["Phi_v"], vel=out["vel"],
+                      p=out["p"])
+        m = np.abs(st["phi"][0]).max()
+        assert (m < 0.35) if bound_ok else (m > 10.0), (tau, m)
