@@ -39,36 +39,16 @@ from .systems import Params
 # ---------------------------------------------------------------- potentials
 
 
-def hess_ter(pp, pn, Phi):
-    """Second derivatives of the reduced ternary density (nodal).
-
-    Keys: 'pp', 'pn', 'nn' (d f_i' / d phi_j), 'pP', 'nP' (d f_i' / d Phi),
-    'vp', 'vn', 'vP' (d f_v' / d phi_p, phi_N, Phi) with f_v' = df/dPhi,
-    'ss', 'sP' (d f_s' / d phi_s, d f_s' / d Phi) for the closure density."""
-    ps = 1.0 - pp - pn
-    p = pot.interp(Phi)
-    dp_ = pot.interp_d(Phi)
-    ddp = 6.0 * (1.0 - 2.0 * Phi)
-    q = 1.0 - p
-    # liquid part 3.5 pp^2 pn^2 + 0.3 ps^2, gas part 3.5 pp^2 + 3.5 pn^2 + 2 ps^2
-    liq_p = 7.0 * pp * pn ** 2 - 0.6 * ps
-    liq_n = 7.0 * pp ** 2 * pn - 0.6 * ps
-    gas_p = 7.0 * pp - 4.0 * ps
-    gas_n = 7.0 * pn - 4.0 * ps
-    liq = 3.5 * pp ** 2 * pn ** 2 + 0.3 * ps ** 2
-    gas = 3.5 * pp ** 2 + 3.5 * pn ** 2 + 2.0 * ps ** 2
-    return {
-        "pp": q * (7.0 * pn ** 2 + 0.6) + p * 11.0,
-        "nn": q * (7.0 * pp ** 2 + 0.6) + p * 11.0,
-        "pn": q * (14.0 * pp * pn + 0.6) + p * 4.0,
-        "pP": dp_ * (gas_p - liq_p),
-        "nP": dp_ * (gas_n - liq_n),
-        "vp": dp_ * (gas_p - liq_p),
-        "vn": dp_ * (gas_n - liq_n),
-        "vP": ddp * (gas - liq),
-        "ss": 0.6 * q + 4.0 * p,
-        "sP": dp_ * (4.0 - 0.6) * ps,
-    }
+def hess_ter(pp, pn, Phi, prm: Params | None = None):
+    """Second derivatives of the reduced ternary density (nodal), from
+    potential.ternary: 'pp', 'pn', 'nn' (d f_i' / d phi_j), 'pP', 'nP'
+    (d f_i' / d Phi), 'vp', 'vn', 'vP' (d f_v' / d phi_p, phi_N, Phi) with
+    f_v' = df/dPhi, and 'sp', 'sn', 'sP' (d f_s' / d phi_p, d phi_N, d Phi) for
+    the closure density f_s'."""
+    t = S.ternary_potential(prm if prm is not None else Params(eps=1.0, tau=1.0), pp, pn, Phi)
+    return {"pp": t["hpp"], "nn": t["hnn"], "pn": t["hpn"], "pP": t["hpP"], "nP": t["hnP"],
+            "vp": t["hpP"], "vn": t["hnP"], "vP": t["hvP"], "sp": t["hsp"], "sn": t["hsn"],
+            "sP": t["hsP"], "dp": t["dp"], "dn": t["dn"], "fv": t["fv"]}
 
 
 # ---------------------------------------------------------------- form VJPs
@@ -155,9 +135,9 @@ def step_vjp(ops: S.Operators, prm: Params, st, st1, lam1):
     beta = prm.beta
     c = tau * gam / beta
     pp, pn, Phi = st["phi"][0], st["phi"][1], st["Phi_v"]
-    H = hess_ter(pp, pn, Phi)
-    fps = pot.dfdphi_ter(pp, pn, Phi)
-    fv = pot.dfdPhi_ter(pp, pn, Phi)
+    H = hess_ter(pp, pn, Phi, prm)
+    fps = (H["dp"], H["dn"])
+    fv = H["fv"]
     lam = zero_adjoint(n)
     dth = np.zeros(3)
     C = fem.p1_convection(m, st["vel"])
@@ -165,8 +145,8 @@ def step_vjp(ops: S.Operators, prm: Params, st, st1, lam1):
     # closure mu_s^{k+1} = f_s'(phi_s^k, Phi^k) + beta M^{-1} K phi_s^{k+1}
     nu_s = lam1["mu_s"]
     q = beta * (K @ ops.mass_solve(nu_s))
-    for i in range(2):
-        lam["phi"][i] -= H["ss"] * nu_s
+    lam["phi"][0] += H["sp"] * nu_s
+    lam["phi"][1] += H["sn"] * nu_s
     lam["Phi_v"] += H["sP"] * nu_s
     ps1 = 1.0 - st1["phi"][0] - st1["phi"][1]
     dth[0] += nu_s @ (2.0 * eps * ops.mass_solve(K @ ps1))

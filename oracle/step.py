@@ -54,6 +54,13 @@ def _solve(A, b, how):
     return solvers.sparse_solve(A, b)
 
 
+def ternary_potential(prm: Params, pp, pn, Phi):
+    """The reduced ternary density's nodal terms for the parameter set (see
+    potential.ternary)."""
+    return pot.ternary(pp, pn, Phi, prm.potential if prm.potential is not None else pot.Quartic(),
+                       prm.truncate)
+
+
 def chemical_potential(ops: Operators, fprime_nodal, phi, beta):
     """mu = M^{-1}(M f' + beta K phi) = f' + beta M^{-1} K phi (second CH equation)."""
     return fprime_nodal + beta * ops.mass_solve(ops.K @ phi)
@@ -70,23 +77,25 @@ def initial_state(ops: Operators, prm: Params, model: str, fields: dict):
     elif model == "ch_ac":
         fp = [pot.dfdphi_bin(st["phi"][0], st["Phi_v"])]
     else:
-        fp = list(pot.dfdphi_ter(st["phi"][0], st["phi"][1], st["Phi_v"]))
+        t = ternary_potential(prm, st["phi"][0], st["phi"][1], st["Phi_v"])
+        fp = [t["dp"], t["dn"]]
     st["mu"] = [chemical_potential(ops, f, ph, prm.beta) for f, ph in zip(fp, st["phi"])]
     if model == "ternary":
         ps = 1.0 - st["phi"][0] - st["phi"][1]
-        st["mu_s"] = chemical_potential(ops, pot.dfdphis_ter(ps, st["Phi_v"]), ps, prm.beta)
+        st["mu_s"] = chemical_potential(ops, t["fs"], ps, prm.beta)
     return st
 
 
-def explicit_terms(model, st):
+def explicit_terms(model, st, prm: Params | None = None):
     """Nodal f'(phi^k) per CH phase and f_v'(Phi^k) for the AC equation."""
     if model == "ch":
         return [pot.dfdphi_bin(st["phi"][0])], None
     if model == "ch_ac":
         return ([pot.dfdphi_bin(st["phi"][0], st["Phi_v"])],
                 pot.dfdPhi_bin(st["phi"][0], st["Phi_v"]))
-    dp, dn = pot.dfdphi_ter(st["phi"][0], st["phi"][1], st["Phi_v"])
-    return [dp, dn], pot.dfdPhi_ter(st["phi"][0], st["phi"][1], st["Phi_v"])
+    t = ternary_potential(prm if prm is not None else Params(eps=1.0, tau=1.0),
+                          st["phi"][0], st["phi"][1], st["Phi_v"])
+    return [t["dp"], t["dn"]], t["fv"]
 
 
 def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
@@ -98,7 +107,7 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
     C = fem.p1_convection(mesh, vel) if vel is not None else None
     if how == "fft" and C is not None:
         raise ValueError("the Fourier solve needs a convection-free system")
-    fps, fv = explicit_terms(model, st)
+    fps, fv = explicit_terms(model, st, prm)
     out = dict(vel=vel, p=st.get("p"))
     sysrec = {}
 
@@ -145,7 +154,8 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         out["vel"] = np.stack([v[:N2], v[N2:]])
         out["p"] = p
         ps1 = 1.0 - phis[0] - phis[1]
-        out["mu_s"] = pot.dfdphis_ter(ps_k, st["Phi_v"]) + prm.beta * ops.mass_solve(K @ ps1)
+        fs_k = ternary_potential(prm, st["phi"][0], st["phi"][1], st["Phi_v"])["fs"]
+        out["mu_s"] = fs_k + prm.beta * ops.mass_solve(K @ ps1)
     if return_systems:
         return out, sysrec
     return out
@@ -171,4 +181,4 @@ def energy_ternary(ops: Operators, prm: Params, pp, pn, Phi):
     lump = ops.M @ np.ones(ops.n * ops.n)
     ps = 1.0 - pp - pn
     grad = sum(u @ (ops.K @ u) for u in (pp, pn, ps))
-    return 0.5 * prm.beta * grad + lump @ pot.f_ter(pp, pn, Phi)
+    return 0.5 * prm.beta * grad + lump @ ternary_potential(prm, pp, pn, Phi)["f"]

@@ -31,6 +31,11 @@ class Params:
     viscosity: float = 1.0
     alpha: float = 1e-8
     rho: float = 1.0
+    # ternary density: None for the fitted quartic of eq. (appPotential), or a
+    # potential.FloryHuggins; truncate: potential terms at the truncated
+    # phase fields of eq. (truncateCH)
+    potential: object = None
+    truncate: bool = False
 
     @property
     def beta(self):

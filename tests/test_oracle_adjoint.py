@@ -21,30 +21,51 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("seed", [0, 1])
-def test_hessian_matches_central_differences(seed):
+@pytest.mark.parametrize("potential", ["quartic", "flory_huggins"])
+def test_hessian_matches_central_differences(seed, potential):
+    """Second derivatives against central differences of the first
+    derivatives, and the first derivatives against central differences of the
+    density itself (so a wrong term anywhere in the chain fails).  The fitted
+    quartic is also checked against its separately written reduced form."""
     g = np.random.default_rng(seed)
     pp, pn, Phi = g.uniform(0.05, 0.6, 50), g.uniform(0.05, 0.35, 50), g.uniform(-0.1, 1.1, 50)
-    H = AD.hess_ter(pp, pn, Phi)
+    prm = Params(eps=0.02, tau=1e-3, potential=None if potential == "quartic" else pot.FloryHuggins())
+    H = AD.hess_ter(pp, pn, Phi, prm)
+    T = lambda a, b, c: S.ternary_potential(prm, a, b, c)
     h = 1e-6
     d = lambda f: (f(h) - f(-h)) / (2 * h)
+    first = {
+        "dp": d(lambda t: T(pp + t, pn, Phi)["f"]),
+        "dn": d(lambda t: T(pp, pn + t, Phi)["f"]),
+        "fv": d(lambda t: T(pp, pn, Phi + t)["f"]),
+    }
+    t0 = T(pp, pn, Phi)
+    for k, fd in first.items():
+        assert np.abs(t0[k] - fd).max() <= 1e-7 * (1 + np.abs(fd).max()), k
     checks = {
-        "pp": d(lambda t: pot.dfdphi_ter(pp + t, pn, Phi)[0]),
-        "pn": d(lambda t: pot.dfdphi_ter(pp, pn + t, Phi)[0]),
-        "nn": d(lambda t: pot.dfdphi_ter(pp, pn + t, Phi)[1]),
-        "pP": d(lambda t: pot.dfdphi_ter(pp, pn, Phi + t)[0]),
-        "nP": d(lambda t: pot.dfdphi_ter(pp, pn, Phi + t)[1]),
-        "vp": d(lambda t: pot.dfdPhi_ter(pp + t, pn, Phi)),
-        "vn": d(lambda t: pot.dfdPhi_ter(pp, pn + t, Phi)),
-        "vP": d(lambda t: pot.dfdPhi_ter(pp, pn, Phi + t)),
-        "ss": d(lambda t: pot.dfdphis_ter(1.0 - pp - pn + t, Phi)),
-        "sP": d(lambda t: pot.dfdphis_ter(1.0 - pp - pn, Phi + t)),
+        "pp": d(lambda t: T(pp + t, pn, Phi)["dp"]),
+        "pn": d(lambda t: T(pp, pn + t, Phi)["dp"]),
+        "nn": d(lambda t: T(pp, pn + t, Phi)["dn"]),
+        "pP": d(lambda t: T(pp, pn, Phi + t)["dp"]),
+        "nP": d(lambda t: T(pp, pn, Phi + t)["dn"]),
+        "vp": d(lambda t: T(pp + t, pn, Phi)["fv"]),
+        "vn": d(lambda t: T(pp, pn + t, Phi)["fv"]),
+        "vP": d(lambda t: T(pp, pn, Phi + t)["fv"]),
+        "sp": d(lambda t: T(pp + t, pn, Phi)["fs"]),
+        "sn": d(lambda t: T(pp, pn + t, Phi)["fs"]),
+        "sP": d(lambda t: T(pp, pn, Phi + t)["fs"]),
     }
     for k, fd in checks.items():
         assert np.abs(H[k] - fd).max() <= 1e-7 * (1 + np.abs(fd).max()), k
     # mixed partials of f from two different first-derivative functions
-    other = d(lambda t: pot.dfdphi_ter(pp + t, pn, Phi)[1])
+    other = d(lambda t: T(pp + t, pn, Phi)["dn"])
     assert np.abs(H["pn"] - other).max() <= 1e-7 * (1 + np.abs(other).max())
     assert np.abs(H["vp"] - checks["pP"]).max() <= 1e-7 * (1 + np.abs(H["vp"]).max())
+    if potential == "quartic":
+        dp, dn = pot.dfdphi_ter(pp, pn, Phi)
+        for a, b in ((t0["f"], pot.f_ter(pp, pn, Phi)), (t0["dp"], dp), (t0["dn"], dn),
+                     (t0["fv"], pot.dfdPhi_ter(pp, pn, Phi)), (t0["fs"], pot.dfdphis_ter(1 - pp - pn, Phi))):
+            assert np.abs(a - b).max() <= 1e-14 * (1 + np.abs(b).max())
 
 
 @pytest.fixture(scope="module")
@@ -121,13 +142,16 @@ def _unflat(x, n):
                 vel=take(8 * N).reshape(2, 4 * N), p=take(N))
 
 
-def test_step_vjp_matches_central_differences():
+@pytest.mark.parametrize("potential", [None, "flory_huggins"])
+def test_step_vjp_matches_central_differences(potential):
     """<lambda^{k+1}, (ds^{k+1}/ds^k) ds> and <lambda^{k+1}, ds^{k+1}/dtheta> by
     central differences of the direct-solve step, against the reverse step;
     alpha = 0.1 so that the chemical-potential path into the Oseen operator is
-    visible."""
+    visible.  Both densities: the fitted quartic and Flory-Huggins."""
     n = 8
     base = dict(eps=0.05, tau=2e-5, mobility=1.3, evap_rate=0.4, viscosity=1.0, alpha=0.1)
+    if potential:
+        base["potential"] = pot.FloryHuggins()
     prm = Params(**base)
     ops, st = _state(n, prm)
     g = np.random.default_rng(8)

@@ -285,3 +285,87 @@ def test_explicit_potential_limits_the_time_step():
                       p=out["p"])
         m = np.abs(st["phi"][0]).max()
         assert (m < 0.35) if bound_ok else (m > 10.0), (tau, m)
+
+
+def test_taylor4_of_xlogx_about_one_half():
+    """The coefficients are the Taylor coefficients of x ln x at 1/2 (checked
+    against high-order central differences of x ln x itself, not of the
+    derivative formulas), and the polynomial matches x ln x with a remainder
+    of fifth order: halving |x - 1/2| divides the error by about 32, with the
+    leading term g^(5)(1/2)/5! u^5 = -0.8 u^5."""
+    c = pot.xlogx_taylor_coefficients()
+    g = lambda x: x * np.log(x)
+    h = 1e-2
+    x0 = 0.5
+    # central differences of orders 1..4 (errors O(h^2))
+    d1 = (g(x0 + h) - g(x0 - h)) / (2 * h)
+    d2 = (g(x0 + h) - 2 * g(x0) + g(x0 - h)) / h ** 2
+    d3 = (g(x0 + 2 * h) - 2 * g(x0 + h) + 2 * g(x0 - h) - g(x0 - 2 * h)) / (2 * h ** 3)
+    d4 = (g(x0 + 2 * h) - 4 * g(x0 + h) + 6 * g(x0) - 4 * g(x0 - h) + g(x0 - 2 * h)) / h ** 4
+    fd = [g(x0), d1, d2 / 2, d3 / 6, d4 / 24]
+    for k in range(5):
+        assert abs(c[k] - fd[k]) <= 2e-3 * max(1.0, abs(fd[k])), (k, c[k], fd[k])
+    us = np.array([0.1, 0.05, 0.025])
+    err = np.abs(pot.xlogx_taylor4(0.5 + us) - g(0.5 + us))
+    assert np.all(np.abs(err / us ** 5 - 0.8) < 0.15), err / us ** 5
+    assert 28.0 < err[0] / err[1] < 36.0 and 29.0 < err[1] / err[2] < 35.0
+    # derivatives of the polynomial against its own central differences
+    x = np.linspace(0.05, 0.95, 19)
+    t = 1e-6
+    assert np.allclose(pot.xlogx_taylor4(x, 1), (pot.xlogx_taylor4(x + t) - pot.xlogx_taylor4(x - t)) / (2 * t),
+                       atol=1e-8)
+    assert np.allclose(pot.xlogx_taylor4(x, 2),
+                       (pot.xlogx_taylor4(x + t, 1) - pot.xlogx_taylor4(x - t, 1)) / (2 * t), atol=1e-8)
+
+
+def test_flory_huggins_density_against_its_definition():
+    """The Flory-Huggins density written out term by term from the free
+    energy section (phi ln phi terms by the Taylor-4 polynomial, air = 0),
+    evaluated separately here, equals the unreduced implementation; its
+    mixing part is symmetric in a swap of polymer and NFA when their sizes
+    and interactions with the solvent agree; the truncation clips exactly."""
+    fh = pot.FloryHuggins()
+    g = np.random.default_rng(4)
+    pp, pn, Phi = g.uniform(0.05, 0.5, 20), g.uniform(0.05, 0.4, 20), g.uniform(0, 1, 20)
+    ps = 1 - pp - pn
+    T = pot.xlogx_taylor4
+    liq = (T(pp) + T(pn)) / 5.0 + T(ps) / 1.0 + 4.0 * pp * pn + 0.3 * pp * ps + 0.3 * pn * ps
+    gas = (T(pp) - pp * np.log(1e-8)) + (T(pn) - pn * np.log(1e-8)) + (T(ps) - ps * np.log(1e-6))
+    P = Phi ** 2 * (3 - 2 * Phi)
+    ref = (1 - P) * liq + P * gas
+    got = pot.ternary(pp, pn, Phi, fh)["f"]
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.allclose(pot.ternary(pn, pp, Phi, fh)["f"], got, rtol=1e-14)
+    # truncation: values outside [0, 1] act as the clipped values
+    a = np.array([-0.2, 0.3, 1.3])
+    b = np.array([0.4, 0.2, -0.1])
+    tr = pot.ternary(a, b, np.full(3, 0.3), fh, truncate=True)
+    # the clipped point, the solvent clipped separately
+    liq_t, gas_t, liq1, gas1, _, _ = fh.parts(np.clip(a, 0, 1), np.clip(b, 0, 1), np.clip(1 - a - b, 0, 1))
+    PP = 0.3 ** 2 * (3 - 0.6)
+    assert np.allclose(tr["f"], (1 - PP) * liq_t + PP * gas_t, rtol=1e-14)
+    F1 = [(1 - PP) * liq1[i] + PP * gas1[i] for i in range(3)]
+    # node 0: phi_p < 0 is clipped (no phi_p dependence), phi_s = 0.8 inside
+    assert tr["dp"][0] == -F1[2][0] and tr["dn"][0] == F1[1][0] - F1[2][0]
+    # node 2: phi_p > 1 clipped, phi_N < 0 clipped, phi_s = -0.2 clipped
+    assert tr["dp"][2] == 0.0 and tr["dn"][2] == 0.0
+
+
+def test_flory_huggins_ternary_step_dense_equals_splu_and_conserves_mass():
+    """A ternary step with the Flory-Huggins potential: dense LU and SuperLU
+    agree, and the CH phases' masses change only by convection (mass balance
+    to 1e-13)."""
+    n = 8
+    ops = S.Operators(n, need_p2=True)
+    prm = Params(eps=0.05, tau=1e-4, mobility=1.0, evap_rate=0.1, potential=pot.FloryHuggins())
+    st = S.initial_state(ops, prm, "ternary", inputs.initial_state(n, "ternary", 0.3, 3))
+    a = S.step(ops, prm, "ternary", st, "dense")
+    b = S.step(ops, prm, "ternary", st, "splu")
+    for k in ("phi", "mu"):
+        for x, y in zip(a[k], b[k]):
+            assert np.abs(x - y).max() <= 1e-10 * np.abs(y).max()
+    C = fem.p1_convection(ops.mesh, st["vel"])
+    one = np.ones(n * n)
+    for i in range(2):
+        bal = one @ (ops.M @ (b["phi"][i] - st["phi"][i])) + prm.tau * one @ (C @ b["phi"][i])
+        assert abs(bal) < 1e-13
