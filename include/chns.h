@@ -95,6 +95,15 @@ typedef struct {
   int32_t model;  /* CHNS_MODEL_* */
 } chns_mesh;
 
+/* Local free-energy density of the ternary model. */
+enum {
+  CHNS_POT_QUARTIC = 0,        /* the fitted quartic of eq. (appPotential), air = 0 */
+  CHNS_POT_FLORY_HUGGINS = 1   /* Flory-Huggins liquid and ideal-gas densities (section "Free
+                                  energy functional") with every phi ln phi replaced by its
+                                  degree-4 Taylor polynomial about 1/2 (section "Numerical
+                                  results"), air = 0 */
+};
+
 typedef struct {
   double eps;        /* interface parameter: beta = beta_v = eps^2 */
   double tau;        /* time step */
@@ -103,6 +112,13 @@ typedef struct {
   double viscosity;  /* eta */
   double alpha;      /* alpha_i in the Oseen convecting field */
   double rho;        /* density (rho = 1 when all pure densities are 1) */
+  /* ternary model only (else CHNS_POT_QUARTIC and truncate 0): */
+  int32_t potential;     /* CHNS_POT_* */
+  int32_t truncate;      /* 1: the density's terms are evaluated at the truncated fields
+                            clip(phi, 0, 1) of eq. (truncateCH) (solvent: clip(1 - phi_p - phi_N)) */
+  double fh_nsize[3];    /* Flory-Huggins molar sizes N_p, N_NFA, N_s (> 0) */
+  double fh_chi[3];      /* interaction parameters chi_(p,NFA), chi_(p,s), chi_(NFA,s) */
+  double fh_phisat[3];   /* saturated vapour fractions of p, NFA, s, in (0, 1] */
 } chns_params;
 
 typedef struct {

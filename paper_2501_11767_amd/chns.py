@@ -46,9 +46,23 @@ class Mesh(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("model", ct.c_int32)]
 
 
+POT_QUARTIC, POT_FLORY_HUGGINS = 0, 1
+# the paper's Flory-Huggins values for the full model (sizes, chi, saturated fractions)
+FLORY_HUGGINS = dict(potential=POT_FLORY_HUGGINS, fh_nsize=(5.0, 5.0, 1.0), fh_chi=(4.0, 0.3, 0.3),
+                     fh_phisat=(1e-8, 1e-8, 1e-6))
+
+
 class Params(ct.Structure):
     _fields_ = [(k, ct.c_double) for k in
-                ("eps", "tau", "mobility", "evap_rate", "viscosity", "alpha", "rho")]
+                ("eps", "tau", "mobility", "evap_rate", "viscosity", "alpha", "rho")] + \
+               [("potential", ct.c_int32), ("truncate", ct.c_int32), ("fh_nsize", ct.c_double * 3),
+                ("fh_chi", ct.c_double * 3), ("fh_phisat", ct.c_double * 3)]
+
+    def __init__(self, *args, **kw):
+        arrays = {k: kw.pop(k) for k in ("fh_nsize", "fh_chi", "fh_phisat") if k in kw}
+        super().__init__(*args, **kw)
+        for k, v in arrays.items():
+            setattr(self, k, (ct.c_double * 3)(*v))
 
 
 class SolveOpts(ct.Structure):

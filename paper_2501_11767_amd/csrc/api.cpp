@@ -135,6 +135,25 @@ int upload_sell(chns_ctx* c, const Sell& S, DSell& d) {
 
 bool is_finite(double v) { return std::isfinite(v); }
 
+// Coefficients of the ternary density for the kernels.  The Taylor
+// coefficients of x ln x about 1/2 come from its derivatives there: ln x + 1,
+// 1/x, -1/x^2, 2/x^3.
+PotCoef pot_coef(const chns_params& p) {
+  PotCoef c;
+  c.fh = p.potential == CHNS_POT_FLORY_HUGGINS ? 1 : 0;
+  c.trunc = p.truncate ? 1 : 0;
+  const double h = 0.5;
+  const double d[5] = {h * std::log(h), std::log(h) + 1.0, 1.0 / h, -1.0 / (h * h), 2.0 / (h * h * h)};
+  const double fact[5] = {1.0, 1.0, 2.0, 6.0, 24.0};
+  for (int k = 0; k < 5; ++k) c.t4[k] = d[k] / fact[k];
+  for (int i = 0; i < 3; ++i) {
+    c.invN[i] = c.fh ? 1.0 / p.fh_nsize[i] : 1.0;
+    c.chi[i] = c.fh ? p.fh_chi[i] : 0.0;
+    c.lsat[i] = c.fh ? std::log(p.fh_phisat[i]) : 0.0;
+  }
+  return c;
+}
+
 // Whether an operator equals its transpose in the context's current state:
 // M, K and the matching factor X always; the P1 operators with a convection
 // part (C, L, AC and the CH block) when no velocity is assembled; the Oseen
@@ -168,6 +187,17 @@ int check_params(chns_ctx* c, const chns_params* p) {
     return fail(c, CHNS_EINVAL, "eps, tau and mobility must be positive");
   if (p->evap_rate < 0 || p->viscosity <= 0 || p->rho <= 0)
     return fail(c, CHNS_EINVAL, "evap_rate must be >= 0, viscosity and rho > 0");
+  if (p->potential != CHNS_POT_QUARTIC && p->potential != CHNS_POT_FLORY_HUGGINS)
+    return fail(c, CHNS_EINVAL, "unknown potential");
+  if (p->truncate != 0 && p->truncate != 1) return fail(c, CHNS_EINVAL, "truncate must be 0 or 1");
+  if (p->potential == CHNS_POT_FLORY_HUGGINS)
+    for (int i = 0; i < 3; ++i) {
+      if (!is_finite(p->fh_nsize[i]) || !(p->fh_nsize[i] > 0.0))
+        return fail(c, CHNS_EINVAL, "Flory-Huggins sizes N_i must be positive");
+      if (!is_finite(p->fh_chi[i])) return fail(c, CHNS_EINVAL, "Flory-Huggins chi must be finite");
+      if (!(p->fh_phisat[i] > 0.0 && p->fh_phisat[i] <= 1.0))
+        return fail(c, CHNS_EINVAL, "saturated vapour fractions must lie in (0, 1]");
+    }
   return CHNS_OK;
 }
 
@@ -1634,7 +1664,7 @@ int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_
   const double beta = p.eps * p.eps;
   Level& L0 = c->lv[0];
   rhs_ternary(L0.d, L0.M, in->phi[0], in->phi[1], in->Phi_v, -(p.tau * p.mobility / beta),
-              -p.tau * p.evap_rate, rhs_ch, rhs_ch + 2 * int64_t(N), rhs_ac, fs, s);
+              -p.tau * p.evap_rate, pot_coef(p), rhs_ch, rhs_ch + 2 * int64_t(N), rhs_ac, fs, s);
   P2Level& P = c->p2;
   const int64_t N4 = 4 * int64_t(N);
   const double cm = p.rho / p.tau;
@@ -1761,6 +1791,7 @@ int ternary_adjoint(chns_ctx* c, const chns_fields& in, const chns_fields& out, 
   a.tau = p.tau;
   a.gam = p.mobility;
   a.gv = p.evap_rate;
+  a.pc = pot_coef(p);
   adj_nodal(N, a, A.part, s);
   adj_finish(3, ADJ_NBLK, A.part, A.acc, s);
   const double cm = p.rho / p.tau;
@@ -1844,6 +1875,10 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = tmp.err;
     return CHNS_EINVAL;
   }
+  if (mesh->model != CHNS_MODEL_TERNARY && (params->potential != CHNS_POT_QUARTIC || params->truncate)) {
+    g_create_err = "the Flory-Huggins density and the truncation apply to the ternary model";
+    return CHNS_EINVAL;
+  }
   chns_ctx* c = new chns_ctx();
   c->alloc = alloc;
   c->free_ = free_;
@@ -1882,6 +1917,8 @@ int chns_destroy(chns_ctx* c) {
 int chns_set_params(chns_ctx* c, const chns_params* p) {
   if (!c) return CHNS_EINVAL;
   TRY(check_params(c, p));
+  if (!c->ternary && (p->potential != CHNS_POT_QUARTIC || p->truncate))
+    return fail(c, CHNS_EINVAL, "the Flory-Huggins density and the truncation apply to the ternary model");
   c->prm = *p;
   // the residual reduction rates of earlier solves belong to other systems
   for (double& r : c->kr.rate) r = -1.0;
@@ -2127,7 +2164,7 @@ int chns_diagnostics(chns_ctx* c, const chns_fields* f, double* h_out, void* str
   hipStream_t s = static_cast<hipStream_t>(stream);
   Level& L0 = c->lv[0];
   diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, vapour ? f->Phi_v : nullptr,
-              c->ternary, c->prm.eps * c->prm.eps, c->kr.part, c->diag, s);
+              c->ternary, c->prm.eps * c->prm.eps, pot_coef(c->prm), c->kr.part, c->diag, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(h_out, c->diag, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -2155,7 +2192,7 @@ int chns_diagnostics_noalloc(chns_ctx* c, const chns_fields* f, double* h_out, v
   double* part = scr;                  // NDIAG x nblk partials, each written before it is read
   double* res = scr + NDIAG * nblk;    // NDIAG results
   diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, vapour ? f->Phi_v : nullptr,
-              c->ternary, c->prm.eps * c->prm.eps, part, res, s);
+              c->ternary, c->prm.eps * c->prm.eps, pot_coef(c->prm), part, res, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(h_out, res, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));

@@ -145,16 +145,121 @@ __device__ __forceinline__ void mu_const(const MuGrad& mg, const int* vtx, const
   wy *= -mg.alpha;
 }
 
-__device__ __forceinline__ void ternary_terms(double pp, double pn, double P, double& dp, double& dn,
-                                              double& fv, double& fs) {
-  const double ps = 1.0 - pp - pn;
-  const double p = P * P * (3.0 - 2.0 * P);
-  dp = (1.0 - p) * (7.0 * pp * pn * pn - 0.6 * ps) + p * (7.0 * pp - 4.0 * ps);
-  dn = (1.0 - p) * (7.0 * pp * pp * pn - 0.6 * ps) + p * (7.0 * pn - 4.0 * ps);
-  const double liq = 3.5 * pp * pp * pn * pn + 0.3 * ps * ps;
-  const double gas = 3.5 * pp * pp + 3.5 * pn * pn + 2.0 * ps * ps;
-  fv = 6.0 * P * (1.0 - P) * (gas - liq);
-  fs = (1.0 - p) * 0.6 * ps + p * 4.0 * ps;
+// ---------------------------------------------------------------- ternary densities
+// Liquid and gas densities of polymer p, NFA n and solvent s (air = 0) in
+// unreduced form with first and second partial derivatives, interpolated by
+// p(Phi) = Phi^2 (3 - 2 Phi); the reduced density follows from s = 1 - p - n.
+//   fitted quartic (eq. (appPotential)): liq = 3.5 p^2 n^2 + 0.3 s^2,
+//     gas = 3.5 p^2 + 3.5 n^2 + 2 s^2;
+//   Flory-Huggins (section "Free energy functional", x ln x by its degree-4
+//     Taylor polynomial T4 about 1/2, section "Numerical results"):
+//     liq = sum_i T4(x_i) / N_i + chi_pn p n + chi_ps p s + chi_ns n s,
+//     gas = sum_i (T4(x_i) - x_i ln phi_sat(i)).
+// trunc: the fields enter as clip(x, 0, 1) (eq. (truncateCH)) and the chain
+// rule carries the clip's derivative (1 inside [0, 1], else 0).
+// Every member is a named scalar assigned on both branches: an earlier form
+// kept the partials in 3x3 arrays with some entries stored per branch, and on
+// gfx950 one of those stores was lost (the gas d2/dn2 of the quartic read 0).
+struct TerParts {
+  double liq, gas;
+  double lp, ln, ls, gp, gn, gs;                    // first partials (liquid, gas)
+  double lpp, lnn, lss, lpn, lps, lns, gpp, gnn, gss;  // second partials (the gas part is diagonal)
+};
+
+__device__ __forceinline__ void t4_eval(const double* c, double x, double& g, double& g1, double& g2) {
+  const double u = x - 0.5;
+  g = c[0] + u * (c[1] + u * (c[2] + u * (c[3] + u * c[4])));
+  g1 = c[1] + u * (2.0 * c[2] + u * (3.0 * c[3] + u * 4.0 * c[4]));
+  g2 = 2.0 * c[2] + u * (6.0 * c[3] + u * 12.0 * c[4]);
+}
+
+__device__ __forceinline__ TerParts ter_parts(double p, double n, double s, const PotCoef& c) {
+  TerParts t;
+  if (!c.fh) {
+    t.liq = 3.5 * p * p * n * n + 0.3 * s * s;
+    t.gas = 3.5 * p * p + 3.5 * n * n + 2.0 * s * s;
+    t.lp = 7.0 * p * n * n;
+    t.ln = 7.0 * p * p * n;
+    t.ls = 0.6 * s;
+    t.gp = 7.0 * p;
+    t.gn = 7.0 * n;
+    t.gs = 4.0 * s;
+    t.lpp = 7.0 * n * n;
+    t.lnn = 7.0 * p * p;
+    t.lss = 0.6;
+    t.lpn = 14.0 * p * n;
+    t.lps = 0.0;
+    t.lns = 0.0;
+    t.gpp = 7.0;
+    t.gnn = 7.0;
+    t.gss = 4.0;
+    return t;
+  }
+  double ap, ap1, ap2, an, an1, an2, as, as1, as2;
+  t4_eval(c.t4, p, ap, ap1, ap2);
+  t4_eval(c.t4, n, an, an1, an2);
+  t4_eval(c.t4, s, as, as1, as2);
+  t.liq = ap * c.invN[0] + an * c.invN[1] + as * c.invN[2] + c.chi[0] * p * n + c.chi[1] * p * s +
+          c.chi[2] * n * s;
+  t.gas = (ap - p * c.lsat[0]) + (an - n * c.lsat[1]) + (as - s * c.lsat[2]);
+  t.lp = ap1 * c.invN[0] + c.chi[0] * n + c.chi[1] * s;
+  t.ln = an1 * c.invN[1] + c.chi[0] * p + c.chi[2] * s;
+  t.ls = as1 * c.invN[2] + c.chi[1] * p + c.chi[2] * n;
+  t.gp = ap1 - c.lsat[0];
+  t.gn = an1 - c.lsat[1];
+  t.gs = as1 - c.lsat[2];
+  t.lpp = ap2 * c.invN[0];
+  t.lnn = an2 * c.invN[1];
+  t.lss = as2 * c.invN[2];
+  t.lpn = c.chi[0];
+  t.lps = c.chi[1];
+  t.lns = c.chi[2];
+  t.gpp = ap2;
+  t.gnn = an2;
+  t.gss = as2;
+  return t;
+}
+
+// The point where the density is evaluated (p, n, s = 1 - p - n, each
+// clipped to [0, 1] when the fields are truncated) and the clip's derivatives.
+struct TerPoint {
+  double p, n, s, cp, cn, cs;  // cp, cn, cs: the clip's derivatives
+};
+
+__device__ __forceinline__ void clip01(bool on, double v, double& x, double& d) {
+  x = on ? fmin(fmax(v, 0.0), 1.0) : v;
+  d = (!on || (v >= 0.0 && v <= 1.0)) ? 1.0 : 0.0;
+}
+
+__device__ __forceinline__ TerPoint ter_point(double pp, double pn, const PotCoef& c) {
+  TerPoint x;
+  const bool on = c.trunc != 0;
+  clip01(on, pp, x.p, x.cp);
+  clip01(on, pn, x.n, x.cn);
+  clip01(on, 1.0 - pp - pn, x.s, x.cs);
+  return x;
+}
+
+// Nodal terms of the reduced density: dp, dn (d f / d phi_p, d phi_N along
+// phi_s = 1 - phi_p - phi_N), fv = d f / d Phi_v, fs = the unreduced d f / d phi_s
+// (the closure of the eliminated phase).
+__device__ __forceinline__ void ternary_terms(double pp, double pn, double P, const PotCoef& c, double& dp,
+                                              double& dn, double& fv, double& fs) {
+  const TerPoint x = ter_point(pp, pn, c);
+  const TerParts t = ter_parts(x.p, x.n, x.s, c);
+  const double ip = P * P * (3.0 - 2.0 * P), q = 1.0 - ip;
+  const double F0 = q * t.lp + ip * t.gp, F1 = q * t.ln + ip * t.gn, F2 = q * t.ls + ip * t.gs;
+  dp = F0 * x.cp - F2 * x.cs;
+  dn = F1 * x.cn - F2 * x.cs;
+  fv = 6.0 * P * (1.0 - P) * (t.gas - t.liq);
+  fs = F2;
+}
+
+__device__ __forceinline__ double density_ternary(double pp, double pn, double P, const PotCoef& c) {
+  const TerPoint x = ter_point(pp, pn, c);
+  const TerParts t = ter_parts(x.p, x.n, x.s, c);
+  const double ip = P * P * (3.0 - 2.0 * P);
+  return (1.0 - ip) * t.liq + ip * t.gas;
 }
 
 }  // namespace chns

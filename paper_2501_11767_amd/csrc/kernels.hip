@@ -1681,12 +1681,7 @@ __device__ __forceinline__ double density_binary(double phi, const double* Phi, 
   return (1.0 - p) * liq + p * (phi * phi + om * om);
 }
 
-__device__ __forceinline__ double density_ternary(double pp, double pn, double P) {
-  const double ps = 1.0 - pp - pn, p = P * P * (3.0 - 2.0 * P);
-  const double liq = 3.5 * pp * pp * pn * pn + 0.3 * ps * ps;
-  const double gas = 3.5 * pp * pp + 3.5 * pn * pn + 2.0 * ps * ps;
-  return (1.0 - p) * liq + p * gas;
-}
+
 
 // Per row: the row sum of M (the nodal weight), the masses weight * u, the
 // gradient terms u (K u) of each phase and weight * density; per block the
@@ -1695,7 +1690,7 @@ __global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restr
                                              const double* __restrict__ Mv, const double* __restrict__ Kv,
                                              const double* __restrict__ p0, const double* __restrict__ p1,
                                              const double* __restrict__ Phi, int ternary, double beta,
-                                             double* __restrict__ part) {
+                                             PotCoef pc, double* __restrict__ part) {
   __shared__ double sh[4];
   double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int stride = gridDim.x * BS;
@@ -1723,7 +1718,7 @@ __global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restr
       acc[1] += w * u1;
       acc[2] += w * us;
       grad += u1 * k1 + us * k2;
-      f = density_ternary(u0, u1, Phi ? Phi[row] : 0.0);
+      f = density_ternary(u0, u1, Phi ? Phi[row] : 0.0, pc);
     } else {
       f = density_binary(u0, Phi, row);
     }
@@ -2012,7 +2007,7 @@ __global__ __launch_bounds__(BS) void k_rhs_ternary(int n, int side, const int* 
                                                     const double* __restrict__ php,
                                                     const double* __restrict__ phn,
                                                     const double* __restrict__ Phi, double c_mu,
-                                                    double c_ac, double* __restrict__ rhs_p,
+                                                    double c_ac, PotCoef pc, double* __restrict__ rhs_p,
                                                     double* __restrict__ rhs_n,
                                                     double* __restrict__ rhs_ac,
                                                     double* __restrict__ fs_out) {
@@ -2029,7 +2024,7 @@ __global__ __launch_bounds__(BS) void k_rhs_ternary(int n, int side, const int* 
     const double m = Mv[base + k * 64];
     const double a = php[j], b = phn[j], P = Phi[j];
     double dp, dn, fv, fs;
-    ternary_terms(a, b, P, dp, dn, fv, fs);
+    ternary_terms(a, b, P, pc, dp, dn, fv, fs);
     s_p += m * a;
     s_n += m * b;
     s_dp += m * dp;
@@ -2043,7 +2038,7 @@ __global__ __launch_bounds__(BS) void k_rhs_ternary(int n, int side, const int* 
   rhs_n[n + row] = c_mu * s_dn;
   rhs_ac[row] = s_P + c_ac * s_fv;
   double dp, dn, fv, fs;
-  ternary_terms(php[row], phn[row], Phi[row], dp, dn, fv, fs);
+  ternary_terms(php[row], phn[row], Phi[row], pc, dp, dn, fv, fs);
   fs_out[row] = fs;
 }
 
@@ -2435,10 +2430,11 @@ void form_ops(int nlev, const FormLevel* tab, int64_t total, const FormCoef& k, 
 int diag_part_blocks(int64_t n) { return reduce_blocks(n); }
 
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
-                 const double* Phi, bool ternary, double beta, double* part, double* out, hipStream_t s) {
+                 const double* Phi, bool ternary, double beta, const PotCoef& pc, double* part, double* out,
+                 hipStream_t s) {
   const int nblk = reduce_blocks(A.nrows);
   hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, Phi,
-                     ternary ? 1 : 0, beta, part);
+                     ternary ? 1 : 0, beta, pc, part);
   hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(BS), 0, s, nblk, part, out);
 }
 
@@ -2504,10 +2500,10 @@ void form_ns(int64_t nslots, const int8_t* kind, const int* src, double cm, cons
 }
 
 void rhs_ternary(const DSell& A, const double* Mv, const double* php, const double* phn,
-                 const double* Phi, double c_mu, double c_ac, double* rhs_p, double* rhs_n,
+                 const double* Phi, double c_mu, double c_ac, const PotCoef& pc, double* rhs_p, double* rhs_n,
                  double* rhs_ac, double* fs, hipStream_t s) {
   hipLaunchKernelGGL(k_rhs_ternary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col, Mv,
-                     php, phn, Phi, c_mu, c_ac, rhs_p, rhs_n, rhs_ac, fs);
+                     php, phn, Phi, c_mu, c_ac, pc, rhs_p, rhs_n, rhs_ac, fs);
 }
 
 template <typename T>

@@ -362,10 +362,21 @@ void diag_inverse(int nrows, const int* diag, const double* val, double* d64, fl
 // width-7 pattern; M and K values): out[0..4] as chns_diagnostics documents,
 // through per-block partials (part: 5 x reduce_blocks(n)) and one summing
 // workgroup.  p1 (ternary second phase) and Phi may be null.
+// Coefficients of the ternary density (definitions with the device
+// functions in device_util.hpp): fh = 0 the fitted quartic, 1 Flory-Huggins;
+// trunc: evaluate at the truncated fields.
+struct PotCoef {
+  int fh = 0, trunc = 0;
+  double t4[5] = {0, 0, 0, 0, 0};  // Taylor coefficients of x ln x about 1/2
+  double invN[3] = {1, 1, 1};
+  double chi[3] = {0, 0, 0};       // (p, n), (p, s), (n, s)
+  double lsat[3] = {0, 0, 0};      // ln phi_sat
+};
 constexpr int NDIAG = 5;
 int diag_part_blocks(int64_t n);  // per-block partial sums diagnostics() writes per quantity
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
-                 const double* Phi, bool ternary, double beta, double* part, double* out, hipStream_t s);
+                 const double* Phi, bool ternary, double beta, const PotCoef& pc, double* part, double* out,
+                 hipStream_t s);
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
                 double c_mu, double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s);
 
@@ -435,7 +446,7 @@ void form_ns(int64_t nslots, const int8_t* kind, const int* src, double cm, cons
 // eliminated), P1 pattern of M: rhs_p = [M phi_p; c_mu M f'_p], rhs_n likewise,
 // rhs_ac = M Phi + c_ac M f_v; fs = d f / d phi_s at the nodes (for the closure).
 void rhs_ternary(const DSell& A, const double* Mv, const double* php, const double* phn,
-                 const double* Phi, double c_mu, double c_ac, double* rhs_p, double* rhs_n,
+                 const double* Phi, double c_mu, double c_ac, const PotCoef& pc, double* rhs_p, double* rhs_n,
                  double* rhs_ac, double* fs, hipStream_t s);
 
 // Mean-zero projection: partial sums (double) then x -= sum / n.

@@ -25,31 +25,33 @@ __global__ __launch_bounds__(BS) void k_gather_slots(int64_t n, const int* __res
 }
 
 // Second derivatives of the reduced ternary density at one node (the
-// derivatives of the nodal f_p', f_N', f_v' and of the closure f_s').
+// derivatives of the nodal f_p', f_N', f_v' and of the closure f_s'), from the
+// unreduced partials by the chain rule along phi_s = 1 - phi_p - phi_N (with
+// the clip's derivative when the fields are truncated).
 struct Hess {
-  double pp, pn, nn, pP, nP, vP, ss, sP;
+  double pp, pn, nn, pP, nP, vP, sp, sn, sP;
 };
 
-__device__ __forceinline__ Hess hess_ter(double pp, double pn, double P) {
-  const double ps = 1.0 - pp - pn;
-  const double p = P * P * (3.0 - 2.0 * P);
-  const double dp = 6.0 * P * (1.0 - P);
-  const double ddp = 6.0 - 12.0 * P;
-  const double q = 1.0 - p;
-  // d/dphi_p and d/dphi_N of the liquid and gas parts (phi_s = 1 - phi_p - phi_N)
-  const double lp = 7.0 * pp * pn * pn - 0.6 * ps, ln = 7.0 * pp * pp * pn - 0.6 * ps;
-  const double gp = 7.0 * pp - 4.0 * ps, gn = 7.0 * pn - 4.0 * ps;
-  const double liq = 3.5 * pp * pp * pn * pn + 0.3 * ps * ps;
-  const double gas = 3.5 * pp * pp + 3.5 * pn * pn + 2.0 * ps * ps;
+__device__ __forceinline__ Hess hess_ter(double pp, double pn, double P, const PotCoef& c) {
+  const TerPoint x = ter_point(pp, pn, c);
+  const TerParts t = ter_parts(x.p, x.n, x.s, c);
+  const double ip = P * P * (3.0 - 2.0 * P), q = 1.0 - ip;
+  const double dip = 6.0 * P * (1.0 - P), ddip = 6.0 - 12.0 * P;
+  // second partials of the interpolated unreduced density
+  const double Fpp = q * t.lpp + ip * t.gpp, Fnn = q * t.lnn + ip * t.gnn, Fss = q * t.lss + ip * t.gss;
+  const double Fpn = q * t.lpn, Fps = q * t.lps, Fns = q * t.lns;
+  const double Dp = dip * (t.gp - t.lp), Dn = dip * (t.gn - t.ln), Ds = dip * (t.gs - t.ls);
+  const double Ip = x.cp, In = x.cn, Is = x.cs;
   Hess h;
-  h.pp = q * (7.0 * pn * pn + 0.6) + 11.0 * p;
-  h.nn = q * (7.0 * pp * pp + 0.6) + 11.0 * p;
-  h.pn = q * (14.0 * pp * pn + 0.6) + 4.0 * p;
-  h.pP = dp * (gp - lp);
-  h.nP = dp * (gn - ln);
-  h.vP = ddp * (gas - liq);
-  h.ss = 0.6 * q + 4.0 * p;
-  h.sP = 3.4 * dp * ps;
+  h.pp = Fpp * Ip - 2.0 * Fps * Ip * Is + Fss * Is;
+  h.nn = Fnn * In - 2.0 * Fns * In * Is + Fss * Is;
+  h.pn = Fpn * Ip * In - Fps * Ip * Is - Fns * In * Is + Fss * Is;
+  h.pP = Dp * Ip - Ds * Is;
+  h.nP = Dn * In - Ds * Is;
+  h.vP = ddip * (t.gas - t.liq);
+  h.sp = Fps * Ip - Fss * Is;
+  h.sn = Fns * In - Fss * Is;
+  h.sP = Ds;
   return h;
 }
 
@@ -61,12 +63,12 @@ __global__ __launch_bounds__(BS) void k_adj_nodal(int n, AdjNodal a, double* __r
   for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
     const double pp = a.php[i], pn = a.phn[i], P = a.Phi[i];
     double fp, fn, fv, fs;
-    ternary_terms(pp, pn, P, fp, fn, fv, fs);
-    const Hess H = hess_ter(pp, pn, P);
+    ternary_terms(pp, pn, P, a.pc, fp, fn, fv, fs);
+    const Hess H = hess_ter(pp, pn, P, a.pc);
     const double gp = -c * a.Me2p[i], gn = -c * a.Me2n[i], gvv = -a.tau * a.gv * a.Mz[i];
     const double nu = a.nus[i];
-    a.lam_php[i] = a.Me1p[i] + H.pp * gp + H.pn * gn + H.pP * gvv - H.ss * nu;
-    a.lam_phn[i] = a.Me1n[i] + H.pn * gp + H.nn * gn + H.nP * gvv - H.ss * nu;
+    a.lam_php[i] = a.Me1p[i] + H.pp * gp + H.pn * gn + H.pP * gvv + H.sp * nu;
+    a.lam_phn[i] = a.Me1n[i] + H.pn * gp + H.nn * gn + H.nP * gvv + H.sn * nu;
     a.lam_Phi[i] = a.Mz[i] + H.pP * gp + H.nP * gn + H.vP * gvv + H.sP * nu;
     const double mp = a.mup1[i], mn = a.mun1[i];
     const double sch = a.Me2p[i] * (fp - mp) + a.Me2n[i] * (fn - mn);

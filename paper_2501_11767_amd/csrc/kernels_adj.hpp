@@ -31,6 +31,7 @@ struct AdjNodal {
   const double *Me1p, *Me1n, *Me2p, *Me2n, *Ke1p, *Ke1n, *Ke2p, *Ke2n, *Mz, *Kz, *nus;
   double *lam_php, *lam_phn, *lam_Phi;
   double eps, tau, gam, gv;
+  PotCoef pc;  // the ternary density
 };
 constexpr int ADJ_NBLK = 512;  // fixed grid of the reductions (deterministic order)
 void adj_nodal(int n, const AdjNodal& a, double* part, hipStream_t s);
