@@ -296,6 +296,29 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
       if (UPLIKE) xa[idx] = xin[row] + p1_interp(e, gi, gj, s >> 1);
     }
   }
+  // up pass with the M product: the values of M for the own rows, taken in
+  // a direct map (interior row o = tid + p NTH of the TT x TT tile), are
+  // loaded here, after every other load, so that they arrive during the
+  // sweeps instead of after them
+  constexpr int NOWN = MODE == TILE_UPM ? TT * TT / NTH : 1;
+  static_assert(MODE != TILE_UPM || NOWN * NTH == TT * TT, "interior rows per thread");
+  T mv[NOWN][W7];
+  int orow[NOWN], oidx[NOWN];
+  if constexpr (MODE == TILE_UPM) {
+#pragma unroll
+    for (int p = 0; p < NOWN; ++p) {
+      const int o = tid + p * NTH;
+      const int oj = o / TT, oi = o - oj * TT;
+      const int gi = tx * TT + oi, gj = ty * TT + oj;
+      const bool in = gi < s && gj < s;  // ragged last tiles
+      orow[p] = in ? gi + s * gj : -1;
+      oidx[p] = (oi + H) + W * (oj + H);
+      const int rr = in ? orow[p] : tx * TT + s * (ty * TT);
+      const size_t base = size_t(rr >> 6) * (64 * W7) + (rr & 63);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) mv[p][k] = mval[base + k * 64];
+    }
+  }
   if (!UPLIKE) {  // first step from zero: x = d = c2 D^{-1} b
     const T c20 = c2s[0];
 #pragma unroll
@@ -336,18 +359,13 @@ __device__ __forceinline__ void vtile_body(int s, int steps, const T* __restrict
   if constexpr (MODE == TILE_UPM) {
     // the result is valid at ring >= steps, so on every neighbour of an own row
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      if (own[q]) {
-        const int idx = tid + q * NTH;
-        const size_t base = size_t(gr[q] >> 6) * (64 * W7) + (gr[q] & 63);
-        T m[W7];
-#pragma unroll
-        for (int k = 0; k < W7; ++k) m[k] = mval[base + k * 64];
+    for (int p = 0; p < NOWN; ++p) {
+      if (orow[p] >= 0) {
         T y = T(0);
 #pragma unroll
-        for (int k = 0; k < W7; ++k) y += m[k] * cur[idx + off[k]];
-        if (x64) x64[gr[q]] = double(y) * (xs ? xs[0] : 1.0);
-        else x[gr[q]] = y;
+        for (int k = 0; k < W7; ++k) y += mv[p][k] * cur[oidx[p] + off[k]];
+        if (x64) x64[orow[p]] = double(y) * (xs ? xs[0] : 1.0);
+        else x[orow[p]] = y;
       }
     }
   } else if (x64) {
