@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 #include "device_util.hpp"
@@ -414,6 +415,251 @@ __global__ __launch_bounds__(TileCfg<TT>::NTH) void k_vtile(TileArgs<T> a) {
   __shared__ T xa[WMAX * WMAX], xb[WMAX * WMAX];
   vtile_body<T, MODE, TT>(a.side, a.steps, a.val, a.dinv, a.b, a.xin, a.e, a.x, a.bc, a.c1, a.c2,
                           xcd_block(blockIdx.x, gridDim.x), xa, xb, a.b64, a.x64, a.xs, a.mval);
+}
+
+// Software-pipelined form of the 64 x 64 FP32 tile pass (the finest level
+// of the mixed-precision cycles).  The region's rows are cut into bands of
+// NTH consecutive region indices (one row of each band per thread; a band
+// spans more than one region line, so a stencil reaches only the adjacent
+// bands).  Stage t issues the loads of band t + LA (all bands up to LA ahead
+// are in flight), initialises band t - 1 (x = c2 D^{-1} b from zero, or x +
+// P e in the up pass), runs sweep k of band t - 1 - 2k and stores the result
+// of band t - 2 - 2S: every band's sweep k comes one stage after sweep k - 1
+// of its lower neighbour band and after its upper neighbour's, and the loads
+// of the bands still ahead are in flight during the sweeps of the bands
+// behind.  The number of sweeps S, the halo and the FP64 boundary are
+// compile-time, so that every band's registers are fixed and the waits for
+// its loads name only those loads; the right-hand side stays in its load
+// type until the band's initialisation.  The arithmetic per row and sweep is
+// k_vtile's.
+constexpr int PIPE_LA = 1;  // bands loaded ahead of the band being initialised
+
+template <typename T, int MODE, int S, int IO>
+struct PipeTile {
+  static constexpr int TT = 64, NTH = 1024;
+  static constexpr bool UPLIKE = MODE == TILE_UP || MODE == TILE_UPM;
+  static constexpr bool BIN64 = (IO & 1) != 0, XOUT64 = (IO & 2) != 0;
+  static constexpr int STEPS = UPLIKE ? S : S + 1;
+  static constexpr int H = tile_halo(MODE, STEPS);
+  static constexpr int W = TT + 2 * H, R = W * W;
+  static constexpr int NB = (R + NTH - 1) / NTH;
+  static constexpr int NOWN = MODE == TILE_UPM ? TT * TT / NTH : 1;
+  // last stage: the result stores of the last band (DOWN: its residual, one later)
+  static constexpr int NST = NB + 2 + 2 * S + (MODE == TILE_DOWN ? 1 : 0);
+  using BIn = typename std::conditional<BIN64, double, T>::type;
+  const TileArgs<T>& a;
+  T* buf0;
+  T* buf1;
+  int s, tx, ty, i0, j0, tid, row_safe;
+  T v[NB][W7], di[NB], d[NB], xin[NB], ea[NB], eb[NB];
+  BIn bl[NB];
+  T bb[NB];
+  int ring[NB], gr[NB];
+  bool own[NB], odd[NB];
+  T mv[NOWN][W7];
+  int orow[NOWN], oidx[NOWN];
+  double xsc = 1.0;  // the FP64 output's scale
+  __device__ __forceinline__ PipeTile(const TileArgs<T>& a_, T* b0, T* b1) : a(a_), buf0(b0), buf1(b1) {}
+  template <int K> __device__ __forceinline__ T* B() { return (K & 1) ? buf1 : buf0; }
+
+  template <int q> __device__ __forceinline__ void load() {
+    const int idx = tid + q * NTH;
+    const bool in = idx < R;
+    const int ic = in ? idx : W + 1;
+    const int rj = ic / W, ri = ic - rj * W;
+    const int gi = wrap_once(i0 + ri, s), gj = wrap_once(j0 + rj, s);
+    const int row = gi + s * gj;
+    const int rg = min(min(ri, rj), min(W - 1 - ri, W - 1 - rj));
+    ring[q] = in ? rg : -1;
+    own[q] = in && rg >= H && tx * TT + (ri - H) < s && ty * TT + (rj - H) < s;
+    gr[q] = row;
+    const bool upd = in && rg >= 1;
+    const int rv = upd ? row : row_safe;
+    const int rd = (UPLIKE && !upd) ? row_safe : row;
+    const size_t base = size_t(rv >> 6) * (64 * W7) + (rv & 63);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) v[q][k] = a.val[base + k * 64];
+    di[q] = a.dinv[rd];
+    if constexpr (BIN64) bl[q] = a.b64[rd];
+    else bl[q] = a.b[rd];
+    if constexpr (UPLIKE) {
+      const int nc = s >> 1, I = gi >> 1, J = gj >> 1;
+      const int I1 = (gi & 1) ? (I + 1 == nc ? 0 : I + 1) : I;
+      const int J1 = (gj & 1) ? (J + 1 == nc ? 0 : J + 1) : J;
+      odd[q] = ((gi | gj) & 1) != 0;
+      xin[q] = a.xin[row];
+      ea[q] = a.e[I + nc * J];
+      eb[q] = a.e[I1 + nc * J1];
+    }
+  }
+
+  __device__ __forceinline__ void load_m() {
+    if constexpr (MODE == TILE_UPM) {
+#pragma unroll
+      for (int p = 0; p < NOWN; ++p) {
+        const int o = tid + p * NTH;
+        const int oj = o / TT, oi = o - oj * TT;
+        const int gi = tx * TT + oi, gj = ty * TT + oj;
+        const bool in = gi < s && gj < s;
+        orow[p] = in ? gi + s * gj : -1;
+        oidx[p] = (oi + H) + W * (oj + H);
+        const int rr = in ? orow[p] : tx * TT + s * (ty * TT);
+        const size_t base = size_t(rr >> 6) * (64 * W7) + (rr & 63);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) mv[p][k] = a.mval[base + k * 64];
+      }
+    }
+  }
+
+  template <int q> __device__ __forceinline__ void init() {
+    const int idx = tid + q * NTH;
+    bb[q] = T(bl[q]);
+    d[q] = T(0);
+    if (idx < R) {
+      if constexpr (UPLIKE) {
+        buf0[idx] = xin[q] + (odd[q] ? T(0.5) * (ea[q] + eb[q]) : ea[q]);
+      } else {
+        d[q] = a.c2[0] * (di[q] * bb[q]);
+        buf0[idx] = d[q];
+      }
+    }
+  }
+
+  template <int q, int k> __device__ __forceinline__ void sweep() {
+    // valid at ring >= k after sweep k
+    constexpr int ci = UPLIKE ? k - 1 : k;
+    const T c1 = a.c1[ci], c2 = a.c2[ci];
+    T* cur = B<k - 1>();
+    T* nxt = B<k>();
+    const int idx = tid + q * NTH;
+    if (ring[q] >= k) {
+      T sum = T(0);
+#pragma unroll
+      for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + off(m)];
+      const T r = di[q] * (bb[q] - sum);
+      const T dn = (UPLIKE && k == 1) ? c2 * r : c1 * d[q] + c2 * r;
+      d[q] = dn;
+      nxt[idx] = cur[idx] + dn;
+    }
+  }
+
+  template <int q> __device__ __forceinline__ void store() {
+    if constexpr (MODE != TILE_UPM) {
+      const int idx = tid + q * NTH;
+      if (own[q]) {
+        const T y = B<S>()[idx];
+        if constexpr (XOUT64) a.x64[gr[q]] = double(y) * xsc;
+        else a.x[gr[q]] = y;
+      }
+    }
+  }
+
+  template <int q> __device__ __forceinline__ void resid() {
+    if constexpr (MODE == TILE_DOWN) {
+      // residual on ring >= steps, into the buffer the last sweep did not write
+      T* cur = B<S>();
+      T* nxt = B<S + 1>();
+      const int idx = tid + q * NTH;
+      if (ring[q] >= STEPS) {
+        T sum = T(0);
+#pragma unroll
+        for (int m = 0; m < W7; ++m) sum += v[q][m] * cur[idx + off(m)];
+        nxt[idx] = bb[q] - sum;
+      }
+    }
+  }
+
+  static __device__ __forceinline__ constexpr int off(int m) {
+    return m == 0 ? 0 : m == 1 ? -W - 1 : m == 2 ? -W : m == 3 ? -1 : m == 4 ? 1 : m == 5 ? W : W + 1;
+  }
+
+  template <int t, int k> __device__ __forceinline__ void sweeps_at() {
+    if constexpr (k <= S) {
+      constexpr int q = t - 1 - 2 * k;
+      if constexpr (q >= 0 && q < NB) sweep<q, k>();
+      sweeps_at<t, k + 1>();
+    }
+  }
+
+  template <int t, int q> __device__ __forceinline__ void loads_at() {
+    if constexpr (q < NB) {
+      constexpr int ls = q - PIPE_LA < 0 ? 0 : q - PIPE_LA;  // stage that issues band q's loads
+      if constexpr (ls == t) load<q>();
+      loads_at<t, q + 1>();
+    }
+  }
+
+  template <int t> __device__ __forceinline__ void stage() {
+    loads_at<t, 0>();
+    constexpr int lastls = NB - 1 - PIPE_LA < 0 ? 0 : NB - 1 - PIPE_LA;
+    if constexpr (t == lastls) load_m();
+    if constexpr (t - 1 >= 0 && t - 1 < NB) init<t - 1>();
+    sweeps_at<t, 1>();
+    constexpr int qs = t - 2 - 2 * S;
+    if constexpr (qs >= 0 && qs < NB) store<qs>();
+    constexpr int qr = t - 3 - 2 * S;
+    if constexpr (qr >= 0 && qr < NB) resid<qr>();
+    __syncthreads();
+  }
+
+  template <int t> __device__ __forceinline__ void run_from() {
+    if constexpr (t < NST) {
+      stage<t>();
+      run_from<t + 1>();
+    }
+  }
+
+  __device__ __forceinline__ void run(int tile) {
+    s = a.side;
+    const int nt = (s + TT - 1) / TT;
+    ty = tile / nt;
+    tx = tile - ty * nt;
+    i0 = tx * TT - H;
+    j0 = ty * TT - H;
+    tid = threadIdx.x;
+    row_safe = wrap_once(i0 + 1, s) + s * wrap_once(j0 + 1, s);
+    if constexpr (XOUT64) xsc = a.xs ? a.xs[0] : 1.0;
+    run_from<0>();
+    if constexpr (MODE == TILE_UPM) {
+      T* cur = B<S>();
+#pragma unroll
+      for (int p = 0; p < NOWN; ++p) {
+        if (orow[p] >= 0) {
+          T y = T(0);
+#pragma unroll
+          for (int k = 0; k < W7; ++k) y += mv[p][k] * cur[oidx[p] + off(k)];
+          if constexpr (XOUT64) a.x64[orow[p]] = double(y) * xsc;
+          else a.x[orow[p]] = y;
+        }
+      }
+    }
+    if constexpr (MODE == TILE_DOWN) {
+      // R = P^T of the residual into the coarse rows whose fine vertex lies
+      // in the tile interior
+      const T* res = B<S + 1>();
+      constexpr int TC = TT / 2;
+      const int nc = s >> 1;
+      if (tid < TC * TC) {
+        const int lj = tid / TC, lc = tid - lj * TC;
+        const int cI = tx * TC + lc, cJ = ty * TC + lj;
+        if (cI < nc && cJ < nc) {
+          const int idx = (2 * lc + H) + W * (2 * lj + H);
+          T sm = T(0);
+#pragma unroll
+          for (int m = 1; m < W7; ++m) sm += res[idx + off(m)];
+          a.bc[cI + nc * cJ] = res[idx] + T(0.5) * sm;
+        }
+      }
+    }
+  }
+};
+
+template <typename T, int MODE, int S, int IO>
+__global__ __launch_bounds__(1024) void k_vtile_pipe(TileArgs<T> a) {
+  using P = PipeTile<T, MODE, S, IO>;
+  __shared__ T b0[P::R], b1[P::R];
+  P p(a, b0, b1);
+  p.run(xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Batched: workgroup -> (instance, tile) from the tile list; the launch's
@@ -2185,12 +2431,56 @@ void vtile_tt(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev) {
   else LAUNCH_EV(ev, (k_vtile<T, TILE_UP, TT>), g, b, 0, s, a);
 }
 
+// The pipelined 64 x 64 pass for the modes, sweep counts and FP64 boundary
+// combinations of the mixed-precision cycles; false for the others.
+template <int MODE, int S, int IO>
+bool vpipe_io(const TileArgs<float>& a, hipStream_t s, LaunchEv ev) {
+  const int nt = (a.side + 63) / 64;
+  LAUNCH_EV(ev, (k_vtile_pipe<float, MODE, S, IO>), dim3(nt * nt), dim3(1024), 0, s, a);
+  return true;
+}
+
+template <int MODE, int S>
+bool vpipe_s(const TileArgs<float>& a, hipStream_t s, LaunchEv ev) {
+  const int io = (a.b64 ? 1 : 0) | (a.x64 ? 2 : 0);
+  if (io == 0) return vpipe_io<MODE, S, 0>(a, s, ev);
+  if constexpr (MODE == TILE_ZERO) {
+    if (io == 3) return vpipe_io<MODE, S, 3>(a, s, ev);
+  } else if constexpr (MODE == TILE_UP) {
+    if (io == 2) return vpipe_io<MODE, S, 2>(a, s, ev);
+  } else {
+    if (io == 1) return vpipe_io<MODE, S, 1>(a, s, ev);
+  }
+  return false;
+}
+
+template <int MODE>
+bool vpipe_mode(const TileArgs<float>& a, hipStream_t s, LaunchEv ev) {
+  constexpr bool UPLIKE = MODE == TILE_UP || MODE == TILE_UPM;
+  const int S = UPLIKE ? a.steps : a.steps - 1;
+  // the halo fits the 64 x 64 tiles' (tile_fits) and the sweeps are few
+  switch (S) {
+    case 0: return vpipe_s<MODE, 0>(a, s, ev);
+    case 1: return vpipe_s<MODE, 1>(a, s, ev);
+    case 2: return tile_halo(MODE, UPLIKE ? 2 : 3) <= TileCfg<64>::HMAX && vpipe_s<MODE, 2>(a, s, ev);
+    case 3: return tile_halo(MODE, UPLIKE ? 3 : 4) <= TileCfg<64>::HMAX && vpipe_s<MODE, 3>(a, s, ev);
+    default: return false;
+  }
+}
+
+bool vtile_pipe(int mode, const TileArgs<float>& a, hipStream_t s, LaunchEv ev) {
+  if (mode == TILE_ZERO) return vpipe_mode<TILE_ZERO>(a, s, ev);
+  if (mode == TILE_DOWN) return vpipe_mode<TILE_DOWN>(a, s, ev);
+  if (mode == TILE_UP) return vpipe_mode<TILE_UP>(a, s, ev);
+  return vpipe_mode<TILE_UPM>(a, s, ev);
+}
+
 template <typename T>
 void vtile(int mode, const TileArgs<T>& a, hipStream_t s, LaunchEv ev) {
   const int tt = tile_side<T>(a.side);
   if constexpr (sizeof(T) == 4) {
     if (tt == 64) {
-      vtile_tt<T, 64>(mode, a, s, ev);
+      if (!vtile_pipe(mode, a, s, ev)) vtile_tt<T, 64>(mode, a, s, ev);
       return;
     }
   }
