@@ -1459,7 +1459,10 @@ __global__ __launch_bounds__(BS) void k_ch_dots(int N, int side, const int* __re
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const int stride = gridDim.x * BS;
-  for (int row = blockIdx.x * BS + threadIdx.x; row < N; row += stride) {
+  // XCD-contiguous blocks: the mesh lines above and below a block's rows are
+  // mostly read through the same XCD's L2
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  for (int row = blk * BS + threadIdx.x; row < N; row += stride) {
     const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
     int c[W7];
     row_cols7(row, side, col, base, c);
