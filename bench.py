@@ -53,6 +53,9 @@ TRAFFIC = {
     # profiles/chac1024_dcgs_update_hbm_counters.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
     # per dispatch (the scales: the same counters on the 512 MiB negation probe)
     "k_dcgs_update": 152869730,
+    # profiles/chac1024_tile_hbm_counters.md: the five finest-level tile passes
+    # of a CH iteration (and the AC block's), averaged per launch like the ledger
+    "k_vtile_pipe (finest-level tile passes; k_vtile in FP64)": 57340000,
 }
 METRIC = "solve DOF·iters/s + ms per coupled step, mixed vs FP64 at 1e-8; HBM GB/s"
 

@@ -24,7 +24,7 @@ KERNEL_NAMES = {
     KERNEL_CH_BLOCK: "CH operator (k_ch_block; k_ch_dots with the dot pass)",
     KERNEL_DCGS_DOTS: "k_dcgs_dots",
     KERNEL_DCGS_UPDATE: "k_dcgs_update",
-    KERNEL_MG_FINE: "k_vtile (finest level)",
+    KERNEL_MG_FINE: "k_vtile_pipe (finest-level tile passes; k_vtile in FP64)",
 }
 F64, MIXED = 0, 1
 MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}
