@@ -129,6 +129,8 @@ def next_state(out):
 def step_vjp(ops: S.Operators, prm: Params, st, st1, lam1):
     """Adjoint of one ternary step: (lambda^k, dL/dtheta contribution) from the
     state s^k, the state s^{k+1} it produced and lambda^{k+1}."""
+    if prm.rho_pure is not None or prm.picard > 1:
+        raise NotImplementedError("the reverse step covers the linear scheme with constant density")
     n, N = ops.n, ops.n * ops.n
     m, M, K = ops.mesh, ops.M, ops.K
     eps, tau, gam, gv = prm.eps, prm.tau, prm.gamma, prm.gamma_v

@@ -197,6 +197,24 @@ def p2_mass(m: Mesh):
     return _scatter(m.tri2, m.tri2, Ae, (4 * m.nv, 4 * m.nv))
 
 
+def p2_mass_weighted(m: Mesh, rho_p1):
+    """Scalar P2 mass weighted by a P1 field: int rho psi_m psi_n, rho the P1
+    interpolant of the nodal values rho_p1 (degree 5: the 7-point rule is
+    exact).  The variable-density mass rho^k M of eq. (matrixns)."""
+    psi = p2_basis(QP)
+    rq = np.einsum("qa,ea->eq", p1_basis(QP), rho_p1[m.tri])
+    Ae = np.einsum("e,q,eq,qa,qb->eab", m.area, QW, rq, psi, psi)
+    return _scatter(m.tri2, m.tri2, Ae, (4 * m.nv, 4 * m.nv))
+
+
+def p1_mass_weighted(m: Mesh, rho_p1):
+    """P1 mass weighted by a P1 field: int rho phi_i phi_j (exact)."""
+    phi = p1_basis(QP)
+    rq = np.einsum("qa,ea->eq", phi, rho_p1[m.tri])
+    Ae = np.einsum("e,q,eq,qa,qb->eab", m.area, QW, rq, phi, phi)
+    return _scatter(m.tri, m.tri, Ae, (m.nv, m.nv))
+
+
 def p2_stiffness(m: Mesh):
     """Scalar P2 stiffness matrix int grad psi_j . grad psi_i."""
     G = _p2_grads(m)

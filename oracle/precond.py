@@ -87,10 +87,12 @@ class ACPreconditioner:
         return mg.mg_solve(self.H, r, **self.mgkw)
 
 
-def pcd_matrix(M, K, Cw, prm):
+def pcd_matrix(M, K, Cw, prm, Mrho=None):
     """A_p = (rho/tau) M_p + eta K_p + N_p(w): the convection-diffusion operator
-    of the velocity block discretised on the pressure space."""
-    A = (prm.rho / prm.tau) * M + prm.viscosity * K
+    of the velocity block discretised on the pressure space (Mrho / tau, the
+    density-weighted P1 mass, for variable density)."""
+    mass = (prm.rho / prm.tau) * M if Mrho is None else Mrho / prm.tau
+    A = mass + prm.viscosity * K
     if Cw is not None:
         A = A + Cw
     return A.tocsr()

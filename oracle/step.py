@@ -98,6 +98,15 @@ def explicit_terms(model, st, prm: Params | None = None):
     return [t["dp"], t["dn"]], t["fv"]
 
 
+def convecting_field(n: int, prm: Params, rho_k, vel):
+    """The P2 field rho v of the Oseen convection (eq. (matrixns)): rho v with
+    constant density, else the P2 interpolant of the nodal product of rho^k
+    (its P1 interpolant at the P2 nodes) and v."""
+    if rho_k is None:
+        return prm.rho * vel
+    return fem.p2_eval_p1_interp(n, rho_k)[None, :] * vel
+
+
 def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
          return_systems: bool = False):
     """Advance one step; ``how`` in {"dense", "splu", "fft"} (fft needs v = 0)."""
@@ -144,14 +153,25 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         betas = [prm.beta, prm.beta, prm.beta, prm.beta_v]
         mu_grads = [fem.p1_grad(mesh, u) for u in (st["mu"][0], st["mu"][1], st["mu_s"])]
         w_const = -prm.alpha * (mu_grads[0] + mu_grads[1] + mu_grads[2])
-        J = fem.p2_convection(mesh, prm.rho * vel, w_const)
-        Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm)
+        rho_k = systems.density(prm, st["phi"][0], st["phi"][1])
+        Mrho = None if rho_k is None else fem.p2_mass_weighted(mesh, rho_k)
         F = fem.korteweg_load(mesh, grads, betas)
-        rhs = systems.oseen_rhs(ops.Mv, vel, F, prm)
-        sysrec["ns_A"], sysrec["ns_rhs"] = Avel, rhs
-        v, p, _ = solvers.bordered_oseen_solve(Avel, ops.B, M, rhs, dense=(how == "dense"))
+        rhs = systems.oseen_rhs(ops.Mv, vel, F, prm, Mrho)
         N2 = 4 * n * n
-        out["vel"] = np.stack([v[:N2], v[N2:]])
+        conv = vel  # the velocity the convecting field is formed with
+        for m in range(max(1, prm.picard)):
+            used = conv
+            J = fem.p2_convection(mesh, convecting_field(n, prm, rho_k, conv), w_const)
+            Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm, Mrho)
+            v, p, _ = solvers.bordered_oseen_solve(Avel, ops.B, M, rhs, dense=(how == "dense"))
+            v = np.stack([v[:N2], v[N2:]])
+            change = np.linalg.norm(v - conv) / max(np.linalg.norm(v), 1e-300)
+            conv = v
+            if m > 0 and change <= prm.picard_tol:
+                break
+        sysrec["ns_A"], sysrec["ns_rhs"], sysrec["ns_passes"] = Avel, rhs, m + 1
+        sysrec["ns_Mrho"], sysrec["ns_conv_vel"], sysrec["ns_w_const"] = Mrho, used, w_const
+        out["vel"] = v
         out["p"] = p
         ps1 = 1.0 - phis[0] - phis[1]
         fs_k = ternary_potential(prm, st["phi"][0], st["phi"][1], st["Phi_v"])["fs"]

@@ -8,7 +8,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   linear system after the discrete AC equation): (M + tau delta_v K + tau C) Phi
   = M Phi^k - tau gamma_v f_v^k.
 * Oseen saddle point, eq. (linearnav): [[A, B^T], [B, 0]] with
-  A = (rho/tau) M + J(w^k) + K_sym and right-hand side (rho/tau) M v^k + F^k.
+  A = (rho/tau) M + J(w^k) + K_sym and right-hand side (rho/tau) M v^k + F^k;
+  with variable density rho^k M is the mass weighted by the P1 field rho^k.
 
 Parameter readings: beta_i = beta_v = eps^2, gamma_i = mobility,
 gamma_v = evaporation rate, delta_v = gamma_v eps^2, rho = 1, alpha_i = alpha.
@@ -36,6 +37,15 @@ class Params:
     # phase fields of eq. (truncateCH)
     potential: object = None
     truncate: bool = False
+    # variable density (eq. (matrixns)): rho^k = sum_i rho_i phi_i^k with the
+    # pure densities (polymer, NFA, solvent) and phi_s = 1 - phi_p - phi_N (air
+    # set to zero); None: the constant rho above
+    rho_pure: tuple | None = None
+    # Picard passes of the Oseen solve per step: pass m convects with the
+    # velocity of pass m - 1 (pass 1 with v^k, the linear scheme); stop early
+    # when the relative 2-norm change of the velocity is <= picard_tol
+    picard: int = 1
+    picard_tol: float = 0.0
 
     @property
     def beta(self):
@@ -80,10 +90,12 @@ def ac_rhs(M, Phi_k, fv, prm: Params):
     return M @ Phi_k - prm.tau * prm.gamma_v * (M @ fv)
 
 
-def oseen_velocity_block(Mv, J, Ksym, prm: Params):
-    """A = (rho/tau) M (per component) + J (per component) + K_sym."""
-    N2 = Mv.shape[0]
-    diag = (prm.rho / prm.tau) * Mv + J
+def oseen_velocity_block(Mv, J, Ksym, prm: Params, Mrho=None):
+    """A = (rho/tau) M (per component) + J (per component) + K_sym; with the
+    density-weighted scalar mass Mrho (int rho^k psi_m psi_n), Mrho / tau in
+    place of (rho/tau) M."""
+    mass = (prm.rho / prm.tau) * Mv if Mrho is None else Mrho / prm.tau
+    diag = mass + J
     return (sp.bmat([[diag, None], [None, diag]], format="csr") + Ksym).tocsr()
 
 
@@ -91,7 +103,19 @@ def oseen_matrix(Avel, B):
     return sp.bmat([[Avel, B.T], [B, None]], format="csr")
 
 
-def oseen_rhs(Mv, v_k, F, prm: Params):
-    N2 = Mv.shape[0]
-    mv = np.concatenate([Mv @ v_k[0], Mv @ v_k[1]])
-    return np.concatenate([(prm.rho / prm.tau) * mv + F])
+def oseen_rhs(Mv, v_k, F, prm: Params, Mrho=None):
+    """(rho/tau) M v^k + F^k (Mrho v^k / tau with the density-weighted mass)."""
+    if Mrho is None:
+        mv = (prm.rho / prm.tau) * np.concatenate([Mv @ v_k[0], Mv @ v_k[1]])
+    else:
+        mv = np.concatenate([Mrho @ v_k[0], Mrho @ v_k[1]]) / prm.tau
+    return mv + F
+
+
+def density(prm: Params, pp, pn):
+    """rho^k at the vertices: sum_i rho_i phi_i^k over polymer, NFA and the
+    eliminated solvent (air zero); None for constant density."""
+    if prm.rho_pure is None:
+        return None
+    rp, rn, rs = prm.rho_pure
+    return rp * pp + rn * pn + rs * (1.0 - pp - pn)
