@@ -119,6 +119,17 @@ typedef struct {
   double fh_nsize[3];    /* Flory-Huggins molar sizes N_p, N_NFA, N_s (> 0) */
   double fh_chi[3];      /* interaction parameters chi_(p,NFA), chi_(p,s), chi_(NFA,s) */
   double fh_phisat[3];   /* saturated vapour fractions of p, NFA, s, in (0, 1] */
+  /* ternary model only (else 0): */
+  int32_t var_density;   /* 1: the Oseen step's density is the field rho^k = sum_i rho_pure[i]
+                            phi_i^k of eq. (matrixns) (polymer, NFA, solvent phi_s = 1 - phi_p -
+                            phi_N, air zero): the velocity mass int rho^k psi_m psi_n, the
+                            convecting field the P2 interpolant of the nodal rho^k v^k, and the
+                            PCD matrix's mass weighted alike; 0: the constant rho above */
+  int32_t ns_picard;     /* Oseen solves per step (<= 1: one, the linear scheme): solve m convects
+                            with the velocity of solve m - 1 (the outer iteration the remark on
+                            Newton schemes after eq. (linearnav) implies); 1..100 */
+  double rho_pure[3];    /* pure densities of polymer, NFA, solvent (> 0) when var_density */
+  double ns_picard_tol;  /* stop the solves once ||v^(m) - v^(m-1)||_2 <= tol ||v^(m)||_2 (>= 0) */
 } chns_params;
 
 typedef struct {
@@ -143,6 +154,9 @@ typedef struct {
   double res0;        /* ||b - A x0||_2 */
   double res_true;    /* ||b - A x||_2 of the returned iterate (recomputed) */
   double ms;          /* wall time of the solve in milliseconds (hipEvent) */
+  int32_t passes;     /* Oseen solve with ns_picard > 1: solves made (iters, restarts and ms
+                         summed over them, converged of all, the rest of the last); else 1 */
+  double change;      /* the last solve's ||v^(m) - v^(m-1)||_2 / ||v^(m)||_2 (Oseen, else 0) */
 } chns_solve_info;
 
 /* Field set at one time level (device pointers; NULL where the model has no
@@ -204,6 +218,14 @@ CHNS_API int chns_destroy(chns_ctx* ctx);
  * before enqueuing more work); after chns_set_params the first solve of each
  * block runs without that prediction.  Synchronising on return. */
 CHNS_API int chns_set_params(chns_ctx* ctx, const chns_params* params);
+
+/* Variable density (eq. (matrixns), ternary contexts with var_density): form
+ * rho^k = sum_i rho_pure[i] phi_i^k from the device fields d_phi_p, d_phi_n
+ * (N each; phi_s = 1 - phi_p - phi_N) and the density-weighted velocity and
+ * pressure masses; the next chns_assemble convects with rho^k v.
+ * chns_timestep calls it on its input state.  CHNS_EINVAL for other
+ * contexts or NULL fields. */
+CHNS_API int chns_set_density(chns_ctx* ctx, const double* d_phi_p, const double* d_phi_n, void* stream);
 
 /* Per-step assembly (paper: C(v^k) of eq. (CH_linear); J(w^k) and the PCD
  * matrix A_p(w^k) for the Oseen step): coloured element scatter of the
@@ -360,7 +382,9 @@ CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fiel
  * s^k; h_info (4 entries, may be NULL) receives their reports.  The initial
  * state of a run is data (independent of theta).  Leaves the context holding
  * the transposed operators.  Returns CHNS_WNOCONV if a solve did not
- * converge; CHNS_EUNSUPPORTED for the binary models.  Synchronising. */
+ * converge; CHNS_EUNSUPPORTED for the binary models and for var_density or
+ * ns_picard > 1 (the reverse step covers the linear constant-density scheme).
+ * Synchronising. */
 CHNS_API int chns_timestep_adjoint(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
                                    const chns_fields* lam_out, const chns_fields* lam_in,
                                    double* h_dtheta, const chns_solve_opts* opts,

@@ -30,7 +30,7 @@ F64, MIXED = 0, 1
 MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}
 
 EXPORTS = [
-    "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble",
+    "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble", "chns_set_density",
     "chns_matrix_shape", "chns_get_matrix", "chns_spmv", "chns_precond_apply",
     "chns_krylov_solve", "chns_step_rhs", "chns_diagnostics", "chns_diagnostics_noalloc",
     "chns_timestep", "chns_last_error",
@@ -56,10 +56,12 @@ class Params(ct.Structure):
     _fields_ = [(k, ct.c_double) for k in
                 ("eps", "tau", "mobility", "evap_rate", "viscosity", "alpha", "rho")] + \
                [("potential", ct.c_int32), ("truncate", ct.c_int32), ("fh_nsize", ct.c_double * 3),
-                ("fh_chi", ct.c_double * 3), ("fh_phisat", ct.c_double * 3)]
+                ("fh_chi", ct.c_double * 3), ("fh_phisat", ct.c_double * 3),
+                ("var_density", ct.c_int32), ("ns_picard", ct.c_int32), ("rho_pure", ct.c_double * 3),
+                ("ns_picard_tol", ct.c_double)]
 
     def __init__(self, *args, **kw):
-        arrays = {k: kw.pop(k) for k in ("fh_nsize", "fh_chi", "fh_phisat") if k in kw}
+        arrays = {k: kw.pop(k) for k in ("fh_nsize", "fh_chi", "fh_phisat", "rho_pure") if k in kw}
         super().__init__(*args, **kw)
         for k, v in arrays.items():
             setattr(self, k, (ct.c_double * 3)(*v))
@@ -75,7 +77,8 @@ class SolveOpts(ct.Structure):
 class SolveInfo(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("restarts", ct.c_int32), ("converged", ct.c_int32),
                 ("status", ct.c_int32), ("bnorm", ct.c_double), ("res0", ct.c_double),
-                ("res_true", ct.c_double), ("ms", ct.c_double)]
+                ("res_true", ct.c_double), ("ms", ct.c_double), ("passes", ct.c_int32),
+                ("change", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -146,6 +149,7 @@ def lib():
     L.chns_destroy.argtypes = [vp]
     L.chns_set_params.argtypes = [vp, ct.POINTER(Params)]
     L.chns_assemble.argtypes = [vp, vp, vp, vp]
+    L.chns_set_density.argtypes = [vp, vp, vp, vp]
     L.chns_matrix_shape.argtypes = [vp, i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                                     ct.POINTER(ct.c_int64)]
     L.chns_get_matrix.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -274,6 +278,11 @@ class Context:
         self._mu_keep = mu
         return (ct.c_void_p * 3)(*[_ptr(t, self.N, name=f"mu[{i}]", optional=True)
                                    for i, t in enumerate(mu)])
+
+    def set_density(self, phi_p, phi_n):
+        """rho^k from the phase fields for the next assemble (var_density)."""
+        self._check(self.L.chns_set_density(self.h, _ptr(phi_p, self.N, name="phi_p"),
+                                            _ptr(phi_n, self.N, name="phi_n"), _stream()))
 
     def assemble(self, vel=None, mu=None):
         self._check(self.L.chns_assemble(self.h, _ptr(vel, 8 * self.N, name="vel", optional=True),

@@ -190,6 +190,14 @@ int check_params(chns_ctx* c, const chns_params* p) {
   if (p->potential != CHNS_POT_QUARTIC && p->potential != CHNS_POT_FLORY_HUGGINS)
     return fail(c, CHNS_EINVAL, "unknown potential");
   if (p->truncate != 0 && p->truncate != 1) return fail(c, CHNS_EINVAL, "truncate must be 0 or 1");
+  if (p->var_density != 0 && p->var_density != 1) return fail(c, CHNS_EINVAL, "var_density must be 0 or 1");
+  if (p->var_density)
+    for (int i = 0; i < 3; ++i)
+      if (!is_finite(p->rho_pure[i]) || !(p->rho_pure[i] > 0.0))
+        return fail(c, CHNS_EINVAL, "pure densities must be positive");
+  if (p->ns_picard < 0 || p->ns_picard > 100) return fail(c, CHNS_EINVAL, "ns_picard must be in 0..100");
+  if (!is_finite(p->ns_picard_tol) || p->ns_picard_tol < 0.0)
+    return fail(c, CHNS_EINVAL, "ns_picard_tol must be >= 0");
   if (p->potential == CHNS_POT_FLORY_HUGGINS)
     for (int i = 0; i < 3; ++i) {
       if (!is_finite(p->fh_nsize[i]) || !(p->fh_nsize[i] > 0.0))
@@ -262,16 +270,21 @@ int form_operators(chns_ctx* c, hipStream_t s) {
 // PCD matrix A_p = (rho/tau) M + eta K + N_p(w) on the finest P1 level.
 int form_ternary(chns_ctx* c, hipStream_t s) {
   const auto& p = c->prm;
-  const double cm = p.rho / p.tau;
-  c->coefV[0] = cm;
-  c->coefV[1] = 1.5 * p.viscosity;  // the xx/yy forms have a P1 diagonal of 6 eta
   P2Level& P = c->p2;
+  Level& L0 = c->lv[0];
+  // mass terms: (rho/tau) M, or (1/tau) times the rho^k-weighted masses
+  const bool vd = p.var_density != 0;
+  const double cm = vd ? 1.0 / p.tau : p.rho / p.tau;
+  const double* Mvel = vd ? P.Mr : P.Mv;
+  const double* Mpcd = vd ? L0.Mrp : L0.M;
+  // the hierarchy cut takes the smallest density's diagonal weight
+  c->coefV[0] = vd ? std::min({p.rho_pure[0], p.rho_pure[1], p.rho_pure[2]}) / p.tau : cm;
+  c->coefV[1] = 1.5 * p.viscosity;  // the xx/yy forms have a P1 diagonal of 6 eta
   const int64_t ns2 = P.sell.slots();
-  combine(ns2, cm, P.Mv, 1.0, P.J, 1.0, P.Kxx, P.Vx.v64, P.Vx.v32, s);
-  combine(ns2, cm, P.Mv, 1.0, P.J, 1.0, P.Kyy, P.Vy.v64, P.Vy.v32, s);
+  combine(ns2, cm, Mvel, 1.0, P.J, 1.0, P.Kxx, P.Vx.v64, P.Vx.v32, s);
+  combine(ns2, cm, Mvel, 1.0, P.J, 1.0, P.Kyy, P.Vy.v64, P.Vy.v32, s);
   diag_inverse(P.N4, P.diag, P.Vx.v64, P.Vx.d64, P.Vx.d32, s);
   diag_inverse(P.N4, P.diag, P.Vy.v64, P.Vy.d64, P.Vy.d32, s);
-  Level& L0 = c->lv[0];
   galerkin(L0.sell.slots(), P.gptr, P.gsrc, P.gw, P.Vx.v64, L0.Vx.v64, s);
   galerkin(L0.sell.slots(), P.gptr, P.gsrc, P.gw, P.Vy.v64, L0.Vy.v64, s);
   for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
@@ -287,9 +300,9 @@ int form_ternary(chns_ctx* c, hipStream_t s) {
     diag_inverse(L.N, L.diag, L.Vx.v64, L.Vx.d64, L.Vx.d32, s);
     diag_inverse(L.N, L.diag, L.Vy.v64, L.Vy.d64, L.Vy.d32, s);
   }
-  form_ns(c->ns.sell.slots(), c->ns.kind, c->ns.src, cm, P.Mv, P.J, P.Kxx, P.Kxy, P.Kyx, P.Kyy,
+  form_ns(c->ns.sell.slots(), c->ns.kind, c->ns.src, cm, Mvel, P.J, P.Kxx, P.Kxy, P.Kyx, P.Kyy,
           c->ns.B, c->ns.val, s);
-  combine(L0.sell.slots(), cm, L0.M, p.viscosity, L0.K, 1.0, L0.Cw, L0.Ap.v64, L0.Ap.v32, s);
+  combine(L0.sell.slots(), cm, Mpcd, p.viscosity, L0.K, 1.0, L0.Cw, L0.Ap.v64, L0.Ap.v32, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -343,31 +356,76 @@ int transpose_values(chns_ctx* c, int64_t n, const int* tmap, double* val, hipSt
   return CHNS_OK;
 }
 
+// The Oseen convection J(w) and the PCD convection N_p(w) of the ternary
+// model, w = rho v - alpha sum_i grad mu_i (rho^k v at the P2 nodes with
+// variable density).
+int assemble_ternary_conv(chns_ctx* c, const double* d_vel, const double* const* d_mu, bool transposed,
+                          hipStream_t s) {
+  Level& L0 = c->lv[0];
+  P2Level& P = c->p2;
+  MuGrad mg{{nullptr, nullptr, nullptr}, c->prm.alpha};
+  if (d_mu)
+    for (int i = 0; i < 3; ++i) mg.mu[i] = d_mu[i];
+  HIPCHK(c, hipMemsetAsync(P.J, 0, P.sell.slots() * sizeof(double), s));
+  HIPCHK(c, hipMemsetAsync(L0.Cw, 0, L0.sell.slots() * sizeof(double), s));
+  double* jo[1] = {P.J};
+  const double* rho2 = c->prm.var_density ? c->rho2 : nullptr;
+  for (int col = 0; col < 8; ++col) {
+    const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
+    assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb, 0.0,
+                d_vel, c->prm.rho, 4 * int64_t(c->N), mg, jo, s, rho2);
+    assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, 1.0 / c->mesh.n, d_vel, c->prm.rho,
+                     4 * int64_t(c->N), mg, L0.Cw, s, rho2);
+  }
+  HIPCHK(c, hipGetLastError());
+  if (transposed) {
+    TRY(transpose_values(c, P.sell.slots(), c->tslot2, P.J, s));
+    TRY(transpose_values(c, L0.sell.slots(), c->tslot1, L0.Cw, s));
+  }
+  return CHNS_OK;
+}
+
+// Variable density: rho^k = sum_i rho_i phi_i^k at the vertices and the P2
+// nodes, and the masses weighted by it: the P2 velocity mass (int rho psi_m
+// psi_n) and the finest-level P1 mass of the PCD matrix.
+int weighted_masses(chns_ctx* c, hipStream_t s);
+
+int set_density(chns_ctx* c, const double* php, const double* phn, hipStream_t s) {
+  density_fields(c->mesh.n, php, phn, c->prm.rho_pure, c->rho1, c->rho2, s);
+  return weighted_masses(c, s);
+}
+
+// Before the first chns_set_density: the uniform density rho.
+int uniform_density(chns_ctx* c, hipStream_t s) {
+  fill(c->N, c->prm.rho, c->rho1, s);
+  fill(4 * int64_t(c->N), c->prm.rho, c->rho2, s);
+  return weighted_masses(c, s);
+}
+
+int weighted_masses(chns_ctx* c, hipStream_t s) {
+  P2Level& P = c->p2;
+  Level& L0 = c->lv[0];
+  const double h = 1.0 / c->mesh.n;
+  const int64_t n2 = 4 * int64_t(c->N);
+  HIPCHK(c, hipMemsetAsync(P.Mr, 0, P.sell.slots() * sizeof(double), s));
+  HIPCHK(c, hipMemsetAsync(L0.Mrp, 0, L0.sell.slots() * sizeof(double), s));
+  double* mo[1] = {P.Mr};
+  const MuGrad none{{nullptr, nullptr, nullptr}, 0.0};
+  for (int col = 0; col < 8; ++col) {
+    const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
+    assemble_p2(3, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, h, c->ns.tb, 0.0, nullptr, 0.0, n2,
+                none, mo, s, c->rho1);
+    assemble_p1(3, e0, e1, c->ep2, c->etype, c->eslot, h, nullptr, n2, L0.Mrp, s, c->rho1);
+  }
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
 int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bool transposed,
                  hipStream_t s) {
   if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
   Level& L0 = c->lv[0];
-  if (c->ternary) {
-    P2Level& P = c->p2;
-    MuGrad mg{{nullptr, nullptr, nullptr}, c->prm.alpha};
-    if (d_mu)
-      for (int i = 0; i < 3; ++i) mg.mu[i] = d_mu[i];
-    HIPCHK(c, hipMemsetAsync(P.J, 0, P.sell.slots() * sizeof(double), s));
-    HIPCHK(c, hipMemsetAsync(L0.Cw, 0, L0.sell.slots() * sizeof(double), s));
-    double* jo[1] = {P.J};
-    for (int col = 0; col < 8; ++col) {
-      const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
-      assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb,
-                  0.0, d_vel, c->prm.rho, 4 * int64_t(c->N), mg, jo, s);
-      assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, 1.0 / c->mesh.n, d_vel,
-                       c->prm.rho, 4 * int64_t(c->N), mg, L0.Cw, s);
-    }
-    HIPCHK(c, hipGetLastError());
-    if (transposed) {
-      TRY(transpose_values(c, P.sell.slots(), c->tslot2, P.J, s));
-      TRY(transpose_values(c, L0.sell.slots(), c->tslot1, L0.Cw, s));
-    }
-  }
+  if (c->ternary) TRY(assemble_ternary_conv(c, d_vel, d_mu, transposed, s));
   if (d_vel) {
     c->c_zero = false;
     TRY(assemble_base(c, 2, L0.C, d_vel, s));
@@ -1391,9 +1449,10 @@ int build_ternary_tables(chns_ctx* c) {
   S.tb.T2 = S.tb.T3 + 648;
   S.tb.TB = S.tb.T2 + 108;
   S.tb.TI = S.tb.TB + 54;
+  S.tb.MW = S.tb.TI + 18;
   // values and vectors
   const size_t ns2 = P.sell.slots(), n4 = P.N4;
-  for (double** v : {&P.Mv, &P.J, &P.Kxx, &P.Kxy, &P.Kyx, &P.Kyy}) TRY(dalloc(c, v, ns2));
+  for (double** v : {&P.Mv, &P.J, &P.Kxx, &P.Kxy, &P.Kyx, &P.Kyy, &P.Mr}) TRY(dalloc(c, v, ns2));
   for (OpVals* o : {&P.Vx, &P.Vy}) {
     TRY(dalloc(c, &o->v64, ns2));
     TRY(dalloc(c, &o->v32, ns2));
@@ -1503,6 +1562,7 @@ int build(chns_ctx* c) {
         TRY(dalloc(c, &L.Ap.v32, ns));
         TRY(dalloc(c, &L.Cw, ns));
         HIPCHK(c, hipMemset(L.Cw, 0, ns * sizeof(double)));
+        TRY(dalloc(c, &L.Mrp, ns));
       }
     }
     for (double** v : {&L.b64, &L.x64, &L.t64, &L.r64, &L.e64, &L.d64}) TRY(dalloc(c, v, N));
@@ -1541,8 +1601,13 @@ int build(chns_ctx* c) {
   for (double** v : {&c->w64a, &c->w64b, &c->w64c, &c->w64d, &c->rhs_ac, &c->xac, &c->fs})
     TRY(dalloc(c, v, N1));
   for (double** v : {&c->rhs_ch, &c->xch}) TRY(dalloc(c, v, 2 * N2));
-  if (c->ternary)
+  if (c->ternary) {
     for (double** v : {&c->rhs_ns, &c->xns}) TRY(dalloc(c, v, 9 * N1));
+    TRY(dalloc(c, &c->rho1, N1));
+    TRY(dalloc(c, &c->rho2, 4 * N1));
+    TRY(dalloc(c, &c->vprev, 8 * N1));
+    TRY(dalloc(c, &c->pic, 2 * 256 + 2));
+  }
   for (float** v : {&c->r32, &c->z32}) TRY(dalloc(c, v, NB));
   for (float** v : {&c->w32a, &c->w32b, &c->w32c}) TRY(dalloc(c, v, N1));
   TRY(dalloc(c, &c->red, 1024));
@@ -1628,6 +1693,7 @@ int build(chns_ctx* c) {
       assemble_b(e0, e1, c->etype, c->ns.eslotb, 1.0 / c->mesh.n, c->ns.tb, c->ns.B, s);
     }
     TRY(assemble_sym_stiffness(c, s));
+    TRY(uniform_density(c, s));
   }
   TRY(form_operators(c, s));
   HIPCHK(c, hipDeviceSynchronize());
@@ -1667,9 +1733,11 @@ int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_
               -p.tau * p.evap_rate, pot_coef(p), rhs_ch, rhs_ch + 2 * int64_t(N), rhs_ac, fs, s);
   P2Level& P = c->p2;
   const int64_t N4 = 4 * int64_t(N);
-  const double cm = p.rho / p.tau;
-  spmv<double, double>(P.d, P.Mv, in->vel, rhs_ns, cm, 0.0, s);
-  spmv<double, double>(P.d, P.Mv, in->vel + N4, rhs_ns + N4, cm, 0.0, s);
+  // (rho/tau) M v^k, or M_rho v^k / tau with the weighted mass of chns_set_density
+  const double cm = p.var_density ? 1.0 / p.tau : p.rho / p.tau;
+  const double* Mvel = p.var_density ? P.Mr : P.Mv;
+  spmv<double, double>(P.d, Mvel, in->vel, rhs_ns, cm, 0.0, s);
+  spmv<double, double>(P.d, Mvel, in->vel + N4, rhs_ns + N4, cm, 0.0, s);
   HIPCHK(c, hipMemsetAsync(rhs_ns + 2 * N4, 0, N * sizeof(double), s));
   for (int col = 0; col < 8; ++col)
     korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
@@ -1681,6 +1749,54 @@ int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_
 int chns_solve_block(chns_ctx* c, int block, const double* b, double* x, const chns_solve_opts& o,
                      chns_solve_info** info, int& worst, hipStream_t s);
 
+// ||v - w||_2 / ||v||_2 for the velocity part of the Oseen unknown (read back).
+int velocity_change(chns_ctx* c, const double* w, double* out, hipStream_t s) {
+  double nrm[2];
+  diff_norms(8 * int64_t(c->N), c->xns, w, c->pic, c->pic + 512, s);
+  HIPCHK(c, hipMemcpyAsync(nrm, c->pic + 512, sizeof(nrm), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *out = nrm[1] > 0.0 ? nrm[0] / nrm[1] : 0.0;
+  return CHNS_OK;
+}
+
+// Picard passes of the Oseen solve: solve m convects with the velocity of
+// solve m - 1 (mu and rho at level k, same right-hand side, warm start), until
+// the relative change of the velocity is <= ns_picard_tol or ns_picard solves
+// are made.  Their reports are merged into the first solve's (rec).
+int picard_passes(chns_ctx* c, const chns_fields& cur, const double* const* mu3, const chns_solve_opts& o,
+                  chns_solve_info* rec, int& worst, hipStream_t s) {
+  const size_t vbytes = 8 * size_t(c->N) * sizeof(double);
+  double change = 0.0;
+  TRY(velocity_change(c, cur.vel, &change, s));
+  int passes = 1;
+  for (int m = 1; m < c->prm.ns_picard; ++m) {
+    HIPCHK(c, hipMemcpyAsync(c->vprev, c->xns, vbytes, hipMemcpyDeviceToDevice, s));
+    TRY(assemble_ternary_conv(c, c->vprev, mu3, false, s));
+    TRY(form_ternary(c, s));
+    chns_solve_info inf{};
+    chns_solve_info* ip = &inf;
+    TRY(chns_solve_block(c, CHNS_BLOCK_NS, c->rhs_ns, c->xns, o, &ip, worst, s));
+    ++passes;
+    TRY(velocity_change(c, c->vprev, &change, s));
+    if (rec) {
+      rec->iters += inf.iters;
+      rec->restarts += inf.restarts;
+      rec->converged = rec->converged && inf.converged;
+      if (inf.status != CHNS_OK) rec->status = inf.status;
+      rec->bnorm = inf.bnorm;
+      rec->res0 = inf.res0;
+      rec->res_true = inf.res_true;
+      rec->ms += inf.ms;
+    }
+    if (change <= c->prm.ns_picard_tol) break;
+  }
+  if (rec) {
+    rec->passes = passes;
+    rec->change = change;
+  }
+  return CHNS_OK;
+}
+
 // One ternary step from `cur` into `out` (all outputs written at the end, so
 // the two field sets may coincide).
 int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
@@ -1689,6 +1805,7 @@ int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   const size_t bytes = size_t(N) * sizeof(double);
   const double beta = c->prm.eps * c->prm.eps;
   const double* mu3[3] = {cur.mu[0], cur.mu[1], cur.mu[2]};
+  if (c->prm.var_density) TRY(set_density(c, cur.phi[0], cur.phi[1], s));
   TRY(chns_assemble(c, cur.vel, mu3, s));
   TRY(ternary_rhs(c, &cur, c->rhs_ch, c->rhs_ac, c->rhs_ns, c->fs, s));
   double* xch = c->xch;
@@ -1702,7 +1819,9 @@ int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   TRY(chns_solve_block(c, CHNS_BLOCK_CH, c->rhs_ch, xch, o, info, worst, s));
   TRY(chns_solve_block(c, CHNS_BLOCK_CH, c->rhs_ch + 2 * size_t(N), xch + 2 * size_t(N), o, info, worst, s));
   TRY(chns_solve_block(c, CHNS_BLOCK_AC, c->rhs_ac, c->xac, o, info, worst, s));
+  chns_solve_info* ns_rec = (info && *info) ? *info : nullptr;  // the Oseen solve's report
   TRY(chns_solve_block(c, CHNS_BLOCK_NS, c->rhs_ns, c->xns, o, info, worst, s));
+  if (c->prm.ns_picard > 1) TRY(picard_passes(c, cur, mu3, o, ns_rec, worst, s));
   for (int ph = 0; ph < 2; ++ph) {
     HIPCHK(c, hipMemcpyAsync(out->phi[ph], xch + 2 * ph * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(out->mu[ph], xch + (2 * ph + 1) * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
@@ -1823,6 +1942,7 @@ int chns_solve_block(chns_ctx* c, int block, const double* b, double* x, const c
                      chns_solve_info** info, int& worst, hipStream_t s) {
   chns_solve_info inf{};
   const int rc = fgmres(c, block, b, x, o, &inf, s);
+  inf.passes = 1;
   if (rc < 0) return rc;
   if (rc > worst) worst = rc;
   if (info && *info) *(*info)++ = inf;
@@ -1879,6 +1999,10 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = "the Flory-Huggins density and the truncation apply to the ternary model";
     return CHNS_EINVAL;
   }
+  if (mesh->model != CHNS_MODEL_TERNARY && (params->var_density || params->ns_picard > 1)) {
+    g_create_err = "variable density and Picard passes apply to the ternary model";
+    return CHNS_EINVAL;
+  }
   chns_ctx* c = new chns_ctx();
   c->alloc = alloc;
   c->free_ = free_;
@@ -1919,6 +2043,8 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
   TRY(check_params(c, p));
   if (!c->ternary && (p->potential != CHNS_POT_QUARTIC || p->truncate))
     return fail(c, CHNS_EINVAL, "the Flory-Huggins density and the truncation apply to the ternary model");
+  if (!c->ternary && (p->var_density || p->ns_picard > 1))
+    return fail(c, CHNS_EINVAL, "variable density and Picard passes apply to the ternary model");
   c->prm = *p;
   // the residual reduction rates of earlier solves belong to other systems
   for (double& r : c->kr.rate) r = -1.0;
@@ -1931,6 +2057,14 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
 int chns_assemble(chns_ctx* c, const double* d_vel, const double* const* d_mu, void* stream) {
   if (!c) return CHNS_EINVAL;
   return assemble_ops(c, d_vel, d_mu, false, static_cast<hipStream_t>(stream));
+}
+
+int chns_set_density(chns_ctx* c, const double* d_phi_p, const double* d_phi_n, void* stream) {
+  if (!c) return CHNS_EINVAL;
+  if (!c->ternary || !c->prm.var_density)
+    return fail(c, CHNS_EINVAL, "the density field needs a ternary context with var_density");
+  if (!d_phi_p || !d_phi_n) return fail(c, CHNS_EINVAL, "phi_p and phi_n are required");
+  return set_density(c, d_phi_p, d_phi_n, static_cast<hipStream_t>(stream));
 }
 
 int chns_assemble_transposed(chns_ctx* c, const double* d_vel, const double* const* d_mu, void* stream) {
@@ -2142,6 +2276,7 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
   if (c->ternary) {
     if (!in->phi[1] || !in->Phi_v || !in->vel || !d_rhs_ac || !d_rhs_ns)
       return fail(c, CHNS_EINVAL, "the ternary model needs phi[0..1], Phi_v, vel and all outputs");
+    if (c->prm.var_density) TRY(set_density(c, in->phi[0], in->phi[1], static_cast<hipStream_t>(stream)));
     return ternary_rhs(c, in, d_rhs_ch, d_rhs_ac, d_rhs_ns, c->fs, static_cast<hipStream_t>(stream));
   }
   const bool ac = c->mesh.model == CHNS_MODEL_CH_AC;
@@ -2262,6 +2397,8 @@ int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields*
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
   if (!c->ternary) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is defined for the ternary model");
+  if (c->prm.var_density || c->prm.ns_picard > 1)
+    return fail(c, CHNS_EUNSUPPORTED, "the adjoint step covers the linear scheme with constant density");
   if (!in || !out || !lam_out || !lam_in || !h_dtheta) return fail(c, CHNS_EINVAL, "NULL argument");
   const chns_fields* full[3] = {in, out, lam_in};
   for (const chns_fields* f : full)

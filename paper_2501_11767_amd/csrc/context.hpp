@@ -48,6 +48,7 @@ struct Level {
   // P1 convection by the Oseen convecting field
   OpVals Vx, Vy, Kp, Mp, Ap;
   double* Cw = nullptr;
+  double* Mrp = nullptr;  // finest level: P1 mass weighted by rho^k (the PCD matrix's)
   // multigrid work vectors (per precision)
   double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *e64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *t32 = nullptr, *r32 = nullptr, *e32 = nullptr;
@@ -71,6 +72,7 @@ struct P2Level {
   double* gw = nullptr;
   int* diag = nullptr;
   double *Mv = nullptr, *J = nullptr, *Kxx = nullptr, *Kxy = nullptr, *Kyx = nullptr, *Kyy = nullptr;
+  double* Mr = nullptr;  // mass weighted by rho^k (variable density)
   OpVals Vx, Vy;
   double *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *r64 = nullptr, *d64 = nullptr,
          *e64 = nullptr, *c64 = nullptr;
@@ -166,6 +168,9 @@ struct chns_ctx {
   double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr;
   double *rhs_ns = nullptr, *xns = nullptr, *xac = nullptr, *fs = nullptr, *w64d = nullptr;
   double* red = nullptr;  // reduction partials for mean projections
+  // variable density and Picard passes (ternary): rho^k at the vertices and
+  // at the P2 nodes, the previous velocity iterate, norm partials and results
+  double *rho1 = nullptr, *rho2 = nullptr, *vprev = nullptr, *pic = nullptr;
   double* diag = nullptr;  // diagnostics results (NDIAG)
   float *r32 = nullptr, *z32 = nullptr, *w32a = nullptr, *w32b = nullptr, *w32c = nullptr;
   std::vector<void*> allocs;

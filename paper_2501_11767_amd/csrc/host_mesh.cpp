@@ -425,6 +425,9 @@ P2Tables p2_tables() {
       for (int a = 0; a < 3; ++a) T.TB[q][k][a] = integrate(mul(lam(q), dpsi[k][a]));
   for (int k = 0; k < 6; ++k)
     for (int a = 0; a < 3; ++a) T.TI[k][a] = integrate(dpsi[k][a]);
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) T.MW[a][i][j] = integrate(mul(lam(a), mul(psi[i], psi[j])));
   return T;
 }
 

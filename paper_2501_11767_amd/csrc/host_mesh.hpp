@@ -108,6 +108,7 @@ struct P2Tables {
   double T2[6][6][3];        // int psi_m dpsi[n][a]
   double TB[3][6][3];        // int lambda_q dpsi[k][a]
   double TI[6][3];           // int dpsi[k][a]
+  double MW[3][6][6];        // int lambda_a psi_i psi_j (P1-weighted mass)
 };
 P2Tables p2_tables();
 

@@ -1805,7 +1805,8 @@ __global__ __launch_bounds__(BS) void k_assemble_p1(int kind, int e0, int e1,
                                                     const int* __restrict__ etype,
                                                     const int* __restrict__ eslot, double h,
                                                     const double* __restrict__ vel, int64_t n2,
-                                                    double* __restrict__ val) {
+                                                    double* __restrict__ val,
+                                                    const double* __restrict__ rho) {
   const int e = e0 + blockIdx.x * BS + threadIdx.x;
   if (e >= e1) return;
   // local vertex coordinates relative to the first vertex
@@ -1828,6 +1829,24 @@ __global__ __launch_bounds__(BS) void k_assemble_p1(int kind, int e0, int e1,
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) loc[a * 3 + b] = area / 12.0 * (a == b ? 2.0 : 1.0);
+  } else if (kind == 3) {
+    // int rho lambda_a lambda_b, rho = sum_c rho_c lambda_c: int lambda_a lambda_b
+    // lambda_c = |T| / 10 (all equal), / 30 (two equal), / 60 (all distinct)
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = rho[ep2[e * 6 + c]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int eq = (a == b) + (b == c) + (a == c);  // 3: all equal, 1: two equal, 0: distinct
+          acc += r[c] * (eq == 3 ? 1.0 / 10.0 : (eq == 1 ? 1.0 / 30.0 : 1.0 / 60.0));
+        }
+        loc[a * 3 + b] = area * acc;
+      }
   } else if (kind == 1) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -2103,7 +2122,8 @@ __global__ __launch_bounds__(BS) void k_assemble_p2(int kind, int e0, int e1,
                                                     DP2Tables tb, double eta,
                                                     const double* __restrict__ vel, double wscale,
                                                     int64_t n2, MuGrad mg, double* o0, double* o1,
-                                                    double* o2, double* o3) {
+                                                    double* o2, double* o3,
+                                                    const double* __restrict__ rho) {
   const int e = e0 + blockIdx.x * BS + threadIdx.x;
   if (e >= e1) return;
   const ElemGeo g = elem_geo(etype[e], h);
@@ -2111,6 +2131,15 @@ __global__ __launch_bounds__(BS) void k_assemble_p2(int kind, int e0, int e1,
   if (kind == 0) {
     for (int i = 0; i < 6; ++i)
       for (int j = 0; j < 6; ++j) o0[slot[i * 6 + j]] += g.area * tb.MM[i * 6 + j];
+    return;
+  }
+  if (kind == 3) {  // int rho psi_i psi_j, rho the P1 field at the vertices
+    double r[3];
+    for (int a = 0; a < 3; ++a) r[a] = rho[ep2[e * 6 + a]];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j)
+        o0[slot[i * 6 + j]] +=
+            g.area * (r[0] * tb.MW[i * 6 + j] + r[1] * tb.MW[36 + i * 6 + j] + r[2] * tb.MW[72 + i * 6 + j]);
     return;
   }
   if (kind == 1) {
@@ -2137,7 +2166,8 @@ __global__ __launch_bounds__(BS) void k_assemble_p2(int kind, int e0, int e1,
   double wg[6][3];
   for (int k = 0; k < 6; ++k) {
     const int node = ep2[e * 6 + k];
-    const double wx = wscale * vel[node], wy = wscale * vel[n2 + node];
+    const double ws = rho ? rho[node] : wscale;  // rho v at the P2 nodes
+    const double wx = ws * vel[node], wy = ws * vel[n2 + node];
     for (int a = 0; a < 3; ++a) wg[k][a] = wx * g.gx[a] + wy * g.gy[a];
   }
   double cx, cy;
@@ -2182,7 +2212,8 @@ __global__ __launch_bounds__(BS) void k_assemble_p1_conv(int e0, int e1, const i
                                                          const int* __restrict__ eslot, double h,
                                                          const double* __restrict__ vel,
                                                          double wscale, int64_t n2, MuGrad mg,
-                                                         double* __restrict__ val) {
+                                                         double* __restrict__ val,
+                                                         const double* __restrict__ rho) {
   const int e = e0 + blockIdx.x * BS + threadIdx.x;
   if (e >= e1) return;
   const ElemGeo g = elem_geo(etype[e], h);
@@ -2190,8 +2221,9 @@ __global__ __launch_bounds__(BS) void k_assemble_p1_conv(int e0, int e1, const i
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const int node = ep2[e * 6 + k];
-    vx[k] = wscale * vel[node];
-    vy[k] = wscale * vel[n2 + node];
+    const double ws = rho ? rho[node] : wscale;  // rho v at the P2 nodes
+    vx[k] = ws * vel[node];
+    vy[k] = ws * vel[n2 + node];
   }
   double cx, cy;
   mu_const(mg, ep1 + size_t(e) * 3, g, cx, cy);
@@ -2709,10 +2741,10 @@ void norm_finish(int nblk, const double* part, double* scal, double* g, int m, h
 }
 
 void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, const int* eslot,
-                 double h, const double* vel, int64_t n2, double* val, hipStream_t s) {
+                 double h, const double* vel, int64_t n2, double* val, hipStream_t s, const double* rho) {
   if (e1 <= e0) return;
   hipLaunchKernelGGL(k_assemble_p1, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, kind, e0, e1, ep2,
-                     etype, eslot, h, vel, n2, val);
+                     etype, eslot, h, vel, n2, val, rho);
 }
 
 void galerkin(int64_t nslots, const int* ptr, const int* src, const double* w, const double* fine,
@@ -2772,12 +2804,13 @@ void sell_op(const DSell& A, const TV* val, int mode, const T* x, const T* b, co
 
 void assemble_p2(int kind, int e0, int e1, const int* ep1, const int* ep2, const int* etype,
                  const int* eslot36, double h, DP2Tables tb, double eta, const double* vel,
-                 double wscale, int64_t n2, MuGrad mg, double* const* out, hipStream_t s) {
+                 double wscale, int64_t n2, MuGrad mg, double* const* out, hipStream_t s,
+                 const double* rho) {
   if (e1 <= e0) return;
   hipLaunchKernelGGL(k_assemble_p2, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, kind, e0, e1, ep1,
                      ep2, etype, eslot36, h, tb, eta, vel, wscale, n2, mg, out[0],
                      kind == 1 ? out[1] : nullptr, kind == 1 ? out[2] : nullptr,
-                     kind == 1 ? out[3] : nullptr);
+                     kind == 1 ? out[3] : nullptr, rho);
 }
 
 void assemble_b(int e0, int e1, const int* etype, const int* eslotb, double h, DP2Tables tb,
@@ -2789,10 +2822,78 @@ void assemble_b(int e0, int e1, const int* etype, const int* eslotb, double h, D
 
 void assemble_p1_conv(int e0, int e1, const int* ep1, const int* ep2, const int* etype,
                       const int* eslot, double h, const double* vel, double wscale, int64_t n2,
-                      MuGrad mg, double* val, hipStream_t s) {
+                      MuGrad mg, double* val, hipStream_t s, const double* rho) {
   if (e1 <= e0) return;
   hipLaunchKernelGGL(k_assemble_p1_conv, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, e0, e1, ep1,
-                     ep2, etype, eslot, h, vel, wscale, n2, mg, val);
+                     ep2, etype, eslot, h, vel, wscale, n2, mg, val, rho);
+}
+
+// rho = rp phi_p + rn phi_n + rs (1 - phi_p - phi_n) at the vertices, and its
+// P1 interpolant at the P2 nodes (vertices; horizontal, vertical and diagonal
+// edge midpoints i + n j between (i,j) and (i+1,j), (i,j+1), (i+1,j+1)).
+__global__ __launch_bounds__(BS) void k_density(int n, const double* __restrict__ pp,
+                                                const double* __restrict__ pn, double rp, double rn,
+                                                double rs, double* __restrict__ rho1,
+                                                double* __restrict__ rho2) {
+  const int N = n * n;
+  const int v = blockIdx.x * BS + threadIdx.x;
+  if (v >= N) return;
+  const int j = v / n, i = v - j * n;
+  const int i1 = i + 1 == n ? 0 : i + 1, j1 = j + 1 == n ? 0 : j + 1;
+  auto r = [&](int k) { return rp * pp[k] + rn * pn[k] + rs * (1.0 - pp[k] - pn[k]); };
+  const double r0 = r(v);
+  rho1[v] = r0;
+  rho2[v] = r0;
+  rho2[N + v] = 0.5 * (r0 + r(i1 + n * j));
+  rho2[2 * N + v] = 0.5 * (r0 + r(i + n * j1));
+  rho2[3 * N + v] = 0.5 * (r0 + r(i1 + n * j1));
+}
+
+__global__ __launch_bounds__(BS) void k_fill(int64_t n, double v, double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+void fill(int64_t n, double v, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, v, out);
+}
+
+void density_fields(int n, const double* pp, const double* pn, const double* rpure, double* rho1,
+                    double* rho2, hipStream_t s) {
+  hipLaunchKernelGGL(k_density, dim3(ceil_div(n * n, BS)), dim3(BS), 0, s, n, pp, pn, rpure[0],
+                     rpure[1], rpure[2], rho1, rho2);
+}
+
+// ||v - w||_2 and ||v||_2 into out[0..1] (fixed grid, deterministic order).
+constexpr int DIFF_NBLK = 256;
+__global__ __launch_bounds__(BS) void k_diff_norms(int64_t n, const double* __restrict__ v,
+                                                   const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double dd = 0.0, vv = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(BS) + threadIdx.x; i < n; i += int64_t(gridDim.x) * BS) {
+    const double d = v[i] - w[i];
+    dd += d * d;
+    vv += v[i] * v[i];
+  }
+  const double a = block_sum(dd, sh);
+  const double b = block_sum(vv, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[DIFF_NBLK + blockIdx.x] = b;
+  }
+}
+
+__global__ void k_diff_norms_finish(const double* __restrict__ part, double* __restrict__ out) {
+  const double a = sum_partials_wave(DIFF_NBLK, part), b = sum_partials_wave(DIFF_NBLK, part + DIFF_NBLK);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(a);
+    out[1] = sqrt(b);
+  }
+}
+
+void diff_norms(int64_t n, const double* v, const double* w, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diff_norms, dim3(DIFF_NBLK), dim3(BS), 0, s, n, v, w, part);
+  hipLaunchKernelGGL(k_diff_norms_finish, dim3(1), dim3(64), 0, s, part, out);
 }
 
 void korteweg(int e0, int e1, const int* ep1, const int* ep2, const int* etype, double h,

@@ -322,9 +322,11 @@ void norm_finish(int nblk, const double* part, double* scal, double* g, int m, h
                  double* host = nullptr, double tag = 0.0);
 
 // Assembly: coloured element scatter into a SELL value array.  kind 0: P1
-// mass, 1: P1 stiffness, 2: P1 convection by a P2 velocity vel (2 x n2 nodes).
+// mass, 1: P1 stiffness, 2: P1 convection by a P2 velocity vel (2 x n2 nodes),
+// 3: P1 mass weighted by the vertex field rho (int rho phi_i phi_j, exact).
 void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, const int* eslot,
-                 double h, const double* vel, int64_t n2, double* val, hipStream_t s);
+                 double h, const double* vel, int64_t n2, double* val, hipStream_t s,
+                 const double* rho = nullptr);
 
 // coarse[s] = sum_k w_k fine[src_k] over the Galerkin map.
 void galerkin(int64_t nslots, const int* ptr, const int* src, const double* w, const double* fine,
@@ -405,6 +407,7 @@ struct DP2Tables {
   const double* T2;   // [6][6][3]
   const double* TB;   // [3][6][3]
   const double* TI;   // [6][3]
+  const double* MW;   // [3][6][6]
 };
 
 // Per-element gradient sources for the constant part of the convecting field
@@ -416,11 +419,14 @@ struct MuGrad {
 
 // P2 element scatter (one colour [e0, e1)).  kind 0: mass into out[0];
 // kind 1: symmetric-gradient blocks eta (2G^xx + G^yy), eta G^yx, eta G^xy,
-// eta (G^xx + 2G^yy) into out[0..3]; kind 2: convection by w = wscale * vel +
-// w_const(mu) into out[0].  eslot36: 36 P2 SELL slots per element.
+// eta (G^xx + 2G^yy) into out[0..3]; kind 2: convection by w = wscale * vel
+// (rho * vel at the P2 nodes when rho, a P2 field, is given) + w_const(mu)
+// into out[0]; kind 3: mass weighted by the vertex field rho (int rho psi_i
+// psi_j, exact) into out[0].  eslot36: 36 P2 SELL slots per element.
 void assemble_p2(int kind, int e0, int e1, const int* ep1, const int* ep2, const int* etype,
                  const int* eslot36, double h, DP2Tables tb, double eta, const double* vel,
-                 double wscale, int64_t n2, MuGrad mg, double* const* out, hipStream_t s);
+                 double wscale, int64_t n2, MuGrad mg, double* const* out, hipStream_t s,
+                 const double* rho = nullptr);
 // B_e[q][c,k] = -int d_c psi_k lambda_q into the B SELL (36 slots per element).
 void assemble_b(int e0, int e1, const int* etype, const int* eslotb, double h, DP2Tables tb,
                 double* out, hipStream_t s);
@@ -428,7 +434,15 @@ void assemble_b(int e0, int e1, const int* etype, const int* eslotb, double h, D
 // constant part), into a P1 SELL value array.
 void assemble_p1_conv(int e0, int e1, const int* ep1, const int* ep2, const int* etype,
                       const int* eslot, double h, const double* vel, double wscale, int64_t n2,
-                      MuGrad mg, double* val, hipStream_t s);
+                      MuGrad mg, double* val, hipStream_t s, const double* rho = nullptr);
+// (rho: the P2 nodal field that replaces wscale in w = rho v - alpha sum grad mu)
+// Variable density: rho1 = sum_i rpure[i] phi_i at the vertices (phi_s = 1 -
+// phi_p - phi_n), rho2 its P1 interpolant at the P2 nodes (4N).
+void density_fields(int n, const double* pp, const double* pn, const double* rpure, double* rho1,
+                    double* rho2, hipStream_t s);
+void fill(int64_t n, double v, double* out, hipStream_t s);
+// out[0] = ||v - w||_2, out[1] = ||v||_2; part holds 2 * 256 partial sums.
+void diff_norms(int64_t n, const double* v, const double* w, double* part, double* out, hipStream_t s);
 // Korteweg load F_(c,k) += int G : grad(psi_k e_c), G = beta sum over
 // phi_p, phi_N, phi_s = 1 - phi_p - phi_N of grad phi (x) grad phi, plus
 // beta_v grad Phi (x) grad Phi; out has 2 x n2 entries.

@@ -31,13 +31,13 @@ def probe():
 
 
 def tables(probe):
-    out = np.zeros(36 + 324 + 648 + 108 + 54 + 18)
+    out = np.zeros(36 + 324 + 648 + 108 + 54 + 18 + 108)
     k = probe.chns_probe_p2_tables(out.ctypes.data_as(ct.c_void_p))
     assert k == len(out)
     o = 0
     res = {}
     for name, shape in (("MM", (6, 6)), ("S", (6, 3, 6, 3)), ("T3", (6, 6, 6, 3)), ("T2", (6, 6, 3)),
-                        ("TB", (3, 6, 3)), ("TI", (6, 3))):
+                        ("TB", (3, 6, 3)), ("TI", (6, 3)), ("MW", (3, 6, 6))):
         sz = int(np.prod(shape))
         res[name] = out[o:o + sz].reshape(shape)
         o += sz
@@ -56,6 +56,9 @@ def test_tables_match_quadrature(probe):
     assert np.allclose(T["T2"], np.einsum("q,qm,qna->mna", w, psi, dps), atol=1e-15)
     assert np.allclose(T["TB"], np.einsum("q,qs,qka->ska", w, lam, dps), atol=1e-15)
     assert np.allclose(T["TI"], np.einsum("q,qka->ka", w, dps), atol=1e-15)
+    # the P1-weighted mass table (degree 5: the 7-point rule is exact)
+    assert np.allclose(T["MW"], np.einsum("q,qa,qi,qj->aij", w, lam, psi, psi), atol=1e-15)
+    assert np.allclose(T["MW"].sum(axis=0), T["MM"], atol=1e-15)  # sum_a lambda_a = 1
     # textbook P2 mass matrix times 180/|T| (edge node e opposite vertex e)
     ref = np.array([[6, -1, -1, -4, 0, 0], [-1, 6, -1, 0, -4, 0], [-1, -1, 6, 0, 0, -4],
                     [-4, 0, 0, 32, 16, 16], [0, -4, 0, 16, 32, 16], [0, 0, -4, 16, 16, 32]], float)
