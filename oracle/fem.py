@@ -70,6 +70,58 @@ def p2_basis_dlam(lam):
 # ---------------------------------------------------------------- mesh
 
 
+def _geometry(m):
+    """Element areas and barycentric gradients from m.xy (ne, 3, 2)."""
+    x0 = m.xy[:, 0, :]
+    T = np.stack([m.xy[:, 1, :] - x0, m.xy[:, 2, :] - x0], axis=2)  # columns
+    det = T[:, 0, 0] * T[:, 1, 1] - T[:, 0, 1] * T[:, 1, 0]
+    m.area = 0.5 * np.abs(det)
+    Tinv = np.linalg.inv(T)  # rows = grad lambda_1, grad lambda_2
+    g = np.zeros((m.ne, 3, 2))
+    g[:, 1, :] = Tinv[:, 0, :]
+    g[:, 2, :] = Tinv[:, 1, :]
+    g[:, 0, :] = -g[:, 1, :] - g[:, 2, :]
+    m.grad = g  # grad lambda_a per element (ne, 3, 2)
+
+
+class BoxMesh:
+    """Right-diagonal triangulation of the square [0, L]^2 without
+    identification (the paper's closed domain, section "Numerical results"):
+    (n + 1)^2 vertices numbered i + (n + 1) j, cells (i, j) split along their
+    (i, j)-(i+1, j+1) diagonal like the periodic mesh.  The P1 forms assembled
+    on it carry the natural (no-flux) boundary conditions of the phase
+    fields and chemical potentials (eq. (bc)).  P1 only."""
+
+    def __init__(self, n: int, length: float = 1.0):
+        if n < 2:
+            raise ValueError("need n >= 2")
+        self.n, self.length = n, length
+        self.h = length / n
+        m = n + 1
+        self.nv = m * m
+        jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        i, j = ii.ravel(), jj.ravel()
+        idx = lambda a, b: a + m * b
+        a, b, c, d = idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)
+        lo, up = np.stack([a, b, c], 1), np.stack([a, c, d], 1)
+        base = np.stack([i, j], 1).astype(np.float64)
+        lo_off = base[:, None, :] + np.array([[0, 0], [1, 0], [1, 1]], dtype=np.float64)
+        up_off = base[:, None, :] + np.array([[0, 0], [1, 1], [0, 1]], dtype=np.float64)
+        self.tri = np.stack([lo, up], 1).reshape(-1, 3).astype(np.int64)
+        self.tri2 = None
+        self.xy = np.stack([lo_off, up_off], 1).reshape(-1, 3, 2) * self.h
+        self.ne = self.tri.shape[0]
+        _geometry(self)
+
+    def quad_points(self):
+        return np.einsum("qa,ead->eqd", QP, self.xy)
+
+    def vertex_xy(self):
+        """(nv, 2) vertex coordinates in id order."""
+        jj, ii = np.meshgrid(np.arange(self.n + 1), np.arange(self.n + 1), indexing="ij")
+        return np.stack([ii.ravel(), jj.ravel()], 1) * self.h
+
+
 class Mesh:
     """Periodic right-diagonal triangulation of the unit square."""
 
@@ -101,16 +153,7 @@ class Mesh:
         self.tri2 = np.stack([lo2, up2], 1).reshape(-1, 6).astype(np.int64)
         self.xy = np.stack([lo_off, up_off], 1).reshape(-1, 3, 2) * self.h
         self.ne = self.tri.shape[0]
-        x0 = self.xy[:, 0, :]
-        T = np.stack([self.xy[:, 1, :] - x0, self.xy[:, 2, :] - x0], axis=2)  # columns
-        det = T[:, 0, 0] * T[:, 1, 1] - T[:, 0, 1] * T[:, 1, 0]
-        self.area = 0.5 * np.abs(det)
-        Tinv = np.linalg.inv(T)  # rows = grad lambda_1, grad lambda_2
-        g = np.zeros((self.ne, 3, 2))
-        g[:, 1, :] = Tinv[:, 0, :]
-        g[:, 2, :] = Tinv[:, 1, :]
-        g[:, 0, :] = -g[:, 1, :] - g[:, 2, :]
-        self.grad = g  # grad lambda_a per element (ne, 3, 2)
+        _geometry(self)
 
     def quad_points(self):
         """Physical quadrature points (ne, nq, 2), unwrapped."""
@@ -166,7 +209,7 @@ def p1_convection(m: Mesh, vel_p2, w_const=None):
 
 
 def p1_load(m: Mesh, f):
-    """b_i = int f phi_i for a callable f(x, y) (periodic), by the 7-point rule."""
+    """b_i = int f phi_i for a callable f(x, y), by the 7-point rule."""
     X = m.quad_points()
     fq = f(X[..., 0], X[..., 1])
     phi = p1_basis(QP)

@@ -28,11 +28,17 @@ from .systems import Params
 
 
 class Operators:
-    """Mesh plus the step-independent matrices."""
+    """Mesh plus the step-independent matrices.  box_length: the closed
+    square [0, L]^2 with no-flux boundaries (fem.BoxMesh, P1 models only)
+    instead of the periodic unit square."""
 
-    def __init__(self, n: int, need_p2: bool = False):
+    def __init__(self, n: int, need_p2: bool = False, box_length: float | None = None):
+        if box_length is not None and need_p2:
+            raise ValueError("the closed domain carries the P1 models only")
         self.n = n
-        self.mesh = fem.Mesh(n)
+        self.box = box_length is not None
+        self.mesh = fem.BoxMesh(n, box_length) if self.box else fem.Mesh(n)
+        self.N = self.mesh.nv
         self.M = fem.p1_mass(self.mesh)
         self.K = fem.p1_stiffness(self.mesh)
         self.Mv = fem.p2_mass(self.mesh) if need_p2 else None
@@ -111,11 +117,12 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
          return_systems: bool = False):
     """Advance one step; ``how`` in {"dense", "splu", "fft"} (fft needs v = 0)."""
     n, M, K = ops.n, ops.M, ops.K
+    N = ops.N
     mesh = ops.mesh
     vel = st.get("vel")
     C = fem.p1_convection(mesh, vel) if vel is not None else None
-    if how == "fft" and C is not None:
-        raise ValueError("the Fourier solve needs a convection-free system")
+    if how == "fft" and (C is not None or ops.box):
+        raise ValueError("the Fourier solve needs a convection-free periodic system")
     fps, fv = explicit_terms(model, st, prm)
     out = dict(vel=vel, p=st.get("p"))
     sysrec = {}
@@ -128,13 +135,12 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         b = systems.ch_rhs(M, ph, fp, prm)
         sysrec.setdefault("ch_rhs", []).append(b)
         if how == "fft":
-            N = n * n
             x1, x2 = solvers.fft_ch_solve(n, prm, b[:N], b[N:])
             x = np.concatenate([x1, x2])
         else:
             x = _solve(A_ch, b, how)
-        phis.append(x[: n * n])
-        mus.append(x[n * n:])
+        phis.append(x[:N])
+        mus.append(x[N:])
     out["phi"], out["mu"] = phis, mus
 
     # Allen-Cahn
@@ -183,12 +189,12 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
 
 def mass(ops: Operators, u):
     """Discrete mass 1^T M u."""
-    return float(np.ones(ops.n * ops.n) @ (ops.M @ u))
+    return float(np.ones(ops.N) @ (ops.M @ u))
 
 
 def energy_ch(ops: Operators, prm: Params, phi, Phi=None):
     """E_h = beta/2 phi^T K phi + sum_i (M 1)_i f(phi_i) (binary potential)."""
-    lump = ops.M @ np.ones(ops.n * ops.n)
+    lump = ops.M @ np.ones(ops.N)
     return 0.5 * prm.beta * phi @ (ops.K @ phi) + lump @ pot.f_bin(phi, Phi)
 
 
@@ -198,7 +204,7 @@ def energy_ternary(ops: Operators, prm: Params, pp, pn, Phi):
     the eliminated solvent phi_s = 1 - phi_p - phi_N) plus the fitted quartic
     density of the reduced ternary model, nodal with the row sums of M:
     E_h = sum_i beta/2 phi_i^T K phi_i + sum_j (M 1)_j f(phi_p, phi_N, Phi)_j."""
-    lump = ops.M @ np.ones(ops.n * ops.n)
+    lump = ops.M @ np.ones(ops.N)
     ps = 1.0 - pp - pn
     grad = sum(u @ (ops.K @ u) for u in (pp, pn, ps))
     return 0.5 * prm.beta * grad + lump @ ternary_potential(prm, pp, pn, Phi)["f"]

@@ -75,6 +75,33 @@ def stream_velocity(n: int, seed: int, modes: int = 16, amp: float = 0.01) -> np
     return np.stack([vx, vy], axis=0)
 
 
+def box_vertex_coords(n: int, length: float) -> np.ndarray:
+    """((n+1)^2, 2) coordinates of the vertices of the closed square [0, L]^2
+    with n cells per side: vertex (i, j) has id ``i + (n+1)*j`` and sits at
+    ``(i L/n, j L/n)``."""
+    m = n + 1
+    j, i = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    return np.stack([i.ravel(), j.ravel()], axis=1) * (length / n)
+
+
+def box_state(n: int, length: float, model: str, mean: float, seed: int, film: float = 0.5):
+    """Initial fields on the closed square after the paper's two-dimensional
+    set-up (section "Numerical results", figure of the initial condition): a
+    film on the substrate y <= film * L holding the phase at mean + U(-0.01,
+    0.01), with vapour field 0; above it the ambient air, phase 0 and vapour
+    field 1.  Models "ch" and "ch_ac"; keys as initial_state."""
+    if model not in ("ch", "ch_ac"):
+        raise ValueError("the closed square carries the binary models")
+    y = box_vertex_coords(n, length)[:, 1]
+    below = y <= film * length
+    ss = np.random.SeedSequence(seed)
+    s0 = int(ss.spawn(1)[0].generate_state(1)[0])
+    noise = rng(s0).uniform(-1.0, 1.0, size=y.size)
+    phi = np.where(below, mean + 0.01 * noise, 0.0)
+    Phi_v = np.where(below, 0.0, 1.0) if model == "ch_ac" else None
+    return dict(phi=[phi], Phi_v=Phi_v, vel=None, p=None)
+
+
 def log_uniform(g: np.random.Generator, lo: float, hi: float) -> float:
     return float(np.exp(g.uniform(np.log(lo), np.log(hi))))
 
@@ -90,6 +117,13 @@ CONFIGS = {
     "chac1024": dict(n=1024, model="ch_ac", eps=0.005, tau=1e-4, mobility=1.0, evap_rate=0.1,
                      viscosity=1.0, steps=1, mean=0.4, seed=BASE_SEED + 2,
                      tau_sweep=(1e-5, 1e-4, 1e-3, 1e-2)),
+    # the paper's closed domain and two-phase set-up (section "Evaporation of
+    # solvent" with its two-dimensional appendix): 10 x 10 square with no-flux
+    # boundaries, a film at 1 +- 0.01 under air, beta = 0.1, gamma = gamma_v = 1,
+    # tau = 1e-4; 128 cells per side (the paper takes 100) so that the
+    # multigrid hierarchy halves down to 4
+    "box10": dict(n=128, length=10.0, model="ch_ac", eps=0.1 ** 0.5, tau=1e-4, mobility=1.0,
+                  evap_rate=1.0, viscosity=1.0, steps=1, mean=1.0, seed=BASE_SEED + 5),
     "batch64": dict(instances=64, sizes=(64, 128, 256, 512), seed=BASE_SEED + 3),
     # Differentiation workload.  With the explicit potential the ternary run on
     # this mesh diverges within 6 steps at tau = 1e-3, 8 at 1e-4 and 17 at 1e-5
