@@ -17,11 +17,15 @@
  * with FGMRES and the paper's block-diagonal preconditioners.
  *
  * Conventions shared by every entry point
- *   - Mesh: periodic unit square, n cells per side (n even, 8 <= n <= 8192),
- *     each cell split along its (i,j)-(i+1,j+1) diagonal.  P1 node (i, j) has
- *     id i + n*j.  P2 velocity nodes: the n*n vertices, then the midpoints of
- *     horizontal, vertical and diagonal edges, each block numbered i + n*j;
- *     a velocity field is 2 * 4n^2 doubles, x components first.
+ *   - Mesh: periodic square of side `length` (default 1), n cells per side
+ *     (n even, 8 <= n <= 8192), each cell split along its (i,j)-(i+1,j+1)
+ *     diagonal.  P1 node (i, j) has id i + n*j.  P2 velocity nodes: the n*n
+ *     vertices, then the midpoints of horizontal, vertical and diagonal edges,
+ *     each block numbered i + n*j; a velocity field is 2 * 4n^2 doubles, x
+ *     components first.  Or the closed square [0, length]^2 with no-flux
+ *     boundaries (CHNS_BOUNDARY_NOFLUX): the same cells, (n+1)^2 vertices
+ *     numbered i + (n+1)*j, P1 fields of N = (n+1)^2 doubles, binary models
+ *     without convection.
  *   - Parameter reading: beta = eps^2, gamma = mobility, gamma_v = evap_rate,
  *     delta_v = evap_rate * eps^2, beta_v = eps^2, rho and alpha as given.
  *   - Every "d_" pointer is device memory owned by the caller, FP64 unless
@@ -72,7 +76,9 @@ enum {
 /* Linear systems (blocks) of a step. */
 enum { CHNS_BLOCK_CH = 0, CHNS_BLOCK_AC = 1, CHNS_BLOCK_NS = 2 };
 
-/* Operators for chns_spmv / chns_get_matrix. */
+/* Operators for chns_spmv / chns_get_matrix.  N is the P1 node count: n^2 on
+ * the periodic square, (n+1)^2 on the closed one (CHNS_BOUNDARY_*); the sizes
+ * below are written for the periodic square (n^2 = N). */
 enum {
   CHNS_OP_M = 0,       /* P1 mass, n^2 x n^2 */
   CHNS_OP_K = 1,       /* P1 stiffness */
@@ -90,9 +96,21 @@ enum {
  * FP64 flexible Krylov method (residuals, dots, Hessenberg in FP64). */
 enum { CHNS_F64 = 0, CHNS_MIXED = 1 };
 
+/* Domain boundary (section "Model", eq. (bc); section "Numerical results"
+ * for the square of side 10). */
+enum {
+  CHNS_BOUNDARY_PERIODIC = 0, /* periodic square, n*n vertices i + n*j at (i h, j h) */
+  CHNS_BOUNDARY_NOFLUX = 1    /* closed square [0, length]^2 with the natural (no-flux)
+                                 conditions of the phase fields, chemical potentials and
+                                 vapour field: (n+1)^2 vertices i + (n+1)*j at (i h, j h),
+                                 0 <= i, j <= n; models CH and CH_AC only, no velocity */
+};
+
 typedef struct {
-  int32_t n;      /* cells per side */
-  int32_t model;  /* CHNS_MODEL_* */
+  int32_t n;        /* cells per side (even, 8..8192) */
+  int32_t model;    /* CHNS_MODEL_* */
+  int32_t boundary; /* CHNS_BOUNDARY_*; 0 = periodic */
+  double length;    /* side of the square (h = length / n); 0 means 1 */
 } chns_mesh;
 
 /* Local free-energy density of the ternary model. */

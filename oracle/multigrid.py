@@ -1,4 +1,5 @@
-"""Geometric multigrid on the nested periodic P1 meshes (FP64).
+"""Geometric multigrid on the nested periodic P1 meshes, or on the nested
+meshes of the closed square (FP64).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -16,8 +17,8 @@ Definition of the cycle for an operator A = a M + b K (+ c C):
   sits at fine vertex (2I, 2J); fine edge midpoints take the mean of the two
   coarse edge ends; the diagonal edge joins (I, J) and (I+1, J+1));
   restriction R = P^T; Galerkin coarse operators A_c = P^T A P;
-* level cut: with rho_l = 8 b n_l^2 / a (the ratio of the K and M parts of
-  the diagonal, 8 b / (a h^2)), the cycle stops at the first level with
+* level cut: with rho_l = 8 b / (a h_l^2) (the ratio of the K and M parts of
+  the diagonal; h_l = 1 / n_l on the unit square), the cycle stops at the first level with
   rho_l <= rho_cut (that operator is mass-dominated and well conditioned) or
   at the last level; a mass-dominated operator (L = M + tau C) is therefore
   handled on the fine level alone;
@@ -77,6 +78,27 @@ def prolongation(nf: int):
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf * nf, nc * nc))
 
 
+def prolongation_box(nf: int):
+    """P1 interpolation ((nf+1)^2 x (nf/2+1)^2) on the closed square: fine
+    vertex (i, j) sits at (i/2, j/2) in coarse cells; with both indices even it
+    is coarse vertex (i/2, j/2), otherwise the midpoint of the coarse edge that
+    starts at (floor(i/2), floor(j/2)) and runs right, up or along the cell's
+    diagonal."""
+    nc = nf // 2
+    mf, mc = nf + 1, nc + 1
+    rows, cols, vals = [], [], []
+    for j in range(mf):
+        for i in range(mf):
+            r = i + mf * j
+            I, J = i // 2, j // 2
+            ends = [(I, J)] if (i % 2 == 0 and j % 2 == 0) else [(I, J), (I + i % 2, J + j % 2)]
+            for (a, b) in ends:
+                rows.append(r)
+                cols.append(a + mc * b)
+                vals.append(1.0 / len(ends))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(mf * mf, mc * mc))
+
+
 def p2_to_p1(n: int):
     """P1 on mesh n into P2 on mesh n: vertex nodes copy, edge midpoints average."""
     N = n * n
@@ -102,13 +124,14 @@ def level_sizes(n: int, nmin: int = 4):
     return out
 
 
-def rho(a, b, nl):
-    return 8.0 * b * nl * nl / a
+def rho(a, b, nl, length=1.0):
+    """8 b / (a h^2) with h = length / nl."""
+    return 8.0 * b * (nl / length) ** 2 / a
 
 
-def cut_level(sizes, a, b, rho_cut=RHO_CUT):
+def cut_level(sizes, a, b, rho_cut=RHO_CUT, length=1.0):
     for l, nl in enumerate(sizes):
-        if rho(a, b, nl) <= rho_cut:
+        if rho(a, b, nl, length) <= rho_cut:
             return l
     return len(sizes) - 1
 
@@ -116,13 +139,19 @@ def cut_level(sizes, a, b, rho_cut=RHO_CUT):
 class Hierarchy:
     """Galerkin hierarchy of A = a M + b K (+ c C) down to its cut level.
 
-    ``p2``: A is a P2 operator; ``singular``: pressure Laplacian (a = 0)."""
+    ``p2``: A is a P2 operator; ``singular``: pressure Laplacian (a = 0);
+    ``box_length``: A lives on the closed square [0, L]^2 (P1, (n+1)^2 nodes)
+    instead of the periodic unit square."""
 
     def __init__(self, A, n: int, a: float = 1.0, b: float = 0.0, nmin: int = 4,
-                 rho_cut: float = RHO_CUT, p2: bool = False, singular: bool = False):
+                 rho_cut: float = RHO_CUT, p2: bool = False, singular: bool = False,
+                 box_length: float | None = None):
+        if box_length is not None and (p2 or singular):
+            raise ValueError("the closed square carries P1 operators with a mass part")
         sizes = level_sizes(n, nmin)
         self.singular = singular
-        self.cut = len(sizes) - 1 if singular else cut_level(sizes, a, b, rho_cut)
+        length = 1.0 if box_length is None else box_length
+        self.cut = len(sizes) - 1 if singular else cut_level(sizes, a, b, rho_cut, length)
         self.sizes = sizes[: self.cut + 1]
         self.A = [sp.csr_matrix(A)]
         self.P = []
@@ -133,7 +162,7 @@ class Hierarchy:
             self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
             self.lmax.append(LMAX_P2)
         for nf in self.sizes[:-1]:
-            P = prolongation(nf)
+            P = prolongation(nf) if box_length is None else prolongation_box(nf)
             self.P.append(P)
             self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
             self.lmax.append(LMAX)
@@ -142,7 +171,7 @@ class Hierarchy:
         if singular:
             self.lo_last = 0.9 * (1.0 - np.cos(2.0 * np.pi / nl)) / 2.0
         else:
-            self.lo_last = 0.9 * 0.5 / (1.0 + rho(a, b, nl))
+            self.lo_last = 0.9 * 0.5 / (1.0 + rho(a, b, nl, length))
         self.Dinv = [1.0 / Al.diagonal() for Al in self.A]
 
 

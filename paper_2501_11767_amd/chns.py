@@ -43,7 +43,12 @@ EXPORTS = [
 
 
 class Mesh(ct.Structure):
-    _fields_ = [("n", ct.c_int32), ("model", ct.c_int32)]
+    _fields_ = [("n", ct.c_int32), ("model", ct.c_int32), ("boundary", ct.c_int32),
+                ("length", ct.c_double)]
+
+
+BOUNDARY_PERIODIC, BOUNDARY_NOFLUX = 0, 1
+BOUNDARIES = {"periodic": BOUNDARY_PERIODIC, "noflux": BOUNDARY_NOFLUX}
 
 
 POT_QUARTIC, POT_FLORY_HUGGINS = 0, 1
@@ -231,17 +236,21 @@ def _stream():
 
 
 class Context:
-    """Owns a chns_ctx for one mesh/model/parameter set."""
+    """Owns a chns_ctx for one mesh/model/parameter set.  boundary "periodic"
+    (n^2 nodes) or "noflux" (the closed square, (n+1)^2 nodes); length: the
+    square's side."""
 
-    def __init__(self, n: int, model: str = "ch_ac", torch_alloc: bool = True, **params):
+    def __init__(self, n: int, model: str = "ch_ac", torch_alloc: bool = True,
+                 boundary: str = "periodic", length: float = 1.0, **params):
         self.L = lib()
         self.n, self.model = n, model
-        self.N = n * n
+        self.boundary, self.length = boundary, length
+        self.N = (n + 1) ** 2 if boundary == "noflux" else n * n
         p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.0, viscosity=1.0, alpha=1e-8,
                  rho=1.0)
         p.update(params)
         self.params = p
-        m = Mesh(n, MODELS[model])
+        m = Mesh(n, MODELS[model], BOUNDARIES[boundary], length)
         h = ct.c_void_p()
         af, ff = _allocator(torch_alloc)
         rc = self.L.chns_create(ct.byref(m), ct.byref(Params(**p)), af, ff, None, ct.byref(h))

@@ -315,7 +315,7 @@ int assemble_sym_stiffness(chns_ctx* c, hipStream_t s) {
   MuGrad none{{nullptr, nullptr, nullptr}, 0.0};
   for (int col = 0; col < 8; ++col)
     assemble_p2(1, c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
-                c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb, c->prm.viscosity, nullptr, 0.0,
+                c->ns.eslot36, c->h, c->ns.tb, c->prm.viscosity, nullptr, 0.0,
                 4 * int64_t(c->N), none, outs, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
@@ -337,7 +337,7 @@ int assemble_base(chns_ctx* c, int kind, double* val, const double* vel, hipStre
   const int64_t n2 = 4 * int64_t(c->N);
   for (int col = 0; col < 8; ++col)
     assemble_p1(kind, c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep2, c->etype, c->eslot,
-                1.0 / c->mesh.n, vel, n2, val, s);
+                c->h, vel, n2, val, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -372,9 +372,9 @@ int assemble_ternary_conv(chns_ctx* c, const double* d_vel, const double* const*
   const double* rho2 = c->prm.var_density ? c->rho2 : nullptr;
   for (int col = 0; col < 8; ++col) {
     const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
-    assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb, 0.0,
+    assemble_p2(2, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, c->h, c->ns.tb, 0.0,
                 d_vel, c->prm.rho, 4 * int64_t(c->N), mg, jo, s, rho2);
-    assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, 1.0 / c->mesh.n, d_vel, c->prm.rho,
+    assemble_p1_conv(e0, e1, c->ep1, c->ep2, c->etype, c->eslot, c->h, d_vel, c->prm.rho,
                      4 * int64_t(c->N), mg, L0.Cw, s, rho2);
   }
   HIPCHK(c, hipGetLastError());
@@ -405,7 +405,7 @@ int uniform_density(chns_ctx* c, hipStream_t s) {
 int weighted_masses(chns_ctx* c, hipStream_t s) {
   P2Level& P = c->p2;
   Level& L0 = c->lv[0];
-  const double h = 1.0 / c->mesh.n;
+  const double h = c->h;
   const int64_t n2 = 4 * int64_t(c->N);
   HIPCHK(c, hipMemsetAsync(P.Mr, 0, P.sell.slots() * sizeof(double), s));
   HIPCHK(c, hipMemsetAsync(L0.Mrp, 0, L0.sell.slots() * sizeof(double), s));
@@ -424,6 +424,7 @@ int weighted_masses(chns_ctx* c, hipStream_t s) {
 int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bool transposed,
                  hipStream_t s) {
   if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
+  if (c->box && d_vel) return fail(c, CHNS_EUNSUPPORTED, "no velocity field on the closed square");
   Level& L0 = c->lv[0];
   if (c->ternary) TRY(assemble_ternary_conv(c, d_vel, d_mu, transposed, s));
   if (d_vel) {
@@ -519,8 +520,8 @@ ChebCoef<T> cheb_coef(double lo, double hi, int steps) {
 // Level where the cycle of a M + b K stops: first l with 8 b n_l^2 / a <= rho_cut.
 size_t cut_level(chns_ctx* c, const double* coef, double rho_cut) {
   for (size_t l = 0; l < c->lv.size(); ++l) {
-    const double nl = c->lv[l].n;
-    if (8.0 * coef[1] * nl * nl / coef[0] <= rho_cut) return l;
+    const double ih = c->lv[l].n / c->len;  // 1 / h on level l
+    if (8.0 * coef[1] * ih * ih / coef[0] <= rho_cut) return l;
   }
   return c->lv.size() - 1;
 }
@@ -589,12 +590,12 @@ void cheb_from_zero(chns_ctx* c, Level& L, const OpVals& A, const T* b, T* x, co
 template <typename T>
 ChebCoef<T> cut_coef(chns_ctx* c, OpVals Level::*op, size_t l, const chns_solve_opts& o) {
   const double* cf = coef_of(c, op);
-  const double nl = c->lv[l].n;
+  const double nl = c->lv[l].n, ih = nl / c->len;  // cells per side, 1 / h
   double lo;
   if (singular_of(op)) {
     lo = 0.9 * (1.0 - std::cos(2.0 * M_PI / nl)) / 2.0;  // smallest nonzero eigenvalue of D^-1 K
   } else {
-    lo = 0.45 / (1.0 + 8.0 * cf[1] * nl * nl / cf[0]);
+    lo = 0.45 / (1.0 + 8.0 * cf[1] * ih * ih / cf[0]);
   }
   const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
   return cheb_coef<T>(lo, o.mg_lmax, std::min(steps, MAXCHEB));
@@ -1468,7 +1469,10 @@ int build_ternary_tables(chns_ctx* c) {
 
 int build(chns_ctx* c) {
   const int n = c->mesh.n;
-  c->N = n * n;
+  const bool box = c->box;
+  // P1 nodes: n^2 on the periodic square, (n+1)^2 on the closed one
+  auto nodes = [box](int m) { return box ? (m + 1) * (m + 1) : m * m; };
+  c->N = nodes(n);
   // levels n, n/2, ... while even and the next size is >= 4
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 4) sizes.push_back(sizes.back() / 2);
@@ -1476,11 +1480,11 @@ int build(chns_ctx* c) {
   for (size_t l = 0; l < sizes.size(); ++l) {
     Level& L = c->lv[l];
     L.n = sizes[l];
-    L.N = L.n * L.n;
-    Elements E = make_elements(L.n);
+    L.N = nodes(L.n);
+    Elements E = make_elements(L.n, box);
     L.csr = pattern_from_elements(L.N, L.N, E.ne, E.v.data(), 3, E.v.data(), 3);
-    L.sell = make_sell_p1(L.csr, L.n);
-    if (!L.sell.uniform || L.sell.width_max != 7 || L.sell.side != L.n)
+    L.sell = box ? make_sell_p1_box(L.csr, L.n) : make_sell_p1(L.csr, L.n);
+    if (!L.sell.uniform || L.sell.width_max != 7 || L.sell.side != (box ? 0 : L.n))
       return fail(c, CHNS_EINVAL, "P1 pattern is not the uniform 7-point stencil");
     TRY(upload_sell(c, L.sell, L.d));
     TRY(upload(c, &L.diag, L.sell.diag));
@@ -1494,7 +1498,7 @@ int build(chns_ctx* c) {
             slot[size_t(e) * 9 + a * 3 + b] = L.sell.csr2sell[q];
           }
       TRY(upload(c, &c->ep1, c->el.v));
-      TRY(upload(c, &c->ep2, c->el.p2));
+      if (!box) TRY(upload(c, &c->ep2, c->el.p2));  // no P2 nodes on the closed square
       TRY(upload(c, &c->etype, c->el.type));
       TRY(upload(c, &c->eslot, slot));
     }
@@ -1502,7 +1506,7 @@ int build(chns_ctx* c) {
   for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
     Level& F = c->lv[l];
     Level& G = c->lv[l + 1];
-    p1_prolongation(F.n, F.Pcsr, F.Pval);
+    p1_prolongation(F.n, F.Pcsr, F.Pval, box);
     csr_transpose(F.Pcsr, F.Pval, F.Rcsr, F.Rval);
     F.Psell = make_sell(F.Pcsr, 64, 1);
     F.Rsell = make_sell(F.Rcsr, 64, 1);
@@ -1688,9 +1692,9 @@ int build(chns_ctx* c) {
     double* mo[1] = {P.Mv};
     for (int col = 0; col < 8; ++col) {
       const int e0 = c->el.colour_ptr[col], e1 = c->el.colour_ptr[col + 1];
-      assemble_p2(0, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, 1.0 / c->mesh.n, c->ns.tb, 0.0,
+      assemble_p2(0, e0, e1, c->ep1, c->ep2, c->etype, c->ns.eslot36, c->h, c->ns.tb, 0.0,
                   nullptr, 0.0, 4 * int64_t(c->N), none, mo, s);
-      assemble_b(e0, e1, c->etype, c->ns.eslotb, 1.0 / c->mesh.n, c->ns.tb, c->ns.B, s);
+      assemble_b(e0, e1, c->etype, c->ns.eslotb, c->h, c->ns.tb, c->ns.B, s);
     }
     TRY(assemble_sym_stiffness(c, s));
     TRY(uniform_density(c, s));
@@ -1741,7 +1745,7 @@ int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_
   HIPCHK(c, hipMemsetAsync(rhs_ns + 2 * N4, 0, N * sizeof(double), s));
   for (int col = 0; col < 8; ++col)
     korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
-             1.0 / c->mesh.n, c->ns.tb, in->phi[0], in->phi[1], in->Phi_v, beta, beta, N4, rhs_ns, s);
+             c->h, c->ns.tb, in->phi[0], in->phi[1], in->Phi_v, beta, beta, N4, rhs_ns, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -1857,7 +1861,7 @@ int ternary_adjoint(chns_ctx* c, const chns_fields& in, const chns_fields& out, 
   AdjData& A = c->adj;
   Level& L0 = c->lv[0];
   P2Level& P = c->p2;
-  const double h = 1.0 / c->mesh.n;
+  const double h = c->h;
   const double* mu3[3] = {in.mu[0], in.mu[1], in.mu[2]};
   TRY(assemble_ops(c, in.vel, mu3, true, s));
   cheb_from_zero<double>(c, L0, L0.Mp, lo.mu[2], c->w64a, cheb_coef<double>(0.49, 2.01, 40), s);
@@ -1990,6 +1994,18 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = "unknown model";
     return CHNS_EINVAL;
   }
+  if (mesh->boundary != CHNS_BOUNDARY_PERIODIC && mesh->boundary != CHNS_BOUNDARY_NOFLUX) {
+    g_create_err = "unknown boundary";
+    return CHNS_EINVAL;
+  }
+  if (!(mesh->length >= 0.0 && std::isfinite(mesh->length))) {
+    g_create_err = "length must be finite and > 0 (0 for 1)";
+    return CHNS_EINVAL;
+  }
+  if (mesh->boundary == CHNS_BOUNDARY_NOFLUX && mesh->model == CHNS_MODEL_TERNARY) {
+    g_create_err = "the closed square carries the binary models (no Taylor-Hood spaces with no-slip walls)";
+    return CHNS_EUNSUPPORTED;
+  }
   chns_ctx tmp;
   if (check_params(&tmp, params) != CHNS_OK) {
     g_create_err = tmp.err;
@@ -2010,6 +2026,9 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
   c->mesh = *mesh;
   c->prm = *params;
   c->ternary = (mesh->model == CHNS_MODEL_TERNARY);
+  c->box = mesh->boundary == CHNS_BOUNDARY_NOFLUX;
+  c->len = mesh->length > 0.0 ? mesh->length : 1.0;
+  c->h = c->len / mesh->n;
   int rc = CHNS_OK;
   if (hipGetDevice(&c->device) != hipSuccess) {
     c->err = "hipGetDevice failed";

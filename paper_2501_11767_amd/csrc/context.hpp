@@ -140,6 +140,9 @@ struct chns_ctx {
   chns_params prm{};
   int device = 0;       // the GPU current at chns_create
   int N = 0;            // P1 nodes
+  bool box = false;     // closed square (no-flux boundaries) instead of the periodic one
+  double len = 1.0;     // side of the square
+  double h = 0.0;       // finest mesh width len / n
   bool has_conv = false;
   bool c_zero = true;   // C and C32 hold zeros on every level
   bool ternary = false;

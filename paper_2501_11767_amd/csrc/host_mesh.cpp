@@ -13,14 +13,17 @@ int Csr::find(int r, int c) const {
   return (it != e && *it == c) ? int(it - col.begin()) : -1;
 }
 
-Elements make_elements(int n) {
+Elements make_elements(int n, bool box) {
   Elements E;
   E.n = n;
+  E.box = box;
   E.ne = 2 * n * n;
   const int N = n * n;
-  auto id = [n](int i, int j) { return ((i % n + n) % n) + n * ((j % n + n) % n); };
+  auto id = [n, box](int i, int j) {
+    return box ? i + (n + 1) * j : ((i % n + n) % n) + n * ((j % n + n) % n);
+  };
   E.v.reserve(E.ne * 3);
-  E.p2.reserve(E.ne * 6);
+  if (!box) E.p2.reserve(E.ne * 6);
   E.type.reserve(E.ne);
   int count = 0;
   for (int colour = 0; colour < 8; ++colour) {
@@ -31,16 +34,20 @@ Elements make_elements(int n) {
         const int a = id(i, j), b = id(i + 1, j), c = id(i + 1, j + 1), d = id(i, j + 1);
         if (ty == 0) {
           const int loc[3] = {a, b, c};
-          const int e2[3] = {2 * N + id(i + 1, j), 3 * N + id(i, j), N + id(i, j)};
           E.v.insert(E.v.end(), loc, loc + 3);
-          E.p2.insert(E.p2.end(), loc, loc + 3);
-          E.p2.insert(E.p2.end(), e2, e2 + 3);
+          if (!box) {
+            const int e2[3] = {2 * N + id(i + 1, j), 3 * N + id(i, j), N + id(i, j)};
+            E.p2.insert(E.p2.end(), loc, loc + 3);
+            E.p2.insert(E.p2.end(), e2, e2 + 3);
+          }
         } else {
           const int loc[3] = {a, c, d};
-          const int e2[3] = {N + id(i, j + 1), 2 * N + id(i, j), 3 * N + id(i, j)};
           E.v.insert(E.v.end(), loc, loc + 3);
-          E.p2.insert(E.p2.end(), loc, loc + 3);
-          E.p2.insert(E.p2.end(), e2, e2 + 3);
+          if (!box) {
+            const int e2[3] = {N + id(i, j + 1), 2 * N + id(i, j), 3 * N + id(i, j)};
+            E.p2.insert(E.p2.end(), loc, loc + 3);
+            E.p2.insert(E.p2.end(), e2, e2 + 3);
+          }
         }
         E.type.push_back(ty);
         ++count;
@@ -177,23 +184,77 @@ Sell make_sell(const Csr& A, int C, int sigma) {
   return S;
 }
 
-void p1_prolongation(int nf, Csr& P, std::vector<double>& val) {
+Sell make_sell_p1_box(const Csr& A, int n) {
+  Sell S;
+  const int m = n + 1, N = m * m;
+  S.nrows = N;
+  S.ncols = N;
+  S.C = 64;
+  S.sigma = 1;
+  S.side = 0;  // columns are stored, not computed
+  S.nslices = (N + 63) / 64;
+  S.width_max = 7;
+  S.uniform = true;
+  S.perm.assign(size_t(S.nslices) * 64, -1);
+  for (int r = 0; r < N; ++r) S.perm[r] = r;
+  S.slice_ptr.resize(S.nslices + 1);
+  for (int s = 0; s <= S.nslices; ++s) S.slice_ptr[s] = s * 448;
+  S.slice_w.assign(S.nslices, 7);
+  S.col.assign(size_t(S.nslices) * 448, 0);
+  S.csr2sell.assign(A.nnz(), -1);
+  S.diag.assign(N, -1);
+  for (int r = 0; r < S.nslices * 64; ++r) {
+    const bool pad = r >= N;  // padding lanes of a partial slice: column 0, value 0
+    const int i = r % m, j = r / m;
+    for (int k = 0; k < 7; ++k) {
+      const int ci = i + P1_DI[k], cj = j + P1_DJ[k];
+      const bool in = !pad && ci >= 0 && ci < m && cj >= 0 && cj < m;
+      // a neighbour outside the square: the row's own column, value 0
+      S.col[size_t(r >> 6) * 448 + k * 64 + (r & 63)] = pad ? 0 : (in ? ci + m * cj : r);
+    }
+  }
+  for (int r = 0; r < N; ++r) {
+    const int i = r % m, j = r / m;
+    for (int q = A.rowptr[r]; q < A.rowptr[r + 1]; ++q) {
+      const int c = A.col[q], di = c % m - i, dj = c / m - j;
+      int k = -1;
+      for (int t = 0; t < 7; ++t)
+        if (P1_DI[t] == di && P1_DJ[t] == dj) k = t;
+      if (k < 0) return Sell{};  // not the 7-point pattern
+      const int slot = (r >> 6) * 448 + k * 64 + (r & 63);
+      S.csr2sell[q] = slot;
+      if (c == r) S.diag[r] = slot;
+    }
+  }
+  return S;
+}
+
+void p1_prolongation(int nf, Csr& P, std::vector<double>& val, bool box) {
   const int nc = nf / 2;
-  auto fid = [nf](int i, int j) { return ((i % nf + nf) % nf) + nf * ((j % nf + nf) % nf); };
-  auto cid = [nc](int i, int j) { return ((i % nc + nc) % nc) + nc * ((j % nc + nc) % nc); };
-  std::vector<std::vector<std::pair<int, double>>> rows(nf * nf);
-  for (int J = 0; J < nc; ++J)
-    for (int I = 0; I < nc; ++I) {
+  // vertices per side: n on the periodic square, n + 1 on the closed one
+  const int vf = box ? nf + 1 : nf, vc = box ? nc + 1 : nc;
+  auto fid = [nf, vf, box](int i, int j) {
+    return box ? i + vf * j : ((i % nf + nf) % nf) + nf * ((j % nf + nf) % nf);
+  };
+  auto cid = [nc, vc, box](int i, int j) {
+    return box ? i + vc * j : ((i % nc + nc) % nc) + nc * ((j % nc + nc) % nc);
+  };
+  std::vector<std::vector<std::pair<int, double>>> rows(size_t(vf) * vf);
+  for (int J = 0; J < vc; ++J)
+    for (int I = 0; I < vc; ++I) {
       rows[fid(2 * I, 2 * J)].push_back({cid(I, J), 1.0});
       const int d[3][2] = {{1, 0}, {0, 1}, {1, 1}};
       for (auto& o : d) {
+        // on the closed square the last coarse row and column have no
+        // midpoints beyond them
+        if (box && ((o[0] && I == nc) || (o[1] && J == nc))) continue;
         auto& row = rows[fid(2 * I + o[0], 2 * J + o[1])];
         row.push_back({cid(I, J), 0.5});
         row.push_back({cid(I + o[0], J + o[1]), 0.5});
       }
     }
-  P.nrows = nf * nf;
-  P.ncols = nc * nc;
+  P.nrows = vf * vf;
+  P.ncols = vc * vc;
   P.rowptr.assign(P.nrows + 1, 0);
   P.col.clear();
   val.clear();

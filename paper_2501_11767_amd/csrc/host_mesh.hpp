@@ -1,9 +1,11 @@
 // Host-side mesh tables, sparsity patterns and SELL-C-sigma layouts.
 //
-// Mesh: periodic unit square with n cells per side, each cell (i, j) split by
+// Mesh: periodic square with n cells per side, each cell (i, j) split by
 // its (i,j)-(i+1,j+1) diagonal into a lower triangle ((i,j),(i+1,j),(i+1,j+1))
 // and an upper triangle ((i,j),(i+1,j+1),(i,j+1)).  P1 node (i, j) = i + n*j;
 // P2 nodes: vertices, then horizontal, vertical and diagonal edge midpoints.
+// The closed square (box) has the same cells and (n+1)^2 vertices
+// i + (n+1)*j, 0 <= i, j <= n, and carries P1 only.
 // P2 local order on a triangle (v0, v1, v2): vertices, then the nodes of the
 // edges (v1,v2), (v0,v2), (v0,v1).
 //
@@ -47,12 +49,13 @@ struct Sell {
 struct Elements {
   int n = 0, ne = 0;
   std::vector<int> v;            // ne*3 P1 vertex ids, colour-sorted
-  std::vector<int> p2;           // ne*6 P2 node ids
+  std::vector<int> p2;           // ne*6 P2 node ids (empty on the closed square)
   std::vector<int> type;         // 0 lower, 1 upper
   int colour_ptr[9] = {0};
+  bool box = false;
 };
 
-Elements make_elements(int n);
+Elements make_elements(int n, bool box = false);
 
 // Node-pair pattern of an element list: rows from `rn` (per element nr ids),
 // columns from `cn` (nc ids), sorted, duplicates merged.
@@ -72,8 +75,14 @@ constexpr int P1_DJ[7] = {0, -1, -1, 0, 0, 1, 1};
 // permutation), so a kernel can compute the columns from the row index.
 Sell make_sell_p1(const Csr& A, int n);
 
-// Nested P1 prolongation from size n/2 to n (values: 1 or 1/2).
-void p1_prolongation(int nf, Csr& P, std::vector<double>& val);
+// The same layout on the closed square with n cells per side ((n+1)^2 rows):
+// a neighbour outside the square is stored as the row's own column with value
+// 0 (never in the CSR pattern); side = 0, so kernels read the columns.
+Sell make_sell_p1_box(const Csr& A, int n);
+
+// Nested P1 prolongation from size n/2 to n (values: 1 or 1/2), periodic or
+// on the closed square.
+void p1_prolongation(int nf, Csr& P, std::vector<double>& val, bool box = false);
 
 // Galerkin map A_c = P^T A_f P on fixed patterns: for each coarse SELL slot,
 // the list of (fine SELL slot, weight).  ptr has Sc.slots()+1 entries.

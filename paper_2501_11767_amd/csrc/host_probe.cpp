@@ -14,6 +14,39 @@ void copy_out(const std::vector<int>& v, int32_t* dst) {
   if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(int));
 }
 
+// vertices of the periodic (n^2) or closed ((n+1)^2) square
+int nodes(int n, bool box) { return box ? (n + 1) * (n + 1) : n * n; }
+
+Csr p1_pattern(const Elements& E, int n, bool box) {
+  const int N = nodes(n, box);
+  return pattern_from_elements(N, N, E.ne, E.v.data(), 3, E.v.data(), 3);
+}
+
+Sell p1_sell(const Csr& A, int n, bool box) { return box ? make_sell_p1_box(A, n) : make_sell_p1(A, n); }
+
+int probe_galerkin(int nf, bool box, const double* fine_csr, double* coarse_csr) {
+  Elements Ef = make_elements(nf, box), Ec = make_elements(nf / 2, box);
+  Csr Af = p1_pattern(Ef, nf, box), Ac = p1_pattern(Ec, nf / 2, box);
+  Sell Sf = p1_sell(Af, nf, box), Sc = p1_sell(Ac, nf / 2, box);
+  Csr P;
+  std::vector<double> Pv;
+  p1_prolongation(nf, P, Pv, box);
+  std::string err;
+  GalerkinMap G = make_galerkin(Af, Sf, P, Pv, Ac, Sc, &err);
+  if (!err.empty()) return -1;
+  std::vector<double> fs(Sf.slots(), 0.0), cs(Sc.slots(), 0.0);
+  for (int64_t q = 0; q < Af.nnz(); ++q) fs[Sf.csr2sell[q]] = fine_csr[q];
+  for (int64_t s = 0; s < Sc.slots(); ++s)
+    for (int k = G.ptr[s]; k < G.ptr[s + 1]; ++k) cs[s] += G.w[k] * fs[G.src[k]];
+  for (int64_t q = 0; q < Ac.nnz(); ++q) coarse_csr[q] = cs[Sc.csr2sell[q]];
+  // slots outside the coarse pattern (padding) must receive nothing
+  std::vector<char> used(Sc.slots(), 0);
+  for (int64_t q = 0; q < Ac.nnz(); ++q) used[Sc.csr2sell[q]] = 1;
+  for (int64_t s = 0; s < Sc.slots(); ++s)
+    if (!used[s] && G.ptr[s + 1] != G.ptr[s]) return -2;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -59,22 +92,7 @@ __attribute__((visibility("default"))) int chns_probe_elements(int n, int32_t* v
 // order; coarse values returned in CSR order.
 __attribute__((visibility("default"))) int chns_probe_galerkin(int nf, const double* fine_csr,
                                                                double* coarse_csr) {
-  Elements Ef = make_elements(nf), Ec = make_elements(nf / 2);
-  Csr Af = pattern_from_elements(nf * nf, nf * nf, Ef.ne, Ef.v.data(), 3, Ef.v.data(), 3);
-  Csr Ac = pattern_from_elements(nf * nf / 4, nf * nf / 4, Ec.ne, Ec.v.data(), 3, Ec.v.data(), 3);
-  Sell Sf = make_sell_p1(Af, nf), Sc = make_sell_p1(Ac, nf / 2);
-  Csr P;
-  std::vector<double> Pv;
-  p1_prolongation(nf, P, Pv);
-  std::string err;
-  GalerkinMap G = make_galerkin(Af, Sf, P, Pv, Ac, Sc, &err);
-  if (!err.empty()) return -1;
-  std::vector<double> fs(Sf.slots(), 0.0), cs(Sc.slots(), 0.0);
-  for (int64_t q = 0; q < Af.nnz(); ++q) fs[Sf.csr2sell[q]] = fine_csr[q];
-  for (int64_t s = 0; s < Sc.slots(); ++s)
-    for (int k = G.ptr[s]; k < G.ptr[s + 1]; ++k) cs[s] += G.w[k] * fs[G.src[k]];
-  for (int64_t q = 0; q < Ac.nnz(); ++q) coarse_csr[q] = cs[Sc.csr2sell[q]];
-  return 0;
+  return probe_galerkin(nf, false, fine_csr, coarse_csr);
 }
 
 // Prolongation nf -> nf/2 as CSR (rowptr[nf^2+1], col, val) and the SELL
@@ -115,6 +133,58 @@ __attribute__((visibility("default"))) int64_t chns_probe_th_pattern(int n, int 
   copy_out(A.rowptr, rowptr);
   copy_out(A.col, col);
   return A.nnz();
+}
+
+// The closed square [0, L]^2 ((n+1)^2 vertices i + (n+1) j): P1 pattern and
+// its padded SELL layout (as chns_probe_p1, flags[3] = side), element tables
+// (v, type, colour_ptr), the Galerkin map nf -> nf/2 (-2 when a padding slot
+// would receive a contribution) and the prolongation (returns nnz).
+__attribute__((visibility("default"))) int64_t chns_probe_box_p1_nnz(int n) {
+  return p1_pattern(make_elements(n, true), n, true).nnz();
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_p1(int n, int32_t* rowptr, int32_t* col,
+                                                             int32_t* sell_col, int32_t* csr2sell,
+                                                             int32_t* diag, int32_t* flags) {
+  Csr A = p1_pattern(make_elements(n, true), n, true);
+  Sell S = make_sell_p1_box(A, n);
+  copy_out(A.rowptr, rowptr);
+  copy_out(A.col, col);
+  copy_out(S.col, sell_col);
+  copy_out(S.csr2sell, csr2sell);
+  copy_out(S.diag, diag);
+  if (flags) {
+    flags[0] = S.uniform;
+    flags[1] = S.width_max;
+    flags[2] = int(S.slots());
+    flags[3] = S.side;
+  }
+  return 0;
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_elements(int n, int32_t* v, int32_t* type,
+                                                                   int32_t* cptr) {
+  Elements E = make_elements(n, true);
+  copy_out(E.v, v);
+  copy_out(E.type, type);
+  if (cptr) std::memcpy(cptr, E.colour_ptr, 9 * sizeof(int));
+  return int(E.p2.size());
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_galerkin(int nf, const double* fine_csr,
+                                                                   double* coarse_csr) {
+  return probe_galerkin(nf, true, fine_csr, coarse_csr);
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_prolongation(int nf, int32_t* rowptr,
+                                                                       int32_t* col, double* val) {
+  Csr P;
+  std::vector<double> Pv;
+  p1_prolongation(nf, P, Pv, true);
+  copy_out(P.rowptr, rowptr);
+  copy_out(P.col, col);
+  if (val) std::memcpy(val, Pv.data(), Pv.size() * sizeof(double));
+  return int(P.nnz());
 }
 
 }  // extern "C"

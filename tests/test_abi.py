@@ -47,6 +47,20 @@ def test_create_rejects_bad_mesh(L, n, model):
     assert len(L.chns_last_error(None)) > 0
 
 
+@pytest.mark.parametrize("boundary,length,model,code", [(7, 1.0, 0, -1), (1, -2.0, 0, -1),
+                                                         (1, float("nan"), 1, -1), (0, float("inf"), 0, -1),
+                                                         (1, 10.0, 2, -5)])
+def test_create_rejects_bad_domain(L, boundary, length, model, code):
+    """Unknown boundary, a side that is not finite and positive, and the
+    ternary model on the closed square (no Taylor-Hood spaces with walls)."""
+    h = ct.c_void_p()
+    rc = L.chns_create(ct.byref(chns.Mesh(16, model, boundary, length)),
+                       ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)), chns.ALLOC_FN(), chns.FREE_FN(), None,
+                       ct.byref(h))
+    assert rc == code and not h.value
+    assert len(L.chns_last_error(None)) > 0
+
+
 @pytest.mark.parametrize("bad", [dict(eps=float("nan")), dict(tau=-1.0), dict(mobility=0.0),
                                  dict(rho=float("inf")), dict(viscosity=0.0)])
 def test_create_rejects_bad_params(L, bad):

@@ -178,3 +178,47 @@ def test_direct_solvers_agree_and_the_fourier_solve_is_refused():
         S.step(ops, prm, "ch_ac", st, "fft")
     with pytest.raises(ValueError):
         S.Operators(n, need_p2=True, box_length=L10)
+
+
+# ---------------------------------------------------------------- multigrid on the closed square
+
+
+def test_box_prolongation_is_exact_on_linear_functions_and_nested():
+    from oracle import multigrid as mg
+    nf, L = 16, L10
+    P = mg.prolongation_box(nf)
+    fine, coarse = fem.BoxMesh(nf, L), fem.BoxMesh(nf // 2, L)
+    lin = lambda xy: 0.4 * xy[:, 0] + 0.9 * xy[:, 1] - 2.0
+    assert np.abs(P @ lin(coarse.vertex_xy()) - lin(fine.vertex_xy())).max() < 1e-12
+    for form in (fem.p1_mass, fem.p1_stiffness):
+        Af, Ac = form(fine), form(coarse)
+        assert abs(P.T @ Af @ P - Ac).max() < 1e-13 * abs(Ac).max()
+
+
+def test_box_vcycle_converges_and_is_symmetric():
+    from oracle import multigrid as mg, precond as PC
+    n = 32
+    ops = _box(n)
+    prm = Params(eps=0.1 ** 0.5, tau=1e-2, mobility=1.0)
+    X = PC.matching_factor(ops.M, ops.K, prm)
+    a, b = np.sqrt(prm.tau * prm.gamma / prm.beta), prm.tau * prm.gamma
+    H = mg.Hierarchy(X, n, a=a, b=b, rho_cut=0.0, box_length=L10)
+    assert H.sizes == [32, 16, 8, 4] and H.A[-1].shape == (25, 25)
+    g = np.random.default_rng(2)
+    x, y = g.standard_normal(ops.N), g.standard_normal(ops.N)
+    assert abs(x @ mg.vcycle(H, y) - y @ mg.vcycle(H, x)) < 1e-10 * abs(x @ mg.vcycle(H, x))
+    e = g.standard_normal(ops.N)
+    e0 = np.linalg.norm(e)
+    for _ in range(5):
+        e = e - mg.vcycle(H, X @ e)
+    assert (np.linalg.norm(e) / e0) ** (1 / 5) < 0.3
+
+
+def test_level_cut_uses_the_mesh_width():
+    """rho_l = 8 b / (a h_l^2): on a square of side L the rule cuts where the unit
+    square cuts b / L^2."""
+    from oracle import multigrid as mg
+    sizes = mg.level_sizes(128)
+    for a, b in ((0.03, 1e-4), (1.0, 1e-3), (2.0, 0.5)):
+        assert mg.cut_level(sizes, a, b, length=L10) == mg.cut_level(sizes, a, b / L10 ** 2)
+    assert mg.rho(2.0, 0.5, 64, 4.0) == 8 * 0.5 * 16 ** 2 / 2.0
