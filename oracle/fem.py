@@ -122,6 +122,23 @@ class BoxMesh:
         return np.stack([ii.ravel(), jj.ravel()], 1) * self.h
 
 
+def top_edge_load(m: BoxMesh, g=None):
+    """b_i = int_{y = L} g phi_i ds over the top edge of the closed square for
+    a callable g(x) (constant 1 when None), by two-point Gauss on each of its
+    n segments (exact for g linear)."""
+    n, h = m.n, m.h
+    b = np.zeros(m.nv)
+    t = 0.5 * np.array([1.0 - 1.0 / np.sqrt(3.0), 1.0 + 1.0 / np.sqrt(3.0)])
+    for i in range(n):
+        left, right = i + (n + 1) * n, i + 1 + (n + 1) * n
+        for s in t:
+            x = (i + s) * h
+            w = 0.5 * h * (1.0 if g is None else g(x))
+            b[left] += w * (1.0 - s)
+            b[right] += w * s
+    return b
+
+
 class Mesh:
     """Periodic right-diagonal triangulation of the unit square."""
 

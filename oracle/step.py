@@ -127,12 +127,22 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
     out = dict(vel=vel, p=st.get("p"))
     sysrec = {}
 
+    # evaporation flux at the top wall (closed square, one phase: the solvent)
+    flux = None
+    if prm.top_flux != 0.0:
+        if not ops.box or model == "ternary":
+            raise ValueError("the top-wall flux belongs to the binary models on the closed square")
+        ref = n // 2 + (n + 1) * n  # midpoint of the top edge
+        j_out = prm.top_flux * (st["phi"][0][ref] - prm.flux_inf)
+        flux = j_out * fem.top_edge_load(mesh)
+        sysrec["j_out"] = j_out
+
     # Cahn-Hilliard, one solve per phase (same matrix)
     A_ch = systems.ch_matrix(M, K, C, prm)
     sysrec["ch"] = A_ch
     phis, mus = [], []
     for ph, fp in zip(st["phi"], fps):
-        b = systems.ch_rhs(M, ph, fp, prm)
+        b = systems.ch_rhs(M, ph, fp, prm, flux)
         sysrec.setdefault("ch_rhs", []).append(b)
         if how == "fft":
             x1, x2 = solvers.fft_ch_solve(n, prm, b[:N], b[N:])

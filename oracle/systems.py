@@ -46,6 +46,12 @@ class Params:
     # when the relative 2-norm change of the velocity is <= picard_tol
     picard: int = 1
     picard_tol: float = 0.0
+    # evaporation at the top wall of the closed square (eq. (bc), Hertz-Knudsen
+    # flux): d phi / dn = j_out = top_flux (phi^k(x_ref) - flux_inf) on the top
+    # edge, x_ref its midpoint; top_flux lumps the flow rate, the square root
+    # and P_0 into one coefficient
+    top_flux: float = 0.0
+    flux_inf: float = 0.0
 
     @property
     def beta(self):
@@ -74,9 +80,15 @@ def ch_matrix(M, K, C, prm: Params):
     return sp.bmat([[A11, t * g * K], [t * g * K, -(t * g / b) * M]], format="csr")
 
 
-def ch_rhs(M, phi_k, fprime, prm: Params):
+def ch_rhs(M, phi_k, fprime, prm: Params, flux=None):
+    """flux: the boundary load int_Gamma_t j_out w_i ds of the second CH
+    equation (eq. (weakch) for mu: M mu - beta K phi = M f' - beta flux),
+    which enters the scaled second row as + tau g flux."""
     t, g, b = prm.tau, prm.gamma, prm.beta
-    return np.concatenate([M @ phi_k, -(t * g / b) * (M @ fprime)])
+    second = -(t * g / b) * (M @ fprime)
+    if flux is not None:
+        second = second + t * g * flux
+    return np.concatenate([M @ phi_k, second])
 
 
 def ac_matrix(M, K, C, prm: Params):

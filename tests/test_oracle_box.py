@@ -222,3 +222,62 @@ def test_level_cut_uses_the_mesh_width():
     for a, b in ((0.03, 1e-4), (1.0, 1e-3), (2.0, 0.5)):
         assert mg.cut_level(sizes, a, b, length=L10) == mg.cut_level(sizes, a, b / L10 ** 2)
     assert mg.rho(2.0, 0.5, 64, 4.0) == 8 * 0.5 * 16 ** 2 / 2.0
+
+
+# ---------------------------------------------------------------- evaporation flux at the top wall
+
+
+def test_top_edge_load_integrates_and_carries_inhomogeneous_neumann_data():
+    """b_i = int_top g phi_i ds: sums to int_top g and integrates linear g
+    exactly; with it, (M + K) u_h = (f, phi_i) + j b solves -lap u + u = f with
+    du/dn = j on the top wall and 0 elsewhere: u = y^2 (f = y^2 - 2, j = 2 L)
+    is reached at second order."""
+    L = L10
+    m = fem.BoxMesh(12, L)
+    b = fem.top_edge_load(m)
+    assert abs(b.sum() - L) < 1e-13 and np.count_nonzero(b) == 13
+    xy = m.vertex_xy()
+    bx = fem.top_edge_load(m, lambda x: 1.0 + 0.3 * x)
+    assert abs(bx @ xy[:, 0] - (L * L / 2 + 0.3 * L ** 3 / 3)) < 1e-11
+    errs = []
+    for n in (8, 16, 32, 64):
+        m = fem.BoxMesh(n, L)
+        M = fem.p1_mass(m)
+        rhs = fem.p1_load(m, lambda x, y: y * y - 2.0) + 2.0 * L * fem.top_edge_load(m)
+        uh = solvers.sparse_solve(M + fem.p1_stiffness(m), rhs)
+        e = uh - m.vertex_xy()[:, 1] ** 2
+        errs.append(np.sqrt(e @ (M @ e)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates.min() > 1.95, (errs, rates)
+
+
+def test_top_flux_enters_linearly_conserves_mass_and_draws_phase_to_the_wall():
+    """The flux j_out = k (phi^k(x_ref) - phi_inf) only loads the mu equation:
+    no flux when phi(x_ref) = phi_inf, a response linear in k, the phase mass
+    unchanged (d mu / dn = 0 on every wall), and for j_out > 0 a lower mu at
+    the wall that draws phase towards it (d phi / dn > 0 there)."""
+    n = 16
+    ops = _box(n)
+    base = Params(**PB)
+    st = S.initial_state(ops, base, "ch_ac", inputs.box_state(n, L10, "ch_ac", 0.5, 6))
+    ref = n // 2 + (n + 1) * n
+    phi_ref = st["phi"][0][ref]
+    plain = S.step(ops, base, "ch_ac", st)
+    same = S.step(ops, Params(**dict(PB, top_flux=3.0, flux_inf=phi_ref)), "ch_ac", st)
+    assert np.array_equal(same["phi"][0], plain["phi"][0])
+    d = []
+    for k in (1.0, 2.0):
+        out, sysr = S.step(ops, Params(**dict(PB, top_flux=k, flux_inf=phi_ref - 0.2)), "ch_ac", st,
+                           return_systems=True)
+        assert abs(sysr["j_out"] - 0.2 * k) < 1e-15
+        d.append(out["phi"][0] - plain["phi"][0])
+        assert abs(S.mass(ops, out["phi"][0]) - S.mass(ops, plain["phi"][0])) < 1e-12 * L10 * L10
+        assert np.array_equal(out["Phi_v"], plain["Phi_v"])  # the vapour equation is untouched
+    # linear up to the rounding of the two O(1) solutions whose difference d is
+    assert np.abs(d[1] - 2.0 * d[0]).max() < 1e-12 * np.abs(plain["phi"][0]).max()
+    assert np.abs(d[1]).max() > 1e-5
+    top = np.arange(ops.N) >= (n + 1) * n
+    assert d[0][top].sum() > 0 and d[0][~top].sum() < 0
+    with pytest.raises(ValueError):
+        S.step(S.Operators(n), Params(**dict(PB, top_flux=1.0)), "ch", {"phi": [np.zeros(n * n)],
+                                                                      "mu": [np.zeros(n * n)]})
