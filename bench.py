@@ -45,6 +45,10 @@ MG = dict(mg_pre=1, mg_post=3, mg_coarse=8, mg_rho_cut=16.0)
 # the 256^2 ternary workload: the same multigrid with FGMRES(15) (restart 15
 # measured fastest of 12/15/20 with this multigrid)
 DRY_OPTS = dict(MG, restart=15)
+# the closed-square workload: the 1024^2 multigrid with the cut threshold swept
+# (its X operator has rho = 4 on the finest level, where the 1024^2 threshold
+# would cut it to a four-step Chebyshev smoother)
+BOX_RHO_CUTS = (16.0, 4.0, 1.0)
 # HBM bytes per launch of a kernel from rocprofv3 counter runs of this
 # benchmark (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
 # copy of known size); filled in from profiles/ once measured for the kernel
@@ -80,6 +84,7 @@ def parse():
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--dry-steps", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--box-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64", help="timed forms of the 1024^2 step")
@@ -291,6 +296,47 @@ def dry_section(chns, steps):
                          f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid cut at rho <= {MG['mg_rho_cut']}",
                 ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
                 iters_ch_p_ch_n_ac_ns=its, steps=steps)
+
+
+def box_section(chns, steps, restart):
+    """The paper's closed domain: the CH + AC step on the 10 x 10 square with
+    no-flux walls (128 cells per side, 129^2 vertices, film under air),
+    mixed precision with the 1024^2 workload's solver options: ms per step
+    and FGMRES iterations, each step from the seeded state (mu^0 = 0: in the
+    binary step it is only the Krylov initial guess)."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    cfg = inputs.CONFIGS["box10"]
+    n, L = cfg["n"], cfg["length"]
+    p = {k: cfg[k] for k in ("eps", "tau", "mobility", "evap_rate")}
+    ctx = chns.Context(n, "ch_ac", boundary="noflux", length=L, **p)
+    st = inputs.box_state(n, L, "ch_ac", cfg["mean"], cfg["seed"])
+    N = ctx.N
+    f = ctx.fields(phi=[dev(st["phi"][0])], mu=[torch.zeros(N, dtype=torch.float64, device="cuda")],
+                   Phi_v=dev(st["Phi_v"]))
+    e = lambda: torch.empty(N, dtype=torch.float64, device="cuda")
+    fo = ctx.fields(phi=[e()], mu=[e()], Phi_v=e())
+    by_cut = {}
+    for cut in BOX_RHO_CUTS:
+        opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=restart, **dict(MG, mg_rho_cut=cut))
+        ctx.timestep(f, fo, 1, opts)
+        torch.cuda.synchronize()
+        walls, its = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            rc, inf = ctx.timestep(f, fo, 1, opts)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+            its.append([i["iters"] for i in inf])
+        by_cut[cut] = dict(ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
+                           iters_ch_ac=its[-1])
+    ctx.close()
+    best = min(by_cut, key=lambda k: by_cut[k]["ms_per_step"])
+    return dict(workload=f"box10: CH + AC step on the closed square [0, {L}]^2 with no-flux walls, {n} cells "
+                         f"per side ({N} vertices, {3 * N} unknowns), film at {cfg['mean']} +- 0.01 under air, "
+                         f"eps^2 {cfg['eps'] ** 2:.3g}, tau {cfg['tau']}, mixed precision, FGMRES({restart}) "
+                         f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid; per hierarchy cut threshold",
+                rho_cut=best, **by_cut[best], by_rho_cut={str(k): v for k, v in by_cut.items()}, steps=steps)
 
 
 def batch_section(chns, steps):
@@ -715,6 +761,7 @@ def main():
         log(f"dry256: {args.dry_steps} steps")
     dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
     bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
+    box = box_section(chns, args.box_steps, args.restart) if args.box_steps > 0 else None
     adj = None if args.no_adjoint else adjoint_section(chns)
     cpu = None
     if not args.no_cpu:
@@ -777,6 +824,7 @@ def main():
         "trajectory": traj,
         "dry256": dry,
         "batch64": bat,
+        "box10": box,
         "adjoint128": adj,
     }
     ctx.close()

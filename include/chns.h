@@ -148,6 +148,15 @@ typedef struct {
                             Newton schemes after eq. (linearnav) implies); 1..100 */
   double rho_pure[3];    /* pure densities of polymer, NFA, solvent (> 0) when var_density */
   double ns_picard_tol;  /* stop the solves once ||v^(m) - v^(m-1)||_2 <= tol ||v^(m)||_2 (>= 0) */
+  /* closed square only (CHNS_BOUNDARY_NOFLUX; else 0): evaporation at the top
+     wall (eq. (bc), Hertz-Knudsen outflux): d phi / dn = j_out = top_flux *
+     (phi^k(x_ref) - flux_inf) on y = length, x_ref the wall's midpoint (vertex
+     n/2 + (n+1) n); it loads the mu equation (eq. (weakch)) with -beta j_out
+     int_top w ds, i.e. the CH right-hand side's second block with
+     + tau gamma j_out int_top phi_i ds.  top_flux lumps the flow rate, the
+     square root and P_0 of the flux law into one finite coefficient. */
+  double top_flux;
+  double flux_inf;
 } chns_params;
 
 typedef struct {

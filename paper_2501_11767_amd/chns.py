@@ -63,7 +63,7 @@ class Params(ct.Structure):
                [("potential", ct.c_int32), ("truncate", ct.c_int32), ("fh_nsize", ct.c_double * 3),
                 ("fh_chi", ct.c_double * 3), ("fh_phisat", ct.c_double * 3),
                 ("var_density", ct.c_int32), ("ns_picard", ct.c_int32), ("rho_pure", ct.c_double * 3),
-                ("ns_picard_tol", ct.c_double)]
+                ("ns_picard_tol", ct.c_double), ("top_flux", ct.c_double), ("flux_inf", ct.c_double)]
 
     def __init__(self, *args, **kw):
         arrays = {k: kw.pop(k) for k in ("fh_nsize", "fh_chi", "fh_phisat", "rho_pure") if k in kw}

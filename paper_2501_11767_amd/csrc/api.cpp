@@ -198,6 +198,8 @@ int check_params(chns_ctx* c, const chns_params* p) {
   if (p->ns_picard < 0 || p->ns_picard > 100) return fail(c, CHNS_EINVAL, "ns_picard must be in 0..100");
   if (!is_finite(p->ns_picard_tol) || p->ns_picard_tol < 0.0)
     return fail(c, CHNS_EINVAL, "ns_picard_tol must be >= 0");
+  if (!is_finite(p->top_flux) || !is_finite(p->flux_inf))
+    return fail(c, CHNS_EINVAL, "top_flux and flux_inf must be finite");
   if (p->potential == CHNS_POT_FLORY_HUGGINS)
     for (int i = 0; i < 3; ++i) {
       if (!is_finite(p->fh_nsize[i]) || !(p->fh_nsize[i] > 0.0))
@@ -2002,6 +2004,10 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = "length must be finite and > 0 (0 for 1)";
     return CHNS_EINVAL;
   }
+  if (mesh->boundary != CHNS_BOUNDARY_NOFLUX && params->top_flux != 0.0) {
+    g_create_err = "the top-wall flux belongs to the closed square";
+    return CHNS_EINVAL;
+  }
   if (mesh->boundary == CHNS_BOUNDARY_NOFLUX && mesh->model == CHNS_MODEL_TERNARY) {
     g_create_err = "the closed square carries the binary models (no Taylor-Hood spaces with no-slip walls)";
     return CHNS_EUNSUPPORTED;
@@ -2064,6 +2070,7 @@ int chns_set_params(chns_ctx* c, const chns_params* p) {
     return fail(c, CHNS_EINVAL, "the Flory-Huggins density and the truncation apply to the ternary model");
   if (!c->ternary && (p->var_density || p->ns_picard > 1))
     return fail(c, CHNS_EINVAL, "variable density and Picard passes apply to the ternary model");
+  if (!c->box && p->top_flux != 0.0) return fail(c, CHNS_EINVAL, "the top-wall flux belongs to the closed square");
   c->prm = *p;
   // the residual reduction rates of earlier solves belong to other systems
   for (double& r : c->kr.rate) r = -1.0;
@@ -2302,8 +2309,17 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
   if (ac && !in->Phi_v) return fail(c, CHNS_EINVAL, "model needs Phi_v");
   const auto& p = c->prm;
   const double beta = p.eps * p.eps;
+  TopFlux tf;
+  if (c->box && p.top_flux != 0.0) {
+    const int n = c->mesh.n;
+    tf.coef = p.tau * p.mobility * p.top_flux;
+    tf.phi_inf = p.flux_inf;
+    tf.h = c->h;
+    tf.top0 = n * (n + 1);
+    tf.ref = n / 2 + (n + 1) * n;  // midpoint of the top wall
+  }
   rhs_binary(c->lv[0].d, c->lv[0].M, in->phi[0], ac ? in->Phi_v : nullptr,
-             -(p.tau * p.mobility / beta), -p.tau * p.evap_rate, d_rhs_ch, ac ? d_rhs_ac : nullptr,
+             -(p.tau * p.mobility / beta), -p.tau * p.evap_rate, tf, d_rhs_ch, ac ? d_rhs_ac : nullptr,
              static_cast<hipStream_t>(stream));
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;

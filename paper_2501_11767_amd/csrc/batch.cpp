@@ -1220,6 +1220,10 @@ int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_pa
       g_batch_err = "eps, tau, mobility must be positive and evap_rate >= 0";
       return CHNS_EINVAL;
     }
+    if (p.top_flux != 0.0) {  // instances live on periodic squares
+      g_batch_err = "the top-wall flux belongs to the closed square";
+      return CHNS_EINVAL;
+    }
   }
   chns_batch* b = new chns_batch();
   b->alloc = alloc;

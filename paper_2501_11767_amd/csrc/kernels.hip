@@ -2052,7 +2052,7 @@ __global__ __launch_bounds__(BS) void k_rhs_binary(int n, int side, const int* _
                                                    const double* __restrict__ Mv,
                                                    const double* __restrict__ phi,
                                                    const double* __restrict__ Phi, double c_mu,
-                                                   double c_ac, double* __restrict__ rhs_ch,
+                                                   double c_ac, TopFlux tf, double* __restrict__ rhs_ch,
                                                    double* __restrict__ rhs_ac) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * BS + threadIdx.x;
@@ -2076,7 +2076,12 @@ __global__ __launch_bounds__(BS) void k_rhs_binary(int n, int side, const int* _
     }
   }
   rhs_ch[row] = s_phi;
-  rhs_ch[n + row] = c_mu * s_fp;
+  double second = c_mu * s_fp;
+  if (tf.coef != 0.0 && row >= tf.top0) {
+    const double w = (row == tf.top0 || row == n - 1) ? 0.5 * tf.h : tf.h;
+    second += tf.coef * (phi[tf.ref] - tf.phi_inf) * w;
+  }
+  rhs_ch[n + row] = second;
   if (rhs_ac) rhs_ac[row] = s_Phi + c_ac * s_fv;
 }
 
@@ -2782,9 +2787,9 @@ void diagnostics(const DSell& A, const double* M, const double* K, const double*
 }
 
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,
-                double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s) {
+                double c_ac, const TopFlux& tf, double* rhs_ch, double* rhs_ac, hipStream_t s) {
   hipLaunchKernelGGL(k_rhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col, Mv,
-                     phi, Phi, c_mu, c_ac, rhs_ch, rhs_ac);
+                     phi, Phi, c_mu, c_ac, tf, rhs_ch, rhs_ac);
 }
 
 template <typename T, typename TV>

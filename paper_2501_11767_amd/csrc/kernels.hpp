@@ -379,8 +379,16 @@ int diag_part_blocks(int64_t n);  // per-block partial sums diagnostics() writes
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
                  const double* Phi, bool ternary, double beta, const PotCoef& pc, double* part, double* out,
                  hipStream_t s);
+// Evaporation load of the closed square's top wall: rows top0 .. nrows-1 (the
+// vertices on y = length; top0 and nrows - 1 are the corners) gain
+// coef * (phi[ref] - phi_inf) * w_i in the CH right-hand side's second block,
+// w_i = int_top phi_i ds = h (h/2 at the corners).  coef = 0: no load.
+struct TopFlux {
+  double coef = 0.0, phi_inf = 0.0, h = 0.0;
+  int top0 = 0, ref = 0;
+};
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
-                double c_mu, double c_ac, double* rhs_ch, double* rhs_ac, hipStream_t s);
+                double c_mu, double c_ac, const TopFlux& tf, double* rhs_ch, double* rhs_ac, hipStream_t s);
 
 // Library-owned device scratch of the allocation-free diagnostics entry
 // point: a file-scope device array (one copy per GPU) of STATIC_SCRATCH

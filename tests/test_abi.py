@@ -61,6 +61,17 @@ def test_create_rejects_bad_domain(L, boundary, length, model, code):
     assert len(L.chns_last_error(None)) > 0
 
 
+@pytest.mark.parametrize("boundary,flux,inf", [(0, 1.0, 0.0), (1, float("inf"), 0.0), (1, 1.0, float("nan"))])
+def test_create_rejects_bad_top_flux(L, boundary, flux, inf):
+    """The top-wall flux exists on the closed square only, with finite values."""
+    h = ct.c_void_p()
+    p = chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)
+    p.top_flux, p.flux_inf = flux, inf
+    rc = L.chns_create(ct.byref(chns.Mesh(16, 1, boundary, 10.0)), ct.byref(p), chns.ALLOC_FN(),
+                       chns.FREE_FN(), None, ct.byref(h))
+    assert rc == chns.EINVAL and not h.value
+
+
 @pytest.mark.parametrize("bad", [dict(eps=float("nan")), dict(tau=-1.0), dict(mobility=0.0),
                                  dict(rho=float("inf")), dict(viscosity=0.0)])
 def test_create_rejects_bad_params(L, bad):

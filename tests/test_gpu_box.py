@@ -249,6 +249,46 @@ def test_paper_square_workload_matches_oracle(C):
     ctx.close()
 
 
+FLUX = dict(PB, top_flux=2.5, flux_inf=0.1)
+
+
+def test_top_flux_rhs_and_steps_match_oracle(C):
+    """The evaporation load of the top wall: the CH right-hand side's second
+    block within 1e-13, three FP64 steps within the step bars, and the phase
+    mass unchanged (the flux loads the mu equation only)."""
+    import torch
+    n = 40
+    ctx = _ctx(C, n, "ch_ac", FLUX)
+    ops = S.Operators(n, box_length=L10)
+    prm = Params(**{k: FLUX[k] for k in ("eps", "tau", "mobility", "evap_rate", "top_flux", "flux_inf")})
+    st = S.initial_state(ops, prm, "ch_ac", inputs.box_state(n, L10, "ch_ac", 0.5, 8, film=0.95))
+    _, sysr = S.step(ops, prm, "ch_ac", st, return_systems=True)
+    assert abs(sysr["j_out"]) > 0.2  # air at the wall: phi(x_ref) = 0, j_out = -k phi_inf
+    phi, mu, Phi = _t(st["phi"][0]), _t(st["mu"][0]), _t(st["Phi_v"])
+    f = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+    rch = torch.zeros(2 * ops.N, dtype=torch.float64, device="cuda")
+    rac = torch.zeros(ops.N, dtype=torch.float64, device="cuda")
+    ctx.step_rhs(f, rch, rac)
+    torch.cuda.synchronize()
+    assert _maxrel(_np(rch), sysr["ch_rhs"][0]) < 1e-13
+    ref = st
+    for _ in range(3):
+        ref = dict(ref, **{k: v for k, v in S.step(ops, prm, "ch_ac", ref).items() if v is not None})
+    m0 = ctx.diagnostics(f)[0]
+    rc, infos = ctx.timestep(f, f, nsteps=3, opts=C.default_opts(rtol=1e-12))
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    assert _rel(_np(phi), ref["phi"][0]) < 1e-10 and _maxrel(_np(phi), ref["phi"][0]) < 1e-10
+    assert _rel(_np(mu), ref["mu"][0]) < 1e-9 and _rel(_np(Phi), ref["Phi_v"]) < 1e-10
+    assert abs(ctx.diagnostics(f)[0] - m0) <= 1e-11 * abs(m0)
+    # the flux may be switched on a periodic context neither at creation nor later
+    per = C.Context(16, "ch_ac", **PB)
+    with pytest.raises(C.ChnsError):
+        per.set_params(**FLUX)
+    per.close()
+    ctx.close()
+
+
 def test_closed_square_refuses_a_velocity(C):
     """No P2 velocity space on the closed square: the convection is refused
     (creation with bad domains is checked on the CPU)."""
