@@ -93,6 +93,28 @@ def dfdPhi_ter(pp, pn, Phi):
     return interp_d(Phi) * (gas - liq)
 
 
+# ----- quaternary: eq. (appPotential) in full (polymer, NFA, solvent, air),
+# the air eliminated as phi_a = 1 - phi_p - phi_N - phi_s (section "Numerical
+# results")
+
+
+def quaternary(pp, pn, ps, Phi):
+    """Nodal terms of eq. (appPotential) with the air eliminated.  Liquid
+    3.5 p^2 n^2 + 0.3 s^2 + 0.3 a^2 - 10 s a, gas 3.5 p^2 + 3.5 n^2 + 2 s^2
+    + 0.1 a^2, interpolated by p(Phi).  Returns f, dp, dn, ds (derivatives along
+    phi_a = 1 - phi_p - phi_N - phi_s: the unreduced partial minus the air's),
+    fa (the unreduced d f / d phi_a, for the closure of mu_a) and fv."""
+    pa = 1.0 - pp - pn - ps
+    liq = 3.5 * pp ** 2 * pn ** 2 + 0.3 * ps ** 2 + 0.3 * pa ** 2 - 10.0 * ps * pa
+    gas = 3.5 * pp ** 2 + 3.5 * pn ** 2 + 2.0 * ps ** 2 + 0.1 * pa ** 2
+    l1 = [7.0 * pp * pn ** 2, 7.0 * pp ** 2 * pn, 0.6 * ps - 10.0 * pa, 0.6 * pa - 10.0 * ps]
+    g1 = [7.0 * pp, 7.0 * pn, 4.0 * ps, 0.2 * pa]
+    P = interp(Phi)
+    F = [(1.0 - P) * l1[i] + P * g1[i] for i in range(4)]
+    return dict(f=(1.0 - P) * liq + P * gas, dp=F[0] - F[3], dn=F[1] - F[3], ds=F[2] - F[3], fa=F[3],
+                fv=interp_d(Phi) * (gas - liq))
+
+
 # ----- ternary densities in unreduced form, with the Flory-Huggins option
 #
 # Section "Free energy functional": the liquid density is the Flory-Huggins

@@ -18,6 +18,12 @@ Models:
               potential is recovered from the second CH equation (the paper's
               air-elimination procedure in section "Numerical results", applied
               to the solvent).
+* ``quaternary`` the paper's full system: polymer, NFA and solvent phases with
+              the air eliminated (phi_a = 1 - phi_p - phi_N - phi_s), the
+              fitted quartic of eq. (appPotential) with its air terms, a
+              gradient coefficient per phase, mu_a from eq. (airdisc), the
+              vapour field and the Oseen step with all four phases in the
+              Korteweg force and the convecting field.
 """
 from __future__ import annotations
 
@@ -82,14 +88,31 @@ def initial_state(ops: Operators, prm: Params, model: str, fields: dict):
         fp = [pot.dfdphi_bin(st["phi"][0])]
     elif model == "ch_ac":
         fp = [pot.dfdphi_bin(st["phi"][0], st["Phi_v"])]
+    elif model == "quaternary":
+        q = pot.quaternary(*st["phi"], st["Phi_v"])
+        fp = [q["dp"], q["dn"], q["ds"]]
     else:
         t = ternary_potential(prm, st["phi"][0], st["phi"][1], st["Phi_v"])
         fp = [t["dp"], t["dn"]]
-    st["mu"] = [chemical_potential(ops, f, ph, prm.beta) for f, ph in zip(fp, st["phi"])]
+    bs = phase_betas(prm, model)
+    st["mu"] = [chemical_potential(ops, f, ph, b) for f, ph, b in zip(fp, st["phi"], bs)]
     if model == "ternary":
         ps = 1.0 - st["phi"][0] - st["phi"][1]
         st["mu_s"] = chemical_potential(ops, t["fs"], ps, prm.beta)
+    if model == "quaternary":
+        pa = 1.0 - st["phi"][0] - st["phi"][1] - st["phi"][2]
+        st["mu_a"] = chemical_potential(ops, q["fa"], pa, bs[3])
     return st
+
+
+def phase_betas(prm: Params, model: str):
+    """Gradient coefficients per phase: (beta_p, beta_N, beta_s, beta_a) for the
+    quaternary model, eps^2 for every phase otherwise."""
+    if model == "quaternary":
+        return [prm.beta_of(i) for i in range(4)]
+    if prm.betas is not None:
+        raise ValueError("per-phase gradient coefficients belong to the quaternary model")
+    return [prm.beta] * 3
 
 
 def explicit_terms(model, st, prm: Params | None = None):
@@ -99,6 +122,9 @@ def explicit_terms(model, st, prm: Params | None = None):
     if model == "ch_ac":
         return ([pot.dfdphi_bin(st["phi"][0], st["Phi_v"])],
                 pot.dfdPhi_bin(st["phi"][0], st["Phi_v"]))
+    if model == "quaternary":
+        q = pot.quaternary(*st["phi"], st["Phi_v"])
+        return [q["dp"], q["dn"], q["ds"]], q["fv"]
     t = ternary_potential(prm if prm is not None else Params(eps=1.0, tau=1.0),
                           st["phi"][0], st["phi"][1], st["Phi_v"])
     return [t["dp"], t["dn"]], t["fv"]
@@ -130,21 +156,28 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
     # evaporation flux at the top wall (closed square, one phase: the solvent)
     flux = None
     if prm.top_flux != 0.0:
-        if not ops.box or model == "ternary":
+        if not ops.box or model not in ("ch", "ch_ac"):
             raise ValueError("the top-wall flux belongs to the binary models on the closed square")
         ref = n // 2 + (n + 1) * n  # midpoint of the top edge
         j_out = prm.top_flux * (st["phi"][0][ref] - prm.flux_inf)
         flux = j_out * fem.top_edge_load(mesh)
         sysrec["j_out"] = j_out
 
-    # Cahn-Hilliard, one solve per phase (same matrix)
-    A_ch = systems.ch_matrix(M, K, C, prm)
-    sysrec["ch"] = A_ch
+    # Cahn-Hilliard, one solve per phase (the same matrix unless the phases'
+    # gradient coefficients differ)
+    bs = phase_betas(prm, model)
+    mats = {}
     phis, mus = [], []
-    for ph, fp in zip(st["phi"], fps):
-        b = systems.ch_rhs(M, ph, fp, prm, flux)
+    for i, (ph, fp) in enumerate(zip(st["phi"], fps)):
+        if bs[i] not in mats:
+            mats[bs[i]] = systems.ch_matrix(M, K, C, prm, beta=bs[i])
+        A_ch = mats[bs[i]]
+        sysrec.setdefault("ch_all", []).append(A_ch)
+        b = systems.ch_rhs(M, ph, fp, prm, flux, beta=bs[i])
         sysrec.setdefault("ch_rhs", []).append(b)
         if how == "fft":
+            if bs[i] != prm.beta:
+                raise ValueError("the Fourier solve takes beta = eps^2")
             x1, x2 = solvers.fft_ch_solve(n, prm, b[:N], b[N:])
             x = np.concatenate([x1, x2])
         else:
@@ -152,9 +185,10 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         phis.append(x[:N])
         mus.append(x[N:])
     out["phi"], out["mu"] = phis, mus
+    sysrec["ch"] = sysrec["ch_all"][0]
 
     # Allen-Cahn
-    if model in ("ch_ac", "ternary"):
+    if model in ("ch_ac", "ternary", "quaternary"):
         A_ac = systems.ac_matrix(M, K, C, prm)
         b = systems.ac_rhs(M, st["Phi_v"], fv, prm)
         sysrec["ac"], sysrec["ac_rhs"] = A_ac, b
@@ -163,12 +197,21 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         out["Phi_v"] = None
 
     # Oseen step and closure
-    if model == "ternary":
-        ps_k = 1.0 - st["phi"][0] - st["phi"][1]
-        grads = [fem.p1_grad(mesh, u) for u in (st["phi"][0], st["phi"][1], ps_k, st["Phi_v"])]
-        betas = [prm.beta, prm.beta, prm.beta, prm.beta_v]
-        mu_grads = [fem.p1_grad(mesh, u) for u in (st["mu"][0], st["mu"][1], st["mu_s"])]
-        w_const = -prm.alpha * (mu_grads[0] + mu_grads[1] + mu_grads[2])
+    if model in ("ternary", "quaternary"):
+        if model == "ternary":
+            ps_k = 1.0 - st["phi"][0] - st["phi"][1]
+            fields = (st["phi"][0], st["phi"][1], ps_k, st["Phi_v"])
+            betas = [prm.beta, prm.beta, prm.beta, prm.beta_v]
+            mu_all = (st["mu"][0], st["mu"][1], st["mu_s"])
+        else:
+            if prm.rho_pure is not None:
+                raise ValueError("variable density is defined for the ternary model")
+            pa_k = 1.0 - st["phi"][0] - st["phi"][1] - st["phi"][2]
+            fields = (st["phi"][0], st["phi"][1], st["phi"][2], pa_k, st["Phi_v"])
+            betas = bs + [prm.beta_v]
+            mu_all = (st["mu"][0], st["mu"][1], st["mu"][2], st["mu_a"])
+        grads = [fem.p1_grad(mesh, u) for u in fields]
+        w_const = -prm.alpha * sum(fem.p1_grad(mesh, u) for u in mu_all)
         rho_k = systems.density(prm, st["phi"][0], st["phi"][1])
         Mrho = None if rho_k is None else fem.p2_mass_weighted(mesh, rho_k)
         F = fem.korteweg_load(mesh, grads, betas)
@@ -189,9 +232,14 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         sysrec["ns_Mrho"], sysrec["ns_conv_vel"], sysrec["ns_w_const"] = Mrho, used, w_const
         out["vel"] = v
         out["p"] = p
-        ps1 = 1.0 - phis[0] - phis[1]
-        fs_k = ternary_potential(prm, st["phi"][0], st["phi"][1], st["Phi_v"])["fs"]
-        out["mu_s"] = fs_k + prm.beta * ops.mass_solve(K @ ps1)
+        if model == "ternary":
+            ps1 = 1.0 - phis[0] - phis[1]
+            fs_k = ternary_potential(prm, st["phi"][0], st["phi"][1], st["Phi_v"])["fs"]
+            out["mu_s"] = fs_k + prm.beta * ops.mass_solve(K @ ps1)
+        else:  # eq. (airdisc) for the air: M mu_a = M f_a^k + beta_a K phi_a^{k+1}
+            pa1 = 1.0 - phis[0] - phis[1] - phis[2]
+            fa_k = pot.quaternary(*st["phi"], st["Phi_v"])["fa"]
+            out["mu_a"] = fa_k + bs[3] * ops.mass_solve(K @ pa1)
     if return_systems:
         return out, sysrec
     return out
@@ -218,3 +266,15 @@ def energy_ternary(ops: Operators, prm: Params, pp, pn, Phi):
     ps = 1.0 - pp - pn
     grad = sum(u @ (ops.K @ u) for u in (pp, pn, ps))
     return 0.5 * prm.beta * grad + lump @ ternary_potential(prm, pp, pn, Phi)["f"]
+
+
+def energy_quaternary(ops: Operators, prm: Params, pp, pn, ps, Phi):
+    """The discrete free energy of the quaternary model like energy_ternary:
+    sum_i beta_i/2 phi_i^T K phi_i over polymer, NFA, solvent and the
+    eliminated air, plus sum_j (M 1)_j f(phi_p, phi_N, phi_s, Phi)_j with the
+    density of eq. (appPotential)."""
+    lump = ops.M @ np.ones(ops.N)
+    pa = 1.0 - pp - pn - ps
+    bs = phase_betas(prm, "quaternary")
+    grad = sum(b * (u @ (ops.K @ u)) for b, u in zip(bs, (pp, pn, ps, pa)))
+    return 0.5 * grad + lump @ pot.quaternary(pp, pn, ps, Phi)["f"]

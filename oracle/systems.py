@@ -52,6 +52,13 @@ class Params:
     # and P_0 into one coefficient
     top_flux: float = 0.0
     flux_inf: float = 0.0
+    # per-phase gradient coefficients (beta_p, beta_N, beta_s, beta_a) of the
+    # quaternary model (section "Numerical results" gives them per phase);
+    # None: eps^2 for every phase.  The vapour field keeps beta_v = eps^2.
+    betas: tuple | None = None
+
+    def beta_of(self, i: int) -> float:
+        return self.beta if self.betas is None else self.betas[i]
 
     @property
     def beta(self):
@@ -74,17 +81,21 @@ class Params:
         return self.eps ** 2
 
 
-def ch_matrix(M, K, C, prm: Params):
-    t, g, b = prm.tau, prm.gamma, prm.beta
+def ch_matrix(M, K, C, prm: Params, beta=None):
+    """beta: the phase's gradient coefficient (default eps^2)."""
+    t, g = prm.tau, prm.gamma
+    b = prm.beta if beta is None else beta
     A11 = M + t * C if C is not None else M
     return sp.bmat([[A11, t * g * K], [t * g * K, -(t * g / b) * M]], format="csr")
 
 
-def ch_rhs(M, phi_k, fprime, prm: Params, flux=None):
+def ch_rhs(M, phi_k, fprime, prm: Params, flux=None, beta=None):
     """flux: the boundary load int_Gamma_t j_out w_i ds of the second CH
     equation (eq. (weakch) for mu: M mu - beta K phi = M f' - beta flux),
-    which enters the scaled second row as + tau g flux."""
-    t, g, b = prm.tau, prm.gamma, prm.beta
+    which enters the scaled second row as + tau g flux.  beta: the phase's
+    gradient coefficient (default eps^2)."""
+    t, g = prm.tau, prm.gamma
+    b = prm.beta if beta is None else beta
     second = -(t * g / b) * (M @ fprime)
     if flux is not None:
         second = second + t * g * flux

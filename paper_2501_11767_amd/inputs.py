@@ -108,7 +108,8 @@ def log_uniform(g: np.random.Generator, lo: float, hi: float) -> float:
 
 # Workloads.  "binary" = one Cahn-Hilliard phase with the double-well / mixing
 # potential; "ternary" = polymer and NFA phases (solvent eliminated) with the
-# fitted quartic potential, plus the vapour field and the Oseen step.
+# fitted quartic potential, plus the vapour field and the Oseen step;
+# "quaternary" = polymer, NFA and solvent phases with the air eliminated.
 CONFIGS = {
     "ch32": dict(n=32, model="ch", eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.0,
                  viscosity=1.0, steps=1, mean=0.5, seed=BASE_SEED + 0),
@@ -142,15 +143,25 @@ def initial_state(n: int, model: str, mean: float, seed: int, with_velocity: boo
     Each field draws from its own child stream of ``SeedSequence(seed)``.
     """
     ss = np.random.SeedSequence(seed)
-    kids = ss.spawn(4)
+    kids = ss.spawn(5 if model == "quaternary" else 4)
     seeds = [int(k.generate_state(1)[0]) for k in kids]
-    nphase = 2 if model == "ternary" else 1
-    phi = [noisy_field(n, mean, 0.01, seeds[i]) for i in range(nphase)]
-    Phi_v = vapour_layer(n) if model in ("ch_ac", "ternary") else None
+    flow = model in ("ternary", "quaternary")
+    if model == "quaternary":
+        # the paper's film (polymer and NFA at mean, solvent at 1 - 2 mean, each
+        # +- 0.01) where the vapour layer is liquid (Phi_v^0 < 1/2), air (all
+        # three phases 0) where it is vapour
+        film = vapour_layer(n) < 0.5
+        means = (mean, mean, 1.0 - 2.0 * mean)
+        phi = [np.where(film, noisy_field(n, means[i], 0.01, seeds[i if i < 2 else 4]), 0.0)
+               for i in range(3)]
+    else:
+        nphase = 2 if model == "ternary" else 1
+        phi = [noisy_field(n, mean, 0.01, seeds[i]) for i in range(nphase)]
+    Phi_v = vapour_layer(n) if model in ("ch_ac", "ternary", "quaternary") else None
     if with_velocity is None:
-        with_velocity = model == "ternary"
+        with_velocity = flow
     vel = stream_velocity(n, seeds[2]) if with_velocity else None
-    p = np.zeros(n * n) if model == "ternary" else None
+    p = np.zeros(n * n) if flow else None
     return dict(phi=phi, Phi_v=Phi_v, vel=vel, p=p)
 
 
