@@ -70,7 +70,13 @@ enum {
 enum {
   CHNS_MODEL_CH = 0,      /* one CH phase, double-well potential phi^2 (1-phi)^2 */
   CHNS_MODEL_CH_AC = 1,   /* one CH phase + vapour field, liquid/gas interpolated potential */
-  CHNS_MODEL_TERNARY = 2  /* polymer + NFA CH phases (solvent = 1 - sum), vapour, Oseen */
+  CHNS_MODEL_TERNARY = 2, /* polymer + NFA CH phases (solvent = 1 - sum), vapour, Oseen */
+  CHNS_MODEL_QUATERNARY = 3 /* the paper's full system: polymer, NFA, solvent CH phases with the
+                               air eliminated (phi_a = 1 - sum, section "Numerical results"), the
+                               fitted quartic of eq. (appPotential) with its air terms, a gradient
+                               coefficient per phase (beta_phase), mu_a from eq. (airdisc),
+                               vapour, Oseen with all four phases in the Korteweg force and the
+                               convecting field */
 };
 
 /* Linear systems (blocks) of a step. */
@@ -157,6 +163,13 @@ typedef struct {
      square root and P_0 of the flux law into one finite coefficient. */
   double top_flux;
   double flux_inf;
+  /* quaternary model only (else 0): the gradient coefficients beta_p, beta_N,
+     beta_s, beta_a (each > 0) of the CH phases and of the eliminated air; the
+     vapour field keeps beta_v = eps^2 and delta_v = evap_rate * eps^2.  Each
+     CH solve forms its block with its phase's beta (the second row's
+     -(tau g / beta_i) M and X = tau g K + sqrt(tau g / beta_i) M); between
+     steps the CH operators hold the polymer's. */
+  double beta_phase[4];
 } chns_params;
 
 typedef struct {
@@ -188,11 +201,13 @@ typedef struct {
 
 /* Field set at one time level (device pointers; NULL where the model has no
  * such field).  phi[0], phi[1]: CH phases (n^2 each); mu[0..1] their chemical
- * potentials; mu[2] the eliminated solvent's potential (ternary); Phi_v: vapour
- * field (n^2); vel: P2 velocity (2 * 4n^2); p: pressure (n^2, mean zero). */
+ * potentials; mu[2] the eliminated solvent's potential (ternary); quaternary:
+ * phi[0..2] polymer, NFA, solvent, mu[0..2] theirs and mu[3] the eliminated
+ * air's; Phi_v: vapour field (n^2); vel: P2 velocity (2 * 4n^2); p: pressure
+ * (n^2, mean zero). */
 typedef struct {
-  double* phi[2];
-  double* mu[3];
+  double* phi[3];
+  double* mu[4];
   double* Phi_v;
   double* vel;
   double* p;
@@ -260,8 +275,9 @@ CHNS_API int chns_set_density(chns_ctx* ctx, const double* d_phi_p, const double
  * for the ternary model), Galerkin refresh of every coarse level, and
  * re-forming of the block values.  d_mu: for the ternary model the three
  * chemical potentials (polymer, NFA, solvent) entering the convecting field
- * w = rho v - alpha sum_i grad mu_i (an entry or the array may be NULL for
- * mu = 0); ignored otherwise. */
+ * w = rho v - alpha sum_i grad mu_i, for the quaternary model four (polymer,
+ * NFA, solvent, air) (an entry or the array may be NULL for mu = 0); ignored
+ * otherwise. */
 CHNS_API int chns_assemble(chns_ctx* ctx, const double* d_vel, const double* const* d_mu,
                            void* stream);
 
@@ -343,15 +359,18 @@ CHNS_API int chns_krylov_solve(chns_ctx* ctx, int32_t block, int32_t transpose, 
  * the discrete mass 1^T M u of every phase field and the discrete free energy
  * of the paper's functional (section "Free energy functional"; mass
  * conservation of the Cahn-Hilliard phases).  h_out[0]: 1^T M phi (binary) or
- * 1^T M phi_p (ternary); h_out[1]: 1^T M phi_N (ternary, else 0); h_out[2]:
- * 1^T M phi_s of the eliminated solvent phi_s = 1 - phi_p - phi_N (ternary,
- * else 0); h_out[3]: 1^T M Phi_v (models with a vapour field, else 0);
+ * 1^T M phi_p (ternary, quaternary); h_out[1]: 1^T M phi_N (ternary,
+ * quaternary, else 0); h_out[2]: 1^T M phi_s (quaternary; ternary: of the
+ * eliminated solvent phi_s = 1 - phi_p - phi_N; else 0); h_out[3]: 1^T M Phi_v
+ * (models with a vapour field, else 0);
  * h_out[4]: E_h = sum_i beta/2 phi_i^T K phi_i + sum_j (M 1)_j f(x_j), the
  * phases i of the model (ternary: polymer, NFA and solvent), f the model's
  * local density (binary: double-well, interpolated with the gas form by
  * p(Phi_v) when there is a vapour field; ternary: the fitted quartic with
- * air = 0) at the nodal values, beta = eps^2.  Fields: phi[0] (and phi[1]
- * for the ternary model; Phi_v for models with a vapour field) are device
+ * air = 0; quaternary: eq. (appPotential) with the air eliminated and the
+ * gradient sum over the four phases with beta_phase) at the nodal values,
+ * beta = eps^2.  Fields: phi[0] (and phi[1] for the flow models, phi[2] for
+ * the quaternary; Phi_v for models with a vapour field) are device
  * pointers of n^2 doubles; other members are ignored.  h_out: 5 doubles on
  * the host.  CHNS_EINVAL for a missing field or output. */
 CHNS_API int chns_diagnostics(chns_ctx* ctx, const chns_fields* f, double* h_out, void* stream);
@@ -375,9 +394,11 @@ CHNS_API int chns_diagnostics_noalloc(chns_ctx* ctx, const chns_fields* f, doubl
  * right-hand side, and for the ternary model (rho/tau) M v^k + F^k with the
  * Korteweg force F = int G : grad, G = beta sum_i grad phi_i (x) grad phi_i
  * + beta_v grad Phi (x) grad Phi over polymer, NFA and solvent, and zero
- * pressure rows).  d_rhs_ch: 2n^2 per CH phase, phases consecutive; d_rhs_ac:
- * n^2 (required for models with a vapour field); d_rhs_ns: 9n^2 (required for
- * the ternary model). */
+ * pressure rows; quaternary: beta_i per phase, the Korteweg sum over polymer,
+ * NFA, solvent and air).  d_rhs_ch: 2n^2 per CH phase, phases consecutive
+ * (quaternary: the second row of phase i scaled by -(tau g / beta_i));
+ * d_rhs_ac: n^2 (required for models with a vapour field); d_rhs_ns: 9n^2
+ * (required for the flow models). */
 CHNS_API int chns_step_rhs(chns_ctx* ctx, const chns_fields* in, double* d_rhs_ch,
                            double* d_rhs_ac, double* d_rhs_ns, void* stream);
 
@@ -388,9 +409,11 @@ CHNS_API int chns_step_rhs(chns_ctx* ctx, const chns_fields* in, double* d_rhs_c
  * set).  Per step: assemble C(v^k) (and J(w^k), A_p(w^k)), the right-hand
  * sides of chns_step_rhs, one FGMRES solve of eq. (CH_linear) per CH phase,
  * the AC solve, the Oseen solve of eq. (linearnav), and the closure of the
- * eliminated phase (section "Numerical results", air elimination applied to
- * the solvent).  h_info (may be NULL) receives one entry per solve, in the
- * order CH phases, AC, NS, per step.  Synchronising. */
+ * eliminated phase (section "Numerical results": the air for the quaternary
+ * model, mu_a = f_a^k + beta_a M^{-1} K phi_a^{k+1}; the same procedure
+ * applied to the solvent for the ternary model).  h_info (may be NULL)
+ * receives one entry per solve, in the order CH phases, AC, NS, per step.
+ * Synchronising. */
 CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
                            int32_t nsteps, const chns_solve_opts* opts,
                            chns_solve_info* h_info, void* stream);
@@ -409,8 +432,9 @@ CHNS_API int chns_timestep(chns_ctx* ctx, const chns_fields* in, const chns_fiel
  * s^k; h_info (4 entries, may be NULL) receives their reports.  The initial
  * state of a run is data (independent of theta).  Leaves the context holding
  * the transposed operators.  Returns CHNS_WNOCONV if a solve did not
- * converge; CHNS_EUNSUPPORTED for the binary models and for var_density or
- * ns_picard > 1 (the reverse step covers the linear constant-density scheme).
+ * converge; CHNS_EUNSUPPORTED for the binary and quaternary models and for
+ * var_density or ns_picard > 1 (the reverse step covers the linear
+ * constant-density ternary scheme).
  * Synchronising. */
 CHNS_API int chns_timestep_adjoint(chns_ctx* ctx, const chns_fields* in, const chns_fields* out,
                                    const chns_fields* lam_out, const chns_fields* lam_in,

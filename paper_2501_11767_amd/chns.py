@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libchns.so")
 
 OK, WNOCONV, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
-MODEL_CH, MODEL_CH_AC, MODEL_TERNARY = 0, 1, 2
+MODEL_CH, MODEL_CH_AC, MODEL_TERNARY, MODEL_QUATERNARY = 0, 1, 2, 3
 BLOCK_CH, BLOCK_AC, BLOCK_NS = 0, 1, 2
 OP_M, OP_K, OP_C, OP_CH, OP_AC, OP_X, OP_L, OP_NS, OP_VX, OP_AP = range(10)
 KERNEL_CHEB32, KERNEL_CHEB64, KERNEL_CH_BLOCK, KERNEL_DCGS_DOTS, KERNEL_DCGS_UPDATE, KERNEL_MG_FINE = range(6)
@@ -27,7 +27,7 @@ KERNEL_NAMES = {
     KERNEL_MG_FINE: "k_vtile_pipe (finest-level tile passes; k_vtile in FP64)",
 }
 F64, MIXED = 0, 1
-MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY}
+MODELS = {"ch": MODEL_CH, "ch_ac": MODEL_CH_AC, "ternary": MODEL_TERNARY, "quaternary": MODEL_QUATERNARY}
 
 EXPORTS = [
     "chns_default_opts", "chns_create", "chns_destroy", "chns_set_params", "chns_assemble", "chns_set_density",
@@ -63,13 +63,14 @@ class Params(ct.Structure):
                [("potential", ct.c_int32), ("truncate", ct.c_int32), ("fh_nsize", ct.c_double * 3),
                 ("fh_chi", ct.c_double * 3), ("fh_phisat", ct.c_double * 3),
                 ("var_density", ct.c_int32), ("ns_picard", ct.c_int32), ("rho_pure", ct.c_double * 3),
-                ("ns_picard_tol", ct.c_double), ("top_flux", ct.c_double), ("flux_inf", ct.c_double)]
+                ("ns_picard_tol", ct.c_double), ("top_flux", ct.c_double), ("flux_inf", ct.c_double),
+                ("beta_phase", ct.c_double * 4)]
 
     def __init__(self, *args, **kw):
-        arrays = {k: kw.pop(k) for k in ("fh_nsize", "fh_chi", "fh_phisat", "rho_pure") if k in kw}
+        arrays = {k: kw.pop(k) for k in ("fh_nsize", "fh_chi", "fh_phisat", "rho_pure", "beta_phase") if k in kw}
         super().__init__(*args, **kw)
         for k, v in arrays.items():
-            setattr(self, k, (ct.c_double * 3)(*v))
+            setattr(self, k, (ct.c_double * len(v))(*v))
 
 
 class SolveOpts(ct.Structure):
@@ -127,7 +128,7 @@ def _allocator(use_torch):
 
 
 class Fields(ct.Structure):
-    _fields_ = [("phi", ct.c_void_p * 2), ("mu", ct.c_void_p * 3), ("Phi_v", ct.c_void_p),
+    _fields_ = [("phi", ct.c_void_p * 3), ("mu", ct.c_void_p * 4), ("Phi_v", ct.c_void_p),
                 ("vel", ct.c_void_p), ("p", ct.c_void_p)]
 
 
@@ -282,10 +283,12 @@ class Context:
         if mu is None:
             return None
         mu = list(mu)
-        if len(mu) != 3:
-            raise ValueError("mu: expected three chemical potentials (polymer, NFA, solvent)")
+        k = 4 if self.model == "quaternary" else 3
+        if len(mu) != k:
+            raise ValueError(f"mu: expected {k} chemical potentials (polymer, NFA, solvent"
+                             + (", air)" if k == 4 else ")"))
         self._mu_keep = mu
-        return (ct.c_void_p * 3)(*[_ptr(t, self.N, name=f"mu[{i}]", optional=True)
+        return (ct.c_void_p * k)(*[_ptr(t, self.N, name=f"mu[{i}]", optional=True)
                                    for i, t in enumerate(mu)])
 
     def set_density(self, phi_p, phi_n):
@@ -348,8 +351,8 @@ class Context:
         layout and size); the tensors stay referenced by the returned
         structure so they outlive the calls that use it."""
         phi, mu = tuple(phi), tuple(mu)
-        if len(phi) > 2 or len(mu) > 3:
-            raise ValueError("at most two phase fields and three chemical potentials")
+        if len(phi) > 3 or len(mu) > 4:
+            raise ValueError("at most three phase fields and four chemical potentials")
         f = Fields()
         f._keep = (phi, mu, Phi_v, vel, p)
         for i, t in enumerate(phi):
@@ -362,7 +365,7 @@ class Context:
         return f
 
     def step_rhs(self, fin: Fields, rhs_ch, rhs_ac=None, rhs_ns=None):
-        nch = 2 if self.model == "ternary" else 1
+        nch = {"ternary": 2, "quaternary": 3}.get(self.model, 1)
         self._check(self.L.chns_step_rhs(self.h, ct.byref(fin), _ptr(rhs_ch, 2 * nch * self.N, name="rhs_ch"),
                                          _ptr(rhs_ac, self.N, name="rhs_ac", optional=True),
                                          _ptr(rhs_ns, 9 * self.N, name="rhs_ns", optional=True), _stream()))
@@ -404,7 +407,7 @@ class Context:
 
     def timestep(self, fin: Fields, fout: Fields, nsteps=1, opts=None, nsolves=None):
         o = opts or default_opts()
-        per = {"ch": 1, "ch_ac": 2, "ternary": 4}[self.model]
+        per = {"ch": 1, "ch_ac": 2, "ternary": 4, "quaternary": 5}[self.model]
         k = nsolves or per * nsteps
         infos = (SolveInfo * k)()
         rc = self._check(self.L.chns_timestep(self.h, ct.byref(fin), ct.byref(fout), nsteps,

@@ -178,6 +178,22 @@ int check_orientation(chns_ctx* c, bool symmetric, int32_t transpose) {
                         : "the context holds the transposed operators: call chns_assemble first");
 }
 
+// Parameters that belong to some models or domains only: the reason, or null.
+const char* model_params_error(int model, bool box, const chns_params* p) {
+  const bool ter = model == CHNS_MODEL_TERNARY, quat = model == CHNS_MODEL_QUATERNARY;
+  if (!ter && (p->potential != CHNS_POT_QUARTIC || p->truncate))
+    return "the Flory-Huggins density and the truncation apply to the ternary model";
+  if (!ter && p->var_density) return "variable density applies to the ternary model";
+  if (!ter && !quat && p->ns_picard > 1) return "Picard passes apply to the ternary and quaternary models";
+  if (!box && p->top_flux != 0.0) return "the top-wall flux belongs to the closed square";
+  for (int i = 0; i < 4; ++i) {
+    const double b = p->beta_phase[i];
+    if (quat && !(std::isfinite(b) && b > 0.0)) return "the quaternary model needs beta_phase[0..3] > 0";
+    if (!quat && b != 0.0) return "per-phase gradient coefficients belong to the quaternary model";
+  }
+  return nullptr;
+}
+
 int check_params(chns_ctx* c, const chns_params* p) {
   if (!p) return fail(c, CHNS_EINVAL, "params is NULL");
   const double v[] = {p->eps, p->tau, p->mobility, p->evap_rate, p->viscosity, p->alpha, p->rho};
@@ -236,7 +252,7 @@ int form_ternary(chns_ctx* c, hipStream_t s);
 // M + tau delta_v K + tau C on every level, with FP32 copies and 1/diag.
 int form_operators(chns_ctx* c, hipStream_t s) {
   const auto& p = c->prm;
-  const double beta = p.eps * p.eps, tg = p.tau * p.mobility;
+  const double beta = c->beta_ch, tg = p.tau * p.mobility;
   const double smatch = std::sqrt(tg / beta);
   const double delta_v = p.evap_rate * p.eps * p.eps;
   c->coefL[0] = 1.0;
@@ -365,9 +381,9 @@ int assemble_ternary_conv(chns_ctx* c, const double* d_vel, const double* const*
                           hipStream_t s) {
   Level& L0 = c->lv[0];
   P2Level& P = c->p2;
-  MuGrad mg{{nullptr, nullptr, nullptr}, c->prm.alpha};
+  MuGrad mg{{nullptr, nullptr, nullptr, nullptr}, c->prm.alpha};
   if (d_mu)
-    for (int i = 0; i < 3; ++i) mg.mu[i] = d_mu[i];
+    for (int i = 0; i < (c->quat ? 4 : 3); ++i) mg.mu[i] = d_mu[i];
   HIPCHK(c, hipMemsetAsync(P.J, 0, P.sell.slots() * sizeof(double), s));
   HIPCHK(c, hipMemsetAsync(L0.Cw, 0, L0.sell.slots() * sizeof(double), s));
   double* jo[1] = {P.J};
@@ -1121,7 +1137,7 @@ int apply_block(chns_ctx* c, int block, const double* x, double* y, double alpha
     yin = nullptr;
   }
   if (block == CHNS_BLOCK_CH) {
-    const double tg = p.tau * p.mobility, beta_ = p.eps * p.eps;
+    const double tg = p.tau * p.mobility, beta_ = c->beta_ch;
     const double* Lv = c->has_conv ? L0.L.v64 : L0.M;
     // values M, K (and L when C != 0), x and y of both rows; y read when beta != 0
     const double bytes = double(c->N) * (8 * (14 + (c->has_conv ? 7 : 0)) + 32 + (beta != 0.0 ? 16 : 0));
@@ -1305,7 +1321,7 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
         // CH operator (values, z read, w written) and the dots of V_0..V_j-1, vt
         const double bytes = double(c->N) * (8 * (14 + (c->has_conv ? 7 : 0)) + 32) + 8.0 * n * (j + 1);
         timed(c, CHNS_KERNEL_CH_BLOCK, bytes, s, [&](LaunchEv ev) {
-          ch_dcgs_dots(L0.d, Lv, L0.K, L0.M, tg, -tg / (p.eps * p.eps), zj, K.V, ld, j, st, s, ev);
+          ch_dcgs_dots(L0.d, Lv, L0.K, L0.M, tg, -tg / c->beta_ch, zj, K.V, ld, j, st, s, ev);
         });
       } else {
         timed(c, CHNS_KERNEL_DCGS_DOTS, 8.0 * n * (kk0 + 2), s,
@@ -1606,7 +1622,7 @@ int build(chns_ctx* c) {
   const size_t NB = c->ternary ? 9 * N1 : N2;  // largest block
   for (double** v : {&c->w64a, &c->w64b, &c->w64c, &c->w64d, &c->rhs_ac, &c->xac, &c->fs})
     TRY(dalloc(c, v, N1));
-  for (double** v : {&c->rhs_ch, &c->xch}) TRY(dalloc(c, v, 2 * N2));
+  for (double** v : {&c->rhs_ch, &c->xch}) TRY(dalloc(c, v, (c->quat ? 3 : 2) * N2));
   if (c->ternary) {
     for (double** v : {&c->rhs_ns, &c->xns}) TRY(dalloc(c, v, 9 * N1));
     TRY(dalloc(c, &c->rho1, N1));
@@ -1747,7 +1763,8 @@ int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_
   HIPCHK(c, hipMemsetAsync(rhs_ns + 2 * N4, 0, N * sizeof(double), s));
   for (int col = 0; col < 8; ++col)
     korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
-             c->h, c->ns.tb, in->phi[0], in->phi[1], in->Phi_v, beta, beta, N4, rhs_ns, s);
+             c->h, c->ns.tb, in->phi[0], in->phi[1], nullptr, in->Phi_v, KorBeta{{beta, beta, beta, 0.0}, beta},
+             N4, rhs_ns, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -1845,6 +1862,88 @@ int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   return CHNS_OK;
 }
 
+// Quaternary right-hand sides: three CH blocks (polymer, NFA, solvent, each
+// with its own beta), the AC block, the Oseen momentum rows with the Korteweg
+// load of all four phases, and f_a (the air's unreduced derivative) into fa.
+int quaternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_ac, double* rhs_ns,
+                   double* fa, hipStream_t s) {
+  const auto& p = c->prm;
+  const int N = c->N;
+  const double tg = p.tau * p.mobility, bv = p.eps * p.eps;
+  Level& L0 = c->lv[0];
+  const Coef3 cmu{{-tg / p.beta_phase[0], -tg / p.beta_phase[1], -tg / p.beta_phase[2]}};
+  rhs_quaternary(L0.d, L0.M, in->phi[0], in->phi[1], in->phi[2], in->Phi_v, cmu, -p.tau * p.evap_rate, rhs_ch,
+                 rhs_ac, fa, s);
+  P2Level& P = c->p2;
+  const int64_t N4 = 4 * int64_t(N);
+  const double cm = p.rho / p.tau;
+  spmv<double, double>(P.d, P.Mv, in->vel, rhs_ns, cm, 0.0, s);
+  spmv<double, double>(P.d, P.Mv, in->vel + N4, rhs_ns + N4, cm, 0.0, s);
+  HIPCHK(c, hipMemsetAsync(rhs_ns + 2 * N4, 0, N * sizeof(double), s));
+  const KorBeta kb{{p.beta_phase[0], p.beta_phase[1], p.beta_phase[2], p.beta_phase[3]}, bv};
+  for (int col = 0; col < 8; ++col)
+    korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype, c->h, c->ns.tb,
+             in->phi[0], in->phi[1], in->phi[2], in->Phi_v, kb, N4, rhs_ns, s);
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
+// The CH block's beta (the second row's -(tau g / beta) M and the matching
+// factor X): re-form the operators on every level when it changes.
+int set_beta_ch(chns_ctx* c, double beta, hipStream_t s) {
+  if (beta == c->beta_ch) return CHNS_OK;
+  c->beta_ch = beta;
+  for (double& r : c->kr.rate) r = -1.0;  // the rate predictor belongs to the other system
+  return form_operators(c, s);
+}
+
+// One quaternary step: three CH solves (each phase's beta), AC, Oseen (with
+// Picard passes when asked), then the air's closure mu_a = f_a^k + beta_a
+// M^{-1} K phi_a^{k+1} with phi_a = 1 - phi_p - phi_N - phi_s (eq. (airdisc)).
+// The CH operators are left formed with the polymer's beta.
+int quaternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out, const chns_solve_opts& o,
+                    chns_solve_info** info, int& worst, hipStream_t s) {
+  const auto& p = c->prm;
+  const int N = c->N;
+  const size_t bytes = size_t(N) * sizeof(double);
+  const double* mu4[4] = {cur.mu[0], cur.mu[1], cur.mu[2], cur.mu[3]};
+  TRY(chns_assemble(c, cur.vel, mu4, s));
+  TRY(quaternary_rhs(c, &cur, c->rhs_ch, c->rhs_ac, c->rhs_ns, c->fs, s));
+  double* xch = c->xch;
+  for (int ph = 0; ph < 3; ++ph) {
+    HIPCHK(c, hipMemcpyAsync(xch + 2 * ph * size_t(N), cur.phi[ph], bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(xch + (2 * ph + 1) * size_t(N), cur.mu[ph], bytes, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->xac, cur.Phi_v, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->xns, cur.vel, 8 * bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->xns + 8 * size_t(N), cur.p, bytes, hipMemcpyDeviceToDevice, s));
+  for (int ph = 0; ph < 3; ++ph) {
+    TRY(set_beta_ch(c, p.beta_phase[ph], s));
+    TRY(chns_solve_block(c, CHNS_BLOCK_CH, c->rhs_ch + 2 * ph * size_t(N), xch + 2 * ph * size_t(N), o, info,
+                         worst, s));
+  }
+  TRY(set_beta_ch(c, p.beta_phase[0], s));
+  TRY(chns_solve_block(c, CHNS_BLOCK_AC, c->rhs_ac, c->xac, o, info, worst, s));
+  chns_solve_info* ns_rec = (info && *info) ? *info : nullptr;
+  TRY(chns_solve_block(c, CHNS_BLOCK_NS, c->rhs_ns, c->xns, o, info, worst, s));
+  if (p.ns_picard > 1) TRY(picard_passes(c, cur, mu4, o, ns_rec, worst, s));
+  for (int ph = 0; ph < 3; ++ph) {
+    HIPCHK(c, hipMemcpyAsync(out->phi[ph], xch + 2 * ph * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(out->mu[ph], xch + (2 * ph + 1) * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(out->Phi_v, c->xac, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(out->vel, c->xns, 8 * bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(out->p, c->xns + 8 * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
+  Level& L0 = c->lv[0];
+  one_minus_sum(N, out->phi[0], out->phi[1], c->w64c, s);                 // 1 - p - n
+  axpby<double>(N, -1.0, out->phi[2], 1.0, c->w64c, s);                    // - s
+  spmv<double, double>(L0.d, L0.K, c->w64c, c->w64a, 1.0, 0.0, s);
+  cheb_from_zero<double>(c, L0, L0.Mp, c->w64a, c->w64b, cheb_coef<double>(0.49, 2.01, 40), s);
+  axpy_into(N, p.beta_phase[3], c->w64b, c->fs, out->mu[3], s);
+  HIPCHK(c, hipGetLastError());
+  return CHNS_OK;
+}
+
 // Adjoint of one ternary step (differentiation form).  With the transposed
 // operators of state k: the closure adjoint q = beta K M^{-1} nu_s, the two CH
 // solves A^T eta_i = [lambda_phi_i - q; lambda_mu_i], the AC solve
@@ -1938,7 +2037,7 @@ int ternary_adjoint(chns_ctx* c, const chns_fields& in, const chns_fields& out, 
   HIPCHK(c, hipMemsetAsync(A.F, 0, 8 * bytes, s));
   for (int col = 0; col < 8; ++col)
     korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype, h, c->ns.tb,
-             in.phi[0], in.phi[1], in.Phi_v, beta, beta, N4, A.F, s);
+             in.phi[0], in.phi[1], nullptr, in.Phi_v, KorBeta{{beta, beta, beta, 0.0}, beta}, N4, A.F, s);
   dot_acc(8 * int64_t(N), A.xi, A.F, 2.0 / p.eps, A.part, A.acc, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
@@ -1992,7 +2091,7 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = "n must be even and in 8..8192";
     return CHNS_EINVAL;
   }
-  if (mesh->model < CHNS_MODEL_CH || mesh->model > CHNS_MODEL_TERNARY) {
+  if (mesh->model < CHNS_MODEL_CH || mesh->model > CHNS_MODEL_QUATERNARY) {
     g_create_err = "unknown model";
     return CHNS_EINVAL;
   }
@@ -2004,11 +2103,7 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = "length must be finite and > 0 (0 for 1)";
     return CHNS_EINVAL;
   }
-  if (mesh->boundary != CHNS_BOUNDARY_NOFLUX && params->top_flux != 0.0) {
-    g_create_err = "the top-wall flux belongs to the closed square";
-    return CHNS_EINVAL;
-  }
-  if (mesh->boundary == CHNS_BOUNDARY_NOFLUX && mesh->model == CHNS_MODEL_TERNARY) {
+  if (mesh->boundary == CHNS_BOUNDARY_NOFLUX && mesh->model >= CHNS_MODEL_TERNARY) {
     g_create_err = "the closed square carries the binary models (no Taylor-Hood spaces with no-slip walls)";
     return CHNS_EUNSUPPORTED;
   }
@@ -2017,12 +2112,8 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = tmp.err;
     return CHNS_EINVAL;
   }
-  if (mesh->model != CHNS_MODEL_TERNARY && (params->potential != CHNS_POT_QUARTIC || params->truncate)) {
-    g_create_err = "the Flory-Huggins density and the truncation apply to the ternary model";
-    return CHNS_EINVAL;
-  }
-  if (mesh->model != CHNS_MODEL_TERNARY && (params->var_density || params->ns_picard > 1)) {
-    g_create_err = "variable density and Picard passes apply to the ternary model";
+  if (const char* why = model_params_error(mesh->model, mesh->boundary == CHNS_BOUNDARY_NOFLUX, params)) {
+    g_create_err = why;
     return CHNS_EINVAL;
   }
   chns_ctx* c = new chns_ctx();
@@ -2031,7 +2122,10 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
   c->alloc_ctx = alloc_ctx;
   c->mesh = *mesh;
   c->prm = *params;
-  c->ternary = (mesh->model == CHNS_MODEL_TERNARY);
+  // the flow models (Taylor-Hood Oseen step): ternary and quaternary
+  c->ternary = (mesh->model == CHNS_MODEL_TERNARY || mesh->model == CHNS_MODEL_QUATERNARY);
+  c->quat = mesh->model == CHNS_MODEL_QUATERNARY;
+  c->beta_ch = c->quat ? params->beta_phase[0] : params->eps * params->eps;
   c->box = mesh->boundary == CHNS_BOUNDARY_NOFLUX;
   c->len = mesh->length > 0.0 ? mesh->length : 1.0;
   c->h = c->len / mesh->n;
@@ -2066,12 +2160,9 @@ int chns_destroy(chns_ctx* c) {
 int chns_set_params(chns_ctx* c, const chns_params* p) {
   if (!c) return CHNS_EINVAL;
   TRY(check_params(c, p));
-  if (!c->ternary && (p->potential != CHNS_POT_QUARTIC || p->truncate))
-    return fail(c, CHNS_EINVAL, "the Flory-Huggins density and the truncation apply to the ternary model");
-  if (!c->ternary && (p->var_density || p->ns_picard > 1))
-    return fail(c, CHNS_EINVAL, "variable density and Picard passes apply to the ternary model");
-  if (!c->box && p->top_flux != 0.0) return fail(c, CHNS_EINVAL, "the top-wall flux belongs to the closed square");
+  if (const char* why = model_params_error(c->mesh.model, c->box, p)) return fail(c, CHNS_EINVAL, why);
   c->prm = *p;
+  c->beta_ch = c->quat ? p->beta_phase[0] : p->eps * p->eps;
   // the residual reduction rates of earlier solves belong to other systems
   for (double& r : c->kr.rate) r = -1.0;
   if (c->ternary) TRY(assemble_sym_stiffness(c, nullptr));
@@ -2087,7 +2178,7 @@ int chns_assemble(chns_ctx* c, const double* d_vel, const double* const* d_mu, v
 
 int chns_set_density(chns_ctx* c, const double* d_phi_p, const double* d_phi_n, void* stream) {
   if (!c) return CHNS_EINVAL;
-  if (!c->ternary || !c->prm.var_density)
+  if (!c->ternary || c->quat || !c->prm.var_density)
     return fail(c, CHNS_EINVAL, "the density field needs a ternary context with var_density");
   if (!d_phi_p || !d_phi_n) return fail(c, CHNS_EINVAL, "phi_p and phi_n are required");
   return set_density(c, d_phi_p, d_phi_n, static_cast<hipStream_t>(stream));
@@ -2183,7 +2274,7 @@ int chns_get_matrix(chns_ctx* c, int32_t op, int32_t* h_rowptr, int32_t* h_col, 
   }
   // CH block [[L, tg K], [tg K, -(tg/beta) M]] assembled on the host from the device streams
   std::vector<double> Lv, Kv, Mv;
-  const double tg = c->prm.tau * c->prm.mobility, beta = c->prm.eps * c->prm.eps;
+  const double tg = c->prm.tau * c->prm.mobility, beta = c->beta_ch;
   if (h_val) {
     TRY(fetch(c->has_conv ? L0.L.v64 : L0.M, Lv));
     TRY(fetch(L0.K, Kv));
@@ -2220,7 +2311,7 @@ int chns_spmv(chns_ctx* c, int32_t op, int32_t precision, int32_t transpose, dou
   hipStream_t s = static_cast<hipStream_t>(stream);
   Level& L0 = c->lv[0];
   const auto& p = c->prm;
-  const double tg = p.tau * p.mobility, be = p.eps * p.eps;
+  const double tg = p.tau * p.mobility, be = c->beta_ch;
   if (op == CHNS_OP_CH) {
     if (precision == CHNS_F64) {
       ch_block<double, double>(L0.d, c->has_conv ? L0.L.v64 : L0.M, L0.K, L0.M, tg, -tg / be,
@@ -2299,6 +2390,11 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
                   void* stream) {
   if (!c) return CHNS_EINVAL;
   if (!in || !in->phi[0] || !d_rhs_ch) return fail(c, CHNS_EINVAL, "missing field or output");
+  if (c->quat) {
+    if (!in->phi[1] || !in->phi[2] || !in->Phi_v || !in->vel || !d_rhs_ac || !d_rhs_ns)
+      return fail(c, CHNS_EINVAL, "the quaternary model needs phi[0..2], Phi_v, vel and all outputs");
+    return quaternary_rhs(c, in, d_rhs_ch, d_rhs_ac, d_rhs_ns, c->fs, static_cast<hipStream_t>(stream));
+  }
   if (c->ternary) {
     if (!in->phi[1] || !in->Phi_v || !in->vel || !d_rhs_ac || !d_rhs_ns)
       return fail(c, CHNS_EINVAL, "the ternary model needs phi[0..1], Phi_v, vel and all outputs");
@@ -2325,16 +2421,27 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
   return CHNS_OK;
 }
 
+// Gradient coefficients of the energy per phase (the eliminated phase last).
+KorBeta diag_betas(const chns_ctx* c) {
+  const double b = c->prm.eps * c->prm.eps;
+  if (c->quat) {
+    const double* q = c->prm.beta_phase;
+    return KorBeta{{q[0], q[1], q[2], q[3]}, b};
+  }
+  return KorBeta{{b, b, b, b}, b};
+}
+
 int chns_diagnostics(chns_ctx* c, const chns_fields* f, double* h_out, void* stream) {
   if (!c) return CHNS_EINVAL;
   if (!f || !f->phi[0] || !h_out) return fail(c, CHNS_EINVAL, "phi[0] and the output are required");
   const bool vapour = c->mesh.model != CHNS_MODEL_CH;
   if (c->ternary && !f->phi[1]) return fail(c, CHNS_EINVAL, "the ternary model needs phi[1]");
+  if (c->quat && !f->phi[2]) return fail(c, CHNS_EINVAL, "the quaternary model needs phi[2]");
   if (vapour && !f->Phi_v) return fail(c, CHNS_EINVAL, "model needs Phi_v");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Level& L0 = c->lv[0];
-  diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, vapour ? f->Phi_v : nullptr,
-              c->ternary, c->prm.eps * c->prm.eps, pot_coef(c->prm), c->kr.part, c->diag, s);
+  diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, c->quat ? f->phi[2] : nullptr,
+              vapour ? f->Phi_v : nullptr, c->ternary, diag_betas(c), pot_coef(c->prm), c->kr.part, c->diag, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(h_out, c->diag, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -2346,6 +2453,7 @@ int chns_diagnostics_noalloc(chns_ctx* c, const chns_fields* f, double* h_out, v
   if (!f || !f->phi[0] || !h_out) return fail(c, CHNS_EINVAL, "phi[0] and the output are required");
   const bool vapour = c->mesh.model != CHNS_MODEL_CH;
   if (c->ternary && !f->phi[1]) return fail(c, CHNS_EINVAL, "the ternary model needs phi[1]");
+  if (c->quat && !f->phi[2]) return fail(c, CHNS_EINVAL, "the quaternary model needs phi[2]");
   if (vapour && !f->Phi_v) return fail(c, CHNS_EINVAL, "model needs Phi_v");
   int dev = -1;
   HIPCHK(c, hipGetDevice(&dev));
@@ -2361,8 +2469,8 @@ int chns_diagnostics_noalloc(chns_ctx* c, const chns_fields* f, double* h_out, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* part = scr;                  // NDIAG x nblk partials, each written before it is read
   double* res = scr + NDIAG * nblk;    // NDIAG results
-  diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, vapour ? f->Phi_v : nullptr,
-              c->ternary, c->prm.eps * c->prm.eps, pot_coef(c->prm), part, res, s);
+  diagnostics(L0.d, L0.M, L0.K, f->phi[0], c->ternary ? f->phi[1] : nullptr, c->quat ? f->phi[2] : nullptr,
+              vapour ? f->Phi_v : nullptr, c->ternary, diag_betas(c), pot_coef(c->prm), part, res, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(h_out, res, NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -2379,15 +2487,19 @@ int chns_timestep(chns_ctx* c, const chns_fields* in, const chns_fields* out, in
     return fail(c, CHNS_EINVAL, "phi[0] and mu[0] are required");
   if (c->ternary) {
     const chns_fields* fs[2] = {in, out};
-    for (const chns_fields* f : fs)
+    for (const chns_fields* f : fs) {
       if (!f->phi[1] || !f->mu[1] || !f->mu[2] || !f->Phi_v || !f->vel || !f->p)
-        return fail(c, CHNS_EINVAL, "the ternary model needs every field");
+        return fail(c, CHNS_EINVAL, "the ternary and quaternary models need every field");
+      if (c->quat && (!f->phi[2] || !f->mu[3]))
+        return fail(c, CHNS_EINVAL, "the quaternary model needs phi[0..2] and mu[0..3]");
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     int worst = CHNS_OK;
     chns_fields cur = *in;
     chns_solve_info* info = h_info;
     for (int k = 0; k < nsteps; ++k) {
-      TRY(ternary_step(c, cur, out, *opts, &info, worst, s));
+      if (c->quat) TRY(quaternary_step(c, cur, out, *opts, &info, worst, s));
+      else TRY(ternary_step(c, cur, out, *opts, &info, worst, s));
       cur = *out;
     }
     HIPCHK(c, hipStreamSynchronize(s));
@@ -2431,7 +2543,7 @@ int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields*
                           const chns_solve_opts* opts, chns_solve_info* h_info, void* stream) {
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
-  if (!c->ternary) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is defined for the ternary model");
+  if (!c->ternary || c->quat) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is defined for the ternary model");
   if (c->prm.var_density || c->prm.ns_picard > 1)
     return fail(c, CHNS_EUNSUPPORTED, "the adjoint step covers the linear scheme with constant density");
   if (!in || !out || !lam_out || !lam_in || !h_dtheta) return fail(c, CHNS_EINVAL, "NULL argument");

@@ -1224,6 +1224,10 @@ int chns_batch_create(int32_t count, const int32_t* h_n, const chns_params* h_pa
       g_batch_err = "the top-wall flux belongs to the closed square";
       return CHNS_EINVAL;
     }
+    if (p.beta_phase[0] != 0.0 || p.beta_phase[1] != 0.0 || p.beta_phase[2] != 0.0 || p.beta_phase[3] != 0.0) {
+      g_batch_err = "per-phase gradient coefficients belong to the quaternary model";
+      return CHNS_EINVAL;
+    }
   }
   chns_batch* b = new chns_batch();
   b->alloc = alloc;

@@ -145,7 +145,9 @@ struct chns_ctx {
   double h = 0.0;       // finest mesh width len / n
   bool has_conv = false;
   bool c_zero = true;   // C and C32 hold zeros on every level
-  bool ternary = false;
+  bool ternary = false;  // a flow model (ternary or quaternary): Taylor-Hood Oseen step
+  bool quat = false;     // the quaternary model (three CH phases, air eliminated)
+  double beta_ch = 0.0;  // the gradient coefficient the CH operators are formed with
   // device table of the fused operator formation (one entry per level)
   chns::FormLevel* form_tab = nullptr;
   int64_t form_total = 0;

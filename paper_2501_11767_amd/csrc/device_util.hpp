@@ -132,7 +132,7 @@ __device__ __forceinline__ void mu_const(const MuGrad& mg, const int* vtx, const
                                          double& wx, double& wy) {
   wx = 0.0;
   wy = 0.0;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     if (!mg.mu[i]) continue;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -260,6 +260,37 @@ __device__ __forceinline__ double density_ternary(double pp, double pn, double P
   const TerParts t = ter_parts(x.p, x.n, x.s, c);
   const double ip = P * P * (3.0 - 2.0 * P);
   return (1.0 - ip) * t.liq + ip * t.gas;
+}
+
+// Quaternary model: eq. (appPotential) in all four phases with the air
+// eliminated, a = 1 - p - n - s.  Liquid 3.5 p^2 n^2 + 0.3 s^2 + 0.3 a^2 -
+// 10 s a, gas 3.5 p^2 + 3.5 n^2 + 2 s^2 + 0.1 a^2, interpolated by
+// P = Phi^2 (3 - 2 Phi).  dp, dn, ds: derivatives along the elimination (the
+// unreduced partial minus the air's); fa: the unreduced air partial (closure
+// of mu_a); fv: d f / d Phi.
+__device__ __forceinline__ void quaternary_terms(double p, double n, double s, double P, double& dp,
+                                                 double& dn, double& ds, double& fa, double& fv) {
+  const double a = 1.0 - p - n - s;
+  const double ip = P * P * (3.0 - 2.0 * P), q = 1.0 - ip;
+  const double Fp = q * (7.0 * p * n * n) + ip * (7.0 * p);
+  const double Fn = q * (7.0 * p * p * n) + ip * (7.0 * n);
+  const double Fs = q * (0.6 * s - 10.0 * a) + ip * (4.0 * s);
+  const double Fa = q * (0.6 * a - 10.0 * s) + ip * (0.2 * a);
+  dp = Fp - Fa;
+  dn = Fn - Fa;
+  ds = Fs - Fa;
+  fa = Fa;
+  const double liq = 3.5 * p * p * n * n + 0.3 * s * s + 0.3 * a * a - 10.0 * s * a;
+  const double gas = 3.5 * p * p + 3.5 * n * n + 2.0 * s * s + 0.1 * a * a;
+  fv = 6.0 * P * (1.0 - P) * (gas - liq);
+}
+
+__device__ __forceinline__ double density_quaternary(double p, double n, double s, double P) {
+  const double a = 1.0 - p - n - s;
+  const double ip = P * P * (3.0 - 2.0 * P);
+  const double liq = 3.5 * p * p * n * n + 0.3 * s * s + 0.3 * a * a - 10.0 * s * a;
+  const double gas = 3.5 * p * p + 3.5 * n * n + 2.0 * s * s + 0.1 * a * a;
+  return (1.0 - ip) * liq + ip * gas;
 }
 
 }  // namespace chns

@@ -1975,7 +1975,8 @@ __device__ __forceinline__ double density_binary(double phi, const double* Phi, 
 __global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restrict__ col,
                                              const double* __restrict__ Mv, const double* __restrict__ Kv,
                                              const double* __restrict__ p0, const double* __restrict__ p1,
-                                             const double* __restrict__ Phi, int ternary, double beta,
+                                             const double* __restrict__ p2,
+                                             const double* __restrict__ Phi, int ternary, KorBeta kb,
                                              PotCoef pc, double* __restrict__ part) {
   __shared__ double sh[4];
   double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1984,32 +1985,40 @@ __global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restr
     const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
     int c[W7];
     row_cols7(row, side, col, base, c);
-    double w = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0;
+    // K-weighted sums of the phases and of the eliminated one
+    double w = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
 #pragma unroll
     for (int k = 0; k < W7; ++k) {
       const double kv = Kv[base + k * 64], a = p0[c[k]];
       w += Mv[base + k * 64];
       k0 += kv * a;
       if (ternary) {
-        const double b = p1[c[k]];
+        const double b = p1[c[k]], d = p2 ? p2[c[k]] : 0.0;
         k1 += kv * b;
-        k2 += kv * (1.0 - a - b);
+        if (p2) k2 += kv * d;
+        k3 += kv * (1.0 - a - b - d);
       }
     }
     const double u0 = p0[row];
-    double grad = u0 * k0, f;
+    double grad = kb.b[0] * u0 * k0, f;
     acc[0] += w * u0;
     if (ternary) {
-      const double u1 = p1[row], us = 1.0 - u0 - u1;
+      const double u1 = p1[row], u2 = p2 ? p2[row] : 0.0, ue = 1.0 - u0 - u1 - u2;
       acc[1] += w * u1;
-      acc[2] += w * us;
-      grad += u1 * k1 + us * k2;
-      f = density_ternary(u0, u1, Phi ? Phi[row] : 0.0, pc);
+      if (p2) {  // quaternary: polymer, NFA, solvent given, air eliminated
+        acc[2] += w * u2;
+        grad += kb.b[1] * u1 * k1 + kb.b[2] * u2 * k2 + kb.b[3] * ue * k3;
+        f = density_quaternary(u0, u1, u2, Phi ? Phi[row] : 0.0);
+      } else {   // ternary: the solvent eliminated
+        acc[2] += w * ue;
+        grad += kb.b[1] * u1 * k1 + kb.b[2] * ue * k3;
+        f = density_ternary(u0, u1, Phi ? Phi[row] : 0.0, pc);
+      }
     } else {
       f = density_binary(u0, Phi, row);
     }
     if (Phi) acc[3] += w * Phi[row];
-    acc[4] += 0.5 * beta * grad + w * f;
+    acc[4] += 0.5 * grad + w * f;
   }
 #pragma unroll
   for (int q = 0; q < NDIAG; ++q) {
@@ -2252,28 +2261,38 @@ __global__ __launch_bounds__(BS) void k_korteweg(int e0, int e1, const int* __re
                                                  const int* __restrict__ etype, double h,
                                                  DP2Tables tb, const double* __restrict__ php,
                                                  const double* __restrict__ phn,
-                                                 const double* __restrict__ Phi, double beta,
-                                                 double beta_v, int64_t n2,
+                                                 const double* __restrict__ phs,
+                                                 const double* __restrict__ Phi, KorBeta kb, int64_t n2,
                                                  double* __restrict__ out) {
   const int e = e0 + blockIdx.x * BS + threadIdx.x;
   if (e >= e1) return;
   const ElemGeo g = elem_geo(etype[e], h);
   const int* v = ep1 + size_t(e) * 3;
-  double gp[2] = {0, 0}, gn[2] = {0, 0}, gv[2] = {0, 0};
+  double gp[2] = {0, 0}, gn[2] = {0, 0}, gs[2] = {0, 0}, gv[2] = {0, 0};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     gp[0] += php[v[a]] * g.gx[a];
     gp[1] += php[v[a]] * g.gy[a];
     gn[0] += phn[v[a]] * g.gx[a];
     gn[1] += phn[v[a]] * g.gy[a];
+    if (phs) {
+      gs[0] += phs[v[a]] * g.gx[a];
+      gs[1] += phs[v[a]] * g.gy[a];
+    }
     gv[0] += Phi[v[a]] * g.gx[a];
     gv[1] += Phi[v[a]] * g.gy[a];
   }
-  const double gs[2] = {-gp[0] - gn[0], -gp[1] - gn[1]};  // solvent = 1 - phi_p - phi_N
+  // the eliminated phase, one minus the given ones (solvent, or air when the
+  // solvent is given)
+  const double ge[2] = {-gp[0] - gn[0] - gs[0], -gp[1] - gn[1] - gs[1]};
   double G[2][2];
   for (int c = 0; c < 2; ++c)
-    for (int d = 0; d < 2; ++d)
-      G[c][d] = beta * (gp[c] * gp[d] + gn[c] * gn[d] + gs[c] * gs[d]) + beta_v * gv[c] * gv[d];
+    for (int d = 0; d < 2; ++d) {
+      double t = kb.b[0] * gp[c] * gp[d] + kb.b[1] * gn[c] * gn[d] + kb.bv * gv[c] * gv[d];
+      if (phs) t += kb.b[2] * gs[c] * gs[d] + kb.b[3] * ge[c] * ge[d];
+      else t += kb.b[2] * ge[c] * ge[d];
+      G[c][d] = t;
+    }
   for (int k = 0; k < 6; ++k) {
     const int node = ep2[e * 6 + k];
     for (int c = 0; c < 2; ++c) {
@@ -2344,6 +2363,55 @@ __global__ __launch_bounds__(BS) void k_rhs_ternary(int n, int side, const int* 
   double dp, dn, fv, fs;
   ternary_terms(php[row], phn[row], Phi[row], pc, dp, dn, fv, fs);
   fs_out[row] = fs;
+}
+
+// Quaternary right-hand sides: per CH phase i (polymer, NFA, solvent) the
+// blocks M phi_i and c_mu[i] M d_i (d_i the derivative along the air's
+// elimination), the AC block M Phi + c_ac M f_v, and the unreduced air
+// derivative f_a at each vertex (closure of mu_a).
+__global__ __launch_bounds__(BS) void k_rhs_quaternary(int n, int side, const int* __restrict__ col,
+                                                       const double* __restrict__ Mv,
+                                                       const double* __restrict__ php,
+                                                       const double* __restrict__ phn,
+                                                       const double* __restrict__ phs,
+                                                       const double* __restrict__ Phi, Coef3 c_mu,
+                                                       double c_ac, double* __restrict__ rhs_ch,
+                                                       double* __restrict__ rhs_ac,
+                                                       double* __restrict__ fa_out) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * BS + threadIdx.x;
+  if (row >= n) return;
+  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  double s_p = 0, s_n = 0, s_s = 0, s_dp = 0, s_dn = 0, s_ds = 0, s_P = 0, s_fv = 0;
+  int cc[W7];
+  row_cols7(row, side, col, base, cc);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const int j = cc[k];
+    const double m = Mv[base + k * 64];
+    const double a = php[j], b = phn[j], c = phs[j], P = Phi[j];
+    double dp, dn, ds, fa, fv;
+    quaternary_terms(a, b, c, P, dp, dn, ds, fa, fv);
+    s_p += m * a;
+    s_n += m * b;
+    s_s += m * c;
+    s_dp += m * dp;
+    s_dn += m * dn;
+    s_ds += m * ds;
+    s_P += m * P;
+    s_fv += m * fv;
+  }
+  const int64_t N = n;
+  rhs_ch[row] = s_p;
+  rhs_ch[N + row] = c_mu.v[0] * s_dp;
+  rhs_ch[2 * N + row] = s_n;
+  rhs_ch[3 * N + row] = c_mu.v[1] * s_dn;
+  rhs_ch[4 * N + row] = s_s;
+  rhs_ch[5 * N + row] = c_mu.v[2] * s_ds;
+  rhs_ac[row] = s_P + c_ac * s_fv;
+  double dp, dn, ds, fa, fv;
+  quaternary_terms(php[row], phn[row], phs[row], Phi[row], dp, dn, ds, fa, fv);
+  fa_out[row] = fa;
 }
 
 template <typename T>
@@ -2778,12 +2846,19 @@ void form_ops(int nlev, const FormLevel* tab, int64_t total, const FormCoef& k, 
 int diag_part_blocks(int64_t n) { return reduce_blocks(n); }
 
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
-                 const double* Phi, bool ternary, double beta, const PotCoef& pc, double* part, double* out,
-                 hipStream_t s) {
+                 const double* p2, const double* Phi, bool ternary, const KorBeta& kb, const PotCoef& pc,
+                 double* part, double* out, hipStream_t s) {
   const int nblk = reduce_blocks(A.nrows);
-  hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, Phi,
-                     ternary ? 1 : 0, beta, pc, part);
+  hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, p2, Phi,
+                     ternary ? 1 : 0, kb, pc, part);
   hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(BS), 0, s, nblk, part, out);
+}
+
+void rhs_quaternary(const DSell& A, const double* Mv, const double* php, const double* phn, const double* phs,
+                    const double* Phi, const Coef3& c_mu, double c_ac, double* rhs_ch, double* rhs_ac,
+                    double* fa, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_quaternary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col,
+                     Mv, php, phn, phs, Phi, c_mu, c_ac, rhs_ch, rhs_ac, fa);
 }
 
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,
@@ -2902,11 +2977,11 @@ void diff_norms(int64_t n, const double* v, const double* w, double* part, doubl
 }
 
 void korteweg(int e0, int e1, const int* ep1, const int* ep2, const int* etype, double h,
-              DP2Tables tb, const double* php, const double* phn, const double* Phi, double beta,
-              double beta_v, int64_t n2, double* out, hipStream_t s) {
+              DP2Tables tb, const double* php, const double* phn, const double* phs, const double* Phi,
+              const KorBeta& kb, int64_t n2, double* out, hipStream_t s) {
   if (e1 <= e0) return;
   hipLaunchKernelGGL(k_korteweg, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, e0, e1, ep1, ep2,
-                     etype, h, tb, php, phn, Phi, beta, beta_v, n2, out);
+                     etype, h, tb, php, phn, phs, Phi, kb, n2, out);
 }
 
 void form_ns(int64_t nslots, const int8_t* kind, const int* src, double cm, const double* Mv,

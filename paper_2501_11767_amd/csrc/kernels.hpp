@@ -374,11 +374,32 @@ struct PotCoef {
   double chi[3] = {0, 0, 0};       // (p, n), (p, s), (n, s)
   double lsat[3] = {0, 0, 0};      // ln phi_sat
 };
+// Gradient coefficients of the phases (in the order of the fields given, the
+// eliminated phase last) and of the vapour field.
+struct KorBeta {
+  double b[4];
+  double bv;
+};
+
+// Three per-phase scalars passed by value.
+struct Coef3 {
+  double v[3];
+};
+
 constexpr int NDIAG = 5;
 int diag_part_blocks(int64_t n);  // per-block partial sums diagnostics() writes per quantity
+// [mass p0, mass p1, mass of the third phase (p2, or 1 - p0 - p1 when p2 is
+// null), mass Phi, energy]; the energy's gradient part sums kb.b[i]/2 u_i^T K u_i
+// over p0, p1, p2 (if given) and the eliminated phase, in that order.
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
-                 const double* Phi, bool ternary, double beta, const PotCoef& pc, double* part, double* out,
-                 hipStream_t s);
+                 const double* p2, const double* Phi, bool ternary, const KorBeta& kb, const PotCoef& pc,
+                 double* part, double* out, hipStream_t s);
+// Quaternary right-hand sides (polymer, NFA, solvent; air eliminated):
+// rhs_ch holds three CH blocks [M phi_i; c_mu[i] M d_i] of 2n each, rhs_ac the
+// AC block, fa the unreduced air derivative per vertex.
+void rhs_quaternary(const DSell& A, const double* Mv, const double* php, const double* phn, const double* phs,
+                    const double* Phi, const Coef3& c_mu, double c_ac, double* rhs_ch, double* rhs_ac,
+                    double* fa, hipStream_t s);
 // Evaporation load of the closed square's top wall: rows top0 .. nrows-1 (the
 // vertices on y = length; top0 and nrows - 1 are the corners) gain
 // coef * (phi[ref] - phi_inf) * w_i in the CH right-hand side's second block,
@@ -419,9 +440,9 @@ struct DP2Tables {
 };
 
 // Per-element gradient sources for the constant part of the convecting field
-// w = rho v - alpha sum_i grad mu_i (mu: up to 3 P1 fields, may be null).
+// w = rho v - alpha sum_i grad mu_i (mu: up to 4 P1 fields, each may be null).
 struct MuGrad {
-  const double* mu[3];
+  const double* mu[4];
   double alpha;
 };
 
@@ -451,12 +472,14 @@ void density_fields(int n, const double* pp, const double* pn, const double* rpu
 void fill(int64_t n, double v, double* out, hipStream_t s);
 // out[0] = ||v - w||_2, out[1] = ||v||_2; part holds 2 * 256 partial sums.
 void diff_norms(int64_t n, const double* v, const double* w, double* part, double* out, hipStream_t s);
-// Korteweg load F_(c,k) += int G : grad(psi_k e_c), G = beta sum over
-// phi_p, phi_N, phi_s = 1 - phi_p - phi_N of grad phi (x) grad phi, plus
-// beta_v grad Phi (x) grad Phi; out has 2 x n2 entries.
+// Korteweg load F_(c,k) += int G : grad(psi_k e_c), G = sum_i b_i grad phi_i
+// (x) grad phi_i over the given phases (phi_p, phi_N and, when phs is not
+// null, phi_s) and the eliminated one (one minus their sum: the solvent, or
+// the air when the solvent is given), coefficients kb.b in that order, plus
+// kb.bv grad Phi (x) grad Phi; out has 2 x n2 entries.
 void korteweg(int e0, int e1, const int* ep1, const int* ep2, const int* etype, double h,
-              DP2Tables tb, const double* php, const double* phn, const double* Phi, double beta,
-              double beta_v, int64_t n2, double* out, hipStream_t s);
+              DP2Tables tb, const double* php, const double* phn, const double* phs, const double* Phi,
+              const KorBeta& kb, int64_t n2, double* out, hipStream_t s);
 
 // Oseen operator values from the streams: kind 0 cm Mv + J + Kxx, 1 Kxy,
 // 2 Kyx, 3 cm Mv + J + Kyy (src: P2 slot), 4 B (src: B slot), -1 zero.

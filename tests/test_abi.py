@@ -61,6 +61,27 @@ def test_create_rejects_bad_domain(L, boundary, length, model, code):
     assert len(L.chns_last_error(None)) > 0
 
 
+QB = (2e-4, 2e-4, 1e-3, 4e-3)
+
+
+@pytest.mark.parametrize("model,boundary,kw,code", [
+    (3, 1, dict(beta_phase=QB), -5),                              # quaternary on the closed square
+    (3, 0, dict(beta_phase=(1e-3, 1e-3, 0.0, 1.0)), -1),          # a beta not positive
+    (3, 0, dict(beta_phase=(1e-3, 1e-3, float("nan"), 1.0)), -1),
+    (2, 0, dict(beta_phase=QB), -1),                              # per-phase betas: quaternary only
+    (3, 0, dict(beta_phase=QB, potential=1), -1),                 # Flory-Huggins: ternary only
+    (3, 0, dict(beta_phase=QB, var_density=1, rho_pure=(1.0, 1.0, 1.0)), -1),
+    (1, 0, dict(ns_picard=3), -1)])                               # Picard: flow models only
+def test_create_rejects_model_parameters(L, model, boundary, kw, code):
+    h = ct.c_void_p()
+    p = chns.Params(**dict(dict(eps=0.05, tau=1e-4, mobility=1.0, evap_rate=0.5, viscosity=1.0,
+                                alpha=1e-3, rho=1.0), **kw))
+    rc = L.chns_create(ct.byref(chns.Mesh(16, model, boundary, 1.0)), ct.byref(p), chns.ALLOC_FN(),
+                       chns.FREE_FN(), None, ct.byref(h))
+    assert rc == code and not h.value
+    assert len(L.chns_last_error(None)) > 0
+
+
 @pytest.mark.parametrize("boundary,flux,inf", [(0, 1.0, 0.0), (1, float("inf"), 0.0), (1, 1.0, float("nan"))])
 def test_create_rejects_bad_top_flux(L, boundary, flux, inf):
     """The top-wall flux exists on the closed square only, with finite values."""
