@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--dry-steps", type=int, default=5)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--box-steps", type=int, default=5)
+    ap.add_argument("--quad-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64", help="timed forms of the 1024^2 step")
@@ -296,6 +297,45 @@ def dry_section(chns, steps):
                          f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid cut at rho <= {MG['mg_rho_cut']}",
                 ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
                 iters_ch_p_ch_n_ac_ns=its, steps=steps)
+
+
+def quad_section(chns, steps):
+    """The paper's full system on the periodic 256 x 256 mesh (quad256): three
+    CH phases with their own beta, AC, Taylor-Hood Oseen, air closure, in
+    plain FP64 with the drying workload's solver options: ms per coupled step
+    and FGMRES iterations, each step from the seeded state (mu^0 = 0)."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    cfg = inputs.CONFIGS["quad256"]
+    n = cfg["n"]
+    N = n * n
+    ctx = chns.Context(n, "quaternary", eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"],
+                       evap_rate=cfg["evap_rate"], viscosity=cfg["viscosity"], alpha=cfg["alpha"], rho=1.0,
+                       beta_phase=cfg["betas"])
+    st = inputs.initial_state(n, "quaternary", cfg["mean"], cfg["seed"])
+    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
+    f = ctx.fields(phi=[dev(st["phi"][i]) for i in range(3)], mu=[z(), z(), z(), z()], Phi_v=dev(st["Phi_v"]),
+                   vel=dev(st["vel"].ravel()), p=dev(st["p"]))
+    e = lambda k: torch.empty(k, dtype=torch.float64, device="cuda")
+    fo = ctx.fields(phi=[e(N), e(N), e(N)], mu=[e(N), e(N), e(N), e(N)], Phi_v=e(N), vel=e(8 * N), p=e(N))
+    opts = chns.default_opts(rtol=1e-8, precision=chns.F64, maxiter=1000, **DRY_OPTS)
+    ctx.timestep(f, fo, 1, opts)
+    torch.cuda.synchronize()
+    walls, its = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rc, inf = ctx.timestep(f, fo, 1, opts)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        its.append([i["iters"] for i in inf])
+    ctx.close()
+    b = cfg["betas"]
+    return dict(workload=f"quad256: quaternary CH (polymer, NFA, solvent; air eliminated) + AC + Taylor-Hood "
+                         f"Oseen step, periodic {n}x{n} ({3 * 2 * N} CH + {N} AC + {9 * N} NS unknowns), FP64, "
+                         f"beta_p,N,s,a {b}, beta_v {cfg['eps'] ** 2:.0e}, tau {cfg['tau']}, FGMRES("
+                         f"{DRY_OPTS['restart']}) rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid",
+                ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
+                iters_ch_p_ch_n_ch_s_ac_ns=its[-1], steps=steps)
 
 
 def box_section(chns, steps, restart):
@@ -762,6 +802,7 @@ def main():
     dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
     bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
     box = box_section(chns, args.box_steps, args.restart) if args.box_steps > 0 else None
+    quad = quad_section(chns, args.quad_steps) if args.quad_steps > 0 else None
     adj = None if args.no_adjoint else adjoint_section(chns)
     cpu = None
     if not args.no_cpu:
@@ -825,6 +866,7 @@ def main():
         "dry256": dry,
         "batch64": bat,
         "box10": box,
+        "quad256": quad,
         "adjoint128": adj,
     }
     ctx.close()

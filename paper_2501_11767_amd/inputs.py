@@ -125,6 +125,13 @@ CONFIGS = {
     # multigrid hierarchy halves down to 4
     "box10": dict(n=128, length=10.0, model="ch_ac", eps=0.1 ** 0.5, tau=1e-4, mobility=1.0,
                   evap_rate=1.0, viscosity=1.0, steps=1, mean=1.0, seed=BASE_SEED + 5),
+    # the paper's full system (polymer, NFA, solvent, air eliminated) with its
+    # per-phase gradient coefficients beta_p = beta_N = 1e-3, beta_s = 1e-1,
+    # beta_a = beta_v = 1 scaled by eps^2 = 1e-4 onto the periodic unit square
+    # (the ratios kept), tau = 1e-4, gamma = gamma_v = 1, alpha = 1e-8, a = 0.33
+    "quad256": dict(n=256, model="quaternary", eps=0.01, tau=1e-4, mobility=1.0, evap_rate=1.0,
+                    viscosity=1.0, alpha=1e-8, betas=(1e-7, 1e-7, 1e-5, 1e-4), steps=1, mean=0.33,
+                    seed=BASE_SEED + 6),
     "batch64": dict(instances=64, sizes=(64, 128, 256, 512), seed=BASE_SEED + 3),
     # Differentiation workload.  With the explicit potential the ternary run on
     # this mesh diverges within 6 steps at tau = 1e-3, 8 at 1e-4 and 17 at 1e-5

@@ -264,6 +264,64 @@ def test_dry256_step_satisfies_oracle_systems(mods):
     assert _rel(g["mu"][2], mus) <= 1e-10
 
 
+def test_quad256_step_satisfies_oracle_systems(mods):
+    """The quaternary workload at full size in the benchmark's configuration:
+    the GPU solution of every system (three CH phases with their betas, AC,
+    Oseen with the four-phase Korteweg load) leaves a residual within 2 rtol in
+    the oracle's independently assembled systems, and the air closure matches
+    eq. (airdisc)."""
+    import torch
+    C, _ = mods
+    cfg = inputs.CONFIGS["quad256"]
+    n, N = cfg["n"], cfg["n"] ** 2
+    rtol = 1e-8
+    print("quad256 full size: quaternary step vs the oracle's systems", flush=True)
+    p = dict(eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"],
+             viscosity=cfg["viscosity"], alpha=cfg["alpha"], rho=1.0)
+    st = inputs.initial_state(n, "quaternary", cfg["mean"], cfg["seed"])
+    vel0 = np.asarray(st["vel"]).reshape(2, 4 * N)
+    ctx = C.Context(n, "quaternary", beta_phase=cfg["betas"], **p)
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    fin = ctx.fields(phi=[_dev(st["phi"][i]) for i in range(3)], mu=[z(N), z(N), z(N), z(N)],
+                     Phi_v=_dev(st["Phi_v"]), vel=_dev(vel0), p=z(N))
+    o = dict(phi=[z(N), z(N), z(N)], mu=[z(N), z(N), z(N), z(N)], Phi_v=z(N), vel=z(8 * N), p=z(N))
+    fout = ctx.fields(**o)
+    rc, info = ctx.timestep(fin, fout, 1, C.default_opts(rtol=rtol, precision=C.F64, maxiter=1000, restart=15,
+                                                         **BENCH_MG))
+    torch.cuda.synchronize()
+    assert rc == C.OK, info
+    g = {k: ([t.cpu().numpy() for t in v] if isinstance(v, list) else v.cpu().numpy()) for k, v in o.items()}
+    ctx.close()
+
+    prm = Params(betas=cfg["betas"], **p)
+    ops = S.Operators(n, need_p2=True)
+    m, M, K = ops.mesh, ops.M, ops.K
+    ph0, Phi0 = st["phi"], st["Phi_v"]
+    q = pot.quaternary(*ph0, Phi0)
+    Cv = fem.p1_convection(m, vel0)
+    for i, d in enumerate(("dp", "dn", "ds")):
+        A = systems.ch_matrix(M, K, Cv, prm, beta=cfg["betas"][i])
+        b = systems.ch_rhs(M, ph0[i], q[d], prm, beta=cfg["betas"][i])
+        x = np.concatenate([g["phi"][i], g["mu"][i]])
+        assert np.linalg.norm(b - A @ x) <= 2 * rtol * np.linalg.norm(b), i
+    Aac = systems.ac_matrix(M, K, Cv, prm)
+    bac = systems.ac_rhs(M, Phi0, q["fv"], prm)
+    assert np.linalg.norm(bac - Aac @ g["Phi_v"]) <= 2 * rtol * np.linalg.norm(bac)
+    J = fem.p2_convection(m, prm.rho * vel0, np.zeros((m.ne, 2)))
+    Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm)
+    pa0 = 1.0 - ph0[0] - ph0[1] - ph0[2]
+    grads = [fem.p1_grad(m, u) for u in (*ph0, pa0, Phi0)]
+    Fk = fem.korteweg_load(m, grads, list(cfg["betas"]) + [prm.beta_v])
+    rhs = systems.oseen_rhs(ops.Mv, vel0, Fk, prm)
+    A = systems.oseen_matrix(Avel, ops.B)
+    x = np.concatenate([g["vel"], g["p"]])
+    full_rhs = np.concatenate([rhs, np.zeros(N)])
+    assert np.linalg.norm(full_rhs - A @ x) <= 2 * rtol * np.linalg.norm(full_rhs)
+    pa1 = 1.0 - g["phi"][0] - g["phi"][1] - g["phi"][2]
+    mua = q["fa"] + cfg["betas"][3] * ops.mass_solve(K @ pa1)
+    assert _rel(g["mu"][3], mua) <= 1e-10
+
+
 def test_batch64_instances_residuals_and_sampled_errors(mods):
     import torch
     C, _ = mods
