@@ -251,6 +251,7 @@ int form_ternary(chns_ctx* c, hipStream_t s);
 // Re-form L = M + tau C, X = tau g K + sqrt(tau g / beta) M and the AC matrix
 // M + tau delta_v K + tau C on every level, with FP32 copies and 1/diag.
 int form_operators(chns_ctx* c, hipStream_t s) {
+  c->formed_c0 = false;
   const auto& p = c->prm;
   const double beta = c->beta_ch, tg = p.tau * p.mobility;
   const double smatch = std::sqrt(tg / beta);
@@ -279,6 +280,7 @@ int form_operators(chns_ctx* c, hipStream_t s) {
   k.useC[2] = 1;
   form_ops(int(c->lv.size()), c->form_tab, c->form_total, k, c->has_conv, s);
   HIPCHK(c, hipGetLastError());
+  c->formed_c0 = c->c_zero;
   if (c->ternary) TRY(form_ternary(c, s));
   return CHNS_OK;
 }
@@ -452,6 +454,9 @@ int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bo
     galerkin_down(c, &Level::C, &Level::C32, s);
     c->has_conv = true;
   } else {
+    // the binary models' operators depend on the parameters, beta and C only:
+    // with C = 0 already formed (and no parameter change since), nothing to do
+    if (!c->ternary && c->c_zero && c->formed_c0 && c->transposed == transposed) return CHNS_OK;
     if (!c->c_zero)  // C = 0 without a velocity
       for (auto& L : c->lv) {
         HIPCHK(c, hipMemsetAsync(L.C, 0, L.sell.slots() * sizeof(double), s));

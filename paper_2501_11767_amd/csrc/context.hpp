@@ -145,6 +145,8 @@ struct chns_ctx {
   double h = 0.0;       // finest mesh width len / n
   bool has_conv = false;
   bool c_zero = true;   // C and C32 hold zeros on every level
+  bool formed_c0 = false;  // the formed operators (L, X, AC) are those of the current
+                           // parameters and beta with C = 0
   bool ternary = false;  // a flow model (ternary or quaternary): Taylor-Hood Oseen step
   bool quat = false;     // the quaternary model (three CH phases, air eliminated)
   double beta_ch = 0.0;  // the gradient coefficient the CH operators are formed with

@@ -937,6 +937,33 @@ __global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
   const int tid = threadIdx.x;
   const int off[W7] = {0, -W - 1, -W, -1, 1, W, W + 1};
   const int offc[W7] = {0, -Wc - 1, -Wc, -1, 1, Wc, Wc + 1};
+  // fine rows: operands loaded early (before the cut-level steps when there
+  // are any, else before the coarse smoothing), corrections after it
+  T v[T2_RPTU][W7], di[T2_RPTU], bb[T2_RPTU], d[T2_RPTU], xi[T2_RPTU];
+  int gr[T2_RPTU], ring[T2_RPTU];
+  bool own[T2_RPTU];
+  auto load_fine = [&]() {
+#pragma unroll
+    for (int q = 0; q < T2_RPTU; ++q) {
+      const int idx = tid + q * 1024;
+      ring[q] = -1;
+      own[q] = false;
+      if (idx < R) {
+        const int rj = idx / W, ri = idx - rj * W;
+        const int gi = wrap_once(i0 + ri, s), gj = wrap_once(j0 + rj, s);
+        const int row = gi + s * gj;
+        gr[q] = row;
+        ring[q] = min(min(ri, rj), min(W - 1 - ri, W - 1 - rj));
+        own[q] = ring[q] >= Q && tx * T2_TT + (ri - Q) < s && ty * T2_TT + (rj - Q) < s;
+        const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) v[q][k] = a.valf[base + k * 64];
+        di[q] = a.dinvf[row];
+        bb[q] = a.bf[row];
+        xi[q] = a.xinf[row];
+      }
+    }
+  };
   // coarse row: corrected iterate into LDS
   T cv[W7], cdi = T(0), cd = T(0), cbv = T(0), cxv = T(0);
   int cring = -1, crow = 0, cri = 0, crj = 0;
@@ -954,6 +981,7 @@ __global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
     cxv = a.xc[crow];
     if (a.csteps == 0) cx[tid] = cxv + p1_interp(a.e, cgi, cgj, scc);
   }
+  if (a.csteps == 0) load_fine();
   if (a.csteps > 0) {
     // the cut level (side scc) from zero on the region the interpolation
     // reads (origin floor(ci0 / 2) - (S - 1)), in the fine buffers, which
@@ -974,6 +1002,8 @@ __global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
       edi = a.dinvcc[row];
       eb = a.bcc[row];
     }
+    // the fine rows' operands are in flight during the cut-level steps
+    load_fine();
     T* ecur = fx;
     T* enxt = fy;
     for (int k = 0; k < S; ++k) {
@@ -999,30 +1029,6 @@ __global__ __launch_bounds__(1024) void k_vup2(Tile2Args<T> a) {
       const int oi = (cri + pi) & 1, oj = (crj + pj) & 1;
       const T e0 = ecur[I + We * J];
       cx[tid] = cxv + ((oi | oj) ? T(0.5) * (e0 + ecur[(I + oi) + We * (J + oj)]) : e0);
-    }
-  }
-  // fine rows: operands now, corrections after the coarse smoothing
-  T v[T2_RPTU][W7], di[T2_RPTU], bb[T2_RPTU], d[T2_RPTU], xi[T2_RPTU];
-  int gr[T2_RPTU], ring[T2_RPTU];
-  bool own[T2_RPTU];
-#pragma unroll
-  for (int q = 0; q < T2_RPTU; ++q) {
-    const int idx = tid + q * 1024;
-    ring[q] = -1;
-    own[q] = false;
-    if (idx < R) {
-      const int rj = idx / W, ri = idx - rj * W;
-      const int gi = wrap_once(i0 + ri, s), gj = wrap_once(j0 + rj, s);
-      const int row = gi + s * gj;
-      gr[q] = row;
-      ring[q] = min(min(ri, rj), min(W - 1 - ri, W - 1 - rj));
-      own[q] = ring[q] >= Q && tx * T2_TT + (ri - Q) < s && ty * T2_TT + (rj - Q) < s;
-      const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
-#pragma unroll
-      for (int k = 0; k < W7; ++k) v[q][k] = a.valf[base + k * 64];
-      di[q] = a.dinvf[row];
-      bb[q] = a.bf[row];
-      xi[q] = a.xinf[row];
     }
   }
   __syncthreads();
