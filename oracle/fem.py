@@ -90,7 +90,13 @@ class BoxMesh:
     (n + 1)^2 vertices numbered i + (n + 1) j, cells (i, j) split along their
     (i, j)-(i+1, j+1) diagonal like the periodic mesh.  The P1 forms assembled
     on it carry the natural (no-flux) boundary conditions of the phase
-    fields and chemical potentials (eq. (bc)).  P1 only."""
+    fields and chemical potentials (eq. (bc)).
+
+    P2 nodes in four blocks of N = (n + 1)^2 ids, each numbered i + (n + 1) j:
+    the vertices, then the midpoints of the edges (i,j)-(i+1,j) (i < n), of
+    (i,j)-(i,j+1) (j < n) and of (i,j)-(i+1,j+1) (i, j < n); the ids the
+    ranges leave out (4n + 3 of them) belong to no element.  p2_fixed marks
+    them and the wall nodes: the velocity's no-slip set (eq. (bc))."""
 
     def __init__(self, n: int, length: float = 1.0):
         if n < 2:
@@ -108,10 +114,40 @@ class BoxMesh:
         lo_off = base[:, None, :] + np.array([[0, 0], [1, 0], [1, 1]], dtype=np.float64)
         up_off = base[:, None, :] + np.array([[0, 0], [1, 1], [0, 1]], dtype=np.float64)
         self.tri = np.stack([lo, up], 1).reshape(-1, 3).astype(np.int64)
-        self.tri2 = None
+        N = self.nv
+        H = lambda p, q: N + idx(p, q)
+        V = lambda p, q: 2 * N + idx(p, q)
+        D = lambda p, q: 3 * N + idx(p, q)
+        # lower (a, b, c): edges (b,c) = V(i+1,j), (a,c) = D(i,j), (a,b) = H(i,j);
+        # upper (a, c, d): edges (c,d) = H(i,j+1), (a,d) = V(i,j), (a,c) = D(i,j)
+        lo2 = np.stack([a, b, c, V(i + 1, j), D(i, j), H(i, j)], 1)
+        up2 = np.stack([a, c, d, H(i, j + 1), V(i, j), D(i, j)], 1)
+        self.tri2 = np.stack([lo2, up2], 1).reshape(-1, 6).astype(np.int64)
         self.xy = np.stack([lo_off, up_off], 1).reshape(-1, 3, 2) * self.h
         self.ne = self.tri.shape[0]
         _geometry(self)
+
+    def p2_xy(self):
+        """(4N, 2) coordinates of the P2 ids (an unused id gets the point its
+        formula names, outside the square or on an edge that does not exist)."""
+        v = self.vertex_xy()
+        h = self.h
+        return np.concatenate([v, v + [0.5 * h, 0.0], v + [0.0, 0.5 * h], v + [0.5 * h, 0.5 * h]], axis=0)
+
+    def p2_fixed(self):
+        """(4N,) True for the P2 ids of the no-slip set: nodes on the walls and
+        the unused ids."""
+        n, m = self.n, self.n + 1
+        jj, ii = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+        i, j = ii.ravel(), jj.ravel()
+        wall_v = (i == 0) | (i == n) | (j == 0) | (j == n)
+        used = np.zeros(4 * self.nv, bool)
+        used[self.tri2.ravel()] = True
+        fixed = ~used
+        fixed[:self.nv] |= wall_v
+        fixed[self.nv:2 * self.nv] |= (j == 0) | (j == n)        # horizontal edges on the walls
+        fixed[2 * self.nv:3 * self.nv] |= (i == 0) | (i == n)    # vertical edges on the walls
+        return fixed
 
     def quad_points(self):
         return np.einsum("qa,ead->eqd", QP, self.xy)

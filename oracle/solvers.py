@@ -81,9 +81,19 @@ def fft_mass_solve(n, b):
 # ---------------------------------------------------------------- saddle point
 
 
-def bordered_oseen_solve(Avel, B, Mp, rhs_v, dense=False):
+def bordered_oseen_solve(Avel, B, Mp, rhs_v, dense=False, fixed=None):
     """Solve [[A, B^T, 0], [B, 0, m], [0, m^T, 0]] [v; p; lam] = [rhs_v; 0; 0]
-    with m = M_p 1, giving the mean-zero pressure solution."""
+    with m = M_p 1, giving the mean-zero pressure solution.  fixed: boolean
+    mask of velocity unknowns held at zero (no-slip walls): the system is
+    solved on the others and the fixed ones are returned as zeros."""
+    if fixed is not None:
+        free = np.flatnonzero(~fixed)
+        Af = sp.csr_matrix(Avel)[free][:, free]
+        Bf = sp.csr_matrix(B)[:, free]
+        vf, p, lam = bordered_oseen_solve(Af, Bf, Mp, rhs_v[free], dense)
+        v = np.zeros(Avel.shape[0])
+        v[free] = vf
+        return v, p, lam
     nv, npr = Avel.shape[0], B.shape[0]
     m = Mp @ np.ones(npr)
     mcol = sp.csr_matrix(m.reshape(-1, 1))

@@ -35,16 +35,17 @@ from .systems import Params
 
 class Operators:
     """Mesh plus the step-independent matrices.  box_length: the closed
-    square [0, L]^2 with no-flux boundaries (fem.BoxMesh, P1 models only)
-    instead of the periodic unit square."""
+    square [0, L]^2 (fem.BoxMesh) with no-flux boundaries for the phase and
+    vapour fields and no-slip walls for the velocity, instead of the periodic
+    unit square."""
 
     def __init__(self, n: int, need_p2: bool = False, box_length: float | None = None):
-        if box_length is not None and need_p2:
-            raise ValueError("the closed domain carries the P1 models only")
         self.n = n
         self.box = box_length is not None
         self.mesh = fem.BoxMesh(n, box_length) if self.box else fem.Mesh(n)
         self.N = self.mesh.nv
+        # velocity unknowns held at zero (no-slip walls of the closed square)
+        self.vfixed = np.concatenate([self.mesh.p2_fixed()] * 2) if (self.box and need_p2) else None
         self.M = fem.p1_mass(self.mesh)
         self.K = fem.p1_stiffness(self.mesh)
         self.Mv = fem.p2_mass(self.mesh) if need_p2 else None
@@ -136,6 +137,8 @@ def convecting_field(n: int, prm: Params, rho_k, vel):
     (its P1 interpolant at the P2 nodes) and v."""
     if rho_k is None:
         return prm.rho * vel
+    if vel.shape[1] != 4 * n * n:
+        raise ValueError("variable density is built for the periodic square")
     return fem.p2_eval_p1_interp(n, rho_k)[None, :] * vel
 
 
@@ -216,13 +219,13 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         Mrho = None if rho_k is None else fem.p2_mass_weighted(mesh, rho_k)
         F = fem.korteweg_load(mesh, grads, betas)
         rhs = systems.oseen_rhs(ops.Mv, vel, F, prm, Mrho)
-        N2 = 4 * n * n
+        N2 = 4 * N
         conv = vel  # the velocity the convecting field is formed with
         for m in range(max(1, prm.picard)):
             used = conv
             J = fem.p2_convection(mesh, convecting_field(n, prm, rho_k, conv), w_const)
             Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm, Mrho)
-            v, p, _ = solvers.bordered_oseen_solve(Avel, ops.B, M, rhs, dense=(how == "dense"))
+            v, p, _ = solvers.bordered_oseen_solve(Avel, ops.B, M, rhs, dense=(how == "dense"), fixed=ops.vfixed)
             v = np.stack([v[:N2], v[N2:]])
             change = np.linalg.norm(v - conv) / max(np.linalg.norm(v), 1e-300)
             conv = v

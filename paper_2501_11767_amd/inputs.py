@@ -84,22 +84,84 @@ def box_vertex_coords(n: int, length: float) -> np.ndarray:
     return np.stack([i.ravel(), j.ravel()], axis=1) * (length / n)
 
 
+def box_p2_coords(n: int, length: float) -> np.ndarray:
+    """(4N, 2), N = (n+1)^2: coordinates of the P2 ids on the closed square:
+    the vertices, then the midpoints of the edges (i,j)-(i+1,j), (i,j)-(i,j+1)
+    and (i,j)-(i+1,j+1), each block numbered i + (n+1)*j (ids with i = n in the
+    first and third edge block or j = n in the second and third belong to no
+    edge)."""
+    v = box_vertex_coords(n, length)
+    h = length / n
+    return np.concatenate([v, v + [0.5 * h, 0.0], v + [0.0, 0.5 * h], v + [0.5 * h, 0.5 * h]], axis=0)
+
+
+def box_p2_unused(n: int) -> np.ndarray:
+    """(4N,) True for the P2 ids of the closed square that belong to no edge."""
+    m = n + 1
+    j, i = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    return np.concatenate([np.zeros(m * m, bool), i == n, j == n, (i == n) | (j == n)])
+
+
+def box_p2_wall(n: int) -> np.ndarray:
+    """(4N,) True for the P2 ids on the walls of the closed square: wall
+    vertices, edges of the bottom and top walls, edges of the side walls."""
+    m = n + 1
+    j, i = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    side, tb = (i == 0) | (i == n), (j == 0) | (j == n)
+    return np.concatenate([side | tb, tb & (i < n), side & (j < n), np.zeros(m * m, bool)])
+
+
+def box_stream_velocity(n: int, length: float, seed: int, amp: float = 0.01) -> np.ndarray:
+    """Divergence-free velocity (d psi/dy, -d psi/dx) at the P2 ids of the
+    closed square that vanishes with its stream function on the walls:
+    psi = amp S(x) S(y) (1 + 0.3 sin(2 pi x/L + t1) sin(2 pi y/L + t2)),
+    S(u) = sin^2(pi u/L), phases t1, t2 ~ U(0, 2 pi).  Exactly zero on the
+    walls and at the unused ids.  Returns (2, 4N)."""
+    t1, t2 = rng(seed).uniform(0.0, 2.0 * np.pi, size=2)
+    xy = box_p2_coords(n, length)
+    x, y = xy[:, 0], xy[:, 1]
+    k, q = np.pi / length, 2.0 * np.pi / length
+    S = lambda u: np.sin(k * u) ** 2
+    dS = lambda u: 2.0 * k * np.sin(k * u) * np.cos(k * u)
+    g = 1.0 + 0.3 * np.sin(q * x + t1) * np.sin(q * y + t2)
+    gx = 0.3 * q * np.cos(q * x + t1) * np.sin(q * y + t2)
+    gy = 0.3 * q * np.sin(q * x + t1) * np.cos(q * y + t2)
+    psi_x = amp * (dS(x) * S(y) * g + S(x) * S(y) * gx)
+    psi_y = amp * (S(x) * dS(y) * g + S(x) * S(y) * gy)
+    vel = np.stack([psi_y, -psi_x], axis=0)
+    vel[:, box_p2_unused(n) | box_p2_wall(n)] = 0.0
+    return vel
+
+
 def box_state(n: int, length: float, model: str, mean: float, seed: int, film: float = 0.5):
     """Initial fields on the closed square after the paper's two-dimensional
     set-up (section "Numerical results", figure of the initial condition): a
-    film on the substrate y <= film * L holding the phase at mean + U(-0.01,
-    0.01), with vapour field 0; above it the ambient air, phase 0 and vapour
-    field 1.  Models "ch" and "ch_ac"; keys as initial_state."""
-    if model not in ("ch", "ch_ac"):
-        raise ValueError("the closed square carries the binary models")
+    film on the substrate y <= film * L, vapour field 0, under the ambient air
+    (vapour field 1).  Binary models: the phase at mean + U(-0.01, 0.01) in the
+    film, 0 above.  Ternary (solvent eliminated, no air): polymer and NFA at
+    mean +- 0.01 in the film, 0 above (pure solvent).  Quaternary (air
+    eliminated): polymer and NFA at mean, solvent at 1 - 2 mean (each +- 0.01)
+    in the film, all three 0 above (pure air).  The flow models start from
+    box_stream_velocity and p = 0.  Keys as initial_state."""
     y = box_vertex_coords(n, length)[:, 1]
     below = y <= film * length
-    ss = np.random.SeedSequence(seed)
-    s0 = int(ss.spawn(1)[0].generate_state(1)[0])
-    noise = rng(s0).uniform(-1.0, 1.0, size=y.size)
-    phi = np.where(below, mean + 0.01 * noise, 0.0)
-    Phi_v = np.where(below, 0.0, 1.0) if model == "ch_ac" else None
-    return dict(phi=[phi], Phi_v=Phi_v, vel=None, p=None)
+    kids = np.random.SeedSequence(seed).spawn(4)
+    seeds = [int(k.generate_state(1)[0]) for k in kids]
+    noise = lambda i: rng(seeds[i]).uniform(-1.0, 1.0, size=y.size)
+    Phi_v = np.where(below, 0.0, 1.0) if model != "ch" else None
+    if model in ("ch", "ch_ac"):
+        return dict(phi=[np.where(below, mean + 0.01 * noise(0), 0.0)], Phi_v=Phi_v, vel=None, p=None)
+    if model == "ternary":
+        means = (mean, mean)
+    elif model == "quaternary":
+        means = (mean, mean, 1.0 - 2.0 * mean)
+    else:
+        raise ValueError(model)
+    phi = [np.where(below, means[i] + 0.01 * noise(i), 0.0) for i in range(len(means))]
+    vel = box_stream_velocity(n, length, seeds[3])
+    return dict(phi=phi, Phi_v=Phi_v, vel=vel, p=np.zeros(y.size))
 
 
 def log_uniform(g: np.random.Generator, lo: float, hi: float) -> float:

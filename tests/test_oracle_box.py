@@ -176,8 +176,6 @@ def test_direct_solvers_agree_and_the_fourier_solve_is_refused():
     assert np.abs(a["Phi_v"] - b["Phi_v"]).max() < 1e-12
     with pytest.raises(ValueError):
         S.step(ops, prm, "ch_ac", st, "fft")
-    with pytest.raises(ValueError):
-        S.Operators(n, need_p2=True, box_length=L10)
 
 
 # ---------------------------------------------------------------- multigrid on the closed square
