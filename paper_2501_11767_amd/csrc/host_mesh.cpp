@@ -18,12 +18,12 @@ Elements make_elements(int n, bool box) {
   E.n = n;
   E.box = box;
   E.ne = 2 * n * n;
-  const int N = n * n;
+  const int N = E.nodes();
   auto id = [n, box](int i, int j) {
     return box ? i + (n + 1) * j : ((i % n + n) % n) + n * ((j % n + n) % n);
   };
   E.v.reserve(E.ne * 3);
-  if (!box) E.p2.reserve(E.ne * 6);
+  E.p2.reserve(E.ne * 6);
   E.type.reserve(E.ne);
   int count = 0;
   for (int colour = 0; colour < 8; ++colour) {
@@ -34,20 +34,16 @@ Elements make_elements(int n, bool box) {
         const int a = id(i, j), b = id(i + 1, j), c = id(i + 1, j + 1), d = id(i, j + 1);
         if (ty == 0) {
           const int loc[3] = {a, b, c};
+          const int e2[3] = {2 * N + id(i + 1, j), 3 * N + id(i, j), N + id(i, j)};
           E.v.insert(E.v.end(), loc, loc + 3);
-          if (!box) {
-            const int e2[3] = {2 * N + id(i + 1, j), 3 * N + id(i, j), N + id(i, j)};
-            E.p2.insert(E.p2.end(), loc, loc + 3);
-            E.p2.insert(E.p2.end(), e2, e2 + 3);
-          }
+          E.p2.insert(E.p2.end(), loc, loc + 3);
+          E.p2.insert(E.p2.end(), e2, e2 + 3);
         } else {
           const int loc[3] = {a, c, d};
+          const int e2[3] = {N + id(i, j + 1), 2 * N + id(i, j), 3 * N + id(i, j)};
           E.v.insert(E.v.end(), loc, loc + 3);
-          if (!box) {
-            const int e2[3] = {N + id(i, j + 1), 2 * N + id(i, j), 3 * N + id(i, j)};
-            E.p2.insert(E.p2.end(), loc, loc + 3);
-            E.p2.insert(E.p2.end(), e2, e2 + 3);
-          }
+          E.p2.insert(E.p2.end(), loc, loc + 3);
+          E.p2.insert(E.p2.end(), e2, e2 + 3);
         }
         E.type.push_back(ty);
         ++count;
@@ -319,23 +315,25 @@ void csr_transpose(const Csr& A, const std::vector<double>& av, Csr& T, std::vec
     }
 }
 
-void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val) {
-  const int N = n * n;
-  auto id = [n](int i, int j) { return ((i % n + n) % n) + n * ((j % n + n) % n); };
+void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val, bool box) {
+  const int m = box ? n + 1 : n, N = m * m;
+  auto id = [n, m, box](int i, int j) { return box ? i + m * j : ((i % n + n) % n) + n * ((j % n + n) % n); };
   P.nrows = 4 * N;
   P.ncols = N;
   P.rowptr.assign(P.nrows + 1, 0);
   P.col.clear();
   val.clear();
   std::vector<std::vector<std::pair<int, double>>> rows(P.nrows);
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) {
-      rows[id(i, j)].push_back({id(i, j), 1.0});
+  const std::vector<char> fixed = box ? p2_fixed_box(n) : std::vector<char>(size_t(4) * N, 0);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      if (!fixed[id(i, j)]) rows[id(i, j)].push_back({id(i, j), 1.0});
       const int d[3][2] = {{1, 0}, {0, 1}, {1, 1}};
       for (int blk = 0; blk < 3; ++blk) {
-        auto& r = rows[(blk + 1) * N + id(i, j)];
-        r.push_back({id(i, j), 0.5});
-        r.push_back({id(i + d[blk][0], j + d[blk][1]), 0.5});
+        const int r = (blk + 1) * N + id(i, j);
+        if (fixed[r]) continue;  // a wall node or an id of no edge: no interpolation
+        rows[r].push_back({id(i, j), 0.5});
+        rows[r].push_back({id(i + d[blk][0], j + d[blk][1]), 0.5});
       }
     }
   for (int r = 0; r < P.nrows; ++r) {
@@ -349,13 +347,49 @@ void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val) {
   }
 }
 
+std::vector<char> p2_fixed_box(int n) {
+  const int m = n + 1, N = m * m;
+  std::vector<char> f(size_t(4) * N, 0);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      const bool side = i == 0 || i == n, tb = j == 0 || j == n;
+      const int v = i + m * j;
+      f[v] = side || tb;                           // wall vertices
+      f[N + v] = i == n || tb;                     // (i,j)-(i+1,j): none at i = n, walls at j = 0, n
+      f[2 * N + v] = j == n || side;               // (i,j)-(i,j+1): none at j = n, walls at i = 0, n
+      f[3 * N + v] = i == n || j == n;             // diagonals: none on the last row or column
+    }
+  return f;
+}
+
+// Every row keeps its diagonal entry, also a row no element touches (the
+// unused ids of the closed square's padded P2 numbering).
+static Csr with_diagonal(const Csr& A) {
+  Csr B;
+  B.nrows = A.nrows;
+  B.ncols = A.ncols;
+  B.rowptr.assign(A.nrows + 1, 0);
+  for (int r = 0; r < A.nrows; ++r) {
+    const int* b = A.col.data() + A.rowptr[r];
+    const int* e = A.col.data() + A.rowptr[r + 1];
+    const bool has = std::binary_search(b, e, r);
+    for (const int* q = b; q < e; ++q) {
+      if (!has && *q > r && (q == b || q[-1] < r)) B.col.push_back(r);
+      B.col.push_back(*q);
+    }
+    if (!has && (b == e || e[-1] < r)) B.col.push_back(r);
+    B.rowptr[r + 1] = int(B.col.size());
+  }
+  return B;
+}
+
 Csr p2_pattern(const Elements& E) {
-  const int N = E.n * E.n;
-  return pattern_from_elements(4 * N, 4 * N, E.ne, E.p2.data(), 6, E.p2.data(), 6);
+  const int N = E.nodes();
+  return with_diagonal(pattern_from_elements(4 * N, 4 * N, E.ne, E.p2.data(), 6, E.p2.data(), 6));
 }
 
 Csr b_pattern(const Elements& E) {
-  const int N = E.n * E.n;
+  const int N = E.nodes();
   std::vector<int> vel(size_t(E.ne) * 12);
   for (int e = 0; e < E.ne; ++e)
     for (int k = 0; k < 6; ++k) {
@@ -367,9 +401,11 @@ Csr b_pattern(const Elements& E) {
 
 Csr ns_pattern(const Elements& E) {
   // velocity rows couple to both velocity components and to pressure;
-  // pressure rows couple to both velocity components only.
-  const int N = E.n * E.n;
+  // pressure rows couple to both velocity components only; a velocity row no
+  // element touches keeps its diagonal.
+  const int N = E.nodes();
   std::vector<std::vector<int>> rows(9 * N);
+  for (int r = 0; r < 8 * N; ++r) rows[r].push_back(r);
   for (int e = 0; e < E.ne; ++e) {
     const int* q = &E.p2[e * 6];
     const int* v = &E.v[e * 3];

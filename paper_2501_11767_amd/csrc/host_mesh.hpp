@@ -5,7 +5,8 @@
 // and an upper triangle ((i,j),(i+1,j+1),(i,j+1)).  P1 node (i, j) = i + n*j;
 // P2 nodes: vertices, then horizontal, vertical and diagonal edge midpoints.
 // The closed square (box) has the same cells and (n+1)^2 vertices
-// i + (n+1)*j, 0 <= i, j <= n, and carries P1 only.
+// i + (n+1)*j, 0 <= i, j <= n; its P2 ids pad the four blocks to (n+1)^2
+// each (edge ids i + (n+1)*j with i = n, j = n, or either, name no edge).
 // P2 local order on a triangle (v0, v1, v2): vertices, then the nodes of the
 // edges (v1,v2), (v0,v2), (v0,v1).
 //
@@ -53,6 +54,7 @@ struct Elements {
   std::vector<int> type;         // 0 lower, 1 upper
   int colour_ptr[9] = {0};
   bool box = false;
+  int nodes() const { return box ? (n + 1) * (n + 1) : n * n; }  // P1 nodes N
 };
 
 Elements make_elements(int n, bool box = false);
@@ -96,10 +98,17 @@ GalerkinMap make_galerkin(const Csr& Af, const Sell& Sf, const Csr& P, const std
 // Transpose of a CSR pattern with values.
 void csr_transpose(const Csr& A, const std::vector<double>& av, Csr& T, std::vector<double>& tv);
 
-// P1 on mesh n into P2 on mesh n (vertex nodes copy, edge midpoints average).
-void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val);
+// P1 on mesh n into P2 on mesh n (vertex nodes copy, edge midpoints average);
+// on the closed square the rows of p2_fixed_box are empty (the velocity's
+// no-slip set receives no coarse correction).
+void p2_from_p1_prolongation(int n, Csr& P, std::vector<double>& val, bool box = false);
 
-// Taylor-Hood patterns on mesh n (N = n^2 vertices, 4N P2 nodes):
+// The closed square's P2 ids held at zero by the no-slip walls: the wall
+// vertices and wall edges, and the ids of no edge (4 (n+1)^2 flags).
+std::vector<char> p2_fixed_box(int n);
+
+// Taylor-Hood patterns on mesh n (N = n^2 vertices, or (n+1)^2 on the closed
+// square; 4N P2 ids, every row with its diagonal):
 //   scalar P2 (4N x 4N), B (N x 8N: pressure rows, [x; y] velocity columns),
 //   the Oseen operator (9N x 9N: rows/cols [v_x; v_y; p], no p-p block).
 Csr p2_pattern(const Elements& E);

@@ -187,4 +187,38 @@ __attribute__((visibility("default"))) int chns_probe_box_prolongation(int nf, i
   return int(P.nnz());
 }
 
+// Taylor-Hood patterns of the closed square (which: 0 scalar P2, 1 B, 2 Oseen;
+// returns nnz), its P1 -> P2 transfer (returns nnz) and the no-slip flags.
+__attribute__((visibility("default"))) int64_t chns_probe_box_th_pattern(int n, int which, int32_t* rowptr,
+                                                                         int32_t* col) {
+  Elements E = make_elements(n, true);
+  Csr A = which == 0 ? p2_pattern(E) : which == 1 ? b_pattern(E) : ns_pattern(E);
+  copy_out(A.rowptr, rowptr);
+  copy_out(A.col, col);
+  return A.nnz();
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_p2_transfer(int n, int32_t* rowptr, int32_t* col,
+                                                                      double* val) {
+  Csr P;
+  std::vector<double> Pv;
+  p2_from_p1_prolongation(n, P, Pv, true);
+  copy_out(P.rowptr, rowptr);
+  copy_out(P.col, col);
+  if (val) std::memcpy(val, Pv.data(), Pv.size() * sizeof(double));
+  return int(P.nnz());
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_p2_fixed(int n, int8_t* out) {
+  const std::vector<char> f = p2_fixed_box(n);
+  for (size_t i = 0; i < f.size(); ++i) out[i] = int8_t(f[i]);
+  return int(f.size());
+}
+
+__attribute__((visibility("default"))) int chns_probe_box_p2_elements(int n, int32_t* p2) {
+  Elements E = make_elements(n, true);
+  copy_out(E.p2, p2);
+  return int(E.p2.size());
+}
+
 }  // extern "C"

@@ -93,7 +93,7 @@ def test_pattern_and_padded_sell_layout(probe, n):
 def test_elements_match_the_oracle_and_colours_are_conflict_free(probe, n):
     v, ty, cp, np2 = _elements(probe, n)
     m = fem.BoxMesh(n, L10)
-    assert np2 == 0 and cp[8] == 2 * n * n
+    assert np2 == 6 * 2 * n * n and cp[8] == 2 * n * n
     key = lambda t: [tuple(r) for r in t]
     assert sorted(key(v)) == sorted(key(m.tri))
     # type 0 = lower (vertex ids a, a+1, a+n+2), 1 = upper (a, a+n+2, a+n+1)
@@ -161,3 +161,76 @@ def test_prolongation_and_galerkin_reproduce_the_coarse_forms(probe, nf):
         got = np.zeros(Ac.nnz)
         assert probe.chns_probe_box_galerkin(nf, _ptr(np.ascontiguousarray(Af.data)), _ptr(got)) == 0
         assert np.abs(got - Ac.data).max() < 1e-13 * abs(Ac).max()
+
+
+# ---------------------------------------------------------------- Taylor-Hood on the closed square
+
+
+def _csr_probe(probe, fn, n, *args, nrows):
+    rp = np.zeros(nrows + 1, np.int32)
+    nnz = fn(n, *args, _ptr(rp), None)
+    col = np.zeros(nnz, np.int32)
+    fn(n, *args, _ptr(rp), _ptr(col))
+    return rp, col
+
+
+def _pattern(A):
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    return A.indptr, A.indices
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_box_taylor_hood_tables_match_the_oracle(probe, n):
+    probe.chns_probe_box_th_pattern.restype = ct.c_int64
+    m = fem.BoxMesh(n, L10)
+    N = m.nv
+    # element P2 ids: the same six per element (the library orders elements by colour)
+    p2 = np.zeros(2 * n * n * 6, np.int32)
+    assert probe.chns_probe_box_p2_elements(n, _ptr(p2)) == p2.size
+    v, ty, cp, _ = _elements(probe, n)
+    lib = {tuple(r[:3]): tuple(r) for r in p2.reshape(-1, 6)}
+    assert all(lib[tuple(r[:3])] == tuple(r) for r in m.tri2)
+    fixed = np.zeros(4 * N, np.int8)
+    assert probe.chns_probe_box_p2_fixed(n, _ptr(fixed)) == 4 * N
+    assert np.array_equal(fixed.astype(bool), m.p2_fixed())
+    # patterns: the oracle's, plus a lone diagonal on every id of no edge
+    used = np.zeros(4 * N, bool)
+    used[m.tri2.ravel()] = True
+    eye_unused = sp.diags(np.where(used, 0.0, 1.0))
+    Mv = fem.p2_mass(m)
+    rp, col = _csr_probe(probe, probe.chns_probe_box_th_pattern, n, 0, nrows=4 * N)
+    ref = sp.csr_matrix((np.ones(Mv.nnz), Mv.indices, Mv.indptr), shape=Mv.shape) + eye_unused
+    ip, ix = _pattern(ref)
+    assert np.array_equal(rp, ip) and np.array_equal(col, ix)
+    B = fem.divergence_matrix(m)
+    rp, col = _csr_probe(probe, probe.chns_probe_box_th_pattern, n, 1, nrows=N)
+    ib = sp.csr_matrix((np.ones(B.nnz), B.indices, B.indptr), shape=B.shape)
+    ip, ix = _pattern(ib)
+    assert np.array_equal(rp, ip) and np.array_equal(col, ix)
+    # velocity rows couple to both components on the P2 pattern and to pressure
+    vv = sp.bmat([[Mv, Mv], [Mv, Mv]])
+    A = sp.bmat([[vv, B.T], [B, None]]).tocsr()
+    ones = sp.csr_matrix((np.ones(A.nnz), A.indices, A.indptr), shape=A.shape)
+    ones = ones + sp.diags(np.concatenate([np.where(used, 0.0, 1.0)] * 2 + [np.zeros(N)]))
+    rp, col = _csr_probe(probe, probe.chns_probe_box_th_pattern, n, 2, nrows=9 * N)
+    ip, ix = _pattern(ones)
+    assert np.array_equal(rp, ip) and np.array_equal(col, ix)
+
+
+def test_box_p1_to_p2_transfer(probe):
+    """The P1 -> P2 transfer of the velocity hierarchy: linear fields exact at
+    every P2 id off the no-slip set, no row on it."""
+    n = 10
+    m = fem.BoxMesh(n, L10)
+    N = m.nv
+    rp = np.zeros(4 * N + 1, np.int32)
+    nnz = probe.chns_probe_box_p2_transfer(n, _ptr(rp), None, None)
+    col, val = np.zeros(nnz, np.int32), np.zeros(nnz)
+    probe.chns_probe_box_p2_transfer(n, _ptr(rp), _ptr(col), _ptr(val))
+    P = sp.csr_matrix((val, col, rp), shape=(4 * N, N))
+    fixed = m.p2_fixed()
+    assert np.all(np.diff(rp)[fixed] == 0)
+    lin = lambda xy: 0.7 * xy[:, 0] - 0.2 * xy[:, 1] + 1.0
+    got = P @ lin(m.vertex_xy())
+    assert np.abs(got[~fixed] - lin(m.p2_xy())[~fixed]).max() < 1e-12
