@@ -22,10 +22,12 @@
  *     diagonal.  P1 node (i, j) has id i + n*j.  P2 velocity nodes: the n*n
  *     vertices, then the midpoints of horizontal, vertical and diagonal edges,
  *     each block numbered i + n*j; a velocity field is 2 * 4n^2 doubles, x
- *     components first.  Or the closed square [0, length]^2 with no-flux
- *     boundaries (CHNS_BOUNDARY_NOFLUX): the same cells, (n+1)^2 vertices
- *     numbered i + (n+1)*j, P1 fields of N = (n+1)^2 doubles, binary models
- *     without convection.
+ *     components first.  Or the closed square [0, length]^2
+ *     (CHNS_BOUNDARY_NOFLUX): the same cells, (n+1)^2 vertices numbered
+ *     i + (n+1)*j, P1 fields of N = (n+1)^2 doubles; P2 ids in the same four
+ *     blocks of N ids each numbered i + (n+1)*j (ids with i = n in the first
+ *     and third edge block or j = n in the second and third name no edge), a
+ *     velocity field 2 * 4N doubles.
  *   - Parameter reading: beta = eps^2, gamma = mobility, gamma_v = evap_rate,
  *     delta_v = evap_rate * eps^2, beta_v = eps^2, rho and alpha as given.
  *   - Every "d_" pointer is device memory owned by the caller, FP64 unless
@@ -108,8 +110,13 @@ enum {
   CHNS_BOUNDARY_PERIODIC = 0, /* periodic square, n*n vertices i + n*j at (i h, j h) */
   CHNS_BOUNDARY_NOFLUX = 1    /* closed square [0, length]^2 with the natural (no-flux)
                                  conditions of the phase fields, chemical potentials and
-                                 vapour field: (n+1)^2 vertices i + (n+1)*j at (i h, j h),
-                                 0 <= i, j <= n; models CH and CH_AC only, no velocity */
+                                 vapour field and the no-slip walls of the velocity: (n+1)^2
+                                 vertices i + (n+1)*j at (i h, j h), 0 <= i, j <= n.  The
+                                 Oseen operator holds the no-slip set (wall nodes and the ids
+                                 of no edge) with identity rows no other row couples to and
+                                 zero right-hand side rows; a convecting velocity given to
+                                 chns_assemble must vanish there.  No variable density, no
+                                 adjoint step */
 };
 
 typedef struct {

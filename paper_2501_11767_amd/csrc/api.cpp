@@ -116,6 +116,9 @@ int upload(chns_ctx* c, T** p, const std::vector<T>& h) {
 }
 
 int upload_sell(chns_ctx* c, const Sell& S, DSell& d) {
+  // every stored column (padding included) is read by the kernels
+  for (int col : S.col)
+    if (col < 0 || col >= S.ncols) return fail(c, CHNS_EINVAL, "SELL column out of range");
   d.nrows = S.nrows;
   d.nslices = S.nslices;
   d.width = S.width_max;
@@ -184,6 +187,7 @@ const char* model_params_error(int model, bool box, const chns_params* p) {
   if (!ter && (p->potential != CHNS_POT_QUARTIC || p->truncate))
     return "the Flory-Huggins density and the truncation apply to the ternary model";
   if (!ter && p->var_density) return "variable density applies to the ternary model";
+  if (box && p->var_density) return "variable density is built for the periodic square";
   if (!ter && !quat && p->ns_picard > 1) return "Picard passes apply to the ternary and quaternary models";
   if (!box && p->top_flux != 0.0) return "the top-wall flux belongs to the closed square";
   for (int i = 0; i < 4; ++i) {
@@ -303,6 +307,12 @@ int form_ternary(chns_ctx* c, hipStream_t s) {
   const int64_t ns2 = P.sell.slots();
   combine(ns2, cm, Mvel, 1.0, P.J, 1.0, P.Kxx, P.Vx.v64, P.Vx.v32, s);
   combine(ns2, cm, Mvel, 1.0, P.J, 1.0, P.Kyy, P.Vy.v64, P.Vy.v32, s);
+  const NSData& S = c->ns;
+  if (c->box)  // no-slip walls: identity rows, and no coupling into them
+    for (OpVals* o : {&P.Vx, &P.Vy}) {
+      set_slots(S.n_p2_zero, S.p2_zero, 0.0, o->v64, o->v32, s);
+      set_slots(S.n_p2_one, S.p2_one, 1.0, o->v64, o->v32, s);
+    }
   diag_inverse(P.N4, P.diag, P.Vx.v64, P.Vx.d64, P.Vx.d32, s);
   diag_inverse(P.N4, P.diag, P.Vy.v64, P.Vy.d64, P.Vy.d32, s);
   galerkin(L0.sell.slots(), P.gptr, P.gsrc, P.gw, P.Vx.v64, L0.Vx.v64, s);
@@ -322,6 +332,10 @@ int form_ternary(chns_ctx* c, hipStream_t s) {
   }
   form_ns(c->ns.sell.slots(), c->ns.kind, c->ns.src, cm, Mvel, P.J, P.Kxx, P.Kxy, P.Kyx, P.Kyy,
           c->ns.B, c->ns.val, s);
+  if (c->box) {
+    set_slots(S.n_ns_zero, S.ns_zero, 0.0, c->ns.val, nullptr, s);
+    set_slots(S.n_ns_one, S.ns_one, 1.0, c->ns.val, nullptr, s);
+  }
   combine(L0.sell.slots(), cm, Mpcd, p.viscosity, L0.K, 1.0, L0.Cw, L0.Ap.v64, L0.Ap.v32, s);
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
@@ -444,7 +458,6 @@ int weighted_masses(chns_ctx* c, hipStream_t s) {
 int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bool transposed,
                  hipStream_t s) {
   if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
-  if (c->box && d_vel) return fail(c, CHNS_EUNSUPPORTED, "no velocity field on the closed square");
   Level& L0 = c->lv[0];
   if (c->ternary) TRY(assemble_ternary_conv(c, d_vel, d_mu, transposed, s));
   if (d_vel) {
@@ -616,7 +629,9 @@ ChebCoef<T> cut_coef(chns_ctx* c, OpVals Level::*op, size_t l, const chns_solve_
   const double nl = c->lv[l].n, ih = nl / c->len;  // cells per side, 1 / h
   double lo;
   if (singular_of(op)) {
-    lo = 0.9 * (1.0 - std::cos(2.0 * M_PI / nl)) / 2.0;  // smallest nonzero eigenvalue of D^-1 K
+    // smallest nonzero eigenvalue of D^-1 K: its slowest mode has period n_l
+    // cells on the periodic square, 2 n_l on the closed one (Neumann)
+    lo = 0.9 * (1.0 - std::cos((c->box ? 1.0 : 2.0) * M_PI / nl)) / 2.0;
   } else {
     lo = 0.45 / (1.0 + 8.0 * cf[1] * ih * ih / cf[0]);
   }
@@ -1370,7 +1385,13 @@ int fgmres(chns_ctx* c, int block, const double* b, double* x, const chns_solve_
   }
   if (iters > 0 && inf.res0 > 0.0 && inf.res_true > 0.0)
     K.rate[block] = std::pow(inf.res_true / inf.res0, 1.0 / iters);
-  if (block == CHNS_BLOCK_NS) mean_zero<double>(c, c->N, x + 8 * int64_t(c->N), s);
+  if (block == CHNS_BLOCK_NS) {
+    // the pressure in L^2_0: zero integral, i.e. 1^T M p = 0 (the plain mean
+    // on the periodic square, where every row of M sums to h^2)
+    double* p = x + 8 * int64_t(c->N);
+    if (c->pw) wmean_zero(c->N, c->pw, c->len * c->len, p, c->red, s);
+    else mean_zero<double>(c, c->N, p, s);
+  }
   HIPCHK(c, hipEventRecord(c->ev1, s));
   HIPCHK(c, hipEventSynchronize(c->ev1));
   float ms = 0.f;
@@ -1402,6 +1423,41 @@ int build_ternary_tables(chns_ctx* c) {
   S.csr = ns_pattern(E);
   S.sell = make_sell(S.csr, 64, 1);
   TRY(upload_sell(c, S.sell, S.d));
+  if (c->box) {
+    // no-slip walls: the P2 ids held at zero give identity rows, and no
+    // other row couples to them (velocity blocks, B and B^T in the Oseen
+    // operator); their right-hand side rows are zero
+    const std::vector<char> f = p2_fixed_box(c->mesh.n);
+    const int N4 = 4 * N;
+    std::vector<int> z2, o2, zn, on, vf;
+    for (int r = 0; r < P.csr.nrows; ++r)
+      for (int q = P.csr.rowptr[r]; q < P.csr.rowptr[r + 1]; ++q) {
+        const int col = P.csr.col[q];
+        if (!f[r] && !f[col]) continue;
+        (col == r ? o2 : z2).push_back(P.sell.csr2sell[q]);
+      }
+    auto vfixed = [&](int i) { return i < 2 * N4 && f[i % N4]; };
+    for (int r = 0; r < S.csr.nrows; ++r)
+      for (int q = S.csr.rowptr[r]; q < S.csr.rowptr[r + 1]; ++q) {
+        const int col = S.csr.col[q];
+        if (!vfixed(r) && !vfixed(col)) continue;
+        (col == r ? on : zn).push_back(S.sell.csr2sell[q]);
+      }
+    for (int i = 0; i < 2 * N4; ++i)
+      if (vfixed(i)) vf.push_back(i);
+    for (auto* l : {&z2, &o2, &zn, &on, &vf})
+      if (l->empty()) return fail(c, CHNS_EINVAL, "no-slip tables are empty");
+    TRY(upload(c, &S.p2_zero, z2));
+    TRY(upload(c, &S.p2_one, o2));
+    TRY(upload(c, &S.ns_zero, zn));
+    TRY(upload(c, &S.ns_one, on));
+    TRY(upload(c, &S.vfix, vf));
+    S.n_p2_zero = int64_t(z2.size());
+    S.n_p2_one = int64_t(o2.size());
+    S.n_ns_zero = int64_t(zn.size());
+    S.n_ns_one = int64_t(on.size());
+    S.n_vfix = int64_t(vf.size());
+  }
   // element slot tables
   std::vector<int> s36(size_t(E.ne) * 36), sb(size_t(E.ne) * 36);
   for (int e = 0; e < E.ne; ++e) {
@@ -1438,7 +1494,7 @@ int build_ternary_tables(chns_ctx* c) {
   TRY(upload(c, &S.kind, kind));
   TRY(upload(c, &S.src, src));
   // P1 -> P2 on the finest mesh and the Galerkin map P2 -> P1
-  p2_from_p1_prolongation(c->mesh.n, P.Pcsr, P.Pval);
+  p2_from_p1_prolongation(c->mesh.n, P.Pcsr, P.Pval, c->box);
   csr_transpose(P.Pcsr, P.Pval, P.Rcsr, P.Rval);
   P.Psell = make_sell(P.Pcsr, 64, 1);
   P.Rsell = make_sell(P.Rcsr, 64, 1);
@@ -1521,7 +1577,7 @@ int build(chns_ctx* c) {
             slot[size_t(e) * 9 + a * 3 + b] = L.sell.csr2sell[q];
           }
       TRY(upload(c, &c->ep1, c->el.v));
-      if (!box) TRY(upload(c, &c->ep2, c->el.p2));  // no P2 nodes on the closed square
+      TRY(upload(c, &c->ep2, c->el.p2));
       TRY(upload(c, &c->etype, c->el.type));
       TRY(upload(c, &c->eslot, slot));
     }
@@ -1721,6 +1777,11 @@ int build(chns_ctx* c) {
     }
     TRY(assemble_sym_stiffness(c, s));
     TRY(uniform_density(c, s));
+    if (c->box) {  // row sums of M: the weights of the pressure's mean on the closed square
+      TRY(dalloc(c, &c->pw, size_t(c->N)));
+      fill(c->N, 1.0, c->w64a, s);
+      spmv<double, double>(L0.d, L0.M, c->w64a, c->pw, 1.0, 0.0, s);
+    }
   }
   TRY(form_operators(c, s));
   HIPCHK(c, hipDeviceSynchronize());
@@ -1770,6 +1831,7 @@ int ternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* rhs_
     korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype,
              c->h, c->ns.tb, in->phi[0], in->phi[1], nullptr, in->Phi_v, KorBeta{{beta, beta, beta, 0.0}, beta},
              N4, rhs_ns, s);
+  if (c->box) set_slots(c->ns.n_vfix, c->ns.vfix, 0.0, rhs_ns, nullptr, s);  // no-slip rows
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -1850,6 +1912,7 @@ int ternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   chns_solve_info* ns_rec = (info && *info) ? *info : nullptr;  // the Oseen solve's report
   TRY(chns_solve_block(c, CHNS_BLOCK_NS, c->rhs_ns, c->xns, o, info, worst, s));
   if (c->prm.ns_picard > 1) TRY(picard_passes(c, cur, mu3, o, ns_rec, worst, s));
+  if (c->box) set_slots(c->ns.n_vfix, c->ns.vfix, 0.0, c->xns, nullptr, s);  // walls exactly at rest
   for (int ph = 0; ph < 2; ++ph) {
     HIPCHK(c, hipMemcpyAsync(out->phi[ph], xch + 2 * ph * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(out->mu[ph], xch + (2 * ph + 1) * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
@@ -1889,6 +1952,7 @@ int quaternary_rhs(chns_ctx* c, const chns_fields* in, double* rhs_ch, double* r
   for (int col = 0; col < 8; ++col)
     korteweg(c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep1, c->ep2, c->etype, c->h, c->ns.tb,
              in->phi[0], in->phi[1], in->phi[2], in->Phi_v, kb, N4, rhs_ns, s);
+  if (c->box) set_slots(c->ns.n_vfix, c->ns.vfix, 0.0, rhs_ns, nullptr, s);  // no-slip rows
   HIPCHK(c, hipGetLastError());
   return CHNS_OK;
 }
@@ -1932,6 +1996,7 @@ int quaternary_step(chns_ctx* c, const chns_fields& cur, const chns_fields* out,
   chns_solve_info* ns_rec = (info && *info) ? *info : nullptr;
   TRY(chns_solve_block(c, CHNS_BLOCK_NS, c->rhs_ns, c->xns, o, info, worst, s));
   if (p.ns_picard > 1) TRY(picard_passes(c, cur, mu4, o, ns_rec, worst, s));
+  if (c->box) set_slots(c->ns.n_vfix, c->ns.vfix, 0.0, c->xns, nullptr, s);  // walls exactly at rest
   for (int ph = 0; ph < 3; ++ph) {
     HIPCHK(c, hipMemcpyAsync(out->phi[ph], xch + 2 * ph * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(out->mu[ph], xch + (2 * ph + 1) * size_t(N), bytes, hipMemcpyDeviceToDevice, s));
@@ -2107,10 +2172,6 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
   if (!(mesh->length >= 0.0 && std::isfinite(mesh->length))) {
     g_create_err = "length must be finite and > 0 (0 for 1)";
     return CHNS_EINVAL;
-  }
-  if (mesh->boundary == CHNS_BOUNDARY_NOFLUX && mesh->model >= CHNS_MODEL_TERNARY) {
-    g_create_err = "the closed square carries the binary models (no Taylor-Hood spaces with no-slip walls)";
-    return CHNS_EUNSUPPORTED;
   }
   chns_ctx tmp;
   if (check_params(&tmp, params) != CHNS_OK) {
@@ -2549,6 +2610,7 @@ int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields*
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
   if (!c->ternary || c->quat) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is defined for the ternary model");
+  if (c->box) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is built for the periodic square");
   if (c->prm.var_density || c->prm.ns_picard > 1)
     return fail(c, CHNS_EUNSUPPORTED, "the adjoint step covers the linear scheme with constant density");
   if (!in || !out || !lam_out || !lam_in || !h_dtheta) return fail(c, CHNS_EINVAL, "NULL argument");

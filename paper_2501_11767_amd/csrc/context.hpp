@@ -91,6 +91,10 @@ struct NSData {
   int *eslot36 = nullptr, *eslotb = nullptr;
   double* tables = nullptr;
   DP2Tables tb{};
+  // closed square: the no-slip set's slots (zeroed; the diagonal set to 1) in
+  // the P2 and Oseen SELL value arrays, and its rows of the 8N velocity
+  int *p2_zero = nullptr, *p2_one = nullptr, *ns_zero = nullptr, *ns_one = nullptr, *vfix = nullptr;
+  int64_t n_p2_zero = 0, n_p2_one = 0, n_ns_zero = 0, n_ns_one = 0, n_vfix = 0;
 };
 
 struct Krylov {
@@ -175,6 +179,7 @@ struct chns_ctx {
   double *rhs_ch = nullptr, *rhs_ac = nullptr, *xch = nullptr;
   double *rhs_ns = nullptr, *xns = nullptr, *xac = nullptr, *fs = nullptr, *w64d = nullptr;
   double* red = nullptr;  // reduction partials for mean projections
+  double* pw = nullptr;   // closed square, flow models: M 1, the weights of the pressure's mean
   // variable density and Picard passes (ternary): rho^k at the vertices and
   // at the P2 nodes, the previous velocity iterate, norm partials and results
   double *rho1 = nullptr, *rho2 = nullptr, *vprev = nullptr, *pic = nullptr;

@@ -171,7 +171,8 @@ Sell make_sell(const Csr& A, int C, int sigma) {
           S.csr2sell[q] = slot;
           if (A.col[q] == r) S.diag[r] = slot;
         } else {
-          S.col[slot] = A.col[A.rowptr[r]];  // padding: valid column, value stays 0
+          // padding: a valid column (the row's first, or 0 for an empty row), value stays 0
+          S.col[slot] = L > 0 ? A.col[A.rowptr[r]] : 0;
         }
       }
     }

@@ -209,6 +209,19 @@ __attribute__((visibility("default"))) int chns_probe_box_p2_transfer(int n, int
   return int(P.nnz());
 }
 
+// Stored columns outside [0, ncols) in the SELL layouts of the closed
+// square's P1 -> P2 transfer and of its transpose (padding included).
+__attribute__((visibility("default"))) int chns_probe_box_p2_transfer_sell_bad(int n) {
+  Csr P, R;
+  std::vector<double> Pv, Rv;
+  p2_from_p1_prolongation(n, P, Pv, true);
+  csr_transpose(P, Pv, R, Rv);
+  int bad = 0;
+  for (const Sell& S : {make_sell(P, 64, 1), make_sell(R, 64, 1)})
+    for (int col : S.col) bad += col < 0 || col >= S.ncols;
+  return bad;
+}
+
 __attribute__((visibility("default"))) int chns_probe_box_p2_fixed(int n, int8_t* out) {
   const std::vector<char> f = p2_fixed_box(n);
   for (size_t i = 0; i < f.size(); ++i) out[i] = int8_t(f[i]);

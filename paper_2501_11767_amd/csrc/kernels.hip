@@ -2431,15 +2431,26 @@ __global__ __launch_bounds__(BS) void k_sum_partial(int64_t n, const T* __restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Per-block partials of sum_i w_i x_i.
+__global__ __launch_bounds__(BS) void k_wsum_partial(int64_t n, const double* __restrict__ w,
+                                                     const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * BS;
+  for (int64_t r = int64_t(blockIdx.x) * BS + threadIdx.x; r < n; r += stride) acc += w[r] * x[r];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(BS) void k_sub_mean(int64_t n, int nblk, const double* __restrict__ part,
-                                                 T* __restrict__ x) {
+                                                 double total, T* __restrict__ x) {
   __shared__ double sh[4];
   __shared__ double mean;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += BS) s += part[b];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) mean = s / double(n);
+  if (threadIdx.x == 0) mean = s / total;
   __syncthreads();
   const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
   if (i < n) x[i] = T(double(x[i]) - mean);
@@ -2860,6 +2871,20 @@ void diagnostics(const DSell& A, const double* M, const double* K, const double*
   hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(BS), 0, s, nblk, part, out);
 }
 
+__global__ __launch_bounds__(BS) void k_set_slots(int64_t n, const int* __restrict__ idx, double v,
+                                                  double* __restrict__ a, float* __restrict__ a32) {
+  const int64_t i = int64_t(blockIdx.x) * BS + threadIdx.x;
+  if (i >= n) return;
+  const int q = idx[i];
+  a[q] = v;
+  if (a32) a32[q] = float(v);
+}
+
+void set_slots(int64_t n, const int* idx, double v, double* a, float* a32, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_set_slots, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, idx, v, a, a32);
+}
+
 void rhs_quaternary(const DSell& A, const double* Mv, const double* php, const double* phn, const double* phs,
                     const double* Phi, const Coef3& c_mu, double c_ac, double* rhs_ch, double* rhs_ac,
                     double* fa, hipStream_t s) {
@@ -3010,8 +3035,14 @@ void sum_partial(int64_t n, const T* x, double* part, hipStream_t s) {
 }
 
 template <typename T>
-void sub_mean(int64_t n, int nblk, const double* part, T* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_sub_mean<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, nblk, part, x);
+void sub_mean(int64_t n, int nblk, const double* part, T* x, hipStream_t s, double total) {
+  hipLaunchKernelGGL((k_sub_mean<T>), dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, nblk, part,
+                     total > 0.0 ? total : double(n), x);
+}
+
+void wmean_zero(int64_t n, const double* w, double wtotal, double* x, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_wsum_partial, dim3(reduce_blocks(n)), dim3(BS), 0, s, n, w, x, part);
+  sub_mean<double>(n, reduce_blocks(n), part, x, s, wtotal);
 }
 
 void one_minus_sum(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
@@ -3082,8 +3113,8 @@ template void sell_op<float, float>(const DSell&, const float*, int, const float
                                     const float*, float*, float, float, float*, hipStream_t);
 template void sum_partial<double>(int64_t, const double*, double*, hipStream_t);
 template void sum_partial<float>(int64_t, const float*, double*, hipStream_t);
-template void sub_mean<double>(int64_t, int, const double*, double*, hipStream_t);
-template void sub_mean<float>(int64_t, int, const double*, float*, hipStream_t);
+template void sub_mean<double>(int64_t, int, const double*, double*, hipStream_t, double);
+template void sub_mean<float>(int64_t, int, const double*, float*, hipStream_t, double);
 
 }  // namespace chns
 

@@ -394,6 +394,8 @@ int diag_part_blocks(int64_t n);  // per-block partial sums diagnostics() writes
 void diagnostics(const DSell& A, const double* M, const double* K, const double* p0, const double* p1,
                  const double* p2, const double* Phi, bool ternary, const KorBeta& kb, const PotCoef& pc,
                  double* part, double* out, hipStream_t s);
+// a[idx[i]] = v (and a32[idx[i]] when a32 is given), i < n.
+void set_slots(int64_t n, const int* idx, double v, double* a, float* a32, hipStream_t s);
 // Quaternary right-hand sides (polymer, NFA, solvent; air eliminated):
 // rhs_ch holds three CH blocks [M phi_i; c_mu[i] M d_i] of 2n each, rhs_ac the
 // AC block, fa the unreduced air derivative per vertex.
@@ -498,7 +500,9 @@ void rhs_ternary(const DSell& A, const double* Mv, const double* php, const doub
 template <typename T>
 void sum_partial(int64_t n, const T* x, double* part, hipStream_t s);
 template <typename T>
-void sub_mean(int64_t n, int nblk, const double* part, T* x, hipStream_t s);
+void sub_mean(int64_t n, int nblk, const double* part, T* x, hipStream_t s, double total = 0.0);
+// x -= (sum_i w_i x_i) / wtotal (the mean with weights w; wtotal = sum_i w_i).
+void wmean_zero(int64_t n, const double* w, double wtotal, double* x, double* part, hipStream_t s);
 
 // Elementwise helpers of the ternary closure.
 void one_minus_sum(int64_t n, const double* a, const double* b, double* out, hipStream_t s);

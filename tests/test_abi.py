@@ -48,11 +48,9 @@ def test_create_rejects_bad_mesh(L, n, model):
 
 
 @pytest.mark.parametrize("boundary,length,model,code", [(7, 1.0, 0, -1), (1, -2.0, 0, -1),
-                                                         (1, float("nan"), 1, -1), (0, float("inf"), 0, -1),
-                                                         (1, 10.0, 2, -5)])
+                                                         (1, float("nan"), 1, -1), (0, float("inf"), 0, -1)])
 def test_create_rejects_bad_domain(L, boundary, length, model, code):
-    """Unknown boundary, a side that is not finite and positive, and the
-    ternary model on the closed square (no Taylor-Hood spaces with walls)."""
+    """Unknown boundary and a side that is not finite and positive."""
     h = ct.c_void_p()
     rc = L.chns_create(ct.byref(chns.Mesh(16, model, boundary, length)),
                        ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)), chns.ALLOC_FN(), chns.FREE_FN(), None,
@@ -65,7 +63,7 @@ QB = (2e-4, 2e-4, 1e-3, 4e-3)
 
 
 @pytest.mark.parametrize("model,boundary,kw,code", [
-    (3, 1, dict(beta_phase=QB), -5),                              # quaternary on the closed square
+    (2, 1, dict(var_density=1, rho_pure=(1.0, 1.0, 1.0)), -1),  # variable density: periodic only
     (3, 0, dict(beta_phase=(1e-3, 1e-3, 0.0, 1.0)), -1),          # a beta not positive
     (3, 0, dict(beta_phase=(1e-3, 1e-3, float("nan"), 1.0)), -1),
     (2, 0, dict(beta_phase=QB), -1),                              # per-phase betas: quaternary only

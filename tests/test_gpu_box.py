@@ -289,14 +289,33 @@ def test_top_flux_rhs_and_steps_match_oracle(C):
     ctx.close()
 
 
-def test_closed_square_refuses_a_velocity(C):
-    """No P2 velocity space on the closed square: the convection is refused
-    (creation with bad domains is checked on the CPU)."""
+def test_convected_binary_step_matches_oracle(C):
+    """CH + AC convected by a velocity that vanishes on the walls (P2 ids of
+    the closed square's padded numbering): operators and three steps."""
     import torch
-    ctx = _ctx(C, 16, "ch_ac")
-    vel = torch.zeros(8 * ctx.N, dtype=torch.float64, device="cuda")
-    with pytest.raises(C.ChnsError) as e:
-        ctx.assemble(vel)
-    assert e.value.code == C.EUNSUPPORTED
-    ctx.assemble(None)  # no convection: allowed
+    n = 32
+    ctx = _ctx(C, n, "ch_ac")
+    ops = S.Operators(n, box_length=L10)
+    prm = _prm(PB)
+    vel = inputs.box_stream_velocity(n, L10, 7, amp=0.2)
+    f0 = inputs.box_state(n, L10, "ch_ac", 0.5, 9)
+    f0["vel"] = vel
+    st = S.initial_state(ops, prm, "ch_ac", f0)
+    vt = _t(vel.ravel())
+    ctx.assemble(vt)
+    Cm = fem.p1_convection(ops.mesh, vel)
+    for op, ref in ((C.OP_C, Cm), (C.OP_AC, systems.ac_matrix(ops.M, ops.K, Cm, prm))):
+        rp, col, val, shape = ctx.matrix(op)
+        G = sp.csr_matrix((val, col, rp), shape=shape)
+        assert abs(G - ref).max() <= 1e-13 * abs(ref).max(), op
+    ref = st
+    for _ in range(3):
+        ref = dict(ref, **{k: v for k, v in S.step(ops, prm, "ch_ac", ref).items() if v is not None})
+    phi, mu, Phi = _t(st["phi"][0]), _t(st["mu"][0]), _t(st["Phi_v"])
+    fin = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi, vel=vt)
+    rc, infos = ctx.timestep(fin, fin, nsteps=3, opts=C.default_opts(rtol=1e-12))
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    assert _rel(_np(phi), ref["phi"][0]) < 1e-10 and _rel(_np(Phi), ref["Phi_v"]) < 1e-10
+    assert _rel(_np(mu), ref["mu"][0]) < 1e-9
     ctx.close()

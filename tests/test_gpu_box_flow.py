@@ -1,0 +1,185 @@
+"""GPU parity of the flow models (ternary, quaternary) on the closed square with
+no-slip walls, through the C-ABI, against the oracle.
+
+The library keeps the padded P2 numbering of the closed square and holds the
+no-slip set (wall nodes and the ids of no edge) with identity rows that no
+other row couples to; the oracle solves on the velocity unknowns off that set.
+The Oseen operator is compared with the oracle's after the same masking
+(1e-12 of the largest entry); right-hand sides within 1e-13 (1e-12 for the
+Oseen rows); one FP64 step (FGMRES rtol 1e-13 per solve) within 1e-10 for
+every field but the pressure, whose bar is ten times the oracle's own
+sensitivity to rounding-level perturbations of its system.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fem, solvers, step as S, systems
+from oracle.systems import Params
+from paper_2501_11767_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+L2 = 2.0
+PF = dict(eps=0.3, tau=1e-3, mobility=1.0, evap_rate=0.5, viscosity=0.5, alpha=1e-3, rho=1.0)
+QB = (2e-3, 2e-3, 1e-2, 4e-2)
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_11767_amd import chns
+    chns.lib()
+    return chns
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def _maxrel(a, b):
+    return np.abs(np.ravel(a) - np.ravel(b)).max() / max(np.abs(np.ravel(b)).max(), 1e-300)
+
+
+def _setup(model, n, seed=3, **kw):
+    prm = Params(**dict(PF, **(dict(betas=QB) if model == "quaternary" else {}), **kw))
+    ops = S.Operators(n, need_p2=True, box_length=L2)
+    st = S.initial_state(ops, prm, model, inputs.box_state(n, L2, model, 0.33, seed))
+    out, sysr = S.step(ops, prm, model, st, "splu", return_systems=True)
+    return ops, prm, st, out, sysr
+
+
+def _ctx(C, model, n, **kw):
+    q = dict(PF, **kw)
+    if model == "quaternary":
+        q["beta_phase"] = QB
+    return C.Context(n, model, boundary="noflux", length=L2, **q)
+
+
+def _fields(ctx, model, st):
+    nph = 3 if model == "quaternary" else 2
+    mus = [st["mu"][i] for i in range(nph)] + [st["mu_a"] if model == "quaternary" else st["mu_s"]]
+    fld = dict(phi=[_t(st["phi"][i]) for i in range(nph)], mu=[_t(u) for u in mus], Phi_v=_t(st["Phi_v"]),
+               vel=_t(np.asarray(st["vel"]).ravel()), p=_t(st["p"]))
+    return fld, ctx.fields(**fld)
+
+
+def _masked(A, fixed):
+    """A with the rows and columns of the fixed unknowns zeroed and a unit
+    diagonal there (what the library assembles for the no-slip set)."""
+    keep = sp.diags((~fixed).astype(float))
+    return (keep @ A @ keep + sp.diags(fixed.astype(float))).tocsr()
+
+
+def _pressure_sensitivity(ops, sysr, p_ref, trials=3):
+    A, B, rhs = sysr["ns_A"].tocsr(), ops.B.tocsr(), sysr["ns_rhs"]
+    g = np.random.default_rng(1)
+    worst = 0.0
+    for _ in range(trials):
+        A2, B2 = A.copy(), B.copy()
+        A2.data = A2.data * (1 + 2e-16 * g.uniform(-1, 1, A2.data.size))
+        B2.data = B2.data * (1 + 2e-16 * g.uniform(-1, 1, B2.data.size))
+        _, p2, _ = solvers.bordered_oseen_solve(A2, B2, ops.M, rhs * (1 + 2e-16 * g.uniform(-1, 1, rhs.size)),
+                                                fixed=ops.vfixed)
+        worst = max(worst, _rel(p2, p_ref), _maxrel(p2, p_ref))
+    return worst
+
+
+@pytest.mark.parametrize("model", ["ternary", "quaternary"])
+def test_operators_and_right_hand_sides(C, model):
+    import torch
+    n = 16
+    ops, prm, st, out, sysr = _setup(model, n)
+    N = ops.N
+    ctx = _ctx(C, model, n)
+    fld, f = _fields(ctx, model, st)
+    print(f"box flow operators {model}", flush=True)
+    ctx.assemble(fld["vel"], fld["mu"])
+    rp, col, val, shape = ctx.matrix(C.OP_NS)
+    G = sp.csr_matrix((val, col, rp), shape=shape)
+    fixed = np.concatenate([ops.vfixed, np.zeros(N, bool)])
+    ref = _masked(systems.oseen_matrix(sysr["ns_A"], ops.B), fixed)
+    assert abs(G - ref).max() <= 1e-12 * abs(ref).max()
+    nch = 3 if model == "quaternary" else 2
+    rch = torch.zeros(2 * nch * N, dtype=torch.float64, device="cuda")
+    rac = torch.zeros(N, dtype=torch.float64, device="cuda")
+    rns = torch.zeros(9 * N, dtype=torch.float64, device="cuda")
+    ctx.step_rhs(f, rch, rac, rns)
+    torch.cuda.synchronize()
+    for i in range(nch):
+        assert _maxrel(_np(rch)[2 * i * N:2 * (i + 1) * N], sysr["ch_rhs"][i]) < 1e-13, i
+    assert _maxrel(_np(rac), sysr["ac_rhs"]) < 1e-13
+    want = np.where(ops.vfixed, 0.0, sysr["ns_rhs"])
+    got = _np(rns)[:8 * N]
+    assert np.all(got[ops.vfixed] == 0.0) and _rel(got, want) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("model,picard", [("ternary", 1), ("quaternary", 1), ("ternary", 3)])
+def test_step_matches_oracle(C, model, picard):
+    import torch
+    n = 16
+    kw = dict(picard=picard) if picard > 1 else {}
+    ops, prm, st, out, sysr = _setup(model, n, **kw)
+    ctx = _ctx(C, model, n, **(dict(ns_picard=picard) if picard > 1 else {}))
+    fld, f = _fields(ctx, model, st)
+    print(f"box flow step {model} picard={picard}", flush=True)
+    rc, infos = ctx.timestep(f, f, nsteps=1, opts=C.default_opts(rtol=1e-13, maxiter=800))
+    torch.cuda.synchronize()
+    nsolve = 5 if model == "quaternary" else 4
+    assert rc == C.OK and len(infos) == nsolve and all(i["converged"] for i in infos), infos
+    nph = 3 if model == "quaternary" else 2
+    pairs = [(fld["phi"][i], out["phi"][i]) for i in range(nph)] + \
+            [(fld["mu"][i], out["mu"][i]) for i in range(nph)] + \
+            [(fld["mu"][nph], out["mu_a"] if model == "quaternary" else out["mu_s"]),
+             (fld["Phi_v"], out["Phi_v"]), (fld["vel"], out["vel"].ravel())]
+    for k, (got, ref) in enumerate(pairs):
+        assert _rel(_np(got), ref) < 1e-10 and _maxrel(_np(got), ref) < 1e-10, k
+    v = _np(fld["vel"])
+    assert np.all(v[ops.vfixed] == 0.0)
+    pbar = max(10 * _pressure_sensitivity(ops, sysr, out["p"]), 1e-10 if picard > 1 else 0.0)
+    assert _rel(_np(fld["p"]), out["p"]) < pbar, pbar
+    ctx.close()
+
+
+def test_mixed_precision_steps(C):
+    """Two mixed-precision ternary steps on the closed square against the
+    oracle's two steps (FGMRES rtol 1e-11)."""
+    import torch
+    n = 32
+    ops, prm, st, out, sysr = _setup("ternary", n)
+    ref = S.step(ops, prm, "ternary", out)
+    ctx = _ctx(C, "ternary", n)
+    fld, f = _fields(ctx, "ternary", st)
+    print("box flow mixed", flush=True)
+    rc, infos = ctx.timestep(f, f, nsteps=2, opts=C.default_opts(rtol=1e-11, precision=C.MIXED, maxiter=1000))
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    for i in range(2):
+        assert _rel(_np(fld["phi"][i]), ref["phi"][i]) < 1e-8
+    assert _rel(_np(fld["vel"]), ref["vel"].ravel()) < 1e-7
+    ctx.close()
+
+
+def test_adjoint_is_refused_on_the_closed_square(C):
+    import torch
+    n = 16
+    ctx = _ctx(C, "ternary", n)
+    N = (n + 1) ** 2
+    z = lambda k=N: torch.zeros(k, dtype=torch.float64, device="cuda")
+    f = ctx.fields(phi=[z(), z()], mu=[z(), z(), z()], Phi_v=z(), vel=z(8 * N), p=z())
+    with pytest.raises(C.ChnsError) as e:
+        ctx.timestep_adjoint(f, f, f, f)
+    assert e.value.code == C.EUNSUPPORTED
+    ctx.close()

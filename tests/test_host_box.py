@@ -234,3 +234,11 @@ def test_box_p1_to_p2_transfer(probe):
     lin = lambda xy: 0.7 * xy[:, 0] - 0.2 * xy[:, 1] + 1.0
     got = P @ lin(m.vertex_xy())
     assert np.abs(got[~fixed] - lin(m.p2_xy())[~fixed]).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [8, 16, 66])
+def test_box_transfer_sell_columns_stay_in_range(probe, n):
+    """The P1 -> P2 transfer of the closed square ends with rows of no entry
+    (ids of no edge); their SELL padding must still name a valid column (the
+    kernels read x at every stored column)."""
+    assert probe.chns_probe_box_p2_transfer_sell_bad(n) == 0

@@ -40,6 +40,10 @@ def test_noalloc_diagnostics_equal_the_allocating_entry_point(C):
     import torch
     cases = [(512, "ternary", 3), (64, "ch_ac", 4), (32, "ch", 5)]  # each smaller than the last
     ctxs = [_case(C, n, model, seed) for n, model, seed in cases]
+    # objects of earlier tests freed by the collector inside the window would
+    # move the allocator's count: collect them first
+    import gc
+    gc.collect()
     torch.cuda.synchronize()
     a0 = C.TorchAllocator.alloc_calls
     m0 = torch.cuda.memory_allocated()
