@@ -338,6 +338,44 @@ def quad_section(chns, steps):
                 iters_ch_p_ch_n_ch_s_ac_ns=its[-1], steps=steps)
 
 
+def quadbox_section(chns, steps):
+    """The paper's full two-dimensional run (quadbox): the quaternary step on
+    the closed 10 x 10 square with no-flux and no-slip walls, FP64 with the
+    drying workload's solver options: ms per coupled step and FGMRES
+    iterations, each step from the seeded state (mu^0 = 0)."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    cfg = inputs.CONFIGS["quadbox"]
+    n, L = cfg["n"], cfg["length"]
+    ctx = chns.Context(n, "quaternary", boundary="noflux", length=L, eps=cfg["eps"], tau=cfg["tau"],
+                       mobility=cfg["mobility"], evap_rate=cfg["evap_rate"], viscosity=cfg["viscosity"],
+                       alpha=cfg["alpha"], rho=1.0, beta_phase=cfg["betas"])
+    N = ctx.N
+    st = inputs.box_state(n, L, "quaternary", cfg["mean"], cfg["seed"])
+    z = lambda: torch.zeros(N, dtype=torch.float64, device="cuda")
+    f = ctx.fields(phi=[dev(st["phi"][i]) for i in range(3)], mu=[z(), z(), z(), z()], Phi_v=dev(st["Phi_v"]),
+                   vel=dev(st["vel"].ravel()), p=dev(st["p"]))
+    e = lambda k: torch.empty(k, dtype=torch.float64, device="cuda")
+    fo = ctx.fields(phi=[e(N), e(N), e(N)], mu=[e(N), e(N), e(N), e(N)], Phi_v=e(N), vel=e(8 * N), p=e(N))
+    opts = chns.default_opts(rtol=1e-8, precision=chns.F64, maxiter=1000, **DRY_OPTS)
+    ctx.timestep(f, fo, 1, opts)
+    torch.cuda.synchronize()
+    walls, its = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rc, inf = ctx.timestep(f, fo, 1, opts)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        its.append([i["iters"] for i in inf])
+    ctx.close()
+    return dict(workload=f"quadbox: quaternary CH + AC + Taylor-Hood Oseen step on the closed square [0, {L}]^2 "
+                         f"(no-flux walls, no-slip velocity), {n} cells per side ({N} vertices), betas "
+                         f"{cfg['betas']}, beta_v = delta_v = {cfg['eps'] ** 2:g}, tau {cfg['tau']}, FP64, FGMRES("
+                         f"{DRY_OPTS['restart']}) rtol 1e-8",
+                ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
+                iters_ch_p_ch_n_ch_s_ac_ns=its[-1], steps=steps)
+
+
 def box_section(chns, steps, restart):
     """The paper's closed domain: the CH + AC step on the 10 x 10 square with
     no-flux walls (128 cells per side, 129^2 vertices, film under air),
@@ -803,6 +841,7 @@ def main():
     bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
     box = box_section(chns, args.box_steps, args.restart) if args.box_steps > 0 else None
     quad = quad_section(chns, args.quad_steps) if args.quad_steps > 0 else None
+    qbox = quadbox_section(chns, args.quad_steps) if args.quad_steps > 0 else None
     adj = None if args.no_adjoint else adjoint_section(chns)
     cpu = None
     if not args.no_cpu:
@@ -867,6 +906,7 @@ def main():
         "batch64": bat,
         "box10": box,
         "quad256": quad,
+        "quadbox": qbox,
         "adjoint128": adj,
     }
     ctx.close()

@@ -194,6 +194,15 @@ CONFIGS = {
     "quad256": dict(n=256, model="quaternary", eps=0.01, tau=1e-4, mobility=1.0, evap_rate=1.0,
                     viscosity=1.0, alpha=1e-8, betas=(1e-7, 1e-7, 1e-5, 1e-4), steps=1, mean=0.33,
                     seed=BASE_SEED + 6),
+    # the paper's full two-dimensional run (section "Numerical results", figure
+    # of GMRES iterations for polymer, NFA, solvent and Navier-Stokes): the
+    # closed 10 x 10 square, no-flux walls, no-slip velocity, beta_p = beta_N =
+    # 1e-3, beta_s = 1e-1, beta_a = beta_v = delta_v = 1 (eps = 1, gamma_v = 1),
+    # gamma = 1, alpha = 1e-8, tau = 1e-4, a = b = 0.33; 64 cells per side (the
+    # paper takes 50) so that the hierarchy halves to 4
+    "quadbox": dict(n=64, length=10.0, model="quaternary", eps=1.0, tau=1e-4, mobility=1.0, evap_rate=1.0,
+                    viscosity=1.0, alpha=1e-8, betas=(1e-3, 1e-3, 1e-1, 1.0), steps=1, mean=0.33,
+                    seed=BASE_SEED + 7),
     "batch64": dict(instances=64, sizes=(64, 128, 256, 512), seed=BASE_SEED + 3),
     # Differentiation workload.  With the explicit potential the ternary run on
     # this mesh diverges within 6 steps at tau = 1e-3, 8 at 1e-4 and 17 at 1e-5

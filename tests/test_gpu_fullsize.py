@@ -322,6 +322,43 @@ def test_quad256_step_satisfies_oracle_systems(mods):
     assert _rel(g["mu"][3], mua) <= 1e-10
 
 
+def test_quadbox_step_matches_the_direct_solves(mods):
+    """The paper's full two-dimensional run at the benchmark's size and
+    configuration (closed 10 x 10 square, 64 cells per side, quaternary with
+    the paper's betas, FGMRES rtol 1e-8): one step against the oracle's direct
+    solves, within the solver's forward error (kappa * rtol with kappa <= 100);
+    the walls at rest and the pressure's integral zero."""
+    import torch
+    C, _ = mods
+    cfg = inputs.CONFIGS["quadbox"]
+    n, L = cfg["n"], cfg["length"]
+    print("quadbox full size: quaternary step on the closed square vs direct solves", flush=True)
+    p = dict(eps=cfg["eps"], tau=cfg["tau"], mobility=cfg["mobility"], evap_rate=cfg["evap_rate"],
+             viscosity=cfg["viscosity"], alpha=cfg["alpha"], rho=1.0)
+    prm = Params(betas=cfg["betas"], **p)
+    ops = S.Operators(n, need_p2=True, box_length=L)
+    st = S.initial_state(ops, prm, "quaternary", inputs.box_state(n, L, "quaternary", cfg["mean"], cfg["seed"]))
+    out = S.step(ops, prm, "quaternary", st)
+    ctx = C.Context(n, "quaternary", boundary="noflux", length=L, beta_phase=cfg["betas"], **p)
+    fld = dict(phi=[_dev(st["phi"][i]) for i in range(3)],
+               mu=[_dev(st["mu"][0]), _dev(st["mu"][1]), _dev(st["mu"][2]), _dev(st["mu_a"])],
+               Phi_v=_dev(st["Phi_v"]), vel=_dev(np.asarray(st["vel"]).ravel()), p=_dev(st["p"]))
+    f = ctx.fields(**fld)
+    rc, info = ctx.timestep(f, f, 1, C.default_opts(rtol=1e-8, precision=C.F64, maxiter=1000, restart=15,
+                                                    **BENCH_MG))
+    torch.cuda.synchronize()
+    assert rc == C.OK, info
+    g = {k: ([t.cpu().numpy() for t in v] if isinstance(v, list) else v.cpu().numpy()) for k, v in fld.items()}
+    ctx.close()
+    bar = 100 * 1e-8
+    for i in range(3):
+        assert _rel(g["phi"][i], out["phi"][i]) < bar, i
+    assert _rel(g["Phi_v"], out["Phi_v"]) < bar
+    assert _rel(g["vel"], out["vel"].ravel()) < bar
+    assert np.all(g["vel"][ops.vfixed] == 0.0)
+    assert abs(np.ones(ops.N) @ (ops.M @ g["p"])) < 1e-12 * np.abs(g["p"]).sum()
+
+
 def test_batch64_instances_residuals_and_sampled_errors(mods):
     import torch
     C, _ = mods
