@@ -61,6 +61,26 @@ class Operators:
         return solvers.sparse_solve(self.M, b)
 
 
+class Operators3D:
+    """The periodic unit cube (fem3d.Mesh3, Kuhn tetrahedra) with the P1
+    matrices, for the binary models without convection."""
+
+    three_d = True
+    box = False
+    Mv = B = vfixed = None
+
+    def __init__(self, n: int, length: float = 1.0):
+        from . import fem3d
+        self.n = n
+        self.mesh = fem3d.Mesh3(n, length)
+        self.N = self.mesh.nv
+        self.M = fem3d.p1_mass(self.mesh)
+        self.K = fem3d.p1_stiffness(self.mesh)
+
+    def mass_solve(self, b):
+        return solvers.sparse_solve(self.M, b)
+
+
 def _solve(A, b, how):
     if how == "dense":
         return solvers.dense_solve(A, b)
@@ -150,8 +170,10 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
     mesh = ops.mesh
     vel = st.get("vel")
     C = fem.p1_convection(mesh, vel) if vel is not None else None
-    if how == "fft" and (C is not None or ops.box):
-        raise ValueError("the Fourier solve needs a convection-free periodic system")
+    if how == "fft" and (C is not None or ops.box or getattr(ops, "three_d", False)):
+        raise ValueError("the Fourier solve needs a convection-free periodic square")
+    if getattr(ops, "three_d", False) and (vel is not None or model not in ("ch", "ch_ac")):
+        raise ValueError("the cube carries the binary models without convection")
     fps, fv = explicit_terms(model, st, prm)
     out = dict(vel=vel, p=st.get("p"))
     sysrec = {}
