@@ -44,6 +44,14 @@ level, whose Chebyshev interval starts at 0.9 (1 - cos(2 pi / n_L)) / 2 (the
 smallest nonzero eigenvalue of D^{-1} K there), and the result is projected to
 mean zero.
 
+The periodic cube (Kuhn tetrahedra): the same cycle on the nested meshes of
+the cube (coarse vertex (I, J, K) at fine vertex (2I, 2J, 2K); a fine vertex
+with odd coordinates (a, b, c) in {0, 1}^3 is the midpoint of the coarse edge
+from (I, J, K) to (I + a, J + b, K + c)).  There diag(K) = 6 h and diag(M) =
+0.4 h^3, so rho_l = 15 b / (a h_l^2), and D^{-1} M has spectrum in [0.5, 2.5]
+(D^{-1} K in [0, 2]): the smoother's upper bound becomes LMAX_CUBE = 1.25
+LMAX and the cut level's interval [0.9 * 0.5 / (1 + rho), LMAX_CUBE].
+
 Chebyshev iteration (first kind) on [lo, hi] with theta = (hi + lo) / 2,
 delta = (hi - lo) / 2, sigma = theta / delta:
   r_0 = D^{-1}(b - A x_0), d_0 = r_0 / theta, x_1 = x_0 + d_0, rho_0 = 1 / sigma;
@@ -57,6 +65,7 @@ import numpy as np
 import scipy.sparse as sp
 
 LMAX = 2.1
+LMAX_CUBE = 1.25 * LMAX
 LMAX_P2 = 2.3
 RHO_CUT = 0.25
 
@@ -117,6 +126,25 @@ def p2_to_p1(n: int):
                          shape=(4 * N, N))
 
 
+def prolongation_cube(nf: int):
+    """P1 interpolation from the periodic cube of side nf/2 to side nf (Kuhn
+    meshes, vertex (i, j, k) -> i + n j + n^2 k): each fine vertex takes the
+    mean of the coarse ends of the coarse edge it halves, or copies the coarse
+    vertex it sits on."""
+    nc = nf // 2
+    k, j, i = np.unravel_index(np.arange(nf ** 3), (nf, nf, nf))
+    f = np.stack([i, j, k], 1)
+    base, odd = f // 2, f % 2
+    cid = lambda q: (q[:, 0] % nc) + nc * (q[:, 1] % nc) + nc * nc * (q[:, 2] % nc)
+    rows = np.arange(nf ** 3)
+    on_vertex = ~odd.any(axis=1)
+    P = sp.coo_matrix((np.where(on_vertex, 1.0, 0.5), (rows, cid(base))), shape=(nf ** 3, nc ** 3))
+    Q = sp.coo_matrix((np.where(on_vertex, 0.0, 0.5), (rows, cid(base + odd))), shape=(nf ** 3, nc ** 3))
+    out = (P + Q).tocsr()
+    out.eliminate_zeros()
+    return out
+
+
 def level_sizes(n: int, nmin: int = 4):
     out = [n]
     while out[-1] % 2 == 0 and out[-1] // 2 >= nmin:
@@ -124,14 +152,15 @@ def level_sizes(n: int, nmin: int = 4):
     return out
 
 
-def rho(a, b, nl, length=1.0):
-    """8 b / (a h^2) with h = length / nl."""
-    return 8.0 * b * (nl / length) ** 2 / a
+def rho(a, b, nl, length=1.0, cube=False):
+    """r b / (a h^2) with h = length / nl, r = diag(K) h^2 / diag(M): 8 on the
+    triangles, 15 on the Kuhn tetrahedra."""
+    return (15.0 if cube else 8.0) * b * (nl / length) ** 2 / a
 
 
-def cut_level(sizes, a, b, rho_cut=RHO_CUT, length=1.0):
+def cut_level(sizes, a, b, rho_cut=RHO_CUT, length=1.0, cube=False):
     for l, nl in enumerate(sizes):
-        if rho(a, b, nl, length) <= rho_cut:
+        if rho(a, b, nl, length, cube) <= rho_cut:
             return l
     return len(sizes) - 1
 
@@ -141,17 +170,22 @@ class Hierarchy:
 
     ``p2``: A is a P2 operator; ``singular``: pressure Laplacian (a = 0);
     ``box_length``: A lives on the closed square [0, L]^2 (P1, (n+1)^2 nodes)
-    instead of the periodic unit square."""
+    instead of the periodic unit square; ``cube_length``: on the periodic cube
+    [0, L]^3 (P1 on the Kuhn tetrahedra, n^3 nodes)."""
 
     def __init__(self, A, n: int, a: float = 1.0, b: float = 0.0, nmin: int = 4,
                  rho_cut: float = RHO_CUT, p2: bool = False, singular: bool = False,
-                 box_length: float | None = None):
-        if box_length is not None and (p2 or singular):
-            raise ValueError("the closed square carries P1 operators with a mass part")
+                 box_length: float | None = None, cube_length: float | None = None):
+        if (box_length is not None or cube_length is not None) and (p2 or singular):
+            raise ValueError("the closed square and the cube carry P1 operators with a mass part")
+        if box_length is not None and cube_length is not None:
+            raise ValueError("one domain at a time")
         sizes = level_sizes(n, nmin)
         self.singular = singular
-        length = 1.0 if box_length is None else box_length
-        self.cut = len(sizes) - 1 if singular else cut_level(sizes, a, b, rho_cut, length)
+        cube = cube_length is not None
+        length = box_length if box_length is not None else (cube_length if cube else 1.0)
+        lmax = LMAX_CUBE if cube else LMAX
+        self.cut = len(sizes) - 1 if singular else cut_level(sizes, a, b, rho_cut, length, cube)
         self.sizes = sizes[: self.cut + 1]
         self.A = [sp.csr_matrix(A)]
         self.P = []
@@ -162,16 +196,19 @@ class Hierarchy:
             self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
             self.lmax.append(LMAX_P2)
         for nf in self.sizes[:-1]:
-            P = prolongation(nf) if box_length is None else prolongation_box(nf)
+            if cube:
+                P = prolongation_cube(nf)
+            else:
+                P = prolongation(nf) if box_length is None else prolongation_box(nf)
             self.P.append(P)
             self.A.append(sp.csr_matrix(P.T @ self.A[-1] @ P))
-            self.lmax.append(LMAX)
-        self.lmax.append(LMAX)
+            self.lmax.append(lmax)
+        self.lmax.append(lmax)
         nl = self.sizes[-1]
         if singular:
             self.lo_last = 0.9 * (1.0 - np.cos(2.0 * np.pi / nl)) / 2.0
         else:
-            self.lo_last = 0.9 * 0.5 / (1.0 + rho(a, b, nl, length))
+            self.lo_last = 0.9 * 0.5 / (1.0 + rho(a, b, nl, length, cube))
         self.Dinv = [1.0 / Al.diagonal() for Al in self.A]
 
 

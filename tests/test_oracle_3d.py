@@ -147,3 +147,56 @@ def test_small_steps_decrease_the_energy():
         st = dict(st, phi=out["phi"], mu=out["mu"])
         E.append(S.energy_ch(ops, prm, st["phi"][0]))
     assert all(E[i + 1] < E[i] for i in range(3)), E
+
+
+@pytest.mark.parametrize("nf", [8, 12])
+def test_cube_prolongation_is_nested(nf):
+    """P^T A_h P equals the coarse mesh's own form (the Kuhn meshes are nested,
+    so the coarse P1 space is a subspace of the fine one), and P copies the
+    coarse vertices."""
+    from oracle import multigrid as mg
+    P = mg.prolongation_cube(nf)
+    nc = nf // 2
+    assert P.shape == (nf ** 3, nc ** 3) and np.allclose(P @ np.ones(nc ** 3), 1.0)
+    g = np.random.default_rng(1).standard_normal(nc ** 3)
+    kk, jj, ii = np.meshgrid(np.arange(nc), np.arange(nc), np.arange(nc), indexing="ij")
+    assert np.array_equal((P @ g)[_ids(nf, 2 * ii, 2 * jj, 2 * kk).ravel()], g)
+    for form in (fem3d.p1_mass, fem3d.p1_stiffness):
+        ref = form(fem3d.Mesh3(nc, 2.0))
+        assert abs(P.T @ form(fem3d.Mesh3(nf, 2.0)) @ P - ref).max() <= 1e-14 * abs(ref).max()
+
+
+def test_cube_smoother_bounds_hold():
+    """The spectral facts the cube's cycle rests on: D^{-1} M in [0.5, 2.5],
+    D^{-1} K in [0, 2], so D^{-1}(a M + b K) stays below LMAX_CUBE and above
+    0.5 / (1 + 15 b / (a h^2))."""
+    from oracle import multigrid as mg
+    n = 6
+    m = fem3d.Mesh3(n, 1.5)
+    M, K = fem3d.p1_mass(m).toarray(), fem3d.p1_stiffness(m).toarray()
+    ev = lambda A: np.linalg.eigvals(A / A.diagonal()[:, None]).real
+    em, ek = ev(M), ev(K)
+    assert em.min() > 0.5 - 1e-12 and em.max() < 2.5 + 1e-12 and abs(em.max() - 2.5) < 1e-9
+    assert ek.min() > -1e-12 and ek.max() < 2.0 + 1e-12
+    for a, b in ((1.0, 0.0), (1.0, 1e-3), (0.3, 0.05), (1.0, 10.0)):
+        e = ev(a * M + b * K)
+        assert e.max() < mg.LMAX_CUBE
+        assert e.min() >= 0.5 / (1.0 + mg.rho(a, b, n, 1.5, cube=True)) - 1e-12, (a, b)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_cube_cycle_contracts(n):
+    """One V(2, 1) cycle on the matching factor tau g K + sqrt(tau g / beta) M
+    contracts the error by a mesh-independent factor."""
+    from oracle import multigrid as mg
+    prm = Params(**PC)
+    t, g, b = prm.tau, prm.gamma, prm.beta
+    m = fem3d.Mesh3(n)
+    X = (t * g * fem3d.p1_stiffness(m) + np.sqrt(t * g / b) * fem3d.p1_mass(m)).tocsr()
+    H = mg.Hierarchy(X, n, a=np.sqrt(t * g / b), b=t * g, cube_length=1.0)
+    assert len(H.A) >= 2  # the operator is cut below the fine level
+    e = np.random.default_rng(2).standard_normal(n ** 3)
+    for _ in range(4):
+        e = e - mg.vcycle(H, X @ e, pre=2, post=1, coarse=12)
+    e1 = e - mg.vcycle(H, X @ e, pre=2, post=1, coarse=12)
+    assert np.linalg.norm(e1) < 0.35 * np.linalg.norm(e)
