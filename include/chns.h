@@ -120,10 +120,15 @@ enum {
 };
 
 typedef struct {
-  int32_t n;        /* cells per side (even, 8..8192) */
+  int32_t n;        /* cells per side (even, 8..8192; 8..128 on the cube) */
   int32_t model;    /* CHNS_MODEL_* */
   int32_t boundary; /* CHNS_BOUNDARY_*; 0 = periodic */
-  double length;    /* side of the square (h = length / n); 0 means 1 */
+  int32_t dim;      /* 2 (0 means 2): the square; 3: the periodic cube [0, length]^3
+                       (section "Numerical results", three-dimensional runs) with n^3
+                       vertices i + n j + n^2 k at (i h, j h, k h), each cell split into
+                       the six Kuhn tetrahedra along its main diagonal (P1 rows of 15
+                       entries); the binary models only, no convecting velocity */
+  double length;    /* side of the square or cube (h = length / n); 0 means 1 */
 } chns_mesh;
 
 /* Local free-energy density of the ternary model. */

@@ -43,7 +43,7 @@ EXPORTS = [
 
 
 class Mesh(ct.Structure):
-    _fields_ = [("n", ct.c_int32), ("model", ct.c_int32), ("boundary", ct.c_int32),
+    _fields_ = [("n", ct.c_int32), ("model", ct.c_int32), ("boundary", ct.c_int32), ("dim", ct.c_int32),
                 ("length", ct.c_double)]
 
 
@@ -239,19 +239,19 @@ def _stream():
 class Context:
     """Owns a chns_ctx for one mesh/model/parameter set.  boundary "periodic"
     (n^2 nodes) or "noflux" (the closed square, (n+1)^2 nodes); length: the
-    square's side."""
+    square's side; dim 3: the periodic cube (n^3 nodes, binary models)."""
 
     def __init__(self, n: int, model: str = "ch_ac", torch_alloc: bool = True,
-                 boundary: str = "periodic", length: float = 1.0, **params):
+                 boundary: str = "periodic", length: float = 1.0, dim: int = 2, **params):
         self.L = lib()
-        self.n, self.model = n, model
+        self.n, self.model, self.dim = n, model, dim
         self.boundary, self.length = boundary, length
-        self.N = (n + 1) ** 2 if boundary == "noflux" else n * n
+        self.N = n ** 3 if dim == 3 else ((n + 1) ** 2 if boundary == "noflux" else n * n)
         p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.0, viscosity=1.0, alpha=1e-8,
                  rho=1.0)
         p.update(params)
         self.params = p
-        m = Mesh(n, MODELS[model], BOUNDARIES[boundary], length)
+        m = Mesh(n=n, model=MODELS[model], boundary=BOUNDARIES[boundary], dim=dim, length=length)
         h = ct.c_void_p()
         af, ff = _allocator(torch_alloc)
         rc = self.L.chns_create(ct.byref(m), ct.byref(Params(**p)), af, ff, None, ct.byref(h))

@@ -368,6 +368,13 @@ void galerkin_down(chns_ctx* c, double* Level::*stream, float* Level::*copy32, h
 int assemble_base(chns_ctx* c, int kind, double* val, const double* vel, hipStream_t s) {
   Level& L0 = c->lv[0];
   HIPCHK(c, hipMemsetAsync(val, 0, L0.sell.slots() * sizeof(double), s));
+  if (c->dim3) {
+    if (kind > 1) return fail(c, CHNS_EUNSUPPORTED, "the cube assembles the mass and stiffness matrices only");
+    for (int col = 0; col < 48; ++col)
+      assemble_p1_tet(kind, c->colour_ptr3[col], c->colour_ptr3[col + 1], c->etype, c->eslot, c->h, val, s);
+    HIPCHK(c, hipGetLastError());
+    return CHNS_OK;
+  }
   const int64_t n2 = 4 * int64_t(c->N);
   for (int col = 0; col < 8; ++col)
     assemble_p1(kind, c->el.colour_ptr[col], c->el.colour_ptr[col + 1], c->ep2, c->etype, c->eslot,
@@ -458,6 +465,7 @@ int weighted_masses(chns_ctx* c, hipStream_t s) {
 int assemble_ops(chns_ctx* c, const double* d_vel, const double* const* d_mu, bool transposed,
                  hipStream_t s) {
   if (c->ternary && !d_vel) return fail(c, CHNS_EINVAL, "the ternary model needs a velocity");
+  if (c->dim3 && d_vel) return fail(c, CHNS_EUNSUPPORTED, "no convecting velocity on the cube");
   Level& L0 = c->lv[0];
   if (c->ternary) TRY(assemble_ternary_conv(c, d_vel, d_mu, transposed, s));
   if (d_vel) {
@@ -553,11 +561,17 @@ ChebCoef<T> cheb_coef(double lo, double hi, int steps) {
   return cc;
 }
 
-// Level where the cycle of a M + b K stops: first l with 8 b n_l^2 / a <= rho_cut.
+// Upper Chebyshev bound of D^{-1}A for A = a M + b K: the option's value on
+// triangles; on the Kuhn tetrahedra, whose D^{-1}M reaches 2.5 (2 on
+// triangles), scaled by 5/4.
+double lmax_of(const chns_ctx* c, const chns_solve_opts& o) { return c->dim3 ? 1.25 * o.mg_lmax : o.mg_lmax; }
+
+// Level where the cycle of a M + b K stops: first l with r b / (a h_l^2) <=
+// rho_cut, r = diag(K) h^2 / diag(M) (8 on triangles, 15 on the tetrahedra).
 size_t cut_level(chns_ctx* c, const double* coef, double rho_cut) {
   for (size_t l = 0; l < c->lv.size(); ++l) {
     const double ih = c->lv[l].n / c->len;  // 1 / h on level l
-    if (8.0 * coef[1] * ih * ih / coef[0] <= rho_cut) return l;
+    if (c->diag_ratio * coef[1] * ih * ih / coef[0] <= rho_cut) return l;
   }
   return c->lv.size() - 1;
 }
@@ -577,13 +591,14 @@ const double* coef_of(chns_ctx* c, OpVals Level::*op) {
 bool singular_of(OpVals Level::*op) { return op == &Level::Kp; }
 
 // One Chebyshev sweep of the P1 stencil kernel, through the ledger.
-// Algorithmic bytes per row: the 7 values, x (own entry), b, 1/diag, d (read
-// when c1 != 0), d and y written; columns are computed, not read.
+// Algorithmic bytes per row: the row's values (7 on triangles), x (own entry),
+// b, 1/diag, d (read when c1 != 0), d and y written; columns are computed on
+// the periodic square, not read.
 template <typename T>
 void cheb_sweep(chns_ctx* c, Level& L, const OpVals& A, const T* x, const T* b, T* d, T c1, T c2,
                 T* y, hipStream_t s) {
   const bool f32 = std::is_same<T, float>::value;
-  const double bytes = double(L.N) * sizeof(T) * (7 + 5 + (c1 != T(0) ? 1 : 0));
+  const double bytes = double(L.N) * sizeof(T) * (L.d.width + 5 + (c1 != T(0) ? 1 : 0));
   timed(c, f32 ? CHNS_KERNEL_CHEB32 : CHNS_KERNEL_CHEB64, bytes, s, [&](LaunchEv ev) {
     stencil<T, T>(L.d, Sel<T>::v(A), ST_CHEB, x, b, Sel<T>::d(A), d, c1, c2, y, s, ev);
   });
@@ -633,10 +648,10 @@ ChebCoef<T> cut_coef(chns_ctx* c, OpVals Level::*op, size_t l, const chns_solve_
     // cells on the periodic square, 2 n_l on the closed one (Neumann)
     lo = 0.9 * (1.0 - std::cos((c->box ? 1.0 : 2.0) * M_PI / nl)) / 2.0;
   } else {
-    lo = 0.45 / (1.0 + 8.0 * cf[1] * ih * ih / cf[0]);
+    lo = 0.45 / (1.0 + c->diag_ratio * cf[1] * ih * ih / cf[0]);
   }
   const int steps = (l > 0) ? o.mg_coarse : o.mg_pre + o.mg_post;
-  return cheb_coef<T>(lo, o.mg_lmax, std::min(steps, MAXCHEB));
+  return cheb_coef<T>(lo, lmax_of(c, o), std::min(steps, MAXCHEB));
 }
 
 template <typename T>
@@ -678,8 +693,8 @@ bool vcycle_tail(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
   a.x = x;
   a.pre = o.mg_pre;
   a.post = o.mg_post;
-  const ChebCoef<T> pre = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre);
-  const ChebCoef<T> post = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post);
+  const ChebCoef<T> pre = cheb_coef<T>(lmax_of(c, o) / 4.0, lmax_of(c, o), o.mg_pre);
+  const ChebCoef<T> post = cheb_coef<T>(lmax_of(c, o) / 4.0, lmax_of(c, o), o.mg_post);
   for (int k = 0; k < o.mg_pre; ++k) {
     a.pre_c1[k] = pre.c1[k];
     a.pre_c2[k] = pre.c2[k];
@@ -735,7 +750,7 @@ bool vcycle_pair(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
   a.dinvc = Sel<T>::d(AG);
   a.bc = Sel<T>::b(G);
   a.xc = Sel<T>::t(G);
-  const ChebCoef<T> pre = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre);
+  const ChebCoef<T> pre = cheb_coef<T>(lmax_of(c, o) / 4.0, lmax_of(c, o), o.mg_pre);
   a.steps = o.mg_pre;
   for (int k = 0; k < o.mg_pre; ++k) {
     a.c1[k] = pre.c1[k];
@@ -752,7 +767,7 @@ bool vcycle_pair(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* 
     cut_in_up = tile2_cut_fits(side, o.mg_post, cc.steps);
   }
   if (!cut_in_up) vcycle<T>(c, op, l + 2, cut, Sel<T>::b(GG), Sel<T>::x(GG), o, s);
-  const ChebCoef<T> post = cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post);
+  const ChebCoef<T> post = cheb_coef<T>(lmax_of(c, o) / 4.0, lmax_of(c, o), o.mg_post);
   a.steps = o.mg_post;
   for (int k = 0; k < o.mg_post; ++k) {
     a.c1[k] = post.c1[k];
@@ -782,7 +797,7 @@ void vcycle(chns_ctx* c, OpVals Level::*op, size_t l, size_t cut, const T* b, T*
             const chns_solve_opts& o, hipStream_t s) {
   Level& L = c->lv[l];
   const OpVals& A = L.*op;
-  const double lmax = o.mg_lmax;
+  const double lmax = lmax_of(c, o);
   if (vcycle_tail<T>(c, op, l, cut, b, x, o, s)) return;
   if (l == cut) {
     const ChebCoef<T> cc = cut_coef<T>(c, op, l, o);
@@ -1022,14 +1037,14 @@ void vcycle_top(chns_ctx* c, OpVals Level::*op, size_t cut, const T* b, const do
   Level& L = c->lv[0];
   Level& G = c->lv[1];
   const OpVals& A = L.*op;
-  TileArgs<T> dn = tile_args<T>(L, A, o.mg_pre, cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_pre));
+  TileArgs<T> dn = tile_args<T>(L, A, o.mg_pre, cheb_coef<T>(lmax_of(c, o) / 4.0, lmax_of(c, o), o.mg_pre));
   dn.b = b;
   dn.b64 = b64;
   dn.x = Sel<T>::t(L);
   dn.bc = Sel<T>::b(G);
   vtile_at<T>(c, TILE_DOWN, dn, true, s);
   vcycle<T>(c, op, 1, cut, Sel<T>::b(G), Sel<T>::x(G), o, s);
-  TileArgs<T> up = tile_args<T>(L, A, o.mg_post, cheb_coef<T>(o.mg_lmax / 4.0, o.mg_lmax, o.mg_post));
+  TileArgs<T> up = tile_args<T>(L, A, o.mg_post, cheb_coef<T>(lmax_of(c, o) / 4.0, lmax_of(c, o), o.mg_post));
   up.b = b;
   up.b64 = b64;
   up.xin = Sel<T>::t(L);
@@ -1546,9 +1561,49 @@ int build_ternary_tables(chns_ctx* c) {
   return CHNS_OK;
 }
 
+// The periodic cube: P1 levels n, n/2, ... (Kuhn tetrahedra, width-15 rows,
+// stored columns), nested prolongation, Galerkin maps; the finest level's
+// element tables (types and the 16 SELL slots of each tetrahedron, colour by
+// colour) for the assembly.
+int build_cube_levels(chns_ctx* c) {
+  const int n = c->mesh.n;
+  c->N = n * n * n;
+  std::vector<int> sizes{n};
+  while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 4) sizes.push_back(sizes.back() / 2);
+  c->lv.resize(sizes.size());
+  for (size_t l = 0; l < sizes.size(); ++l) {
+    Level& L = c->lv[l];
+    L.n = sizes[l];
+    L.N = L.n * L.n * L.n;
+    Tets T = make_tets(L.n);
+    L.csr = pattern_from_elements(L.N, L.N, T.ne, T.v.data(), 4, T.v.data(), 4);
+    L.sell = make_sell(L.csr, 64, 1);
+    if (!L.sell.uniform || L.sell.width_max != 15)
+      return fail(c, CHNS_EINVAL, "P1 pattern of the cube is not the uniform 15-point stencil");
+    TRY(upload_sell(c, L.sell, L.d));
+    TRY(upload(c, &L.diag, L.sell.diag));
+    if (l == 0) {
+      std::vector<int> slot(size_t(T.ne) * 16);
+      for (int e = 0; e < T.ne; ++e)
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) {
+            const int q = L.csr.find(T.v[size_t(e) * 4 + a], T.v[size_t(e) * 4 + b]);
+            if (q < 0) return fail(c, CHNS_EINVAL, "tetrahedron edge missing from the pattern");
+            slot[size_t(e) * 16 + a * 4 + b] = L.sell.csr2sell[q];
+          }
+      TRY(upload(c, &c->etype, T.type));
+      TRY(upload(c, &c->eslot, slot));
+      std::copy(T.colour_ptr, T.colour_ptr + 49, c->colour_ptr3);
+    }
+  }
+  return CHNS_OK;
+}
+
 int build(chns_ctx* c) {
   const int n = c->mesh.n;
   const bool box = c->box;
+  if (c->dim3) TRY(build_cube_levels(c));
+  else {
   // P1 nodes: n^2 on the periodic square, (n+1)^2 on the closed one
   auto nodes = [box](int m) { return box ? (m + 1) * (m + 1) : m * m; };
   c->N = nodes(n);
@@ -1582,10 +1637,12 @@ int build(chns_ctx* c) {
       TRY(upload(c, &c->eslot, slot));
     }
   }
+  }
   for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
     Level& F = c->lv[l];
     Level& G = c->lv[l + 1];
-    p1_prolongation(F.n, F.Pcsr, F.Pval, box);
+    if (c->dim3) p1_prolongation3(F.n, F.Pcsr, F.Pval);
+    else p1_prolongation(F.n, F.Pcsr, F.Pval, box);
     csr_transpose(F.Pcsr, F.Pval, F.Rcsr, F.Rval);
     F.Psell = make_sell(F.Pcsr, 64, 1);
     F.Rsell = make_sell(F.Rcsr, 64, 1);
@@ -2173,6 +2230,16 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     g_create_err = "length must be finite and > 0 (0 for 1)";
     return CHNS_EINVAL;
   }
+  if (mesh->dim != 0 && mesh->dim != 2 && mesh->dim != 3) {
+    g_create_err = "dim must be 2 or 3 (0 for 2)";
+    return CHNS_EINVAL;
+  }
+  if (mesh->dim == 3) {
+    if (mesh->boundary != CHNS_BOUNDARY_PERIODIC || mesh->model > CHNS_MODEL_CH_AC || mesh->n > 128) {
+      g_create_err = "the cube takes the periodic boundary, the binary models and n <= 128";
+      return CHNS_EINVAL;
+    }
+  }
   chns_ctx tmp;
   if (check_params(&tmp, params) != CHNS_OK) {
     g_create_err = tmp.err;
@@ -2195,6 +2262,8 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
   c->box = mesh->boundary == CHNS_BOUNDARY_NOFLUX;
   c->len = mesh->length > 0.0 ? mesh->length : 1.0;
   c->h = c->len / mesh->n;
+  c->dim3 = mesh->dim == 3;
+  c->diag_ratio = c->dim3 ? 15.0 : 8.0;
   int rc = CHNS_OK;
   if (hipGetDevice(&c->device) != hipSuccess) {
     c->err = "hipGetDevice failed";

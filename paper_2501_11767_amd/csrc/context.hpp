@@ -147,6 +147,8 @@ struct chns_ctx {
   bool box = false;     // closed square (no-flux boundaries) instead of the periodic one
   double len = 1.0;     // side of the square
   double h = 0.0;       // finest mesh width len / n
+  bool dim3 = false;    // the periodic cube (Kuhn tetrahedra, binary models)
+  double diag_ratio = 8.0;  // diag(K) h^2 / diag(M): 8 on triangles, 15 on the tetrahedra
   bool has_conv = false;
   bool c_zero = true;   // C and C32 hold zeros on every level
   bool formed_c0 = false;  // the formed operators (L, X, AC) are those of the current
@@ -165,6 +167,7 @@ struct chns_ctx {
   std::vector<chns::Level> lv;
   chns::Elements el;
   int *ep1 = nullptr, *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;
+  int colour_ptr3[49] = {0};  // the cube: colour ranges of the tetrahedra (48 colours)
   chns::Krylov kr;
   // differentiation form: operators hold the transposed convection parts;
   // slot maps of the transposed entries (finest P1 and P2 patterns)

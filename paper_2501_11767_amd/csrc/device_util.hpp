@@ -105,6 +105,18 @@ __device__ __forceinline__ void row_cols7(int row, int side, const int* __restri
   }
 }
 
+// Columns of a row of a uniform width-W pattern: width 7 (triangles; computed
+// on the periodic square), width 15 (tetrahedra; always loaded).
+template <int W>
+__device__ __forceinline__ void row_cols(int row, int side, const int* __restrict__ col, size_t base, int* c) {
+  if constexpr (W == 7) {
+    row_cols7(row, side, col, base, c);
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) c[k] = col[base + k * 64];
+  }
+}
+
 struct ElemGeo {
   double area;
   double gx[3], gy[3];

@@ -53,6 +53,75 @@ Elements make_elements(int n, bool box) {
   return E;
 }
 
+Tets make_tets(int n) {
+  Tets T;
+  T.n = n;
+  T.ne = 6 * n * n * n;
+  auto id = [n](int i, int j, int k) {
+    return ((i % n + n) % n) + n * ((j % n + n) % n) + n * n * ((k % n + n) % n);
+  };
+  T.v.reserve(size_t(T.ne) * 4);
+  T.type.reserve(T.ne);
+  int count = 0;
+  for (int colour = 0; colour < 48; ++colour) {
+    T.colour_ptr[colour] = count;
+    const int pi = colour & 1, pj = (colour >> 1) & 1, pk = (colour >> 2) & 1, ty = colour >> 3;
+    for (int k = pk; k < n; k += 2)
+      for (int j = pj; j < n; j += 2)
+        for (int i = pi; i < n; i += 2) {
+          int o[3] = {i, j, k};
+          T.v.push_back(id(o[0], o[1], o[2]));
+          for (int s = 0; s < 3; ++s) {
+            ++o[KUHN_ORDER[ty][s]];
+            T.v.push_back(id(o[0], o[1], o[2]));
+          }
+          T.type.push_back(ty);
+          ++count;
+        }
+  }
+  T.colour_ptr[48] = count;
+  return T;
+}
+
+void p1_prolongation3(int nf, Csr& P, std::vector<double>& val) {
+  const int nc = nf / 2;
+  auto fid = [nf](int i, int j, int k) {
+    return ((i % nf + nf) % nf) + nf * ((j % nf + nf) % nf) + nf * nf * ((k % nf + nf) % nf);
+  };
+  auto cid = [nc](int i, int j, int k) {
+    return ((i % nc + nc) % nc) + nc * ((j % nc + nc) % nc) + nc * nc * ((k % nc + nc) % nc);
+  };
+  const int64_t Nf = int64_t(nf) * nf * nf;
+  std::vector<std::vector<std::pair<int, double>>> rows(Nf);
+  for (int K = 0; K < nc; ++K)
+    for (int J = 0; J < nc; ++J)
+      for (int I = 0; I < nc; ++I)
+        for (int d = 0; d < 8; ++d) {
+          const int a = d & 1, b = (d >> 1) & 1, c = (d >> 2) & 1;
+          auto& row = rows[fid(2 * I + a, 2 * J + b, 2 * K + c)];
+          if (d == 0) {
+            row.push_back({cid(I, J, K), 1.0});
+          } else {
+            row.push_back({cid(I, J, K), 0.5});
+            row.push_back({cid(I + a, J + b, K + c), 0.5});
+          }
+        }
+  P.nrows = int(Nf);
+  P.ncols = nc * nc * nc;
+  P.rowptr.assign(P.nrows + 1, 0);
+  P.col.clear();
+  val.clear();
+  for (int r = 0; r < P.nrows; ++r) {
+    auto& row = rows[r];
+    std::sort(row.begin(), row.end());
+    for (auto& e : row) {
+      P.col.push_back(e.first);
+      val.push_back(e.second);
+    }
+    P.rowptr[r + 1] = int(P.col.size());
+  }
+}
+
 Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, const int* cn,
                           int nc) {
   std::vector<std::vector<int>> rows(nrows);

@@ -59,6 +59,25 @@ struct Elements {
 
 Elements make_elements(int n, bool box = false);
 
+// Periodic unit cube with n cells per side (n even): vertex (i, j, k) has id
+// i + n j + n^2 k; each cell is split into the six Kuhn tetrahedra sharing its
+// main diagonal, type t taking the axes in the order KUHN_ORDER[t]: vertices
+// v0, v0 + e_a, v0 + e_a + e_b, v0 + (1, 1, 1).  48 colours,
+// (i mod 2) + 2 (j mod 2) + 4 (k mod 2) + 8 type: no two tetrahedra of a colour
+// share a vertex.
+constexpr int KUHN_ORDER[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+struct Tets {
+  int n = 0, ne = 0;
+  std::vector<int> v;     // ne*4 vertex ids, colour-sorted
+  std::vector<int> type;  // 0..5
+  int colour_ptr[49] = {0};
+};
+Tets make_tets(int n);
+// Nested P1 prolongation on the periodic cube from n/2 to n: coarse vertex
+// (I, J, K) at fine (2I, 2J, 2K); the other fine vertices are midpoints of
+// the coarse edges in the directions (a, b, c) in {0, 1}^3 (values 1 or 1/2).
+void p1_prolongation3(int nf, Csr& P, std::vector<double>& val);
+
 // Node-pair pattern of an element list: rows from `rn` (per element nr ids),
 // columns from `cn` (nc ids), sorted, duplicates merged.
 Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, const int* cn,

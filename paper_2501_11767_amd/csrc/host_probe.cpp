@@ -47,9 +47,97 @@ int probe_galerkin(int nf, bool box, const double* fine_csr, double* coarse_csr)
   return 0;
 }
 
+Csr cube_pattern(const Tets& T) {
+  const int N = T.n * T.n * T.n;
+  return pattern_from_elements(N, N, T.ne, T.v.data(), 4, T.v.data(), 4);
+}
+
 }  // namespace
 
 extern "C" {
+
+// The periodic cube: tetrahedra in colour order (v[ne*4], type[ne],
+// colour_ptr[49]); returns ne.
+__attribute__((visibility("default"))) int chns_probe_cube_tets(int n, int32_t* v, int32_t* type,
+                                                                int32_t* colour_ptr) {
+  Tets T = make_tets(n);
+  copy_out(T.v, v);
+  copy_out(T.type, type);
+  if (colour_ptr) std::memcpy(colour_ptr, T.colour_ptr, sizeof(T.colour_ptr));
+  return T.ne;
+}
+
+// Its P1 pattern (CSR; returns nnz) and SELL-C-64 layout as the library
+// builds it: sell_col[slots], csr2sell[nnz], diag[N], flags (uniform, width,
+// slots), and the 16 SELL slots of each tetrahedron (eslot[ne*16], -1 for a
+// pair missing from the pattern).
+__attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int32_t* rowptr, int32_t* col,
+                                                                  int32_t* sell_col, int32_t* csr2sell,
+                                                                  int32_t* diag, int32_t* flags,
+                                                                  int32_t* eslot) {
+  Tets T = make_tets(n);
+  Csr A = cube_pattern(T);
+  Sell S = make_sell(A, 64, 1);
+  copy_out(A.rowptr, rowptr);
+  copy_out(A.col, col);
+  copy_out(S.col, sell_col);
+  copy_out(S.csr2sell, csr2sell);
+  copy_out(S.diag, diag);
+  if (flags) {
+    flags[0] = S.uniform;
+    flags[1] = S.width_max;
+    flags[2] = int(S.slots());
+  }
+  if (eslot)
+    for (int e = 0; e < T.ne; ++e)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const int q = A.find(T.v[size_t(e) * 4 + a], T.v[size_t(e) * 4 + b]);
+          eslot[size_t(e) * 16 + a * 4 + b] = q < 0 ? -1 : S.csr2sell[q];
+        }
+  return A.nnz();
+}
+
+// Nested prolongation n/2 -> n on the cube (returns nnz).
+__attribute__((visibility("default"))) int chns_probe_cube_prolongation(int nf, int32_t* rowptr, int32_t* col,
+                                                                        double* val) {
+  Csr P;
+  std::vector<double> Pv;
+  p1_prolongation3(nf, P, Pv);
+  copy_out(P.rowptr, rowptr);
+  copy_out(P.col, col);
+  if (val) std::memcpy(val, Pv.data(), Pv.size() * sizeof(double));
+  return int(P.nnz());
+}
+
+// Galerkin coarsening of fine CSR values on the cube through the library's
+// slot map: coarse CSR values; -1 when the map cannot be built, -2 when a
+// padding slot would receive a value, -3 when a source slot is out of range.
+__attribute__((visibility("default"))) int chns_probe_cube_galerkin(int nf, const double* fine_csr,
+                                                                    double* coarse_csr) {
+  Tets Tf = make_tets(nf), Tc = make_tets(nf / 2);
+  Csr Af = cube_pattern(Tf), Ac = cube_pattern(Tc);
+  Sell Sf = make_sell(Af, 64, 1), Sc = make_sell(Ac, 64, 1);
+  Csr P;
+  std::vector<double> Pv;
+  p1_prolongation3(nf, P, Pv);
+  std::string err;
+  GalerkinMap G = make_galerkin(Af, Sf, P, Pv, Ac, Sc, &err);
+  if (!err.empty()) return -1;
+  std::vector<double> fs(Sf.slots(), 0.0), cs(Sc.slots(), 0.0);
+  for (int64_t q = 0; q < Af.nnz(); ++q) fs[Sf.csr2sell[q]] = fine_csr[q];
+  for (int64_t s = 0; s < Sc.slots(); ++s)
+    for (int k = G.ptr[s]; k < G.ptr[s + 1]; ++k) {
+      if (G.src[k] < 0 || G.src[k] >= Sf.slots()) return -3;
+      cs[s] += G.w[k] * fs[G.src[k]];
+    }
+  for (int64_t q = 0; q < Ac.nnz(); ++q) coarse_csr[q] = cs[Sc.csr2sell[q]];
+  std::vector<char> used(Sc.slots(), 0);
+  for (int64_t q = 0; q < Ac.nnz(); ++q) used[Sc.csr2sell[q]] = 1;
+  for (int64_t s = 0; s < Sc.slots(); ++s)
+    if (!used[s] && G.ptr[s + 1] != G.ptr[s]) return -2;
+  return 0;
+}
 
 __attribute__((visibility("default"))) int64_t chns_probe_p1_nnz(int n) {
   Elements E = make_elements(n);

@@ -24,7 +24,8 @@ namespace chns {
 namespace {
 
 constexpr int BS = 256;   // workgroup size (4 wavefronts)
-constexpr int W7 = 7;     // width of every P1 row on the periodic mesh
+constexpr int W7 = 7;     // width of every P1 row on a triangle mesh
+constexpr int W15 = 15;   // width of every P1 row on the Kuhn tetrahedral mesh
 constexpr int MAXRED = 1024;
 
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
@@ -56,8 +57,8 @@ __global__ __launch_bounds__(BS) void k_spmv_sell(int nslices, int nrows, const 
 }
 
 // Uniform width-7 patterns (P1): identity permutation, slice s = rows 64s..64s+63.
-template <typename T, typename TV, int MODE>
-__global__ __launch_bounds__(BS) void k_stencil7(int nrows, int side, const int* __restrict__ col,
+template <typename T, typename TV, int MODE, int W>
+__global__ __launch_bounds__(BS) void k_stencil(int nrows, int side, const int* __restrict__ col,
                                                  const TV* __restrict__ val,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ b,
@@ -67,15 +68,15 @@ __global__ __launch_bounds__(BS) void k_stencil7(int nrows, int side, const int*
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * BS + threadIdx.x;
   if (row >= nrows) return;
-  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
-  int c[W7];
-  TV v[W7];
-  row_cols7(row, side, col, base, c);
+  const size_t base = size_t(row >> 6) * (64 * W) + (row & 63);
+  int c[W];
+  TV v[W];
+  row_cols<W>(row, side, col, base, c);
 #pragma unroll
-  for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
+  for (int k = 0; k < W; ++k) v[k] = val[base + k * 64];
   T sum = T(0);
 #pragma unroll
-  for (int k = 0; k < W7; ++k) sum += T(v[k]) * x[c[k]];
+  for (int k = 0; k < W; ++k) sum += T(v[k]) * x[c[k]];
   if (MODE == ST_SPMV) {  // p0 = alpha, p1 = beta
     y[row] = (p1 == T(0)) ? p0 * sum : p0 * sum + p1 * y[row];
   } else if (MODE == ST_RESID) {
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(BS) void k_cheb0(int n, const T* __restrict__ dinv,
 
 // Chebyshev steps from x = 0 on a level of at most 1024 rows: one workgroup,
 // one row per thread, the row kept in registers, x in LDS.
-template <typename T, typename TV>
+template <typename T, typename TV, int W>
 __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const int* __restrict__ col,
                                                       const TV* __restrict__ val,
                                                       const T* __restrict__ dinv,
@@ -188,14 +189,14 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const
   const int r = threadIdx.x;
   T* cur = xa;
   T* nxt = xb;
-  int c[W7];
-  TV v[W7];
+  int c[W];
+  TV v[W];
   T di = T(0), br = T(0), dd = T(0);
   if (r < nrows) {
-    const size_t base = size_t(r >> 6) * (64 * W7) + (r & 63);
-    row_cols7(r, side, col, base, c);
+    const size_t base = size_t(r >> 6) * (64 * W) + (r & 63);
+    row_cols<W>(r, side, col, base, c);
 #pragma unroll
-    for (int k = 0; k < W7; ++k) v[k] = val[base + k * 64];
+    for (int k = 0; k < W; ++k) v[k] = val[base + k * 64];
     di = dinv[r];
     br = b[r];
     dd = cc.c2[0] * (di * br);
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cheb(int nrows, int side, const
     if (r < nrows) {
       T sum = T(0);
 #pragma unroll
-      for (int k = 0; k < W7; ++k) sum += T(v[k]) * cur[c[k]];
+      for (int k = 0; k < W; ++k) sum += T(v[k]) * cur[c[k]];
       dd = cc.c1[s] * dd + cc.c2[s] * (di * (br - sum));
       nxt[r] = cur[r] + dd;
     }
@@ -1298,7 +1299,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_bvtail(const TailArgs<T>* __re
   vtail_body<T, RPT>(t, bbase, xbase);
 }
 
-template <typename T, typename TV, bool L_IS_M>
+template <typename T, typename TV, bool L_IS_M, int W>
 __global__ __launch_bounds__(BS) void k_ch_block(int n, int side, const int* __restrict__ col,
                                                  const TV* __restrict__ Lv,
                                                  const TV* __restrict__ Kv,
@@ -1308,21 +1309,21 @@ __global__ __launch_bounds__(BS) void k_ch_block(int n, int side, const int* __r
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * BS + threadIdx.x;
   if (row >= n) return;
-  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  const size_t base = size_t(row >> 6) * (64 * W) + (row & 63);
   const T* x1 = x;
   const T* x2 = x + n;
-  int c[W7];
-  TV kv[W7], mv[W7], lv[W7];
-  row_cols7(row, side, col, base, c);
+  int c[W];
+  TV kv[W], mv[W], lv[W];
+  row_cols<W>(row, side, col, base, c);
 #pragma unroll
-  for (int k = 0; k < W7; ++k) {
+  for (int k = 0; k < W; ++k) {
     kv[k] = Kv[base + k * 64];
     mv[k] = Mv[base + k * 64];
     if (!L_IS_M) lv[k] = Lv[base + k * 64];
   }
   T sl = T(0), sk1 = T(0), sk2 = T(0), sm = T(0);
 #pragma unroll
-  for (int k = 0; k < W7; ++k) {
+  for (int k = 0; k < W; ++k) {
     const T a = x1[c[k]], bb = x2[c[k]];
     sl += T(L_IS_M ? mv[k] : lv[k]) * a;
     sk1 += T(kv[k]) * a;
@@ -1448,7 +1449,7 @@ __device__ void form_coefs(int j, int m, const double* __restrict__ red, double*
 // with the dot pass of Arnoldi step j = KK < DG: w is written once and its dots
 // are taken from registers (the separate pass would read it back).  Slots as
 // k_dcgs_dots with LAST; partials per block, grid-stride over the nodes.
-template <int KK, bool L_IS_M>
+template <int KK, bool L_IS_M, int W>
 __global__ __launch_bounds__(BS) void k_ch_dots(int N, int side, const int* __restrict__ col,
                                                 const double* __restrict__ Lv, const double* __restrict__ Kv,
                                                 const double* __restrict__ Mv, double c12, double c22,
@@ -1469,12 +1470,12 @@ __global__ __launch_bounds__(BS) void k_ch_dots(int N, int side, const int* __re
   // mostly read through the same XCD's L2
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   for (int row = blk * BS + threadIdx.x; row < N; row += stride) {
-    const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
-    int c[W7];
-    row_cols7(row, side, col, base, c);
+    const size_t base = size_t(row >> 6) * (64 * W) + (row & 63);
+    int c[W];
+    row_cols<W>(row, side, col, base, c);
     double sl = 0.0, sk1 = 0.0, sk2 = 0.0, sm = 0.0;
 #pragma unroll
-    for (int k = 0; k < W7; ++k) {
+    for (int k = 0; k < W; ++k) {
       const double kv = Kv[base + k * 64], mv = Mv[base + k * 64];
       const double lv = L_IS_M ? mv : Lv[base + k * 64];
       const double a = z[c[k]], bb = z[N + c[k]];
@@ -1978,6 +1979,7 @@ __device__ __forceinline__ double density_binary(double phi, const double* Phi, 
 // Per row: the row sum of M (the nodal weight), the masses weight * u, the
 // gradient terms u (K u) of each phase and weight * density; per block the
 // five sums.
+template <int W>
 __global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restrict__ col,
                                              const double* __restrict__ Mv, const double* __restrict__ Kv,
                                              const double* __restrict__ p0, const double* __restrict__ p1,
@@ -1988,13 +1990,13 @@ __global__ __launch_bounds__(BS) void k_diag(int n, int side, const int* __restr
   double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int stride = gridDim.x * BS;
   for (int row = blockIdx.x * BS + threadIdx.x; row < n; row += stride) {
-    const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
-    int c[W7];
-    row_cols7(row, side, col, base, c);
+    const size_t base = size_t(row >> 6) * (64 * W) + (row & 63);
+    int c[W];
+    row_cols<W>(row, side, col, base, c);
     // K-weighted sums of the phases and of the eliminated one
     double w = 0.0, k0 = 0.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
 #pragma unroll
-    for (int k = 0; k < W7; ++k) {
+    for (int k = 0; k < W; ++k) {
       const double kv = Kv[base + k * 64], a = p0[c[k]];
       w += Mv[base + k * 64];
       k0 += kv * a;
@@ -2063,6 +2065,7 @@ __device__ __forceinline__ void binary_terms(double phi, const double* Phi, int 
   fv = 6.0 * P * (1.0 - P) * (fgas - fliq);
 }
 
+template <int W>
 __global__ __launch_bounds__(BS) void k_rhs_binary(int n, int side, const int* __restrict__ col,
                                                    const double* __restrict__ Mv,
                                                    const double* __restrict__ phi,
@@ -2072,12 +2075,12 @@ __global__ __launch_bounds__(BS) void k_rhs_binary(int n, int side, const int* _
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * BS + threadIdx.x;
   if (row >= n) return;
-  const size_t base = size_t(row >> 6) * (64 * W7) + (row & 63);
+  const size_t base = size_t(row >> 6) * (64 * W) + (row & 63);
   double s_phi = 0.0, s_fp = 0.0, s_Phi = 0.0, s_fv = 0.0;
-  int cc[W7];
-  row_cols7(row, side, col, base, cc);
+  int cc[W];
+  row_cols<W>(row, side, col, base, cc);
 #pragma unroll
-  for (int k = 0; k < W7; ++k) {
+  for (int k = 0; k < W; ++k) {
     const int j = cc[k];
     const double m = Mv[base + k * 64];
     const double ph = phi[j];
@@ -2486,7 +2489,11 @@ __global__ __launch_bounds__(BS) void k_axpy_into(int64_t n, double a, const dou
 template <typename T, typename TV>
 void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipStream_t s) {
   if (A.uniform && A.width == W7) {
-    hipLaunchKernelGGL((k_stencil7<T, TV, ST_SPMV>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
+    hipLaunchKernelGGL((k_stencil<T, TV, ST_SPMV, W7>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
+                       A.nrows, A.side, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       alpha, beta, y);
+  } else if (A.uniform && A.width == W15) {
+    hipLaunchKernelGGL((k_stencil<T, TV, ST_SPMV, W15>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
                        A.nrows, A.side, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
                        alpha, beta, y);
   } else {
@@ -2501,11 +2508,20 @@ template <typename T, typename TV>
 void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, const T* dinv, T* d,
              T c1, T c2, T* y, hipStream_t s, LaunchEv ev) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
+  if (A.width == W15) {
+    if (mode == ST_RESID)
+      LAUNCH_EV(ev, (k_stencil<T, TV, ST_RESID, W15>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+                d, c1, c2, y);
+    else
+      LAUNCH_EV(ev, (k_stencil<T, TV, ST_CHEB, W15>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+                d, c1, c2, y);
+    return;
+  }
   if (mode == ST_RESID)
-    LAUNCH_EV(ev, (k_stencil7<T, TV, ST_RESID>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+    LAUNCH_EV(ev, (k_stencil<T, TV, ST_RESID, W7>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
               d, c1, c2, y);
   else
-    LAUNCH_EV(ev, (k_stencil7<T, TV, ST_CHEB>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+    LAUNCH_EV(ev, (k_stencil<T, TV, ST_CHEB, W7>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
               d, c1, c2, y);
 }
 
@@ -2531,8 +2547,12 @@ void pcheb(const DSell& A, const TV* val, const T* x, const T* e, const T* b, co
 template <typename T, typename TV>
 void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const ChebCoef<T>& cc,
                  T* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_cheb<T, TV>), dim3(1), dim3(1024), 0, s, A.nrows, A.side, A.col, val, dinv,
-                     b, cc, x);
+  if (A.width == W15)
+    hipLaunchKernelGGL((k_coarse_cheb<T, TV, W15>), dim3(1), dim3(1024), 0, s, A.nrows, A.side, A.col, val,
+                       dinv, b, cc, x);
+  else
+    hipLaunchKernelGGL((k_coarse_cheb<T, TV, W7>), dim3(1), dim3(1024), 0, s, A.nrows, A.side, A.col, val,
+                       dinv, b, cc, x);
 }
 
 template <typename T>
@@ -2704,11 +2724,20 @@ template <typename T, typename TV>
 void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c22, const T* x,
               T alpha, T beta, T* y, hipStream_t s, LaunchEv ev, const T* yin) {
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
+  if (A.width == W15) {
+    if (L == M)
+      LAUNCH_EV(ev, (k_ch_block<T, TV, true, W15>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
+                x, alpha, beta, y, yin);
+    else
+      LAUNCH_EV(ev, (k_ch_block<T, TV, false, W15>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
+                x, alpha, beta, y, yin);
+    return;
+  }
   if (L == M)
-    LAUNCH_EV(ev, (k_ch_block<T, TV, true>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
+    LAUNCH_EV(ev, (k_ch_block<T, TV, true, W7>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
               alpha, beta, y, yin);
   else
-    LAUNCH_EV(ev, (k_ch_block<T, TV, false>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
+    LAUNCH_EV(ev, (k_ch_block<T, TV, false, W7>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22, x,
               alpha, beta, y, yin);
 }
 
@@ -2774,7 +2803,7 @@ void dcgs_dots(int64_t n, const double* V, int64_t ld, int j, const DcgsState& s
   hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(n), st.part, st.red);
 }
 
-template <bool LM>
+template <bool LM, int W>
 static void launch_ch_dots(int j, int N, const DSell& A, const double* Lv, const double* Kv, const double* Mv,
                            double c12, double c22, const double* z, double* V, int64_t ld, const DcgsState& st,
                            hipStream_t s, LaunchEv ev) {
@@ -2782,7 +2811,7 @@ static void launch_ch_dots(int j, int N, const DSell& A, const double* Lv, const
   switch (j) {
 #define CHNS_CHD_CASE(K)                                                                                 \
   case K:                                                                                                 \
-    LAUNCH_EV(ev, (k_ch_dots<K, LM>), g, b, 0, s, N, A.side, A.col, Lv, Kv, Mv, c12, c22, z, V, ld, st.part, \
+    LAUNCH_EV(ev, (k_ch_dots<K, LM, W>), g, b, 0, s, N, A.side, A.col, Lv, Kv, Mv, c12, c22, z, V, ld, st.part, \
               st.vscale);                                                                                 \
     break;
     CHNS_CHD_CASE(0) CHNS_CHD_CASE(1) CHNS_CHD_CASE(2) CHNS_CHD_CASE(3) CHNS_CHD_CASE(4) CHNS_CHD_CASE(5)
@@ -2798,8 +2827,13 @@ bool ch_dots_fits(int j) { return j >= 0 && j < DG; }
 void ch_dcgs_dots(const DSell& A, const double* Lv, const double* Kv, const double* Mv, double c12, double c22,
                   const double* z, double* V, int64_t ld, int j, const DcgsState& st, hipStream_t s, LaunchEv ev) {
   const int N = A.nrows;
-  if (Lv == Mv) launch_ch_dots<true>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
-  else launch_ch_dots<false>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+  if (A.width == W15) {
+    if (Lv == Mv) launch_ch_dots<true, W15>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+    else launch_ch_dots<false, W15>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+  } else {
+    if (Lv == Mv) launch_ch_dots<true, W7>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+    else launch_ch_dots<false, W7>(j, N, A, Lv, Kv, Mv, c12, c22, z, V, ld, st, s, ev);
+  }
   hipLaunchKernelGGL(k_slot_reduce, dim3(2 * j + 3), dim3(BS), 0, s, dcgs_dot_blocks(2 * int64_t(N)), st.part,
                      st.red);
 }
@@ -2828,6 +2862,63 @@ void norm_partial(int64_t n, const double* w, double* part, hipStream_t s) {
 void norm_finish(int nblk, const double* part, double* scal, double* g, int m, hipStream_t s, double* host,
                  double tag) {
   hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, nblk, part, scal, g, m, host, tag);
+}
+
+// Kuhn tetrahedron of type t: vertices 0, h e_a, h (e_a + e_b), h (1, 1, 1)
+// with (a, b, c) the t-th ordering of the axes; its barycentric gradients are
+// the rows of the inverse of the edge matrix [v1 v2 v3] (columns), the first
+// one minus their sum.
+__global__ __launch_bounds__(BS) void k_assemble_p1_tet(int kind, int e0, int e1,
+                                                        const int* __restrict__ etype,
+                                                        const int* __restrict__ eslot16, double h,
+                                                        double* __restrict__ val) {
+  const int e = e0 + blockIdx.x * BS + threadIdx.x;
+  if (e >= e1) return;
+  constexpr int ORD[6][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 2}, {2, 0}, {2, 1}};
+  const int t = etype[e], a = ORD[t][0], b = ORD[t][1];
+  double E[3][3];  // E[r][c]: component r of edge vector c
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    E[r][0] = r == a ? h : 0.0;
+    E[r][1] = (r == a || r == b) ? h : 0.0;
+    E[r][2] = h;
+  }
+  const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                     E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                     E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+  const double vol = fabs(det) / 6.0;
+  double loc[16];
+  if (kind == 0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) loc[p * 4 + q] = vol / 20.0 * (p == q ? 2.0 : 1.0);
+  } else {
+    // rows of E^{-1}: the cofactors of E transposed, over det
+    double g[4][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+        g[r + 1][c] = (E[r1][c1] * E[r2][c2] - E[r1][c2] * E[r2][c1]) / det;
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) loc[p * 4 + q] = vol * (g[p][0] * g[q][0] + g[p][1] * g[q][1] + g[p][2] * g[q][2]);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) val[eslot16[int64_t(e) * 16 + q]] += loc[q];
+}
+
+void assemble_p1_tet(int kind, int e0, int e1, const int* etype, const int* eslot16, double h, double* val,
+                     hipStream_t s) {
+  if (e1 <= e0) return;
+  hipLaunchKernelGGL(k_assemble_p1_tet, dim3(ceil_div(e1 - e0, BS)), dim3(BS), 0, s, kind, e0, e1, etype,
+                     eslot16, h, val);
 }
 
 void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, const int* eslot,
@@ -2866,8 +2957,12 @@ void diagnostics(const DSell& A, const double* M, const double* K, const double*
                  const double* p2, const double* Phi, bool ternary, const KorBeta& kb, const PotCoef& pc,
                  double* part, double* out, hipStream_t s) {
   const int nblk = reduce_blocks(A.nrows);
-  hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, p2, Phi,
-                     ternary ? 1 : 0, kb, pc, part);
+  if (A.width == W15)
+    hipLaunchKernelGGL(k_diag<W15>, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, p2, Phi,
+                       ternary ? 1 : 0, kb, pc, part);
+  else
+    hipLaunchKernelGGL(k_diag<W7>, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, p2, Phi,
+                       ternary ? 1 : 0, kb, pc, part);
   hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(BS), 0, s, nblk, part, out);
 }
 
@@ -2894,8 +2989,12 @@ void rhs_quaternary(const DSell& A, const double* Mv, const double* php, const d
 
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,
                 double c_ac, const TopFlux& tf, double* rhs_ch, double* rhs_ac, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_binary, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col, Mv,
-                     phi, Phi, c_mu, c_ac, tf, rhs_ch, rhs_ac);
+  if (A.width == W15)
+    hipLaunchKernelGGL(k_rhs_binary<W15>, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col,
+                       Mv, phi, Phi, c_mu, c_ac, tf, rhs_ch, rhs_ac);
+  else
+    hipLaunchKernelGGL(k_rhs_binary<W7>, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col,
+                       Mv, phi, Phi, c_mu, c_ac, tf, rhs_ch, rhs_ac);
 }
 
 template <typename T, typename TV>

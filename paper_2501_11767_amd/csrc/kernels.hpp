@@ -328,6 +328,11 @@ void assemble_p1(int kind, int e0, int e1, const int* ep2, const int* etype, con
                  double h, const double* vel, int64_t n2, double* val, hipStream_t s,
                  const double* rho = nullptr);
 
+// P1 on the periodic Kuhn tetrahedral mesh, one colour [e0, e1): kind 0 mass
+// (|T| (1 + delta_ab) / 20), 1 stiffness; eslot16: 16 SELL slots per element.
+void assemble_p1_tet(int kind, int e0, int e1, const int* etype, const int* eslot16, double h, double* val,
+                     hipStream_t s);
+
 // coarse[s] = sum_k w_k fine[src_k] over the Galerkin map.
 void galerkin(int64_t nslots, const int* ptr, const int* src, const double* w, const double* fine,
               double* coarse, hipStream_t s);

@@ -164,6 +164,25 @@ def box_state(n: int, length: float, model: str, mean: float, seed: int, film: f
     return dict(phi=phi, Phi_v=Phi_v, vel=vel, p=np.zeros(y.size))
 
 
+def cube_vertex_coords(n: int, length: float = 1.0) -> np.ndarray:
+    """(n^3, 3) coordinates of the periodic cube's vertices, id i + n j + n^2 k."""
+    k, j, i = np.unravel_index(np.arange(n ** 3), (n, n, n))
+    return np.stack([i, j, k], 1) * (length / n)
+
+
+def cube_state(n: int, model: str, mean: float, seed: int, length: float = 1.0):
+    """Initial fields of the binary models on the periodic cube: the phase at
+    mean + U(-0.01, 0.01) at every vertex; the vapour field (CH + AC) a layer
+    sin^2(pi z / L), liquid at z = 0 and vapour at z = L/2.  Keys as
+    initial_state."""
+    if model not in ("ch", "ch_ac"):
+        raise ValueError(model)
+    phi = mean + 0.01 * rng(seed).uniform(-1.0, 1.0, size=n ** 3)
+    z = cube_vertex_coords(n, length)[:, 2]
+    Phi_v = np.sin(np.pi * z / length) ** 2 if model == "ch_ac" else None
+    return dict(phi=[phi], Phi_v=Phi_v, vel=None, p=None)
+
+
 def log_uniform(g: np.random.Generator, lo: float, hi: float) -> float:
     return float(np.exp(g.uniform(np.log(lo), np.log(hi))))
 
@@ -203,6 +222,12 @@ CONFIGS = {
     "quadbox": dict(n=64, length=10.0, model="quaternary", eps=1.0, tau=1e-4, mobility=1.0, evap_rate=1.0,
                     viscosity=1.0, alpha=1e-8, betas=(1e-3, 1e-3, 1e-1, 1.0), steps=1, mean=0.33,
                     seed=BASE_SEED + 7),
+    # the paper's three-dimensional runs on a uniform 40 x 40 x 40 grid (section
+    # "Numerical results", tau = 1e-4), here for the binary CH + AC model on the
+    # periodic unit cube (Kuhn tetrahedra; levels 40, 20, 10, 5), a film mean of
+    # 0.4, eps = 0.05 (2 cells of the mesh); 128 cells per side as the larger size
+    "cube40": dict(n=40, model="ch_ac", eps=0.05, tau=1e-4, mobility=1.0, evap_rate=0.1,
+                   viscosity=1.0, steps=1, mean=0.4, seed=BASE_SEED + 8, sizes=(40, 64, 128)),
     "batch64": dict(instances=64, sizes=(64, 128, 256, 512), seed=BASE_SEED + 3),
     # Differentiation workload.  With the explicit potential the ternary run on
     # this mesh diverges within 6 steps at tau = 1e-3, 8 at 1e-4 and 17 at 1e-5

@@ -52,11 +52,29 @@ def test_create_rejects_bad_mesh(L, n, model):
 def test_create_rejects_bad_domain(L, boundary, length, model, code):
     """Unknown boundary and a side that is not finite and positive."""
     h = ct.c_void_p()
-    rc = L.chns_create(ct.byref(chns.Mesh(16, model, boundary, length)),
+    rc = L.chns_create(ct.byref(chns.Mesh(n=16, model=model, boundary=boundary, length=length)),
                        ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)), chns.ALLOC_FN(), chns.FREE_FN(), None,
                        ct.byref(h))
     assert rc == code and not h.value
     assert len(L.chns_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("dim,n,model,boundary", [(4, 16, 0, 0), (-1, 16, 0, 0), (3, 16, 2, 0), (3, 16, 3, 0),
+                                                   (3, 16, 1, 1), (3, 130, 1, 0), (3, 6, 0, 0)])
+def test_create_rejects_bad_cube(L, dim, n, model, boundary):
+    """The cube takes dim 3 with the periodic boundary, the binary models and
+    8 <= n <= 128 (checked before any device call)."""
+    h = ct.c_void_p()
+    rc = L.chns_create(ct.byref(chns.Mesh(n=n, model=model, boundary=boundary, dim=dim)),
+                       ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)), chns.ALLOC_FN(), chns.FREE_FN(), None,
+                       ct.byref(h))
+    assert rc == chns.EINVAL and not h.value
+    assert len(L.chns_last_error(None)) > 0
+
+
+def test_mesh_struct_layout():
+    """chns_mesh: n, model, boundary, dim (int32), then length (double) at byte 16."""
+    assert ct.sizeof(chns.Mesh) == 24 and chns.Mesh.length.offset == 16 and chns.Mesh.dim.offset == 12
 
 
 QB = (2e-4, 2e-4, 1e-3, 4e-3)
@@ -74,7 +92,7 @@ def test_create_rejects_model_parameters(L, model, boundary, kw, code):
     h = ct.c_void_p()
     p = chns.Params(**dict(dict(eps=0.05, tau=1e-4, mobility=1.0, evap_rate=0.5, viscosity=1.0,
                                 alpha=1e-3, rho=1.0), **kw))
-    rc = L.chns_create(ct.byref(chns.Mesh(16, model, boundary, 1.0)), ct.byref(p), chns.ALLOC_FN(),
+    rc = L.chns_create(ct.byref(chns.Mesh(n=16, model=model, boundary=boundary, length=1.0)), ct.byref(p), chns.ALLOC_FN(),
                        chns.FREE_FN(), None, ct.byref(h))
     assert rc == code and not h.value
     assert len(L.chns_last_error(None)) > 0
@@ -86,7 +104,7 @@ def test_create_rejects_bad_top_flux(L, boundary, flux, inf):
     h = ct.c_void_p()
     p = chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)
     p.top_flux, p.flux_inf = flux, inf
-    rc = L.chns_create(ct.byref(chns.Mesh(16, 1, boundary, 10.0)), ct.byref(p), chns.ALLOC_FN(),
+    rc = L.chns_create(ct.byref(chns.Mesh(n=16, model=1, boundary=boundary, length=10.0)), ct.byref(p), chns.ALLOC_FN(),
                        chns.FREE_FN(), None, ct.byref(h))
     assert rc == chns.EINVAL and not h.value
 
