@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--box-steps", type=int, default=5)
     ap.add_argument("--quad-steps", type=int, default=5)
+    ap.add_argument("--cube-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64", help="timed forms of the 1024^2 step")
@@ -415,6 +416,54 @@ def box_section(chns, steps, restart):
                          f"eps^2 {cfg['eps'] ** 2:.3g}, tau {cfg['tau']}, mixed precision, FGMRES({restart}) "
                          f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid; per hierarchy cut threshold",
                 rho_cut=best, **by_cut[best], by_rho_cut={str(k): v for k, v in by_cut.items()}, steps=steps)
+
+
+def cube_section(chns, steps, restart):
+    """The paper's three-dimensional grid: the CH + AC step on the periodic
+    cube (Kuhn tetrahedra, 15-entry P1 rows) at 40 cells per side and the
+    larger sizes, mixed precision with the 1024^2 workload's solver options:
+    ms per step and FGMRES iterations per hierarchy cut threshold, each step
+    from the seeded state (mu^0 = 0, the Krylov initial guess)."""
+    import torch
+    from paper_2501_11767_amd import inputs
+    cfg = inputs.CONFIGS["cube40"]
+    p = {k: cfg[k] for k in ("eps", "tau", "mobility", "evap_rate")}
+    out = {}
+    for n in cfg["sizes"]:
+        t0 = time.perf_counter()
+        ctx = chns.Context(n, "ch_ac", dim=3, **p)
+        log(f"cube{n}: create {time.perf_counter() - t0:.1f} s")
+        st = inputs.cube_state(n, "ch_ac", cfg["mean"], cfg["seed"])
+        N = ctx.N
+        f = ctx.fields(phi=[dev(st["phi"][0])], mu=[torch.zeros(N, dtype=torch.float64, device="cuda")],
+                       Phi_v=dev(st["Phi_v"]))
+        e = lambda: torch.empty(N, dtype=torch.float64, device="cuda")
+        fo = ctx.fields(phi=[e()], mu=[e()], Phi_v=e())
+        by_cut = {}
+        for cut in BOX_RHO_CUTS:
+            opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=restart, **dict(MG, mg_rho_cut=cut))
+            ctx.timestep(f, fo, 1, opts)
+            torch.cuda.synchronize()
+            walls, its = [], []
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                rc, inf = ctx.timestep(f, fo, 1, opts)
+                torch.cuda.synchronize()
+                walls.append((time.perf_counter() - t0) * 1e3)
+                its.append([i["iters"] for i in inf])
+            by_cut[cut] = dict(ms_per_step=float(np.mean(walls)), ms_per_step_median=float(np.median(walls)),
+                               iters_ch_ac=its[-1])
+        ctx.close()
+        best = min(by_cut, key=lambda k: by_cut[k]["ms_per_step"])
+        b = by_cut[best]
+        out[str(n)] = dict(nodes=N, unknowns=3 * N, rho_cut=best, **b,
+                           dof_iters_per_s=3 * N * sum(b["iters_ch_ac"]) / (b["ms_per_step"] * 1e-3),
+                           by_rho_cut={str(k): v for k, v in by_cut.items()})
+    return dict(workload=f"cube40: CH + AC step on the periodic unit cube, Kuhn tetrahedra, "
+                         f"{cfg['sizes']} cells per side (40 is the paper's grid), phase at {cfg['mean']} +- 0.01, "
+                         f"vapour layer sin^2(pi z), eps {cfg['eps']}, tau {cfg['tau']}, mixed precision, "
+                         f"FGMRES({restart}) rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid; per size the "
+                         f"best hierarchy cut threshold", sizes=out, steps=steps)
 
 
 def batch_section(chns, steps):
@@ -842,6 +891,7 @@ def main():
     box = box_section(chns, args.box_steps, args.restart) if args.box_steps > 0 else None
     quad = quad_section(chns, args.quad_steps) if args.quad_steps > 0 else None
     qbox = quadbox_section(chns, args.quad_steps) if args.quad_steps > 0 else None
+    cube = cube_section(chns, args.cube_steps, args.restart) if args.cube_steps > 0 else None
     adj = None if args.no_adjoint else adjoint_section(chns)
     cpu = None
     if not args.no_cpu:
@@ -907,6 +957,7 @@ def main():
         "box10": box,
         "quad256": quad,
         "quadbox": qbox,
+        "cube40": cube,
         "adjoint128": adj,
     }
     ctx.close()

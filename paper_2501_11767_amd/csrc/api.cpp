@@ -124,6 +124,7 @@ int upload_sell(chns_ctx* c, const Sell& S, DSell& d) {
   d.width = S.width_max;
   d.uniform = S.uniform ? 1 : 0;
   d.side = S.side;
+  d.cube = S.cube;
   int *sp, *sw, *col, *perm;
   TRY(upload(c, &sp, S.slice_ptr));
   TRY(upload(c, &sw, S.slice_w));
@@ -1577,8 +1578,8 @@ int build_cube_levels(chns_ctx* c) {
     L.N = L.n * L.n * L.n;
     Tets T = make_tets(L.n);
     L.csr = pattern_from_elements(L.N, L.N, T.ne, T.v.data(), 4, T.v.data(), 4);
-    L.sell = make_sell(L.csr, 64, 1);
-    if (!L.sell.uniform || L.sell.width_max != 15)
+    L.sell = make_sell_p1_cube(L.csr, L.n);
+    if (!L.sell.uniform || L.sell.width_max != 15 || L.sell.cube != L.n)
       return fail(c, CHNS_EINVAL, "P1 pattern of the cube is not the uniform 15-point stencil");
     TRY(upload_sell(c, L.sell, L.d));
     TRY(upload(c, &L.diag, L.sell.diag));

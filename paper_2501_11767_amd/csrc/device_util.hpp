@@ -105,15 +105,49 @@ __device__ __forceinline__ void row_cols7(int row, int side, const int* __restri
   }
 }
 
+// Columns of a row of the periodic cube's 15-entry P1 pattern (side n,
+// vertex i + n j + n^2 k): the vertex, then the neighbours at -d and +d for
+// the edge directions (1,0,0), (0,1,0), (0,0,1), (1,1,0), (1,0,1), (0,1,1),
+// (1,1,1) in turn.
+__device__ __forceinline__ void p1_cols_cube(int row, int n, int* c) {
+  const int nn = n * n;
+  const int k = row / nn, rem = row - k * nn;
+  const int j = rem / n, i = rem - j * n;
+  const int x[3] = {i == 0 ? n - 1 : i - 1, i, i == n - 1 ? 0 : i + 1};
+  const int y[3] = {(j == 0 ? n - 1 : j - 1) * n, j * n, (j == n - 1 ? 0 : j + 1) * n};
+  const int z[3] = {(k == 0 ? n - 1 : k - 1) * nn, k * nn, (k == n - 1 ? 0 : k + 1) * nn};
+  c[0] = row;
+  c[1] = x[0] + y[1] + z[1];
+  c[2] = x[2] + y[1] + z[1];
+  c[3] = x[1] + y[0] + z[1];
+  c[4] = x[1] + y[2] + z[1];
+  c[5] = x[1] + y[1] + z[0];
+  c[6] = x[1] + y[1] + z[2];
+  c[7] = x[0] + y[0] + z[1];
+  c[8] = x[2] + y[2] + z[1];
+  c[9] = x[0] + y[1] + z[0];
+  c[10] = x[2] + y[1] + z[2];
+  c[11] = x[1] + y[0] + z[0];
+  c[12] = x[1] + y[2] + z[2];
+  c[13] = x[0] + y[0] + z[0];
+  c[14] = x[2] + y[2] + z[2];
+}
+
 // Columns of a row of a uniform width-W pattern: width 7 (triangles; computed
-// on the periodic square), width 15 (tetrahedra; always loaded).
+// on the periodic square, side > 0), width 15 (tetrahedra; computed on the
+// periodic cube, side > 0 its side); otherwise loaded.
 template <int W>
 __device__ __forceinline__ void row_cols(int row, int side, const int* __restrict__ col, size_t base, int* c) {
   if constexpr (W == 7) {
     row_cols7(row, side, col, base, c);
   } else {
+    static_assert(W == 15, "rows of 7 or 15 entries");
+    if (side > 0) {
+      p1_cols_cube(row, side, c);
+    } else {
 #pragma unroll
-    for (int k = 0; k < W; ++k) c[k] = col[base + k * 64];
+      for (int k = 0; k < W; ++k) c[k] = col[base + k * 64];
+    }
   }
 }
 

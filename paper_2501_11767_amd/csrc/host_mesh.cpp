@@ -122,6 +122,50 @@ void p1_prolongation3(int nf, Csr& P, std::vector<double>& val) {
   }
 }
 
+Sell make_sell_p1_cube(const Csr& A, int n) {
+  Sell S;
+  const int N = n * n * n;
+  constexpr int W = 15;
+  S.nrows = N;
+  S.ncols = N;
+  S.C = 64;
+  S.sigma = 1;
+  S.cube = n;
+  S.nslices = (N + 63) / 64;
+  S.width_max = W;
+  S.uniform = true;
+  S.perm.assign(size_t(S.nslices) * 64, -1);
+  for (int r = 0; r < N; ++r) S.perm[r] = r;
+  S.slice_ptr.resize(S.nslices + 1);
+  for (int s = 0; s <= S.nslices; ++s) S.slice_ptr[s] = s * 64 * W;
+  S.slice_w.assign(S.nslices, W);
+  S.col.assign(size_t(S.nslices) * 64 * W, 0);
+  S.csr2sell.assign(A.nnz(), -1);
+  S.diag.assign(N, -1);
+  auto wrap = [n](int a) { return ((a % n) + n) % n; };
+  auto neighbour = [&](int r, int k) {
+    const int i = r % n, j = (r / n) % n, l = r / (n * n);
+    if (k == 0) return r;
+    const int* d = CUBE_DIRS[(k - 1) / 2];
+    const int sg = (k % 2 == 1) ? -1 : 1;
+    return wrap(i + sg * d[0]) + n * wrap(j + sg * d[1]) + n * n * wrap(l + sg * d[2]);
+  };
+  for (int r = 0; r < S.nslices * 64; ++r)
+    for (int k = 0; k < W; ++k)  // padding lanes of a partial slice: column 0, value 0
+      S.col[size_t(r >> 6) * 64 * W + k * 64 + (r & 63)] = r < N ? neighbour(r, k) : 0;
+  for (int r = 0; r < N; ++r)
+    for (int q = A.rowptr[r]; q < A.rowptr[r + 1]; ++q) {
+      int k = -1;
+      for (int t = 0; t < W; ++t)
+        if (neighbour(r, t) == A.col[q]) k = t;
+      if (k < 0) return Sell{};  // not the 15-point stencil
+      const int slot = (r >> 6) * 64 * W + k * 64 + (r & 63);
+      S.csr2sell[q] = slot;
+      if (A.col[q] == r) S.diag[r] = slot;
+    }
+  return S;
+}
+
 Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, const int* cn,
                           int nc) {
   std::vector<std::vector<int>> rows(nrows);

@@ -44,6 +44,8 @@ struct Sell {
   std::vector<int> diag;         // per row: SELL slot of the diagonal entry (-1 if absent)
   int side = 0;                  // > 0: P1 pattern of the periodic side x side mesh stored in
                                  // the fixed neighbour order of p1_offset (columns computable)
+  int cube = 0;                  // > 0: P1 pattern of the periodic cube of this side in the
+                                 // neighbour order of CUBE_DIRS (columns computable)
   int64_t slots() const { return slice_ptr.empty() ? 0 : slice_ptr.back(); }
 };
 
@@ -66,6 +68,10 @@ Elements make_elements(int n, bool box = false);
 // (i mod 2) + 2 (j mod 2) + 4 (k mod 2) + 8 type: no two tetrahedra of a colour
 // share a vertex.
 constexpr int KUHN_ORDER[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+// Neighbour order of the cube's 15-entry P1 rows in the library's SELL
+// layout: the vertex itself, then for each edge direction d of
+// CUBE_DIRS the neighbours at -d and +d (entries 2m + 1 and 2m + 2).
+constexpr int CUBE_DIRS[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
 struct Tets {
   int n = 0, ne = 0;
   std::vector<int> v;     // ne*4 vertex ids, colour-sorted
@@ -77,6 +83,10 @@ Tets make_tets(int n);
 // (I, J, K) at fine (2I, 2J, 2K); the other fine vertices are midpoints of
 // the coarse edges in the directions (a, b, c) in {0, 1}^3 (values 1 or 1/2).
 void p1_prolongation3(int nf, Csr& P, std::vector<double>& val);
+// SELL-C-64 layout of the cube's P1 pattern with entry k of every row at the
+// fixed neighbour of the order above (columns computable from the row index:
+// Sell::cube = n); an empty Sell when the pattern is not that stencil.
+Sell make_sell_p1_cube(const Csr& A, int n);
 
 // Node-pair pattern of an element list: rows from `rn` (per element nr ids),
 // columns from `cn` (nc ids), sorted, duplicates merged.

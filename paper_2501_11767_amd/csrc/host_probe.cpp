@@ -69,7 +69,7 @@ __attribute__((visibility("default"))) int chns_probe_cube_tets(int n, int32_t* 
 
 // Its P1 pattern (CSR; returns nnz) and SELL-C-64 layout as the library
 // builds it: sell_col[slots], csr2sell[nnz], diag[N], flags (uniform, width,
-// slots), and the 16 SELL slots of each tetrahedron (eslot[ne*16], -1 for a
+// slots, side of the computed columns), and the 16 SELL slots of each tetrahedron (eslot[ne*16], -1 for a
 // pair missing from the pattern).
 __attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int32_t* rowptr, int32_t* col,
                                                                   int32_t* sell_col, int32_t* csr2sell,
@@ -77,7 +77,7 @@ __attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int32_t
                                                                   int32_t* eslot) {
   Tets T = make_tets(n);
   Csr A = cube_pattern(T);
-  Sell S = make_sell(A, 64, 1);
+  Sell S = make_sell_p1_cube(A, n);
   copy_out(A.rowptr, rowptr);
   copy_out(A.col, col);
   copy_out(S.col, sell_col);
@@ -87,6 +87,7 @@ __attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int32_t
     flags[0] = S.uniform;
     flags[1] = S.width_max;
     flags[2] = int(S.slots());
+    flags[3] = S.cube;
   }
   if (eslot)
     for (int e = 0; e < T.ne; ++e)
@@ -117,7 +118,7 @@ __attribute__((visibility("default"))) int chns_probe_cube_galerkin(int nf, cons
                                                                     double* coarse_csr) {
   Tets Tf = make_tets(nf), Tc = make_tets(nf / 2);
   Csr Af = cube_pattern(Tf), Ac = cube_pattern(Tc);
-  Sell Sf = make_sell(Af, 64, 1), Sc = make_sell(Ac, 64, 1);
+  Sell Sf = make_sell_p1_cube(Af, nf), Sc = make_sell_p1_cube(Ac, nf / 2);
   Csr P;
   std::vector<double> Pv;
   p1_prolongation3(nf, P, Pv);

@@ -2494,7 +2494,7 @@ void spmv(const DSell& A, const TV* val, const T* x, T* y, T alpha, T beta, hipS
                        alpha, beta, y);
   } else if (A.uniform && A.width == W15) {
     hipLaunchKernelGGL((k_stencil<T, TV, ST_SPMV, W15>), dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s,
-                       A.nrows, A.side, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       A.nrows, A.cube, A.col, val, x, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
                        alpha, beta, y);
   } else {
     const int npos = A.nslices * 64;
@@ -2510,10 +2510,10 @@ void stencil(const DSell& A, const TV* val, int mode, const T* x, const T* b, co
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (A.width == W15) {
     if (mode == ST_RESID)
-      LAUNCH_EV(ev, (k_stencil<T, TV, ST_RESID, W15>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+      LAUNCH_EV(ev, (k_stencil<T, TV, ST_RESID, W15>), g, blk, 0, s, A.nrows, A.cube, A.col, val, x, b, dinv,
                 d, c1, c2, y);
     else
-      LAUNCH_EV(ev, (k_stencil<T, TV, ST_CHEB, W15>), g, blk, 0, s, A.nrows, A.side, A.col, val, x, b, dinv,
+      LAUNCH_EV(ev, (k_stencil<T, TV, ST_CHEB, W15>), g, blk, 0, s, A.nrows, A.cube, A.col, val, x, b, dinv,
                 d, c1, c2, y);
     return;
   }
@@ -2548,7 +2548,7 @@ template <typename T, typename TV>
 void coarse_cheb(const DSell& A, const TV* val, const T* dinv, const T* b, const ChebCoef<T>& cc,
                  T* x, hipStream_t s) {
   if (A.width == W15)
-    hipLaunchKernelGGL((k_coarse_cheb<T, TV, W15>), dim3(1), dim3(1024), 0, s, A.nrows, A.side, A.col, val,
+    hipLaunchKernelGGL((k_coarse_cheb<T, TV, W15>), dim3(1), dim3(1024), 0, s, A.nrows, A.cube, A.col, val,
                        dinv, b, cc, x);
   else
     hipLaunchKernelGGL((k_coarse_cheb<T, TV, W7>), dim3(1), dim3(1024), 0, s, A.nrows, A.side, A.col, val,
@@ -2726,10 +2726,10 @@ void ch_block(const DSell& A, const TV* L, const TV* K, const TV* M, T c12, T c2
   const dim3 g(ceil_div(A.nrows, BS)), blk(BS);
   if (A.width == W15) {
     if (L == M)
-      LAUNCH_EV(ev, (k_ch_block<T, TV, true, W15>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
+      LAUNCH_EV(ev, (k_ch_block<T, TV, true, W15>), g, blk, 0, s, A.nrows, A.cube, A.col, L, K, M, c12, c22,
                 x, alpha, beta, y, yin);
     else
-      LAUNCH_EV(ev, (k_ch_block<T, TV, false, W15>), g, blk, 0, s, A.nrows, A.side, A.col, L, K, M, c12, c22,
+      LAUNCH_EV(ev, (k_ch_block<T, TV, false, W15>), g, blk, 0, s, A.nrows, A.cube, A.col, L, K, M, c12, c22,
                 x, alpha, beta, y, yin);
     return;
   }
@@ -2808,10 +2808,11 @@ static void launch_ch_dots(int j, int N, const DSell& A, const double* Lv, const
                            double c12, double c22, const double* z, double* V, int64_t ld, const DcgsState& st,
                            hipStream_t s, LaunchEv ev) {
   const dim3 g(dcgs_dot_blocks(2 * int64_t(N))), b(BS);
+  const int side = W == W15 ? A.cube : A.side;  // computed columns
   switch (j) {
 #define CHNS_CHD_CASE(K)                                                                                 \
   case K:                                                                                                 \
-    LAUNCH_EV(ev, (k_ch_dots<K, LM, W>), g, b, 0, s, N, A.side, A.col, Lv, Kv, Mv, c12, c22, z, V, ld, st.part, \
+    LAUNCH_EV(ev, (k_ch_dots<K, LM, W>), g, b, 0, s, N, side, A.col, Lv, Kv, Mv, c12, c22, z, V, ld, st.part, \
               st.vscale);                                                                                 \
     break;
     CHNS_CHD_CASE(0) CHNS_CHD_CASE(1) CHNS_CHD_CASE(2) CHNS_CHD_CASE(3) CHNS_CHD_CASE(4) CHNS_CHD_CASE(5)
@@ -2958,7 +2959,7 @@ void diagnostics(const DSell& A, const double* M, const double* K, const double*
                  double* part, double* out, hipStream_t s) {
   const int nblk = reduce_blocks(A.nrows);
   if (A.width == W15)
-    hipLaunchKernelGGL(k_diag<W15>, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, p2, Phi,
+    hipLaunchKernelGGL(k_diag<W15>, dim3(nblk), dim3(BS), 0, s, A.nrows, A.cube, A.col, M, K, p0, p1, p2, Phi,
                        ternary ? 1 : 0, kb, pc, part);
   else
     hipLaunchKernelGGL(k_diag<W7>, dim3(nblk), dim3(BS), 0, s, A.nrows, A.side, A.col, M, K, p0, p1, p2, Phi,
@@ -2990,7 +2991,7 @@ void rhs_quaternary(const DSell& A, const double* Mv, const double* php, const d
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi, double c_mu,
                 double c_ac, const TopFlux& tf, double* rhs_ch, double* rhs_ac, hipStream_t s) {
   if (A.width == W15)
-    hipLaunchKernelGGL(k_rhs_binary<W15>, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col,
+    hipLaunchKernelGGL(k_rhs_binary<W15>, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.cube, A.col,
                        Mv, phi, Phi, c_mu, c_ac, tf, rhs_ch, rhs_ac);
   else
     hipLaunchKernelGGL(k_rhs_binary<W7>, dim3(ceil_div(A.nrows, BS)), dim3(BS), 0, s, A.nrows, A.side, A.col,

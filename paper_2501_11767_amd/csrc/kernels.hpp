@@ -16,6 +16,7 @@ struct DSell {
   const int* col = nullptr;
   const int* perm = nullptr;              // lane position -> row (-1 padding)
   int side = 0;  // > 0: periodic side x side P1 pattern in neighbour order (columns computed)
+  int cube = 0;  // > 0: periodic cube P1 pattern of this side in neighbour order (columns computed)
 };
 
 // Optional start/stop events taken by the dispatch itself (the kernel's own

@@ -43,7 +43,7 @@ def _tets(probe, n):
 def _p1(probe, n):
     N = n ** 3
     nnz = probe.chns_probe_cube_p1(n, None, None, None, None, None, None, None)
-    flags = np.zeros(3, np.int32)
+    flags = np.zeros(4, np.int32)
     rp = np.zeros(N + 1, np.int32)
     col = np.zeros(nnz, np.int32)
     probe.chns_probe_cube_p1(n, _ptr(rp), _ptr(col), None, None, None, _ptr(flags), None)
@@ -84,6 +84,16 @@ def test_pattern_and_sell_layout(probe, n):
     assert np.array_equal(scol[c2s], col)
     assert np.array_equal(scol[diag], np.arange(N))
     assert es.min() >= 0 and es.max() < flags[2]
+    # entry k of row (i, j, l) is the fixed neighbour the kernels compute: the
+    # vertex, then -d and +d for each edge direction in turn
+    assert flags[3] == n
+    dirs = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]
+    offs = [(0, 0, 0)] + [tuple(sg * np.array(d)) for d in dirs for sg in (-1, 1)]
+    l, j, i = np.unravel_index(np.arange(N), (n, n, n))
+    for k, (a, b, c) in enumerate(offs):
+        want = (i + a) % n + n * ((j + b) % n) + n * n * ((l + c) % n)
+        slots = (np.arange(N) // 64) * 64 * 15 + k * 64 + np.arange(N) % 64
+        assert np.array_equal(scol[slots], want), k
 
 
 def test_coloured_scatter_reenacted_with_the_oracle_element_matrices(probe):
