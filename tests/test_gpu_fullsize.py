@@ -129,7 +129,7 @@ def test_chac1024_step_matches_exact_solve(mods, tau):
             print(f"chac1024 full size: tau {tau:g} {precision} rtol {rtol:.3g}", flush=True)
             out = [z(), z(), z()]
             fout = ctx.fields(phi=[out[0]], mu=[out[1]], Phi_v=out[2])
-            o = C.default_opts(rtol=rtol, precision=prec, restart=13, maxiter=1500, **BENCH_MG)
+            o = C.default_opts(rtol=rtol, precision=prec, restart=11, maxiter=1500, **BENCH_MG)
             rc, info = ctx.timestep(fin, fout, 1, o)
             torch.cuda.synchronize()
             assert rc == C.OK, info
