@@ -44,20 +44,24 @@ def kuhn_offsets():
 
 
 class Mesh3:
-    """Periodic Kuhn triangulation of the unit cube with n cells per side."""
+    """Kuhn triangulation of the cube [0, L]^3 with n cells per side: periodic
+    (n^3 vertices i + n j + n^2 k), or with ``box`` the closed cube without
+    identification ((n+1)^3 vertices i + (n+1) j + (n+1)^2 k, 0 <= i, j, k <= n)."""
 
-    def __init__(self, n: int, length: float = 1.0):
-        if n < 3:
-            raise ValueError("need n >= 3 so that the neighbourhoods are distinct")
-        self.n, self.length = n, length
+    def __init__(self, n: int, length: float = 1.0, box: bool = False):
+        if n < (1 if box else 3):
+            raise ValueError("need n >= 3 on the periodic cube (distinct neighbourhoods), n >= 1 on the closed one")
+        self.n, self.length, self.box = n, length, box
         self.h = length / n
-        self.nv = n ** 3
+        m = n + 1 if box else n  # vertices per side
+        self.m = m
+        self.nv = m ** 3
         kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
         base = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1)  # cell (i, j, k) in order i + n j + n^2 k
         off = kuhn_offsets()
         pts = base[:, None, None, :] + off[None, :, :, :]  # (cells, 6, 4, 3), unwrapped
-        w = pts % n
-        ids = w[..., 0] + n * w[..., 1] + n * n * w[..., 2]
+        w = pts if box else pts % n
+        ids = w[..., 0] + m * w[..., 1] + m * m * w[..., 2]
         self.tet = ids.reshape(-1, 4).astype(np.int64)
         self.type = np.tile(np.arange(6), base.shape[0])
         self.xyz = pts.reshape(-1, 4, 3).astype(np.float64) * self.h
@@ -73,8 +77,8 @@ class Mesh3:
         self.grad = g
 
     def vertex_xyz(self):
-        n = self.n
-        kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        m = self.m
+        kk, jj, ii = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
         return np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1) * self.h
 
 
@@ -96,6 +100,22 @@ def p1_stiffness(m: Mesh3):
     """K_ab = |T| grad lambda_a . grad lambda_b per element."""
     Ae = np.einsum("e,ead,ebd->eab", m.vol, m.grad, m.grad)
     return _scatter(m.tet, Ae, m.nv)
+
+
+def top_face_load(m: Mesh3):
+    """b_i = int_{z = L} phi_i dS over the top face of the closed cube: the
+    faces of the tetrahedra with three vertices on z = L, each adding a third
+    of its area to each of its vertices (exact for P1)."""
+    if not m.box:
+        raise ValueError("the top face belongs to the closed cube")
+    b = np.zeros(m.nv)
+    top = np.isclose(m.xyz[..., 2], m.length)  # (ne, 4)
+    for e in np.nonzero(top.sum(axis=1) == 3)[0]:
+        a = np.nonzero(top[e])[0]
+        p = m.xyz[e, a]
+        area = 0.5 * np.linalg.norm(np.cross(p[1] - p[0], p[2] - p[0]))
+        b[m.tet[e, a]] += area / 3.0
+    return b
 
 
 def _rule4():

@@ -145,6 +145,25 @@ def prolongation_cube(nf: int):
     return out
 
 
+def prolongation_cube_box(nf: int):
+    """P1 interpolation between the closed cubes of side nf/2 and nf ((n+1)^3
+    vertices, no identification): as prolongation_cube without wrapping."""
+    nc = nf // 2
+    mf, mc = nf + 1, nc + 1
+    k, j, i = np.unravel_index(np.arange(mf ** 3), (mf, mf, mf))
+    f = np.stack([i, j, k], 1)
+    base, odd = f // 2, f % 2
+    cid = lambda q: q[:, 0] + mc * q[:, 1] + mc * mc * q[:, 2]
+    rows = np.arange(mf ** 3)
+    on_vertex = ~odd.any(axis=1)
+    P = sp.coo_matrix((np.where(on_vertex, 1.0, 0.5), (rows, cid(base))), shape=(mf ** 3, mc ** 3))
+    Q = sp.coo_matrix((np.where(on_vertex, 0.0, 0.5), (rows, cid(np.minimum(base + odd, nc)))),
+                      shape=(mf ** 3, mc ** 3))
+    out = (P + Q).tocsr()
+    out.eliminate_zeros()
+    return out
+
+
 def level_sizes(n: int, nmin: int = 4):
     out = [n]
     while out[-1] % 2 == 0 and out[-1] // 2 >= nmin:
@@ -171,11 +190,12 @@ class Hierarchy:
     ``p2``: A is a P2 operator; ``singular``: pressure Laplacian (a = 0);
     ``box_length``: A lives on the closed square [0, L]^2 (P1, (n+1)^2 nodes)
     instead of the periodic unit square; ``cube_length``: on the periodic cube
-    [0, L]^3 (P1 on the Kuhn tetrahedra, n^3 nodes)."""
+    [0, L]^3 (P1 on the Kuhn tetrahedra, n^3 nodes; with ``cube_box`` the
+    closed cube, (n+1)^3 nodes)."""
 
     def __init__(self, A, n: int, a: float = 1.0, b: float = 0.0, nmin: int = 4,
                  rho_cut: float = RHO_CUT, p2: bool = False, singular: bool = False,
-                 box_length: float | None = None, cube_length: float | None = None):
+                 box_length: float | None = None, cube_length: float | None = None, cube_box: bool = False):
         if (box_length is not None or cube_length is not None) and (p2 or singular):
             raise ValueError("the closed square and the cube carry P1 operators with a mass part")
         if box_length is not None and cube_length is not None:
@@ -197,7 +217,7 @@ class Hierarchy:
             self.lmax.append(LMAX_P2)
         for nf in self.sizes[:-1]:
             if cube:
-                P = prolongation_cube(nf)
+                P = prolongation_cube_box(nf) if cube_box else prolongation_cube(nf)
             else:
                 P = prolongation(nf) if box_length is None else prolongation_box(nf)
             self.P.append(P)

@@ -53,14 +53,14 @@ class CHPreconditioner:
     multigrid.cut_level)."""
 
     def __init__(self, M, K, C, prm, n, inner="exact", rho_cut=mg.RHO_CUT, box_length=None, cube_length=None,
-                 **mgkw):
+                 cube_box=False, **mgkw):
         self.M = M
         self.L = (M + prm.tau * C).tocsr() if C is not None else M.tocsr()
         self.X = matching_factor(M, K, prm)
         self.inner, self.mgkw, self.N = inner, mgkw, M.shape[0]
         if inner == "mg":
             t, g, b = prm.tau, prm.gamma, prm.beta
-            dom = dict(box_length=box_length, cube_length=cube_length)
+            dom = dict(box_length=box_length, cube_length=cube_length, cube_box=cube_box)
             self.HL = mg.Hierarchy(self.L, n, a=1.0, b=0.0, rho_cut=rho_cut, **dom)
             self.HX = mg.Hierarchy(self.X, n, a=np.sqrt(t * g / b), b=t * g, rho_cut=rho_cut, **dom)
 
@@ -78,11 +78,12 @@ class CHPreconditioner:
 
 
 class ACPreconditioner:
-    def __init__(self, A, n, prm, inner="exact", rho_cut=mg.RHO_CUT, box_length=None, cube_length=None, **mgkw):
+    def __init__(self, A, n, prm, inner="exact", rho_cut=mg.RHO_CUT, box_length=None, cube_length=None,
+                 cube_box=False, **mgkw):
         self.A, self.inner, self.mgkw = A.tocsr(), inner, mgkw
         if inner == "mg":
             self.H = mg.Hierarchy(self.A, n, a=1.0, b=prm.tau * prm.delta_v, rho_cut=rho_cut,
-                                  box_length=box_length, cube_length=cube_length)
+                                  box_length=box_length, cube_length=cube_length, cube_box=cube_box)
 
     def apply(self, r):
         if self.inner == "exact":

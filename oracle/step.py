@@ -62,17 +62,18 @@ class Operators:
 
 
 class Operators3D:
-    """The periodic unit cube (fem3d.Mesh3, Kuhn tetrahedra) with the P1
-    matrices, for the binary models without convection."""
+    """The cube (fem3d.Mesh3, Kuhn tetrahedra; periodic, or closed with
+    ``box``: no-flux walls) with the P1 matrices, for the binary models
+    without convection."""
 
     three_d = True
-    box = False
     Mv = B = vfixed = None
 
-    def __init__(self, n: int, length: float = 1.0):
+    def __init__(self, n: int, length: float = 1.0, box: bool = False):
         from . import fem3d
         self.n = n
-        self.mesh = fem3d.Mesh3(n, length)
+        self.box = box
+        self.mesh = fem3d.Mesh3(n, length, box)
         self.N = self.mesh.nv
         self.M = fem3d.p1_mass(self.mesh)
         self.K = fem3d.p1_stiffness(self.mesh)
@@ -182,10 +183,16 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
     flux = None
     if prm.top_flux != 0.0:
         if not ops.box or model not in ("ch", "ch_ac"):
-            raise ValueError("the top-wall flux belongs to the binary models on the closed square")
-        ref = n // 2 + (n + 1) * n  # midpoint of the top edge
+            raise ValueError("the top-wall flux belongs to the binary models on the closed square or cube")
+        if getattr(ops, "three_d", False):
+            from . import fem3d
+            ref = n // 2 + (n + 1) * (n // 2) + (n + 1) ** 2 * n  # centre of the top face
+            load = fem3d.top_face_load(mesh)
+        else:
+            ref = n // 2 + (n + 1) * n  # midpoint of the top edge
+            load = fem.top_edge_load(mesh)
         j_out = prm.top_flux * (st["phi"][0][ref] - prm.flux_inf)
-        flux = j_out * fem.top_edge_load(mesh)
+        flux = j_out * load
         sysrec["j_out"] = j_out
 
     # Cahn-Hilliard, one solve per phase (the same matrix unless the phases'
