@@ -123,11 +123,14 @@ typedef struct {
   int32_t n;        /* cells per side (even, 8..8192; 8..128 on the cube) */
   int32_t model;    /* CHNS_MODEL_* */
   int32_t boundary; /* CHNS_BOUNDARY_*; 0 = periodic */
-  int32_t dim;      /* 2 (0 means 2): the square; 3: the periodic cube [0, length]^3
-                       (section "Numerical results", three-dimensional runs) with n^3
-                       vertices i + n j + n^2 k at (i h, j h, k h), each cell split into
+  int32_t dim;      /* 2 (0 means 2): the square; 3: the cube [0, length]^3 (section
+                       "Numerical results", three-dimensional runs), each cell split into
                        the six Kuhn tetrahedra along its main diagonal (P1 rows of 15
-                       entries); the binary models only, no convecting velocity */
+                       entries): periodic with n^3 vertices i + n j + n^2 k at (i h, j h,
+                       k h), or with CHNS_BOUNDARY_NOFLUX closed with (n+1)^3 vertices
+                       i + (n+1) j + (n+1)^2 k and the top-face flux (top_flux on the face
+                       z = length, phi read at its centre); the binary models only, no
+                       convecting velocity */
   double length;    /* side of the square or cube (h = length / n); 0 means 1 */
 } chns_mesh;
 

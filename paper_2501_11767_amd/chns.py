@@ -239,14 +239,16 @@ def _stream():
 class Context:
     """Owns a chns_ctx for one mesh/model/parameter set.  boundary "periodic"
     (n^2 nodes) or "noflux" (the closed square, (n+1)^2 nodes); length: the
-    square's side; dim 3: the periodic cube (n^3 nodes, binary models)."""
+    square's side; dim 3: the cube (n^3 nodes periodic, (n+1)^3 closed; binary
+    models)."""
 
     def __init__(self, n: int, model: str = "ch_ac", torch_alloc: bool = True,
                  boundary: str = "periodic", length: float = 1.0, dim: int = 2, **params):
         self.L = lib()
         self.n, self.model, self.dim = n, model, dim
         self.boundary, self.length = boundary, length
-        self.N = n ** 3 if dim == 3 else ((n + 1) ** 2 if boundary == "noflux" else n * n)
+        m = n + 1 if boundary == "noflux" else n  # vertices per side
+        self.N = m ** dim
         p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.0, viscosity=1.0, alpha=1e-8,
                  rho=1.0)
         p.update(params)

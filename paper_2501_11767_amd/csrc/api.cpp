@@ -1568,18 +1568,21 @@ int build_ternary_tables(chns_ctx* c) {
 // colour) for the assembly.
 int build_cube_levels(chns_ctx* c) {
   const int n = c->mesh.n;
-  c->N = n * n * n;
+  const bool box = c->box;
+  // vertices: n^3 on the periodic cube, (n+1)^3 on the closed one
+  auto nodes = [box](int k) { return box ? (k + 1) * (k + 1) * (k + 1) : k * k * k; };
+  c->N = nodes(n);
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() / 2 >= 4) sizes.push_back(sizes.back() / 2);
   c->lv.resize(sizes.size());
   for (size_t l = 0; l < sizes.size(); ++l) {
     Level& L = c->lv[l];
     L.n = sizes[l];
-    L.N = L.n * L.n * L.n;
-    Tets T = make_tets(L.n);
+    L.N = nodes(L.n);
+    Tets T = make_tets(L.n, box);
     L.csr = pattern_from_elements(L.N, L.N, T.ne, T.v.data(), 4, T.v.data(), 4);
-    L.sell = make_sell_p1_cube(L.csr, L.n);
-    if (!L.sell.uniform || L.sell.width_max != 15 || L.sell.cube != L.n)
+    L.sell = box ? make_sell_p1_cube_box(L.csr, L.n) : make_sell_p1_cube(L.csr, L.n);
+    if (!L.sell.uniform || L.sell.width_max != 15 || L.sell.cube != (box ? 0 : L.n))
       return fail(c, CHNS_EINVAL, "P1 pattern of the cube is not the uniform 15-point stencil");
     TRY(upload_sell(c, L.sell, L.d));
     TRY(upload(c, &L.diag, L.sell.diag));
@@ -1595,6 +1598,7 @@ int build_cube_levels(chns_ctx* c) {
       TRY(upload(c, &c->etype, T.type));
       TRY(upload(c, &c->eslot, slot));
       std::copy(T.colour_ptr, T.colour_ptr + 49, c->colour_ptr3);
+      if (box) TRY(upload(c, &c->topw, cube_top_weights(T, c->h)));
     }
   }
   return CHNS_OK;
@@ -1642,7 +1646,7 @@ int build(chns_ctx* c) {
   for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
     Level& F = c->lv[l];
     Level& G = c->lv[l + 1];
-    if (c->dim3) p1_prolongation3(F.n, F.Pcsr, F.Pval);
+    if (c->dim3) p1_prolongation3(F.n, F.Pcsr, F.Pval, box);
     else p1_prolongation(F.n, F.Pcsr, F.Pval, box);
     csr_transpose(F.Pcsr, F.Pval, F.Rcsr, F.Rval);
     F.Psell = make_sell(F.Pcsr, 64, 1);
@@ -2236,8 +2240,8 @@ int chns_create(const chns_mesh* mesh, const chns_params* params, chns_alloc_fn 
     return CHNS_EINVAL;
   }
   if (mesh->dim == 3) {
-    if (mesh->boundary != CHNS_BOUNDARY_PERIODIC || mesh->model > CHNS_MODEL_CH_AC || mesh->n > 128) {
-      g_create_err = "the cube takes the periodic boundary, the binary models and n <= 128";
+    if (mesh->model > CHNS_MODEL_CH_AC || mesh->n > 128) {
+      g_create_err = "the cube takes the binary models and n <= 128";
       return CHNS_EINVAL;
     }
   }
@@ -2547,8 +2551,14 @@ int chns_step_rhs(chns_ctx* c, const chns_fields* in, double* d_rhs_ch, double* 
     tf.coef = p.tau * p.mobility * p.top_flux;
     tf.phi_inf = p.flux_inf;
     tf.h = c->h;
-    tf.top0 = n * (n + 1);
-    tf.ref = n / 2 + (n + 1) * n;  // midpoint of the top wall
+    if (c->dim3) {  // the top face z = length: vertices (i, j, n), weights int phi_i dS
+      tf.top0 = n * (n + 1) * (n + 1);
+      tf.ref = n / 2 + (n + 1) * (n / 2) + (n + 1) * (n + 1) * n;  // centre of the top face
+      tf.w = c->topw;
+    } else {
+      tf.top0 = n * (n + 1);
+      tf.ref = n / 2 + (n + 1) * n;  // midpoint of the top wall
+    }
   }
   rhs_binary(c->lv[0].d, c->lv[0].M, in->phi[0], ac ? in->Phi_v : nullptr,
              -(p.tau * p.mobility / beta), -p.tau * p.evap_rate, tf, d_rhs_ch, ac ? d_rhs_ac : nullptr,

@@ -168,6 +168,7 @@ struct chns_ctx {
   chns::Elements el;
   int *ep1 = nullptr, *ep2 = nullptr, *etype = nullptr, *eslot = nullptr;
   int colour_ptr3[49] = {0};  // the cube: colour ranges of the tetrahedra (48 colours)
+  double* topw = nullptr;     // closed cube: int phi_i dS of the top-face vertices
   chns::Krylov kr;
   // differentiation form: operators hold the transposed convection parts;
   // slot maps of the transposed entries (finest P1 and P2 patterns)

@@ -1,6 +1,7 @@
 #include "host_mesh.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <array>
 #include <map>
 #include <numeric>
@@ -53,11 +54,14 @@ Elements make_elements(int n, bool box) {
   return E;
 }
 
-Tets make_tets(int n) {
+Tets make_tets(int n, bool box) {
   Tets T;
   T.n = n;
+  T.box = box;
   T.ne = 6 * n * n * n;
-  auto id = [n](int i, int j, int k) {
+  const int m = box ? n + 1 : n;
+  auto id = [n, m, box](int i, int j, int k) {
+    if (box) return i + m * j + m * m * k;
     return ((i % n + n) % n) + n * ((j % n + n) % n) + n * n * ((k % n + n) % n);
   };
   T.v.reserve(size_t(T.ne) * 4);
@@ -83,21 +87,27 @@ Tets make_tets(int n) {
   return T;
 }
 
-void p1_prolongation3(int nf, Csr& P, std::vector<double>& val) {
+void p1_prolongation3(int nf, Csr& P, std::vector<double>& val, bool box) {
   const int nc = nf / 2;
-  auto fid = [nf](int i, int j, int k) {
+  // vertices per side: n on the periodic cube, n + 1 on the closed one
+  const int mf = box ? nf + 1 : nf, mc = box ? nc + 1 : nc;
+  auto fid = [nf, mf, box](int i, int j, int k) {
+    if (box) return i + mf * j + mf * mf * k;
     return ((i % nf + nf) % nf) + nf * ((j % nf + nf) % nf) + nf * nf * ((k % nf + nf) % nf);
   };
-  auto cid = [nc](int i, int j, int k) {
+  auto cid = [nc, mc, box](int i, int j, int k) {
+    if (box) return i + mc * j + mc * mc * k;
     return ((i % nc + nc) % nc) + nc * ((j % nc + nc) % nc) + nc * nc * ((k % nc + nc) % nc);
   };
-  const int64_t Nf = int64_t(nf) * nf * nf;
+  const int64_t Nf = int64_t(mf) * mf * mf;
   std::vector<std::vector<std::pair<int, double>>> rows(Nf);
-  for (int K = 0; K < nc; ++K)
-    for (int J = 0; J < nc; ++J)
-      for (int I = 0; I < nc; ++I)
+  for (int K = 0; K < mc; ++K)
+    for (int J = 0; J < mc; ++J)
+      for (int I = 0; I < mc; ++I)
         for (int d = 0; d < 8; ++d) {
           const int a = d & 1, b = (d >> 1) & 1, c = (d >> 2) & 1;
+          // closed cube: the midpoints of edges leaving the last coarse layer do not exist
+          if (box && ((a && I == nc) || (b && J == nc) || (c && K == nc))) continue;
           auto& row = rows[fid(2 * I + a, 2 * J + b, 2 * K + c)];
           if (d == 0) {
             row.push_back({cid(I, J, K), 1.0});
@@ -107,7 +117,7 @@ void p1_prolongation3(int nf, Csr& P, std::vector<double>& val) {
           }
         }
   P.nrows = int(Nf);
-  P.ncols = nc * nc * nc;
+  P.ncols = mc * mc * mc;
   P.rowptr.assign(P.nrows + 1, 0);
   P.col.clear();
   val.clear();
@@ -164,6 +174,80 @@ Sell make_sell_p1_cube(const Csr& A, int n) {
       if (A.col[q] == r) S.diag[r] = slot;
     }
   return S;
+}
+
+Sell make_sell_p1_cube_box(const Csr& A, int n) {
+  Sell S;
+  const int m = n + 1, N = m * m * m;
+  constexpr int W = 15;
+  S.nrows = N;
+  S.ncols = N;
+  S.C = 64;
+  S.sigma = 1;
+  S.cube = 0;  // columns are stored, not computed
+  S.nslices = (N + 63) / 64;
+  S.width_max = W;
+  S.uniform = true;
+  S.perm.assign(size_t(S.nslices) * 64, -1);
+  for (int r = 0; r < N; ++r) S.perm[r] = r;
+  S.slice_ptr.resize(S.nslices + 1);
+  for (int s = 0; s <= S.nslices; ++s) S.slice_ptr[s] = s * 64 * W;
+  S.slice_w.assign(S.nslices, W);
+  S.col.assign(size_t(S.nslices) * 64 * W, 0);
+  S.csr2sell.assign(A.nnz(), -1);
+  S.diag.assign(N, -1);
+  // neighbour k of row r, or -1 outside the cube
+  auto neighbour = [m](int r, int k) {
+    if (k == 0) return r;
+    const int i = r % m, j = (r / m) % m, l = r / (m * m);
+    const int* d = CUBE_DIRS[(k - 1) / 2];
+    const int sg = (k % 2 == 1) ? -1 : 1;
+    const int a = i + sg * d[0], b = j + sg * d[1], c = l + sg * d[2];
+    if (a < 0 || a >= m || b < 0 || b >= m || c < 0 || c >= m) return -1;
+    return a + m * b + m * m * c;
+  };
+  for (int r = 0; r < S.nslices * 64; ++r)
+    for (int k = 0; k < W; ++k) {
+      // padding lanes of a partial slice: column 0; a missing neighbour: the row itself
+      const int c = r < N ? neighbour(r, k) : 0;
+      S.col[size_t(r >> 6) * 64 * W + k * 64 + (r & 63)] = c < 0 ? r : c;
+    }
+  for (int r = 0; r < N; ++r)
+    for (int q = A.rowptr[r]; q < A.rowptr[r + 1]; ++q) {
+      int k = -1;
+      for (int t = 0; t < W; ++t)
+        if (neighbour(r, t) == A.col[q]) k = t;
+      if (k < 0) return Sell{};  // not the 15-point stencil
+      const int slot = (r >> 6) * 64 * W + k * 64 + (r & 63);
+      S.csr2sell[q] = slot;
+      if (A.col[q] == r) S.diag[r] = slot;
+    }
+  return S;
+}
+
+std::vector<double> cube_top_weights(const Tets& T, double h) {
+  const int n = T.n, m = n + 1;
+  std::vector<double> w(size_t(m) * m, 0.0);
+  const int top0 = n * m * m;  // first vertex of the layer k = n
+  for (int e = 0; e < T.ne; ++e) {
+    int on[4], cnt = 0;
+    for (int a = 0; a < 4; ++a) {
+      const int v = T.v[size_t(e) * 4 + a];
+      if (v >= top0) on[cnt++] = v;
+    }
+    if (cnt != 3) continue;
+    // the face's corners in the layer's (i, j) coordinates, area by the cross product
+    double xy[3][2];
+    for (int t = 0; t < 3; ++t) {
+      const int q = on[t] - top0;
+      xy[t][0] = (q % m) * h;
+      xy[t][1] = (q / m) * h;
+    }
+    const double area = 0.5 * std::fabs((xy[1][0] - xy[0][0]) * (xy[2][1] - xy[0][1]) -
+                                        (xy[2][0] - xy[0][0]) * (xy[1][1] - xy[0][1]));
+    for (int t = 0; t < 3; ++t) w[on[t] - top0] += area / 3.0;
+  }
+  return w;
 }
 
 Csr pattern_from_elements(int nrows, int ncols, int ne, const int* rn, int nr, const int* cn,

@@ -74,19 +74,29 @@ constexpr int KUHN_ORDER[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2
 constexpr int CUBE_DIRS[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
 struct Tets {
   int n = 0, ne = 0;
+  bool box = false;
   std::vector<int> v;     // ne*4 vertex ids, colour-sorted
   std::vector<int> type;  // 0..5
   int colour_ptr[49] = {0};
 };
-Tets make_tets(int n);
+// box: the closed cube, (n+1)^3 vertices i + (n+1) j + (n+1)^2 k (no wrap;
+// the same 48 colours).
+Tets make_tets(int n, bool box = false);
+// Closed cube: int_{z = L} phi_i dS of the top-face vertices (k = n), in the
+// order i + (n+1) j, from the faces of the tetrahedra lying on that face.
+std::vector<double> cube_top_weights(const Tets& T, double h);
 // Nested P1 prolongation on the periodic cube from n/2 to n: coarse vertex
 // (I, J, K) at fine (2I, 2J, 2K); the other fine vertices are midpoints of
 // the coarse edges in the directions (a, b, c) in {0, 1}^3 (values 1 or 1/2).
-void p1_prolongation3(int nf, Csr& P, std::vector<double>& val);
+void p1_prolongation3(int nf, Csr& P, std::vector<double>& val, bool box = false);
 // SELL-C-64 layout of the cube's P1 pattern with entry k of every row at the
 // fixed neighbour of the order above (columns computable from the row index:
 // Sell::cube = n); an empty Sell when the pattern is not that stencil.
 Sell make_sell_p1_cube(const Csr& A, int n);
+// The closed cube's P1 pattern ((n+1)^3 rows) in the same neighbour order,
+// a neighbour outside the cube stored as the row's own column (value 0);
+// columns stored (Sell::cube = 0).
+Sell make_sell_p1_cube_box(const Csr& A, int n);
 
 // Node-pair pattern of an element list: rows from `rn` (per element nr ids),
 // columns from `cn` (nc ids), sorted, duplicates merged.

@@ -48,9 +48,11 @@ int probe_galerkin(int nf, bool box, const double* fine_csr, double* coarse_csr)
 }
 
 Csr cube_pattern(const Tets& T) {
-  const int N = T.n * T.n * T.n;
+  const int m = T.box ? T.n + 1 : T.n, N = m * m * m;
   return pattern_from_elements(N, N, T.ne, T.v.data(), 4, T.v.data(), 4);
 }
+
+Sell cube_sell(const Csr& A, int n, bool box) { return box ? make_sell_p1_cube_box(A, n) : make_sell_p1_cube(A, n); }
 
 }  // namespace
 
@@ -58,9 +60,9 @@ extern "C" {
 
 // The periodic cube: tetrahedra in colour order (v[ne*4], type[ne],
 // colour_ptr[49]); returns ne.
-__attribute__((visibility("default"))) int chns_probe_cube_tets(int n, int32_t* v, int32_t* type,
+__attribute__((visibility("default"))) int chns_probe_cube_tets(int n, int box, int32_t* v, int32_t* type,
                                                                 int32_t* colour_ptr) {
-  Tets T = make_tets(n);
+  Tets T = make_tets(n, box != 0);
   copy_out(T.v, v);
   copy_out(T.type, type);
   if (colour_ptr) std::memcpy(colour_ptr, T.colour_ptr, sizeof(T.colour_ptr));
@@ -71,13 +73,13 @@ __attribute__((visibility("default"))) int chns_probe_cube_tets(int n, int32_t* 
 // builds it: sell_col[slots], csr2sell[nnz], diag[N], flags (uniform, width,
 // slots, side of the computed columns), and the 16 SELL slots of each tetrahedron (eslot[ne*16], -1 for a
 // pair missing from the pattern).
-__attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int32_t* rowptr, int32_t* col,
+__attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int box, int32_t* rowptr, int32_t* col,
                                                                   int32_t* sell_col, int32_t* csr2sell,
                                                                   int32_t* diag, int32_t* flags,
                                                                   int32_t* eslot) {
-  Tets T = make_tets(n);
+  Tets T = make_tets(n, box != 0);
   Csr A = cube_pattern(T);
-  Sell S = make_sell_p1_cube(A, n);
+  Sell S = cube_sell(A, n, box != 0);
   copy_out(A.rowptr, rowptr);
   copy_out(A.col, col);
   copy_out(S.col, sell_col);
@@ -99,12 +101,19 @@ __attribute__((visibility("default"))) int64_t chns_probe_cube_p1(int n, int32_t
   return A.nnz();
 }
 
+// The closed cube's top-face weights int phi_i dS ((n+1)^2 values).
+__attribute__((visibility("default"))) int chns_probe_cube_top_weights(int n, double h, double* w) {
+  const std::vector<double> v = cube_top_weights(make_tets(n, true), h);
+  if (w) std::memcpy(w, v.data(), v.size() * sizeof(double));
+  return int(v.size());
+}
+
 // Nested prolongation n/2 -> n on the cube (returns nnz).
-__attribute__((visibility("default"))) int chns_probe_cube_prolongation(int nf, int32_t* rowptr, int32_t* col,
-                                                                        double* val) {
+__attribute__((visibility("default"))) int chns_probe_cube_prolongation(int nf, int box, int32_t* rowptr,
+                                                                        int32_t* col, double* val) {
   Csr P;
   std::vector<double> Pv;
-  p1_prolongation3(nf, P, Pv);
+  p1_prolongation3(nf, P, Pv, box != 0);
   copy_out(P.rowptr, rowptr);
   copy_out(P.col, col);
   if (val) std::memcpy(val, Pv.data(), Pv.size() * sizeof(double));
@@ -114,14 +123,14 @@ __attribute__((visibility("default"))) int chns_probe_cube_prolongation(int nf, 
 // Galerkin coarsening of fine CSR values on the cube through the library's
 // slot map: coarse CSR values; -1 when the map cannot be built, -2 when a
 // padding slot would receive a value, -3 when a source slot is out of range.
-__attribute__((visibility("default"))) int chns_probe_cube_galerkin(int nf, const double* fine_csr,
+__attribute__((visibility("default"))) int chns_probe_cube_galerkin(int nf, int box, const double* fine_csr,
                                                                     double* coarse_csr) {
-  Tets Tf = make_tets(nf), Tc = make_tets(nf / 2);
+  Tets Tf = make_tets(nf, box != 0), Tc = make_tets(nf / 2, box != 0);
   Csr Af = cube_pattern(Tf), Ac = cube_pattern(Tc);
-  Sell Sf = make_sell_p1_cube(Af, nf), Sc = make_sell_p1_cube(Ac, nf / 2);
+  Sell Sf = cube_sell(Af, nf, box != 0), Sc = cube_sell(Ac, nf / 2, box != 0);
   Csr P;
   std::vector<double> Pv;
-  p1_prolongation3(nf, P, Pv);
+  p1_prolongation3(nf, P, Pv, box != 0);
   std::string err;
   GalerkinMap G = make_galerkin(Af, Sf, P, Pv, Ac, Sc, &err);
   if (!err.empty()) return -1;

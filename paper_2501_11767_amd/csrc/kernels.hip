@@ -2096,7 +2096,7 @@ __global__ __launch_bounds__(BS) void k_rhs_binary(int n, int side, const int* _
   rhs_ch[row] = s_phi;
   double second = c_mu * s_fp;
   if (tf.coef != 0.0 && row >= tf.top0) {
-    const double w = (row == tf.top0 || row == n - 1) ? 0.5 * tf.h : tf.h;
+    const double w = tf.w ? tf.w[row - tf.top0] : ((row == tf.top0 || row == n - 1) ? 0.5 * tf.h : tf.h);
     second += tf.coef * (phi[tf.ref] - tf.phi_inf) * w;
   }
   rhs_ch[n + row] = second;

@@ -408,13 +408,15 @@ void set_slots(int64_t n, const int* idx, double v, double* a, float* a32, hipSt
 void rhs_quaternary(const DSell& A, const double* Mv, const double* php, const double* phn, const double* phs,
                     const double* Phi, const Coef3& c_mu, double c_ac, double* rhs_ch, double* rhs_ac,
                     double* fa, hipStream_t s);
-// Evaporation load of the closed square's top wall: rows top0 .. nrows-1 (the
-// vertices on y = length; top0 and nrows - 1 are the corners) gain
-// coef * (phi[ref] - phi_inf) * w_i in the CH right-hand side's second block,
-// w_i = int_top phi_i ds = h (h/2 at the corners).  coef = 0: no load.
+// Evaporation load of the closed square's top wall or the closed cube's top
+// face: rows top0 .. nrows-1 (the vertices on y = length, resp. z = length)
+// gain coef * (phi[ref] - phi_inf) * w_i in the CH right-hand side's second
+// block, w_i = int_top phi_i: w[i - top0] when w is given (the cube), else h
+// (h/2 at the corners; the square).  coef = 0: no load.
 struct TopFlux {
   double coef = 0.0, phi_inf = 0.0, h = 0.0;
   int top0 = 0, ref = 0;
+  const double* w = nullptr;
 };
 void rhs_binary(const DSell& A, const double* Mv, const double* phi, const double* Phi,
                 double c_mu, double c_ac, const TopFlux& tf, double* rhs_ch, double* rhs_ac, hipStream_t s);

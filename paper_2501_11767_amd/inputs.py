@@ -183,6 +183,20 @@ def cube_state(n: int, model: str, mean: float, seed: int, length: float = 1.0):
     return dict(phi=[phi], Phi_v=Phi_v, vel=None, p=None)
 
 
+def cube_box_state(n: int, length: float, model: str, mean: float, seed: int, film: float = 0.5):
+    """Initial fields of the binary models on the closed cube [0, L]^3 ((n+1)^3
+    vertices), the three-dimensional form of box_state: a film z <= film * L at
+    mean + U(-0.01, 0.01) with vapour field 0, air above (phase 0, vapour
+    field 1).  Keys as initial_state."""
+    if model not in ("ch", "ch_ac"):
+        raise ValueError(model)
+    z = cube_vertex_coords(n + 1, length * (n + 1) / n)[:, 2]
+    below = z <= film * length
+    phi = np.where(below, mean + 0.01 * rng(seed).uniform(-1.0, 1.0, size=z.size), 0.0)
+    Phi_v = np.where(below, 0.0, 1.0) if model == "ch_ac" else None
+    return dict(phi=[phi], Phi_v=Phi_v, vel=None, p=None)
+
+
 def log_uniform(g: np.random.Generator, lo: float, hi: float) -> float:
     return float(np.exp(g.uniform(np.log(lo), np.log(hi))))
 
@@ -228,6 +242,11 @@ CONFIGS = {
     # 0.4, eps = 0.05 (2 cells of the mesh); 128 cells per side as the larger size
     "cube40": dict(n=40, model="ch_ac", eps=0.05, tau=1e-4, mobility=1.0, evap_rate=0.1,
                    viscosity=1.0, steps=1, mean=0.4, seed=BASE_SEED + 8, sizes=(40, 64, 128)),
+    # the paper's three-dimensional domain: the closed 10 x 10 x 10 cube with
+    # no-flux walls on its 40^3 grid, the two-phase set-up of box10 (film at
+    # 1 +- 0.01 under air, beta = 0.1, gamma = gamma_v = 1, tau = 1e-4)
+    "cubebox40": dict(n=40, length=10.0, model="ch_ac", eps=0.1 ** 0.5, tau=1e-4, mobility=1.0,
+                      evap_rate=1.0, viscosity=1.0, steps=1, mean=1.0, seed=BASE_SEED + 9),
     "batch64": dict(instances=64, sizes=(64, 128, 256, 512), seed=BASE_SEED + 3),
     # Differentiation workload.  With the explicit potential the ternary run on
     # this mesh diverges within 6 steps at tau = 1e-3, 8 at 1e-4 and 17 at 1e-5

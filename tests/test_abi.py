@@ -60,10 +60,10 @@ def test_create_rejects_bad_domain(L, boundary, length, model, code):
 
 
 @pytest.mark.parametrize("dim,n,model,boundary", [(4, 16, 0, 0), (-1, 16, 0, 0), (3, 16, 2, 0), (3, 16, 3, 0),
-                                                   (3, 16, 1, 1), (3, 130, 1, 0), (3, 6, 0, 0)])
+                                                   (3, 16, 2, 1), (3, 130, 1, 0), (3, 6, 0, 0)])
 def test_create_rejects_bad_cube(L, dim, n, model, boundary):
-    """The cube takes dim 3 with the periodic boundary, the binary models and
-    8 <= n <= 128 (checked before any device call)."""
+    """The cube takes dim 3 with the binary models and 8 <= n <= 128 (checked
+    before any device call)."""
     h = ct.c_void_p()
     rc = L.chns_create(ct.byref(chns.Mesh(n=n, model=model, boundary=boundary, dim=dim)),
                        ct.byref(chns.Params(0.02, 1e-3, 1, 0, 1, 0, 1)), chns.ALLOC_FN(), chns.FREE_FN(), None,

@@ -249,3 +249,175 @@ def test_convection_is_refused_on_the_cube(C):
         ctx.assemble(vel)
     assert e.value.code == C.EUNSUPPORTED
     ctx.close()
+
+
+# ---------------------------------------------------------------- the closed cube
+
+LB = 2.0
+FLUX3 = dict(P3, tau=1e-3, top_flux=2.5, flux_inf=0.1)
+
+
+def _bctx(C, n, model, p=P3, L=LB):
+    return C.Context(n, model, dim=3, boundary="noflux", length=L, **p)
+
+
+def _bprm(p):
+    return Params(**{k: p[k] for k in ("eps", "tau", "mobility", "evap_rate")},
+                  top_flux=p.get("top_flux", 0.0), flux_inf=p.get("flux_inf", 0.0))
+
+
+def _bstate(n, model, seed, L=LB, mean=0.4):
+    return inputs.cube_box_state(n, L, model, mean, seed)
+
+
+@pytest.mark.parametrize("n", [8, 10])
+def test_closed_cube_operators_match_oracle(C, n):
+    ctx = _bctx(C, n, "ch_ac")
+    ops = S.Operators3D(n, LB, box=True)
+    prm = _prm(P3)
+    refs = {C.OP_M: ops.M, C.OP_K: ops.K, C.OP_X: PC.matching_factor(ops.M, ops.K, prm),
+            C.OP_AC: systems.ac_matrix(ops.M, ops.K, None, prm),
+            C.OP_CH: systems.ch_matrix(ops.M, ops.K, None, prm)}
+    print(f"closed cube operators n={n}", flush=True)
+    for op, ref in refs.items():
+        rp, col, val, shape = ctx.matrix(op)
+        ref = sp.csr_matrix(ref)
+        ref.sort_indices()
+        G = sp.csr_matrix((val, col, rp), shape=shape)
+        assert shape == ref.shape and np.array_equal(G.indptr, ref.indptr) and np.array_equal(G.indices, ref.indices)
+        assert np.abs(G.data - ref.data).max() <= 1e-13 * np.abs(ref.data).max(), op
+    g = np.random.default_rng(0)
+    x = g.standard_normal(ops.N)
+    y = _t(np.zeros(ops.N))
+    ctx.spmv(C.OP_K, _t(x), y)
+    import torch
+    torch.cuda.synchronize()
+    assert _maxrel(_np(y), ops.K @ x) < 1e-13
+    ctx.close()
+
+
+def test_closed_cube_rhs_with_the_top_face_flux(C):
+    import torch
+    n = 10
+    ctx = _bctx(C, n, "ch_ac", FLUX3)
+    ops = S.Operators3D(n, LB, box=True)
+    prm = _bprm(FLUX3)
+    st = S.initial_state(ops, prm, "ch_ac", _bstate(n, "ch_ac", 7))
+    _, sysr = S.step(ops, prm, "ch_ac", st, return_systems=True)
+    assert sysr["j_out"] != 0.0
+    f = ctx.fields(phi=[_t(st["phi"][0])], mu=[_t(st["mu"][0])], Phi_v=_t(st["Phi_v"]))
+    rch = torch.zeros(2 * ops.N, dtype=torch.float64, device="cuda")
+    rac = torch.zeros(ops.N, dtype=torch.float64, device="cuda")
+    ctx.step_rhs(f, rch, rac)
+    torch.cuda.synchronize()
+    assert _maxrel(_np(rch), sysr["ch_rhs"][0]) < 1e-13
+    assert _maxrel(_np(rac), sysr["ac_rhs"]) < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,p", [(10, P3), (16, P3), (16, dict(P3, tau=1e-1, evap_rate=30.0))])
+def test_closed_cube_precond_matches_oracle_vcycle(C, n, p):
+    import torch
+    ctx = _bctx(C, n, "ch_ac", p)
+    ops = S.Operators3D(n, LB, box=True)
+    prm = _prm(p)
+    g = np.random.default_rng(4)
+    N = ops.N
+    print(f"closed cube precond n={n}", flush=True)
+    for cycles in (1, 2):
+        kw = dict(pre=2, post=1, coarse=12, cycles=cycles)
+        opts = C.default_opts(mg_pre=2, mg_post=1, mg_coarse=12, mg_cycles=cycles)
+        P = PC.CHPreconditioner(ops.M, ops.K, None, prm, n, inner="mg", cube_length=LB, cube_box=True, **kw)
+        r = g.standard_normal(2 * N)
+        z = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+        ctx.precond(C.BLOCK_CH, _t(r), z, opts)
+        torch.cuda.synchronize()
+        zr = P.apply(r)
+        assert _maxrel(_np(z)[:N], zr[:N]) < 1e-12 and _maxrel(_np(z)[N:], zr[N:]) < 1e-12
+        Pa = PC.ACPreconditioner(systems.ac_matrix(ops.M, ops.K, None, prm), n, prm, inner="mg",
+                                 cube_length=LB, cube_box=True, **kw)
+        ra = g.standard_normal(N)
+        za = torch.zeros(N, dtype=torch.float64, device="cuda")
+        ctx.precond(C.BLOCK_AC, _t(ra), za, opts)
+        torch.cuda.synchronize()
+        assert _maxrel(_np(za), Pa.apply(ra)) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("model,p,precision", [("ch", P3, 0), ("ch_ac", P3, 0), ("ch_ac", FLUX3, 0),
+                                               ("ch_ac", FLUX3, 1)])
+def test_closed_cube_steps_match_oracle(C, model, p, precision):
+    """Three steps (FGMRES rtol 1e-12) against the oracle's direct solves, with
+    and without the top-face flux; the phase mass is unchanged (the flux loads
+    the mu equation only)."""
+    import torch
+    n = 12
+    ctx = _bctx(C, n, model, p)
+    ops = S.Operators3D(n, LB, box=True)
+    prm = _bprm(p)
+    st = S.initial_state(ops, prm, model, _bstate(n, model, 9))
+    ref = st
+    for _ in range(3):
+        ref = dict(ref, **{k: v for k, v in S.step(ops, prm, model, ref).items() if v is not None})
+    phi, mu = _t(st["phi"][0]), _t(st["mu"][0])
+    Phi = _t(st["Phi_v"]) if model == "ch_ac" else None
+    fin = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+    print(f"closed cube timestep {model} flux={p.get('top_flux', 0)} precision={precision}", flush=True)
+    rc, infos = ctx.timestep(fin, fin, nsteps=3, opts=C.default_opts(rtol=1e-12, precision=precision))
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    assert _rel(_np(phi), ref["phi"][0]) < 1e-10 and _maxrel(_np(phi), ref["phi"][0]) < 1e-10
+    assert _rel(_np(mu), ref["mu"][0]) < 1e-9
+    if model == "ch_ac":
+        assert _rel(_np(Phi), ref["Phi_v"]) < 1e-10 and _maxrel(_np(Phi), ref["Phi_v"]) < 1e-10
+    m0 = S.mass(ops, st["phi"][0])
+    assert abs(S.mass(ops, _np(phi)) - m0) <= 1e-11 * abs(m0)
+    ctx.close()
+
+
+def test_closed_cube_diagnostics_match_oracle(C):
+    n = 10
+    ctx = _bctx(C, n, "ch_ac")
+    ops = S.Operators3D(n, LB, box=True)
+    prm = _prm(P3)
+    st = S.initial_state(ops, prm, "ch_ac", _bstate(n, "ch_ac", 5))
+    fin = ctx.fields(phi=[_t(st["phi"][0])], mu=[_t(st["mu"][0])], Phi_v=_t(st["Phi_v"]))
+    got = ctx.diagnostics(fin)
+    ref = [S.mass(ops, st["phi"][0]), 0.0, 0.0, S.mass(ops, st["Phi_v"]),
+           S.energy_ch(ops, prm, st["phi"][0], st["Phi_v"])]
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= 1e-12 * abs(r) if r != 0.0 else g == 0.0, (got, ref)
+    ctx.close()
+
+
+def test_closed_cube_workload_step_satisfies_the_oracle_systems(C):
+    """The paper's three-dimensional domain on its 40^3 grid (cubebox40): one
+    mixed-precision step at the default tolerance; the result in the oracle's
+    own systems leaves relative residuals within the solver's tolerance, and
+    the phase mass is unchanged (mu^0 = 0, the Krylov initial guess)."""
+    import torch
+    cfg = inputs.CONFIGS["cubebox40"]
+    n, L = cfg["n"], cfg["length"]
+    p = {k: cfg[k] for k in ("eps", "tau", "mobility", "evap_rate")}
+    prm = _prm(p)
+    ctx = _bctx(C, n, "ch_ac", p, L)
+    ops = S.Operators3D(n, L, box=True)
+    st = inputs.cube_box_state(n, L, "ch_ac", cfg["mean"], cfg["seed"])
+    fps, fv = S.explicit_terms("ch_ac", st, prm)
+    phi, mu, Phi = _t(st["phi"][0]), _t(np.zeros(ops.N)), _t(st["Phi_v"])
+    fin = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+    opts = C.default_opts(precision=C.MIXED)
+    print(f"closed cube workload n={n}", flush=True)
+    rc, infos = ctx.timestep(fin, fin, 1, opts)
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    x = np.concatenate([_np(phi), _np(mu)])
+    A = systems.ch_matrix(ops.M, ops.K, None, prm)
+    b = systems.ch_rhs(ops.M, st["phi"][0], fps[0], prm)
+    assert np.linalg.norm(A @ x - b) <= 2 * opts.rtol * np.linalg.norm(b)
+    Aac = systems.ac_matrix(ops.M, ops.K, None, prm)
+    bac = systems.ac_rhs(ops.M, st["Phi_v"], fv, prm)
+    assert np.linalg.norm(Aac @ _np(Phi) - bac) <= 2 * opts.rtol * np.linalg.norm(bac)
+    m0 = S.mass(ops, st["phi"][0])
+    assert abs(S.mass(ops, _np(phi)) - m0) <= 1e-10 * abs(m0)
+    ctx.close()
