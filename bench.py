@@ -48,6 +48,11 @@ DRY_OPTS = dict(MG, restart=15)
 # the cube's CH + AC step: FGMRES(13) (40^3 / 64^3 / 128^3 mixed steps 4.3 / 5.5 / 29.9 ms
 # against 5.4 / 6.6 / 31.7 ms with 11)
 CUBE_RESTART = 13
+# the closed 10 x 10 square (box10): V(3,3) with FGMRES(20), measured fastest of V(1,3),
+# V(2,2), V(2,4), V(3,3) with restarts 11, 13, 20 (3.45 ms at 32 CH iterations; V(1,3)
+# with FGMRES(11): 4.7 ms at 62)
+BOX_MG = dict(MG, mg_pre=3, mg_post=3)
+BOX_RESTART = 20
 # the closed-square workload: the 1024^2 multigrid with the cut threshold swept
 # (its X operator has rho = 4 on the finest level, where the 1024^2 threshold
 # would cut it to a four-step Chebyshev smoother)
@@ -401,7 +406,7 @@ def box_section(chns, steps, restart):
     fo = ctx.fields(phi=[e()], mu=[e()], Phi_v=e())
     by_cut = {}
     for cut in BOX_RHO_CUTS:
-        opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=restart, **dict(MG, mg_rho_cut=cut))
+        opts = chns.default_opts(rtol=1e-8, precision=chns.MIXED, restart=restart, **dict(BOX_MG, mg_rho_cut=cut))
         ctx.timestep(f, fo, 1, opts)
         torch.cuda.synchronize()
         walls, its = [], []
@@ -418,7 +423,7 @@ def box_section(chns, steps, restart):
     return dict(workload=f"box10: CH + AC step on the closed square [0, {L}]^2 with no-flux walls, {n} cells "
                          f"per side ({N} vertices, {3 * N} unknowns), film at {cfg['mean']} +- 0.01 under air, "
                          f"eps^2 {cfg['eps'] ** 2:.3g}, tau {cfg['tau']}, mixed precision, FGMRES({restart}) "
-                         f"rtol 1e-8, V({MG['mg_pre']},{MG['mg_post']}) multigrid; per hierarchy cut threshold",
+                         f"rtol 1e-8, V({BOX_MG['mg_pre']},{BOX_MG['mg_post']}) multigrid; per hierarchy cut threshold",
                 rho_cut=best, **by_cut[best], by_rho_cut={str(k): v for k, v in by_cut.items()}, steps=steps)
 
 
@@ -901,7 +906,7 @@ def main():
         log(f"dry256: {args.dry_steps} steps")
     dry = dry_section(chns, args.dry_steps) if args.dry_steps > 0 else None
     bat = batch_section(chns, args.batch_steps) if args.batch_steps > 0 else None
-    box = box_section(chns, args.box_steps, args.restart) if args.box_steps > 0 else None
+    box = box_section(chns, args.box_steps, BOX_RESTART) if args.box_steps > 0 else None
     quad = quad_section(chns, args.quad_steps) if args.quad_steps > 0 else None
     qbox = quadbox_section(chns, args.quad_steps) if args.quad_steps > 0 else None
     cube = cube_section(chns, args.cube_steps, CUBE_RESTART) if args.cube_steps > 0 else None
