@@ -391,6 +391,19 @@ def korteweg_load(m: Mesh, grads, betas):
     return np.concatenate(out)
 
 
+def p2_eval_p1_interp_mesh(m, u_p1):
+    """P2 nodal values of a P1 field on any mesh with a P2 numbering (tri2):
+    each element's vertex nodes take the vertex values, its edge nodes the mean
+    of the edge's two vertex values (local node 3 + a is the edge opposite
+    vertex a); ids that belong to no element stay 0."""
+    out = np.zeros(4 * m.nv)
+    t, t2 = m.tri, m.tri2
+    out[t2[:, :3].ravel()] = u_p1[t].ravel()
+    for a, (b, c) in zip((3, 4, 5), ((1, 2), (0, 2), (0, 1))):
+        out[t2[:, a]] = 0.5 * (u_p1[t[:, b]] + u_p1[t[:, c]])
+    return out
+
+
 def p2_eval_p1_interp(n: int, u_p1):
     """P2 nodal values of a P1 field (vertex values copied, edge midpoints averaged)."""
     N = n * n

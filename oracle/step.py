@@ -152,14 +152,17 @@ def explicit_terms(model, st, prm: Params | None = None):
     return [t["dp"], t["dn"]], t["fv"]
 
 
-def convecting_field(n: int, prm: Params, rho_k, vel):
+def convecting_field(n: int, prm: Params, rho_k, vel, mesh=None):
     """The P2 field rho v of the Oseen convection (eq. (matrixns)): rho v with
     constant density, else the P2 interpolant of the nodal product of rho^k
-    (its P1 interpolant at the P2 nodes) and v."""
+    (its P1 interpolant at the P2 nodes) and v.  mesh: the closed square's
+    mesh (its padded P2 numbering) instead of the periodic square."""
     if rho_k is None:
         return prm.rho * vel
+    if mesh is not None:
+        return fem.p2_eval_p1_interp_mesh(mesh, rho_k)[None, :] * vel
     if vel.shape[1] != 4 * n * n:
-        raise ValueError("variable density is built for the periodic square")
+        raise ValueError("the periodic square's P2 numbering has 4 n^2 nodes")
     return fem.p2_eval_p1_interp(n, rho_k)[None, :] * vel
 
 
@@ -252,7 +255,7 @@ def step(ops: Operators, prm: Params, model: str, st: dict, how: str = "splu",
         conv = vel  # the velocity the convecting field is formed with
         for m in range(max(1, prm.picard)):
             used = conv
-            J = fem.p2_convection(mesh, convecting_field(n, prm, rho_k, conv), w_const)
+            J = fem.p2_convection(mesh, convecting_field(n, prm, rho_k, conv, mesh if ops.box else None), w_const)
             Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm, Mrho)
             v, p, _ = solvers.bordered_oseen_solve(Avel, ops.B, M, rhs, dense=(how == "dense"), fixed=ops.vfixed)
             v = np.stack([v[:N2], v[N2:]])

@@ -141,3 +141,42 @@ def test_stream_velocity_is_discretely_near_solenoidal_and_zero_on_the_walls():
     d = B @ vel.ravel()
     # interpolation error only: O(h^2) relative to the gradient scale
     assert np.abs(d).max() < 0.05 * (L2 / n) ** 2 * 10
+
+
+def test_p1_to_p2_interpolation_on_any_numbering():
+    """The mesh-generic P1 -> P2 interpolation: the periodic formula on the
+    periodic square, exact for linear fields at the closed square's P2 nodes,
+    zero at its unused ids."""
+    n = 6
+    g = np.random.default_rng(0)
+    m = fem.Mesh(n)
+    u = g.standard_normal(m.nv)
+    assert np.abs(fem.p2_eval_p1_interp_mesh(m, u) - fem.p2_eval_p1_interp(n, u)).max() == 0.0
+    b = fem.BoxMesh(n, L2)
+    xy, xy2 = b.vertex_xy(), b.p2_xy()
+    a = np.array([0.7, -1.3])
+    got = fem.p2_eval_p1_interp_mesh(b, xy @ a + 0.2)
+    unused = inputs.box_p2_unused(n)
+    assert np.abs(got[~unused] - (xy2[~unused] @ a + 0.2)).max() < 1e-14 and np.all(got[unused] == 0.0)
+
+
+def test_variable_density_step_on_the_closed_square():
+    """Variable density with Picard passes on the closed square: walls held,
+    discrete incompressibility, the convected phases' mass balance, dense =
+    sparse; the density changes the step (against rho = 1)."""
+    n = 8
+    prm = Params(**PF, rho_pure=(1.3, 0.8, 1.0), picard=3)
+    ops = S.Operators(n, need_p2=True, box_length=L2)
+    st = S.initial_state(ops, prm, "ternary", inputs.box_state(n, L2, "ternary", 0.33, 3))
+    a = S.step(ops, prm, "ternary", st, "dense")
+    b = S.step(ops, prm, "ternary", st, "splu")
+    assert np.abs(a["vel"] - b["vel"]).max() < 1e-11 * np.abs(a["vel"]).max()
+    vel = b["vel"].ravel()
+    assert np.all(vel[ops.vfixed] == 0.0) and np.abs(ops.B @ vel).max() < 1e-12 * np.abs(vel).max()
+    C = fem.p1_convection(ops.mesh, st["vel"])
+    one = np.ones(ops.N)
+    for i in range(2):
+        r = one @ (ops.M @ (b["phi"][i] - st["phi"][i])) + prm.tau * one @ (C @ b["phi"][i])
+        assert abs(r) < 1e-12 * abs(one @ (ops.M @ st["phi"][i])), i
+    c = S.step(ops, Params(**PF, picard=3), "ternary", st, "splu")
+    assert np.abs(c["vel"] - b["vel"]).max() > 1e-6 * np.abs(b["vel"]).max()
