@@ -115,8 +115,7 @@ enum {
                                  Oseen operator holds the no-slip set (wall nodes and the ids
                                  of no edge) with identity rows no other row couples to and
                                  zero right-hand side rows; a convecting velocity given to
-                                 chns_assemble must vanish there.  No variable density, no
-                                 adjoint step */
+                                 chns_assemble must vanish there.  No adjoint step */
 };
 
 typedef struct {

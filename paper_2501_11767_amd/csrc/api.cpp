@@ -188,7 +188,6 @@ const char* model_params_error(int model, bool box, const chns_params* p) {
   if (!ter && (p->potential != CHNS_POT_QUARTIC || p->truncate))
     return "the Flory-Huggins density and the truncation apply to the ternary model";
   if (!ter && p->var_density) return "variable density applies to the ternary model";
-  if (box && p->var_density) return "variable density is built for the periodic square";
   if (!ter && !quat && p->ns_picard > 1) return "Picard passes apply to the ternary and quaternary models";
   if (!box && p->top_flux != 0.0) return "the top-wall flux belongs to the closed square";
   for (int i = 0; i < 4; ++i) {
@@ -433,7 +432,7 @@ int assemble_ternary_conv(chns_ctx* c, const double* d_vel, const double* const*
 int weighted_masses(chns_ctx* c, hipStream_t s);
 
 int set_density(chns_ctx* c, const double* php, const double* phn, hipStream_t s) {
-  density_fields(c->mesh.n, php, phn, c->prm.rho_pure, c->rho1, c->rho2, s);
+  density_fields(c->mesh.n, c->box, php, phn, c->prm.rho_pure, c->rho1, c->rho2, s);
   return weighted_masses(c, s);
 }
 

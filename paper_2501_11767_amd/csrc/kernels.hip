@@ -3042,19 +3042,30 @@ void assemble_p1_conv(int e0, int e1, const int* ep1, const int* ep2, const int*
 // rho = rp phi_p + rn phi_n + rs (1 - phi_p - phi_n) at the vertices, and its
 // P1 interpolant at the P2 nodes (vertices; horizontal, vertical and diagonal
 // edge midpoints i + n j between (i,j) and (i+1,j), (i,j+1), (i+1,j+1)).
-__global__ __launch_bounds__(BS) void k_density(int n, const double* __restrict__ pp,
+// box: the closed square ((n+1)^2 vertices, no wrap); the P2 ids of edges
+// that do not exist (i = n for the horizontal and diagonal blocks, j = n for
+// the vertical and diagonal ones) get 0 (no element reads them).
+__global__ __launch_bounds__(BS) void k_density(int n, int box, const double* __restrict__ pp,
                                                 const double* __restrict__ pn, double rp, double rn,
                                                 double rs, double* __restrict__ rho1,
                                                 double* __restrict__ rho2) {
-  const int N = n * n;
+  const int m = box ? n + 1 : n;  // vertices per side
+  const int N = m * m;
   const int v = blockIdx.x * BS + threadIdx.x;
   if (v >= N) return;
-  const int j = v / n, i = v - j * n;
-  const int i1 = i + 1 == n ? 0 : i + 1, j1 = j + 1 == n ? 0 : j + 1;
+  const int j = v / m, i = v - j * m;
   auto r = [&](int k) { return rp * pp[k] + rn * pn[k] + rs * (1.0 - pp[k] - pn[k]); };
   const double r0 = r(v);
   rho1[v] = r0;
   rho2[v] = r0;
+  if (box) {
+    const bool ie = i < n, je = j < n;
+    rho2[N + v] = ie ? 0.5 * (r0 + r(v + 1)) : 0.0;
+    rho2[2 * N + v] = je ? 0.5 * (r0 + r(v + m)) : 0.0;
+    rho2[3 * N + v] = (ie && je) ? 0.5 * (r0 + r(v + m + 1)) : 0.0;
+    return;
+  }
+  const int i1 = i + 1 == n ? 0 : i + 1, j1 = j + 1 == n ? 0 : j + 1;
   rho2[N + v] = 0.5 * (r0 + r(i1 + n * j));
   rho2[2 * N + v] = 0.5 * (r0 + r(i + n * j1));
   rho2[3 * N + v] = 0.5 * (r0 + r(i1 + n * j1));
@@ -3069,9 +3080,10 @@ void fill(int64_t n, double v, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, v, out);
 }
 
-void density_fields(int n, const double* pp, const double* pn, const double* rpure, double* rho1,
+void density_fields(int n, bool box, const double* pp, const double* pn, const double* rpure, double* rho1,
                     double* rho2, hipStream_t s) {
-  hipLaunchKernelGGL(k_density, dim3(ceil_div(n * n, BS)), dim3(BS), 0, s, n, pp, pn, rpure[0],
+  const int m = box ? n + 1 : n;
+  hipLaunchKernelGGL(k_density, dim3(ceil_div(m * m, BS)), dim3(BS), 0, s, n, box ? 1 : 0, pp, pn, rpure[0],
                      rpure[1], rpure[2], rho1, rho2);
 }
 

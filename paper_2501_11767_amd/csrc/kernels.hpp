@@ -476,8 +476,9 @@ void assemble_p1_conv(int e0, int e1, const int* ep1, const int* ep2, const int*
                       MuGrad mg, double* val, hipStream_t s, const double* rho = nullptr);
 // (rho: the P2 nodal field that replaces wscale in w = rho v - alpha sum grad mu)
 // Variable density: rho1 = sum_i rpure[i] phi_i at the vertices (phi_s = 1 -
-// phi_p - phi_n), rho2 its P1 interpolant at the P2 nodes (4N).
-void density_fields(int n, const double* pp, const double* pn, const double* rpure, double* rho1,
+// phi_p - phi_n), rho2 its P1 interpolant at the P2 nodes (4N; box: the
+// closed square's padded numbering, 0 at the ids of no edge).
+void density_fields(int n, bool box, const double* pp, const double* pn, const double* rpure, double* rho1,
                     double* rho2, hipStream_t s);
 void fill(int64_t n, double v, double* out, hipStream_t s);
 // out[0] = ||v - w||_2, out[1] = ||v||_2; part holds 2 * 256 partial sums.

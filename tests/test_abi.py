@@ -81,7 +81,6 @@ QB = (2e-4, 2e-4, 1e-3, 4e-3)
 
 
 @pytest.mark.parametrize("model,boundary,kw,code", [
-    (2, 1, dict(var_density=1, rho_pure=(1.0, 1.0, 1.0)), -1),  # variable density: periodic only
     (3, 0, dict(beta_phase=(1e-3, 1e-3, 0.0, 1.0)), -1),          # a beta not positive
     (3, 0, dict(beta_phase=(1e-3, 1e-3, float("nan"), 1.0)), -1),
     (2, 0, dict(beta_phase=QB), -1),                              # per-phase betas: quaternary only

@@ -183,3 +183,43 @@ def test_adjoint_is_refused_on_the_closed_square(C):
         ctx.timestep_adjoint(f, f, f, f)
     assert e.value.code == C.EUNSUPPORTED
     ctx.close()
+
+
+RHO = (1.3, 0.8, 1.0)
+
+
+def test_variable_density_operators_and_step(C):
+    """Variable density on the closed square: after chns_set_density the
+    Oseen operator carries the rho^k-weighted mass (masked like the constant
+    one) and one FP64 step with three Picard passes matches the oracle (the
+    passes' velocity differences enter the pressure, which takes the fields'
+    bar)."""
+    import torch
+    n = 16
+    ops, prm, st, out, sysr = _setup("ternary", n, rho_pure=RHO, picard=3)
+    assert sysr["ns_Mrho"] is not None
+    ctx = _ctx(C, "ternary", n, var_density=1, rho_pure=RHO, ns_picard=3)
+    fld, f = _fields(ctx, "ternary", st)
+    print("box flow variable density", flush=True)
+    ctx.set_density(fld["phi"][0], fld["phi"][1])
+    ctx.assemble(fld["vel"], fld["mu"])
+    rp, col, val, shape = ctx.matrix(C.OP_NS)
+    G = sp.csr_matrix((val, col, rp), shape=shape)
+    fixed = np.concatenate([ops.vfixed, np.zeros(ops.N, bool)])
+    # the first pass's operator: convected by v^k (the oracle's record is the last pass's)
+    w_const = sysr["ns_w_const"]
+    rho_k = systems.density(prm, st["phi"][0], st["phi"][1])
+    J0 = fem.p2_convection(ops.mesh, S.convecting_field(n, prm, rho_k, st["vel"], ops.mesh), w_const)
+    A0 = systems.oseen_velocity_block(ops.Mv, J0, ops.Ksym(prm.viscosity), prm, sysr["ns_Mrho"])
+    ref = _masked(systems.oseen_matrix(A0, ops.B), fixed)
+    assert abs(G - ref).max() <= 1e-12 * abs(ref).max()
+    rc, infos = ctx.timestep(f, f, nsteps=1, opts=C.default_opts(rtol=1e-13, maxiter=800))
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    assert infos[3]["passes"] == sysr["ns_passes"]
+    for got, want in ((fld["phi"][0], out["phi"][0]), (fld["phi"][1], out["phi"][1]),
+                      (fld["vel"], out["vel"].ravel())):
+        assert _rel(_np(got), want) < 1e-10 and _maxrel(_np(got), want) < 1e-10
+    assert np.all(_np(fld["vel"])[ops.vfixed] == 0.0)
+    assert _rel(_np(fld["p"]), out["p"]) < 1e-10
+    ctx.close()
