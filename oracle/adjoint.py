@@ -115,8 +115,8 @@ def korteweg_vjp(m: fem.Mesh, xi, fields, betas):
 # ---------------------------------------------------------------- one step
 
 
-def zero_adjoint(n):
-    N = n * n
+def zero_adjoint(N):
+    """Zero adjoint state for N P1 nodes (4N P2 ids per velocity component)."""
     return dict(phi=[np.zeros(N), np.zeros(N)], mu=[np.zeros(N), np.zeros(N)], mu_s=np.zeros(N),
                 Phi_v=np.zeros(N), vel=np.zeros((2, 4 * N)), p=np.zeros(N))
 
@@ -131,7 +131,7 @@ def step_vjp(ops: S.Operators, prm: Params, st, st1, lam1):
     state s^k, the state s^{k+1} it produced and lambda^{k+1}."""
     if prm.rho_pure is not None or prm.picard > 1:
         raise NotImplementedError("the reverse step covers the linear scheme with constant density")
-    n, N = ops.n, ops.n * ops.n
+    n, N = ops.n, ops.N
     m, M, K = ops.mesh, ops.M, ops.K
     eps, tau, gam, gv = prm.eps, prm.tau, prm.gamma, prm.gamma_v
     beta = prm.beta
@@ -140,7 +140,7 @@ def step_vjp(ops: S.Operators, prm: Params, st, st1, lam1):
     H = hess_ter(pp, pn, Phi, prm)
     fps = (H["dp"], H["dn"])
     fv = H["fv"]
-    lam = zero_adjoint(n)
+    lam = zero_adjoint(N)
     dth = np.zeros(3)
     C = fem.p1_convection(m, st["vel"])
 
@@ -193,7 +193,9 @@ def step_vjp(ops: S.Operators, prm: Params, st, st1, lam1):
     J = fem.p2_convection(m, prm.rho * st["vel"], w_const)
     Avel = systems.oseen_velocity_block(ops.Mv, J, ops.Ksym(prm.viscosity), prm)
     rhs_v = np.concatenate([lam1["vel"][0], lam1["vel"][1]])
-    xi, _, _ = solvers.bordered_oseen_solve(Avel.T.tocsr(), ops.B, M, rhs_v)
+    # closed square: the step holds the no-slip unknowns at zero, so the
+    # adjoint solve leaves them out (their entries of lambda^{k+1} act on nothing)
+    xi, _, _ = solvers.bordered_oseen_solve(Avel.T.tocsr(), ops.B, M, rhs_v, fixed=ops.vfixed)
     N2 = 4 * N
     xi2 = np.stack([xi[:N2], xi[N2:]])
     u1 = st1["vel"]
@@ -236,7 +238,7 @@ def gradient(ops: S.Operators, prm: Params, st0, target, steps: int):
     """(L, dL/d(eps, mobility, evaporation rate)) by the reverse sweep."""
     states = rollout(ops, prm, st0, steps)
     L = loss(ops, states[-1], target)
-    lam = zero_adjoint(ops.n)
+    lam = zero_adjoint(ops.N)
     for i in range(2):
         lam["phi"][i] = ops.M @ (states[-1]["phi"][i] - target[i])
     grad = np.zeros(3)

@@ -119,7 +119,7 @@ def test_adjoint_step_matches_oracle(mods):
     st1 = AD.next_state(S.step(ops, prm, "ternary", st))
     rng = np.random.default_rng(8)
     N = n * n
-    lam1 = AD.zero_adjoint(n)
+    lam1 = AD.zero_adjoint(n * n)
     for i in range(2):
         lam1["phi"][i] = rng.standard_normal(N)
         lam1["mu"][i] = rng.standard_normal(N)

@@ -135,7 +135,7 @@ def test_adjoint_step_matches_oracle(C, kind, truncate):
     ops, st = _state(n, prm, seed=21, spread=0.3 if truncate else None)
     st1 = AD.next_state(S.step(ops, prm, "ternary", st))
     rng = np.random.default_rng(8)
-    lam1 = AD.zero_adjoint(n)
+    lam1 = AD.zero_adjoint(n * n)
     for i in range(2):
         lam1["phi"][i] = rng.standard_normal(N)
         lam1["mu"][i] = rng.standard_normal(N)

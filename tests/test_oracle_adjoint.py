@@ -130,8 +130,8 @@ def _flat(st):
                            st["Phi_v"], st["vel"].ravel(), st["p"]])
 
 
-def _unflat(x, n):
-    N = n * n
+def _unflat(x, n, N=None):
+    N = n * n if N is None else N
     o = 0
 
     def take(k):
@@ -155,7 +155,7 @@ def test_step_vjp_matches_central_differences(potential):
     prm = Params(**base)
     ops, st = _state(n, prm)
     g = np.random.default_rng(8)
-    lam1 = AD.zero_adjoint(n)
+    lam1 = AD.zero_adjoint(n * n)
     for i in range(2):
         lam1["phi"][i] = g.standard_normal(n * n)
         lam1["mu"][i] = g.standard_normal(n * n)
@@ -203,3 +203,40 @@ def test_gradient_matches_central_differences_of_the_loss():
     # at the reference parameters the loss and its gradient vanish
     L0, g0 = AD.gradient(ops, Params(**ref), st0, target, steps)
     assert L0 == 0.0 and np.all(g0 == 0.0)
+
+
+def test_step_vjp_on_the_closed_square_matches_central_differences():
+    """The reverse step on the closed square (no-slip unknowns left out of the
+    adjoint Oseen solve) against central differences of the direct-solve step,
+    state and parameters; the perturbation touches every input, walls
+    included."""
+    n, Lb = 6, 2.0
+    base = dict(eps=0.1, tau=1e-4, mobility=1.3, evap_rate=0.4, viscosity=1.0, alpha=0.1)
+    prm = Params(**base)
+    ops = S.Operators(n, need_p2=True, box_length=Lb)
+    st = S.initial_state(ops, prm, "ternary", inputs.box_state(n, Lb, "ternary", 0.33, 5))
+    N = ops.N
+    g = np.random.default_rng(8)
+    lam1 = AD.zero_adjoint(N)
+    for i in range(2):
+        lam1["phi"][i] = g.standard_normal(N)
+        lam1["mu"][i] = g.standard_normal(N)
+    lam1["mu_s"] = g.standard_normal(N)
+    lam1["Phi_v"] = g.standard_normal(N)
+    lam1["vel"] = g.standard_normal((2, 4 * N))
+    lam0, dth = AD.step_vjp(ops, prm, st, AD.next_state(S.step(ops, prm, "ternary", st)), lam1)
+    L1 = _flat(lam1)
+    fwd = lambda p, s: _flat(AD.next_state(S.step(ops, p, "ternary", s)))
+    x0 = _flat(st)
+    for seed in (1, 2):
+        dx = np.random.default_rng(seed).standard_normal(x0.size)
+        dx[-N:] = 0.0  # the pressure of step k enters nothing
+        h = 1e-5
+        fd = L1 @ (fwd(prm, _unflat(x0 + h * dx, n, N)) - fwd(prm, _unflat(x0 - h * dx, n, N))) / (2 * h)
+        assert _rel(_flat(lam0) @ dx, fd) < 1e-6, seed
+    for j, key in enumerate(("eps", "mobility", "evap_rate")):
+        h = 1e-3 * base[key]
+        pp = Params(**dict(base, **{key: base[key] + h}))
+        pm = Params(**dict(base, **{key: base[key] - h}))
+        fd = L1 @ (fwd(pp, st) - fwd(pm, st)) / (2 * h)
+        assert _rel(dth[j], fd) < 1e-6, key

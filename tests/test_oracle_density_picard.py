@@ -162,4 +162,4 @@ def test_picard_tolerance_stops_early_and_the_reverse_step_refuses():
     st1 = AD.next_state(S.step(ops, Params(**base), "ternary", st))
     for bad in (dict(picard=2), dict(rho_pure=(1.0, 1.0, 1.0))):
         with pytest.raises(NotImplementedError):
-            AD.step_vjp(ops, Params(**dict(base, **bad)), st, st1, AD.zero_adjoint(n))
+            AD.step_vjp(ops, Params(**dict(base, **bad)), st, st1, AD.zero_adjoint(n * n))
