@@ -115,7 +115,8 @@ enum {
                                  Oseen operator holds the no-slip set (wall nodes and the ids
                                  of no edge) with identity rows no other row couples to and
                                  zero right-hand side rows; a convecting velocity given to
-                                 chns_assemble must vanish there.  No adjoint step */
+                                 chns_assemble must vanish there; the adjoint step's
+                                 transposed Oseen solve holds it the same way */
 };
 
 typedef struct {

@@ -2109,6 +2109,9 @@ int ternary_adjoint(chns_ctx* c, const chns_fields& in, const chns_fields& out, 
   TRY(chns_solve_block(c, CHNS_BLOCK_AC, lo.Phi_v, A.zeta, o, info, worst, s));
   HIPCHK(c, hipMemcpyAsync(A.rhs, lo.vel, 8 * bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipMemsetAsync(A.rhs + 8 * int64_t(N), 0, bytes, s));
+  // closed square: the step holds the no-slip unknowns at zero, so their
+  // entries of lambda^{k+1} act on nothing (identity rows, zero right-hand side)
+  if (c->box) set_slots(c->ns.n_vfix, c->ns.vfix, 0.0, A.rhs, nullptr, s);
   HIPCHK(c, hipMemsetAsync(A.xi, 0, 9 * bytes, s));
   TRY(chns_solve_block(c, CHNS_BLOCK_NS, A.rhs, A.xi, o, info, worst, s));
   // M and K products of the CH and AC adjoint solutions
@@ -2689,7 +2692,6 @@ int chns_timestep_adjoint(chns_ctx* c, const chns_fields* in, const chns_fields*
   if (!c) return CHNS_EINVAL;
   TRY(check_opts(c, opts));
   if (!c->ternary || c->quat) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is defined for the ternary model");
-  if (c->box) return fail(c, CHNS_EUNSUPPORTED, "the adjoint step is built for the periodic square");
   if (c->prm.var_density || c->prm.ns_picard > 1)
     return fail(c, CHNS_EUNSUPPORTED, "the adjoint step covers the linear scheme with constant density");
   if (!in || !out || !lam_out || !lam_in || !h_dtheta) return fail(c, CHNS_EINVAL, "NULL argument");

@@ -172,16 +172,50 @@ def test_mixed_precision_steps(C):
     ctx.close()
 
 
-def test_adjoint_is_refused_on_the_closed_square(C):
+def test_adjoint_step_on_the_closed_square_matches_oracle(C):
+    """The reverse step (transposed CH, AC and Oseen solves, FGMRES rtol 1e-13)
+    on the closed square against the oracle's: every adjoint field within
+    1e-9, the parameter derivatives within 1e-9 relative."""
     import torch
+    from oracle import adjoint as AD
     n = 16
-    ctx = _ctx(C, "ternary", n)
-    N = (n + 1) ** 2
+    base = dict(eps=0.1, tau=1e-4, mobility=1.3, evap_rate=0.4, viscosity=1.0, alpha=0.1, rho=1.0)
+    prm = Params(**{k: v for k, v in base.items()})
+    ops = S.Operators(n, need_p2=True, box_length=L2)
+    st = S.initial_state(ops, prm, "ternary", inputs.box_state(n, L2, "ternary", 0.33, 5))
+    st1 = AD.next_state(S.step(ops, prm, "ternary", st))
+    N = ops.N
+    g = np.random.default_rng(8)
+    lam1 = AD.zero_adjoint(N)
+    for i in range(2):
+        lam1["phi"][i] = g.standard_normal(N)
+        lam1["mu"][i] = g.standard_normal(N)
+    lam1["mu_s"] = g.standard_normal(N)
+    lam1["Phi_v"] = g.standard_normal(N)
+    lam1["vel"] = g.standard_normal((2, 4 * N))
+    lam0, dth = AD.step_vjp(ops, prm, st, st1, lam1)
+    ctx = C.Context(n, "ternary", boundary="noflux", length=L2, **base)
+
+    def dev(s_):
+        return dict(phi=[_t(s_["phi"][0]), _t(s_["phi"][1])], mu=[_t(s_["mu"][0]), _t(s_["mu"][1]), _t(s_["mu_s"])],
+                    Phi_v=_t(s_["Phi_v"]), vel=_t(np.asarray(s_["vel"]).ravel()), p=_t(s_["p"]))
+
+    g0, g1, gl = dev(st), dev(st1), dev(dict(lam1, p=np.zeros(N)))
     z = lambda k=N: torch.zeros(k, dtype=torch.float64, device="cuda")
-    f = ctx.fields(phi=[z(), z()], mu=[z(), z(), z()], Phi_v=z(), vel=z(8 * N), p=z())
-    with pytest.raises(C.ChnsError) as e:
-        ctx.timestep_adjoint(f, f, f, f)
-    assert e.value.code == C.EUNSUPPORTED
+    out = dict(phi=[z(), z()], mu=[z(), z(), z()], Phi_v=z(), vel=z(8 * N), p=z())
+    print("box flow adjoint step", flush=True)
+    opts = C.default_opts(rtol=1e-13, precision=C.F64, maxiter=2000)
+    rc, d, info = ctx.timestep_adjoint(ctx.fields(**g0), ctx.fields(**g1), ctx.fields(**gl), ctx.fields(**out), opts)
+    torch.cuda.synchronize()
+    assert rc == C.OK, info
+    pairs = [(out["phi"][0], lam0["phi"][0]), (out["phi"][1], lam0["phi"][1]), (out["mu"][0], lam0["mu"][0]),
+             (out["mu"][1], lam0["mu"][1]), (out["mu"][2], lam0["mu_s"]), (out["Phi_v"], lam0["Phi_v"]),
+             (out["vel"], lam0["vel"].ravel())]
+    for k, (got, ref) in enumerate(pairs):
+        assert _rel(_np(got), ref) < 1e-9 and _maxrel(_np(got), ref) < 1e-9, (k, _rel(_np(got), ref))
+    assert np.abs(_np(out["p"])).max() == 0.0
+    for j in range(3):
+        assert abs(d[j] - dth[j]) <= 1e-9 * abs(dth[j]), (j, d[j], dth[j])
     ctx.close()
 
 
