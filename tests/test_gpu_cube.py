@@ -421,3 +421,58 @@ def test_closed_cube_workload_step_satisfies_the_oracle_systems(C):
     m0 = S.mass(ops, st["phi"][0])
     assert abs(S.mass(ops, _np(phi)) - m0) <= 1e-10 * abs(m0)
     ctx.close()
+
+
+@pytest.mark.parametrize("closed", [False, True])
+def test_constant_state_stays_constant(C, closed):
+    """A constant state is a fixed point of the phase equation: phi stays at
+    c, mu takes f'(c, Phi), Phi takes one explicit reaction step (the
+    oracle's degenerate case, on either cube), within 100 times the solver's
+    relative tolerance (1e-13)."""
+    import torch
+    from oracle import potential as pot
+    n = 8
+    ctx = _bctx(C, n, "ch_ac") if closed else _ctx(C, n, "ch_ac")
+    N = ctx.N
+    c, cv = 0.3, 0.7
+    prm = _prm(P3)
+    phi, mu, Phi = _t(np.full(N, c)), _t(np.zeros(N)), _t(np.full(N, cv))
+    fin = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+    rc, infos = ctx.timestep(fin, fin, 1, C.default_opts(rtol=1e-13, maxiter=400))
+    torch.cuda.synchronize()
+    assert rc == C.OK, infos
+    assert np.abs(_np(phi) - c).max() < 1e-11 * c
+    assert np.abs(_np(mu) - pot.dfdphi_bin(c, cv)).max() < 1e-11 * abs(pot.dfdphi_bin(c, cv))
+    Phi1 = cv - prm.tau * prm.gamma_v * pot.dfdPhi_bin(c, cv)
+    assert np.abs(_np(Phi) - Phi1).max() < 1e-11 * Phi1
+    ctx.close()
+
+
+@pytest.mark.parametrize("closed", [False, True])
+def test_largest_cube_step(C, closed):
+    """The largest cube (128 cells per side: 2,097,152 or 2,146,689 vertices,
+    31-32 million stored slots, 12.6 million tetrahedra): one mixed-precision
+    step converges, the phase mass (from the assembled M, checked against the
+    oracle at the small sizes above) is unchanged, and the mass matrix's
+    entries sum to the volume."""
+    import torch
+    n = 128
+    L = 10.0 if closed else 1.0
+    p = dict(P3, eps=0.05 * L)
+    ctx = _bctx(C, n, "ch_ac", p, L) if closed else _ctx(C, n, "ch_ac", p, L)
+    N = ctx.N
+    st = inputs.cube_box_state(n, L, "ch_ac", 0.4, 3) if closed else inputs.cube_state(n, "ch_ac", 0.4, 3, L)
+    phi, mu, Phi = _t(st["phi"][0]), _t(np.zeros(N)), _t(st["Phi_v"])
+    fin = ctx.fields(phi=[phi], mu=[mu], Phi_v=Phi)
+    print(f"largest cube closed={closed}", flush=True)
+    rc, infos = ctx.timestep(fin, fin, 1, C.default_opts(precision=C.MIXED, maxiter=400))
+    torch.cuda.synchronize()
+    assert rc == C.OK and all(i["converged"] for i in infos), infos
+    rp, col, val, shape = ctx.matrix(C.OP_M)
+    assert shape == (N, N) and len(val) == rp[-1]
+    M = sp.csr_matrix((val, col, rp), shape=shape)
+    assert abs(val.sum() - L ** 3) < 1e-9 * L ** 3
+    one = np.ones(N)
+    m0, m1 = one @ (M @ st["phi"][0]), one @ (M @ _np(phi))
+    assert abs(m1 - m0) <= 1e-10 * abs(m0)
+    ctx.close()
