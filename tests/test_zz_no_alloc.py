@@ -27,10 +27,13 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def _case(C, n, model, seed):
+def _case(C, n, model, seed, dim=2):
     p = dict(eps=0.02, tau=1e-3, mobility=1.0, evap_rate=0.1, viscosity=1.0, alpha=1e-8, rho=1.0)
-    ctx = C.Context(n, model, **p)
-    st = inputs.initial_state(n, model, 0.3 if model == "ternary" else 0.45, seed)
+    ctx = C.Context(n, model, dim=dim, **p)
+    if dim == 3:
+        st = inputs.cube_state(n, model, 0.45, seed)
+    else:
+        st = inputs.initial_state(n, model, 0.3 if model == "ternary" else 0.45, seed)
     phi = [_dev(u) for u in st["phi"]]
     f = ctx.fields(phi=phi, Phi_v=_dev(st["Phi_v"]) if st.get("Phi_v") is not None else None)
     return ctx, f
@@ -38,8 +41,9 @@ def _case(C, n, model, seed):
 
 def test_noalloc_diagnostics_equal_the_allocating_entry_point(C):
     import torch
-    cases = [(512, "ternary", 3), (64, "ch_ac", 4), (32, "ch", 5)]  # each smaller than the last
-    ctxs = [_case(C, n, model, seed) for n, model, seed in cases]
+    # each smaller than the last (the third on the periodic cube, 40^3 nodes)
+    cases = [(512, "ternary", 3, 2), (256, "ch_ac", 4, 2), (40, "ch_ac", 6, 3), (64, "ch_ac", 4, 2), (32, "ch", 5, 2)]
+    ctxs = [_case(C, n, model, seed, dim) for n, model, seed, dim in cases]
     # objects of earlier tests freed by the collector inside the window would
     # move the allocator's count: collect them first
     import gc
@@ -49,7 +53,7 @@ def test_noalloc_diagnostics_equal_the_allocating_entry_point(C):
     m0 = torch.cuda.memory_allocated()
     got = []
     for ctx, f in ctxs:
-        print(f"no-alloc diagnostics n={ctx.n} {ctx.model}", flush=True)
+        print(f"no-alloc diagnostics n={ctx.n} dim={ctx.dim} {ctx.model}", flush=True)
         got.append(ctx.diagnostics_noalloc(f))
     assert C.TorchAllocator.alloc_calls == a0
     assert torch.cuda.memory_allocated() == m0
